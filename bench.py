@@ -1,0 +1,165 @@
+#!/usr/bin/env python3
+"""Benchmark: FP64 slice evaluations per second of the bisection PIMC estimator at level p = 18.
+
+Workload (one step): the p = 18 column of the convergence sweep -- the quartic oscillator
+V = q^2/2 + g q^4/24 with g in {1, 10, 48} and T in {1, 2, 5}, endpoints a = 0, b = 1, 1e8 Philox
+samples per point, every N = 2^1 .. 2^10 estimated (one s = 10 bisection run per point reads all
+coarser levels off the same paths, as the paper's program does). Slice evaluations per sample =
+sum_{n=1..10} 2^n = 2046; the N = 1 level is analytic.
+
+Prints one JSON line with the metric, the roofline of the estimation kernel (FP64 vector ALU;
+algorithmic FLOP per slice from the table size at p = 18), and the CPU oracle timed on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+P_LEVEL = 18
+S_DEPTH = 10
+N_SAMPLES = 100_000_000
+POINTS = [(g, T) for g in (1.0, 10.0, 48.0) for T in (1.0, 2.0, 5.0)]
+# Algorithmic FP64 work of one slice evaluation at p = 18: E = 48 table entries -> 47 FMA (94 FLOP)
+# plus mid-point (2), deviation (1), two squares (2) and the accumulation (1): 100 FLOP.
+E_TABLE = {18: 48}
+FLOP_PER_SLICE = 2 * (E_TABLE[P_LEVEL] - 1) + 6
+FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector: 256 CU x 64 lanes x 2 FLOP x 2.4 GHz
+CPU_SAMPLE_PATHS = 2048          # per point, for the oracle timing
+
+
+def slices_per_sample(s: int, hierarchy: bool) -> int:
+    return (2 ** (s + 1) - 2) if hierarchy else 2 ** s
+
+
+def _oracle_worker(args):
+    g, T, first, count = args
+    import numpy as np
+    from oracle import effective_action as ea
+    from oracle import pimc as opimc
+    idx = np.arange(first, first + count, dtype=np.uint64)
+    S = opimc.path_actions(ea.quartic(1, g), 1, 0.0, 1.0, T, S_DEPTH, P_LEVEL, 1, 0, idx)
+    return float(S[:, S_DEPTH].sum())
+
+
+def cpu_baseline(paths_per_point: int):
+    """The oracle as it stands, on the host cores: level actions of the first paths of each point."""
+    import multiprocessing as mp
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    chunk = 256
+    jobs = [(g, T, st, min(chunk, paths_per_point - st)) for (g, T) in POINTS for st in range(0, paths_per_point, chunk)]
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        pool.map(_oracle_worker, jobs)
+    dt = time.perf_counter() - t0
+    n_slices = len(POINTS) * paths_per_point * slices_per_sample(S_DEPTH, True)
+    return {"value": n_slices / dt, "unit": "slice-evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {paths_per_point} paths of each of the {len(POINTS)} points (p=18, s=10, every level), "
+                      f"{dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--samples", type=int, default=N_SAMPLES)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding of path ranges is a design "
+                                   "note only", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    # The oracle runs first, in worker processes forked before this process touches the GPU.
+    cpu = None if args.no_cpu_baseline else cpu_baseline(CPU_SAMPLE_PATHS)
+
+    import paper_1105_0542_amd as P
+
+    ctx = P.Context(device=0)
+    H = P.FLAG_HIERARCHY
+    N = 1 << S_DEPTH
+
+    def step():
+        out = []
+        kms = 0.0
+        for i, (g, T) in enumerate(POINTS):
+            res, st = ctx.amplitude(P.quartic(1.0, g), 1.0, 0.0, 1.0, T, N, P_LEVEL, args.samples, 1, i, H)
+            kms += ctx.last_kernel_ms()
+            out.append((g, T, res))
+        return out, kms
+
+    for _ in range(args.warmup):
+        step()
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kernel_ms = 0.0
+    last = None
+    for _ in range(args.steps):
+        last, kms = step()
+        kernel_ms += kms
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    slices_step = len(POINTS) * args.samples * slices_per_sample(S_DEPTH, True)
+    value = slices_step * args.steps / wall
+    launches = args.steps * len(POINTS)
+    kernel_avg_s = kernel_ms / launches / 1e3
+    flop_per_launch = args.samples * slices_per_sample(S_DEPTH, True) * FLOP_PER_SLICE
+    achieved = flop_per_launch / kernel_avg_s / 1e12
+
+    # level-s only (no hierarchy): one point, same kernel family, for the second figure
+    res_s, _ = ctx.amplitude(P.quartic(1.0, 10.0), 1.0, 0.0, 1.0, 1.0, N, P_LEVEL, args.samples, 1, 100, 0)
+    ms_s = ctx.last_kernel_ms()
+    level_s_rate = args.samples * slices_per_sample(S_DEPTH, False) / (ms_s / 1e3)
+
+    line = {
+        "metric": "slice-evals/s (p=18, FP64)",
+        "value": value,
+        "unit": "slice-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (Philox4x32-10 samples, seed 1, stream = point index)",
+        "config": {
+            "workload": "p=18 column of the convergence sweep: V=q^2/2+g q^4/24, g in {1,10,48}, T in {1,2,5}, "
+                        "a=0, b=1, N=2^1..2^10 from one s=10 bisection run per point, "
+                        f"{args.samples:.0e} samples per point",
+            "p": P_LEVEL, "s": S_DEPTH, "samples_per_point": args.samples, "points": len(POINTS),
+            "slice_evals_per_sample": slices_per_sample(S_DEPTH, True),
+        },
+        "roofline": {
+            "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+            "kernel": "k_amplitude<4, QuarticEval64<18>>", "kernel_avg_ms": kernel_avg_s * 1e3,
+            "flop_per_slice": FLOP_PER_SLICE, "flop_per_launch": flop_per_launch,
+        },
+        "level_s_only": {"slice_evals_per_s": level_s_rate,
+                         "frac": level_s_rate * FLOP_PER_SLICE / 1e12 / FP64_PEAK_TFLOPS,
+                         "note": "same point g=10 T=1 without the coarser levels: 1024 slices per sample"},
+        "results": {f"g={g:g},T={T:g}": {"A_1024": r[S_DEPTH].amp, "err": r[S_DEPTH].err,
+                                          "relvar": r[S_DEPTH].relvar, "nonfinite": r[S_DEPTH].n_nonfinite}
+                    for (g, T, r) in last},
+    }
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,144 @@
+/*
+ * pimc.h -- C ABI of the MI355X (gfx950) Path Integral Monte Carlo amplitude library.
+ *
+ * The library estimates the imaginary-time transition amplitude A(a,b;T) = <b|exp(-T H)|a> of a
+ * particle of mass m in a 1D polynomial potential V, H = p^2/(2m) + V(q), hbar = 1, following
+ * Balaz et al., "SPEEDUP Code for Calculation of Transition Amplitudes via the Effective Action
+ * Approach":
+ *   - time slicing, eq.(AMC), into N = 2^s steps of eps = T/N;
+ *   - the level-p short-time effective action, eq.(ansatz) truncated at m <= p-1, with the
+ *     coefficients c_{m,k}(x) from eq.(1Drec) and eq.(diagonal) (Sec. 2.1);
+ *   - the discretized amplitude A_N^(p) and action eq.(SNp) (Sec. 4);
+ *   - trajectories by bisection with Gaussian offsets, every coarser level 2^n, n = 0..s, read off
+ *     the same level-s trajectory, amplitude and Monte Carlo error per level (Sec. 4.1).
+ *
+ * Conventions (shared by every entry point):
+ *   - Status: 0 = PIMC_OK, < 0 error (nothing written to outputs unless stated), > 0 warning
+ *     (outputs written).
+ *   - All pointers are plain host pointers unless the argument says "device". The caller owns every
+ *     input and output array; the context owns its device buffers, streams and graphs.
+ *   - Offsets of the bisection are standard normals from Philox4x32-10 (Salmon et al., SC'11) with
+ *     counter (h>>1, path_lo32, path_hi32, stream) and key (seed_lo32, seed_hi32) for heap node h of a
+ *     path; Box-Muller cosine for even h, sine for odd h; the offset of a level-n node has
+ *     variance T/2^(n+1) (the Brownian-bridge width), so the estimator of A_N^(p) is
+ *     K_0(a,b;T) * E[exp(-sum_k eps W_p(x_k, xbar_k; eps))] with K_0 the free kernel.
+ *   - Mass: A_m(a,b;T) = sqrt(m) A_1(sqrt(m) a, sqrt(m) b; T) with V(y/sqrt(m)).
+ *   - Level 0 (N = 1) is the analytic short-time amplitude with error 0 (Sec. 4.2).
+ *   - A context is used by one host thread at a time; calls on one context are serialized on its
+ *     stream.
+ */
+#ifndef PIMC_H
+#define PIMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------------------------- */
+enum {
+    PIMC_OK = 0,
+    PIMC_EINVAL = -1,          /* argument out of range or non-finite                              */
+    PIMC_EUNSUPPORTED = -2,    /* valid request outside what the library implements                */
+    PIMC_ENOMEM = -3,          /* host or device allocation failed                                 */
+    PIMC_EDEVICE = -4,         /* a HIP call failed; text via pimc_last_error                       */
+    PIMC_WNONFINITE = 1        /* some weights were inf/nan; they are kept in the sums (never dropped) */
+};
+
+/* ---- flags ---------------------------------------------------------------------------------- */
+enum {
+    PIMC_FP64 = 0,             /* slice polynomials in FP64 (default)                              */
+    PIMC_FP32_POLY = 1,        /* slice polynomials in FP32; mid-point/deviation, per-path action
+                                  sums and weights stay FP64                                        */
+    PIMC_HIERARCHY = 2         /* also estimate every coarser level n < s from the same paths       */
+};
+
+#define PIMC_MAX_DEGREE 8      /* highest power of q in a potential                                 */
+#define PIMC_MAX_P 18          /* highest effective-action level                                    */
+#define PIMC_MAX_S 20          /* N <= 2^20                                                         */
+
+/* V(q) = sum_{j=0..degree} coef[j] q^j. The paper's anharmonic oscillator (Sec. 3.3)
+ * V = A q^2/2 + g q^4/24 is coef[2] = A/2, coef[4] = g/24. */
+typedef struct {
+    int degree;                /* 0..PIMC_MAX_DEGREE; coef[j] for j > degree are ignored            */
+    double coef[PIMC_MAX_DEGREE + 1];
+} pimc_potential;
+
+/* Per bisection level n (N = 2^n): the amplitude estimate and its Monte Carlo error (standard
+ * deviation of the mean, unbiased sample variance), as printed per level by the paper's program. */
+typedef struct {
+    double amp;                /* A_{2^n}^(p)(a,b;T)                                               */
+    double err;                /* Monte Carlo error of amp; 0 at n = 0                              */
+    double log_amp;            /* log(amp) (finite where amp underflows)                             */
+    double relvar;             /* var(w)/mean(w)^2 of the weights                                   */
+    double ess;                /* (sum w)^2 / sum w^2                                                */
+    uint64_t n;                /* samples used                                                      */
+    uint64_t n_nonfinite;      /* weights that were inf or nan                                      */
+} pimc_level_result;
+
+typedef struct pimc_ctx pimc_ctx;
+
+/* Message for a status code (static string). */
+const char *pimc_strerror(int status);
+
+/* Detail of the last failure on this context (HIP error text, which argument was invalid).
+ * ctx may be NULL: then the last failure of this host thread outside any context. */
+const char *pimc_last_error(const pimc_ctx *ctx);
+
+/* Validate a problem (Sec. 2.1/4 problem statement) without touching any device.
+ * EINVAL: N not a power of two or N > 2^PIMC_MAX_S, p outside 1..PIMC_MAX_P, T <= 0, m <= 0,
+ * n_samples < 2, non-finite a/b/T/m/coefficients, degree outside 0..PIMC_MAX_DEGREE. */
+int pimc_check_problem(const pimc_potential *V, double m, double a, double b, double T,
+                       uint32_t N, int p, uint64_t n_samples);
+
+/* Host-side effective-action table of one level (no device needed).
+ * Writes the folded polynomials of  eps W_p(x, xbar; eps) = sum_k dlt^(2k) P_k(u),  with
+ * dlt = 2 xbar the full slice deviation, eps = T/2^level, and u = x^2 if V is even (all odd
+ * coefficients zero) else u = x, after the mass rescaling: P_k = eps 4^-k sum_{m=k}^{p-1}
+ * eps^(m-k) c_{m,k} (eq.(ansatz) and eq.(1Drec)/(diagonal) evaluated in FP64).
+ * Layout of out: for k = 0..*n_k-1, the coefficients of P_k from the highest power deg[k] down to
+ * power 0 (deg[k]+1 doubles each). deg must hold PIMC_MAX_P ints; *is_even reports the variable.
+ * cap = capacity of out in doubles; EINVAL if too small (*n_out then holds the size needed). */
+int pimc_level_table(const pimc_potential *V, double m, double T, int p, uint32_t level,
+                     double *out, size_t cap, size_t *n_out, int *n_k, int *deg, int *is_even);
+
+/* Create a context on HIP device `device`. hip_stream: a hipStream_t to launch on (for example
+ * torch's current stream), or NULL for a stream owned by the context. */
+int pimc_create(pimc_ctx **out, int device, void *hip_stream);
+int pimc_destroy(pimc_ctx *ctx);
+
+/* Estimate A_{2^n}^(p)(a,b;T) +- err for every level n = 0..s (N = 2^s) from n_samples paths with
+ * path indices 0..n_samples-1 (Sec. 4.1: trajectories by bisection, action eq.(SNp), e^{-S}
+ * averaged, error per level). Without PIMC_HIERARCHY only levels 0 and s are estimated (entries
+ * 1..s-1 have n = 0). out: caller-owned host array of log2(N)+1 entries.
+ * Returns PIMC_WNONFINITE (> 0) if any weight was not finite. */
+int pimc_amplitude(pimc_ctx *ctx, const pimc_potential *V, double m, double a, double b, double T,
+                   uint32_t N, int p, uint64_t n_samples, uint64_t seed, uint32_t stream,
+                   uint32_t flags, pimc_level_result *out);
+
+/* Per-path level actions sum_k eps_n W_p(x_k, xbar_k; eps_n) (the potential part of eq.(SNp); the
+ * kinetic part is absorbed by the bisection sampling) of paths first_path..first_path+k_paths-1,
+ * computed by the same kernels as pimc_amplitude.  S_out: caller-owned host array
+ * [k_paths][log2(N)+1]; levels not evaluated (no PIMC_HIERARCHY: 1..s-1) are written as 0. */
+int pimc_path_actions(pimc_ctx *ctx, const pimc_potential *V, double m, double a, double b,
+                      double T, uint32_t N, int p, uint64_t seed, uint32_t stream, uint32_t flags,
+                      uint64_t first_path, uint64_t k_paths, double *S_out);
+
+/* Canonical-chunk partial sums of the last pimc_amplitude call on this context: for level
+ * `level`, chunks first_chunk..first_chunk+n_chunks-1, four doubles per chunk:
+ * (paths, sum d, sum d^2, non-finite count) with d = exp(-(S - S_ref)) - 1 and S_ref the level
+ * action of the straight line from a to b (written to *shift). A chunk holds paths
+ * [c*chunk_paths, (c+1)*chunk_paths). Lets any chunk of a large run be checked independently. */
+int pimc_last_partials(pimc_ctx *ctx, uint32_t level, uint64_t first_chunk, uint64_t n_chunks,
+                       double *out, uint64_t *chunk_paths, uint64_t *total_chunks, double *shift);
+
+/* Device time of the last estimation kernel on this context, in milliseconds (HIP events on the
+ * context's stream around that launch). */
+int pimc_last_kernel_ms(pimc_ctx *ctx, double *ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PIMC_H */

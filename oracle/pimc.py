@@ -107,6 +107,26 @@ def level_actions(q: np.ndarray, s: int, tables) -> np.ndarray:
     return out
 
 
+def level_action_scales(q: np.ndarray, s: int, tables) -> np.ndarray:
+    """sum_k |eps_n W_p(x_k, xbar_k)| per path and level: the natural scale of a level action, used to
+    state a rounding tolerance that does not blow up when the action itself is near zero."""
+    out = np.zeros((q.shape[0], s + 1))
+    for n in range(s + 1):
+        sub = q[:, :: 1 << (s - n)]
+        x = 0.5 * (sub[:, 1:] + sub[:, :-1])
+        xbar = 0.5 * (sub[:, 1:] - sub[:, :-1])
+        out[:, n] = np.abs(eps_W(tables[n], x, xbar)).sum(axis=1)
+    return out
+
+
+def path_actions_and_scales(V, m, a, b, T, s, p, seed, stream, paths):
+    """(level actions, level scales) for explicit path indices, after the mass rescaling."""
+    Vt, at, bt, _ = rescale_mass(ea.poly(V) if not isinstance(V, tuple) else V, m, a, b)
+    tabs = level_tables(Vt, p, T, s)
+    q = bisection_paths(at, bt, T, s, seed, stream, paths)
+    return level_actions(q, s, tabs), level_action_scales(q, s, tabs)
+
+
 def path_actions(V, m, a, b, T, s, p, seed, stream, paths) -> np.ndarray:
     """Level actions (paths, s+1) after the mass rescaling, for explicit path indices."""
     Vt, at, bt, _ = rescale_mass(ea.poly(V) if not isinstance(V, tuple) else V, m, a, b)

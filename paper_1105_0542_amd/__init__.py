@@ -1,0 +1,11 @@
+"""MI355X-native Path Integral Monte Carlo transition amplitudes (SPEEDUP method, Balaz et al.).
+
+The computation runs in the HIP library ``libpimc.so`` (C ABI in ``include/pimc.h``); this package
+only marshals arguments to it. Importing the package does not load the library; the first call
+does, and raises ``PimcLibraryMissing`` if it has not been built (``python -m
+paper_1105_0542_amd.build``). There is no CPU fallback.
+"""
+from .binding import (  # noqa: F401
+    FLAG_FP32_POLY, FLAG_HIERARCHY, Context, LevelResult, PimcError, PimcLibraryMissing, check_problem,
+    level_table, lib_path, load_library, potential_from_coefs, quartic,
+)

@@ -1,0 +1,237 @@
+"""ctypes binding of libpimc.so: same names as the C ABI, argument marshalling only."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+PIMC_OK = 0
+PIMC_EINVAL = -1
+PIMC_EUNSUPPORTED = -2
+PIMC_ENOMEM = -3
+PIMC_EDEVICE = -4
+PIMC_WNONFINITE = 1
+
+FLAG_FP64 = 0
+FLAG_FP32_POLY = 1
+FLAG_HIERARCHY = 2
+
+MAX_DEGREE = 8
+MAX_P = 18
+
+
+class PimcLibraryMissing(RuntimeError):
+    """libpimc.so is not built: there is no other implementation to fall back to."""
+
+
+class PimcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"pimc status {status}: {msg}")
+        self.status = status
+
+
+class Potential(C.Structure):
+    _fields_ = [("degree", C.c_int), ("coef", C.c_double * (MAX_DEGREE + 1))]
+
+
+class _LevelResult(C.Structure):
+    _fields_ = [("amp", C.c_double), ("err", C.c_double), ("log_amp", C.c_double), ("relvar", C.c_double),
+                ("ess", C.c_double), ("n", C.c_uint64), ("n_nonfinite", C.c_uint64)]
+
+
+@dataclass
+class LevelResult:
+    amp: float
+    err: float
+    log_amp: float
+    relvar: float
+    ess: float
+    n: int
+    n_nonfinite: int
+
+
+_lib = None
+
+
+def lib_path() -> str:
+    return os.path.join(_HERE, "libpimc.so")
+
+
+def load_library():
+    """Load the in-tree libpimc.so (raises PimcLibraryMissing when absent)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = lib_path()
+    if not os.path.exists(path):
+        raise PimcLibraryMissing(f"{path} is missing: build it with `python -m paper_1105_0542_amd.build`")
+    # torch ships its own HIP runtime under the same soname (libamdhip64.so.7). Importing torch first
+    # makes the dynamic loader bind libpimc.so to that already-loaded runtime, so the library and
+    # torch's streams and allocations live in one HIP runtime. Loading libpimc.so first and torch
+    # afterwards would put two HSA runtimes in the process, and the second cannot open the GPU.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = C.CDLL(path)
+    vp = C.c_void_p
+    P = C.POINTER
+    lib.pimc_strerror.restype = C.c_char_p
+    lib.pimc_strerror.argtypes = [C.c_int]
+    lib.pimc_last_error.restype = C.c_char_p
+    lib.pimc_last_error.argtypes = [vp]
+    lib.pimc_check_problem.restype = C.c_int
+    lib.pimc_check_problem.argtypes = [P(Potential), C.c_double, C.c_double, C.c_double, C.c_double,
+                                       C.c_uint32, C.c_int, C.c_uint64]
+    lib.pimc_level_table.restype = C.c_int
+    lib.pimc_level_table.argtypes = [P(Potential), C.c_double, C.c_double, C.c_int, C.c_uint32, P(C.c_double),
+                                     C.c_size_t, P(C.c_size_t), P(C.c_int), P(C.c_int), P(C.c_int)]
+    lib.pimc_create.restype = C.c_int
+    lib.pimc_create.argtypes = [P(vp), C.c_int, vp]
+    lib.pimc_destroy.restype = C.c_int
+    lib.pimc_destroy.argtypes = [vp]
+    lib.pimc_amplitude.restype = C.c_int
+    lib.pimc_amplitude.argtypes = [vp, P(Potential), C.c_double, C.c_double, C.c_double, C.c_double, C.c_uint32,
+                                   C.c_int, C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32, P(_LevelResult)]
+    lib.pimc_path_actions.restype = C.c_int
+    lib.pimc_path_actions.argtypes = [vp, P(Potential), C.c_double, C.c_double, C.c_double, C.c_double,
+                                      C.c_uint32, C.c_int, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64,
+                                      C.c_uint64, P(C.c_double)]
+    lib.pimc_last_partials.restype = C.c_int
+    lib.pimc_last_partials.argtypes = [vp, C.c_uint32, C.c_uint64, C.c_uint64, P(C.c_double), P(C.c_uint64),
+                                       P(C.c_uint64), P(C.c_double)]
+    lib.pimc_last_kernel_ms.restype = C.c_int
+    lib.pimc_last_kernel_ms.argtypes = [vp, P(C.c_double)]
+    _lib = lib
+    return lib
+
+
+def potential_from_coefs(coefs: Sequence[float]) -> Potential:
+    coefs = list(coefs)
+    if len(coefs) > MAX_DEGREE + 1:
+        raise ValueError(f"degree > {MAX_DEGREE}")
+    V = Potential()
+    V.degree = max(len(coefs) - 1, 0)
+    for j in range(MAX_DEGREE + 1):
+        V.coef[j] = float(coefs[j]) if j < len(coefs) else 0.0
+    return V
+
+
+def quartic(A: float, g: float) -> List[float]:
+    """Coefficients of V = A q^2/2 + g q^4/24."""
+    return [0.0, 0.0, A / 2.0, 0.0, g / 24.0]
+
+
+def _err(lib, ctx, status) -> PimcError:
+    msg = lib.pimc_last_error(ctx)
+    return PimcError(status, (msg or b"").decode() or lib.pimc_strerror(status).decode())
+
+
+def check_problem(coefs, m, a, b, T, N, p, n_samples) -> int:
+    lib = load_library()
+    V = potential_from_coefs(coefs)
+    return lib.pimc_check_problem(C.byref(V), m, a, b, T, N, p, n_samples)
+
+
+def level_table(coefs, m, T, p, level):
+    """(coef array, degrees per k, even flag) of pimc_level_table (host-only call)."""
+    lib = load_library()
+    V = potential_from_coefs(coefs)
+    need = C.c_size_t(0)
+    nk = C.c_int(0)
+    deg = (C.c_int * MAX_P)()
+    ev = C.c_int(0)
+    lib.pimc_level_table(C.byref(V), m, T, p, level, None, 0, C.byref(need), C.byref(nk), deg, C.byref(ev))
+    out = np.zeros(need.value, dtype=np.float64)
+    st = lib.pimc_level_table(C.byref(V), m, T, p, level, out.ctypes.data_as(C.POINTER(C.c_double)), out.size,
+                              C.byref(need), C.byref(nk), deg, C.byref(ev))
+    if st != PIMC_OK:
+        raise _err(lib, None, st)
+    return out, [deg[k] for k in range(nk.value)], bool(ev.value)
+
+
+def _torch_stream_handle() -> Optional[int]:
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return int(torch.cuda.current_stream().cuda_stream) or None
+    except Exception:
+        return None
+    return None
+
+
+class Context:
+    """pimc_create/pimc_destroy. ``stream``: a hipStream_t handle (int); default = torch's current
+    stream if torch sees a GPU, else a stream owned by the context."""
+
+    def __init__(self, device: int = 0, stream: Optional[int] = None, use_torch_stream: bool = True):
+        self.lib = load_library()
+        if stream is None and use_torch_stream:
+            stream = _torch_stream_handle()
+        h = C.c_void_p()
+        st = self.lib.pimc_create(C.byref(h), device, C.c_void_p(stream) if stream else None)
+        if st != PIMC_OK:
+            raise _err(self.lib, None, st)
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pimc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, st):
+        if st < 0:
+            raise _err(self.lib, self.h, st)
+        return st
+
+    def amplitude(self, coefs, m, a, b, T, N, p, n_samples, seed, stream=0, flags=0):
+        """pimc_amplitude -> (list of LevelResult for n = 0..s, status)."""
+        V = potential_from_coefs(coefs)
+        s = int(N).bit_length() - 1
+        out = (_LevelResult * (s + 1))()
+        st = self._check(self.lib.pimc_amplitude(self.h, C.byref(V), m, a, b, T, N, p, n_samples, seed, stream,
+                                                 flags, out))
+        res = [LevelResult(r.amp, r.err, r.log_amp, r.relvar, r.ess, int(r.n), int(r.n_nonfinite)) for r in out]
+        return res, st
+
+    def path_actions(self, coefs, m, a, b, T, N, p, seed, stream, flags, first_path, k_paths):
+        """pimc_path_actions -> array [k_paths, s+1]."""
+        V = potential_from_coefs(coefs)
+        s = int(N).bit_length() - 1
+        out = np.zeros((k_paths, s + 1), dtype=np.float64)
+        self._check(self.lib.pimc_path_actions(self.h, C.byref(V), m, a, b, T, N, p, seed, stream, flags,
+                                               first_path, k_paths, out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
+
+    def last_partials(self, level, first_chunk, n_chunks):
+        """pimc_last_partials -> (array [n_chunks, 4], chunk_paths, total_chunks, shift)."""
+        out = np.zeros((n_chunks, 4), dtype=np.float64)
+        cp = C.c_uint64(0)
+        tc = C.c_uint64(0)
+        sh = C.c_double(0)
+        self._check(self.lib.pimc_last_partials(self.h, level, first_chunk, n_chunks,
+                                                out.ctypes.data_as(C.POINTER(C.c_double)), C.byref(cp),
+                                                C.byref(tc), C.byref(sh)))
+        return out, cp.value, tc.value, sh.value
+
+    def last_kernel_ms(self) -> float:
+        ms = C.c_double(0)
+        self._check(self.lib.pimc_last_kernel_ms(self.h, C.byref(ms)))
+        return ms.value

@@ -1,0 +1,53 @@
+// Internal interface between the host library (pimc_host.cpp) and the kernels (pimc_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pimc_device.hpp"
+
+namespace pimc {
+
+constexpr int kBlock = 256;            // threads per workgroup (4 waves); also the lanes of a chunk
+
+// Arguments of one estimation launch (passed by value in the kernel argument segment, so every
+// field is wave-uniform and scalar-loaded).
+struct AmpArgs {
+    const double* tab64;               // device: level tables, level-major
+    const float* tab32;                // device: FP32 copy (PIMC_FP32_POLY)
+    const int* gdeg;                   // device: generic shape, degree of each P_k
+    int gK;                            // generic shape: number of P_k
+    int gstride;                       // generic shape: doubles per level table
+    double a, b;                       // endpoints (after the mass rescaling)
+    const double* sig;                 // device: sigma_n = sqrt(T / 2^(n+1)), n = 0..s (0 unused)
+    const double* shift;               // device: straight-line level action S_ref,n, n = 0..s
+    RngKey key;
+    uint64_t first_path;               // path index of local path 0
+    uint64_t n_paths;                  // local paths 0..n_paths-1
+    uint64_t n_chunks;                 // ceil(n_paths / (kBlock * ppl))
+    uint32_t ppl;                      // paths per lane per chunk
+    int s;                             // N = 2^s
+    int D;                             // s - U: levels walked with the explicit stack
+    int hier;                          // evaluate every level (else level s only)
+    double* partials;                  // device [level][chunk][4] or null
+    double* dump;                      // device [path][s+1] or null
+};
+
+enum class EvalKind { Quartic64, Quartic32, GenericEven64, GenericOdd64 };
+
+// Dynamic LDS bytes of the estimation kernel for a given D and s.
+inline size_t amp_lds_bytes(int D, int s) {
+    return (size_t(3 * D + 2) * kBlock + size_t(4 * (s + 1) * 3)) * sizeof(double);
+}
+
+// Launch the estimation kernel; p selects the quartic specialization, U = s - D the unrolled
+// subtree depth. Returns hipErrorInvalidValue for an unsupported combination.
+hipError_t launch_amplitude(const AmpArgs& A, EvalKind kind, int p, int U, int grid, hipStream_t st);
+
+// Sum the canonical chunks of every level in chunk order: out[level][4] (device).
+hipError_t launch_reduce(const double* partials, uint64_t n_chunks, int n_levels, double* out, hipStream_t st);
+
+// Occupancy-derived number of resident workgroups of the estimation kernel on this device.
+int amplitude_resident_blocks(EvalKind kind, int p, int U, size_t lds_bytes, int device);
+
+}  // namespace pimc

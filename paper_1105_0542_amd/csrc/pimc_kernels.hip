@@ -1,0 +1,339 @@
+// Estimation kernels of the bisection PIMC amplitude (Sec. 4 of Balaz et al.) for gfx950.
+//
+// One lane owns one path at a time. The path is built depth first, left to right, and never
+// leaves the lane: the bottom U bisection levels of each subtree live in registers (2^U + 1
+// points), the levels above them keep one pending right endpoint and one cached sibling normal per
+// level in LDS. Every level-n slice is evaluated as soon as both of its endpoints exist, which for
+// n < s is the moment its midpoint (a level-(n+1) node) is generated; the level-s slices are the
+// leaves. Levels D..s of a subtree are evaluated coefficient-major over all slices of the level
+// (up to 8 at once) so that each wave-uniform table coefficient feeds independent FMA chains.
+//
+// Per level, each path's weight enters as d = exp(-(S_n - S_ref,n)) - 1 (a shift by the
+// straight-line action only changes rounding); a wave butterfly sums d and d^2, lane 0 adds the
+// wave sum to a per-wave LDS accumulator, and at the end of a canonical chunk (kBlock*ppl
+// consecutive paths, lanes in a fixed order) the four wave accumulators are added in wave order and
+// written to the chunk's slot. The chunk slots are summed in chunk order by k_reduce_chunks, so
+// the result is bitwise independent of the grid size and of which workgroup ran which chunk.
+#include <hip/hip_runtime.h>
+
+#include "pimc_internal.hpp"
+
+namespace pimc {
+
+// ---------------------------------------------------------------------------- subtree (registers)
+template <int U, int L, class Eval>
+__device__ __forceinline__ void gen_level(const AmpArgs& A, const PathRng& pr, uint32_t root, int D,
+                                          double (&q)[(1 << U) + 1]) {
+    if constexpr (L <= U) {
+        constexpr int step = 1 << (U - L);
+        const double sg = A.sig[D + L];
+#pragma unroll
+        for (int i2 = 0; i2 < (1 << (L - 2)); ++i2) {
+            const uint32_t parent = (root << (L - 2)) + uint32_t(i2);   // node of sub-level L-1
+            double ze, zo;
+            normal_pair(A.key, pr, parent, ze, zo);                      // children 2*parent, 2*parent+1
+            const int jl = (4 * i2 + 1) * step;
+            const int jr = (4 * i2 + 3) * step;
+            q[jl] = sg * ze + 0.5 * (q[jl - step] + q[jl + step]);
+            q[jr] = sg * zo + 0.5 * (q[jr - step] + q[jr + step]);
+        }
+        gen_level<U, L + 1, Eval>(A, pr, root, D, q);
+    }
+}
+
+// Add the 2^L slices of sub-level L (point stride 2^(U-L)) at tree level `level` to S, left to right.
+template <int U, int L, class Eval>
+__device__ __forceinline__ void level_sum(const Eval& ev, int level, const double (&q)[(1 << U) + 1], double& S) {
+    constexpr int W = 1 << L;
+    constexpr int ST = 1 << (U - L);
+    constexpr int B = W < 8 ? W : 8;
+#pragma unroll
+    for (int b0 = 0; b0 < W; b0 += B) {
+        double qa[B], qb[B];
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+            qa[i] = q[(b0 + i) * ST];
+            qb[i] = q[(b0 + i + 1) * ST];
+        }
+        ev.template eval<B>(level, qa, qb, S);
+    }
+}
+
+template <int U, int L, class Eval>
+__device__ __forceinline__ void hier_levels(const Eval& ev, int D, const double (&q)[(1 << U) + 1],
+                                            double (&Ssub)[U + 1]) {
+    if constexpr (L < U) {
+        level_sum<U, L, Eval>(ev, D + L, q, Ssub[L]);
+        hier_levels<U, L + 1, Eval>(ev, D, q, Ssub);
+    }
+}
+
+// Subtree rooted at heap node `root` (level D+1) over the level-D slice (qL, qR) with root normal z.
+template <int U, class Eval>
+__device__ __forceinline__ void run_subtree(const Eval& ev, const AmpArgs& A, const PathRng& pr,
+                                            uint32_t root, int D, double qL, double qR, double zroot,
+                                            double (&Ssub)[U + 1]) {
+    double q[(1 << U) + 1];
+    q[0] = qL;
+    q[1 << U] = qR;
+    q[1 << (U - 1)] = A.sig[D + 1] * zroot + 0.5 * (qL + qR);
+    gen_level<U, 2, Eval>(A, pr, root, D, q);
+    if (A.hier) hier_levels<U, 0, Eval>(ev, D, q, Ssub);
+    level_sum<U, U, Eval>(ev, D + U, q, Ssub[U]);
+}
+
+// ---------------------------------------------------------------------------- one path
+// top: this lane's LDS slots (stride kBlock): S_top[n] at slot n (n < D), pending right endpoint
+// of level L at slot D+L, pending normal at slot 2D+1+L (L = 2..D).
+template <int U, class Eval>
+__device__ __forceinline__ void walk_path(const Eval& ev, const AmpArgs& A, uint64_t path, double* top,
+                                          double (&Ssub)[U + 1]) {
+    const PathRng pr = path_rng(A.key, path);
+    const int D = A.D;
+#pragma unroll
+    for (int j = 0; j <= U; ++j) Ssub[j] = 0.0;
+    double z0_unused, z1;
+    normal_pair(A.key, pr, 0u, z0_unused, z1);        // node 1 = sine output of call 0
+    if (D == 0) {
+        run_subtree<U, Eval>(ev, A, pr, 1u, 0, A.a, A.b, z1, Ssub);
+        return;
+    }
+    for (int n = 0; n < D; ++n) top[n * kBlock] = 0.0;
+    double* R = top + D * kBlock;
+    double* Z = top + (2 * D + 1) * kBlock;
+    const uint32_t nTop = 1u << (D - 1);             // level-D nodes nTop .. 2 nTop - 1
+    double qlast = A.a;
+    for (uint32_t J = 0; J < nTop; ++J) {
+        int L;
+        uint32_t node;
+        double qL = qlast, qR, z;
+        if (J == 0) {
+            L = 1;
+            node = 1u;
+            qR = A.b;
+            z = z1;
+        } else {
+            const int t = __builtin_ctz(J);
+            L = D - t;
+            node = (nTop + J) >> t;
+            qR = R[L * kBlock];
+            z = Z[L * kBlock];
+        }
+        double qm, zl, zr;
+        while (true) {
+            if (A.hier) {
+                const double qa1[1] = {qL};
+                const double qb1[1] = {qR};
+                double St = top[(L - 1) * kBlock];
+                ev.template eval<1>(L - 1, qa1, qb1, St);
+                top[(L - 1) * kBlock] = St;
+            }
+            qm = A.sig[L] * z + 0.5 * (qL + qR);
+            normal_pair(A.key, pr, node, zl, zr);
+            if (L == D) break;
+            R[(L + 1) * kBlock] = qR;                 // right child of `node`: (qm, qR), normal zr
+            Z[(L + 1) * kBlock] = zr;
+            qR = qm;
+            z = zl;
+            node = 2u * node;
+            ++L;
+        }
+        run_subtree<U, Eval>(ev, A, pr, 2u * node, D, qL, qm, zl, Ssub);
+        run_subtree<U, Eval>(ev, A, pr, 2u * node + 1u, D, qm, qR, zr, Ssub);
+        qlast = qR;
+    }
+}
+
+// ---------------------------------------------------------------------------- estimation kernel
+__device__ __forceinline__ void reduce_level(const AmpArgs& A, double* acc, int nlev, int wave, int lane,
+                                             int n, double S, bool valid) {
+    const double d = valid ? expm1(-(S - A.shift[n])) : 0.0;
+    const bool bad = valid && !isfinite(d);
+    const double sd = wave_sum(d);
+    const double sd2 = wave_sum(d * d);
+    const unsigned long long badmask = __ballot(bad);
+    if (lane == 0) {
+        double* a = acc + (wave * nlev + n) * 3;
+        a[0] += sd;
+        a[1] += sd2;
+        a[2] += double(__popcll(badmask));
+    }
+}
+
+template <int U, class Eval>
+__global__ void __launch_bounds__(kBlock) k_amplitude(AmpArgs A, Eval ev) {
+    extern __shared__ double smem[];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int D = A.D;
+    const int nlev = A.s + 1;
+    double* top = smem + tid;
+    double* acc = smem + size_t(3 * D + 2) * kBlock;
+    const uint64_t CH = uint64_t(kBlock) * A.ppl;
+    for (uint64_t c = blockIdx.x; c < A.n_chunks; c += gridDim.x) {
+        if (A.partials) {
+            for (int i = tid; i < 4 * nlev * 3; i += kBlock) acc[i] = 0.0;
+            __syncthreads();
+        }
+        for (uint32_t r = 0; r < A.ppl; ++r) {
+            const uint64_t local = c * CH + uint64_t(r) * kBlock + uint64_t(tid);
+            const bool valid = local < A.n_paths;
+            double Ssub[U + 1];
+            walk_path<U, Eval>(ev, A, A.first_path + local, top, Ssub);
+            if (A.dump && valid) {
+                double* o = A.dump + local * uint64_t(nlev);
+                for (int n = 0; n < D; ++n) o[n] = A.hier ? top[n * kBlock] : 0.0;
+#pragma unroll
+                for (int j = 0; j <= U; ++j) o[D + j] = (A.hier || j == U) ? Ssub[j] : 0.0;
+            }
+            if (A.partials) {
+                if (A.hier) {
+                    for (int n = 0; n < D; ++n) reduce_level(A, acc, nlev, wave, lane, n, top[n * kBlock], valid);
+#pragma unroll
+                    for (int j = 0; j < U; ++j) reduce_level(A, acc, nlev, wave, lane, D + j, Ssub[j], valid);
+                }
+                reduce_level(A, acc, nlev, wave, lane, D + U, Ssub[U], valid);
+            }
+        }
+        if (A.partials) {
+            __syncthreads();
+            if (tid < nlev) {
+                const uint64_t rem = A.n_paths - c * CH;
+                const double cnt = (A.hier || tid == nlev - 1) ? double(rem < CH ? rem : CH) : 0.0;
+                double s1 = 0.0, s2 = 0.0, nb = 0.0;
+                for (int w = 0; w < kBlock / 64; ++w) {
+                    const double* a = acc + (w * nlev + tid) * 3;
+                    s1 += a[0];
+                    s2 += a[1];
+                    nb += a[2];
+                }
+                double* o = A.partials + (uint64_t(tid) * A.n_chunks + c) * 4;
+                o[0] = cnt;
+                o[1] = s1;
+                o[2] = s2;
+                o[3] = nb;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------- chunk reduction
+__global__ void __launch_bounds__(kBlock) k_reduce_chunks(const double* __restrict__ partials, uint64_t n_chunks,
+                                                          double* __restrict__ out) {
+    __shared__ double red[4][kBlock];
+    const int lev = blockIdx.x;
+    const int tid = threadIdx.x;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (uint64_t c = tid; c < n_chunks; c += kBlock) {
+        const double* p = partials + (uint64_t(lev) * n_chunks + c) * 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) s[j] += p[j];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) red[j][tid] = s[j];
+    __syncthreads();
+    for (int w = kBlock / 2; w >= 1; w >>= 1) {
+        if (tid < w) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) red[j][tid] += red[j][tid + w];
+        }
+        __syncthreads();
+    }
+    if (tid < 4) out[lev * 4 + tid] = red[tid][0];
+}
+
+// ---------------------------------------------------------------------------- dispatch
+template <int U, class Eval>
+static hipError_t launch_one(const AmpArgs& A, const Eval& ev, int grid, hipStream_t st) {
+    const size_t lds = amp_lds_bytes(A.D, A.s);
+    hipLaunchKernelGGL((k_amplitude<U, Eval>), dim3(grid), dim3(kBlock), lds, st, A, ev);
+    return hipGetLastError();
+}
+
+template <int P>
+static hipError_t launch_quartic(const AmpArgs& A, bool fp32, int grid, hipStream_t st) {
+    if (fp32) {
+        QuarticEval32<P> ev{A.tab32};
+        return launch_one<4>(A, ev, grid, st);
+    }
+    QuarticEval64<P> ev{A.tab64};
+    return launch_one<4>(A, ev, grid, st);
+}
+
+template <bool EVEN>
+static hipError_t launch_generic(const AmpArgs& A, int U, int grid, hipStream_t st) {
+    GenericEval64<EVEN> ev{A.tab64, A.gdeg, A.gK, A.gstride};
+    switch (U) {
+        case 1: return launch_one<1>(A, ev, grid, st);
+        case 2: return launch_one<2>(A, ev, grid, st);
+        case 3: return launch_one<3>(A, ev, grid, st);
+        case 4: return launch_one<4>(A, ev, grid, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int P>
+static hipError_t quartic_dispatch(const AmpArgs& A, bool fp32, int p, int grid, hipStream_t st) {
+    if constexpr (P <= kMaxP) {
+        if (p == P) return launch_quartic<P>(A, fp32, grid, st);
+        return quartic_dispatch<P + 1>(A, fp32, p, grid, st);
+    } else {
+        return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_amplitude(const AmpArgs& A, EvalKind kind, int p, int U, int grid, hipStream_t st) {
+    switch (kind) {
+        case EvalKind::Quartic64:
+        case EvalKind::Quartic32:
+            if (U != 4) return hipErrorInvalidValue;
+            return quartic_dispatch<1>(A, kind == EvalKind::Quartic32, p, grid, st);
+        case EvalKind::GenericEven64: return launch_generic<true>(A, U, grid, st);
+        case EvalKind::GenericOdd64: return launch_generic<false>(A, U, grid, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_reduce(const double* partials, uint64_t n_chunks, int n_levels, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce_chunks, dim3(n_levels), dim3(kBlock), 0, st, partials, n_chunks, out);
+    return hipGetLastError();
+}
+
+template <int U, class Eval>
+static int resident_one(size_t lds, int device) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_amplitude<U, Eval>, kBlock, lds) != hipSuccess) per_cu = 1;
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) ncu = 256;
+    return (per_cu < 1 ? 1 : per_cu) * ncu;
+}
+
+template <int P>
+static int resident_quartic(bool fp32, int p, size_t lds, int device) {
+    if constexpr (P <= kMaxP) {
+        if (p == P) return fp32 ? resident_one<4, QuarticEval32<P>>(lds, device) : resident_one<4, QuarticEval64<P>>(lds, device);
+        return resident_quartic<P + 1>(fp32, p, lds, device);
+    } else {
+        return 256;
+    }
+}
+
+int amplitude_resident_blocks(EvalKind kind, int p, int U, size_t lds_bytes, int device) {
+    switch (kind) {
+        case EvalKind::Quartic64: return resident_quartic<1>(false, p, lds_bytes, device);
+        case EvalKind::Quartic32: return resident_quartic<1>(true, p, lds_bytes, device);
+        case EvalKind::GenericEven64:
+        case EvalKind::GenericOdd64:
+            switch (U) {
+                case 1: return resident_one<1, GenericEval64<true>>(lds_bytes, device);
+                case 2: return resident_one<2, GenericEval64<true>>(lds_bytes, device);
+                case 3: return resident_one<3, GenericEval64<true>>(lds_bytes, device);
+                default: return resident_one<4, GenericEval64<true>>(lds_bytes, device);
+            }
+    }
+    return 256;
+}
+
+}  // namespace pimc
