@@ -34,6 +34,44 @@ E_TABLE = {18: 48}
 FLOP_PER_SLICE = 2 * (E_TABLE[P_LEVEL] - 1) + 6
 FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector: 256 CU x 64 lanes x 2 FLOP x 2.4 GHz
 CPU_SAMPLE_PATHS = 2048          # per point, for the oracle timing
+KERNEL_SOURCES = ["pimc_device.hpp", "pimc_kernels.hip", "pimc_internal.hpp", "pimc_tables.hpp", "pimc_math.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_amplitude_quartic64_p18_s10.json")
+
+
+def kernel_source_hash() -> str:
+    """Hash of the estimation kernel's sources: a traffic measurement is valid only for this hash."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        path = os.path.join(ROOT, "paper_1105_0542_amd", "csrc", name)
+        if os.path.exists(path):
+            h.update(name.encode())
+            h.update(open(path, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(samples: int):
+    """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE measurement (scaled by the
+    plain-copy factors), or None when the kernel sources changed since it was taken."""
+    import json as _json
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = _json.load(open(TRAFFIC_FILE))
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec["bytes_per_sample"] * samples
+
+
+def copy_probe():
+    """Plain device copy of known size (512 MiB): the reference for FETCH_SIZE/WRITE_SIZE scaling."""
+    import torch
+    x = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    x.fill_(1.0)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y = x.clone()
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": x.numel() * 8, "copies": 3, "check": float(y[0])}), flush=True)
 
 
 def slices_per_sample(s: int, hierarchy: bool) -> int:
@@ -73,7 +111,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--samples", type=int, default=N_SAMPLES)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true", help="only run the 512 MiB copy used to scale HBM counters")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding of path ranges is a design "
                                    "note only", "n_gpus": args.gpus}))
@@ -144,7 +186,7 @@ def main():
         },
         "roofline": {
             "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+            "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic(args.samples),
             "kernel": "k_amplitude<4, QuarticEval64<18>>", "kernel_avg_ms": kernel_avg_s * 1e3,
             "flop_per_slice": FLOP_PER_SLICE, "flop_per_launch": flop_per_launch,
         },

@@ -33,6 +33,17 @@ constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
 constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
 constexpr int kMaxLevels = 21;          // s <= 20
 
+// Read-only, wave-uniform data (tables, per-level constants) is read through the constant address
+// space: the kernels never write it, so the compiler may use scalar loads (one load per wave,
+// kept in SGPRs) instead of per-lane vector loads.
+template <class T>
+using const_ptr = const __attribute__((address_space(4))) T*;
+
+template <class T>
+__device__ __forceinline__ const_ptr<T> as_const(const T* p) {
+    return (const_ptr<T>)(p);
+}
+
 __device__ __forceinline__ void mulhilo(uint32_t a, uint32_t b, uint32_t& hi, uint32_t& lo) {
     const uint64_t p = uint64_t(a) * uint64_t(b);
     hi = uint32_t(p >> 32);
@@ -126,9 +137,16 @@ template <int P>
 struct QuarticEval64 {
     using Shape = QuarticShape<P>;
     const double* __restrict__ tab;   // level-major, Shape::E doubles per level
+    // Hide the table address from loop-invariant code motion: coefficients are then re-read from
+    // the scalar cache where they are used instead of being hoisted (and spilled) across the path.
+    __device__ __forceinline__ void launder() {
+#ifndef PIMC_NO_LAUNDER
+        asm volatile("" : "+s"(tab));
+#endif
+    }
     template <int W>
     __device__ __forceinline__ void eval(int level, const double (&qa)[W], const double (&qb)[W], double& S) const {
-        const double* __restrict__ t = tab + level * Shape::E;
+        const const_ptr<double> t = as_const(tab) + level * Shape::E;
         double y[W], z[W], acc[W];
 #pragma unroll
         for (int i = 0; i < W; ++i) {
@@ -164,9 +182,14 @@ template <int P>
 struct QuarticEval32 {
     using Shape = QuarticShape<P>;
     const float* __restrict__ tab;
+    __device__ __forceinline__ void launder() {
+#ifndef PIMC_NO_LAUNDER
+        asm volatile("" : "+s"(tab));
+#endif
+    }
     template <int W>
     __device__ __forceinline__ void eval(int level, const double (&qa)[W], const double (&qb)[W], double& S) const {
-        const float* __restrict__ t = tab + level * Shape::E;
+        const const_ptr<float> t = as_const(tab) + level * Shape::E;
         float y[W], z[W], acc[W];
 #pragma unroll
         for (int i = 0; i < W; ++i) {
@@ -202,9 +225,14 @@ struct GenericEval64 {
     const int* __restrict__ deg;      // device, K entries
     int K;
     int stride;
+    __device__ __forceinline__ void launder() {
+#ifndef PIMC_NO_LAUNDER
+        asm volatile("" : "+s"(tab));
+#endif
+    }
     template <int W>
     __device__ __forceinline__ void eval(int level, const double (&qa)[W], const double (&qb)[W], double& S) const {
-        const double* __restrict__ t = tab + level * stride;
+        const const_ptr<double> t = as_const(tab) + level * stride;
         double u[W], z[W], acc[W];
 #pragma unroll
         for (int i = 0; i < W; ++i) {
@@ -217,7 +245,7 @@ struct GenericEval64 {
         // P_k stored consecutively for k = 0..K-1; walk them from the last one.
         int off = stride;
         for (int k = K - 1; k >= 0; --k) {
-            const int d = deg[k];
+            const int d = as_const(deg)[k];
             off -= d + 1;
             double v[W];
             const double c0 = t[off];

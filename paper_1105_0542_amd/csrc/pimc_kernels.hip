@@ -26,7 +26,7 @@ __device__ __forceinline__ void gen_level(const AmpArgs& A, const PathRng& pr, u
                                           double (&q)[(1 << U) + 1]) {
     if constexpr (L <= U) {
         constexpr int step = 1 << (U - L);
-        const double sg = A.sig[D + L];
+        const double sg = as_const(A.sig)[D + L];
 #pragma unroll
         for (int i2 = 0; i2 < (1 << (L - 2)); ++i2) {
             const uint32_t parent = (root << (L - 2)) + uint32_t(i2);   // node of sub-level L-1
@@ -70,13 +70,15 @@ __device__ __forceinline__ void hier_levels(const Eval& ev, int D, const double 
 
 // Subtree rooted at heap node `root` (level D+1) over the level-D slice (qL, qR) with root normal z.
 template <int U, class Eval>
-__device__ __forceinline__ void run_subtree(const Eval& ev, const AmpArgs& A, const PathRng& pr,
+__device__ __forceinline__ void run_subtree(const Eval& ev_in, const AmpArgs& A, const PathRng& pr,
                                             uint32_t root, int D, double qL, double qR, double zroot,
                                             double (&Ssub)[U + 1]) {
+    Eval ev = ev_in;
+    ev.launder();
     double q[(1 << U) + 1];
     q[0] = qL;
     q[1 << U] = qR;
-    q[1 << (U - 1)] = A.sig[D + 1] * zroot + 0.5 * (qL + qR);
+    q[1 << (U - 1)] = as_const(A.sig)[D + 1] * zroot + 0.5 * (qL + qR);
     gen_level<U, 2, Eval>(A, pr, root, D, q);
     if (A.hier) hier_levels<U, 0, Eval>(ev, D, q, Ssub);
     level_sum<U, U, Eval>(ev, D + U, q, Ssub[U]);
@@ -128,7 +130,7 @@ __device__ __forceinline__ void walk_path(const Eval& ev, const AmpArgs& A, uint
                 ev.template eval<1>(L - 1, qa1, qb1, St);
                 top[(L - 1) * kBlock] = St;
             }
-            qm = A.sig[L] * z + 0.5 * (qL + qR);
+            qm = as_const(A.sig)[L] * z + 0.5 * (qL + qR);
             normal_pair(A.key, pr, node, zl, zr);
             if (L == D) break;
             R[(L + 1) * kBlock] = qR;                 // right child of `node`: (qm, qR), normal zr
@@ -147,7 +149,7 @@ __device__ __forceinline__ void walk_path(const Eval& ev, const AmpArgs& A, uint
 // ---------------------------------------------------------------------------- estimation kernel
 __device__ __forceinline__ void reduce_level(const AmpArgs& A, double* acc, int nlev, int wave, int lane,
                                              int n, double S, bool valid) {
-    const double d = valid ? expm1(-(S - A.shift[n])) : 0.0;
+    const double d = valid ? expm1(-(S - as_const(A.shift)[n])) : 0.0;
     const bool bad = valid && !isfinite(d);
     const double sd = wave_sum(d);
     const double sd2 = wave_sum(d * d);
@@ -160,8 +162,12 @@ __device__ __forceinline__ void reduce_level(const AmpArgs& A, double* acc, int 
     }
 }
 
+#ifndef PIMC_WAVES_PER_EU
+#define PIMC_WAVES_PER_EU 2
+#endif
 template <int U, class Eval>
-__global__ void __launch_bounds__(kBlock) k_amplitude(AmpArgs A, Eval ev) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PIMC_WAVES_PER_EU)))
+k_amplitude(AmpArgs A, Eval ev) {
     extern __shared__ double smem[];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
