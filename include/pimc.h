@@ -134,6 +134,13 @@ int pimc_path_actions(pimc_ctx *ctx, const pimc_potential *V, double m, double a
 int pimc_last_partials(pimc_ctx *ctx, uint32_t level, uint64_t first_chunk, uint64_t n_chunks,
                        double *out, uint64_t *chunk_paths, uint64_t *total_chunks, double *shift);
 
+/* Standard normals of the bisection (Sec. 4.1 offsets before scaling by sigma_n): for paths
+ * first_path..first_path+k_paths-1 and heap nodes h = 1..n_nodes, out[path][h-1] = z_h from the
+ * Philox4x32-10 / Box-Muller map stated at the top of this header. out: caller-owned host array
+ * of k_paths*n_nodes doubles. EINVAL if n_nodes == 0 or n_nodes > 2^PIMC_MAX_S - 1. */
+int pimc_normals(pimc_ctx *ctx, uint64_t seed, uint32_t stream, uint64_t first_path, uint64_t k_paths,
+                 uint32_t n_nodes, double *out);
+
 /* Device time of the last estimation kernel on this context, in milliseconds (HIP events on the
  * context's stream around that launch). */
 int pimc_last_kernel_ms(pimc_ctx *ctx, double *ms);

@@ -105,6 +105,8 @@ def load_library():
     lib.pimc_last_partials.restype = C.c_int
     lib.pimc_last_partials.argtypes = [vp, C.c_uint32, C.c_uint64, C.c_uint64, P(C.c_double), P(C.c_uint64),
                                        P(C.c_uint64), P(C.c_double)]
+    lib.pimc_normals.restype = C.c_int
+    lib.pimc_normals.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint64, C.c_uint32, P(C.c_double)]
     lib.pimc_last_kernel_ms.restype = C.c_int
     lib.pimc_last_kernel_ms.argtypes = [vp, P(C.c_double)]
     _lib = lib
@@ -230,6 +232,13 @@ class Context:
                                                 out.ctypes.data_as(C.POINTER(C.c_double)), C.byref(cp),
                                                 C.byref(tc), C.byref(sh)))
         return out, cp.value, tc.value, sh.value
+
+    def normals(self, seed, stream, first_path, k_paths, n_nodes):
+        """pimc_normals -> array [k_paths, n_nodes] of z_h, h = 1..n_nodes."""
+        out = np.zeros((k_paths, n_nodes), dtype=np.float64)
+        self._check(self.lib.pimc_normals(self.h, seed, stream, first_path, k_paths, n_nodes,
+                                          out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
 
     def last_kernel_ms(self) -> float:
         ms = C.c_double(0)

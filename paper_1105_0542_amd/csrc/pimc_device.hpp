@@ -9,7 +9,8 @@
 //    Within one wave the node index j and the stream are uniform, and the path words are constant
 //    over a path: the first two Philox rounds therefore need no per-node vector multiply (their
 //    multiplications are either scalar or hoisted per path), leaving 16 of 20 per-lane 32x32->64
-//    products per call.
+//    products per call; each round's two three-input xors are single v_bitop3 instructions.
+//    ln, sqrt, sin and cos come from pimc_math.hpp (argument-range-specific polynomials).
 //  * Bisection (Sec. 4.1): the point of heap node h (level n = floor(log2 h)+1, offset
 //    i = h - 2^(n-1)) is sigma_n z_h + (left + right)/2 with sigma_n^2 = T/2^(n+1), the conditional
 //    (Brownian-bridge) width that makes the kinetic term and normalizations integrate out to the
@@ -23,6 +24,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "pimc_math.hpp"
 #include "pimc_tables.hpp"
 
 namespace pimc {
@@ -98,8 +100,8 @@ __device__ __forceinline__ void philox_node_pair(const RngKey& key, const PathRn
         uint32_t a_hi, a_lo, b_hi, b_lo;
         mulhilo(kPhiloxM0, c0, a_hi, a_lo);
         mulhilo(kPhiloxM1, c2, b_hi, b_lo);
-        const uint32_t n0 = b_hi ^ c1 ^ k0;
-        const uint32_t n2 = a_hi ^ c3 ^ k1;
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32(b_hi, c1, k0, 0x96);   // b_hi ^ c1 ^ k0
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32(a_hi, c3, k1, 0x96);   // a_hi ^ c3 ^ k1
         c0 = n0;
         c1 = b_lo;
         c2 = n2;
@@ -118,11 +120,9 @@ __device__ __forceinline__ void normal_pair(const RngKey& key, const PathRng& pr
                                             double& z_even, double& z_odd) {
     uint32_t o0, o1, o2, o3;
     philox_node_pair(key, pr, j, o0, o1, o2, o3);
-    const double u1 = odd53(o0, o1);
-    const double u2 = odd53(o2, o3);
-    const double r = sqrt(-2.0 * log(u1));
+    const double r = sqrt_pos(neg2_log_odd53(o0, o1));
     double sn, cs;
-    sincospi(2.0 * u2, &sn, &cs);
+    sincos_2pi(odd53(o2, o3), sn, cs);
     z_even = r * cs;
     z_odd = r * sn;
 }
@@ -139,14 +139,10 @@ struct QuarticEval64 {
     const double* __restrict__ tab;   // level-major, Shape::E doubles per level
     // Hide the table address from loop-invariant code motion: coefficients are then re-read from
     // the scalar cache where they are used instead of being hoisted (and spilled) across the path.
-    __device__ __forceinline__ void launder() {
-#ifndef PIMC_NO_LAUNDER
-        asm volatile("" : "+s"(tab));
-#endif
-    }
+    __device__ __forceinline__ void launder() { asm volatile("" : "+s"(tab)); }
     template <int W>
     __device__ __forceinline__ void eval(int level, const double (&qa)[W], const double (&qb)[W], double& S) const {
-        const const_ptr<double> t = as_const(tab) + level * Shape::E;
+        const_ptr<double> t = as_const(tab) + level * Shape::E;
         double y[W], z[W], acc[W];
 #pragma unroll
         for (int i = 0; i < W; ++i) {
@@ -157,6 +153,8 @@ struct QuarticEval64 {
         }
 #pragma unroll
         for (int k = Shape::K - 1; k >= 0; --k) {
+            // one P_k's coefficients at a time in scalar registers (see launder())
+            asm volatile("" : "+s"(t));
             double v[W];
             const double c0 = t[Shape::off(k)];
 #pragma unroll
@@ -182,11 +180,7 @@ template <int P>
 struct QuarticEval32 {
     using Shape = QuarticShape<P>;
     const float* __restrict__ tab;
-    __device__ __forceinline__ void launder() {
-#ifndef PIMC_NO_LAUNDER
-        asm volatile("" : "+s"(tab));
-#endif
-    }
+    __device__ __forceinline__ void launder() { asm volatile("" : "+s"(tab)); }
     template <int W>
     __device__ __forceinline__ void eval(int level, const double (&qa)[W], const double (&qb)[W], double& S) const {
         const const_ptr<float> t = as_const(tab) + level * Shape::E;
@@ -225,11 +219,7 @@ struct GenericEval64 {
     const int* __restrict__ deg;      // device, K entries
     int K;
     int stride;
-    __device__ __forceinline__ void launder() {
-#ifndef PIMC_NO_LAUNDER
-        asm volatile("" : "+s"(tab));
-#endif
-    }
+    __device__ __forceinline__ void launder() { asm volatile("" : "+s"(tab)); }
     template <int W>
     __device__ __forceinline__ void eval(int level, const double (&qa)[W], const double (&qb)[W], double& S) const {
         const const_ptr<double> t = as_const(tab) + level * stride;

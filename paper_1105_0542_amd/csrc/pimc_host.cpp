@@ -526,6 +526,25 @@ int pimc_last_partials(pimc_ctx* c, uint32_t level, uint64_t first_chunk, uint64
     return PIMC_OK;
 }
 
+int pimc_normals(pimc_ctx* c, uint64_t seed, uint32_t stream, uint64_t first_path, uint64_t k_paths, uint32_t n_nodes,
+                 double* out) {
+    if (!c) { set_thread_error("context is NULL"); return PIMC_EINVAL; }
+    if (n_nodes == 0 || n_nodes > (1u << PIMC_MAX_S) - 1)
+        return ctx_fail(c, PIMC_EINVAL, "n_nodes = %u outside 1..2^%d-1", n_nodes, PIMC_MAX_S);
+    if (k_paths == 0) return PIMC_OK;
+    if (!out) return ctx_fail(c, PIMC_EINVAL, "out is NULL");
+    if (k_paths > (uint64_t(1) << 40) / n_nodes) return ctx_fail(c, PIMC_EINVAL, "request too large");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const size_t bytes = size_t(k_paths) * n_nodes * 8;
+    int st = ensure(c, reinterpret_cast<void**>(&c->d_dump), &c->dump_bytes, bytes);
+    if (st) return st;
+    RngKey key{uint32_t(seed), uint32_t(seed >> 32), stream};
+    HIP_TRY(c, launch_normals(key, first_path, k_paths, n_nodes, c->d_dump, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(out, c->d_dump, bytes, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return PIMC_OK;
+}
+
 int pimc_last_kernel_ms(pimc_ctx* c, double* ms) {
     if (!c || !ms) { set_thread_error("NULL argument"); return PIMC_EINVAL; }
     *ms = c->last_ms;

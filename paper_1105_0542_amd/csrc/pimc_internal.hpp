@@ -35,7 +35,8 @@ struct AmpArgs {
 
 enum class EvalKind { Quartic64, Quartic32, GenericEven64, GenericOdd64 };
 
-// Dynamic LDS bytes of the estimation kernel for a given D and s.
+// Dynamic LDS bytes of the estimation kernel: per lane, 3D+2 slots of the explicit stack; per wave
+// and level, three accumulators.
 inline size_t amp_lds_bytes(int D, int s) {
     return (size_t(3 * D + 2) * kBlock + size_t(4 * (s + 1) * 3)) * sizeof(double);
 }
@@ -43,6 +44,10 @@ inline size_t amp_lds_bytes(int D, int s) {
 // Launch the estimation kernel; p selects the quartic specialization, U = s - D the unrolled
 // subtree depth. Returns hipErrorInvalidValue for an unsupported combination.
 hipError_t launch_amplitude(const AmpArgs& A, EvalKind kind, int p, int U, int grid, hipStream_t st);
+
+// Raw standard normals of heap nodes 1..n_nodes for k_paths paths: out[path][node-1] (device).
+hipError_t launch_normals(const RngKey& key, uint64_t first_path, uint64_t k_paths, uint32_t n_nodes, double* out,
+                          hipStream_t st);
 
 // Sum the canonical chunks of every level in chunk order: out[level][4] (device).
 hipError_t launch_reduce(const double* partials, uint64_t n_chunks, int n_levels, double* out, hipStream_t st);

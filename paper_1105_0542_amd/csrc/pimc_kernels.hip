@@ -18,6 +18,15 @@
 
 #include "pimc_internal.hpp"
 
+// Occupancy target of the estimation kernel (waves per SIMD) and the number of slices evaluated
+// together, coefficient-major (measured best on MI355X at p = 18: 2 waves, all 16 leaves at once).
+#ifndef PIMC_WAVES_PER_EU
+#define PIMC_WAVES_PER_EU 2
+#endif
+#ifndef PIMC_BATCH
+#define PIMC_BATCH 16
+#endif
+
 namespace pimc {
 
 // ---------------------------------------------------------------------------- subtree (registers)
@@ -46,7 +55,7 @@ template <int U, int L, class Eval>
 __device__ __forceinline__ void level_sum(const Eval& ev, int level, const double (&q)[(1 << U) + 1], double& S) {
     constexpr int W = 1 << L;
     constexpr int ST = 1 << (U - L);
-    constexpr int B = W < 8 ? W : 8;
+    constexpr int B = W < PIMC_BATCH ? W : PIMC_BATCH;
 #pragma unroll
     for (int b0 = 0; b0 < W; b0 += B) {
         double qa[B], qb[B];
@@ -162,9 +171,6 @@ __device__ __forceinline__ void reduce_level(const AmpArgs& A, double* acc, int 
     }
 }
 
-#ifndef PIMC_WAVES_PER_EU
-#define PIMC_WAVES_PER_EU 2
-#endif
 template <int U, class Eval>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PIMC_WAVES_PER_EU)))
 k_amplitude(AmpArgs A, Eval ev) {
@@ -223,6 +229,35 @@ k_amplitude(AmpArgs A, Eval ev) {
             __syncthreads();
         }
     }
+}
+
+// ---------------------------------------------------------------------------- raw normals
+// One thread per (path, node pair): nodes 2j and 2j+1 of path first_path + i, written where
+// 1 <= node <= n_nodes.
+__global__ void __launch_bounds__(kBlock) k_normals(RngKey key, uint64_t first_path, uint64_t k_paths,
+                                                    uint32_t n_nodes, double* __restrict__ out) {
+    const uint32_t pairs = n_nodes / 2 + 1;
+    const uint64_t gid = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (gid >= k_paths * pairs) return;
+    const uint64_t i = gid / pairs;
+    const uint32_t j = uint32_t(gid % pairs);
+    const PathRng pr = path_rng(key, first_path + i);
+    double ze, zo;
+    normal_pair(key, pr, j, ze, zo);
+    double* o = out + i * n_nodes;
+    const uint32_t he = 2 * j, ho = 2 * j + 1;
+    if (he >= 1 && he <= n_nodes) o[he - 1] = ze;
+    if (ho <= n_nodes) o[ho - 1] = zo;
+}
+
+hipError_t launch_normals(const RngKey& key, uint64_t first_path, uint64_t k_paths, uint32_t n_nodes, double* out,
+                          hipStream_t st) {
+    const uint64_t work = k_paths * (uint64_t(n_nodes) / 2 + 1);
+    const uint64_t blocks = (work + kBlock - 1) / kBlock;
+    if (blocks == 0) return hipSuccess;
+    if (blocks > 0x7fffffffull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_normals, dim3(uint32_t(blocks)), dim3(kBlock), 0, st, key, first_path, k_paths, n_nodes, out);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------- chunk reduction

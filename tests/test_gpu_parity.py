@@ -59,6 +59,24 @@ def check_actions(ctx, coefs, m, a, b, T, s, p, seed, stream, flags, first, k):
     return got
 
 
+# ------------------------------------------------------------------------- normals (Philox + Box-Muller)
+@pytest.mark.parametrize("seed,stream,first,k,nodes", [
+    (1, 0, 0, 4096, 1023), (0xDEADBEEFCAFE, 7, (1 << 40) + 3, 512, 127), (5, 2**31 + 9, 123456789, 2000, 15),
+])
+def test_normals_match_oracle(ctx, seed, stream, first, k, nodes):
+    """Device normals vs the oracle's (numpy log/sqrt/cos/sin in FP64) on the same counters: the
+    uniforms are identical bits, the elementary functions agree to a few ulp."""
+    _log(f"normals seed={seed} stream={stream} first={first} k={k} nodes={nodes}")
+    got = ctx.normals(seed, stream, first, k, nodes)
+    from oracle.philox import node_normals
+    idx = np.arange(first, first + k, dtype=np.uint64)
+    ref = np.stack([node_normals(seed, stream, idx, np.uint64(h)) for h in range(1, nodes + 1)], axis=1)
+    # the oracle forms the angle 2*pi*u rounded (up to ~4e-16 absolute), so near zero crossings the
+    # comparison is absolute; elsewhere relative
+    err = np.abs(got - ref) / np.maximum(np.abs(ref), 1.0)
+    assert err.max() < 1e-14, err.max()
+
+
 # ------------------------------------------------------------------------- C1 (N=16, p=4, 1e5)
 def test_c1_path_actions_all_paths(ctx):
     check_actions(ctx, P.quartic(1, 1), 1.0, 0.0, 1.0, 1.0, 4, 4, 1, 0, P.FLAG_HIERARCHY, 0, 100000)
