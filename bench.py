@@ -34,6 +34,8 @@ E_TABLE = {18: 48}
 FLOP_PER_SLICE = 2 * (E_TABLE[P_LEVEL] - 1) + 6
 FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector: 256 CU x 64 lanes x 2 FLOP x 2.4 GHz
 CPU_SAMPLE_PATHS = 2048          # per point, for the oracle timing
+# Precision workload: FP32 slice polynomials against FP64, g = 10, p = 18, N = 512, T = 1.
+PREC = dict(g=10.0, p=18, s=9, T=1.0, samples=1_000_000_000, oracle_paths=20_000)
 KERNEL_SOURCES = ["pimc_device.hpp", "pimc_kernels.hip", "pimc_internal.hpp", "pimc_tables.hpp", "pimc_math.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_amplitude_quartic64_p18_s10.json")
 
@@ -88,6 +90,29 @@ def _oracle_worker(args):
     return float(S[:, S_DEPTH].sum())
 
 
+def _oracle_chunk(args):
+    g, T, s, p, first, count, shift = args
+    from oracle import effective_action as ea
+    from oracle import pimc as opimc
+    return opimc.chunk_sums(ea.quartic(1, g), 1, 0.0, 1.0, T, s, p, 1, 0, first, count, shift)
+
+
+def oracle_precision_reference():
+    """Oracle amplitude at level s of the precision workload on its first paths (shifted sums)."""
+    import multiprocessing as mp
+    import numpy as np
+    from oracle import effective_action as ea
+    from oracle import pimc as opimc
+    g, T, s, p, n = PREC["g"], PREC["T"], PREC["s"], PREC["p"], PREC["oracle_paths"]
+    shift = opimc.straight_line_actions(ea.quartic(1, g), 1, 0.0, 1.0, T, s, p)
+    jobs = [(g, T, s, p, st, min(1000, n - st), shift) for st in range(0, n, 1000)]
+    with mp.get_context("fork").Pool(min(len(os.sched_getaffinity(0)), 16)) as pool:
+        parts = pool.map(_oracle_chunk, jobs)
+    tot = np.sum(parts, axis=0)[s]
+    K0 = opimc.free_kernel(0.0, 1.0, T)
+    return K0 * math.exp(-shift[s]) * (1.0 + tot[1] / tot[0])
+
+
 def cpu_baseline(paths_per_point: int):
     """The oracle as it stands, on the host cores: level actions of the first paths of each point."""
     import multiprocessing as mp
@@ -111,6 +136,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--samples", type=int, default=N_SAMPLES)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision-samples", type=int, default=PREC["samples"])
     ap.add_argument("--copy-probe", action="store_true", help="only run the 512 MiB copy used to scale HBM counters")
     args = ap.parse_args()
     if args.copy_probe:
@@ -123,6 +149,7 @@ def main():
 
     # The oracle runs first, in worker processes forked before this process touches the GPU.
     cpu = None if args.no_cpu_baseline else cpu_baseline(CPU_SAMPLE_PATHS)
+    prec_ref = None if args.no_cpu_baseline else oracle_precision_reference()
 
     import paper_1105_0542_amd as P
 
@@ -164,6 +191,33 @@ def main():
     ms_s = ctx.last_kernel_ms()
     level_s_rate = args.samples * slices_per_sample(S_DEPTH, False) / (ms_s / 1e3)
 
+    # precision workload: FP64 and FP32 slice polynomials on identical samples (level s only)
+    prec = {}
+    g, pp, ss, TT, ns = PREC["g"], PREC["p"], PREC["s"], PREC["T"], args.precision_samples
+    for name, fl in (("fp64", 0), ("fp32", P.FLAG_FP32_POLY)):
+        r, _ = ctx.amplitude(P.quartic(1.0, g), 1.0, 0.0, 1.0, TT, 1 << ss, pp, ns, 1, 0, fl)
+        ms = ctx.last_kernel_ms()
+        prec[name] = {"A_512": r[ss].amp, "err": r[ss].err, "slice_evals_per_s": ns * (1 << ss) / (ms / 1e3),
+                      "kernel_ms": ms}
+    small = {}
+    for name, fl in (("fp64", 0), ("fp32", P.FLAG_FP32_POLY)):
+        r, _ = ctx.amplitude(P.quartic(1.0, g), 1.0, 0.0, 1.0, TT, 1 << ss, pp, PREC["oracle_paths"], 1, 0, fl)
+        small[name] = r[ss].amp
+    prec_line = {
+        "workload": f"V=q^2/2+{g:g} q^4/24, p={pp}, N={1 << ss}, T={TT:g}, a=0, b=1, {ns:.0e} samples, level s only",
+        "fp64": prec["fp64"], "fp32": prec["fp32"],
+        "rel_diff_fp32_vs_fp64_gpu": abs(prec["fp32"]["A_512"] - prec["fp64"]["A_512"]) / prec["fp64"]["A_512"],
+        "rel_stat_err": prec["fp64"]["err"] / prec["fp64"]["A_512"],
+        "fp32_frac_of_fp32_peak": prec["fp32"]["slice_evals_per_s"] * FLOP_PER_SLICE / 1e12 / 157.3,
+        "note": "FP32 polynomials run as non-packed FP32 (packed FP32 instructions are disabled in this build), "
+                "whose issue rate equals FP64 on MI355X; the 157.3 TFLOP/s FP32 peak needs packed FP32",
+    }
+    if prec_ref is not None:
+        prec_line[f"oracle_first_{PREC['oracle_paths']}"] = {
+            "A_512": prec_ref,
+            "rel_diff_fp64_gpu": abs(small["fp64"] - prec_ref) / prec_ref,
+            "rel_diff_fp32_gpu": abs(small["fp32"] - prec_ref) / prec_ref}
+
     line = {
         "metric": "slice-evals/s (p=18, FP64)",
         "value": value,
@@ -197,6 +251,7 @@ def main():
                                           "relvar": r[S_DEPTH].relvar, "nonfinite": r[S_DEPTH].n_nonfinite}
                     for (g, T, r) in last},
     }
+    line["precision"] = prec_line
     if cpu is not None:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)

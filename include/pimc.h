@@ -141,6 +141,53 @@ int pimc_last_partials(pimc_ctx *ctx, uint32_t level, uint64_t first_chunk, uint
 int pimc_normals(pimc_ctx *ctx, uint64_t seed, uint32_t stream, uint64_t first_path, uint64_t k_paths,
                  uint32_t n_nodes, double *out);
 
+/* ---- batches: whole grids of endpoints with mixed N, p, T in one graph launch ------------------- */
+
+/* One amplitude of a batch: potential systems[system] with mass m, A_N^(p)(a, b; T) estimated from
+ * n_samples paths with path indices 0..n_samples-1 on Philox stream `stream` (the batch's seed).
+ * Batches use the specialized kernels: the potential must be even with degree <= 4 (the paper's
+ * anharmonic oscillator family, Sec. 3.3) and N >= 16. */
+typedef struct {
+    uint32_t system;
+    double m, a, b, T;
+    uint32_t N;
+    int p;
+    uint64_t n_samples;
+    uint32_t stream;
+} pimc_task;
+
+typedef struct pimc_batch pimc_batch;
+
+/* Plan a batch: validates every task, builds one table set per (system, m, p, T), numbers every
+ * task's canonical chunks (the same chunks as a single pimc_amplitude call, so a task's result is
+ * bitwise the single-call result), uploads everything and captures one HIP graph: queue reset, one
+ * persistent launch per distinct p, the canonical reduction and the copy of the sums to pinned host
+ * memory. flags: 0 or PIMC_HIERARCHY (FP64 only). The batch owns its device memory and stream. */
+int pimc_batch_create(pimc_ctx *ctx, const pimc_potential *systems, int n_systems, const pimc_task *tasks,
+                      size_t n_tasks, uint64_t seed, uint32_t flags, pimc_batch **out);
+
+/* Replay the graph once and assemble every task: out[task * (s_max+1) + n] for level n (s_max the
+ * largest s of the batch; levels a task does not estimate have n = 0). *ms (may be NULL): device
+ * time of the replay. Returns PIMC_WNONFINITE if any task had non-finite weights. */
+int pimc_batch_run(pimc_batch *batch, pimc_level_result *out, double *ms);
+
+/* Launch shape of the persistent kernels: grid = resident workgroups * grid_mult_x2 / 2
+ * (grid_mult_x2 in 1..8), each queue grab takes `grab` consecutive chunks (1..64). Changes only
+ * scheduling: results are bitwise identical for every setting. Re-captures the graph. */
+int pimc_batch_set_tuning(pimc_batch *batch, int grid_mult_x2, uint32_t grab);
+
+/* Time every candidate launch shape with one replay each, keep the fastest, and append it to the
+ * text cache file cache_path (may be NULL) under a key of (GPU architecture, p values, largest s,
+ * flags); a later call with a matching key reuses the cached choice without timing. */
+int pimc_batch_autotune(pimc_batch *batch, const char *cache_path, int *grid_mult_x2, uint32_t *grab);
+
+int pimc_batch_destroy(pimc_batch *batch);
+const char *pimc_batch_last_error(const pimc_batch *batch);
+
+/* Create, run once and destroy: out as in pimc_batch_run. */
+int pimc_amplitude_batch(pimc_ctx *ctx, const pimc_potential *systems, int n_systems, const pimc_task *tasks,
+                         size_t n_tasks, uint64_t seed, uint32_t flags, pimc_level_result *out);
+
 /* Device time of the last estimation kernel on this context, in milliseconds (HIP events on the
  * context's stream around that launch). */
 int pimc_last_kernel_ms(pimc_ctx *ctx, double *ms);

@@ -39,6 +39,11 @@ class Potential(C.Structure):
     _fields_ = [("degree", C.c_int), ("coef", C.c_double * (MAX_DEGREE + 1))]
 
 
+class Task(C.Structure):
+    _fields_ = [("system", C.c_uint32), ("m", C.c_double), ("a", C.c_double), ("b", C.c_double), ("T", C.c_double),
+                ("N", C.c_uint32), ("p", C.c_int), ("n_samples", C.c_uint64), ("stream", C.c_uint32)]
+
+
 class _LevelResult(C.Structure):
     _fields_ = [("amp", C.c_double), ("err", C.c_double), ("log_amp", C.c_double), ("relvar", C.c_double),
                 ("ess", C.c_double), ("n", C.c_uint64), ("n_nonfinite", C.c_uint64)]
@@ -107,6 +112,21 @@ def load_library():
                                        P(C.c_uint64), P(C.c_double)]
     lib.pimc_normals.restype = C.c_int
     lib.pimc_normals.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint64, C.c_uint32, P(C.c_double)]
+    lib.pimc_batch_create.restype = C.c_int
+    lib.pimc_batch_create.argtypes = [vp, P(Potential), C.c_int, P(Task), C.c_size_t, C.c_uint64, C.c_uint32, P(vp)]
+    lib.pimc_batch_run.restype = C.c_int
+    lib.pimc_batch_run.argtypes = [vp, P(_LevelResult), P(C.c_double)]
+    lib.pimc_batch_set_tuning.restype = C.c_int
+    lib.pimc_batch_set_tuning.argtypes = [vp, C.c_int, C.c_uint32]
+    lib.pimc_batch_autotune.restype = C.c_int
+    lib.pimc_batch_autotune.argtypes = [vp, C.c_char_p, P(C.c_int), P(C.c_uint32)]
+    lib.pimc_batch_destroy.restype = C.c_int
+    lib.pimc_batch_destroy.argtypes = [vp]
+    lib.pimc_batch_last_error.restype = C.c_char_p
+    lib.pimc_batch_last_error.argtypes = [vp]
+    lib.pimc_amplitude_batch.restype = C.c_int
+    lib.pimc_amplitude_batch.argtypes = [vp, P(Potential), C.c_int, P(Task), C.c_size_t, C.c_uint64, C.c_uint32,
+                                         P(_LevelResult)]
     lib.pimc_last_kernel_ms.restype = C.c_int
     lib.pimc_last_kernel_ms.argtypes = [vp, P(C.c_double)]
     _lib = lib
@@ -244,3 +264,68 @@ class Context:
         ms = C.c_double(0)
         self._check(self.lib.pimc_last_kernel_ms(self.h, C.byref(ms)))
         return ms.value
+
+
+_RESULT_DTYPE = np.dtype([("amp", "f8"), ("err", "f8"), ("log_amp", "f8"), ("relvar", "f8"), ("ess", "f8"),
+                          ("n", "u8"), ("n_nonfinite", "u8")])
+
+
+def make_tasks(rows) -> "C.Array":
+    """Task array from an iterable of (system, m, a, b, T, N, p, n_samples, stream)."""
+    rows = list(rows)
+    arr = (Task * len(rows))()
+    for i, r in enumerate(rows):
+        arr[i] = Task(*r)
+    return arr
+
+
+class Batch:
+    """pimc_batch_create / run / set_tuning / autotune / destroy."""
+
+    def __init__(self, ctx: Context, systems, tasks, seed: int, flags: int = 0):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        pots = (Potential * len(systems))(*[potential_from_coefs(c) for c in systems])
+        self.tasks = tasks if isinstance(tasks, C.Array) else make_tasks(tasks)
+        self.n_tasks = len(self.tasks)
+        self.s_max = max(int(t.N).bit_length() - 1 for t in self.tasks)
+        h = C.c_void_p()
+        st = self.lib.pimc_batch_create(ctx.h, pots, len(systems), self.tasks, self.n_tasks, seed, flags, C.byref(h))
+        if st != PIMC_OK:
+            raise _err(self.lib, ctx.h, st)
+        self.h = h
+        self._out = (_LevelResult * (self.n_tasks * (self.s_max + 1)))()
+
+    def _check(self, st):
+        if st < 0:
+            msg = self.lib.pimc_batch_last_error(self.h)
+            raise PimcError(st, (msg or b"").decode())
+        return st
+
+    def run(self):
+        """One graph replay -> (structured array [n_tasks, s_max+1], device ms, status)."""
+        ms = C.c_double(0)
+        st = self._check(self.lib.pimc_batch_run(self.h, self._out, C.byref(ms)))
+        arr = np.frombuffer(self._out, dtype=_RESULT_DTYPE).reshape(self.n_tasks, self.s_max + 1).copy()
+        return arr, ms.value, st
+
+    def set_tuning(self, grid_mult_x2: int, grab: int):
+        self._check(self.lib.pimc_batch_set_tuning(self.h, grid_mult_x2, grab))
+
+    def autotune(self, cache_path=None):
+        g = C.c_int(0)
+        gr = C.c_uint32(0)
+        self._check(self.lib.pimc_batch_autotune(self.h, cache_path.encode() if cache_path else None, C.byref(g),
+                                                 C.byref(gr)))
+        return g.value, gr.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pimc_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

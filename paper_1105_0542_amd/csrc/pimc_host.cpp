@@ -5,6 +5,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <thread>
+#include <tuple>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -41,11 +46,14 @@ struct pimc_ctx {
     void* d_prm = nullptr;          size_t prm_bytes = 0;
     double* d_partials = nullptr;   size_t partial_bytes = 0;
     double* d_red = nullptr;        size_t red_bytes = 0;
+    uint64_t* d_seg = nullptr;      size_t seg_bytes = 0;
+    std::vector<uint64_t> h_seg;    // segment base/len of the last reduction (kept alive for the async copy)
     double* d_dump = nullptr;       size_t dump_bytes = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // last estimation
     uint64_t last_chunks = 0, last_chunk_paths = 0;
     int last_s = -1;
+    bool last_hier = false;
     std::vector<double> last_shift;
     double last_ms = 0.0;
 };
@@ -135,6 +143,57 @@ std::vector<int> quartic_xdegrees(int p) {
     return x;
 }
 
+// K_0(a,b;T) = (2 pi T)^(-1/2) exp(-(b-a)^2/(2T)): the free kernel (W = 0 in the ideal-action form,
+// Sec. 2.1), the prefactor of every estimate.
+double free_kernel(double a, double b, double T) {
+    return std::exp(-(b - a) * (b - a) / (2.0 * T)) / std::sqrt(2.0 * M_PI * T);
+}
+
+// Potential part of eq.(SNp) on the straight line from a to b at level n (2^n slices).
+double straight_line_action(const LevelTable& lt, double a, double b, int n) {
+    const int M = 1 << n;
+    double acc = 0.0;
+    for (int k = 0; k < M; ++k) {
+        const double q0 = a + (b - a) * double(k) / double(M);
+        const double q1 = a + (b - a) * double(k + 1) / double(M);
+        acc += eval_level(lt, q0, q1);
+    }
+    return acc;
+}
+
+// Amplitude, error and diagnostics of one level from its canonical sums red = (n, sum d, sum d^2,
+// non-finite count), with log of the prefactor K_0 sqrt(m) e^{-S_ref}. Returns true when the
+// result is not finite.
+bool assemble_level(const double* red, double logbase, pimc_level_result& r) {
+    const double cnt = red[0];
+    const double sd = red[1];
+    const double sd2 = red[2];
+    const double nb = red[3];
+    const double mean = sd / cnt;
+    double var;
+    if (std::isnan(sd) || std::isnan(sd2)) {
+        var = std::numeric_limits<double>::quiet_NaN();
+    } else if (!std::isfinite(sd2)) {
+        var = std::numeric_limits<double>::infinity();   // second moment beyond FP64 range
+    } else {
+        var = (sd2 - sd * mean) / (cnt - 1.0);               // sd*mean <= sd2: no overflow
+        if (var < 0) var = 0;
+    }
+    const double base = std::exp(logbase);
+    r.amp = base * (1.0 + mean);
+    r.err = base * std::sqrt(var / cnt);
+    r.log_amp = logbase + std::log1p(mean);
+    r.relvar = var / ((1.0 + mean) * (1.0 + mean));
+    const double sw = cnt + sd;
+    const double sw2 = cnt + 2.0 * sd + sd2;
+    // one weight beyond the FP64 range of its square dominates the sum: ESS is 1
+    r.ess = !std::isfinite(sw2) && std::isfinite(sw) ? 1.0 : (sw2 > 0 ? sw * sw / sw2 : 0.0);
+    r.n = uint64_t(cnt);
+    r.n_nonfinite = uint64_t(nb);
+    return nb > 0 || !std::isfinite(r.amp) || !std::isfinite(r.err);
+}
+
+
 int build_problem(const pimc_potential* V, double m, double a, double b, double T, uint32_t N, int p,
                   uint32_t flags, Problem& P, char* why, size_t whylen) {
     P.s = log2_exact(N);
@@ -144,7 +203,7 @@ int build_problem(const pimc_potential* V, double m, double a, double b, double 
     P.a = a * sm;
     P.b = b * sm;
     P.pref = sm;
-    P.K0 = std::exp(-(P.b - P.a) * (P.b - P.a) / (2.0 * T)) / std::sqrt(2.0 * M_PI * T);
+    P.K0 = free_kernel(P.a, P.b, T);
     const PolyD Vt = rescaled_potential(V, m);
     P.even = potential_is_even(Vt);
     const int dV = int(Vt.size()) - 1;
@@ -195,16 +254,7 @@ int build_problem(const pimc_potential* V, double m, double a, double b, double 
     P.sig.assign(size_t(P.s + 1), 0.0);
     for (int n = 1; n <= P.s; ++n) P.sig[size_t(n)] = std::sqrt(T / std::ldexp(1.0, n + 1));
     P.shift.assign(size_t(P.s + 1), 0.0);
-    for (int n = 0; n <= P.s; ++n) {
-        const int M = 1 << n;
-        double acc = 0.0;
-        for (int k = 0; k < M; ++k) {
-            const double q0 = P.a + (P.b - P.a) * double(k) / double(M);
-            const double q1 = P.a + (P.b - P.a) * double(k + 1) / double(M);
-            acc += eval_level(levels[size_t(n)], q0, q1);
-        }
-        P.shift[size_t(n)] = acc;
-    }
+    for (int n = 0; n <= P.s; ++n) P.shift[size_t(n)] = straight_line_action(levels[size_t(n)], P.a, P.b, n);
     P.level0_action = P.shift[0];
     return PIMC_OK;
 }
@@ -367,6 +417,7 @@ int pimc_destroy(pimc_ctx* c) {
     (void)hipFree(c->d_prm);
     (void)hipFree(c->d_partials);
     (void)hipFree(c->d_red);
+    (void)hipFree(c->d_seg);
     (void)hipFree(c->d_dump);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
@@ -391,8 +442,8 @@ int pimc_amplitude(pimc_ctx* c, const pimc_potential* V, double m, double a, dou
     const bool hier = (flags & PIMC_HIERARCHY) != 0;
     for (int n = 0; n < nlev; ++n) out[n] = pimc_level_result{};
     // level 0: the analytic short-time amplitude (Sec. 4.2), error 0
-    out[0].amp = P.pref * P.K0 * std::exp(-P.level0_action);
     out[0].log_amp = std::log(P.pref * P.K0) - P.level0_action;
+    out[0].amp = std::exp(out[0].log_amp);
     out[0].n = n_samples;
     out[0].ess = double(n_samples);
     c->last_s = P.s;
@@ -405,10 +456,19 @@ int pimc_amplitude(pimc_ctx* c, const pimc_potential* V, double m, double a, dou
     const uint32_t ppl = paths_per_lane(P.s);
     const uint64_t chunk_paths = uint64_t(kBlock) * ppl;
     const uint64_t n_chunks = (n_samples + chunk_paths - 1) / chunk_paths;
-    st = ensure(c, reinterpret_cast<void**>(&c->d_partials), &c->partial_bytes, size_t(nlev) * n_chunks * 4 * 8);
+    const int slots = hier ? nlev : 1;            // partial slot of level n: n, or 0 for level s alone
+    st = ensure(c, reinterpret_cast<void**>(&c->d_partials), &c->partial_bytes, size_t(slots) * n_chunks * 4 * 8);
     if (st) return st;
-    st = ensure(c, reinterpret_cast<void**>(&c->d_red), &c->red_bytes, size_t(nlev) * 4 * 8);
+    st = ensure(c, reinterpret_cast<void**>(&c->d_red), &c->red_bytes, size_t(slots) * 4 * 8);
     if (st) return st;
+    st = ensure(c, reinterpret_cast<void**>(&c->d_seg), &c->seg_bytes, size_t(slots) * 2 * 8);
+    if (st) return st;
+    c->h_seg.assign(size_t(slots) * 2, 0);
+    for (int k = 0; k < slots; ++k) {
+        c->h_seg[size_t(k)] = uint64_t(k) * n_chunks * 4;
+        c->h_seg[size_t(slots + k)] = n_chunks;
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->d_seg, c->h_seg.data(), c->h_seg.size() * 8, hipMemcpyHostToDevice, c->stream));
     A.first_path = 0;
     A.n_paths = n_samples;
     A.n_chunks = n_chunks;
@@ -420,8 +480,8 @@ int pimc_amplitude(pimc_ctx* c, const pimc_potential* V, double m, double a, dou
     HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
     HIP_TRY(c, launch_amplitude(A, P.kind, P.p, P.U, grid, c->stream));
     HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
-    HIP_TRY(c, launch_reduce(c->d_partials, n_chunks, nlev, c->d_red, c->stream));
-    std::vector<double> red(size_t(nlev) * 4);
+    HIP_TRY(c, launch_seg_reduce(c->d_partials, c->d_seg, c->d_seg + slots, uint64_t(slots), c->d_red, c->stream));
+    std::vector<double> red(size_t(slots) * 4);
     HIP_TRY(c, hipMemcpyAsync(red.data(), c->d_red, red.size() * 8, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     float ms = 0.f;
@@ -429,37 +489,12 @@ int pimc_amplitude(pimc_ctx* c, const pimc_potential* V, double m, double a, dou
     c->last_ms = ms;
     c->last_chunks = n_chunks;
     c->last_chunk_paths = chunk_paths;
+    c->last_hier = hier;
     bool nonfinite = false;
     for (int n = 1; n < nlev; ++n) {
         if (!hier && n != P.s) continue;
-        const double cnt = red[size_t(n) * 4 + 0];
-        const double sd = red[size_t(n) * 4 + 1];
-        const double sd2 = red[size_t(n) * 4 + 2];
-        const double nb = red[size_t(n) * 4 + 3];
-        const double mean = sd / cnt;
-        double var;
-        if (std::isnan(sd) || std::isnan(sd2)) {
-            var = std::numeric_limits<double>::quiet_NaN();
-        } else if (!std::isfinite(sd2)) {
-            var = std::numeric_limits<double>::infinity();   // second moment beyond FP64 range
-        } else {
-            var = (sd2 - sd * mean) / (cnt - 1.0);               // sd*mean <= sd2: no overflow
-            if (var < 0) var = 0;
-        }
-        const double logbase = std::log(P.pref * P.K0) - P.shift[size_t(n)];
-        const double base = std::exp(logbase);
-        pimc_level_result& r = out[n];
-        r.amp = base * (1.0 + mean);
-        r.err = base * std::sqrt(var / cnt);
-        r.log_amp = logbase + std::log1p(mean);
-        r.relvar = var / ((1.0 + mean) * (1.0 + mean));
-        const double sw = cnt + sd;
-        const double sw2 = cnt + 2.0 * sd + sd2;
-        // one weight beyond the FP64 range of its square dominates the sum: ESS is 1
-        r.ess = !std::isfinite(sw2) && std::isfinite(sw) ? 1.0 : (sw2 > 0 ? sw * sw / sw2 : 0.0);
-        r.n = uint64_t(cnt);
-        r.n_nonfinite = uint64_t(nb);
-        if (nb > 0 || !std::isfinite(r.amp) || !std::isfinite(r.err)) nonfinite = true;
+        const size_t k = size_t(hier ? n : 0);
+        if (assemble_level(&red[k * 4], std::log(P.pref * P.K0) - P.shift[size_t(n)], out[n])) nonfinite = true;
     }
     return nonfinite ? PIMC_WNONFINITE : PIMC_OK;
 }
@@ -512,6 +547,9 @@ int pimc_last_partials(pimc_ctx* c, uint32_t level, uint64_t first_chunk, uint64
     if (!c) { set_thread_error("context is NULL"); return PIMC_EINVAL; }
     if (c->last_s < 1 || !c->d_partials) return ctx_fail(c, PIMC_EINVAL, "no estimation has run on this context");
     if (int(level) > c->last_s) return ctx_fail(c, PIMC_EINVAL, "level %u > s = %d", level, c->last_s);
+    if (!c->last_hier && int(level) != c->last_s)
+        return ctx_fail(c, PIMC_EINVAL, "the last run estimated level %d only", c->last_s);
+    const uint64_t slot = c->last_hier ? level : 0;
     if (first_chunk + n_chunks > c->last_chunks || first_chunk + n_chunks < first_chunk)
         return ctx_fail(c, PIMC_EINVAL, "chunks out of range (%llu total)", (unsigned long long)c->last_chunks);
     if (chunk_paths) *chunk_paths = c->last_chunk_paths;
@@ -520,7 +558,7 @@ int pimc_last_partials(pimc_ctx* c, uint32_t level, uint64_t first_chunk, uint64
     if (n_chunks == 0) return PIMC_OK;
     if (!out) return ctx_fail(c, PIMC_EINVAL, "out is NULL");
     HIP_TRY(c, hipSetDevice(c->device));
-    const double* src = c->d_partials + (uint64_t(level) * c->last_chunks + first_chunk) * 4;
+    const double* src = c->d_partials + (slot * c->last_chunks + first_chunk) * 4;
     HIP_TRY(c, hipMemcpyAsync(out, src, n_chunks * 4 * 8, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return PIMC_OK;
@@ -549,6 +587,425 @@ int pimc_last_kernel_ms(pimc_ctx* c, double* ms) {
     if (!c || !ms) { set_thread_error("NULL argument"); return PIMC_EINVAL; }
     *ms = c->last_ms;
     return PIMC_OK;
+}
+
+}  // extern "C"
+
+// ============================================================================================ batch
+struct pimc_batch {
+    pimc_ctx* ctx = nullptr;
+    hipStream_t stream = nullptr;              // capture/replay stream (owned)
+    uint32_t flags = 0;
+    uint64_t seed = 0;
+    int s_max = 0;
+    size_t n_tasks = 0;
+    // per task (caller order)
+    std::vector<int> t_s;
+    std::vector<double> t_logpref;             // log(sqrt(m) K_0) after the mass rescaling
+    std::vector<double> t_level0;              // T W_p at level 0
+    std::vector<uint64_t> t_n;
+    std::vector<std::vector<double>> t_shift;  // S_ref,n
+    std::vector<uint64_t> t_seg;               // first segment of the task
+    // p classes
+    struct Class {
+        int p;
+        int n_tasks;
+        size_t first;                          // first position in the device task array
+        uint64_t n_items;
+        size_t lds;
+        int resident;
+    };
+    std::vector<Class> classes;
+    // device
+    void* d_blob = nullptr;
+    BatchTask* d_tasks = nullptr;
+    double* d_partials = nullptr;
+    uint64_t* d_seg = nullptr;
+    double* d_red = nullptr;
+    unsigned long long* d_queue = nullptr;
+    double* h_red = nullptr;                   // pinned
+    uint64_t n_seg = 0;
+    // graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int grid_mult_x2 = 2;                      // grid = resident * grid_mult_x2 / 2
+    uint32_t grab = 1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    double last_ms = 0.0;
+    char err[512] = "";
+};
+
+namespace {
+
+int batch_fail(pimc_batch* b, int status, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (b) std::snprintf(b->err, sizeof(b->err), "%s", buf);
+    if (b && b->ctx) std::snprintf(b->ctx->err, sizeof(b->ctx->err), "%s", buf);
+    std::snprintf(g_thread_error, sizeof(g_thread_error), "%s", buf);
+    return status;
+}
+
+#define HIP_TRY_B(b, expr)                                                                      \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return batch_fail((b), PIMC_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+void destroy_graph(pimc_batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+// Capture: reset the queues (a fill kernel, no memset node), one persistent launch per p class,
+// the canonical reduction, and the copy of the sums to pinned host memory.
+int capture_graph(pimc_batch* b) {
+    destroy_graph(b);
+    HIP_TRY_B(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = launch_fill_u64(b->d_queue, int(b->classes.size()), 0ull, b->stream);
+    RngKey key{uint32_t(b->seed), uint32_t(b->seed >> 32), 0u};
+    const int hier = (b->flags & PIMC_HIERARCHY) ? 1 : 0;
+    for (size_t k = 0; k < b->classes.size() && e == hipSuccess; ++k) {
+        const auto& C = b->classes[k];
+        const int grid = std::max(1, C.resident * b->grid_mult_x2 / 2);
+        e = launch_batch(b->d_tasks + C.first, C.n_tasks, C.n_items, b->d_queue + k, b->grab, key, hier, C.p, grid,
+                         C.lds, b->stream);
+    }
+    if (e == hipSuccess)
+        e = launch_seg_reduce(b->d_partials, b->d_seg, b->d_seg + b->n_seg, b->n_seg, b->d_red, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->h_red, b->d_red, b->n_seg * 4 * 8, hipMemcpyDeviceToHost, b->stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+    if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return batch_fail(b, PIMC_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    }
+    if (e2 != hipSuccess) return batch_fail(b, PIMC_EDEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(e2));
+    b->graph = g;
+    HIP_TRY_B(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    return PIMC_OK;
+}
+
+int check_task(const pimc_task& t, int n_systems) {
+    if (t.system >= uint32_t(n_systems)) { set_thread_error("task system %u >= %d", t.system, n_systems); return PIMC_EINVAL; }
+    return PIMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pimc_batch_create(pimc_ctx* c, const pimc_potential* systems, int n_systems, const pimc_task* tasks, size_t n_tasks,
+                      uint64_t seed, uint32_t flags, pimc_batch** out) {
+    if (!out) { set_thread_error("out is NULL"); return PIMC_EINVAL; }
+    *out = nullptr;
+    if (!c) { set_thread_error("context is NULL"); return PIMC_EINVAL; }
+    if (!systems || n_systems < 1 || !tasks || n_tasks == 0) return ctx_fail(c, PIMC_EINVAL, "empty batch");
+    if (flags & ~uint32_t(PIMC_HIERARCHY))
+        return ctx_fail(c, (flags & PIMC_FP32_POLY) ? PIMC_EUNSUPPORTED : PIMC_EINVAL,
+                        "batches support the FP64 path with or without PIMC_HIERARCHY");
+    if (n_tasks > (size_t(1) << 31)) return ctx_fail(c, PIMC_EINVAL, "too many tasks");
+    for (size_t i = 0; i < n_tasks; ++i) {
+        const pimc_task& t = tasks[i];
+        int st = check_task(t, n_systems);
+        if (!st) st = check_args(&systems[t.system], t.m, t.a, t.b, t.T, t.N, t.p, t.n_samples);
+        if (st) return ctx_fail(c, st, "task %zu: %s", i, g_thread_error);
+        if (t.N < 16) return ctx_fail(c, PIMC_EUNSUPPORTED, "task %zu: batches need N >= 16", i);
+        const PolyD V = rescaled_potential(&systems[t.system], t.m);
+        if (!potential_is_even(V) || V.size() > 5)
+            return ctx_fail(c, PIMC_EUNSUPPORTED, "task %zu: batches need an even potential of degree <= 4", i);
+    }
+    HIP_TRY(c, hipSetDevice(c->device));
+    pimc_batch* b = new (std::nothrow) pimc_batch();
+    if (!b) return ctx_fail(c, PIMC_ENOMEM, "out of host memory");
+    b->ctx = c;
+    b->flags = flags;
+    b->seed = seed;
+    b->n_tasks = n_tasks;
+    const bool hier = (flags & PIMC_HIERARCHY) != 0;
+    auto fail = [&](int st) { pimc_batch_destroy(b); return st; };
+
+    // ---- tables per (system, mass, p, T), levels 0..s_max of that combination
+    using Key = std::tuple<uint32_t, double, int, double>;
+    std::map<Key, int> combo_smax;
+    for (size_t i = 0; i < n_tasks; ++i) {
+        const Key k{tasks[i].system, tasks[i].m, tasks[i].p, tasks[i].T};
+        combo_smax[k] = std::max(combo_smax[k], log2_exact(tasks[i].N));
+    }
+    std::map<std::tuple<uint32_t, double, int>, Coefficients> coef_cache;
+    std::map<Key, size_t> combo_off;                         // offset (doubles) of level 0 in the blob
+    std::map<Key, std::vector<LevelTable>> combo_levels;
+    std::vector<double> blob;
+    for (const auto& kv : combo_smax) {
+        const auto& [sys, m, p, T] = kv.first;
+        auto ck = std::make_tuple(sys, m, p);
+        if (!coef_cache.count(ck)) coef_cache[ck] = effective_coefficients(rescaled_potential(&systems[sys], m), p);
+        const Coefficients& C = coef_cache[ck];
+        const std::vector<int> xdeg = quartic_xdegrees(p);
+        combo_off[kv.first] = blob.size();
+        auto& lv = combo_levels[kv.first];
+        for (int n = 0; n <= kv.second; ++n) {
+            lv.push_back(fold_level(C, true, std::ldexp(T, -n), xdeg));
+            blob.insert(blob.end(), lv.back().coef.begin(), lv.back().coef.end());
+        }
+    }
+    // ---- per task: sigma, S_ref, chunking; device order grouped by p
+    std::vector<size_t> order(n_tasks);
+    for (size_t i = 0; i < n_tasks; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return tasks[x].p < tasks[y].p; });
+    b->t_s.resize(n_tasks);
+    b->t_logpref.resize(n_tasks);
+    b->t_level0.resize(n_tasks);
+    b->t_n.resize(n_tasks);
+    b->t_shift.resize(n_tasks);
+    b->t_seg.resize(n_tasks);
+    std::vector<size_t> t_sig_off(n_tasks), t_shift_off(n_tasks);
+    // straight-line reference actions, in parallel over tasks (the same host routine as single runs)
+    {
+        const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        std::vector<std::thread> pool;
+        for (unsigned w = 0; w < nth; ++w)
+            pool.emplace_back([&, w]() {
+                for (size_t i = w; i < n_tasks; i += nth) {
+                    const pimc_task& t = tasks[i];
+                    const int s = log2_exact(t.N);
+                    const double sm = std::sqrt(t.m);
+                    const double a = t.a * sm, bb = t.b * sm;
+                    const auto& lv = combo_levels.at(Key{t.system, t.m, t.p, t.T});
+                    std::vector<double> sh(size_t(s + 1), 0.0);
+                    for (int n = 0; n <= s; ++n) {
+                        if (!hier && n != s && n != 0) continue;
+                        sh[size_t(n)] = straight_line_action(lv[size_t(n)], a, bb, n);
+                    }
+                    b->t_s[i] = s;
+                    b->t_n[i] = t.n_samples;
+                    b->t_logpref[i] = std::log(sm * free_kernel(a, bb, t.T));
+                    b->t_level0[i] = sh[0];
+                    b->t_shift[i] = std::move(sh);
+                }
+            });
+        for (auto& th : pool) th.join();
+    }
+    for (size_t i = 0; i < n_tasks; ++i) {
+        b->s_max = std::max(b->s_max, b->t_s[i]);
+        t_sig_off[i] = blob.size();
+        for (int n = 0; n <= b->t_s[i]; ++n) blob.push_back(n ? std::sqrt(tasks[i].T / std::ldexp(1.0, n + 1)) : 0.0);
+        t_shift_off[i] = blob.size();
+        blob.insert(blob.end(), b->t_shift[i].begin(), b->t_shift[i].end());
+    }
+    // partial slots and segments
+    std::vector<uint64_t> t_chunks(n_tasks), t_part_off(n_tasks);
+    uint64_t part_total = 0;
+    std::vector<uint64_t> seg_base, seg_len;
+    for (size_t pos = 0; pos < n_tasks; ++pos) {
+        const size_t i = order[pos];
+        const uint64_t chunk_paths = uint64_t(kBlock) * paths_per_lane(b->t_s[i]);
+        t_chunks[i] = (tasks[i].n_samples + chunk_paths - 1) / chunk_paths;
+        const int slots = hier ? b->t_s[i] + 1 : 1;
+        t_part_off[i] = part_total;
+        b->t_seg[i] = seg_base.size();
+        for (int k = 0; k < slots; ++k) {
+            seg_base.push_back((part_total + uint64_t(k) * t_chunks[i]) * 4);
+            seg_len.push_back(t_chunks[i]);
+        }
+        part_total += uint64_t(slots) * t_chunks[i];
+    }
+    b->n_seg = seg_base.size();
+    // ---- device buffers
+    int st;
+    auto dmalloc = [&](void** p, size_t bytes) -> int {
+        const hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 256));
+        if (e != hipSuccess) return batch_fail(b, PIMC_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+        return PIMC_OK;
+    };
+    if ((st = dmalloc(&b->d_blob, blob.size() * 8))) return fail(st);
+    if ((st = dmalloc(reinterpret_cast<void**>(&b->d_tasks), n_tasks * sizeof(BatchTask)))) return fail(st);
+    if ((st = dmalloc(reinterpret_cast<void**>(&b->d_partials), part_total * 4 * 8))) return fail(st);
+    if ((st = dmalloc(reinterpret_cast<void**>(&b->d_seg), b->n_seg * 2 * 8))) return fail(st);
+    if ((st = dmalloc(reinterpret_cast<void**>(&b->d_red), b->n_seg * 4 * 8))) return fail(st);
+    if ((st = dmalloc(reinterpret_cast<void**>(&b->d_queue), 64 * 8))) return fail(st);
+    {
+        const hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&b->h_red), std::max<size_t>(b->n_seg * 4 * 8, 64), 0);
+        if (e != hipSuccess) return fail(batch_fail(b, PIMC_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e)));
+    }
+    const double* dblob = static_cast<const double*>(b->d_blob);
+    std::vector<BatchTask> dt(n_tasks);
+    for (size_t pos = 0; pos < n_tasks; ++pos) {
+        const size_t i = order[pos];
+        const pimc_task& t = tasks[i];
+        BatchTask& r = dt[pos];
+        r.tab = dblob + combo_off.at(Key{t.system, t.m, t.p, t.T});
+        r.sig = dblob + t_sig_off[i];
+        r.shift = dblob + t_shift_off[i];
+        r.partials = b->d_partials + t_part_off[i] * 4;
+        const double sm = std::sqrt(t.m);
+        r.a = t.a * sm;
+        r.b = t.b * sm;
+        r.n_paths = t.n_samples;
+        r.n_chunks = t_chunks[i];
+        r.ppl = paths_per_lane(b->t_s[i]);
+        r.stream = t.stream;
+        r.s = b->t_s[i];
+        r.pad = 0;
+    }
+    // classes and item numbering
+    for (size_t pos = 0; pos < n_tasks;) {
+        const int p = tasks[order[pos]].p;
+        pimc_batch::Class C{p, 0, pos, 0, 0, 0};
+        int dmax = 0;
+        while (pos < n_tasks && tasks[order[pos]].p == p) {
+            dt[pos].item0 = C.n_items;
+            C.n_items += dt[pos].n_chunks;
+            dmax = std::max(dmax, dt[pos].s - 4);
+            ++C.n_tasks;
+            ++pos;
+        }
+        C.lds = amp_lds_bytes(dmax, dmax + 4);
+        C.resident = batch_resident_blocks(p, C.lds, c->device);
+        b->classes.push_back(C);
+    }
+    if (b->classes.size() > 64) return fail(batch_fail(b, PIMC_EUNSUPPORTED, "more than 64 distinct levels p"));
+    std::vector<uint64_t> seg(b->n_seg * 2);
+    std::copy(seg_base.begin(), seg_base.end(), seg.begin());
+    std::copy(seg_len.begin(), seg_len.end(), seg.begin() + b->n_seg);
+    HIP_TRY_B(b, hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+    HIP_TRY_B(b, hipEventCreate(&b->e0));
+    HIP_TRY_B(b, hipEventCreate(&b->e1));
+    HIP_TRY_B(b, hipMemcpyAsync(b->d_blob, blob.data(), blob.size() * 8, hipMemcpyHostToDevice, b->stream));
+    HIP_TRY_B(b, hipMemcpyAsync(b->d_tasks, dt.data(), dt.size() * sizeof(BatchTask), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY_B(b, hipMemcpyAsync(b->d_seg, seg.data(), seg.size() * 8, hipMemcpyHostToDevice, b->stream));
+    HIP_TRY_B(b, hipStreamSynchronize(b->stream));
+    if ((st = capture_graph(b))) return fail(st);
+    *out = b;
+    return PIMC_OK;
+}
+
+int pimc_batch_set_tuning(pimc_batch* b, int grid_mult_x2, uint32_t grab) {
+    if (!b) { set_thread_error("batch is NULL"); return PIMC_EINVAL; }
+    if (grid_mult_x2 < 1 || grid_mult_x2 > 8 || grab < 1 || grab > 64)
+        return batch_fail(b, PIMC_EINVAL, "tuning out of range (grid_mult_x2 1..8, grab 1..64)");
+    b->grid_mult_x2 = grid_mult_x2;
+    b->grab = grab;
+    return capture_graph(b);
+}
+
+int pimc_batch_run(pimc_batch* b, pimc_level_result* out, double* ms) {
+    if (!b) { set_thread_error("batch is NULL"); return PIMC_EINVAL; }
+    if (!out) return batch_fail(b, PIMC_EINVAL, "out is NULL");
+    HIP_TRY_B(b, hipSetDevice(b->ctx->device));
+    HIP_TRY_B(b, hipEventRecord(b->e0, b->stream));
+    HIP_TRY_B(b, hipGraphLaunch(b->exec, b->stream));
+    HIP_TRY_B(b, hipEventRecord(b->e1, b->stream));
+    HIP_TRY_B(b, hipStreamSynchronize(b->stream));
+    float fms = 0.f;
+    HIP_TRY_B(b, hipEventElapsedTime(&fms, b->e0, b->e1));
+    b->last_ms = fms;
+    if (ms) *ms = fms;
+    const bool hier = (b->flags & PIMC_HIERARCHY) != 0;
+    const size_t stride = size_t(b->s_max + 1);
+    bool nonfinite = false;
+    for (size_t i = 0; i < b->n_tasks; ++i) {
+        pimc_level_result* r = out + i * stride;
+        for (size_t n = 0; n < stride; ++n) r[n] = pimc_level_result{};
+        const int s = b->t_s[i];
+        r[0].amp = std::exp(b->t_logpref[i] - b->t_level0[i]);
+        r[0].log_amp = b->t_logpref[i] - b->t_level0[i];
+        r[0].n = b->t_n[i];
+        r[0].ess = double(b->t_n[i]);
+        for (int n = 1; n <= s; ++n) {
+            if (!hier && n != s) continue;
+            const double* red = b->h_red + (b->t_seg[i] + size_t(hier ? n : 0)) * 4;
+            if (assemble_level(red, b->t_logpref[i] - b->t_shift[i][size_t(n)], r[n])) nonfinite = true;
+        }
+    }
+    return nonfinite ? PIMC_WNONFINITE : PIMC_OK;
+}
+
+int pimc_batch_autotune(pimc_batch* b, const char* cache_path, int* grid_mult_x2, uint32_t* grab) {
+    if (!b) { set_thread_error("batch is NULL"); return PIMC_EINVAL; }
+    // cache key: device architecture, the p classes, the largest s, flags
+    hipDeviceProp_t prop;
+    HIP_TRY_B(b, hipGetDeviceProperties(&prop, b->ctx->device));
+    std::ostringstream key;
+    key << prop.gcnArchName << "|p";
+    for (const auto& C : b->classes) key << ":" << C.p;
+    key << "|s" << b->s_max << "|f" << b->flags;
+    if (cache_path) {
+        std::ifstream in(cache_path);
+        std::string k;
+        int g;
+        unsigned gr;
+        while (in >> k >> g >> gr)
+            if (k == key.str()) {
+                if (grid_mult_x2) *grid_mult_x2 = g;
+                if (grab) *grab = gr;
+                return pimc_batch_set_tuning(b, g, gr);
+            }
+    }
+    std::vector<pimc_level_result> scratch(b->n_tasks * size_t(b->s_max + 1));
+    double best = 1e300;
+    int best_g = 2;
+    uint32_t best_gr = 1;
+    const int gs[] = {1, 2, 4};
+    const uint32_t grs[] = {1, 4, 16};
+    for (int g : gs)
+        for (uint32_t gr : grs) {
+            int st = pimc_batch_set_tuning(b, g, gr);
+            if (st) return st;
+            double ms = 0;
+            st = pimc_batch_run(b, scratch.data(), &ms);
+            if (st < 0) return st;
+            if (ms < best) {
+                best = ms;
+                best_g = g;
+                best_gr = gr;
+            }
+        }
+    if (cache_path) {
+        std::ofstream o(cache_path, std::ios::app);
+        o << key.str() << " " << best_g << " " << best_gr << "\n";
+    }
+    if (grid_mult_x2) *grid_mult_x2 = best_g;
+    if (grab) *grab = best_gr;
+    return pimc_batch_set_tuning(b, best_g, best_gr);
+}
+
+int pimc_batch_destroy(pimc_batch* b) {
+    if (!b) return PIMC_OK;
+    if (b->ctx) (void)hipSetDevice(b->ctx->device);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    destroy_graph(b);
+    (void)hipFree(b->d_blob);
+    (void)hipFree(b->d_tasks);
+    (void)hipFree(b->d_partials);
+    (void)hipFree(b->d_seg);
+    (void)hipFree(b->d_red);
+    (void)hipFree(b->d_queue);
+    if (b->h_red) (void)hipHostFree(b->h_red);
+    if (b->e0) (void)hipEventDestroy(b->e0);
+    if (b->e1) (void)hipEventDestroy(b->e1);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+    return PIMC_OK;
+}
+
+const char* pimc_batch_last_error(const pimc_batch* b) { return b ? b->err : g_thread_error; }
+
+int pimc_amplitude_batch(pimc_ctx* c, const pimc_potential* systems, int n_systems, const pimc_task* tasks,
+                         size_t n_tasks, uint64_t seed, uint32_t flags, pimc_level_result* out) {
+    pimc_batch* b = nullptr;
+    int st = pimc_batch_create(c, systems, n_systems, tasks, n_tasks, seed, flags, &b);
+    if (st) return st;
+    st = pimc_batch_run(b, out, nullptr);
+    pimc_batch_destroy(b);
+    return st;
 }
 
 }  // extern "C"

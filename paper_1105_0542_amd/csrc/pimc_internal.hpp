@@ -49,8 +49,32 @@ hipError_t launch_amplitude(const AmpArgs& A, EvalKind kind, int p, int U, int g
 hipError_t launch_normals(const RngKey& key, uint64_t first_path, uint64_t k_paths, uint32_t n_nodes, double* out,
                           hipStream_t st);
 
-// Sum the canonical chunks of every level in chunk order: out[level][4] (device).
-hipError_t launch_reduce(const double* partials, uint64_t n_chunks, int n_levels, double* out, hipStream_t st);
+// Canonical reduction: segment i = len[i] chunk sums of 4 doubles at partials + base[i], added in
+// chunk order; out[i][4] (all device).
+hipError_t launch_seg_reduce(const double* partials, const uint64_t* base, const uint64_t* len, uint64_t n_seg,
+                             double* out, hipStream_t st);
+
+// One task of a batch, as the persistent kernel reads it (device array, wave-uniform loads).
+struct BatchTask {
+    const double* tab;                 // level tables of the task's (system, T, p), quartic layout
+    const double* sig;                 // sigma_n, n = 0..s
+    const double* shift;               // S_ref,n, n = 0..s
+    double* partials;                  // [slot][chunk][4]
+    double a, b;                       // endpoints after the mass rescaling
+    uint64_t n_paths;
+    uint64_t n_chunks;
+    uint64_t item0;                    // queue index of the task's chunk 0
+    uint32_t ppl;
+    uint32_t stream;
+    int s;
+    int pad;
+};
+
+// Persistent batched estimation for one level p (quartic kernels, U = 4, s >= 4).
+hipError_t launch_batch(const BatchTask* tasks, int n_tasks, uint64_t n_items, unsigned long long* queue, uint32_t grab,
+                        const RngKey& key, int hier, int p, int grid, size_t lds, hipStream_t st);
+int batch_resident_blocks(int p, size_t lds_bytes, int device);
+hipError_t launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t st);
 
 // Occupancy-derived number of resident workgroups of the estimation kernel on this device.
 int amplitude_resident_blocks(EvalKind kind, int p, int U, size_t lds_bytes, int device);

@@ -12,8 +12,9 @@
 // straight-line action only changes rounding); a wave butterfly sums d and d^2, lane 0 adds the
 // wave sum to a per-wave LDS accumulator, and at the end of a canonical chunk (kBlock*ppl
 // consecutive paths, lanes in a fixed order) the four wave accumulators are added in wave order and
-// written to the chunk's slot. The chunk slots are summed in chunk order by k_reduce_chunks, so
-// the result is bitwise independent of the grid size and of which workgroup ran which chunk.
+// written to the chunk's slot. The chunk slots are summed in chunk order by k_seg_reduce, so the
+// result is bitwise independent of the grid size, of which workgroup ran which chunk, and of
+// whether the run was launched alone or as one task of a batch.
 #include <hip/hip_runtime.h>
 
 #include "pimc_internal.hpp"
@@ -171,10 +172,12 @@ __device__ __forceinline__ void reduce_level(const AmpArgs& A, double* acc, int 
     }
 }
 
+// One canonical chunk c of the run described by A: paths c*CH .. c*CH+CH-1 (CH = kBlock * ppl),
+// lane tid takes paths c*CH + r*kBlock + tid for r = 0..ppl-1 in order. Writes the chunk's four
+// sums per evaluated level to A.partials[(slot * n_chunks + c) * 4] (slot = level with every level
+// evaluated, else 0 for level s) and/or the per-path level actions to A.dump.
 template <int U, class Eval>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PIMC_WAVES_PER_EU)))
-k_amplitude(AmpArgs A, Eval ev) {
-    extern __shared__ double smem[];
+__device__ __forceinline__ void process_chunk(const Eval& ev, const AmpArgs& A, uint64_t c, double* smem) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -183,52 +186,125 @@ k_amplitude(AmpArgs A, Eval ev) {
     double* top = smem + tid;
     double* acc = smem + size_t(3 * D + 2) * kBlock;
     const uint64_t CH = uint64_t(kBlock) * A.ppl;
-    for (uint64_t c = blockIdx.x; c < A.n_chunks; c += gridDim.x) {
-        if (A.partials) {
-            for (int i = tid; i < 4 * nlev * 3; i += kBlock) acc[i] = 0.0;
-            __syncthreads();
-        }
-        for (uint32_t r = 0; r < A.ppl; ++r) {
-            const uint64_t local = c * CH + uint64_t(r) * kBlock + uint64_t(tid);
-            const bool valid = local < A.n_paths;
-            double Ssub[U + 1];
-            walk_path<U, Eval>(ev, A, A.first_path + local, top, Ssub);
-            if (A.dump && valid) {
-                double* o = A.dump + local * uint64_t(nlev);
-                for (int n = 0; n < D; ++n) o[n] = A.hier ? top[n * kBlock] : 0.0;
+    if (A.partials) {
+        for (int i = tid; i < 4 * nlev * 3; i += kBlock) acc[i] = 0.0;
+        __syncthreads();
+    }
+    for (uint32_t r = 0; r < A.ppl; ++r) {
+        const uint64_t local = c * CH + uint64_t(r) * kBlock + uint64_t(tid);
+        const bool valid = local < A.n_paths;
+        double Ssub[U + 1];
+        walk_path<U, Eval>(ev, A, A.first_path + local, top, Ssub);
+        if (A.dump && valid) {
+            double* o = A.dump + local * uint64_t(nlev);
+            for (int n = 0; n < D; ++n) o[n] = A.hier ? top[n * kBlock] : 0.0;
 #pragma unroll
-                for (int j = 0; j <= U; ++j) o[D + j] = (A.hier || j == U) ? Ssub[j] : 0.0;
-            }
-            if (A.partials) {
-                if (A.hier) {
-                    for (int n = 0; n < D; ++n) reduce_level(A, acc, nlev, wave, lane, n, top[n * kBlock], valid);
-#pragma unroll
-                    for (int j = 0; j < U; ++j) reduce_level(A, acc, nlev, wave, lane, D + j, Ssub[j], valid);
-                }
-                reduce_level(A, acc, nlev, wave, lane, D + U, Ssub[U], valid);
-            }
+            for (int j = 0; j <= U; ++j) o[D + j] = (A.hier || j == U) ? Ssub[j] : 0.0;
         }
         if (A.partials) {
-            __syncthreads();
-            if (tid < nlev) {
-                const uint64_t rem = A.n_paths - c * CH;
-                const double cnt = (A.hier || tid == nlev - 1) ? double(rem < CH ? rem : CH) : 0.0;
-                double s1 = 0.0, s2 = 0.0, nb = 0.0;
-                for (int w = 0; w < kBlock / 64; ++w) {
-                    const double* a = acc + (w * nlev + tid) * 3;
-                    s1 += a[0];
-                    s2 += a[1];
-                    nb += a[2];
-                }
-                double* o = A.partials + (uint64_t(tid) * A.n_chunks + c) * 4;
-                o[0] = cnt;
-                o[1] = s1;
-                o[2] = s2;
-                o[3] = nb;
+            if (A.hier) {
+                for (int n = 0; n < D; ++n) reduce_level(A, acc, nlev, wave, lane, n, top[n * kBlock], valid);
+#pragma unroll
+                for (int j = 0; j < U; ++j) reduce_level(A, acc, nlev, wave, lane, D + j, Ssub[j], valid);
             }
-            __syncthreads();
+            reduce_level(A, acc, nlev, wave, lane, D + U, Ssub[U], valid);
         }
     }
+    if (A.partials) {
+        __syncthreads();
+        const int slots = A.hier ? nlev : 1;
+        if (tid < slots) {
+            const int lev = A.hier ? tid : nlev - 1;
+            const uint64_t rem = A.n_paths - c * CH;
+            const double cnt = double(rem < CH ? rem : CH);
+            double s1 = 0.0, s2 = 0.0, nb = 0.0;
+            for (int w = 0; w < kBlock / 64; ++w) {
+                const double* a = acc + (w * nlev + lev) * 3;
+                s1 += a[0];
+                s2 += a[1];
+                nb += a[2];
+            }
+            double* o = A.partials + (uint64_t(tid) * A.n_chunks + c) * 4;
+            o[0] = cnt;
+            o[1] = s1;
+            o[2] = s2;
+            o[3] = nb;
+        }
+        __syncthreads();
+    }
+}
+
+template <int U, class Eval>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PIMC_WAVES_PER_EU)))
+k_amplitude(AmpArgs A, Eval ev) {
+    extern __shared__ double smem[];
+    for (uint64_t c = blockIdx.x; c < A.n_chunks; c += gridDim.x) process_chunk<U, Eval>(ev, A, c, smem);
+}
+
+// ---------------------------------------------------------------------------- batched tasks
+// Persistent kernel over the (task, chunk) items of one effective-action level p: each workgroup
+// takes `grab` consecutive items at a time from an atomic counter until the queue is empty (every
+// wave of every workgroup reaches the exit test with the same value). Items are numbered task by
+// task (task t owns items item0[t] .. item0[t] + n_chunks[t] - 1), so an item maps to its task by
+// binary search over the wave-uniform task records; the chunk itself is processed by the same code
+// as a single-task launch, so results do not depend on which workgroup took which item.
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(v));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(v >> 32));
+    return (uint64_t(hi) << 32) | lo;
+}
+
+template <int U, class Eval>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PIMC_WAVES_PER_EU)))
+k_batch(const BatchTask* __restrict__ tasks, int n_tasks, uint64_t n_items, unsigned long long* queue,
+        uint32_t grab, RngKey key, int hier, Eval ev0) {
+    extern __shared__ double smem[];
+    __shared__ unsigned long long s_item;
+    const const_ptr<BatchTask> T = as_const(tasks);
+    while (true) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = atomicAdd(queue, (unsigned long long)grab);
+        __syncthreads();
+        const uint64_t first = uniform_u64(s_item);
+        if (first >= n_items) break;
+        const uint64_t last = first + grab < n_items ? first + grab : n_items;
+        for (uint64_t item = first; item < last; ++item) {
+            int lo = 0, hi = n_tasks - 1;                  // last task with item0 <= item
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (T[mid].item0 <= item) lo = mid; else hi = mid - 1;
+            }
+            AmpArgs A;
+            A.tab64 = T[lo].tab;
+            A.tab32 = nullptr;
+            A.gdeg = nullptr;
+            A.gK = 0;
+            A.gstride = 0;
+            A.a = T[lo].a;
+            A.b = T[lo].b;
+            A.sig = T[lo].sig;
+            A.shift = T[lo].shift;
+            A.key = key;
+            A.key.stream = T[lo].stream;
+            A.first_path = 0;
+            A.n_paths = T[lo].n_paths;
+            A.n_chunks = T[lo].n_chunks;
+            A.ppl = T[lo].ppl;
+            A.s = T[lo].s;
+            A.D = T[lo].s - U;
+            A.hier = hier;
+            A.partials = T[lo].partials;
+            A.dump = nullptr;
+            Eval ev = ev0;
+            ev.tab = T[lo].tab;
+            process_chunk<U, Eval>(ev, A, item - T[lo].item0, smem);
+        }
+    }
+}
+
+__global__ void k_fill_u64(unsigned long long* p, int n, unsigned long long v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 // ---------------------------------------------------------------------------- raw normals
@@ -261,28 +337,28 @@ hipError_t launch_normals(const RngKey& key, uint64_t first_path, uint64_t k_pat
 }
 
 // ---------------------------------------------------------------------------- chunk reduction
-__global__ void __launch_bounds__(kBlock) k_reduce_chunks(const double* __restrict__ partials, uint64_t n_chunks,
-                                                          double* __restrict__ out) {
-    __shared__ double red[4][kBlock];
-    const int lev = blockIdx.x;
-    const int tid = threadIdx.x;
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (uint64_t c = tid; c < n_chunks; c += kBlock) {
-        const double* p = partials + (uint64_t(lev) * n_chunks + c) * 4;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) s[j] += p[j];
+// Canonical reduction: segment i (one level of one run) is the sequence of chunk sums
+// partials[base[i] + c*4 .. +3], c = 0..len[i]-1, added strictly in chunk order by one thread.
+// Any run, single or batched, therefore gives the same bits for the same chunks.
+__global__ void __launch_bounds__(kBlock) k_seg_reduce(const double* __restrict__ partials,
+                                                       const uint64_t* __restrict__ base,
+                                                       const uint64_t* __restrict__ len, uint64_t n_seg,
+                                                       double* __restrict__ out) {
+    const uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= n_seg) return;
+    const double* p = partials + base[i];
+    const uint64_t n = len[i];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (uint64_t c = 0; c < n; ++c) {
+        s0 += p[c * 4 + 0];
+        s1 += p[c * 4 + 1];
+        s2 += p[c * 4 + 2];
+        s3 += p[c * 4 + 3];
     }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) red[j][tid] = s[j];
-    __syncthreads();
-    for (int w = kBlock / 2; w >= 1; w >>= 1) {
-        if (tid < w) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) red[j][tid] += red[j][tid + w];
-        }
-        __syncthreads();
-    }
-    if (tid < 4) out[lev * 4 + tid] = red[tid][0];
+    out[i * 4 + 0] = s0;
+    out[i * 4 + 1] = s1;
+    out[i * 4 + 2] = s2;
+    out[i * 4 + 3] = s3;
 }
 
 // ---------------------------------------------------------------------------- dispatch
@@ -337,10 +413,54 @@ hipError_t launch_amplitude(const AmpArgs& A, EvalKind kind, int p, int U, int g
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_reduce(const double* partials, uint64_t n_chunks, int n_levels, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce_chunks, dim3(n_levels), dim3(kBlock), 0, st, partials, n_chunks, out);
+hipError_t launch_seg_reduce(const double* partials, const uint64_t* base, const uint64_t* len, uint64_t n_seg,
+                             double* out, hipStream_t st) {
+    if (n_seg == 0) return hipSuccess;
+    const uint64_t blocks = (n_seg + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_seg_reduce, dim3(uint32_t(blocks)), dim3(kBlock), 0, st, partials, base, len, n_seg, out);
     return hipGetLastError();
 }
+
+hipError_t launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_u64, dim3((n + 63) / 64), dim3(64), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+template <int P>
+static hipError_t batch_quartic(const BatchTask* tasks, int n_tasks, uint64_t n_items, unsigned long long* queue,
+                                uint32_t grab, RngKey key, int hier, int p, int grid, size_t lds, hipStream_t st) {
+    if constexpr (P <= kMaxP) {
+        if (p != P) return batch_quartic<P + 1>(tasks, n_tasks, n_items, queue, grab, key, hier, p, grid, lds, st);
+        QuarticEval64<P> ev{nullptr};
+        hipLaunchKernelGGL((k_batch<4, QuarticEval64<P>>), dim3(grid), dim3(kBlock), lds, st, tasks, n_tasks, n_items,
+                           queue, grab, key, hier, ev);
+        return hipGetLastError();
+    } else {
+        return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_batch(const BatchTask* tasks, int n_tasks, uint64_t n_items, unsigned long long* queue, uint32_t grab,
+                        const RngKey& key, int hier, int p, int grid, size_t lds, hipStream_t st) {
+    return batch_quartic<1>(tasks, n_tasks, n_items, queue, grab, key, hier, p, grid, lds, st);
+}
+
+template <int P>
+static int batch_resident(int p, size_t lds, int device) {
+    if constexpr (P <= kMaxP) {
+        if (p != P) return batch_resident<P + 1>(p, lds, device);
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<4, QuarticEval64<P>>, kBlock, lds) != hipSuccess)
+            per_cu = 1;
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) ncu = 256;
+        return (per_cu < 1 ? 1 : per_cu) * ncu;
+    } else {
+        return 256;
+    }
+}
+
+int batch_resident_blocks(int p, size_t lds_bytes, int device) { return batch_resident<1>(p, lds_bytes, device); }
 
 template <int U, class Eval>
 static int resident_one(size_t lds, int device) {
