@@ -137,6 +137,8 @@ def main():
     ap.add_argument("--samples", type=int, default=N_SAMPLES)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision-samples", type=int, default=PREC["samples"])
+    ap.add_argument("--batch-samples", type=int, default=10_000,
+                    help="samples per task of the batched 128x128 grid (0 skips it)")
     ap.add_argument("--copy-probe", action="store_true", help="only run the 512 MiB copy used to scale HBM counters")
     args = ap.parse_args()
     if args.copy_probe:
@@ -218,6 +220,33 @@ def main():
             "rel_diff_fp64_gpu": abs(small["fp64"] - prec_ref) / prec_ref,
             "rel_diff_fp32_gpu": abs(small["fp32"] - prec_ref) / prec_ref}
 
+    # batched grid: 2 systems x 3 T x 3 p x 128 x 128 endpoints, mixed N, one graph replay
+    batch_line = None
+    if args.batch_samples > 0:
+        from paper_1105_0542_amd import workloads
+        t0b = time.perf_counter()
+        systems, rows = workloads.evolution_matrix_tasks(samples=args.batch_samples)
+        bt = P.Batch(ctx, systems, rows, seed=1, flags=0)
+        t_plan = time.perf_counter() - t0b
+        tune_path = os.path.join(os.environ.get("TMPDIR", "/tmp"), "pimc_batch_tune.txt")
+        choice = bt.autotune(tune_path)
+        out, ms, st = bt.run()
+        default_ms = None
+        bt.set_tuning(2, 1)
+        _, default_ms, _ = bt.run()
+        bt.set_tuning(*choice)
+        slices = sum(r[7] * r[5] for r in rows)
+        nonfinite = int((out["n_nonfinite"]).sum())
+        batch_line = {
+            "workload": "128x128 endpoint grid on [-4,4]^2, (A,g) in {(1,1),(-1,4)}, T in {0.5,1,2}, p in {8,12,18}, "
+                        f"N in 16..512 by a fixed hash, {args.batch_samples} samples per task, level N only",
+            "tasks": len(rows), "graph_ms": ms, "slice_evals_per_s": slices / (ms / 1e3),
+            "default_shape_graph_ms": default_ms, "autotuned": {"grid_mult_x2": choice[0], "grab": choice[1]},
+            "plan_s": t_plan, "tasks_with_nonfinite_weights": int((out["n_nonfinite"].sum(axis=1) > 0).sum()),
+            "nonfinite_weights": nonfinite,
+        }
+        bt.close()
+
     line = {
         "metric": "slice-evals/s (p=18, FP64)",
         "value": value,
@@ -252,6 +281,8 @@ def main():
                     for (g, T, r) in last},
     }
     line["precision"] = prec_line
+    if batch_line is not None:
+        line["batched"] = batch_line
     if cpu is not None:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)

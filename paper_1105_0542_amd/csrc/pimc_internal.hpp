@@ -49,8 +49,8 @@ hipError_t launch_amplitude(const AmpArgs& A, EvalKind kind, int p, int U, int g
 hipError_t launch_normals(const RngKey& key, uint64_t first_path, uint64_t k_paths, uint32_t n_nodes, double* out,
                           hipStream_t st);
 
-// Canonical reduction: segment i = len[i] chunk sums of 4 doubles at partials + base[i], added in
-// chunk order; out[i][4] (all device).
+// Canonical reduction: segment i = len[i] chunk sums of 4 doubles at partials + base[i], added in a
+// fixed order that depends only on len[i]; out[i][4] (all device).
 hipError_t launch_seg_reduce(const double* partials, const uint64_t* base, const uint64_t* len, uint64_t n_seg,
                              double* out, hipStream_t st);
 

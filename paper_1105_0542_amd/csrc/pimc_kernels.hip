@@ -338,27 +338,35 @@ hipError_t launch_normals(const RngKey& key, uint64_t first_path, uint64_t k_pat
 
 // ---------------------------------------------------------------------------- chunk reduction
 // Canonical reduction: segment i (one level of one run) is the sequence of chunk sums
-// partials[base[i] + c*4 .. +3], c = 0..len[i]-1, added strictly in chunk order by one thread.
-// Any run, single or batched, therefore gives the same bits for the same chunks.
+// partials[base[i] + c*4 .. +3], c = 0..len[i]-1. One workgroup of kBlock threads per segment:
+// thread t adds chunks t, t + kBlock, ... in order, then a fixed halving tree over the threads.
+// The order depends only on the chunk count, so any run -- single or one task of a batch, any
+// grid -- gives the same bits for the same chunks.
 __global__ void __launch_bounds__(kBlock) k_seg_reduce(const double* __restrict__ partials,
                                                        const uint64_t* __restrict__ base,
-                                                       const uint64_t* __restrict__ len, uint64_t n_seg,
+                                                       const uint64_t* __restrict__ len,
                                                        double* __restrict__ out) {
-    const uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
-    if (i >= n_seg) return;
-    const double* p = partials + base[i];
-    const uint64_t n = len[i];
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    for (uint64_t c = 0; c < n; ++c) {
-        s0 += p[c * 4 + 0];
-        s1 += p[c * 4 + 1];
-        s2 += p[c * 4 + 2];
-        s3 += p[c * 4 + 3];
+    __shared__ double red[4][kBlock];
+    const uint64_t seg = blockIdx.x;
+    const int tid = threadIdx.x;
+    const double* p = partials + base[seg];
+    const uint64_t n = len[seg];
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (uint64_t c = tid; c < n; c += kBlock) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) s[j] += p[c * 4 + j];
     }
-    out[i * 4 + 0] = s0;
-    out[i * 4 + 1] = s1;
-    out[i * 4 + 2] = s2;
-    out[i * 4 + 3] = s3;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) red[j][tid] = s[j];
+    __syncthreads();
+    for (int w = kBlock / 2; w >= 1; w >>= 1) {
+        if (tid < w) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) red[j][tid] += red[j][tid + w];
+        }
+        __syncthreads();
+    }
+    if (tid < 4) out[seg * 4 + tid] = red[tid][0];
 }
 
 // ---------------------------------------------------------------------------- dispatch
@@ -416,8 +424,8 @@ hipError_t launch_amplitude(const AmpArgs& A, EvalKind kind, int p, int U, int g
 hipError_t launch_seg_reduce(const double* partials, const uint64_t* base, const uint64_t* len, uint64_t n_seg,
                              double* out, hipStream_t st) {
     if (n_seg == 0) return hipSuccess;
-    const uint64_t blocks = (n_seg + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_seg_reduce, dim3(uint32_t(blocks)), dim3(kBlock), 0, st, partials, base, len, n_seg, out);
+    if (n_seg > 0x7fffffffull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_seg_reduce, dim3(uint32_t(n_seg)), dim3(kBlock), 0, st, partials, base, len, out);
     return hipGetLastError();
 }
 
