@@ -127,6 +127,25 @@ __device__ __forceinline__ void normal_pair(const RngKey& key, const PathRng& pr
     z_odd = r * sn;
 }
 
+// Normal sources of the bisection walker: pair(j, z_even, z_odd) gives the normals of heap nodes
+// 2j and 2j+1 (node 0 does not exist; its value is ignored).
+struct PhiloxSource {
+    RngKey key;
+    PathRng pr;
+    __device__ __forceinline__ void pair(uint32_t j, double& ze, double& zo) const { normal_pair(key, pr, j, ze, zo); }
+};
+
+// Normals held in device memory, feature-major: node h of path `path` at z[(h-1)*ld + path].
+struct MemorySource {
+    const double* z;
+    uint64_t ld;
+    uint64_t path;
+    __device__ __forceinline__ void pair(uint32_t j, double& ze, double& zo) const {
+        ze = j ? z[uint64_t(2 * j - 1) * ld + path] : 0.0;
+        zo = z[uint64_t(2 * j) * ld + path];
+    }
+};
+
 // ---------------------------------------------------------------------------------------------
 // Slice evaluators. eval<W>(level, qa, qb, S) adds eps_level W_p of the slices (qa[i], qb[i]) to S
 // one at a time in index order, so a level action is always the left-to-right sum of its slices

@@ -31,8 +31,8 @@
 namespace pimc {
 
 // ---------------------------------------------------------------------------- subtree (registers)
-template <int U, int L, class Eval>
-__device__ __forceinline__ void gen_level(const AmpArgs& A, const PathRng& pr, uint32_t root, int D,
+template <int U, int L, class Src>
+__device__ __forceinline__ void gen_level(const AmpArgs& A, const Src& src, uint32_t root, int D,
                                           double (&q)[(1 << U) + 1]) {
     if constexpr (L <= U) {
         constexpr int step = 1 << (U - L);
@@ -41,13 +41,13 @@ __device__ __forceinline__ void gen_level(const AmpArgs& A, const PathRng& pr, u
         for (int i2 = 0; i2 < (1 << (L - 2)); ++i2) {
             const uint32_t parent = (root << (L - 2)) + uint32_t(i2);   // node of sub-level L-1
             double ze, zo;
-            normal_pair(A.key, pr, parent, ze, zo);                      // children 2*parent, 2*parent+1
+            src.pair(parent, ze, zo);                                    // children 2*parent, 2*parent+1
             const int jl = (4 * i2 + 1) * step;
             const int jr = (4 * i2 + 3) * step;
             q[jl] = sg * ze + 0.5 * (q[jl - step] + q[jl + step]);
             q[jr] = sg * zo + 0.5 * (q[jr - step] + q[jr + step]);
         }
-        gen_level<U, L + 1, Eval>(A, pr, root, D, q);
+        gen_level<U, L + 1, Src>(A, src, root, D, q);
     }
 }
 
@@ -79,8 +79,8 @@ __device__ __forceinline__ void hier_levels(const Eval& ev, int D, const double 
 }
 
 // Subtree rooted at heap node `root` (level D+1) over the level-D slice (qL, qR) with root normal z.
-template <int U, class Eval>
-__device__ __forceinline__ void run_subtree(const Eval& ev_in, const AmpArgs& A, const PathRng& pr,
+template <int U, class Eval, class Src>
+__device__ __forceinline__ void run_subtree(const Eval& ev_in, const AmpArgs& A, const Src& src,
                                             uint32_t root, int D, double qL, double qR, double zroot,
                                             double (&Ssub)[U + 1]) {
     Eval ev = ev_in;
@@ -89,7 +89,7 @@ __device__ __forceinline__ void run_subtree(const Eval& ev_in, const AmpArgs& A,
     q[0] = qL;
     q[1 << U] = qR;
     q[1 << (U - 1)] = as_const(A.sig)[D + 1] * zroot + 0.5 * (qL + qR);
-    gen_level<U, 2, Eval>(A, pr, root, D, q);
+    gen_level<U, 2, Src>(A, src, root, D, q);
     if (A.hier) hier_levels<U, 0, Eval>(ev, D, q, Ssub);
     level_sum<U, U, Eval>(ev, D + U, q, Ssub[U]);
 }
@@ -97,17 +97,16 @@ __device__ __forceinline__ void run_subtree(const Eval& ev_in, const AmpArgs& A,
 // ---------------------------------------------------------------------------- one path
 // top: this lane's LDS slots (stride kBlock): S_top[n] at slot n (n < D), pending right endpoint
 // of level L at slot D+L, pending normal at slot 2D+1+L (L = 2..D).
-template <int U, class Eval>
-__device__ __forceinline__ void walk_path(const Eval& ev, const AmpArgs& A, uint64_t path, double* top,
+template <int U, class Eval, class Src>
+__device__ __forceinline__ void walk_path(const Eval& ev, const AmpArgs& A, const Src& src, double* top,
                                           double (&Ssub)[U + 1]) {
-    const PathRng pr = path_rng(A.key, path);
     const int D = A.D;
 #pragma unroll
     for (int j = 0; j <= U; ++j) Ssub[j] = 0.0;
     double z0_unused, z1;
-    normal_pair(A.key, pr, 0u, z0_unused, z1);        // node 1 = sine output of call 0
+    src.pair(0u, z0_unused, z1);                      // node 1 = sine output of call 0
     if (D == 0) {
-        run_subtree<U, Eval>(ev, A, pr, 1u, 0, A.a, A.b, z1, Ssub);
+        run_subtree<U, Eval, Src>(ev, A, src, 1u, 0, A.a, A.b, z1, Ssub);
         return;
     }
     for (int n = 0; n < D; ++n) top[n * kBlock] = 0.0;
@@ -141,7 +140,7 @@ __device__ __forceinline__ void walk_path(const Eval& ev, const AmpArgs& A, uint
                 top[(L - 1) * kBlock] = St;
             }
             qm = as_const(A.sig)[L] * z + 0.5 * (qL + qR);
-            normal_pair(A.key, pr, node, zl, zr);
+            src.pair(node, zl, zr);
             if (L == D) break;
             R[(L + 1) * kBlock] = qR;                 // right child of `node`: (qm, qR), normal zr
             Z[(L + 1) * kBlock] = zr;
@@ -150,8 +149,8 @@ __device__ __forceinline__ void walk_path(const Eval& ev, const AmpArgs& A, uint
             node = 2u * node;
             ++L;
         }
-        run_subtree<U, Eval>(ev, A, pr, 2u * node, D, qL, qm, zl, Ssub);
-        run_subtree<U, Eval>(ev, A, pr, 2u * node + 1u, D, qm, qR, zr, Ssub);
+        run_subtree<U, Eval, Src>(ev, A, src, 2u * node, D, qL, qm, zl, Ssub);
+        run_subtree<U, Eval, Src>(ev, A, src, 2u * node + 1u, D, qm, qR, zr, Ssub);
         qlast = qR;
     }
 }
@@ -194,7 +193,8 @@ __device__ __forceinline__ void process_chunk(const Eval& ev, const AmpArgs& A, 
         const uint64_t local = c * CH + uint64_t(r) * kBlock + uint64_t(tid);
         const bool valid = local < A.n_paths;
         double Ssub[U + 1];
-        walk_path<U, Eval>(ev, A, A.first_path + local, top, Ssub);
+        const PhiloxSource src{A.key, path_rng(A.key, A.first_path + local)};
+        walk_path<U, Eval, PhiloxSource>(ev, A, src, top, Ssub);
         if (A.dump && valid) {
             double* o = A.dump + local * uint64_t(nlev);
             for (int n = 0; n < D; ++n) o[n] = A.hier ? top[n * kBlock] : 0.0;
