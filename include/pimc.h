@@ -107,6 +107,7 @@ int pimc_level_table(const pimc_potential *V, double m, double T, int p, uint32_
 /* Create a context on HIP device `device`. hip_stream: a hipStream_t to launch on (for example
  * torch's current stream), or NULL for a stream owned by the context. */
 int pimc_create(pimc_ctx **out, int device, void *hip_stream);
+/* Batches and proposals keep a pointer to the context they were created on: destroy them first. */
 int pimc_destroy(pimc_ctx *ctx);
 
 /* Estimate A_{2^n}^(p)(a,b;T) +- err for every level n = 0..s (N = 2^s) from n_samples paths with
@@ -187,6 +188,78 @@ const char *pimc_batch_last_error(const pimc_batch *batch);
 /* Create, run once and destroy: out as in pimc_batch_run. */
 int pimc_amplitude_batch(pimc_ctx *ctx, const pimc_potential *systems, int n_systems, const pimc_task *tasks,
                          size_t n_tasks, uint64_t seed, uint32_t flags, pimc_level_result *out);
+
+/* ---- learned proposal: affine couplings over the bisection normals -------------------------------
+ *
+ * The estimator is the paper's A_N^(p) = K_0 E[exp(-sum_k eps W_p)] (Sec. 4) with the bisection
+ * normals z (heap nodes h = 1..N-1, z_h scaled by the bridge width of its level as in Sec. 4.1)
+ * drawn from a learned density q instead of N(0, I) and reweighted exactly: with z = f(u),
+ * u ~ N(0, I) the plain sampler's normals,
+ *     log w = -(S(z) - S_ref) - |z|^2/2 + |u|^2/2 + log|det df/du|,   A = sqrt(m) K_0 e^{-S_ref} E[w].
+ * f is `layers` affine couplings; layer c splits the heap nodes by mask type c mod 4
+ * (0: node 1 + left subtree | right subtree, 1: node 1 + right subtree | left subtree, 2: odd h | even h,
+ * 3: even h | odd h; first part conditions, second is transformed) and maps x_B -> x_B e^s + t with
+ * (s_hat, t) = W2 silu(W1 x_A + b1) + b2 and s = 2 tanh(s_hat/2) (hidden width 128, x_A zero-padded
+ * to 64, s_hat = rows 0..|B|-1, t = rows 64..64+|B|-1). The two products run on bfloat16 matrix
+ * cores with FP32 accumulation (x_A, W1, the hidden layer and W2 rounded to bfloat16, round to
+ * nearest even); the affine map, log-determinant, action and weights are FP64.
+ * Parameters per layer, one flat float vector of PIMC_FLOW_NPARAM: W1 [128][64] row-major, b1 [128],
+ * W2 [128][128] row-major [out][hidden], b2 [128].
+ * Training minimizes (1-beta) log mean_i w_i^2 + beta (-mean_i log w_i) over batches of fresh base
+ * samples with Adam; any parameters give an unbiased estimate, training only lowers its variance.
+ * Supported: 2 <= N <= 128 (every coupling part fits 64 inputs); any potential pimc_amplitude takes,
+ * FP64 polynomials.
+ */
+#define PIMC_FLOW_NPARAM 24832
+#define PIMC_FLOW_MAX_LAYERS 16
+
+typedef struct {
+    int layers;                /* coupling layers, 1..PIMC_FLOW_MAX_LAYERS                           */
+    uint32_t batch;            /* training paths per step, 2..65536                                 */
+    double lr;                 /* Adam learning rate (beta1 0.9, beta2 0.999, eps 1e-8)             */
+    double beta;               /* weight of the reverse-KL term, 0..1                               */
+    uint64_t init_seed;        /* W1 ~ U(-1/8, 1/8), W2 ~ init_scale U(-1/20, 1/20), b1 = b2 = 0     */
+    double init_scale;         /* 0: the initial map is the identity (the plain sampler)            */
+} pimc_flow_config;
+
+typedef struct pimc_flow pimc_flow;
+
+/* Plan a proposal for one problem (validated as in pimc_check_problem with N <= 128): builds the
+ * level-s table, allocates parameters, Adam state and training buffers on the context's device.
+ * EUNSUPPORTED for N = 1 or N > 128. The flow uses the context's stream and records errors on it. */
+int pimc_flow_create(pimc_ctx *ctx, const pimc_potential *V, double m, double a, double b, double T,
+                     uint32_t N, int p, const pimc_flow_config *cfg, pimc_flow **out);
+int pimc_flow_destroy(pimc_flow *flow);
+
+/* Copy the FP32 master parameters out (layers * PIMC_FLOW_NPARAM floats; *n_out = that count;
+ * EINVAL if cap is smaller) or in (n must equal that count; resets the Adam moments and step). */
+int pimc_flow_get_params(pimc_flow *flow, float *out, size_t cap, size_t *n_out);
+int pimc_flow_set_params(pimc_flow *flow, const float *in, size_t n);
+
+/* Loss and gradient of one batch without updating: base normals of paths 0..batch-1 on Philox
+ * stream `stream` with the context seed convention (seed, stream) of pimc_normals. loss: host
+ * double; ell: host [batch] log weights (may be NULL); grad: host [layers * PIMC_FLOW_NPARAM]
+ * floats (may be NULL). The gradient of every tile of 64 paths is added in a fixed order. */
+int pimc_flow_grad(pimc_flow *flow, uint64_t seed, uint32_t stream, double *loss, double *ell, float *grad);
+
+/* `steps` Adam steps, step j on paths 0..batch-1 of Philox stream stream_base + (number of steps
+ * taken before it), replayed as one captured HIP graph per step. losses: host [steps] or NULL;
+ * *ms (may be NULL): device time of all steps. */
+int pimc_flow_train(pimc_flow *flow, uint64_t seed, uint32_t stream_base, uint32_t steps, double *losses,
+                    double *ms);
+
+/* Log weights, proposal samples and log-determinants of paths first_path..first_path+k_paths-1
+ * (base normals as in pimc_normals). ell, logdet: host [k_paths] (may be NULL); z: host
+ * [k_paths][N-1] (may be NULL). */
+int pimc_flow_log_weights(pimc_flow *flow, uint64_t seed, uint32_t stream, uint64_t first_path, uint64_t k_paths,
+                          double *ell, double *z, double *logdet);
+
+/* Estimate A_N^(p)(a,b;T) +- err from n_samples proposal paths 0..n_samples-1 with the current
+ * parameters: one level result for level s, summed in the canonical chunks of pimc_amplitude (so
+ * pimc_last_partials on the context reads them afterwards). *ms (may be NULL): device time.
+ * Returns PIMC_WNONFINITE if any weight was not finite. */
+int pimc_flow_amplitude(pimc_flow *flow, uint64_t n_samples, uint64_t seed, uint32_t stream,
+                        pimc_level_result *out, double *ms);
 
 /* Device time of the last estimation kernel on this context, in milliseconds (HIP events on the
  * context's stream around that launch). */

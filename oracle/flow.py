@@ -99,8 +99,8 @@ def silu(v):
 def coupling_forward(theta_layer, x, layer, D, quantize=True):
     """One coupling on x (paths x D, FP64). Returns y, s (per path x |B|), cache for backward."""
     A, B = masks(D, layer)
-    ia = np.array(A) - 1
-    ib = np.array(B) - 1
+    ia = np.array(A, dtype=np.int64) - 1
+    ib = np.array(B, dtype=np.int64) - 1
     W1, b1, W2, b2 = split(np.asarray(theta_layer, dtype=np.float64))
     xa = np.zeros((x.shape[0], KIN))
     xa[:, :len(A)] = x[:, ia]

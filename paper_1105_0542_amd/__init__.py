@@ -6,6 +6,7 @@ does, and raises ``PimcLibraryMissing`` if it has not been built (``python -m
 paper_1105_0542_amd.build``). There is no CPU fallback.
 """
 from .binding import (  # noqa: F401
-    FLAG_FP32_POLY, FLAG_HIERARCHY, Batch, Context, LevelResult, PimcError, PimcLibraryMissing, check_problem,
+    FLAG_FP32_POLY, FLAG_HIERARCHY, FLOW_NPARAM, Batch, Context, Flow, LevelResult, PimcError, PimcLibraryMissing,
+    check_problem,
     level_table, lib_path, load_library, make_tasks, potential_from_coefs, quartic,
 )

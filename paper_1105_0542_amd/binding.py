@@ -3,6 +3,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 from dataclasses import dataclass
 from typing import List, Optional, Sequence
 
@@ -23,6 +24,8 @@ FLAG_HIERARCHY = 2
 
 MAX_DEGREE = 8
 MAX_P = 18
+FLOW_NPARAM = 24832
+FLOW_MAX_LAYERS = 16
 
 
 class PimcLibraryMissing(RuntimeError):
@@ -42,6 +45,11 @@ class Potential(C.Structure):
 class Task(C.Structure):
     _fields_ = [("system", C.c_uint32), ("m", C.c_double), ("a", C.c_double), ("b", C.c_double), ("T", C.c_double),
                 ("N", C.c_uint32), ("p", C.c_int), ("n_samples", C.c_uint64), ("stream", C.c_uint32)]
+
+
+class FlowConfig(C.Structure):
+    _fields_ = [("layers", C.c_int), ("batch", C.c_uint32), ("lr", C.c_double), ("beta", C.c_double),
+                ("init_seed", C.c_uint64), ("init_scale", C.c_double)]
 
 
 class _LevelResult(C.Structure):
@@ -129,6 +137,24 @@ def load_library():
                                          P(_LevelResult)]
     lib.pimc_last_kernel_ms.restype = C.c_int
     lib.pimc_last_kernel_ms.argtypes = [vp, P(C.c_double)]
+    lib.pimc_flow_create.restype = C.c_int
+    lib.pimc_flow_create.argtypes = [vp, P(Potential), C.c_double, C.c_double, C.c_double, C.c_double, C.c_uint32,
+                                     C.c_int, P(FlowConfig), P(vp)]
+    lib.pimc_flow_destroy.restype = C.c_int
+    lib.pimc_flow_destroy.argtypes = [vp]
+    lib.pimc_flow_get_params.restype = C.c_int
+    lib.pimc_flow_get_params.argtypes = [vp, P(C.c_float), C.c_size_t, P(C.c_size_t)]
+    lib.pimc_flow_set_params.restype = C.c_int
+    lib.pimc_flow_set_params.argtypes = [vp, P(C.c_float), C.c_size_t]
+    lib.pimc_flow_grad.restype = C.c_int
+    lib.pimc_flow_grad.argtypes = [vp, C.c_uint64, C.c_uint32, P(C.c_double), P(C.c_double), P(C.c_float)]
+    lib.pimc_flow_train.restype = C.c_int
+    lib.pimc_flow_train.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_uint32, P(C.c_double), P(C.c_double)]
+    lib.pimc_flow_log_weights.restype = C.c_int
+    lib.pimc_flow_log_weights.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint64, P(C.c_double),
+                                          P(C.c_double), P(C.c_double)]
+    lib.pimc_flow_amplitude.restype = C.c_int
+    lib.pimc_flow_amplitude.argtypes = [vp, C.c_uint64, C.c_uint64, C.c_uint32, P(_LevelResult), P(C.c_double)]
     _lib = lib
     return lib
 
@@ -200,9 +226,13 @@ class Context:
         if st != PIMC_OK:
             raise _err(self.lib, None, st)
         self.h = h
+        self._children = weakref.WeakSet()      # batches and proposals that use this context
 
     def close(self):
+        """Destroy the context; batches and proposals created on it are destroyed first."""
         if getattr(self, "h", None):
+            for child in list(getattr(self, "_children", ())):
+                child.close()
             self.lib.pimc_destroy(self.h)
             self.h = None
 
@@ -294,6 +324,7 @@ class Batch:
         if st != PIMC_OK:
             raise _err(self.lib, ctx.h, st)
         self.h = h
+        ctx._children.add(self)
         self._out = (_LevelResult * (self.n_tasks * (self.s_max + 1)))()
 
     def _check(self, st):
@@ -322,6 +353,93 @@ class Batch:
     def close(self):
         if getattr(self, "h", None):
             self.lib.pimc_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _dptr(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Flow:
+    """pimc_flow_create / get_params / set_params / grad / train / log_weights / amplitude / destroy.
+
+    The proposal belongs to the context ``ctx`` (its device, stream and error text)."""
+
+    def __init__(self, ctx: Context, coefs, m, a, b, T, N, p, layers=8, batch=4096, lr=1e-3, beta=0.0,
+                 init_seed=0, init_scale=0.0):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        self.N = int(N)
+        self.D = self.N - 1
+        self.layers = int(layers)
+        self.batch = int(batch)
+        V = potential_from_coefs(coefs)
+        cfg = FlowConfig(int(layers), int(batch), float(lr), float(beta), int(init_seed), float(init_scale))
+        h = C.c_void_p()
+        st = self.lib.pimc_flow_create(ctx.h, C.byref(V), m, a, b, T, N, p, C.byref(cfg), C.byref(h))
+        if st != PIMC_OK:
+            raise _err(self.lib, ctx.h, st)
+        self.h = h
+        ctx._children.add(self)
+
+    def _check(self, st):
+        if st < 0:
+            raise _err(self.lib, self.ctx.h, st)
+        return st
+
+    def get_params(self) -> np.ndarray:
+        """FP32 parameters, shape [layers, FLOW_NPARAM]."""
+        out = np.zeros((self.layers, FLOW_NPARAM), dtype=np.float32)
+        n = C.c_size_t(0)
+        self._check(self.lib.pimc_flow_get_params(self.h, out.ctypes.data_as(C.POINTER(C.c_float)), out.size,
+                                                  C.byref(n)))
+        return out
+
+    def set_params(self, theta):
+        th = np.ascontiguousarray(np.asarray(theta, dtype=np.float32).reshape(-1))
+        self._check(self.lib.pimc_flow_set_params(self.h, th.ctypes.data_as(C.POINTER(C.c_float)), th.size))
+
+    def grad(self, seed, stream):
+        """(loss, ell [batch], grad [layers, FLOW_NPARAM] FP32) of one batch, no update."""
+        loss = C.c_double(0)
+        ell = np.zeros(self.batch, dtype=np.float64)
+        g = np.zeros((self.layers, FLOW_NPARAM), dtype=np.float32)
+        self._check(self.lib.pimc_flow_grad(self.h, seed, stream, C.byref(loss), _dptr(ell),
+                                            g.ctypes.data_as(C.POINTER(C.c_float))))
+        return loss.value, ell, g
+
+    def train(self, seed, stream_base, steps):
+        """(losses [steps], device ms)."""
+        losses = np.zeros(int(steps), dtype=np.float64)
+        ms = C.c_double(0)
+        self._check(self.lib.pimc_flow_train(self.h, seed, stream_base, int(steps), _dptr(losses), C.byref(ms)))
+        return losses, ms.value
+
+    def log_weights(self, seed, stream, first_path, k_paths, want_z=False):
+        """(ell [k], logdet [k], z [k, N-1] or None)."""
+        ell = np.zeros(k_paths, dtype=np.float64)
+        ld = np.zeros(k_paths, dtype=np.float64)
+        z = np.zeros((k_paths, self.D), dtype=np.float64) if want_z else None
+        self._check(self.lib.pimc_flow_log_weights(self.h, seed, stream, first_path, k_paths, _dptr(ell), _dptr(z),
+                                                   _dptr(ld)))
+        return ell, ld, z
+
+    def amplitude(self, n_samples, seed, stream):
+        """(LevelResult of level s, device ms, status)."""
+        r = _LevelResult()
+        ms = C.c_double(0)
+        st = self._check(self.lib.pimc_flow_amplitude(self.h, n_samples, seed, stream, C.byref(r), C.byref(ms)))
+        return LevelResult(r.amp, r.err, r.log_amp, r.relvar, r.ess, int(r.n), int(r.n_nonfinite)), ms.value, st
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pimc_flow_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -15,8 +15,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpimc.so")
 
-SOURCES = ["pimc_host.cpp", "pimc_kernels.hip"]
-HEADERS = ["pimc_tables.hpp", "pimc_device.hpp", "pimc_internal.hpp"]
+SOURCES = ["pimc_host.cpp", "pimc_flow_host.cpp", "pimc_kernels.hip", "pimc_flow.hip"]
+HEADERS = ["pimc_tables.hpp", "pimc_device.hpp", "pimc_internal.hpp", "pimc_math.hpp", "pimc_flow.hpp",
+           "pimc_host_common.hpp"]
 
 # -ffp-contract=off: every fused multiply-add in the kernels is written as fma(); no other
 # expression is contracted, so the arithmetic is exactly what the source states.

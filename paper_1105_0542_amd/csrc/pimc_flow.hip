@@ -1,0 +1,608 @@
+// Learned-proposal kernels (gfx950): affine couplings over the bisection normals.
+//
+// Per-path tensors are feature-major, X[(h-1)*ld + path] for heap node h, so every per-coordinate
+// access of consecutive paths is coalesced. A coupling workgroup takes a tile of 64 paths: the
+// conditioner inputs are rounded to bfloat16 into LDS, the two MLP layers run on
+// v_mfma_f32_16x16x32_bf16 (wave w owns paths 16w..16w+15; operand lanes: A[l%16][8(l/16)+i],
+// B[8(l/16)+i][l%16], C[4(l/16)+j][l%16]), and the MFMA output layout puts s_hat and t of the same
+// (path, coordinate) in the same lane, so the FP64 affine update and log-det follow without
+// another exchange.
+#include <hip/hip_runtime.h>
+
+#include "pimc_flow.hpp"
+#include "pimc_internal.hpp"
+
+namespace pimc {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kLdK = kFlowK + 8;      // LDS row strides (elements), multiples of 8 (16 B)
+constexpr int kLdH = kFlowH + 8;
+constexpr int kLdP = kFlowTile + 8;
+
+// C(16x16) += A(16 rows x K) * BT(16 rows x K)^T; rows K-contiguous, strides in elements.
+__device__ __forceinline__ floatx4 mma16(const __bf16* A, int lda, const __bf16* BT, int ldb, int K, floatx4 c) {
+    const int l = threadIdx.x & 63;
+    for (int ks = 0; ks < K; ks += 32) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(A + (l & 15) * lda + ks + 8 * (l >> 4));
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(BT + (l & 15) * ldb + ks + 8 * (l >> 4));
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+    return c;
+}
+
+__device__ __forceinline__ float silu(float v) { return v / (1.0f + expf(-v)); }
+
+// ------------------------------------------------------------------------------------ base normals
+// u = the plain sampler's bisection normals (node h of path first_path + i), |u|^2/2, log det = 0.
+__global__ void __launch_bounds__(kBlock) k_flow_base(RngKey key, const int* step, uint64_t first_path, uint64_t n,
+                                                      int D, double* __restrict__ X, uint64_t ld,
+                                                      double* __restrict__ hu2, double* __restrict__ logdet) {
+    const uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    RngKey k = key;
+    if (step) k.stream += uint32_t(*step);
+    const PathRng pr = path_rng(k, first_path + i);
+    double z2 = 0.0;
+    for (int j = 0; 2 * j <= D; ++j) {
+        double ze, zo;
+        normal_pair(k, pr, uint32_t(j), ze, zo);
+        if (j > 0) {
+            X[uint64_t(2 * j - 1) * ld + i] = ze;
+            z2 += ze * ze;
+        }
+        if (2 * j + 1 <= D) {
+            X[uint64_t(2 * j) * ld + i] = zo;
+            z2 += zo * zo;
+        }
+    }
+    hu2[i] = 0.5 * z2;
+    logdet[i] = 0.0;
+}
+
+// ------------------------------------------------------------------------------------ coupling forward
+// y[B] = x[B] exp(s) + t, y[A] = x[A]; log det += sum s. In place when Xout == Xin (copyA = 0).
+__global__ void __launch_bounds__(kBlock) k_coupling_fwd(FlowLayerDev L, const double* Xin, double* Xout, uint64_t ld,
+                                                         uint64_t n, double* __restrict__ logdet, int copyA) {
+    __shared__ __attribute__((aligned(16))) __bf16 xa[kFlowTile * kLdK];
+    __shared__ __attribute__((aligned(16))) __bf16 hs[kFlowTile * kLdH];
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    const uint64_t p0 = uint64_t(blockIdx.x) * kFlowTile;
+    for (int i = t; i < kFlowTile * kFlowK; i += kBlock) {
+        const int k = i / kFlowTile, P = i % kFlowTile;
+        double v = 0.0;
+        if (k < L.dA && p0 + P < n) v = Xin[uint64_t(L.Aidx[k]) * ld + p0 + P];
+        xa[P * kLdK + k] = (__bf16)(float)v;
+    }
+    __syncthreads();
+    floatx4 acc[8];
+#pragma unroll
+    for (int nb = 0; nb < 8; ++nb) {
+        acc[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+        acc[nb] = mma16(xa + 16 * w * kLdK, kLdK, L.W1 + 16 * nb * kFlowK, kFlowK, kFlowK, acc[nb]);
+    }
+#pragma unroll
+    for (int nb = 0; nb < 8; ++nb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int P = 16 * w + 4 * (l >> 4) + j, hid = 16 * nb + (l & 15);
+            hs[P * kLdH + hid] = (__bf16)silu(acc[nb][j] + L.b1[hid]);
+        }
+    __syncthreads();
+#pragma unroll
+    for (int nb = 0; nb < 8; ++nb) {
+        acc[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+        acc[nb] = mma16(hs + 16 * w * kLdH, kLdH, L.W2 + 16 * nb * kFlowH, kFlowH, kFlowH, acc[nb]);
+    }
+    double lsum[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = 16 * nb + (l & 15);
+            const uint64_t P = p0 + 16 * w + 4 * (l >> 4) + j;
+            if (k < L.dB) {
+                const float sh = acc[nb][j] + L.b2[k];
+                const float tt = acc[nb + 4][j] + L.b2[64 + k];
+                const float s = 2.0f * tanhf(0.5f * sh);
+                if (P < n) {
+                    const uint64_t a = uint64_t(L.Bidx[k]) * ld + P;
+                    Xout[a] = Xin[a] * exp(double(s)) + double(tt);
+                }
+                lsum[j] += double(s);
+            }
+        }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        double v = lsum[j];
+        v += __shfl_xor(v, 8, 64);
+        v += __shfl_xor(v, 4, 64);
+        v += __shfl_xor(v, 2, 64);
+        v += __shfl_xor(v, 1, 64);
+        const uint64_t P = p0 + 16 * w + 4 * (l >> 4) + j;
+        if ((l & 15) == 0 && P < n) logdet[P] += v;
+    }
+    if (copyA) {
+        for (int i = t; i < kFlowTile * kFlowK; i += kBlock) {
+            const int k = i / kFlowTile, P = i % kFlowTile;
+            if (k < L.dA && p0 + P < n) {
+                const uint64_t a = uint64_t(L.Aidx[k]) * ld + p0 + P;
+                Xout[a] = Xin[a];
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------ coupling backward
+// Given G = d(sum_i alpha_i l_i)/dy for this layer's output and its input x, recompute the layer,
+// overwrite G with the gradient for x and write this tile's parameter gradient to gpart (FP32,
+// [W1 | b1 | W2 | b2] of this layer at gpart + tile*stride + layer_off).
+__global__ void __launch_bounds__(kBlock) k_coupling_bwd(FlowLayerDev L, const double* __restrict__ Xin, double* G,
+                                                         uint64_t ld, uint64_t n, const double* __restrict__ alpha,
+                                                         float* __restrict__ gpart, uint64_t gstride, int layer_off) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+    __bf16* xa = reinterpret_cast<__bf16*>(lds_raw);                  // [P][in]      64 x kLdK
+    __bf16* xaT = xa + kFlowTile * kLdK;                               // [in][P]      64 x kLdP
+    __bf16* hs = xaT + kFlowK * kLdP;                                  // [P][hid], later g_o [P][out]
+    __bf16* hT = hs + kFlowTile * kLdH;                                // [hid][P]     128 x kLdP
+    __bf16* goT = hT + kFlowH * kLdP;                                  // [out][P]
+    __bf16* gp = goT + kFlowH * kLdP;                                  // [P][hid]
+    __bf16* gpT = gp + kFlowTile * kLdH;                               // [hid][P]
+    float* bsum = reinterpret_cast<float*>(gpT + kFlowH * kLdP);       // [4 waves][2][128]
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    const uint64_t p0 = uint64_t(blockIdx.x) * kFlowTile;
+    float* gout = gpart + uint64_t(blockIdx.x) * gstride + layer_off;
+    for (int i = t; i < kFlowTile * kFlowK; i += kBlock) {
+        const int k = i / kFlowTile, P = i % kFlowTile;
+        double v = 0.0;
+        if (k < L.dA && p0 + P < n) v = Xin[uint64_t(L.Aidx[k]) * ld + p0 + P];
+        const __bf16 bv = (__bf16)(float)v;
+        xa[P * kLdK + k] = bv;
+        xaT[k * kLdP + P] = bv;
+    }
+    __syncthreads();
+    floatx4 pre[8], acc[8];
+#pragma unroll
+    for (int nb = 0; nb < 8; ++nb) {
+        pre[nb] = mma16(xa + 16 * w * kLdK, kLdK, L.W1 + 16 * nb * kFlowK, kFlowK, kFlowK, floatx4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int P = 16 * w + 4 * (l >> 4) + j, hid = 16 * nb + (l & 15);
+            pre[nb][j] += L.b1[hid];
+            const __bf16 hv = (__bf16)silu(pre[nb][j]);
+            hs[P * kLdH + hid] = hv;
+            hT[hid * kLdP + P] = hv;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int nb = 0; nb < 8; ++nb)
+        acc[nb] = mma16(hs + 16 * w * kLdH, kLdH, L.W2 + 16 * nb * kFlowH, kFlowH, kFlowH, floatx4{0.f, 0.f, 0.f, 0.f});
+    __syncthreads();                                                   // hs is reused for g_o below
+    __bf16* go = hs;
+    float gb2[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};          // per nb: sum over this lane's 4 paths
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = 16 * nb + (l & 15);
+            const int Pl = 16 * w + 4 * (l >> 4) + j;
+            const uint64_t P = p0 + Pl;
+            float gsh = 0.f, gt = 0.f;
+            if (k < L.dB && P < n) {
+                const float sh = acc[nb][j] + L.b2[k];
+                const float th = tanhf(0.5f * sh);
+                const float s = 2.0f * th;
+                const uint64_t a = uint64_t(L.Bidx[k]) * ld + P;
+                const double es = exp(double(s));
+                const double gy = G[a];
+                G[a] = gy * es;
+                const double gs = gy * Xin[a] * es + alpha[P];
+                gsh = float(gs * (1.0 - double(th) * double(th)));
+                gt = float(gy);
+            }
+            const __bf16 b_sh = (__bf16)gsh, b_t = (__bf16)gt;
+            go[Pl * kLdH + k] = b_sh;
+            go[Pl * kLdH + 64 + k] = b_t;
+            goT[k * kLdP + Pl] = b_sh;
+            goT[(64 + k) * kLdP + Pl] = b_t;
+            gb2[nb] += gsh;
+            gb2[nb + 4] += gt;
+        }
+    __syncthreads();
+    // g_h = g_o W2 (A = g_o [P][out], BT = W2T [hid][out]); g_pre = g_h silu'(pre)
+    float gb1[8];
+#pragma unroll
+    for (int nb = 0; nb < 8; ++nb) {
+        const floatx4 gh = mma16(go + 16 * w * kLdH, kLdH, L.W2T + 16 * nb * kFlowH, kFlowH, kFlowH,
+                                 floatx4{0.f, 0.f, 0.f, 0.f});
+        gb1[nb] = 0.f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int Pl = 16 * w + 4 * (l >> 4) + j, hid = 16 * nb + (l & 15);
+            const float v = pre[nb][j];
+            const float sg = 1.0f / (1.0f + expf(-v));
+            const float g = (p0 + Pl < n) ? gh[j] * (sg * (1.0f + v * (1.0f - sg))) : 0.f;
+            const __bf16 bg = (__bf16)g;
+            gp[Pl * kLdH + hid] = bg;
+            gpT[hid * kLdP + Pl] = bg;
+            gb1[nb] += g;
+        }
+    }
+    __syncthreads();
+    // g_xa = g_pre W1 (A = g_pre [P][hid], BT = W1T [in][hid]) into G[A]
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+        const floatx4 gx = mma16(gp + 16 * w * kLdH, kLdH, L.W1T + 16 * nb * kFlowH, kFlowH, kFlowH,
+                                 floatx4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = 16 * nb + (l & 15);
+            const uint64_t P = p0 + 16 * w + 4 * (l >> 4) + j;
+            if (k < L.dA && P < n) G[uint64_t(L.Aidx[k]) * ld + P] += double(gx[j]);
+        }
+    }
+    // weight gradients of this tile: wave w owns output rows 32w..32w+31
+    // g_W2[out][hid] = sum_P g_o[P][out] h[P][hid]: A = goT [out][P], BT = hT [hid][P]
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 8; ++nb) {
+            const int r0 = 32 * w + 16 * mb;
+            const floatx4 c = mma16(goT + r0 * kLdP, kLdP, hT + 16 * nb * kLdP, kLdP, kFlowTile,
+                                    floatx4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                gout[kFlowOffW2 + (r0 + 4 * (l >> 4) + j) * kFlowH + 16 * nb + (l & 15)] = c[j];
+        }
+    // g_W1[hid][in] = sum_P g_pre[P][hid] xa[P][in]: A = gpT [hid][P], BT = xaT [in][P]
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+            const int r0 = 32 * w + 16 * mb;
+            const floatx4 c = mma16(gpT + r0 * kLdP, kLdP, xaT + 16 * nb * kLdP, kLdP, kFlowTile,
+                                    floatx4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                gout[(r0 + 4 * (l >> 4) + j) * kFlowK + 16 * nb + (l & 15)] = c[j];
+        }
+    // bias gradients: lanes with equal (l & 15) hold the same column; add the 4 row groups, then waves
+#pragma unroll
+    for (int nb = 0; nb < 8; ++nb) {
+        float a = gb1[nb], b = gb2[nb];
+        a += __shfl_xor(a, 16, 64);
+        a += __shfl_xor(a, 32, 64);
+        b += __shfl_xor(b, 16, 64);
+        b += __shfl_xor(b, 32, 64);
+        if (l < 16) {
+            bsum[(w * 2 + 0) * kFlowH + 16 * nb + l] = a;
+            bsum[(w * 2 + 1) * kFlowH + 16 * nb + l] = b;
+        }
+    }
+    __syncthreads();
+    if (t < kFlowH) {
+        float a = 0.f, b = 0.f;
+        for (int ww = 0; ww < 4; ++ww) {
+            a += bsum[(ww * 2 + 0) * kFlowH + t];
+            b += bsum[(ww * 2 + 1) * kFlowH + t];
+        }
+        gout[kFlowOffB1 + t] = a;
+        gout[kFlowOffB2 + t] = b;
+    }
+}
+
+// ------------------------------------------------------------------------------------ action and its gradient
+// One thread per path: the level-s path from the normals z, S = sum_k eps W_p with each slice as
+// sum_k dlt^(2k) P_k(v), v = mid^2 (even potential) or mid, dlt = q_{k+1} - q_k, the folded table
+// of the level (P_k highest power first, consecutive in k). Writes l = -(S - shift) - |z|^2/2 +
+// |u|^2/2 + log det; with G, also G = dl/dz = -dS/dz - z: dS/dq from the slice derivatives, then
+// the adjoint of the (linear) bisection map.
+__global__ void __launch_bounds__(kBlock) k_flow_action_grad(const double* __restrict__ tab, const int* __restrict__ deg,
+                                                             int K, int even, const double* __restrict__ sig, double shift,
+                                                             double a, double b, int s, const double* __restrict__ X,
+                                                             uint64_t ld, uint64_t n, const double* __restrict__ hu2,
+                                                             const double* __restrict__ logdet, double* __restrict__ ell,
+                                                             double* __restrict__ G, double* __restrict__ q,
+                                                             double* __restrict__ gq) {
+    const uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int N = 1 << s;
+    q[i] = a;
+    q[uint64_t(N) * n + i] = b;
+    double z2 = 0.0;
+    for (int lev = 1; lev <= s; ++lev) {
+        const int step = 1 << (s - lev);
+        for (int i2 = 0; i2 < (1 << (lev - 1)); ++i2) {
+            const int h = (1 << (lev - 1)) + i2;
+            const int j = (2 * i2 + 1) * step;
+            const double z = X[uint64_t(h - 1) * ld + i];
+            z2 += z * z;
+            q[uint64_t(j) * n + i] = sig[lev] * z + 0.5 * (q[uint64_t(j - step) * n + i] + q[uint64_t(j + step) * n + i]);
+        }
+    }
+    const bool grad = G != nullptr;
+    if (grad)
+        for (int j = 0; j <= N; ++j) gq[uint64_t(j) * n + i] = 0.0;
+    double S = 0.0;
+    for (int k = 0; k < N; ++k) {
+        const double q0 = q[uint64_t(k) * n + i], q1 = q[uint64_t(k + 1) * n + i];
+        const double mid = 0.5 * (q0 + q1), dl = q1 - q0;
+        const double y = even ? mid * mid : mid, zz = dl * dl;
+        double val = 0.0, dmid = 0.0, ddl = 0.0, pw = 1.0, pwm1 = 0.0;
+        int off = 0;
+        for (int kk = 0; kk < K; ++kk) {
+            const int d = deg[kk];
+            double P = tab[off], dP = 0.0;
+            for (int e = 1; e <= d; ++e) {
+                dP = fma(dP, y, P);
+                P = fma(P, y, tab[off + e]);
+            }
+            off += d + 1;
+            val += pw * P;
+            dmid += pw * dP;
+            ddl += double(kk) * pwm1 * P;
+            pwm1 = pw;
+            pw *= zz;
+        }
+        S += val;
+        if (grad) {
+            const double gmid = even ? 2.0 * mid * dmid : dmid;   // d/dmid of sum_k dlt^(2k) P_k(v)
+            const double gdl = 2.0 * dl * ddl;                    // d/ddlt of the same
+            gq[uint64_t(k) * n + i] += 0.5 * gmid - gdl;
+            gq[uint64_t(k + 1) * n + i] += 0.5 * gmid + gdl;
+        }
+    }
+    for (int lev = s; grad && lev >= 1; --lev) {
+        const int step = 1 << (s - lev);
+        for (int i2 = 0; i2 < (1 << (lev - 1)); ++i2) {
+            const int h = (1 << (lev - 1)) + i2;
+            const int j = (2 * i2 + 1) * step;
+            const double g = gq[uint64_t(j) * n + i];
+            const double z = X[uint64_t(h - 1) * ld + i];
+            G[uint64_t(h - 1) * ld + i] = -sig[lev] * g - z;
+            gq[uint64_t(j - step) * n + i] += 0.5 * g;
+            gq[uint64_t(j + step) * n + i] += 0.5 * g;
+        }
+    }
+    ell[i] = -(S - shift) - 0.5 * z2 + hu2[i] + logdet[i];
+}
+
+// One workgroup per canonical chunk: lane t adds d = expm1(l) of paths c*CH + r*kBlock + t,
+// r = 0..ppl-1, in order; then the waves and the four wave sums in a fixed order.
+__global__ void __launch_bounds__(kBlock) k_flow_partials(const double* __restrict__ ell, uint64_t ell_first_path,
+                                                          uint64_t n_total, uint64_t first_chunk, uint32_t ppl,
+                                                          double* __restrict__ partials) {
+    __shared__ double red[4][3];
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    const uint64_t c = first_chunk + blockIdx.x;
+    const uint64_t CH = uint64_t(kBlock) * ppl;
+    double s1 = 0.0, s2 = 0.0;
+    int bad = 0;
+    for (uint32_t r = 0; r < ppl; ++r) {
+        const uint64_t path = c * CH + uint64_t(r) * kBlock + t;
+        if (path < n_total) {
+            const double d = expm1(ell[path - ell_first_path]);
+            s1 += d;
+            s2 += d * d;
+            bad += isfinite(d) ? 0 : 1;
+        }
+    }
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    double nb = wave_sum(double(bad));
+    if (l == 0) {
+        red[w][0] = s1;
+        red[w][1] = s2;
+        red[w][2] = nb;
+    }
+    __syncthreads();
+    if (t == 0) {
+        double a = 0.0, b = 0.0, e = 0.0;
+        for (int ww = 0; ww < kBlock / 64; ++ww) {
+            a += red[ww][0];
+            b += red[ww][1];
+            e += red[ww][2];
+        }
+        const uint64_t rem = n_total - c * CH;
+        double* o = partials + c * 4;
+        o[0] = double(rem < CH ? rem : CH);
+        o[1] = a;
+        o[2] = b;
+        o[3] = e;
+    }
+}
+
+// ------------------------------------------------------------------------------------ loss weights
+// alpha_i = (1-beta) 2 exp(2 l_i) / sum_j exp(2 l_j) - beta/n; loss = (1-beta) log mean exp(2l) -
+// beta mean l, stored at loss[*step] (loss[0] without step). One workgroup, fixed reduction order.
+__global__ void __launch_bounds__(kBlock) k_flow_alpha(const double* __restrict__ ell, uint64_t n, double beta,
+                                                       double* __restrict__ alpha, double* __restrict__ loss,
+                                                       const int* __restrict__ step) {
+    __shared__ double red[kBlock];
+    const int t = threadIdx.x;
+    double mx = -HUGE_VAL;
+    for (uint64_t i = t; i < n; i += kBlock) mx = fmax(mx, 2.0 * ell[i]);
+    red[t] = mx;
+    __syncthreads();
+    for (int w = kBlock / 2; w >= 1; w >>= 1) {
+        if (t < w) red[t] = fmax(red[t], red[t + w]);
+        __syncthreads();
+    }
+    mx = red[0];
+    __syncthreads();
+    double se = 0.0, sl = 0.0;
+    for (uint64_t i = t; i < n; i += kBlock) {
+        se += exp(2.0 * ell[i] - mx);
+        sl += ell[i];
+    }
+    red[t] = se;
+    __syncthreads();
+    for (int w = kBlock / 2; w >= 1; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    se = red[0];
+    __syncthreads();
+    red[t] = sl;
+    __syncthreads();
+    for (int w = kBlock / 2; w >= 1; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    sl = red[0];
+    for (uint64_t i = t; i < n; i += kBlock)
+        alpha[i] = (1.0 - beta) * 2.0 * exp(2.0 * ell[i] - mx) / se - beta / double(n);
+    if (t == 0 && loss) loss[step ? *step : 0] = (1.0 - beta) * (mx + log(se / double(n))) - beta * sl / double(n);
+}
+
+__global__ void k_flow_seed(double* __restrict__ G, const double* __restrict__ alpha, int D, uint64_t ld, uint64_t n) {
+    const uint64_t g = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (g >= uint64_t(D) * n) return;
+    const uint64_t h = g / n, i = g % n;
+    G[h * ld + i] *= alpha[i];
+}
+
+// ------------------------------------------------------------------------------------ parameters
+__global__ void k_grad_reduce(const float* __restrict__ gpart, int tiles, uint64_t stride, uint64_t count,
+                              float* __restrict__ grad) {
+    const uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= count) return;
+    double s = 0.0;
+    for (int t = 0; t < tiles; ++t) s += double(gpart[uint64_t(t) * stride + i]);
+    grad[i] = float(s);
+}
+
+__device__ __forceinline__ void store_bf16_copies(int layer, int off, float v, __bf16* W1, __bf16* W2, __bf16* W1T,
+                                                  __bf16* W2T) {
+    const __bf16 b = (__bf16)v;
+    if (off < kFlowOffB1) {
+        const int hid = off / kFlowK, in = off % kFlowK;
+        W1[size_t(layer) * kFlowH * kFlowK + off] = b;
+        W1T[size_t(layer) * kFlowH * kFlowK + in * kFlowH + hid] = b;
+    } else if (off >= kFlowOffW2 && off < kFlowOffB2) {
+        const int o = off - kFlowOffW2;
+        const int out = o / kFlowH, hid = o % kFlowH;
+        W2[size_t(layer) * kFlowH * kFlowH + o] = b;
+        W2T[size_t(layer) * kFlowH * kFlowH + hid * kFlowH + out] = b;
+    }
+}
+
+// Adam (beta1 0.9, beta2 0.999, eps 1e-8) on the FP32 master parameters, then bfloat16 copies.
+__global__ void k_adam(float* __restrict__ theta, float* __restrict__ m, float* __restrict__ v,
+                       const float* __restrict__ grad, int layers, const int* __restrict__ step, float lr,
+                       __bf16* W1, __bf16* W2, __bf16* W1T, __bf16* W2T) {
+    const uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= uint64_t(layers) * kFlowNP) return;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const int tstep = *step + 1;
+    const float g = grad[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * g;
+    const float vi = b2 * v[i] + (1.0f - b2) * g * g;
+    m[i] = mi;
+    v[i] = vi;
+    const float mh = mi / (1.0f - powf(b1, float(tstep)));
+    const float vh = vi / (1.0f - powf(b2, float(tstep)));
+    const float th = theta[i] - lr * mh / (sqrtf(vh) + 1e-8f);
+    theta[i] = th;
+    store_bf16_copies(int(i / kFlowNP), int(i % kFlowNP), th, W1, W2, W1T, W2T);
+}
+
+__global__ void k_params_to_bf16(const float* __restrict__ theta, int layers, __bf16* W1, __bf16* W2, __bf16* W1T,
+                                 __bf16* W2T) {
+    const uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= uint64_t(layers) * kFlowNP) return;
+    store_bf16_copies(int(i / kFlowNP), int(i % kFlowNP), theta[i], W1, W2, W1T, W2T);
+}
+
+__global__ void k_step_inc(int* step) { *step += 1; }
+
+// ------------------------------------------------------------------------------------ launchers
+static inline uint32_t blocks_for(uint64_t n) { return uint32_t((n + kBlock - 1) / kBlock); }
+
+hipError_t launch_flow_base(const RngKey& key, const int* step, uint64_t first_path, uint64_t n, int D, double* X,
+                            uint64_t ld, double* hu2, double* logdet, hipStream_t st) {
+    hipLaunchKernelGGL(k_flow_base, dim3(blocks_for(n)), dim3(kBlock), 0, st, key, step, first_path, n, D, X, ld, hu2,
+                       logdet);
+    return hipGetLastError();
+}
+
+hipError_t launch_coupling_fwd(const FlowLayerDev& L, const double* Xin, double* Xout, uint64_t ld, uint64_t n,
+                               double* logdet, int copyA, hipStream_t st) {
+    const uint32_t tiles = uint32_t((n + kFlowTile - 1) / kFlowTile);
+    hipLaunchKernelGGL(k_coupling_fwd, dim3(tiles), dim3(kBlock), 0, st, L, Xin, Xout, ld, n, logdet, copyA);
+    return hipGetLastError();
+}
+
+size_t coupling_bwd_lds_bytes() {
+    return size_t(kFlowTile * kLdK + kFlowK * kLdP + kFlowTile * kLdH + kFlowH * kLdP + kFlowH * kLdP +
+                  kFlowTile * kLdH + kFlowH * kLdP) * sizeof(__bf16) + size_t(4 * 2 * kFlowH) * sizeof(float);
+}
+
+hipError_t launch_coupling_bwd(const FlowLayerDev& L, const double* Xin, double* G, uint64_t ld, uint64_t n,
+                               const double* alpha, float* gpart, uint64_t gstride, int layer_off, hipStream_t st) {
+    const uint32_t tiles = uint32_t((n + kFlowTile - 1) / kFlowTile);
+    hipLaunchKernelGGL(k_coupling_bwd, dim3(tiles), dim3(kBlock), coupling_bwd_lds_bytes(), st, L, Xin, G, ld, n,
+                       alpha, gpart, gstride, layer_off);
+    return hipGetLastError();
+}
+
+hipError_t launch_flow_action_grad(const double* tab, const int* deg, int K, int even, const double* sig, double shift,
+                                   double a, double b, int s, const double* X, uint64_t ld, uint64_t n,
+                                   const double* hu2, const double* logdet, double* ell, double* G, double* qscr,
+                                   double* gqscr, hipStream_t st) {
+    hipLaunchKernelGGL(k_flow_action_grad, dim3(blocks_for(n)), dim3(kBlock), 0, st, tab, deg, K, even, sig, shift, a,
+                       b, s, X, ld, n, hu2, logdet, ell, G, qscr, gqscr);
+    return hipGetLastError();
+}
+
+hipError_t launch_flow_partials(const double* ell, uint64_t ell_first_path, uint64_t n_total, uint64_t first_chunk,
+                                uint64_t n_chunks, uint32_t ppl, double* partials, hipStream_t st) {
+    hipLaunchKernelGGL(k_flow_partials, dim3(uint32_t(n_chunks)), dim3(kBlock), 0, st, ell, ell_first_path, n_total,
+                       first_chunk, ppl, partials);
+    return hipGetLastError();
+}
+
+hipError_t flow_prepare() {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_coupling_bwd),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, int(coupling_bwd_lds_bytes()));
+}
+
+hipError_t launch_flow_alpha(const double* ell, uint64_t n, double beta, double* alpha, double* loss_out,
+                             const int* step, hipStream_t st) {
+    hipLaunchKernelGGL(k_flow_alpha, dim3(1), dim3(kBlock), 0, st, ell, n, beta, alpha, loss_out, step);
+    return hipGetLastError();
+}
+
+hipError_t launch_flow_seed(double* G, const double* alpha, int D, uint64_t ld, uint64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_flow_seed, dim3(blocks_for(uint64_t(D) * n)), dim3(kBlock), 0, st, G, alpha, D, ld, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_reduce(const float* gpart, int tiles, uint64_t stride, uint64_t count, float* grad,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(k_grad_reduce, dim3(blocks_for(count)), dim3(kBlock), 0, st, gpart, tiles, stride, count, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float* theta, float* m, float* v, const float* grad, int layers, const int* step, float lr,
+                       __bf16* W1, __bf16* W2, __bf16* W1T, __bf16* W2T, hipStream_t st) {
+    hipLaunchKernelGGL(k_adam, dim3(blocks_for(uint64_t(layers) * kFlowNP)), dim3(kBlock), 0, st, theta, m, v, grad,
+                       layers, step, lr, W1, W2, W1T, W2T);
+    return hipGetLastError();
+}
+
+hipError_t launch_params_to_bf16(const float* theta, int layers, __bf16* W1, __bf16* W2, __bf16* W1T, __bf16* W2T,
+                                 hipStream_t st) {
+    hipLaunchKernelGGL(k_params_to_bf16, dim3(blocks_for(uint64_t(layers) * kFlowNP)), dim3(kBlock), 0, st, theta,
+                       layers, W1, W2, W1T, W2T);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_inc(int* step, hipStream_t st) {
+    hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(1), 0, st, step);
+    return hipGetLastError();
+}
+
+}  // namespace pimc

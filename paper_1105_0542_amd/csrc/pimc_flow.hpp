@@ -1,0 +1,72 @@
+// Learned proposal for the bisection normals: affine couplings whose conditioners are 2-layer MLPs
+// (bfloat16 MFMA with FP32 accumulation), affine update, log-determinant, action and weights in
+// FP64. Shared by the flow kernels (pimc_flow.hip) and the host code.
+//
+// The estimator stays the paper's (Sec. 4): A_N^(p) = K_0 E_phi[exp(-sum eps W_p)]; with z = f(u),
+// u ~ N(0, I), it is K_0 E_u[w] with log w = -(S(z) - S_ref) - |z|^2/2 + |u|^2/2 + log det df/du.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pimc_device.hpp"
+
+namespace pimc {
+
+constexpr int kFlowH = 128;                       // hidden width
+constexpr int kFlowK = 64;                        // padded conditioner width (|A| <= 64, |B| <= 64)
+constexpr int kFlowNP = kFlowH * kFlowK + kFlowH + kFlowH * kFlowH + kFlowH;   // parameters per layer
+constexpr int kFlowOffB1 = kFlowH * kFlowK;
+constexpr int kFlowOffW2 = kFlowOffB1 + kFlowH;
+constexpr int kFlowOffB2 = kFlowOffW2 + kFlowH * kFlowH;
+constexpr int kFlowTile = 64;                     // paths per workgroup of the coupling kernels
+constexpr int kFlowMaxLayers = 16;
+
+// One coupling layer as the kernels read it.
+struct FlowLayerDev {
+    const __bf16* W1;      // [128][64]  row-major [hidden][in]
+    const __bf16* W2;      // [128][128] row-major [out][hidden]
+    const __bf16* W1T;     // [64][128]  [in][hidden]
+    const __bf16* W2T;     // [128][128] [hidden][out]
+    const float* b1;       // [128]
+    const float* b2;       // [128]
+    const int* Aidx;       // [64] conditioner coordinates (heap node - 1), ascending
+    const int* Bidx;       // [64] transformed coordinates
+    int dA, dB;
+};
+
+// Base normals u (the plain sampler's, stream key.stream + *step when step is not null), |u|^2/2,
+// log det = 0.
+hipError_t launch_flow_base(const RngKey& key, const int* step, uint64_t first_path, uint64_t n, int D, double* X,
+                            uint64_t ld, double* hu2, double* logdet, hipStream_t st);
+hipError_t launch_coupling_fwd(const FlowLayerDev& L, const double* Xin, double* Xout, uint64_t ld, uint64_t n,
+                               double* logdet, int copyA, hipStream_t st);
+hipError_t launch_coupling_bwd(const FlowLayerDev& L, const double* Xin, double* G, uint64_t ld, uint64_t n,
+                               const double* alpha, float* gpart, uint64_t gpart_stride, int layer_off,
+                               hipStream_t st);
+// Level-s action of the paths in X, log weights ell; with G not null also G = d ell / dz. qscr and
+// gqscr: device scratch of (N+1) * n doubles each (gqscr unused without G).
+hipError_t launch_flow_action_grad(const double* tab, const int* deg, int K, int even, const double* sig, double shift,
+                                   double a, double b, int s, const double* X, uint64_t ld, uint64_t n,
+                                   const double* hu2, const double* logdet, double* ell, double* G, double* qscr,
+                                   double* gqscr, hipStream_t st);
+// Canonical chunk sums (n, sum d, sum d^2, non-finite count), d = expm1(ell), of chunks
+// first_chunk .. first_chunk + n_chunks - 1 of ell (chunk = kBlock * ppl paths, the last one may be
+// short: n_total paths in all) into partials[chunk][4].
+hipError_t launch_flow_partials(const double* ell, uint64_t ell_first_path, uint64_t n_total, uint64_t first_chunk,
+                                uint64_t n_chunks, uint32_t ppl, double* partials, hipStream_t st);
+// Dynamic LDS of the coupling backward kernel; flow_prepare raises the kernel's LDS limit to it.
+size_t coupling_bwd_lds_bytes();
+hipError_t flow_prepare();
+hipError_t launch_flow_alpha(const double* ell, uint64_t n, double beta, double* alpha, double* loss_out,
+                             const int* step, hipStream_t st);
+hipError_t launch_flow_seed(double* G, const double* alpha, int D, uint64_t ld, uint64_t n, hipStream_t st);
+hipError_t launch_grad_reduce(const float* gpart, int tiles, uint64_t stride, uint64_t count, float* grad,
+                              hipStream_t st);
+hipError_t launch_adam(float* theta, float* m, float* v, const float* grad, int layers, const int* step, float lr,
+                       __bf16* W1, __bf16* W2, __bf16* W1T, __bf16* W2T, hipStream_t st);
+hipError_t launch_params_to_bf16(const float* theta, int layers, __bf16* W1, __bf16* W2, __bf16* W1T, __bf16* W2T,
+                                 hipStream_t st);
+hipError_t launch_step_inc(int* step, hipStream_t st);
+
+}  // namespace pimc

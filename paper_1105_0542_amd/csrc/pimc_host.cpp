@@ -21,10 +21,12 @@
 #include "pimc.h"
 #include "pimc_internal.hpp"
 #include "pimc_tables.hpp"
+#include "pimc_host_common.hpp"
 
 using namespace pimc;
+using namespace pimc_host;
 
-namespace {
+namespace pimc_host {
 
 thread_local char g_thread_error[512] = "";
 
@@ -35,30 +37,6 @@ void set_thread_error(const char* fmt, ...) {
     va_end(ap);
 }
 
-}  // namespace
-
-struct pimc_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    char err[512] = "";
-    // device buffers, grown on demand
-    void* d_prm = nullptr;          size_t prm_bytes = 0;
-    double* d_partials = nullptr;   size_t partial_bytes = 0;
-    double* d_red = nullptr;        size_t red_bytes = 0;
-    uint64_t* d_seg = nullptr;      size_t seg_bytes = 0;
-    std::vector<uint64_t> h_seg;    // segment base/len of the last reduction (kept alive for the async copy)
-    double* d_dump = nullptr;       size_t dump_bytes = 0;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    // last estimation
-    uint64_t last_chunks = 0, last_chunk_paths = 0;
-    int last_s = -1;
-    bool last_hier = false;
-    std::vector<double> last_shift;
-    double last_ms = 0.0;
-};
-
-namespace {
 
 int ctx_fail(pimc_ctx* c, int status, const char* fmt, ...) {
     char buf[512];
@@ -70,13 +48,6 @@ int ctx_fail(pimc_ctx* c, int status, const char* fmt, ...) {
     std::snprintf(g_thread_error, sizeof(g_thread_error), "%s", buf);
     return status;
 }
-
-#define HIP_TRY(ctx, expr)                                                                      \
-    do {                                                                                        \
-        hipError_t e_ = (expr);                                                                 \
-        if (e_ != hipSuccess)                                                                   \
-            return ctx_fail((ctx), PIMC_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
-    } while (0)
 
 int ensure(pimc_ctx* c, void** buf, size_t* have, size_t need) {
     if (need <= *have) return PIMC_OK;
@@ -102,21 +73,6 @@ int log2_exact(uint32_t N) {
 }
 
 // ------------------------------------------------------------------------------------- problem
-struct Problem {
-    int s = 0, p = 0;
-    bool even = true;
-    EvalKind kind = EvalKind::GenericEven64;
-    int U = 1, D = 0;
-    double a = 0, b = 0, T = 0, pref = 1.0, K0 = 0.0;
-    std::vector<int> deg;            // per k in the evaluation variable
-    int stride = 0;                  // doubles per level table
-    std::vector<double> tab;         // (s+1) * stride
-    std::vector<float> tab32;
-    std::vector<double> sig;         // s+1
-    std::vector<double> shift;       // s+1
-    double level0_action = 0.0;      // T W_p((a+b)/2, (b-a)/2; T)
-};
-
 PolyD rescaled_potential(const pimc_potential* V, double m) {
     PolyD poly(V->coef, V->coef + V->degree + 1);
     if (m != 1.0) {

@@ -129,3 +129,21 @@ def test_create_without_device_reports_device_error():
     with pytest.raises(P.PimcError) as ei:
         P.Context(use_torch_stream=False)
     assert ei.value.status == -4
+
+
+def test_flow_entry_points_validate_without_a_device():
+    """The proposal's entry points reject a missing context or handle before touching a device."""
+    lib = P.load_library()
+    V = P.potential_from_coefs(P.quartic(1, 10))
+    cfg = P.binding.FlowConfig(8, 4096, 1e-3, 0.0, 0, 0.0)
+    h = ctypes.c_void_p()
+    assert lib.pimc_flow_create(None, ctypes.byref(V), 1.0, 0.0, 1.0, 2.0, 128, 12, ctypes.byref(cfg),
+                                ctypes.byref(h)) == -1
+    assert not h.value
+    assert lib.pimc_flow_create(None, ctypes.byref(V), 1.0, 0.0, 1.0, 2.0, 100, 12, ctypes.byref(cfg),
+                                ctypes.byref(h)) == -1          # N not a power of two
+    assert lib.pimc_flow_destroy(None) == 0
+    assert lib.pimc_flow_train(None, 1, 0, 1, None, None) == -1
+    assert lib.pimc_flow_amplitude(None, 100, 1, 0, None, None) == -1
+    loss = ctypes.c_double(0)
+    assert lib.pimc_flow_grad(None, 1, 0, ctypes.byref(loss), None, None) == -1
