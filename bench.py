@@ -36,6 +36,10 @@ FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector: 256 CU x 64 lanes x 2 FLO
 CPU_SAMPLE_PATHS = 2048          # per point, for the oracle timing
 # Precision workload: FP32 slice polynomials against FP64, g = 10, p = 18, N = 512, T = 1.
 PREC = dict(g=10.0, p=18, s=9, T=1.0, samples=1_000_000_000, oracle_paths=20_000)
+# Learned proposal: the anharmonic oscillator g = 10 at p = 12, N = 128, T = 2, a = 0, b = 1; 8 couplings,
+# batches of 4096 fresh base paths, 2442 Adam steps (1e7 training paths), loss 0.1 log E[w^2] + 0.9 KL.
+FLOW = dict(g=10.0, p=12, s=7, T=2.0, layers=8, batch=4096, lr=1e-3, beta=0.9, steps=2442,
+            est_samples=1 << 24, plain_samples=1 << 26, target=1e-5)
 KERNEL_SOURCES = ["pimc_device.hpp", "pimc_kernels.hip", "pimc_internal.hpp", "pimc_tables.hpp", "pimc_math.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_amplitude_quartic64_p18_s10.json")
 
@@ -129,6 +133,46 @@ def cpu_baseline(paths_per_point: int):
                       f"{dt:.1f} s wall"}
 
 
+def proposal_section(P, ctx, steps):
+    """Plain bisection sampler against the trained affine-coupling proposal on one problem: weight
+    variance, effective sample size, estimation rate, training time, and the device time to reach
+    a relative error of 1e-5 (samples needed = relvar / 1e-10)."""
+    F = FLOW
+    coefs = P.quartic(1.0, F["g"])
+    N = 1 << F["s"]
+    est_stream = 1 << 30
+    res, _ = ctx.amplitude(coefs, 1.0, 0.0, 1.0, F["T"], N, F["p"], F["plain_samples"], 1, est_stream, 0)
+    plain = res[F["s"]]
+    plain_rate = F["plain_samples"] / (ctx.last_kernel_ms() / 1e3)
+    f = P.Flow(ctx, coefs, 1.0, 0.0, 1.0, F["T"], N, F["p"], layers=F["layers"], batch=F["batch"], lr=F["lr"],
+               beta=F["beta"])
+    untrained, _, _ = f.amplitude(F["est_samples"], 1, est_stream)
+    losses, train_ms = f.train(1, 1 << 31, steps)
+    f.amplitude(1 << 20, 1, est_stream)                      # warm
+    trained, est_ms, _ = f.amplitude(F["est_samples"], 1, est_stream)
+    flow_rate = F["est_samples"] / (est_ms / 1e3)
+    tgt2 = F["target"] ** 2
+    t_plain = plain.relvar / tgt2 / plain_rate
+    t_flow = trained.relvar / tgt2 / flow_rate
+    f.close()
+    return {
+        "workload": f"V=q^2/2+{F['g']:g} q^4/24, p={F['p']}, N={N}, T={F['T']:g}, a=0, b=1; {F['layers']} affine "
+                    f"couplings (bf16 MFMA MLPs 64-128-128), batch {F['batch']}, {steps} Adam steps "
+                    f"(lr {F['lr']:g}, loss {1 - F['beta']:g} log E[w^2] + {F['beta']:g} KL)",
+        "plain": {"A": plain.amp, "err": plain.err, "relvar": plain.relvar, "ess_frac": plain.ess / plain.n,
+                  "paths_per_s": plain_rate, "samples": plain.n},
+        "proposal_untrained": {"relvar": untrained.relvar},
+        "proposal": {"A": trained.amp, "err": trained.err, "relvar": trained.relvar,
+                     "ess_frac": trained.ess / trained.n, "paths_per_s": flow_rate, "samples": trained.n,
+                     "train_ms": train_ms, "train_paths": steps * F["batch"], "loss_first": float(losses[0]),
+                     "loss_last": float(losses[-1])},
+        "agreement_sigma": abs(trained.amp - plain.amp) / math.hypot(trained.err, plain.err),
+        "time_to_rel_err_1e-5_s": {"plain": t_plain, "proposal_estimation": t_flow,
+                                   "proposal_with_training": t_flow + train_ms / 1e3},
+        "relvar_ratio": plain.relvar / trained.relvar,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,6 +184,10 @@ def main():
     ap.add_argument("--batch-samples", type=int, default=10_000,
                     help="samples per task of the batched 128x128 grid (0 skips it)")
     ap.add_argument("--copy-probe", action="store_true", help="only run the 512 MiB copy used to scale HBM counters")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="run only the timed p=18 sweep (for profiler runs): no other section, no cpu baseline")
+    ap.add_argument("--flow-steps", type=int, default=FLOW["steps"],
+                    help="training steps of the learned proposal (0 skips the proposal section)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
@@ -150,8 +198,9 @@ def main():
         sys.exit(2)
 
     # The oracle runs first, in worker processes forked before this process touches the GPU.
-    cpu = None if args.no_cpu_baseline else cpu_baseline(CPU_SAMPLE_PATHS)
-    prec_ref = None if args.no_cpu_baseline else oracle_precision_reference()
+    skip_cpu = args.no_cpu_baseline or args.only_headline
+    cpu = None if skip_cpu else cpu_baseline(CPU_SAMPLE_PATHS)
+    prec_ref = None if skip_cpu else oracle_precision_reference()
 
     import paper_1105_0542_amd as P
 
@@ -187,6 +236,13 @@ def main():
     kernel_avg_s = kernel_ms / launches / 1e3
     flop_per_launch = args.samples * slices_per_sample(S_DEPTH, True) * FLOP_PER_SLICE
     achieved = flop_per_launch / kernel_avg_s / 1e12
+
+    if args.only_headline:
+        print(json.dumps({"metric": "slice-evals/s (p=18, FP64)", "value": value, "unit": "slice-evals/s",
+                          "kernel_avg_ms": kernel_avg_s * 1e3, "steps": args.steps, "warmup": args.warmup,
+                          "samples_per_point": args.samples, "note": "headline sweep only"}), flush=True)
+        ctx.close()
+        return
 
     # level-s only (no hierarchy): one point, same kernel family, for the second figure
     res_s, _ = ctx.amplitude(P.quartic(1.0, 10.0), 1.0, 0.0, 1.0, 1.0, N, P_LEVEL, args.samples, 1, 100, 0)
@@ -247,6 +303,8 @@ def main():
         }
         bt.close()
 
+    flow_line = proposal_section(P, ctx, args.flow_steps) if args.flow_steps > 0 else None
+
     line = {
         "metric": "slice-evals/s (p=18, FP64)",
         "value": value,
@@ -283,6 +341,8 @@ def main():
     line["precision"] = prec_line
     if batch_line is not None:
         line["batched"] = batch_line
+    if flow_line is not None:
+        line["proposal"] = flow_line
     if cpu is not None:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
