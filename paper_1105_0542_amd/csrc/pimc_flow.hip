@@ -15,6 +15,7 @@
 namespace pimc {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kLdK = kFlowK + 8;      // LDS row strides (elements), multiples of 8 (16 B)
@@ -518,6 +519,219 @@ __global__ void k_params_to_bf16(const float* __restrict__ theta, int layers, __
 
 __global__ void k_step_inc(int* step) { *step += 1; }
 
+// ------------------------------------------------------------------------------------ fused estimation
+// One workgroup carries 64 paths through the whole proposal: base normals (Philox, in LDS as FP64
+// [node][path]), every coupling, the bisection and the level-s action, and writes log w (and,
+// when asked, log det and z) per path. Only 8 bytes per path reach HBM.
+//
+// The products are oriented weights x activations: wave w computes hidden rows 32w..32w+31 and
+// output rows {16w..16w+15} (s_hat) and {64+16w..64+16w+15} (t) for all 64 paths, so each wave
+// reads a quarter of the weights and the workgroup reads each weight once per tile; the
+// activations are shared through LDS. In the output layout a lane holds s_hat and t of the same
+// (coordinate, path) in the same register slot.
+constexpr int kFusedPaths = 64;
+constexpr int kFusedMaxD = 127;
+constexpr int kLdXa = kFlowK + 8;                 // x_A tile [path][in], padded rows
+
+// Hidden tile [path][hidden] without padding: 16-byte chunk c of row P is stored at chunk
+// c ^ (P & 15), so the 16 rows read by one operand fetch fall in 16 different bank groups.
+__device__ __forceinline__ int hs_index(int P, int c) { return P * kFlowH + ((((c >> 3) ^ (P & 15)) << 3) | (c & 7)); }
+
+__device__ __forceinline__ int node_of_position(int pos, int s) {
+    const int tz = __builtin_ctz(pos);             // pos = (2i+1) 2^tz: level n = s - tz, offset i
+    return (1 << (s - tz - 1)) + (pos >> (tz + 1));
+}
+
+__global__ void __launch_bounds__(kBlock, 2)
+k_flow_fused(FlowNet net, RngKey key, uint64_t first_path, uint64_t n, int s, const double* __restrict__ tab,
+             const int* __restrict__ deg, int K, int even, const double* __restrict__ sig, double shift, double a,
+             double b, double* __restrict__ ell_out, double* __restrict__ logdet_out, double* __restrict__ z_out,
+             uint64_t zld) {
+    __shared__ double X[kFusedMaxD * kFusedPaths];                              // [h-1][P]
+    __shared__ __attribute__((aligned(16))) __bf16 act[kFusedPaths * kFlowH];   // x_A or hidden tile; sums at the end
+    const int t = threadIdx.x;
+    const int l = t & 63;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int P = t & 63;                           // path of this thread in the scalar phases
+    const int N = 1 << s, D = N - 1;
+    const uint64_t local = uint64_t(blockIdx.x) * kFusedPaths + uint64_t(P);
+    const bool valid = local < n;
+    // ---- base normals: group w takes node pairs j = w, w+4, ...; |u|^2 in that order
+    double u2 = 0.0;
+    {
+        const PathRng pr = path_rng(key, first_path + local);
+        for (int j = w; 2 * j <= D; j += 4) {
+            double ze, zo;
+            normal_pair(key, pr, uint32_t(j), ze, zo);
+            if (j > 0) {
+                X[(2 * j - 1) * kFusedPaths + P] = ze;
+                u2 += ze * ze;
+            }
+            if (2 * j + 1 <= D) {
+                X[(2 * j) * kFusedPaths + P] = zo;
+                u2 += zo * zo;
+            }
+        }
+    }
+    double ldet[4] = {0.0, 0.0, 0.0, 0.0};        // this wave's share of log det, path 16nb + (l & 15)
+    for (int c = 0; c < net.n_layers; ++c) {
+        const FlowLayerDev& L = net.layer[c];
+        __syncthreads();                             // X complete, act free
+        {   // x_A tile: thread (P, inputs 16w..16w+15)
+            bf16x8 v0, v1;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int k0 = 16 * w + q, k1 = 16 * w + 8 + q;
+                v0[q] = (__bf16)(float)(k0 < L.dA ? X[L.Aidx[k0] * kFusedPaths + P] : 0.0);
+                v1[q] = (__bf16)(float)(k1 < L.dA ? X[L.Aidx[k1] * kFusedPaths + P] : 0.0);
+            }
+            *reinterpret_cast<bf16x8*>(act + P * kLdXa + 16 * w) = v0;
+            *reinterpret_cast<bf16x8*>(act + P * kLdXa + 16 * w + 8) = v1;
+        }
+        __syncthreads();
+        floatx4 acc[2][4];
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb)
+                acc[mb][nb] = mma16(L.W1 + (32 * w + 16 * mb) * kFlowK, kFlowK, act + 16 * nb * kLdXa, kLdXa, kFlowK,
+                                    floatx4{0.f, 0.f, 0.f, 0.f});
+        __syncthreads();                             // every wave has read x_A
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+            const int h0 = 32 * w + 16 * mb + 4 * (l >> 4);
+            float bias[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bias[j] = L.b1[h0 + j];
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb) {
+                const int Pn = 16 * nb + (l & 15);
+                bf16x4 hv;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) hv[j] = (__bf16)silu(acc[mb][nb][j] + bias[j]);
+                *reinterpret_cast<bf16x4*>(act + hs_index(Pn, h0)) = hv;
+            }
+        }
+        __syncthreads();
+        floatx4 os[4], ot[4];
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+            os[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            ot[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            const int Pn = 16 * nb + (l & 15);
+            for (int ks = 0; ks < kFlowH; ks += 32) {
+                const bf16x8 hb = *reinterpret_cast<const bf16x8*>(act + hs_index(Pn, ks + 8 * (l >> 4)));
+                const bf16x8 as = *reinterpret_cast<const bf16x8*>(L.W2 + (16 * w + (l & 15)) * kFlowH + ks + 8 * (l >> 4));
+                const bf16x8 at = *reinterpret_cast<const bf16x8*>(L.W2 + (64 + 16 * w + (l & 15)) * kFlowH + ks +
+                                                                  8 * (l >> 4));
+                os[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as, hb, os[nb], 0, 0, 0);
+                ot[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(at, hb, ot[nb], 0, 0, 0);
+            }
+        }
+        // affine update of coordinates k = 16w + 4(l>>4) + j, paths 16nb + (l & 15)
+        const int kb = 16 * w + 4 * (l >> 4);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = kb + j;
+            if (k < L.dB) {
+                const float bs = L.b2[k], bt = L.b2[64 + k];
+                const int row = L.Bidx[k] * kFusedPaths;
+#pragma unroll
+                for (int nb = 0; nb < 4; ++nb) {
+                    const float sv = 2.0f * tanhf(0.5f * (os[nb][j] + bs));
+                    const int Pn = 16 * nb + (l & 15);
+                    X[row + Pn] = X[row + Pn] * exp(double(sv)) + double(ot[nb][j] + bt);
+                    os[nb][j] = sv;
+                }
+            } else {
+#pragma unroll
+                for (int nb = 0; nb < 4; ++nb) os[nb][j] = 0.f;
+            }
+        }
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+            double v = double(os[nb][0]) + double(os[nb][1]) + double(os[nb][2]) + double(os[nb][3]);
+            v += __shfl_xor(v, 16, 64);
+            v += __shfl_xor(v, 32, 64);
+            ldet[nb] += v;
+        }
+    }
+    __syncthreads();
+    // ---- |z|^2 in the order of |u|^2, optional copy of z
+    double z2 = 0.0;
+    for (int j = w; 2 * j <= D; j += 4) {
+        if (j > 0) {
+            const double z = X[(2 * j - 1) * kFusedPaths + P];
+            z2 += z * z;
+            if (z_out && valid) z_out[uint64_t(2 * j - 1) * zld + local] = z;
+        }
+        if (2 * j + 1 <= D) {
+            const double z = X[(2 * j) * kFusedPaths + P];
+            z2 += z * z;
+            if (z_out && valid) z_out[uint64_t(2 * j) * zld + local] = z;
+        }
+    }
+    // ---- bisection in place, level by level: X[h-1] becomes the point of node h
+    for (int lev = 1; lev <= s; ++lev) {
+        const int step = 1 << (s - lev), cnt = 1 << (lev - 1);
+        for (int i = w; i < cnt; i += 4) {
+            const int h = cnt + i, pos = (2 * i + 1) * step;
+            const int pl = pos - step, pr = pos + step;
+            const double ql = pl == 0 ? a : X[(node_of_position(pl, s) - 1) * kFusedPaths + P];
+            const double qr = pr == N ? b : X[(node_of_position(pr, s) - 1) * kFusedPaths + P];
+            X[(h - 1) * kFusedPaths + P] = sig[lev] * X[(h - 1) * kFusedPaths + P] + 0.5 * (ql + qr);
+        }
+        __syncthreads();
+    }
+    // ---- level-s action: group w takes slices [w*per, (w+1)*per)
+    double S = 0.0;
+    {
+        const int per = (N + 3) / 4;
+        const int k0 = w * per, k1 = min(N, k0 + per);
+        const const_ptr<double> tb = as_const(tab);
+        const const_ptr<int> dg = as_const(deg);
+        double q0 = k0 == 0 ? a : (k0 < N ? X[(node_of_position(k0, s) - 1) * kFusedPaths + P] : b);
+        for (int k = k0; k < k1; ++k) {
+            const double q1 = (k + 1 == N) ? b : X[(node_of_position(k + 1, s) - 1) * kFusedPaths + P];
+            const double mid = 0.5 * (q0 + q1), dl = q1 - q0;
+            const double y = even ? mid * mid : mid, zz = dl * dl;
+            double acc = 0.0;
+            int off = 0;
+            double pw = 1.0;
+            for (int kk = 0; kk < K; ++kk) {
+                const int d = dg[kk];
+                double v = tb[off];
+                for (int e = 1; e <= d; ++e) v = fma(v, y, tb[off + e]);
+                off += d + 1;
+                acc = fma(pw, v, acc);
+                pw *= zz;
+            }
+            S += acc;
+            q0 = q1;
+        }
+    }
+    // ---- combine the four groups / waves in a fixed order
+    double* red = reinterpret_cast<double*>(act);   // [4][4][64]: u2, z2, S, log det
+    red[(0 * 4 + w) * kFusedPaths + P] = u2;
+    red[(1 * 4 + w) * kFusedPaths + P] = z2;
+    red[(2 * 4 + w) * kFusedPaths + P] = S;
+    if (l < 16) {
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) red[(3 * 4 + w) * kFusedPaths + 16 * nb + l] = ldet[nb];
+    }
+    __syncthreads();
+    if (t < kFusedPaths && valid) {
+        double sum[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double* r = red + q * 4 * kFusedPaths + P;
+            sum[q] = ((r[0] + r[kFusedPaths]) + r[2 * kFusedPaths]) + r[3 * kFusedPaths];
+        }
+        ell_out[local] = -(sum[2] - shift) - 0.5 * sum[1] + 0.5 * sum[0] + sum[3];
+        if (logdet_out) logdet_out[local] = sum[3];
+    }
+}
+
 // ------------------------------------------------------------------------------------ launchers
 static inline uint32_t blocks_for(uint64_t n) { return uint32_t((n + kBlock - 1) / kBlock); }
 
@@ -561,6 +775,18 @@ hipError_t launch_flow_partials(const double* ell, uint64_t ell_first_path, uint
                                 uint64_t n_chunks, uint32_t ppl, double* partials, hipStream_t st) {
     hipLaunchKernelGGL(k_flow_partials, dim3(uint32_t(n_chunks)), dim3(kBlock), 0, st, ell, ell_first_path, n_total,
                        first_chunk, ppl, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_flow_fused(const FlowNet& net, const RngKey& key, uint64_t first_path, uint64_t n, int s,
+                             const double* tab, const int* deg, int K, int even, const double* sig, double shift,
+                             double a, double b, double* ell, double* logdet, double* z, uint64_t zld,
+                             hipStream_t st) {
+    if (s < 1 || (1 << s) - 1 > kFusedMaxD || net.n_layers < 0 || net.n_layers > kFlowMaxLayers)
+        return hipErrorInvalidValue;
+    const uint32_t tiles = uint32_t((n + kFusedPaths - 1) / kFusedPaths);
+    hipLaunchKernelGGL(k_flow_fused, dim3(tiles), dim3(kBlock), 0, st, net, key, first_path, n, s, tab, deg, K, even,
+                       sig, shift, a, b, ell, logdet, z, zld);
     return hipGetLastError();
 }
 

@@ -35,6 +35,20 @@ struct FlowLayerDev {
     int dA, dB;
 };
 
+// Every layer of a proposal, passed by value (kernel arguments: scalar loads).
+struct FlowNet {
+    FlowLayerDev layer[kFlowMaxLayers];
+    int n_layers;
+};
+
+// Fused estimation: base normals, every coupling, the bisection and the level-s action in one
+// kernel per 64 paths (N <= 128). Writes log w per path to ell; log det and z ([h-1]*zld + path)
+// only when those pointers are not null.
+hipError_t launch_flow_fused(const FlowNet& net, const RngKey& key, uint64_t first_path, uint64_t n, int s,
+                             const double* tab, const int* deg, int K, int even, const double* sig, double shift,
+                             double a, double b, double* ell, double* logdet, double* z, uint64_t zld,
+                             hipStream_t st);
+
 // Base normals u (the plain sampler's, stream key.stream + *step when step is not null), |u|^2/2,
 // log det = 0.
 hipError_t launch_flow_base(const RngKey& key, const int* step, uint64_t first_path, uint64_t n, int D, double* X,

@@ -55,13 +55,12 @@ struct pimc_flow {
     double* d_loss = nullptr;            // loss history, indexed by the step counter
     double* d_gloss = nullptr;           // loss of pimc_flow_grad
     size_t loss_cap = 0;
-    // device: estimation buffers (ld = EB)
-    uint64_t EB = 0;
-    double* d_EX = nullptr;
-    double* d_Ehu2 = nullptr;
-    double* d_Elogdet = nullptr;
+    // device: estimation buffers (per path: log w, log det; z only for pimc_flow_log_weights)
+    uint64_t EB = 0, ZB = 0;
     double* d_Eell = nullptr;
-    double* d_Eq = nullptr;
+    double* d_Elogdet = nullptr;
+    double* d_EX = nullptr;              // [h-1][ZB]
+    FlowNet net{};
     // graph of one training step
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -203,47 +202,44 @@ void free_flow(pimc_flow* f) {
     destroy_graph(f);
     void* ptrs[] = {f->d_sig, f->d_tab, f->d_deg, f->d_mask, f->d_theta, f->d_m, f->d_v, f->d_grad, f->d_gpart,
                     f->d_W1, f->d_W2, f->d_W1T, f->d_W2T, f->d_step, f->d_X, f->d_G, f->d_hu2, f->d_logdet,
-                    f->d_ell, f->d_alpha, f->d_q, f->d_gq, f->d_loss, f->d_gloss, f->d_EX, f->d_Ehu2, f->d_Elogdet, f->d_Eell,
-                    f->d_Eq};
+                    f->d_ell, f->d_alpha, f->d_q, f->d_gq, f->d_loss, f->d_gloss, f->d_EX, f->d_Elogdet, f->d_Eell};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (f->e0) (void)hipEventDestroy(f->e0);
     if (f->e1) (void)hipEventDestroy(f->e1);
 }
 
-int ensure_estimation(pimc_flow* f, uint64_t eb) {
-    if (eb <= f->EB) return PIMC_OK;
+int ensure_estimation(pimc_flow* f, uint64_t eb, uint64_t zb) {
     pimc_ctx* c = f->ctx;
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    for (double** p : {&f->d_EX, &f->d_Ehu2, &f->d_Elogdet, &f->d_Eell, &f->d_Eq}) {
-        if (*p) (void)hipFree(*p);
-        *p = nullptr;
-    }
-    f->EB = 0;
-    const size_t N = size_t(1) << f->P.s;
     int st;
-    if ((st = dev_alloc(c, &f->d_EX, size_t(f->D) * eb))) return st;
-    if ((st = dev_alloc(c, &f->d_Ehu2, eb))) return st;
-    if ((st = dev_alloc(c, &f->d_Elogdet, eb))) return st;
-    if ((st = dev_alloc(c, &f->d_Eell, eb))) return st;
-    if ((st = dev_alloc(c, &f->d_Eq, (N + 1) * eb))) return st;
-    f->EB = eb;
+    if (eb > f->EB) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        for (double** p : {&f->d_Eell, &f->d_Elogdet}) {
+            if (*p) (void)hipFree(*p);
+            *p = nullptr;
+        }
+        f->EB = 0;
+        if ((st = dev_alloc(c, &f->d_Eell, eb))) return st;
+        if ((st = dev_alloc(c, &f->d_Elogdet, eb))) return st;
+        f->EB = eb;
+    }
+    if (zb > f->ZB) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        if (f->d_EX) (void)hipFree(f->d_EX);
+        f->d_EX = nullptr;
+        f->ZB = 0;
+        if ((st = dev_alloc(c, &f->d_EX, size_t(f->D) * zb))) return st;
+        f->ZB = zb;
+    }
     return PIMC_OK;
 }
 
-// Base samples, every coupling in place and the log weights of paths first..first+n-1 (n <= EB).
-hipError_t enqueue_log_weights(pimc_flow* f, const RngKey& key, uint64_t first, uint64_t n) {
+// Log weights (and log det, and z when want_z) of paths first..first+n-1 by the fused kernel.
+hipError_t enqueue_log_weights(pimc_flow* f, const RngKey& key, uint64_t first, uint64_t n, bool want_z) {
     const Problem& P = f->P;
-    hipStream_t st = f->ctx->stream;
-    const uint64_t ld = f->EB;
-    hipError_t e = launch_flow_base(key, nullptr, first, n, f->D, f->d_EX, ld, f->d_Ehu2, f->d_Elogdet, st);
-    for (int c = 0; c < f->L && e == hipSuccess; ++c)
-        e = launch_coupling_fwd(layer_dev(f, c), f->d_EX, f->d_EX, ld, n, f->d_Elogdet, 0, st);
-    if (e == hipSuccess)
-        e = launch_flow_action_grad(f->d_tab, f->d_deg, int(P.deg.size()), P.even ? 1 : 0, f->d_sig,
-                                    P.shift[size_t(P.s)], P.a, P.b, P.s, f->d_EX, ld, n, f->d_Ehu2, f->d_Elogdet,
-                                    f->d_Eell, nullptr, f->d_Eq, nullptr, st);
-    return e;
+    return launch_flow_fused(f->net, key, first, n, P.s, f->d_tab, f->d_deg, int(P.deg.size()), P.even ? 1 : 0,
+                             f->d_sig, P.shift[size_t(P.s)], P.a, P.b, f->d_Eell, f->d_Elogdet,
+                             want_z ? f->d_EX : nullptr, f->ZB, f->ctx->stream);
 }
 
 constexpr uint64_t kEstimationBatch = uint64_t(1) << 20;
@@ -348,6 +344,8 @@ int pimc_flow_create(pimc_ctx* c, const pimc_potential* V, double m, double a, d
         hipMemcpyAsync(f->d_theta, theta.data(), np * 4, hipMemcpyHostToDevice, s0) != hipSuccess)
         return fail(ctx_fail(c, PIMC_EDEVICE, "upload of the proposal's constants failed"));
     if ((st = reset_optimizer(f))) return fail(st);     // synchronizes: the host vectors may go
+    f->net.n_layers = f->L;
+    for (int l = 0; l < f->L; ++l) f->net.layer[l] = layer_dev(f, l);
     *out = f;
     return PIMC_OK;
 }
@@ -445,19 +443,20 @@ int pimc_flow_log_weights(pimc_flow* f, uint64_t seed, uint32_t stream, uint64_t
     if (k_paths == 0) return PIMC_OK;
     if (k_paths > (uint64_t(1) << 32)) return ctx_fail(c, PIMC_EINVAL, "request too large");
     HIP_TRY(c, hipSetDevice(c->device));
-    int st = ensure_estimation(f, std::min<uint64_t>(k_paths, kEstimationBatch));
+    const uint64_t eb = std::min<uint64_t>(k_paths, kEstimationBatch);
+    int st = ensure_estimation(f, eb, z ? eb : 0);
     if (st) return st;
     const RngKey key{uint32_t(seed), uint32_t(seed >> 32), stream};
     std::vector<double> zt;
-    for (uint64_t off = 0; off < k_paths; off += f->EB) {
-        const uint64_t n = std::min<uint64_t>(f->EB, k_paths - off);
-        HIP_TRY(c, enqueue_log_weights(f, key, first_path + off, n));
+    for (uint64_t off = 0; off < k_paths; off += eb) {
+        const uint64_t n = std::min<uint64_t>(eb, k_paths - off);
+        HIP_TRY(c, enqueue_log_weights(f, key, first_path + off, n, z != nullptr));
         if (ell) HIP_TRY(c, hipMemcpyAsync(ell + off, f->d_Eell, n * 8, hipMemcpyDeviceToHost, c->stream));
         if (logdet) HIP_TRY(c, hipMemcpyAsync(logdet + off, f->d_Elogdet, n * 8, hipMemcpyDeviceToHost, c->stream));
         if (z) {
             zt.resize(size_t(f->D) * n);
             for (int h = 0; h < f->D; ++h)
-                HIP_TRY(c, hipMemcpyAsync(zt.data() + size_t(h) * n, f->d_EX + size_t(h) * f->EB, n * 8,
+                HIP_TRY(c, hipMemcpyAsync(zt.data() + size_t(h) * n, f->d_EX + size_t(h) * f->ZB, n * 8,
                                           hipMemcpyDeviceToHost, c->stream));
         }
         HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -480,7 +479,7 @@ int pimc_flow_amplitude(pimc_flow* f, uint64_t n_samples, uint64_t seed, uint32_
     const uint64_t CH = uint64_t(kBlock) * ppl;
     const uint64_t n_chunks = (n_samples + CH - 1) / CH;
     const uint64_t eb = std::min<uint64_t>(n_chunks * CH, kEstimationBatch);   // a multiple of CH
-    int st = ensure_estimation(f, eb);
+    int st = ensure_estimation(f, eb, 0);
     if (st) return st;
     st = ensure(c, reinterpret_cast<void**>(&c->d_partials), &c->partial_bytes, size_t(n_chunks) * 4 * 8);
     if (st) return st;
@@ -495,7 +494,7 @@ int pimc_flow_amplitude(pimc_flow* f, uint64_t n_samples, uint64_t seed, uint32_
     HIP_TRY(c, hipEventRecord(f->e0, c->stream));
     for (uint64_t first = 0; first < n_samples; first += step) {
         const uint64_t n = std::min<uint64_t>(step, n_samples - first);
-        HIP_TRY(c, enqueue_log_weights(f, key, first, n));
+        HIP_TRY(c, enqueue_log_weights(f, key, first, n, false));
         HIP_TRY(c, launch_flow_partials(f->d_Eell, first, n_samples, first / CH, (n + CH - 1) / CH, ppl,
                                         c->d_partials, c->stream));
     }
