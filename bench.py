@@ -186,6 +186,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="only run the 512 MiB copy used to scale HBM counters")
     ap.add_argument("--only-headline", action="store_true",
                     help="run only the timed p=18 sweep (for profiler runs): no other section, no cpu baseline")
+    ap.add_argument("--only-proposal", action="store_true",
+                    help="run only the proposal section (for profiler runs): no other section, no cpu baseline")
     ap.add_argument("--flow-steps", type=int, default=FLOW["steps"],
                     help="training steps of the learned proposal (0 skips the proposal section)")
     args = ap.parse_args()
@@ -198,7 +200,7 @@ def main():
         sys.exit(2)
 
     # The oracle runs first, in worker processes forked before this process touches the GPU.
-    skip_cpu = args.no_cpu_baseline or args.only_headline
+    skip_cpu = args.no_cpu_baseline or args.only_headline or args.only_proposal
     cpu = None if skip_cpu else cpu_baseline(CPU_SAMPLE_PATHS)
     prec_ref = None if skip_cpu else oracle_precision_reference()
 
@@ -206,6 +208,10 @@ def main():
 
     ctx = P.Context(device=0)
     H = P.FLAG_HIERARCHY
+    if args.only_proposal:
+        print(json.dumps({"proposal": proposal_section(P, ctx, args.flow_steps)}), flush=True)
+        ctx.close()
+        return
     N = 1 << S_DEPTH
 
     def step():

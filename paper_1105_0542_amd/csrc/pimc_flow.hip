@@ -11,6 +11,7 @@
 
 #include "pimc_flow.hpp"
 #include "pimc_internal.hpp"
+#include "pimc_math.hpp"
 
 namespace pimc {
 
@@ -33,7 +34,38 @@ __device__ __forceinline__ floatx4 mma16(const __bf16* A, int lda, const __bf16*
     return c;
 }
 
-__device__ __forceinline__ float silu(float v) { return v / (1.0f + expf(-v)); }
+// Conditioner nonlinearities in FP32 from the hardware exp2 and reciprocal (about 1 ulp each; the
+// conditioner only has to be deterministic, its rounding never biases the estimator).
+__device__ __forceinline__ float sigmoid_fast(float v) { return __builtin_amdgcn_rcpf(1.0f + __expf(-v)); }
+__device__ __forceinline__ float silu(float v) { return v * sigmoid_fast(v); }
+// tanh x = 1 - 2 / (e^{2x} + 1); |x| clamped to 15, where tanh is 1 in FP32.
+__device__ __forceinline__ float tanh_fast(float x) {
+    x = fminf(fmaxf(x, -15.0f), 15.0f);
+    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(__expf(2.0f * x) + 1.0f);
+}
+// e^s in FP64 for |s| <= 2 (the affine log-scales): Cody-Waite reduction s = k ln2 + r with
+// |r| <= ln2/2 (k*kLn2Hi exact), e^r by its Taylor series to degree 13 (truncation < 5e-18), and
+// the exact scaling by 2^k. Error about 1 ulp.
+__device__ __forceinline__ double exp_logscale(double s) {
+    const double k = rint(s * 1.4426950408889634);
+    double r = fma(-k, kLn2Hi, s);
+    r = fma(-k, kLn2Lo, r);
+    double p = 1.0 / 6227020800.0;                                   // 1/13!
+    p = fma(p, r, 1.0 / 479001600.0);
+    p = fma(p, r, 1.0 / 39916800.0);
+    p = fma(p, r, 1.0 / 3628800.0);
+    p = fma(p, r, 1.0 / 362880.0);
+    p = fma(p, r, 1.0 / 40320.0);
+    p = fma(p, r, 1.0 / 5040.0);
+    p = fma(p, r, 1.0 / 720.0);
+    p = fma(p, r, 1.0 / 120.0);
+    p = fma(p, r, 1.0 / 24.0);
+    p = fma(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return ldexp(p, int(k));
+}
 
 // ------------------------------------------------------------------------------------ base normals
 // u = the plain sampler's bisection normals (node h of path first_path + i), |u|^2/2, log det = 0.
@@ -106,10 +138,10 @@ __global__ void __launch_bounds__(kBlock) k_coupling_fwd(FlowLayerDev L, const d
             if (k < L.dB) {
                 const float sh = acc[nb][j] + L.b2[k];
                 const float tt = acc[nb + 4][j] + L.b2[64 + k];
-                const float s = 2.0f * tanhf(0.5f * sh);
+                const float s = 2.0f * tanh_fast(0.5f * sh);
                 if (P < n) {
                     const uint64_t a = uint64_t(L.Bidx[k]) * ld + P;
-                    Xout[a] = Xin[a] * exp(double(s)) + double(tt);
+                    Xout[a] = Xin[a] * exp_logscale(double(s)) + double(tt);
                 }
                 lsum[j] += double(s);
             }
@@ -193,10 +225,10 @@ __global__ void __launch_bounds__(kBlock) k_coupling_bwd(FlowLayerDev L, const d
             float gsh = 0.f, gt = 0.f;
             if (k < L.dB && P < n) {
                 const float sh = acc[nb][j] + L.b2[k];
-                const float th = tanhf(0.5f * sh);
+                const float th = tanh_fast(0.5f * sh);
                 const float s = 2.0f * th;
                 const uint64_t a = uint64_t(L.Bidx[k]) * ld + P;
-                const double es = exp(double(s));
+                const double es = exp_logscale(double(s));
                 const double gy = G[a];
                 G[a] = gy * es;
                 const double gs = gy * Xin[a] * es + alpha[P];
@@ -223,7 +255,7 @@ __global__ void __launch_bounds__(kBlock) k_coupling_bwd(FlowLayerDev L, const d
         for (int j = 0; j < 4; ++j) {
             const int Pl = 16 * w + 4 * (l >> 4) + j, hid = 16 * nb + (l & 15);
             const float v = pre[nb][j];
-            const float sg = 1.0f / (1.0f + expf(-v));
+            const float sg = sigmoid_fast(v);
             const float g = (p0 + Pl < n) ? gh[j] * (sg * (1.0f + v * (1.0f - sg))) : 0.f;
             const __bf16 bg = (__bf16)g;
             gp[Pl * kLdH + hid] = bg;
@@ -295,79 +327,107 @@ __global__ void __launch_bounds__(kBlock) k_coupling_bwd(FlowLayerDev L, const d
 }
 
 // ------------------------------------------------------------------------------------ action and its gradient
-// One thread per path: the level-s path from the normals z, S = sum_k eps W_p with each slice as
-// sum_k dlt^(2k) P_k(v), v = mid^2 (even potential) or mid, dlt = q_{k+1} - q_k, the folded table
-// of the level (P_k highest power first, consecutive in k). Writes l = -(S - shift) - |z|^2/2 +
-// |u|^2/2 + log det; with G, also G = dl/dz = -dS/dz - z: dS/dq from the slice derivatives, then
-// the adjoint of the (linear) bisection map.
+// A workgroup takes 16 paths, 16 threads per path (thread (P = t & 15, g = t >> 4)). The points
+// of the level-s path (positions 0..N, Sec. 4.1 bisection with sigma_n^2 = T/2^(n+1)) are built
+// level by level in LDS; S = sum_k eps W_p with each slice as sum_k dlt^(2k) P_k(v), v = mid^2
+// (even potential) or mid, dlt = q_{k+1} - q_k, from the folded level table (P_k highest power
+// first, consecutive in k); dS/dq from the slice derivatives, then the adjoint of the (linear)
+// bisection map level by level from the finest. Writes l = -(S - shift) - |z|^2/2 + |u|^2/2 +
+// log det and G = dl/dz = -dS/dz - z.
+constexpr int kAgPaths = 16;
+constexpr int kAgMaxN = 128;
+
 __global__ void __launch_bounds__(kBlock) k_flow_action_grad(const double* __restrict__ tab, const int* __restrict__ deg,
                                                              int K, int even, const double* __restrict__ sig, double shift,
                                                              double a, double b, int s, const double* __restrict__ X,
                                                              uint64_t ld, uint64_t n, const double* __restrict__ hu2,
                                                              const double* __restrict__ logdet, double* __restrict__ ell,
-                                                             double* __restrict__ G, double* __restrict__ q,
-                                                             double* __restrict__ gq) {
-    const uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
-    if (i >= n) return;
+                                                             double* __restrict__ G) {
+    __shared__ double Q[(kAgMaxN + 1) * kAgPaths];      // points, then d S / d q, position-major
+    __shared__ double SA[kAgMaxN * kAgPaths];           // slice k: d/dq_k
+    __shared__ double SB[kAgMaxN * kAgPaths];           // slice k: d/dq_{k+1}
+    __shared__ double red[2][16][kAgPaths];
+    const int t = threadIdx.x, P = t & 15, g = t >> 4;
+    const uint64_t path = uint64_t(blockIdx.x) * kAgPaths + uint64_t(P);
+    const bool valid = path < n;
     const int N = 1 << s;
-    q[i] = a;
-    q[uint64_t(N) * n + i] = b;
-    double z2 = 0.0;
-    for (int lev = 1; lev <= s; ++lev) {
-        const int step = 1 << (s - lev);
-        for (int i2 = 0; i2 < (1 << (lev - 1)); ++i2) {
-            const int h = (1 << (lev - 1)) + i2;
-            const int j = (2 * i2 + 1) * step;
-            const double z = X[uint64_t(h - 1) * ld + i];
-            z2 += z * z;
-            q[uint64_t(j) * n + i] = sig[lev] * z + 0.5 * (q[uint64_t(j - step) * n + i] + q[uint64_t(j + step) * n + i]);
-        }
+    if (g == 0) {
+        Q[P] = a;
+        Q[N * kAgPaths + P] = b;
     }
-    const bool grad = G != nullptr;
-    if (grad)
-        for (int j = 0; j <= N; ++j) gq[uint64_t(j) * n + i] = 0.0;
-    double S = 0.0;
-    for (int k = 0; k < N; ++k) {
-        const double q0 = q[uint64_t(k) * n + i], q1 = q[uint64_t(k + 1) * n + i];
+    __syncthreads();
+    for (int lev = 1; lev <= s; ++lev) {
+        const int step = 1 << (s - lev), cnt = 1 << (lev - 1);
+        for (int i = g; i < cnt; i += 16) {
+            const int h = cnt + i, pos = (2 * i + 1) * step;
+            const double z = valid ? X[uint64_t(h - 1) * ld + path] : 0.0;
+            Q[pos * kAgPaths + P] = sig[lev] * z + 0.5 * (Q[(pos - step) * kAgPaths + P] + Q[(pos + step) * kAgPaths + P]);
+        }
+        __syncthreads();
+    }
+    const const_ptr<double> tb = as_const(tab);
+    const const_ptr<int> dg = as_const(deg);
+    double Sp = 0.0;
+    for (int k = g; k < N; k += 16) {
+        const double q0 = Q[k * kAgPaths + P], q1 = Q[(k + 1) * kAgPaths + P];
         const double mid = 0.5 * (q0 + q1), dl = q1 - q0;
         const double y = even ? mid * mid : mid, zz = dl * dl;
         double val = 0.0, dmid = 0.0, ddl = 0.0, pw = 1.0, pwm1 = 0.0;
         int off = 0;
         for (int kk = 0; kk < K; ++kk) {
-            const int d = deg[kk];
-            double P = tab[off], dP = 0.0;
+            const int d = dg[kk];
+            double Pv = tb[off], dP = 0.0;
             for (int e = 1; e <= d; ++e) {
-                dP = fma(dP, y, P);
-                P = fma(P, y, tab[off + e]);
+                dP = fma(dP, y, Pv);
+                Pv = fma(Pv, y, tb[off + e]);
             }
             off += d + 1;
-            val += pw * P;
+            val += pw * Pv;
             dmid += pw * dP;
-            ddl += double(kk) * pwm1 * P;
+            ddl += double(kk) * pwm1 * Pv;
             pwm1 = pw;
             pw *= zz;
         }
-        S += val;
-        if (grad) {
-            const double gmid = even ? 2.0 * mid * dmid : dmid;   // d/dmid of sum_k dlt^(2k) P_k(v)
-            const double gdl = 2.0 * dl * ddl;                    // d/ddlt of the same
-            gq[uint64_t(k) * n + i] += 0.5 * gmid - gdl;
-            gq[uint64_t(k + 1) * n + i] += 0.5 * gmid + gdl;
-        }
+        Sp += val;
+        const double gmid = even ? 2.0 * mid * dmid : dmid;   // d/dmid of sum_k dlt^(2k) P_k(v)
+        const double gdl = 2.0 * dl * ddl;                    // d/ddlt of the same
+        SA[k * kAgPaths + P] = 0.5 * gmid - gdl;
+        SB[k * kAgPaths + P] = 0.5 * gmid + gdl;
     }
-    for (int lev = s; grad && lev >= 1; --lev) {
-        const int step = 1 << (s - lev);
-        for (int i2 = 0; i2 < (1 << (lev - 1)); ++i2) {
-            const int h = (1 << (lev - 1)) + i2;
-            const int j = (2 * i2 + 1) * step;
-            const double g = gq[uint64_t(j) * n + i];
-            const double z = X[uint64_t(h - 1) * ld + i];
-            G[uint64_t(h - 1) * ld + i] = -sig[lev] * g - z;
-            gq[uint64_t(j - step) * n + i] += 0.5 * g;
-            gq[uint64_t(j + step) * n + i] += 0.5 * g;
+    __syncthreads();
+    for (int pos = 1 + g; pos < N; pos += 16) Q[pos * kAgPaths + P] = SA[pos * kAgPaths + P] + SB[(pos - 1) * kAgPaths + P];
+    __syncthreads();
+    double z2p = 0.0;
+    for (int lev = s; lev >= 1; --lev) {
+        const int step = 1 << (s - lev), cnt = 1 << (lev - 1);
+        for (int i = g; i < cnt; i += 16) {
+            const int h = cnt + i, pos = (2 * i + 1) * step;
+            if (valid) {
+                const double z = X[uint64_t(h - 1) * ld + path];
+                G[uint64_t(h - 1) * ld + path] = -sig[lev] * Q[pos * kAgPaths + P] - z;
+            }
         }
+        // the node points at this level depend on the two neighbouring coarser points
+        for (int p2 = 2 * step * (1 + g); p2 < N; p2 += 2 * step * 16)
+            Q[p2 * kAgPaths + P] = (Q[p2 * kAgPaths + P] + 0.5 * Q[(p2 + step) * kAgPaths + P]) +
+                                   0.5 * Q[(p2 - step) * kAgPaths + P];
+        __syncthreads();
     }
-    ell[i] = -(S - shift) - 0.5 * z2 + hu2[i] + logdet[i];
+    for (int h = 1 + g; h < N; h += 16) {
+        const double z = valid ? X[uint64_t(h - 1) * ld + path] : 0.0;
+        z2p += z * z;
+    }
+    red[0][g][P] = Sp;
+    red[1][g][P] = z2p;
+    __syncthreads();
+    if (g == 0 && valid) {
+        double S = 0.0, z2 = 0.0;
+        for (int q = 0; q < 16; ++q) {
+            S += red[0][q][P];
+            z2 += red[1][q][P];
+        }
+        ell[path] = -(S - shift) - 0.5 * z2 + hu2[path] + logdet[path];
+    }
 }
 
 // One workgroup per canonical chunk: lane t adds d = expm1(l) of paths c*CH + r*kBlock + t,
@@ -544,7 +604,7 @@ __device__ __forceinline__ int node_of_position(int pos, int s) {
 
 __global__ void __launch_bounds__(kBlock, 2)
 k_flow_fused(FlowNet net, RngKey key, uint64_t first_path, uint64_t n, int s, const double* __restrict__ tab,
-             const int* __restrict__ deg, int K, int even, const double* __restrict__ sig, double shift, double a,
+             const int* __restrict__ deg, int K, int stride, int even, const double* __restrict__ sig, double shift, double a,
              double b, double* __restrict__ ell_out, double* __restrict__ logdet_out, double* __restrict__ z_out,
              uint64_t zld) {
     __shared__ double X[kFusedMaxD * kFusedPaths];                              // [h-1][P]
@@ -638,9 +698,9 @@ k_flow_fused(FlowNet net, RngKey key, uint64_t first_path, uint64_t n, int s, co
                 const int row = L.Bidx[k] * kFusedPaths;
 #pragma unroll
                 for (int nb = 0; nb < 4; ++nb) {
-                    const float sv = 2.0f * tanhf(0.5f * (os[nb][j] + bs));
+                    const float sv = 2.0f * tanh_fast(0.5f * (os[nb][j] + bs));
                     const int Pn = 16 * nb + (l & 15);
-                    X[row + Pn] = X[row + Pn] * exp(double(sv)) + double(ot[nb][j] + bt);
+                    X[row + Pn] = X[row + Pn] * exp_logscale(double(sv)) + double(ot[nb][j] + bt);
                     os[nb][j] = sv;
                 }
             } else {
@@ -683,31 +743,35 @@ k_flow_fused(FlowNet net, RngKey key, uint64_t first_path, uint64_t n, int s, co
         }
         __syncthreads();
     }
-    // ---- level-s action: group w takes slices [w*per, (w+1)*per)
+    // ---- level-s action: group w takes slices [w*per, (w+1)*per), 8 per coefficient pass
     double S = 0.0;
     {
         const int per = (N + 3) / 4;
         const int k0 = w * per, k1 = min(N, k0 + per);
-        const const_ptr<double> tb = as_const(tab);
-        const const_ptr<int> dg = as_const(deg);
-        double q0 = k0 == 0 ? a : (k0 < N ? X[(node_of_position(k0, s) - 1) * kFusedPaths + P] : b);
-        for (int k = k0; k < k1; ++k) {
-            const double q1 = (k + 1 == N) ? b : X[(node_of_position(k + 1, s) - 1) * kFusedPaths + P];
-            const double mid = 0.5 * (q0 + q1), dl = q1 - q0;
-            const double y = even ? mid * mid : mid, zz = dl * dl;
-            double acc = 0.0;
-            int off = 0;
-            double pw = 1.0;
-            for (int kk = 0; kk < K; ++kk) {
-                const int d = dg[kk];
-                double v = tb[off];
-                for (int e = 1; e <= d; ++e) v = fma(v, y, tb[off + e]);
-                off += d + 1;
-                acc = fma(pw, v, acc);
-                pw *= zz;
+        auto point = [&](int pos) -> double {
+            return pos == 0 ? a : (pos >= N ? b : X[(node_of_position(pos, s) - 1) * kFusedPaths + P]);
+        };
+        if (per % 8 == 0) {
+            for (int k = k0; k < k1; k += 8) {
+                double qa[8], qb[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    qa[i] = point(k + i);
+                    qb[i] = point(k + i + 1);
+                }
+                if (even)
+                    GenericEval64<true>{tab, deg, K, stride}.eval<8>(0, qa, qb, S);
+                else
+                    GenericEval64<false>{tab, deg, K, stride}.eval<8>(0, qa, qb, S);
             }
-            S += acc;
-            q0 = q1;
+        } else {
+            for (int k = k0; k < k1; ++k) {
+                double qa[1] = {point(k)}, qb[1] = {point(k + 1)};
+                if (even)
+                    GenericEval64<true>{tab, deg, K, stride}.eval<1>(0, qa, qb, S);
+                else
+                    GenericEval64<false>{tab, deg, K, stride}.eval<1>(0, qa, qb, S);
+            }
         }
     }
     // ---- combine the four groups / waves in a fixed order
@@ -764,10 +828,11 @@ hipError_t launch_coupling_bwd(const FlowLayerDev& L, const double* Xin, double*
 
 hipError_t launch_flow_action_grad(const double* tab, const int* deg, int K, int even, const double* sig, double shift,
                                    double a, double b, int s, const double* X, uint64_t ld, uint64_t n,
-                                   const double* hu2, const double* logdet, double* ell, double* G, double* qscr,
-                                   double* gqscr, hipStream_t st) {
-    hipLaunchKernelGGL(k_flow_action_grad, dim3(blocks_for(n)), dim3(kBlock), 0, st, tab, deg, K, even, sig, shift, a,
-                       b, s, X, ld, n, hu2, logdet, ell, G, qscr, gqscr);
+                                   const double* hu2, const double* logdet, double* ell, double* G, hipStream_t st) {
+    if (s < 1 || (1 << s) > kAgMaxN || !G) return hipErrorInvalidValue;
+    const uint32_t blocks = uint32_t((n + kAgPaths - 1) / kAgPaths);
+    hipLaunchKernelGGL(k_flow_action_grad, dim3(blocks), dim3(kBlock), 0, st, tab, deg, K, even, sig, shift, a, b, s,
+                       X, ld, n, hu2, logdet, ell, G);
     return hipGetLastError();
 }
 
@@ -779,14 +844,14 @@ hipError_t launch_flow_partials(const double* ell, uint64_t ell_first_path, uint
 }
 
 hipError_t launch_flow_fused(const FlowNet& net, const RngKey& key, uint64_t first_path, uint64_t n, int s,
-                             const double* tab, const int* deg, int K, int even, const double* sig, double shift,
+                             const double* tab, const int* deg, int K, int stride, int even, const double* sig, double shift,
                              double a, double b, double* ell, double* logdet, double* z, uint64_t zld,
                              hipStream_t st) {
     if (s < 1 || (1 << s) - 1 > kFusedMaxD || net.n_layers < 0 || net.n_layers > kFlowMaxLayers)
         return hipErrorInvalidValue;
     const uint32_t tiles = uint32_t((n + kFusedPaths - 1) / kFusedPaths);
-    hipLaunchKernelGGL(k_flow_fused, dim3(tiles), dim3(kBlock), 0, st, net, key, first_path, n, s, tab, deg, K, even,
-                       sig, shift, a, b, ell, logdet, z, zld);
+    hipLaunchKernelGGL(k_flow_fused, dim3(tiles), dim3(kBlock), 0, st, net, key, first_path, n, s, tab, deg, K, stride,
+                       even, sig, shift, a, b, ell, logdet, z, zld);
     return hipGetLastError();
 }
 

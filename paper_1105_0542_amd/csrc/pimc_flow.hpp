@@ -45,7 +45,7 @@ struct FlowNet {
 // kernel per 64 paths (N <= 128). Writes log w per path to ell; log det and z ([h-1]*zld + path)
 // only when those pointers are not null.
 hipError_t launch_flow_fused(const FlowNet& net, const RngKey& key, uint64_t first_path, uint64_t n, int s,
-                             const double* tab, const int* deg, int K, int even, const double* sig, double shift,
+                             const double* tab, const int* deg, int K, int stride, int even, const double* sig, double shift,
                              double a, double b, double* ell, double* logdet, double* z, uint64_t zld,
                              hipStream_t st);
 
@@ -58,12 +58,10 @@ hipError_t launch_coupling_fwd(const FlowLayerDev& L, const double* Xin, double*
 hipError_t launch_coupling_bwd(const FlowLayerDev& L, const double* Xin, double* G, uint64_t ld, uint64_t n,
                                const double* alpha, float* gpart, uint64_t gpart_stride, int layer_off,
                                hipStream_t st);
-// Level-s action of the paths in X, log weights ell; with G not null also G = d ell / dz. qscr and
-// gqscr: device scratch of (N+1) * n doubles each (gqscr unused without G).
+// Level-s action of the paths in X (N <= 128), log weights ell and G = d ell / dz.
 hipError_t launch_flow_action_grad(const double* tab, const int* deg, int K, int even, const double* sig, double shift,
                                    double a, double b, int s, const double* X, uint64_t ld, uint64_t n,
-                                   const double* hu2, const double* logdet, double* ell, double* G, double* qscr,
-                                   double* gqscr, hipStream_t st);
+                                   const double* hu2, const double* logdet, double* ell, double* G, hipStream_t st);
 // Canonical chunk sums (n, sum d, sum d^2, non-finite count), d = expm1(ell), of chunks
 // first_chunk .. first_chunk + n_chunks - 1 of ell (chunk = kBlock * ppl paths, the last one may be
 // short: n_total paths in all) into partials[chunk][4].

@@ -50,8 +50,6 @@ struct pimc_flow {
     double* d_logdet = nullptr;
     double* d_ell = nullptr;
     double* d_alpha = nullptr;
-    double* d_q = nullptr;               // (N+1) * B
-    double* d_gq = nullptr;
     double* d_loss = nullptr;            // loss history, indexed by the step counter
     double* d_gloss = nullptr;           // loss of pimc_flow_grad
     size_t loss_cap = 0;
@@ -142,7 +140,7 @@ hipError_t enqueue_grad(pimc_flow* f, const RngKey& key, const int* step, double
     if (e == hipSuccess)
         e = launch_flow_action_grad(f->d_tab, f->d_deg, int(P.deg.size()), P.even ? 1 : 0, f->d_sig,
                                     P.shift[size_t(P.s)], P.a, P.b, P.s, f->d_X + size_t(f->L) * plane, B, B,
-                                    f->d_hu2, f->d_logdet, f->d_ell, f->d_G, f->d_q, f->d_gq, st);
+                                    f->d_hu2, f->d_logdet, f->d_ell, f->d_G, st);
     if (e == hipSuccess) e = launch_flow_alpha(f->d_ell, B, f->beta, f->d_alpha, loss, step, st);
     if (e == hipSuccess) e = launch_flow_seed(f->d_G, f->d_alpha, f->D, B, B, st);
     const uint64_t stride = uint64_t(f->L) * kFlowNP;
@@ -202,7 +200,7 @@ void free_flow(pimc_flow* f) {
     destroy_graph(f);
     void* ptrs[] = {f->d_sig, f->d_tab, f->d_deg, f->d_mask, f->d_theta, f->d_m, f->d_v, f->d_grad, f->d_gpart,
                     f->d_W1, f->d_W2, f->d_W1T, f->d_W2T, f->d_step, f->d_X, f->d_G, f->d_hu2, f->d_logdet,
-                    f->d_ell, f->d_alpha, f->d_q, f->d_gq, f->d_loss, f->d_gloss, f->d_EX, f->d_Elogdet, f->d_Eell};
+                    f->d_ell, f->d_alpha, f->d_loss, f->d_gloss, f->d_EX, f->d_Elogdet, f->d_Eell};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (f->e0) (void)hipEventDestroy(f->e0);
@@ -237,7 +235,7 @@ int ensure_estimation(pimc_flow* f, uint64_t eb, uint64_t zb) {
 // Log weights (and log det, and z when want_z) of paths first..first+n-1 by the fused kernel.
 hipError_t enqueue_log_weights(pimc_flow* f, const RngKey& key, uint64_t first, uint64_t n, bool want_z) {
     const Problem& P = f->P;
-    return launch_flow_fused(f->net, key, first, n, P.s, f->d_tab, f->d_deg, int(P.deg.size()), P.even ? 1 : 0,
+    return launch_flow_fused(f->net, key, first, n, P.s, f->d_tab, f->d_deg, int(P.deg.size()), P.stride, P.even ? 1 : 0,
                              f->d_sig, P.shift[size_t(P.s)], P.a, P.b, f->d_Eell, f->d_Elogdet,
                              want_z ? f->d_EX : nullptr, f->ZB, f->ctx->stream);
 }
@@ -308,8 +306,6 @@ int pimc_flow_create(pimc_ctx* c, const pimc_potential* V, double m, double a, d
     if ((st = dev_alloc(c, &f->d_logdet, Bs))) return fail(st);
     if ((st = dev_alloc(c, &f->d_ell, Bs))) return fail(st);
     if ((st = dev_alloc(c, &f->d_alpha, Bs))) return fail(st);
-    if ((st = dev_alloc(c, &f->d_q, size_t(N + 1) * Bs))) return fail(st);
-    if ((st = dev_alloc(c, &f->d_gq, size_t(N + 1) * Bs))) return fail(st);
     f->loss_cap = 1 << 16;
     if ((st = dev_alloc(c, &f->d_loss, f->loss_cap))) return fail(st);
     if ((st = dev_alloc(c, &f->d_gloss, 1))) return fail(st);
