@@ -39,7 +39,8 @@ PREC = dict(g=10.0, p=18, s=9, T=1.0, samples=1_000_000_000, oracle_paths=20_000
 # Learned proposal: the anharmonic oscillator g = 10 at p = 12, N = 128, T = 2, a = 0, b = 1; 8 couplings,
 # batches of 4096 fresh base paths, 2442 Adam steps (1e7 training paths), loss 0.1 log E[w^2] + 0.9 KL.
 FLOW = dict(g=10.0, p=12, s=7, T=2.0, layers=8, batch=4096, lr=1e-3, beta=0.9, steps=2442,
-            est_samples=1 << 24, plain_samples=1 << 26, target=1e-5)
+            est_samples=1 << 24, plain_samples=1 << 26, target=1e-5,
+            wide_batch=16384)   # same 1e7 training paths in 610 steps: fills the 256 CUs
 KERNEL_SOURCES = ["pimc_device.hpp", "pimc_kernels.hip", "pimc_internal.hpp", "pimc_tables.hpp", "pimc_math.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_amplitude_quartic64_p18_s10.json")
 
@@ -133,10 +134,23 @@ def cpu_baseline(paths_per_point: int):
                       f"{dt:.1f} s wall"}
 
 
+def _train_and_estimate(P, ctx, coefs, N, batch, steps, est_stream):
+    F = FLOW
+    f = P.Flow(ctx, coefs, 1.0, 0.0, 1.0, F["T"], N, F["p"], layers=F["layers"], batch=batch, lr=F["lr"],
+               beta=F["beta"])
+    untrained, _, _ = f.amplitude(F["est_samples"], 1, est_stream)
+    losses, train_ms = f.train(1, 1 << 31, steps)
+    f.amplitude(1 << 20, 1, est_stream)                      # warm
+    trained, est_ms, _ = f.amplitude(F["est_samples"], 1, est_stream)
+    f.close()
+    return untrained, trained, losses, train_ms, F["est_samples"] / (est_ms / 1e3)
+
+
 def proposal_section(P, ctx, steps):
     """Plain bisection sampler against the trained affine-coupling proposal on one problem: weight
     variance, effective sample size, estimation rate, training time, and the device time to reach
-    a relative error of 1e-5 (samples needed = relvar / 1e-10)."""
+    a relative error of 1e-5 (samples needed = relvar / 1e-10). Two training shapes over the same
+    number of training paths: batches of 4096, and batches of 16384 (fewer, wider steps)."""
     F = FLOW
     coefs = P.quartic(1.0, F["g"])
     N = 1 << F["s"]
@@ -144,33 +158,30 @@ def proposal_section(P, ctx, steps):
     res, _ = ctx.amplitude(coefs, 1.0, 0.0, 1.0, F["T"], N, F["p"], F["plain_samples"], 1, est_stream, 0)
     plain = res[F["s"]]
     plain_rate = F["plain_samples"] / (ctx.last_kernel_ms() / 1e3)
-    f = P.Flow(ctx, coefs, 1.0, 0.0, 1.0, F["T"], N, F["p"], layers=F["layers"], batch=F["batch"], lr=F["lr"],
-               beta=F["beta"])
-    untrained, _, _ = f.amplitude(F["est_samples"], 1, est_stream)
-    losses, train_ms = f.train(1, 1 << 31, steps)
-    f.amplitude(1 << 20, 1, est_stream)                      # warm
-    trained, est_ms, _ = f.amplitude(F["est_samples"], 1, est_stream)
-    flow_rate = F["est_samples"] / (est_ms / 1e3)
     tgt2 = F["target"] ** 2
     t_plain = plain.relvar / tgt2 / plain_rate
-    t_flow = trained.relvar / tgt2 / flow_rate
-    f.close()
-    return {
+    out = {
         "workload": f"V=q^2/2+{F['g']:g} q^4/24, p={F['p']}, N={N}, T={F['T']:g}, a=0, b=1; {F['layers']} affine "
-                    f"couplings (bf16 MFMA MLPs 64-128-128), batch {F['batch']}, {steps} Adam steps "
-                    f"(lr {F['lr']:g}, loss {1 - F['beta']:g} log E[w^2] + {F['beta']:g} KL)",
+                    f"couplings (bf16 MFMA MLPs 64-128-128), Adam lr {F['lr']:g}, loss {1 - F['beta']:g} log E[w^2] + "
+                    f"{F['beta']:g} KL, {steps * F['batch']:.3g} training paths",
         "plain": {"A": plain.amp, "err": plain.err, "relvar": plain.relvar, "ess_frac": plain.ess / plain.n,
-                  "paths_per_s": plain_rate, "samples": plain.n},
-        "proposal_untrained": {"relvar": untrained.relvar},
-        "proposal": {"A": trained.amp, "err": trained.err, "relvar": trained.relvar,
-                     "ess_frac": trained.ess / trained.n, "paths_per_s": flow_rate, "samples": trained.n,
-                     "train_ms": train_ms, "train_paths": steps * F["batch"], "loss_first": float(losses[0]),
-                     "loss_last": float(losses[-1])},
-        "agreement_sigma": abs(trained.amp - plain.amp) / math.hypot(trained.err, plain.err),
-        "time_to_rel_err_1e-5_s": {"plain": t_plain, "proposal_estimation": t_flow,
-                                   "proposal_with_training": t_flow + train_ms / 1e3},
-        "relvar_ratio": plain.relvar / trained.relvar,
+                  "paths_per_s": plain_rate, "samples": plain.n, "time_to_rel_err_1e-5_s": t_plain},
     }
+    for key, batch in (("proposal", F["batch"]), ("proposal_wide_batch", F["wide_batch"])):
+        nsteps = max(1, steps * F["batch"] // batch)
+        untrained, trained, losses, train_ms, rate = _train_and_estimate(P, ctx, coefs, N, batch, nsteps, est_stream)
+        t_est = trained.relvar / tgt2 / rate
+        out[key] = {
+            "batch": batch, "steps": nsteps, "train_ms": train_ms, "train_paths": nsteps * batch,
+            "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
+            "relvar_untrained": untrained.relvar,
+            "A": trained.amp, "err": trained.err, "relvar": trained.relvar, "ess_frac": trained.ess / trained.n,
+            "paths_per_s": rate, "samples": trained.n,
+            "agreement_sigma": abs(trained.amp - plain.amp) / math.hypot(trained.err, plain.err),
+            "relvar_ratio": plain.relvar / trained.relvar,
+            "time_to_rel_err_1e-5_s": {"estimation": t_est, "with_training": t_est + train_ms / 1e3},
+        }
+    return out
 
 
 def main():

@@ -236,6 +236,12 @@ int pimc_flow_destroy(pimc_flow *flow);
 int pimc_flow_get_params(pimc_flow *flow, float *out, size_t cap, size_t *n_out);
 int pimc_flow_set_params(pimc_flow *flow, const float *in, size_t n);
 
+/* Write the parameters to a file (8-byte tag, layer count, N, p, parameters per layer, FP32 values)
+ * or read them back into a proposal with the same layer count and N (then as pimc_flow_set_params).
+ * EINVAL when the file cannot be opened, is not such a file, or has another shape. */
+int pimc_flow_save(pimc_flow *flow, const char *path);
+int pimc_flow_load(pimc_flow *flow, const char *path);
+
 /* Loss and gradient of one batch without updating: base normals of paths 0..batch-1 on Philox
  * stream `stream` with the context seed convention (seed, stream) of pimc_normals. loss: host
  * double; ell: host [batch] log weights (may be NULL); grad: host [layers * PIMC_FLOW_NPARAM]

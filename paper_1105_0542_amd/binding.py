@@ -146,6 +146,10 @@ def load_library():
     lib.pimc_flow_get_params.argtypes = [vp, P(C.c_float), C.c_size_t, P(C.c_size_t)]
     lib.pimc_flow_set_params.restype = C.c_int
     lib.pimc_flow_set_params.argtypes = [vp, P(C.c_float), C.c_size_t]
+    lib.pimc_flow_save.restype = C.c_int
+    lib.pimc_flow_save.argtypes = [vp, C.c_char_p]
+    lib.pimc_flow_load.restype = C.c_int
+    lib.pimc_flow_load.argtypes = [vp, C.c_char_p]
     lib.pimc_flow_grad.restype = C.c_int
     lib.pimc_flow_grad.argtypes = [vp, C.c_uint64, C.c_uint32, P(C.c_double), P(C.c_double), P(C.c_float)]
     lib.pimc_flow_train.restype = C.c_int
@@ -404,6 +408,12 @@ class Flow:
     def set_params(self, theta):
         th = np.ascontiguousarray(np.asarray(theta, dtype=np.float32).reshape(-1))
         self._check(self.lib.pimc_flow_set_params(self.h, th.ctypes.data_as(C.POINTER(C.c_float)), th.size))
+
+    def save(self, path):
+        self._check(self.lib.pimc_flow_save(self.h, os.fsencode(path)))
+
+    def load(self, path):
+        self._check(self.lib.pimc_flow_load(self.h, os.fsencode(path)))
 
     def grad(self, seed, stream):
         """(loss, ell [batch], grad [layers, FLOW_NPARAM] FP32) of one batch, no update."""

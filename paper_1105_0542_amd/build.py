@@ -14,6 +14,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpimc.so")
+CLI = os.path.join(PKG, "pimc")
 
 SOURCES = ["pimc_host.cpp", "pimc_flow_host.cpp", "pimc_kernels.hip", "pimc_flow.hip"]
 HEADERS = ["pimc_tables.hpp", "pimc_device.hpp", "pimc_internal.hpp", "pimc_math.hpp", "pimc_flow.hpp",
@@ -67,8 +68,14 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    # the command-line front end: plain C++ against the C ABI, finds libpimc.so next to itself
+    cli_tmp = CLI + ".tmp"
+    cmd = ["g++", "-O2", "-std=c++17", "-Wall", "-I", os.path.join(ROOT, "include"), os.path.join(CSRC, "pimc_cli.cpp"),
+           "-o", cli_tmp, "-L", PKG, "-lpimc", "-Wl,-rpath,$ORIGIN", "-Wl,-rpath-link,/opt/rocm/lib"]
+    subprocess.run(cmd, check=True)
+    os.replace(cli_tmp, CLI)
     if verbose:
-        print(f"built {LIB} in {time.time() - t0:.1f}s", flush=True)
+        print(f"built {LIB} and {CLI} in {time.time() - t0:.1f}s", flush=True)
     return LIB
 
 

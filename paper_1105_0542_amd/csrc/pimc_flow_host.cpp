@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -377,6 +378,49 @@ int pimc_flow_set_params(pimc_flow* f, const float* in, size_t n) {
     HIP_TRY(c, hipSetDevice(c->device));
     HIP_TRY(c, hipMemcpyAsync(f->d_theta, in, np * 4, hipMemcpyHostToDevice, c->stream));
     return reset_optimizer(f);
+}
+
+// File: 8 bytes "PIMCFLW1", then int32 layers, N, p, parameters per layer, then the FP32 parameters
+// (host byte order).
+int pimc_flow_save(pimc_flow* f, const char* path) {
+    if (!f) { set_thread_error("flow is NULL"); return PIMC_EINVAL; }
+    pimc_ctx* c = f->ctx;
+    if (!path) return ctx_fail(c, PIMC_EINVAL, "path is NULL");
+    const size_t np = size_t(f->L) * kFlowNP;
+    std::vector<float> th(np);
+    int st = pimc_flow_get_params(f, th.data(), np, nullptr);
+    if (st) return st;
+    std::FILE* fp = std::fopen(path, "wb");
+    if (!fp) return ctx_fail(c, PIMC_EINVAL, "cannot open %s for writing", path);
+    const int32_t hdr[4] = {f->L, f->D + 1, f->P.p, kFlowNP};
+    bool ok = std::fwrite("PIMCFLW1", 1, 8, fp) == 8 && std::fwrite(hdr, sizeof(hdr), 1, fp) == 1 &&
+              std::fwrite(th.data(), sizeof(float), np, fp) == np;
+    ok = (std::fclose(fp) == 0) && ok;
+    if (!ok) return ctx_fail(c, PIMC_EINVAL, "write to %s failed", path);
+    return PIMC_OK;
+}
+
+int pimc_flow_load(pimc_flow* f, const char* path) {
+    if (!f) { set_thread_error("flow is NULL"); return PIMC_EINVAL; }
+    pimc_ctx* c = f->ctx;
+    if (!path) return ctx_fail(c, PIMC_EINVAL, "path is NULL");
+    std::FILE* fp = std::fopen(path, "rb");
+    if (!fp) return ctx_fail(c, PIMC_EINVAL, "cannot open %s", path);
+    char magic[8];
+    int32_t hdr[4];
+    const size_t np = size_t(f->L) * kFlowNP;
+    std::vector<float> th(np);
+    bool ok = std::fread(magic, 1, 8, fp) == 8 && std::memcmp(magic, "PIMCFLW1", 8) == 0 &&
+              std::fread(hdr, sizeof(hdr), 1, fp) == 1;
+    if (ok && (hdr[0] != f->L || hdr[1] != f->D + 1 || hdr[3] != kFlowNP)) {
+        std::fclose(fp);
+        return ctx_fail(c, PIMC_EINVAL, "%s holds %d layers for N = %d; this proposal has %d layers, N = %d", path,
+                        hdr[0], hdr[1], f->L, f->D + 1);
+    }
+    ok = ok && std::fread(th.data(), sizeof(float), np, fp) == np;
+    std::fclose(fp);
+    if (!ok) return ctx_fail(c, PIMC_EINVAL, "%s is not a proposal file", path);
+    return pimc_flow_set_params(f, th.data(), np);
 }
 
 int pimc_flow_grad(pimc_flow* f, uint64_t seed, uint32_t stream, double* loss, double* ell, float* grad) {

@@ -1,0 +1,34 @@
+"""The command-line front end (argument order of the paper's program) against the library call."""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_1105_0542_amd as P
+
+pytestmark = pytest.mark.gpu
+
+CLI = os.path.join(os.path.dirname(P.lib_path()), "pimc")
+
+
+def test_cli_prints_every_level_like_the_library():
+    assert os.path.exists(CLI), "build the package first"
+    args = ["-p", "8", "2.0", "0", "1", "5", "20000", "3", "0", "0", "0.5", "0", str(10 / 24)]
+    out = subprocess.run([CLI] + args, capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    rows = np.array([[float(v) for v in line.split()] for line in out.stdout.strip().splitlines()])
+    assert rows.shape == (6, 4)
+    assert list(rows[:, 0]) == [0, 1, 2, 3, 4, 5] and list(rows[:, 1]) == [1, 2, 4, 8, 16, 32]
+    assert rows[0, 3] == 0.0                         # level 0: analytic, error 0
+    with P.Context() as ctx:
+        res, _ = ctx.amplitude([0, 0, 0.5, 0, 10 / 24], 1.0, 0.0, 1.0, 2.0, 32, 8, 20000, 3, 0, P.FLAG_HIERARCHY)
+    for n in range(6):
+        assert rows[n, 2] == res[n].amp and rows[n, 3] == res[n].err
+
+
+def test_cli_help_and_errors():
+    out = subprocess.run([CLI], capture_output=True, text=True, timeout=60)
+    assert out.returncode == 0 and "usage" in out.stdout
+    bad = subprocess.run([CLI, "1", "0", "1", "4", "1"], capture_output=True, text=True, timeout=60)
+    assert bad.returncode == 2

@@ -245,3 +245,22 @@ def test_unsupported_and_invalid(ctx):
     with pytest.raises(P.PimcError):
         f.set_params(bad)
     f.close()
+
+
+def test_save_and_load_round_trip(ctx, tmp_path):
+    coefs, m, a, b, T, s, p = QUARTIC, 1.0, 0.0, 1.0, 2.0, 5, 10
+    f = P.Flow(ctx, coefs, m, a, b, T, 1 << s, p, layers=3, batch=64)
+    f.set_params(_random_params(3, 4))
+    path = str(tmp_path / "proposal.bin")
+    f.save(path)
+    g = P.Flow(ctx, coefs, m, a, b, T, 1 << s, p, layers=3, batch=64)
+    g.load(path)
+    assert np.array_equal(g.get_params(), f.get_params())
+    assert np.array_equal(g.log_weights(1, 2, 0, 500)[0], f.log_weights(1, 2, 0, 500)[0])
+    h = P.Flow(ctx, coefs, m, a, b, T, 1 << s, p, layers=4, batch=64)
+    with pytest.raises(P.PimcError):
+        h.load(path)                                   # another layer count
+    with pytest.raises(P.PimcError):
+        h.load(str(tmp_path / "missing.bin"))
+    for x in (f, g, h):
+        x.close()
