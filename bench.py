@@ -134,7 +134,9 @@ def cpu_baseline(paths_per_point: int):
                       f"{dt:.1f} s wall"}
 
 
-def _train_and_estimate(P, ctx, coefs, N, batch, steps, est_stream):
+def _train_and_estimate(P, ctx, coefs, N, batch, steps, est_stream, run_to_target):
+    """Train, measure relvar on est_samples, then (run_to_target) estimate again from the predicted
+    n* = relvar / target^2 samples on a fresh stream and time that run."""
     F = FLOW
     f = P.Flow(ctx, coefs, 1.0, 0.0, 1.0, F["T"], N, F["p"], layers=F["layers"], batch=batch, lr=F["lr"],
                beta=F["beta"])
@@ -142,15 +144,22 @@ def _train_and_estimate(P, ctx, coefs, N, batch, steps, est_stream):
     losses, train_ms = f.train(1, 1 << 31, steps)
     f.amplitude(1 << 20, 1, est_stream)                      # warm
     trained, est_ms, _ = f.amplitude(F["est_samples"], 1, est_stream)
+    final = None
+    if run_to_target:
+        n_star = int(math.ceil(trained.relvar / F["target"] ** 2))
+        r, ms, _ = f.amplitude(n_star, 1, est_stream + 1)
+        final = {"samples": n_star, "A": r.amp, "err": r.err, "rel_err": r.err / r.amp, "device_s": ms / 1e3}
     f.close()
-    return untrained, trained, losses, train_ms, F["est_samples"] / (est_ms / 1e3)
+    return untrained, trained, losses, train_ms, F["est_samples"] / (est_ms / 1e3), final
 
 
 def proposal_section(P, ctx, steps):
     """Plain bisection sampler against the trained affine-coupling proposal on one problem: weight
     variance, effective sample size, estimation rate, training time, and the device time to reach
-    a relative error of 1e-5 (samples needed = relvar / 1e-10). Two training shapes over the same
-    number of training paths: batches of 4096, and batches of 16384 (fewer, wider steps)."""
+    a relative error of 1e-5 (samples needed n* = relvar / 1e-10, predicted from the measured rate,
+    then run: the n*-sample estimate on a fresh stream, its achieved relative error and device
+    time). Two training shapes over the same number of training paths: batches of 4096, and
+    batches of 16384 (fewer, wider steps)."""
     F = FLOW
     coefs = P.quartic(1.0, F["g"])
     N = 1 << F["s"]
@@ -160,16 +169,23 @@ def proposal_section(P, ctx, steps):
     plain_rate = F["plain_samples"] / (ctx.last_kernel_ms() / 1e3)
     tgt2 = F["target"] ** 2
     t_plain = plain.relvar / tgt2 / plain_rate
+    # run the plain sampler to its predicted n* (level s only, fresh stream)
+    n_star = int(math.ceil(plain.relvar / tgt2))
+    res2, _ = ctx.amplitude(coefs, 1.0, 0.0, 1.0, F["T"], N, F["p"], n_star, 1, est_stream + 1, 0)
+    plain_final = {"samples": n_star, "A": res2[F["s"]].amp, "err": res2[F["s"]].err,
+                   "rel_err": res2[F["s"]].err / res2[F["s"]].amp, "device_s": ctx.last_kernel_ms() / 1e3}
     out = {
         "workload": f"V=q^2/2+{F['g']:g} q^4/24, p={F['p']}, N={N}, T={F['T']:g}, a=0, b=1; {F['layers']} affine "
                     f"couplings (bf16 MFMA MLPs 64-128-128), Adam lr {F['lr']:g}, loss {1 - F['beta']:g} log E[w^2] + "
                     f"{F['beta']:g} KL, {steps * F['batch']:.3g} training paths",
         "plain": {"A": plain.amp, "err": plain.err, "relvar": plain.relvar, "ess_frac": plain.ess / plain.n,
-                  "paths_per_s": plain_rate, "samples": plain.n, "time_to_rel_err_1e-5_s": t_plain},
+                  "paths_per_s": plain_rate, "samples": plain.n, "time_to_rel_err_1e-5_s": t_plain,
+                  "run_to_target": plain_final},
     }
     for key, batch in (("proposal", F["batch"]), ("proposal_wide_batch", F["wide_batch"])):
         nsteps = max(1, steps * F["batch"] // batch)
-        untrained, trained, losses, train_ms, rate = _train_and_estimate(P, ctx, coefs, N, batch, nsteps, est_stream)
+        untrained, trained, losses, train_ms, rate, final = _train_and_estimate(P, ctx, coefs, N, batch, nsteps,
+                                                                                est_stream, run_to_target=True)
         t_est = trained.relvar / tgt2 / rate
         out[key] = {
             "batch": batch, "steps": nsteps, "train_ms": train_ms, "train_paths": nsteps * batch,
@@ -180,6 +196,7 @@ def proposal_section(P, ctx, steps):
             "agreement_sigma": abs(trained.amp - plain.amp) / math.hypot(trained.err, plain.err),
             "relvar_ratio": plain.relvar / trained.relvar,
             "time_to_rel_err_1e-5_s": {"estimation": t_est, "with_training": t_est + train_ms / 1e3},
+            "run_to_target": final,
         }
     return out
 
