@@ -44,7 +44,8 @@ enum {
     PIMC_EUNSUPPORTED = -2,    /* valid request outside what the library implements                */
     PIMC_ENOMEM = -3,          /* host or device allocation failed                                 */
     PIMC_EDEVICE = -4,         /* a HIP call failed; text via pimc_last_error                       */
-    PIMC_WNONFINITE = 1        /* some weights were inf/nan; they are kept in the sums (never dropped) */
+    PIMC_WNONFINITE = 1,       /* some weights were inf/nan; they are kept in the sums (never dropped) */
+    PIMC_WNOTCONVERGED = 2     /* an iteration stopped at its limit before its tolerance; outputs written */
 };
 
 /* ---- flags ---------------------------------------------------------------------------------- */
@@ -266,6 +267,45 @@ int pimc_flow_log_weights(pimc_flow *flow, uint64_t seed, uint32_t stream, uint6
  * Returns PIMC_WNONFINITE if any weight was not finite. */
 int pimc_flow_amplitude(pimc_flow *flow, uint64_t n_samples, uint64_t seed, uint32_t stream,
                         pimc_level_result *out, double *ms);
+
+/* ---- spectrum from the space-discretized evolution operator ----------------------------------
+ *
+ * The paper's application of short-time amplitudes (Sec. 2; Sec. 5 with Fig. 3): on the grid
+ * x_i = -L + (i + 1/2) D, D = 2L/n (symmetric about 0), the matrix
+ *     M_ij = D A_1^(p)(x_i, x_j; t),  A_1^(p)(a,b;t) = sqrt(m) (2 pi t)^(-1/2)
+ *            exp(-m (b-a)^2/(2t) - t W~_p(sqrt(m)(a+b)/2, sqrt(m)(b-a)/2; t))
+ * with W~_p the level-p effective potential of V(y/sqrt(m)) (the mass rescaling above; the N = 1
+ * amplitude of Sec. 4.2 at T = t)
+ * approximates exp(-t H) on the grid; its largest eigenvalues are exp(-t E_n) and its eigenvectors
+ * sample the eigenfunctions. No Monte Carlo is involved (N = 1 at level p). */
+#define PIMC_MAX_P_SHORT_TIME 21   /* highest level p for the short-time matrix                       */
+#define PIMC_MAX_GRID 65536        /* n <= 65536                                                      */
+#define PIMC_MAX_STATES 256        /* eigenpairs per call                                             */
+#define PIMC_MAX_LANCZOS 4096      /* Lanczos steps per call                                          */
+
+typedef struct {
+    uint32_t iterations;       /* Lanczos steps taken                                               */
+    int converged;             /* 1 if every requested residual met the tolerance                   */
+    double max_residual;       /* max |M y - theta y| over the returned pairs, relative to theta_0  */
+    double matrix_ms;          /* device time of the matrix build                                   */
+    double solve_ms;           /* wall time of the eigenvalue iteration (device work + host checks) */
+} pimc_spectrum_info;
+
+/* Fill the n x n matrix M_ij above (row-major, leading dimension ld >= n) into DEVICE memory M
+ * owned by the caller. p in 1..PIMC_MAX_P_SHORT_TIME, 2 <= n <= PIMC_MAX_GRID, t > 0, L > 0.
+ * The matrix is exactly symmetric (every element depends on (x_i - x_j)^2 and x_i + x_j only). */
+int pimc_evolution_matrix(pimc_ctx *ctx, const pimc_potential *V, double m, double t, int p, double L,
+                          uint32_t n, double *M, uint64_t ld);
+
+/* Lowest k energies E_n = -ln(lambda_n)/t of that matrix (host array E[k], ascending) and, if psi
+ * is not NULL, the eigenfunctions on the grid (host psi[k][n], sum_i psi(x_i)^2 D = 1, the largest
+ * |psi| positive). Lanczos with full reorthogonalization on the device (the matrix, n x n doubles,
+ * and max_iter + 1 Lanczos vectors are allocated for the call), checked every 16 steps; stops when
+ * every requested pair has |M y - theta y| <= tol * theta_0 (returns PIMC_OK) or after max_iter
+ * steps (returns PIMC_WNOTCONVERGED with the best values). k in 1..min(n, PIMC_MAX_STATES),
+ * max_iter in k+1..min(n, PIMC_MAX_LANCZOS), 0 < tol < 1. info may be NULL. */
+int pimc_spectrum(pimc_ctx *ctx, const pimc_potential *V, double m, double t, int p, double L, uint32_t n,
+                  uint32_t k, uint32_t max_iter, double tol, double *E, double *psi, pimc_spectrum_info *info);
 
 /* Device time of the last estimation kernel on this context, in milliseconds (HIP events on the
  * context's stream around that launch). */

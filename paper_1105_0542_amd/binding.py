@@ -17,6 +17,7 @@ PIMC_EUNSUPPORTED = -2
 PIMC_ENOMEM = -3
 PIMC_EDEVICE = -4
 PIMC_WNONFINITE = 1
+PIMC_WNOTCONVERGED = 2
 
 FLAG_FP64 = 0
 FLAG_FP32_POLY = 1
@@ -50,6 +51,11 @@ class Task(C.Structure):
 class FlowConfig(C.Structure):
     _fields_ = [("layers", C.c_int), ("batch", C.c_uint32), ("lr", C.c_double), ("beta", C.c_double),
                 ("init_seed", C.c_uint64), ("init_scale", C.c_double)]
+
+
+class SpectrumInfo(C.Structure):
+    _fields_ = [("iterations", C.c_uint32), ("converged", C.c_int), ("max_residual", C.c_double),
+                ("matrix_ms", C.c_double), ("solve_ms", C.c_double)]
 
 
 class _LevelResult(C.Structure):
@@ -159,6 +165,12 @@ def load_library():
                                           P(C.c_double), P(C.c_double)]
     lib.pimc_flow_amplitude.restype = C.c_int
     lib.pimc_flow_amplitude.argtypes = [vp, C.c_uint64, C.c_uint64, C.c_uint32, P(_LevelResult), P(C.c_double)]
+    lib.pimc_evolution_matrix.restype = C.c_int
+    lib.pimc_evolution_matrix.argtypes = [vp, P(Potential), C.c_double, C.c_double, C.c_int, C.c_double, C.c_uint32,
+                                          vp, C.c_uint64]
+    lib.pimc_spectrum.restype = C.c_int
+    lib.pimc_spectrum.argtypes = [vp, P(Potential), C.c_double, C.c_double, C.c_int, C.c_double, C.c_uint32,
+                                  C.c_uint32, C.c_uint32, C.c_double, P(C.c_double), P(C.c_double), P(SpectrumInfo)]
     _lib = lib
     return lib
 
@@ -293,6 +305,27 @@ class Context:
         self._check(self.lib.pimc_normals(self.h, seed, stream, first_path, k_paths, n_nodes,
                                           out.ctypes.data_as(C.POINTER(C.c_double))))
         return out
+
+    def evolution_matrix(self, coefs, m, t, p, L, n, device_ptr, ld):
+        """pimc_evolution_matrix into caller-owned device memory (an address, e.g. a torch tensor's
+        data_ptr(), of at least n*ld doubles)."""
+        V = potential_from_coefs(coefs)
+        self._check(self.lib.pimc_evolution_matrix(self.h, C.byref(V), m, t, p, L, n, C.c_void_p(device_ptr), ld))
+
+    def spectrum(self, coefs, m, t, p, L, n, k, max_iter=None, tol=1e-10, want_psi=False):
+        """pimc_spectrum -> (E [k], psi [k, n] or None, SpectrumInfo, status); max_iter defaults to
+        min(n, 1024)."""
+        V = potential_from_coefs(coefs)
+        if max_iter is None:
+            max_iter = min(int(n), 1024)
+        E = np.zeros(k, dtype=np.float64)
+        psi = np.zeros((k, n), dtype=np.float64) if want_psi else None
+        info = SpectrumInfo()
+        st = self._check(self.lib.pimc_spectrum(self.h, C.byref(V), m, t, p, L, n, k, max_iter, tol,
+                                                E.ctypes.data_as(C.POINTER(C.c_double)),
+                                                None if psi is None else psi.ctypes.data_as(C.POINTER(C.c_double)),
+                                                C.byref(info)))
+        return E, psi, info, st
 
     def last_kernel_ms(self) -> float:
         ms = C.c_double(0)

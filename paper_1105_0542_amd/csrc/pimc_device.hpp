@@ -271,6 +271,36 @@ struct GenericEval64 {
 #pragma unroll
         for (int i = 0; i < W; ++i) S += acc[i];
     }
+    // The W slice values separately (no accumulation): out[i] = sum_k z_i^k P_k(u_i).
+    template <int W>
+    __device__ __forceinline__ void values(int level, const double (&qa)[W], const double (&qb)[W], double (&out)[W]) const {
+        const const_ptr<double> t = as_const(tab) + level * stride;
+        double u[W], z[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            const double mid = 0.5 * (qa[i] + qb[i]);
+            const double dl = qb[i] - qa[i];
+            u[i] = EVEN ? mid * mid : mid;
+            z[i] = dl * dl;
+            out[i] = 0.0;
+        }
+        int off = stride;
+        for (int k = K - 1; k >= 0; --k) {
+            const int d = as_const(deg)[k];
+            off -= d + 1;
+            double v[W];
+            const double c0 = t[off];
+#pragma unroll
+            for (int i = 0; i < W; ++i) v[i] = c0;
+            for (int e = 1; e <= d; ++e) {
+                const double c = t[off + e];
+#pragma unroll
+                for (int i = 0; i < W; ++i) v[i] = fma(v[i], u[i], c);
+            }
+#pragma unroll
+            for (int i = 0; i < W; ++i) out[i] = (k == K - 1) ? v[i] : fma(out[i], z[i], v[i]);
+        }
+    }
 };
 
 // ---------------------------------------------------------------------------------------------

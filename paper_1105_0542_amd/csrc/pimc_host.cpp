@@ -301,6 +301,7 @@ const char* pimc_strerror(int status) {
         case PIMC_ENOMEM: return "out of memory";
         case PIMC_EDEVICE: return "device (HIP) error";
         case PIMC_WNONFINITE: return "warning: non-finite weights in the sums";
+        case PIMC_WNOTCONVERGED: return "warning: iteration limit reached before the tolerance";
         default: return "unknown status";
     }
 }

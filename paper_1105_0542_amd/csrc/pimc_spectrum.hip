@@ -1,0 +1,185 @@
+// Energy spectrum from the space-discretized evolution operator (the paper's application of
+// short-time amplitudes): the matrix M_ij = D A_1^(p)(x_i, x_j; t) on a grid, and the kernels of
+// a Lanczos iteration with full reorthogonalization that finds its largest eigenvalues
+// exp(-t E_n). Everything stays on the device; every reduction has a fixed order.
+#include <hip/hip_runtime.h>
+
+#include "pimc_spectrum.hpp"
+
+namespace pimc {
+
+constexpr int kMatCols = 4;           // matrix elements per thread (consecutive columns)
+
+// Element (i, j): pref * exp(-(y_j - y_i)^2 / (2t) - t W_p((y_i + y_j)/2, (y_j - y_i)/2; t)) with
+// y = sqrt(m) x, x_i = -L + (i + 1/2) D, pref = D sqrt(m) / sqrt(2 pi t).
+template <bool EVEN>
+__global__ void __launch_bounds__(256) k_evolution_matrix(SpecTable tb, double L, double D, double sm, double t,
+                                                          double pref, uint32_t n, double* __restrict__ M,
+                                                          uint64_t ld) {
+    const uint32_t i = blockIdx.y;
+    const uint32_t j0 = (blockIdx.x * 256u + threadIdx.x) * kMatCols;
+    if (j0 >= n) return;
+    const double yi = sm * ((double(i) + 0.5) * D - L);
+    double qa[kMatCols], qb[kMatCols], S[kMatCols];
+#pragma unroll
+    for (int c = 0; c < kMatCols; ++c) {
+        const uint32_t j = min(j0 + c, n - 1);
+        qa[c] = yi;
+        qb[c] = sm * ((double(j) + 0.5) * D - L);
+    }
+    const GenericEval64<EVEN> ev{tb.tab, tb.deg, tb.K, tb.stride};
+    ev.template values<kMatCols>(0, qa, qb, S);
+    double* row = M + uint64_t(i) * ld;
+#pragma unroll
+    for (int c = 0; c < kMatCols; ++c) {
+        if (j0 + c < n) {
+            const double dl = qb[c] - qa[c];
+            row[j0 + c] = pref * exp(-(dl * dl) / (2.0 * t) - S[c]);
+        }
+    }
+}
+
+// y = M x, M dense n x n with leading dimension ld (even, 16-byte aligned rows): a wave takes four
+// consecutive rows, lanes stride the columns two at a time, then a fixed butterfly.
+__global__ void __launch_bounds__(256) k_gemv4(const double* __restrict__ M, uint64_t ld, uint32_t n,
+                                               const double* __restrict__ x, double* __restrict__ y) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t row0 = (blockIdx.x * 4u + (threadIdx.x >> 6)) * 4u;
+    if (row0 >= n) return;
+    const uint32_t nr = min(4u, n - row0);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const double* r0 = M + uint64_t(row0) * ld;
+    for (uint32_t c = 2u * lane; c < n; c += 128u) {
+        if (c + 1 < n) {
+            const double2 xv = *reinterpret_cast<const double2*>(x + c);
+#pragma unroll
+            for (uint32_t r = 0; r < 4; ++r) {
+                if (r < nr) {
+                    const double2 mv = *reinterpret_cast<const double2*>(r0 + r * ld + c);
+                    acc[r] = fma(mv.x, xv.x, acc[r]);
+                    acc[r] = fma(mv.y, xv.y, acc[r]);
+                }
+            }
+        } else {
+            const double xv = x[c];
+#pragma unroll
+            for (uint32_t r = 0; r < 4; ++r)
+                if (r < nr) acc[r] = fma(r0[r * ld + c], xv, acc[r]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        double v = acc[r];
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+        acc[r] = v;
+    }
+    if (lane == 0)
+        for (uint32_t r = 0; r < nr; ++r) y[row0 + r] = acc[r];
+}
+
+// Fixed-order sum of v over one workgroup of 256 threads (result valid in thread 0).
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    const int t = threadIdx.x;
+    red[t] = v;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    return red[0];
+}
+
+// out[c] = sum_i Q[c*ldq + i] w[i], c = 0..ncols-1: one workgroup per column.
+__global__ void __launch_bounds__(256) k_col_dots(const double* __restrict__ Q, uint64_t ldq, uint32_t n,
+                                                  const double* __restrict__ w, double* __restrict__ out) {
+    __shared__ double red[256];
+    const uint32_t c = blockIdx.x;
+    const double* q = Q + uint64_t(c) * ldq;
+    double s = 0.0;
+    for (uint32_t i = threadIdx.x; i < n; i += 256u) s = fma(q[i], w[i], s);
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) out[c] = s;
+}
+
+// w -= alpha[j] q_j + beta[j-1] q_{j-1} (the three-term recurrence).
+__global__ void k_lanczos_recur(double* __restrict__ w, const double* __restrict__ Q, uint64_t ldq, uint32_t n,
+                                uint32_t j, const double* __restrict__ alpha, const double* __restrict__ beta) {
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i >= n) return;
+    double v = w[i] - alpha[j] * Q[uint64_t(j) * ldq + i];
+    if (j > 0) v -= beta[j - 1] * Q[uint64_t(j - 1) * ldq + i];
+    w[i] = v;
+}
+
+// y[i] (+)= sign * sum_{c < ncols} Q[c*ldq + i] h[c]: the Gram-Schmidt correction (sign -1, added to
+// y) or a Ritz vector (sign +1, y overwritten).
+__global__ void k_combine_cols(const double* __restrict__ Q, uint64_t ldq, uint32_t n, uint32_t ncols,
+                               const double* __restrict__ h, double* __restrict__ y, int subtract) {
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (uint32_t c = 0; c < ncols; ++c) s = fma(Q[uint64_t(c) * ldq + i], h[c], s);
+    y[i] = subtract ? y[i] - s : s;
+}
+
+// beta[j] = |w|, q_{j+1} = w / beta[j] (one workgroup; zero vector if |w| = 0).
+__global__ void __launch_bounds__(256) k_normalize(const double* __restrict__ w, uint32_t n, double* __restrict__ beta,
+                                                   uint32_t j, double* __restrict__ qnext) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (uint32_t i = threadIdx.x; i < n; i += 256u) s = fma(w[i], w[i], s);
+    s = block_sum(s, red);
+    __shared__ double nrm;
+    if (threadIdx.x == 0) {
+        nrm = sqrt(s);
+        beta[j] = nrm;
+    }
+    __syncthreads();
+    const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    for (uint32_t i = threadIdx.x; i < n; i += 256u) qnext[i] = w[i] * inv;
+}
+
+static inline uint32_t cdiv(uint64_t a, uint64_t b) { return uint32_t((a + b - 1) / b); }
+
+hipError_t launch_evolution_matrix(const SpecTable& tb, double L, double D, double sm, double t, double pref,
+                                   uint32_t n, double* M, uint64_t ld, hipStream_t st) {
+    if (n == 0 || ld < n) return hipErrorInvalidValue;
+    const dim3 grid(cdiv(n, 256u * kMatCols), n);
+    if (tb.even)
+        hipLaunchKernelGGL(k_evolution_matrix<true>, grid, dim3(256), 0, st, tb, L, D, sm, t, pref, n, M, ld);
+    else
+        hipLaunchKernelGGL(k_evolution_matrix<false>, grid, dim3(256), 0, st, tb, L, D, sm, t, pref, n, M, ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemv(const double* M, uint64_t ld, uint32_t n, const double* x, double* y, hipStream_t st) {
+    if (ld % 2 || (reinterpret_cast<uintptr_t>(M) & 15) || (reinterpret_cast<uintptr_t>(x) & 15))
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gemv4, dim3(cdiv(n, 16)), dim3(256), 0, st, M, ld, n, x, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_col_dots(const double* Q, uint64_t ldq, uint32_t n, uint32_t ncols, const double* w, double* out,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(k_col_dots, dim3(ncols), dim3(256), 0, st, Q, ldq, n, w, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_lanczos_recur(double* w, const double* Q, uint64_t ldq, uint32_t n, uint32_t j, const double* alpha,
+                                const double* beta, hipStream_t st) {
+    hipLaunchKernelGGL(k_lanczos_recur, dim3(cdiv(n, 256)), dim3(256), 0, st, w, Q, ldq, n, j, alpha, beta);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine_cols(const double* Q, uint64_t ldq, uint32_t n, uint32_t ncols, const double* h, double* y,
+                               int subtract, hipStream_t st) {
+    hipLaunchKernelGGL(k_combine_cols, dim3(cdiv(n, 256)), dim3(256), 0, st, Q, ldq, n, ncols, h, y, subtract);
+    return hipGetLastError();
+}
+
+hipError_t launch_normalize(const double* w, uint32_t n, double* beta, uint32_t j, double* qnext, hipStream_t st) {
+    hipLaunchKernelGGL(k_normalize, dim3(1), dim3(256), 0, st, w, n, beta, j, qnext);
+    return hipGetLastError();
+}
+
+}  // namespace pimc

@@ -1,0 +1,39 @@
+// Spectrum from the space-discretized evolution operator: launchers shared by the kernels
+// (pimc_spectrum.hip) and the host driver (pimc_spectrum_host.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pimc_device.hpp"
+
+namespace pimc {
+
+// The level-0 table of a problem with T = t (the short-time amplitude), device pointers.
+struct SpecTable {
+    const double* tab;      // folded P_k, highest power first, consecutive in k
+    const int* deg;         // K degrees
+    int K;
+    int stride;             // doubles in the table
+    int even;               // P_k in mid^2 (even potential) or mid
+};
+
+// M[i*ld + j] = pref * exp(-(y_j - y_i)^2/(2t) - t W_p) for the grid x_i = -L + (i + 1/2) D,
+// y = sm x, i, j < n (device M, ld >= n).
+hipError_t launch_evolution_matrix(const SpecTable& tb, double L, double D, double sm, double t, double pref,
+                                   uint32_t n, double* M, uint64_t ld, hipStream_t st);
+// y = M x (ld even; M and x 16-byte aligned).
+hipError_t launch_gemv(const double* M, uint64_t ld, uint32_t n, const double* x, double* y, hipStream_t st);
+// out[c] = <Q_c, w>, c < ncols (Q_c = Q + c*ldq).
+hipError_t launch_col_dots(const double* Q, uint64_t ldq, uint32_t n, uint32_t ncols, const double* w, double* out,
+                           hipStream_t st);
+// w -= alpha[j] Q_j + beta[j-1] Q_{j-1}.
+hipError_t launch_lanczos_recur(double* w, const double* Q, uint64_t ldq, uint32_t n, uint32_t j, const double* alpha,
+                                const double* beta, hipStream_t st);
+// y = sum_c h[c] Q_c (subtract = 0) or y -= sum_c h[c] Q_c (subtract = 1).
+hipError_t launch_combine_cols(const double* Q, uint64_t ldq, uint32_t n, uint32_t ncols, const double* h, double* y,
+                               int subtract, hipStream_t st);
+// beta[j] = |w|, qnext = w / beta[j].
+hipError_t launch_normalize(const double* w, uint32_t n, double* beta, uint32_t j, double* qnext, hipStream_t st);
+
+}  // namespace pimc

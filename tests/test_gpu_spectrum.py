@@ -1,0 +1,121 @@
+"""GPU parity of the evolution-operator spectrum (the paper's short-time application) against the
+oracle (oracle/spectrum.py) and closed forms.
+
+Tolerances:
+* matrix elements: both sides evaluate the same level-p action in FP64 (the device through the
+  folded table in mid^2 and dlt^2, the oracle by Horner in the mid-point), so t W_p differs by a few
+  ulp of its scale; elements agree to 1e-12 relative, with an absolute floor of 1e-14 of the
+  largest element for the underflowing far corners.
+* energies: the device's Lanczos stops at residuals <= 1e-10 of the top eigenvalue; eigenvalue
+  errors are quadratic in the residual, so E = -ln(lambda)/t agrees with the oracle's dense
+  eigensolver to 1e-8 (1 + |E|).
+* eigenfunctions of well-separated levels: 1e-6 (first order in the residual over the gap).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import paper_1105_0542_amd as P
+from oracle import closed_forms as cf
+from oracle import effective_action as ea
+from oracle import spectrum as osp
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _exact(coefs):
+    from fractions import Fraction
+    return ea.poly([Fraction(c) for c in coefs])
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = P.Context()
+    yield c
+    c.close()
+
+
+CASES = [  # coefs, m, t, p, L, n
+    (P.quartic(1.0, 0.0), 1.0, 0.1, 10, 8.0, 300),
+    (P.quartic(1.0, 48.0), 1.0, 0.02, 12, 8.0, 257),
+    (P.quartic(-10.0, 12.0), 1.0, 0.02, 10, 10.0, 400),
+    ([0.0, 0.3, 0.5, 0.1, 0.05], 1.5, 0.05, 8, 8.0, 333),
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_matrix_matches_oracle(ctx, case):
+    import torch
+    coefs, m, t, p, L, n = case
+    _log(f"matrix coefs={coefs} m={m} t={t} p={p} L={L} n={n}")
+    ld = n + 3
+    buf = torch.full((n, ld), float("nan"), dtype=torch.float64, device="cuda")
+    ctx.evolution_matrix(coefs, m, t, p, L, n, buf.data_ptr(), ld)
+    torch.cuda.synchronize()
+    got = buf[:, :n].cpu().numpy()
+    assert torch.isnan(buf[:, n:]).all()                  # padding untouched
+    ref, _, _ = osp.evolution_matrix(_exact(coefs), m, t, p, L, n)
+    assert np.array_equal(got, got.T)                      # exactly symmetric
+    err = np.abs(got - ref)
+    lim = 1e-12 * np.abs(ref) + 1e-14 * np.abs(ref).max()
+    assert np.all(err <= lim), (err / np.maximum(lim, 1e-300)).max()
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_spectrum_matches_oracle(ctx, case):
+    coefs, m, t, p, L, n = case
+    k = 8
+    _log(f"spectrum coefs={coefs} m={m} t={t} p={p} n={n} k={k}")
+    E, psi, info, st = ctx.spectrum(coefs, m, t, p, L, n, k, max_iter=n - 1, tol=1e-10, want_psi=True)
+    _log(f"  iterations {info.iterations} residual {info.max_residual:.2e}")
+    assert st == 0 and info.converged == 1
+    Er, psir, x, D = osp.spectrum(_exact(coefs), m, t, p, L, n, k)
+    assert np.all(np.abs(E - Er) <= 1e-8 * (1 + np.abs(Er))), (E - Er)
+    # eigenfunctions of levels separated from their neighbours
+    gaps = np.minimum(np.abs(np.diff(np.r_[-np.inf, Er])), np.abs(np.diff(np.r_[Er, np.inf])))
+    for j in range(k):
+        if gaps[j] > 1e-2:
+            # defined up to sign (the largest |psi| of an odd state sits at two mirror points)
+            d = min(np.max(np.abs(psi[j] - psir[:, j])), np.max(np.abs(psi[j] + psir[:, j])))
+            assert d < 1e-6, (j, d)
+            assert abs(np.sum(psi[j] ** 2) * D - 1.0) < 1e-12
+
+
+def test_oscillator_levels_on_the_device(ctx):
+    """E_n = n + 1/2 for V = q^2/2 (closed form), eigenfunction of the ground state."""
+    E, psi, info, st = ctx.spectrum(P.quartic(1.0, 0.0), 1.0, 0.1, 12, 8.0, 512, 10, want_psi=True)
+    assert st == 0
+    assert np.max(np.abs(E - (np.arange(10) + 0.5))) < 1e-10
+    x = -8.0 + (np.arange(512) + 0.5) * (16.0 / 512)
+    assert np.max(np.abs(psi[0] - math.pi ** -0.25 * np.exp(-x * x / 2))) < 1e-8
+
+
+@pytest.mark.parametrize("A,g,t,L", [(1.0, 48.0, 0.02, 8.0), (-10.0, 12.0, 0.1, 10.0)])
+def test_paper_size_grid_against_dvr(ctx, A, g, t, L):
+    """The two potentials of the paper's Fig. 3 at its grid (n = 16384: spacing 9.77e-4 and
+    1.22e-3) and level p = 21: the ten lowest levels against a sinc-DVR diagonalization."""
+    n = 16384
+    E, _, info, st = ctx.spectrum(P.quartic(A, g), 1.0, t, 21, L, n, 10, max_iter=1024, tol=1e-10)
+    _log(f"A={A} g={g}: {info.iterations} iterations, matrix {info.matrix_ms:.2f} ms, solve {info.solve_ms:.1f} ms, "
+         f"E0..2 = {E[:3]}")
+    assert st == 0
+    _, Ed, _ = cf.dvr_eigen(cf.quartic_V(A, g), L=L, h=0.02)
+    assert np.max(np.abs(E - Ed[:10]) / np.maximum(1.0, np.abs(Ed[:10]))) < 1e-8
+
+
+def test_invalid_arguments(ctx):
+    with pytest.raises(P.PimcError):
+        ctx.spectrum(P.quartic(1.0, 0.0), 1.0, 0.1, 22, 8.0, 128, 4)          # p above the short-time limit
+    with pytest.raises(P.PimcError):
+        ctx.spectrum(P.quartic(1.0, 0.0), 1.0, 0.1, 8, 8.0, 128, 4, max_iter=3)
+    with pytest.raises(P.PimcError):
+        ctx.spectrum(P.quartic(1.0, 0.0), 1.0, -0.1, 8, 8.0, 128, 4)
+    E, _, info, st = ctx.spectrum(P.quartic(1.0, 48.0), 1.0, 0.02, 8, 8.0, 2048, 20, max_iter=24, tol=1e-14)
+    assert st == P.binding.PIMC_WNOTCONVERGED and info.converged == 0 and info.iterations == 24

@@ -147,3 +147,12 @@ def test_flow_entry_points_validate_without_a_device():
     assert lib.pimc_flow_amplitude(None, 100, 1, 0, None, None) == -1
     loss = ctypes.c_double(0)
     assert lib.pimc_flow_grad(None, 1, 0, ctypes.byref(loss), None, None) == -1
+
+
+def test_spectrum_entry_points_validate_without_a_device():
+    lib = P.load_library()
+    V = P.potential_from_coefs(P.quartic(1, 48))
+    E = (ctypes.c_double * 4)()
+    assert lib.pimc_spectrum(None, ctypes.byref(V), 1.0, 0.02, 21, 8.0, 1024, 4, 100, 1e-10, E, None, None) == -1
+    assert lib.pimc_evolution_matrix(None, ctypes.byref(V), 1.0, 0.02, 8, 8.0, 64, None, 64) == -1
+    assert lib.pimc_strerror(2)
