@@ -20,6 +20,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -41,6 +43,12 @@ PREC = dict(g=10.0, p=18, s=9, T=1.0, samples=1_000_000_000, oracle_paths=20_000
 FLOW = dict(g=10.0, p=12, s=7, T=2.0, layers=8, batch=4096, lr=1e-3, beta=0.9, steps=2442,
             est_samples=1 << 24, plain_samples=1 << 26, target=1e-5,
             wide_batch=16384)   # same 1e7 training paths in 610 steps: fills the 256 CUs
+# Spectrum from the space-discretized evolution operator: the two potentials of the paper's Fig. 3
+# at its grid (n = 16384) and level p = 21 (short-time amplitudes, no Monte Carlo).
+SPECTRUM = [dict(name="anharmonic A=1 g=48", A=1.0, g=48.0, t=0.02, L=8.0),
+            dict(name="double well A=-10 g=12", A=-10.0, g=12.0, t=0.1, L=10.0)]
+SPEC_N, SPEC_P, SPEC_K = 16384, 21, 10
+HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["pimc_device.hpp", "pimc_kernels.hip", "pimc_internal.hpp", "pimc_tables.hpp", "pimc_math.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_amplitude_quartic64_p18_s10.json")
 
@@ -116,6 +124,48 @@ def oracle_precision_reference():
     tot = np.sum(parts, axis=0)[s]
     K0 = opimc.free_kernel(0.0, 1.0, T)
     return K0 * math.exp(-shift[s]) * (1.0 + tot[1] / tot[0])
+
+
+def oracle_spectrum_reference():
+    """Low-lying levels of the spectrum workloads by the oracle's sinc-DVR diagonalization (CPU)."""
+    from oracle import closed_forms as cf
+    out = []
+    for case in SPECTRUM:
+        _, E, _ = cf.dvr_eigen(cf.quartic_V(case["A"], case["g"]), L=case["L"], h=0.02)
+        out.append([float(v) for v in E[:SPEC_K]])
+    return out
+
+
+def spectrum_section(P, ctx, dvr):
+    """Matrix build (ALU: level-p Horner + exp per element) and Lanczos (HBM: one pass over the
+    matrix per step) for the spectrum workloads; levels against the DVR reference when given."""
+    rows = []
+    for ci, case in enumerate(SPECTRUM):
+        coefs = P.quartic(case["A"], case["g"])
+        ctx.spectrum(coefs, 1.0, case["t"], SPEC_P, case["L"], 1024, 4)            # warm
+        E, _, info, st = ctx.spectrum(coefs, 1.0, case["t"], SPEC_P, case["L"], SPEC_N, SPEC_K, max_iter=1024,
+                                      tol=1e-10)
+        tab, deg, _ = P.level_table(coefs, 1.0, case["t"], SPEC_P, 0)
+        flop_el = 2 * (tab.size - 1) + 10          # Horner over the table, mid/dlt/squares, Gaussian term
+        n2 = float(SPEC_N) ** 2
+        mat_tflops = n2 * flop_el / (info.matrix_ms / 1e3) / 1e12
+        bytes_iter = n2 * 8.0
+        row = {"workload": f"{case['name']}, t={case['t']:g}, L={case['L']:g}, n={SPEC_N}, p={SPEC_P}",
+               "status": st, "E": [float(v) for v in E], "lanczos_steps": info.iterations,
+               "max_residual": info.max_residual,
+               "matrix_ms": info.matrix_ms, "matrix_roofline": {
+                   "bound": "alu", "achieved": mat_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                   "frac": mat_tflops / FP64_PEAK_TFLOPS, "flop_per_element": flop_el,
+                   "note": "exp per element not counted"},
+               "solve_ms": info.solve_ms,
+               "lanczos_stream_GBs": bytes_iter * info.iterations / (info.solve_ms / 1e3) / 1e9,
+               "lanczos_note": "solve time includes the reorthogonalization and host checks every 16 steps; "
+                               "the matrix pass alone is bound by HBM (2.1 GB per step)"}
+        if dvr is not None:
+            ref = np.asarray(dvr[ci])
+            row["max_abs_diff_vs_dvr"] = float(np.max(np.abs(np.asarray(E) - ref)))
+        rows.append(row)
+    return rows
 
 
 def cpu_baseline(paths_per_point: int):
@@ -216,6 +266,8 @@ def main():
                     help="run only the timed p=18 sweep (for profiler runs): no other section, no cpu baseline")
     ap.add_argument("--only-proposal", action="store_true",
                     help="run only the proposal section (for profiler runs): no other section, no cpu baseline")
+    ap.add_argument("--only-spectrum", action="store_true",
+                    help="run only the spectrum section (for profiler runs), with its DVR reference")
     ap.add_argument("--flow-steps", type=int, default=FLOW["steps"],
                     help="training steps of the learned proposal (0 skips the proposal section)")
     args = ap.parse_args()
@@ -228,9 +280,10 @@ def main():
         sys.exit(2)
 
     # The oracle runs first, in worker processes forked before this process touches the GPU.
-    skip_cpu = args.no_cpu_baseline or args.only_headline or args.only_proposal
+    skip_cpu = args.no_cpu_baseline or args.only_headline or args.only_proposal or args.only_spectrum
     cpu = None if skip_cpu else cpu_baseline(CPU_SAMPLE_PATHS)
     prec_ref = None if skip_cpu else oracle_precision_reference()
+    spec_ref = None if (skip_cpu and not args.only_spectrum) else oracle_spectrum_reference()
 
     import paper_1105_0542_amd as P
 
@@ -238,6 +291,10 @@ def main():
     H = P.FLAG_HIERARCHY
     if args.only_proposal:
         print(json.dumps({"proposal": proposal_section(P, ctx, args.flow_steps)}), flush=True)
+        ctx.close()
+        return
+    if args.only_spectrum:
+        print(json.dumps({"spectrum": spectrum_section(P, ctx, spec_ref)}), flush=True)
         ctx.close()
         return
     N = 1 << S_DEPTH
@@ -338,6 +395,7 @@ def main():
         bt.close()
 
     flow_line = proposal_section(P, ctx, args.flow_steps) if args.flow_steps > 0 else None
+    spec_line = spectrum_section(P, ctx, spec_ref)
 
     line = {
         "metric": "slice-evals/s (p=18, FP64)",
@@ -377,6 +435,7 @@ def main():
         line["batched"] = batch_line
     if flow_line is not None:
         line["proposal"] = flow_line
+    line["spectrum"] = spec_line
     if cpu is not None:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)

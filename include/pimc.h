@@ -100,7 +100,8 @@ int pimc_check_problem(const pimc_potential *V, double m, double a, double b, do
  * coefficients zero) else u = x, after the mass rescaling: P_k = eps 4^-k sum_{m=k}^{p-1}
  * eps^(m-k) c_{m,k} (eq.(ansatz) and eq.(1Drec)/(diagonal) evaluated in FP64).
  * Layout of out: for k = 0..*n_k-1, the coefficients of P_k from the highest power deg[k] down to
- * power 0 (deg[k]+1 doubles each). deg must hold PIMC_MAX_P ints; *is_even reports the variable.
+ * power 0 (deg[k]+1 doubles each). deg must hold p ints; *is_even reports the variable.
+ * p in 1..PIMC_MAX_P_SHORT_TIME (the tables of the spectrum entry points go beyond PIMC_MAX_P).
  * cap = capacity of out in doubles; EINVAL if too small (*n_out then holds the size needed). */
 int pimc_level_table(const pimc_potential *V, double m, double T, int p, uint32_t level,
                      double *out, size_t cap, size_t *n_out, int *n_k, int *deg, int *is_even);

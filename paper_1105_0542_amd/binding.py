@@ -208,7 +208,7 @@ def level_table(coefs, m, T, p, level):
     V = potential_from_coefs(coefs)
     need = C.c_size_t(0)
     nk = C.c_int(0)
-    deg = (C.c_int * MAX_P)()
+    deg = (C.c_int * max(MAX_P, int(p)))()
     ev = C.c_int(0)
     lib.pimc_level_table(C.byref(V), m, T, p, level, None, 0, C.byref(need), C.byref(nk), deg, C.byref(ev))
     out = np.zeros(need.value, dtype=np.float64)

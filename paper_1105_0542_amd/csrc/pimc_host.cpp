@@ -315,8 +315,12 @@ int pimc_check_problem(const pimc_potential* V, double m, double a, double b, do
 
 int pimc_level_table(const pimc_potential* V, double m, double T, int p, uint32_t level, double* out, size_t cap,
                      size_t* n_out, int* n_k, int* deg, int* is_even) {
-    int st = check_args(V, m, 0.0, 0.0, T, 1u << std::min<uint32_t>(level, PIMC_MAX_S), p, 2);
+    int st = check_args(V, m, 0.0, 0.0, T, 1u << std::min<uint32_t>(level, PIMC_MAX_S), 1, 2);
     if (st) return st;
+    if (p < 1 || p > PIMC_MAX_P_SHORT_TIME) {
+        set_thread_error("p = %d outside 1..%d", p, PIMC_MAX_P_SHORT_TIME);
+        return PIMC_EINVAL;
+    }
     if (level > PIMC_MAX_S) { set_thread_error("level > %d", PIMC_MAX_S); return PIMC_EINVAL; }
     const PolyD Vt = rescaled_potential(V, m);
     const bool even = potential_is_even(Vt);

@@ -90,6 +90,8 @@ def _oracle_table(coefs, m, T, p, level):
     ([0.25, -0.5, 1.0, 0.3, 1 / 24], 1.0, 1.0, 10, 3),
     ([0.0, 0.0, 0.5, 0.0, -0.2, 0.0, 1 / 30.0], 1.0, 0.5, 14, 4),
     ([0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9], 1.0, 1.0, 18, 8),
+    (P.quartic(1, 48), 1.0, 0.02, 21, 0),         # the short-time tables of the spectrum (p = 21)
+    (P.quartic(-10, 12), 1.0, 0.1, 21, 0),
 ])
 def test_level_table_matches_exact_oracle(coefs, m, T, p, level):
     """The library's FP64 recursion and folding (eq.(1Drec), eq.(diagonal)) agree with the exact
@@ -114,7 +116,7 @@ def test_level_table_capacity_error():
 
 def test_strerror_codes():
     lib = P.load_library()
-    for code in (0, -1, -2, -3, -4, 1):
+    for code in (0, -1, -2, -3, -4, 1, 2):
         assert lib.pimc_strerror(code)
 
 
