@@ -16,7 +16,8 @@
 //    (Brownian-bridge) width that makes the kinetic term and normalizations integrate out to the
 //    free kernel.
 //  * Slice action eps W_p (Sec. 2.1, eq.(ansatz) at level p): sum_k z^k P_k(y), y = mid^2,
-//    z = dlt^2, Horner in y for each P_k then in z. Evaluated for W slices at once, coefficient-
+//    z = dlt^2, Horner in y for each P_k then in z (the quartic evaluators take y = (2 mid)^2 with
+//    the coefficient of y^e pre-scaled by 4^-e: exact, and one multiply fewer per slice). Evaluated for W slices at once, coefficient-
 //    major, so that every table coefficient (wave-uniform, scalar-loaded) feeds W independent FMA
 //    chains.
 #pragma once
@@ -165,9 +166,9 @@ struct QuarticEval64 {
         double y[W], z[W], acc[W];
 #pragma unroll
         for (int i = 0; i < W; ++i) {
-            const double mid = 0.5 * (qa[i] + qb[i]);
+            const double sum = qa[i] + qb[i];           // 2 mid: the table is scaled for (2 mid)^2
             const double dl = qb[i] - qa[i];
-            y[i] = mid * mid;
+            y[i] = sum * sum;
             z[i] = dl * dl;
         }
 #pragma unroll
@@ -206,9 +207,9 @@ struct QuarticEval32 {
         float y[W], z[W], acc[W];
 #pragma unroll
         for (int i = 0; i < W; ++i) {
-            const float mid = float(0.5 * (qa[i] + qb[i]));
+            const float sum = float(qa[i] + qb[i]);     // 2 mid: the table is scaled for (2 mid)^2
             const float dl = float(qb[i] - qa[i]);
-            y[i] = mid * mid;
+            y[i] = sum * sum;
             z[i] = dl * dl;
         }
 #pragma unroll

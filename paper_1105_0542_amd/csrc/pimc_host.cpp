@@ -202,9 +202,13 @@ int build_problem(const pimc_potential* V, double m, double a, double b, double 
         std::copy(lt.coef.begin(), lt.coef.end(), P.tab.begin() + size_t(n) * size_t(P.stride));
         levels.push_back(std::move(lt));
     }
-    P.tab32.resize(P.tab.size());
-    for (size_t i = 0; i < P.tab.size(); ++i) {
-        const double v = P.tab[i];
+    // device copies: the quartic evaluators square the endpoint sum, the generic ones the mid-point
+    P.tab_dev = P.tab;
+    if (P.kind == EvalKind::Quartic64 || P.kind == EvalKind::Quartic32)
+        for (int n = 0; n <= P.s; ++n) scale_for_endpoint_sum(P.tab_dev.data() + size_t(n) * size_t(P.stride), P.deg);
+    P.tab32.resize(P.tab_dev.size());
+    for (size_t i = 0; i < P.tab_dev.size(); ++i) {
+        const double v = P.tab_dev[i];
         P.tab32[i] = (std::fabs(v) < double(std::numeric_limits<float>::min())) ? 0.0f : float(v);
     }
     P.sig.assign(size_t(P.s + 1), 0.0);
@@ -231,7 +235,7 @@ int stage_problem(pimc_ctx* c, const Problem& P, uint64_t seed, uint32_t stream,
     std::memcpy(host.data(), P.sig.data(), nlev * 8);
     std::memcpy(host.data() + off_shift, P.shift.data(), nlev * 8);
     if (n_tab) {
-        std::memcpy(host.data() + off_tab, P.tab.data(), n_tab * 8);
+        std::memcpy(host.data() + off_tab, P.tab_dev.data(), n_tab * 8);
         std::memcpy(host.data() + off_tab32, P.tab32.data(), n_tab * 4);
     }
     if (!P.deg.empty()) std::memcpy(host.data() + off_deg, P.deg.data(), P.deg.size() * 4);
@@ -714,7 +718,9 @@ int pimc_batch_create(pimc_ctx* c, const pimc_potential* systems, int n_systems,
         auto& lv = combo_levels[kv.first];
         for (int n = 0; n <= kv.second; ++n) {
             lv.push_back(fold_level(C, true, std::ldexp(T, -n), xdeg));
+            const size_t at = blob.size();
             blob.insert(blob.end(), lv.back().coef.begin(), lv.back().coef.end());
+            scale_for_endpoint_sum(blob.data() + at, lv.back().deg);     // quartic evaluator form
         }
     }
     // ---- per task: sigma, S_ref, chunking; device order grouped by p

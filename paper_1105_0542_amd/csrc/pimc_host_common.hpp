@@ -57,7 +57,8 @@ struct Problem {
     double a = 0, b = 0, T = 0, pref = 1.0, K0 = 0.0;
     std::vector<int> deg;            // per k in the evaluation variable
     int stride = 0;                  // doubles per level table
-    std::vector<double> tab;         // (s+1) * stride
+    std::vector<double> tab;         // (s+1) * stride, the folded tables (mid-point form)
+    std::vector<double> tab_dev;     // the same as uploaded for the estimation kernels
     std::vector<float> tab32;
     std::vector<double> sig;         // s+1
     std::vector<double> shift;       // s+1

@@ -128,6 +128,18 @@ inline LevelTable fold_level(const Coefficients& C, bool even, double eps, const
     return t;
 }
 
+// Device form of an even table for evaluators that square the endpoint sum (qa + qb) instead of
+// the mid-point: the coefficient of u^e is multiplied by 4^-e, so with u' = (qa + qb)^2 = 4 mid^2
+// every Horner step is the unscaled one times an exact power of two (the same results bit for bit).
+// coef: one level (deg.size() blocks, highest power first).
+inline void scale_for_endpoint_sum(double* coef, const std::vector<int>& deg) {
+    size_t off = 0;
+    for (int d : deg) {
+        for (int i = 0; i <= d; ++i) coef[off + size_t(i)] = std::ldexp(coef[off + size_t(i)], -2 * (d - i));
+        off += size_t(d) + 1;
+    }
+}
+
 // Degree (in x) of each P_k at level p: the largest degree among c_{m,k}, m = k..p-1, with
 // trailing all-zero k dropped.
 inline std::vector<int> table_xdegrees(const Coefficients& C) {
