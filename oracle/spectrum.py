@@ -15,6 +15,11 @@ estimator: coordinates times sqrt(m), coefficient j of V times m^(-j/2), amplitu
 Grid reading (the paper states L and the spacing only): x_i = -L + (i + 1/2) D, i = 0..n-1,
 D = 2L/n -- symmetric about 0, so parity is kept exactly.
 
+Cutoff reading: the short-time expansion in the half-deviation xbar has a finite radius (Sec. 5;
+for the Poeschl-Teller potential the poles of 1/cosh^2), so far from the diagonal the truncated
+exponent can grow without bound where the true amplitude is negligible. Elements whose
+free-particle factor exp(-(x_j - x_i)^2 / (2t)) is below exp(-40) (4e-18) are set to zero.
+
 Pins (tests/test_oracle_spectrum.py): the harmonic oscillator gives E_n = (n + 1/2)/sqrt(m) and its
 ground state pi^(-1/4) exp(-x^2/2) (closed forms); the anharmonic oscillator and the double well
 agree with an independent sinc-DVR diagonalization of H (``closed_forms.dvr_eigen``).
@@ -28,6 +33,9 @@ import numpy as np
 
 from . import effective_action as ea
 from . import pimc as opimc
+
+
+GAUSS_CUT = 40.0
 
 
 def grid(L: float, n: int):
@@ -48,8 +56,11 @@ def evolution_matrix(V, m, t, p, L, n):
     mid = 0.5 * (a + b)
     half = 0.5 * (b - a)
     S = opimc.eps_W(tab, mid, half)
-    logA = -(b - a) ** 2 / (2.0 * t) - S
-    M = D * sm / math.sqrt(2.0 * math.pi * t) * np.exp(logA)
+    g = (b - a) ** 2 / (2.0 * t)
+    logA = -g - S
+    with np.errstate(over="ignore"):
+        M = D * sm / math.sqrt(2.0 * math.pi * t) * np.exp(logA)
+    M[g > GAUSS_CUT] = 0.0
     return M, x, D
 
 
