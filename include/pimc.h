@@ -144,6 +144,30 @@ int pimc_last_partials(pimc_ctx *ctx, uint32_t level, uint64_t first_chunk, uint
 int pimc_normals(pimc_ctx *ctx, uint64_t seed, uint32_t stream, uint64_t first_path, uint64_t k_paths,
                  uint32_t n_nodes, double *out);
 
+/* ---- the modified Poeschl-Teller potential ----------------------------------------------------
+ *
+ * V(q) = -lambda / cosh^2(alpha q) (eq.(1D-MPT)), by the model-specific ansatz of the paper
+ * (eq.(1D-MPTansatz)): with y = tanh(alpha q), 1/cosh^2 = 1 - y^2 and d/dq = alpha (1 - y^2) d/dy,
+ * so eq.(1Drec)/(diagonal) run on polynomials in y and every c_{m,k} is an even polynomial in y.
+ * The slice action is eps W_p = sum_k dlt^(2k) P_k(tanh^2(alpha mid)) with the same folding as the
+ * polynomial tables (mass: alpha -> alpha/sqrt(m), coordinates times sqrt(m), as above). FP64 only
+ * (PIMC_FP32_POLY returns EUNSUPPORTED). Outputs, errors and the Philox/bisection conventions are
+ * those of pimc_amplitude / pimc_path_actions / pimc_level_table. */
+typedef struct {
+    double lambda;             /* depth (any finite value; > 0 is attractive)                       */
+    double alpha;              /* inverse width, finite and > 0                                     */
+} pimc_mpt;
+
+int pimc_amplitude_mpt(pimc_ctx *ctx, const pimc_mpt *V, double m, double a, double b, double T, uint32_t N, int p,
+                       uint64_t n_samples, uint64_t seed, uint32_t stream, uint32_t flags, pimc_level_result *out);
+int pimc_path_actions_mpt(pimc_ctx *ctx, const pimc_mpt *V, double m, double a, double b, double T, uint32_t N,
+                          int p, uint64_t seed, uint32_t stream, uint32_t flags, uint64_t first_path,
+                          uint64_t k_paths, double *S_out);
+/* Table of one level in the variable u = tanh^2(alpha' q'), layout as pimc_level_table (p up to
+ * PIMC_MAX_P_SHORT_TIME; deg must hold p ints). */
+int pimc_level_table_mpt(const pimc_mpt *V, double m, double T, int p, uint32_t level, double *out, size_t cap,
+                         size_t *n_out, int *n_k, int *deg);
+
 /* ---- batches: whole grids of endpoints with mixed N, p, T in one graph launch ------------------- */
 
 /* One amplitude of a batch: potential systems[system] with mass m, A_N^(p)(a, b; T) estimated from

@@ -48,6 +48,10 @@ class Task(C.Structure):
                 ("N", C.c_uint32), ("p", C.c_int), ("n_samples", C.c_uint64), ("stream", C.c_uint32)]
 
 
+class Mpt(C.Structure):
+    _fields_ = [("lambda_", C.c_double), ("alpha", C.c_double)]
+
+
 class FlowConfig(C.Structure):
     _fields_ = [("layers", C.c_int), ("batch", C.c_uint32), ("lr", C.c_double), ("beta", C.c_double),
                 ("init_seed", C.c_uint64), ("init_scale", C.c_double)]
@@ -165,6 +169,16 @@ def load_library():
                                           P(C.c_double), P(C.c_double)]
     lib.pimc_flow_amplitude.restype = C.c_int
     lib.pimc_flow_amplitude.argtypes = [vp, C.c_uint64, C.c_uint64, C.c_uint32, P(_LevelResult), P(C.c_double)]
+    lib.pimc_amplitude_mpt.restype = C.c_int
+    lib.pimc_amplitude_mpt.argtypes = [vp, P(Mpt), C.c_double, C.c_double, C.c_double, C.c_double, C.c_uint32,
+                                       C.c_int, C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32, P(_LevelResult)]
+    lib.pimc_path_actions_mpt.restype = C.c_int
+    lib.pimc_path_actions_mpt.argtypes = [vp, P(Mpt), C.c_double, C.c_double, C.c_double, C.c_double, C.c_uint32,
+                                          C.c_int, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint64,
+                                          P(C.c_double)]
+    lib.pimc_level_table_mpt.restype = C.c_int
+    lib.pimc_level_table_mpt.argtypes = [P(Mpt), C.c_double, C.c_double, C.c_int, C.c_uint32, P(C.c_double),
+                                         C.c_size_t, P(C.c_size_t), P(C.c_int), P(C.c_int)]
     lib.pimc_evolution_matrix.restype = C.c_int
     lib.pimc_evolution_matrix.argtypes = [vp, P(Potential), C.c_double, C.c_double, C.c_int, C.c_double, C.c_uint32,
                                           vp, C.c_uint64]
@@ -217,6 +231,22 @@ def level_table(coefs, m, T, p, level):
     if st != PIMC_OK:
         raise _err(lib, None, st)
     return out, [deg[k] for k in range(nk.value)], bool(ev.value)
+
+
+def level_table_mpt(lam, alpha, m, T, p, level):
+    """(coef array, degrees per k) of pimc_level_table_mpt (host-only call): tables in tanh^2."""
+    lib = load_library()
+    V = Mpt(float(lam), float(alpha))
+    need = C.c_size_t(0)
+    nk = C.c_int(0)
+    deg = (C.c_int * max(MAX_P, int(p)))()
+    lib.pimc_level_table_mpt(C.byref(V), m, T, p, level, None, 0, C.byref(need), C.byref(nk), deg)
+    out = np.zeros(need.value, dtype=np.float64)
+    st = lib.pimc_level_table_mpt(C.byref(V), m, T, p, level, out.ctypes.data_as(C.POINTER(C.c_double)), out.size,
+                                  C.byref(need), C.byref(nk), deg)
+    if st != PIMC_OK:
+        raise _err(lib, None, st)
+    return out, [deg[k] for k in range(nk.value)]
 
 
 def _torch_stream_handle() -> Optional[int]:
@@ -278,6 +308,24 @@ class Context:
                                                  flags, out))
         res = [LevelResult(r.amp, r.err, r.log_amp, r.relvar, r.ess, int(r.n), int(r.n_nonfinite)) for r in out]
         return res, st
+
+    def amplitude_mpt(self, lam, alpha, m, a, b, T, N, p, n_samples, seed, stream=0, flags=0):
+        """pimc_amplitude_mpt (V = -lam / cosh^2(alpha q)) -> (list of LevelResult, status)."""
+        V = Mpt(float(lam), float(alpha))
+        s = int(N).bit_length() - 1
+        out = (_LevelResult * (s + 1))()
+        st = self._check(self.lib.pimc_amplitude_mpt(self.h, C.byref(V), m, a, b, T, N, p, n_samples, seed, stream,
+                                                     flags, out))
+        res = [LevelResult(r.amp, r.err, r.log_amp, r.relvar, r.ess, int(r.n), int(r.n_nonfinite)) for r in out]
+        return res, st
+
+    def path_actions_mpt(self, lam, alpha, m, a, b, T, N, p, seed, stream, flags, first_path, k_paths):
+        V = Mpt(float(lam), float(alpha))
+        s = int(N).bit_length() - 1
+        out = np.zeros((k_paths, s + 1), dtype=np.float64)
+        self._check(self.lib.pimc_path_actions_mpt(self.h, C.byref(V), m, a, b, T, N, p, seed, stream, flags,
+                                                   first_path, k_paths, out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
 
     def path_actions(self, coefs, m, a, b, T, N, p, seed, stream, flags, first_path, k_paths):
         """pimc_path_actions -> array [k_paths, s+1]."""

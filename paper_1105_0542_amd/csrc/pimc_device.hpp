@@ -232,6 +232,49 @@ struct QuarticEval32 {
     }
 };
 
+// The modified Poeschl-Teller potential -lambda/cosh^2(alpha x): runtime shape in
+// u = tanh^2(alpha mid) (the coefficients of eq.(1D-MPTansatz) as polynomials in tanh^2).
+struct TanhEval64 {
+    const double* __restrict__ tab;
+    const int* __restrict__ deg;      // device, K entries
+    int K;
+    int stride;
+    double alpha;
+    __device__ __forceinline__ void launder() { asm volatile("" : "+s"(tab)); }
+    template <int W>
+    __device__ __forceinline__ void eval(int level, const double (&qa)[W], const double (&qb)[W], double& S) const {
+        const const_ptr<double> t = as_const(tab) + level * stride;
+        double u[W], z[W], acc[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            const double mid = 0.5 * (qa[i] + qb[i]);
+            const double dl = qb[i] - qa[i];
+            const double y = tanh(alpha * mid);
+            u[i] = y * y;
+            z[i] = dl * dl;
+            acc[i] = 0.0;
+        }
+        int off = stride;
+        for (int k = K - 1; k >= 0; --k) {
+            const int d = as_const(deg)[k];
+            off -= d + 1;
+            double v[W];
+            const double c0 = t[off];
+#pragma unroll
+            for (int i = 0; i < W; ++i) v[i] = c0;
+            for (int e = 1; e <= d; ++e) {
+                const double c = t[off + e];
+#pragma unroll
+                for (int i = 0; i < W; ++i) v[i] = fma(v[i], u[i], c);
+            }
+#pragma unroll
+            for (int i = 0; i < W; ++i) acc[i] = (k == K - 1) ? v[i] : fma(acc[i], z[i], v[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < W; ++i) S += acc[i];
+    }
+};
+
 // Any polynomial potential: runtime shape (K polynomials, degrees deg[k]) in u = x^2 (EVEN) or x.
 template <bool EVEN>
 struct GenericEval64 {

@@ -219,6 +219,64 @@ int build_problem(const pimc_potential* V, double m, double a, double b, double 
     return PIMC_OK;
 }
 
+int build_problem_mpt(double lambda, double alpha, double m, double a, double b, double T, uint32_t N, int p,
+                      uint32_t flags, Problem& P, char* why, size_t whylen) {
+    if (flags & PIMC_FP32_POLY) {
+        std::snprintf(why, whylen, "FP32 polynomials need an even polynomial potential of degree <= 4");
+        return PIMC_EUNSUPPORTED;
+    }
+    P.s = log2_exact(N);
+    P.p = p;
+    P.T = T;
+    const double sm = std::sqrt(m);
+    P.a = a * sm;
+    P.b = b * sm;
+    P.pref = sm;
+    P.K0 = free_kernel(P.a, P.b, T);
+    P.alpha = alpha / sm;
+    P.even = true;
+    P.kind = EvalKind::Tanh64;
+    P.U = std::min(P.s, 4);
+    if (P.s == 0) P.U = 0;
+    P.D = P.s - P.U;
+    const PolyD Vy = {-lambda, 0.0, lambda};                    // -lambda (1 - tanh^2)
+    const Coefficients C = effective_coefficients(Vy, p, TanhDerivative{P.alpha});
+    const std::vector<int> ydeg = table_xdegrees(C);
+    for (int d : ydeg)
+        if (d % 2) {
+            std::snprintf(why, whylen, "internal: odd power of tanh in the Poeschl-Teller table");
+            return PIMC_EUNSUPPORTED;
+        }
+    P.deg.clear();
+    for (int d : ydeg) P.deg.push_back(d / 2);
+    P.stride = 0;
+    for (int d : P.deg) P.stride += d + 1;
+    P.tab.assign(size_t(P.s + 1) * size_t(P.stride), 0.0);
+    std::vector<LevelTable> levels;
+    for (int n = 0; n <= P.s; ++n) {
+        LevelTable lt = fold_level(C, true, std::ldexp(T, -n), ydeg);
+        lt.tanh_alpha = P.alpha;
+        std::copy(lt.coef.begin(), lt.coef.end(), P.tab.begin() + size_t(n) * size_t(P.stride));
+        levels.push_back(std::move(lt));
+    }
+    P.tab_dev = P.tab;
+    P.tab32.assign(P.tab.size(), 0.0f);
+    P.sig.assign(size_t(P.s + 1), 0.0);
+    for (int n = 1; n <= P.s; ++n) P.sig[size_t(n)] = std::sqrt(T / std::ldexp(1.0, n + 1));
+    P.shift.assign(size_t(P.s + 1), 0.0);
+    for (int n = 0; n <= P.s; ++n) P.shift[size_t(n)] = straight_line_action(levels[size_t(n)], P.a, P.b, n);
+    P.level0_action = P.shift[0];
+    return PIMC_OK;
+}
+
+int check_mpt(const pimc_mpt* V, double m, double a, double b, double T, uint32_t N, int p, uint64_t n_samples) {
+    if (!V) { set_thread_error("potential is NULL"); return PIMC_EINVAL; }
+    if (!std::isfinite(V->lambda)) { set_thread_error("lambda must be finite"); return PIMC_EINVAL; }
+    if (!std::isfinite(V->alpha) || V->alpha <= 0) { set_thread_error("alpha must be finite and > 0"); return PIMC_EINVAL; }
+    pimc_potential zero{};
+    return check_args(&zero, m, a, b, T, N, p, n_samples);
+}
+
 uint32_t paths_per_lane(int s) { return s >= 10 ? 1u : (1u << (10 - s)); }
 
 // Upload tables and per-level constants; fill the kernel arguments except the output pointers.
@@ -255,6 +313,7 @@ int stage_problem(pimc_ctx* c, const Problem& P, uint64_t seed, uint32_t stream,
     A.gstride = P.stride;
     A.a = P.a;
     A.b = P.b;
+    A.alpha = P.alpha;
     A.key.seed_lo = uint32_t(seed);
     A.key.seed_hi = uint32_t(seed >> 32);
     A.key.stream = stream;
@@ -291,6 +350,106 @@ int check_args(const pimc_potential* V, double m, double a, double b, double T, 
 }
 
 const uint32_t kKnownFlags = PIMC_FP32_POLY | PIMC_HIERARCHY;
+
+// Estimation of every requested level of a built problem (the body shared by the potentials).
+int amplitude_core(pimc_ctx* c, const Problem& P, uint64_t n_samples, uint64_t seed, uint32_t stream, uint32_t flags,
+                   pimc_level_result* out) {
+    int st;
+    const int nlev = P.s + 1;
+    const bool hier = (flags & PIMC_HIERARCHY) != 0;
+    for (int n = 0; n < nlev; ++n) out[n] = pimc_level_result{};
+    // level 0: the analytic short-time amplitude (Sec. 4.2), error 0
+    out[0].log_amp = std::log(P.pref * P.K0) - P.level0_action;
+    out[0].amp = std::exp(out[0].log_amp);
+    out[0].n = n_samples;
+    out[0].ess = double(n_samples);
+    c->last_s = P.s;
+    c->last_shift = P.shift;
+    if (P.s == 0) return PIMC_OK;
+
+    AmpArgs A;
+    st = stage_problem(c, P, seed, stream, A);
+    if (st) return st;
+    const uint32_t ppl = paths_per_lane(P.s);
+    const uint64_t chunk_paths = uint64_t(kBlock) * ppl;
+    const uint64_t n_chunks = (n_samples + chunk_paths - 1) / chunk_paths;
+    const int slots = hier ? nlev : 1;            // partial slot of level n: n, or 0 for level s alone
+    st = ensure(c, reinterpret_cast<void**>(&c->d_partials), &c->partial_bytes, size_t(slots) * n_chunks * 4 * 8);
+    if (st) return st;
+    st = ensure(c, reinterpret_cast<void**>(&c->d_red), &c->red_bytes, size_t(slots) * 4 * 8);
+    if (st) return st;
+    st = ensure(c, reinterpret_cast<void**>(&c->d_seg), &c->seg_bytes, size_t(slots) * 2 * 8);
+    if (st) return st;
+    c->h_seg.assign(size_t(slots) * 2, 0);
+    for (int k = 0; k < slots; ++k) {
+        c->h_seg[size_t(k)] = uint64_t(k) * n_chunks * 4;
+        c->h_seg[size_t(slots + k)] = n_chunks;
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->d_seg, c->h_seg.data(), c->h_seg.size() * 8, hipMemcpyHostToDevice, c->stream));
+    A.first_path = 0;
+    A.n_paths = n_samples;
+    A.n_chunks = n_chunks;
+    A.ppl = ppl;
+    A.hier = hier ? 1 : 0;
+    A.partials = c->d_partials;
+    A.dump = nullptr;
+    const int grid = launch_grid(c, P, n_chunks);
+    HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
+    HIP_TRY(c, launch_amplitude(A, P.kind, P.p, P.U, grid, c->stream));
+    HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
+    HIP_TRY(c, launch_seg_reduce(c->d_partials, c->d_seg, c->d_seg + slots, uint64_t(slots), c->d_red, c->stream));
+    std::vector<double> red(size_t(slots) * 4);
+    HIP_TRY(c, hipMemcpyAsync(red.data(), c->d_red, red.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    float ms = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    c->last_ms = ms;
+    c->last_chunks = n_chunks;
+    c->last_chunk_paths = chunk_paths;
+    c->last_hier = hier;
+    bool nonfinite = false;
+    for (int n = 1; n < nlev; ++n) {
+        if (!hier && n != P.s) continue;
+        const size_t k = size_t(hier ? n : 0);
+        if (assemble_level(&red[k * 4], std::log(P.pref * P.K0) - P.shift[size_t(n)], out[n])) nonfinite = true;
+    }
+    return nonfinite ? PIMC_WNONFINITE : PIMC_OK;
+}
+
+
+// Per-path level actions of a built problem by the estimation kernels (shared by the potentials).
+int path_actions_core(pimc_ctx* c, const Problem& P, uint64_t seed, uint32_t stream, uint32_t flags,
+                      uint64_t first_path, uint64_t k_paths, double* S_out) {
+    int st;
+    const size_t nlev = size_t(P.s + 1);
+    if (P.s == 0) {
+        for (uint64_t i = 0; i < k_paths; ++i) S_out[i] = P.level0_action;
+        return PIMC_OK;
+    }
+    AmpArgs A;
+    st = stage_problem(c, P, seed, stream, A);
+    if (st) return st;
+    st = ensure(c, reinterpret_cast<void**>(&c->d_dump), &c->dump_bytes, size_t(k_paths) * nlev * 8);
+    if (st) return st;
+    const uint32_t ppl = paths_per_lane(P.s);
+    const uint64_t chunk_paths = uint64_t(kBlock) * ppl;
+    A.first_path = first_path;
+    A.n_paths = k_paths;
+    A.n_chunks = (k_paths + chunk_paths - 1) / chunk_paths;
+    A.ppl = ppl;
+    A.hier = (flags & PIMC_HIERARCHY) ? 1 : 0;
+    A.partials = nullptr;
+    A.dump = c->d_dump;
+    const int grid = launch_grid(c, P, A.n_chunks);
+    HIP_TRY(c, launch_amplitude(A, P.kind, P.p, P.U, grid, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(S_out, c->d_dump, size_t(k_paths) * nlev * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    // level 0 is the same straight slice for every path: report it for every path
+    for (uint64_t i = 0; i < k_paths; ++i)
+        if (!(flags & PIMC_HIERARCHY)) S_out[i * nlev] = 0.0;
+    return PIMC_OK;
+}
+
 
 }  // namespace
 
@@ -403,65 +562,7 @@ int pimc_amplitude(pimc_ctx* c, const pimc_potential* V, double m, double a, dou
     char why[256] = "";
     st = build_problem(V, m, a, b, T, N, p, flags, P, why, sizeof(why));
     if (st) return ctx_fail(c, st, "%s", why);
-    const int nlev = P.s + 1;
-    const bool hier = (flags & PIMC_HIERARCHY) != 0;
-    for (int n = 0; n < nlev; ++n) out[n] = pimc_level_result{};
-    // level 0: the analytic short-time amplitude (Sec. 4.2), error 0
-    out[0].log_amp = std::log(P.pref * P.K0) - P.level0_action;
-    out[0].amp = std::exp(out[0].log_amp);
-    out[0].n = n_samples;
-    out[0].ess = double(n_samples);
-    c->last_s = P.s;
-    c->last_shift = P.shift;
-    if (P.s == 0) return PIMC_OK;
-
-    AmpArgs A;
-    st = stage_problem(c, P, seed, stream, A);
-    if (st) return st;
-    const uint32_t ppl = paths_per_lane(P.s);
-    const uint64_t chunk_paths = uint64_t(kBlock) * ppl;
-    const uint64_t n_chunks = (n_samples + chunk_paths - 1) / chunk_paths;
-    const int slots = hier ? nlev : 1;            // partial slot of level n: n, or 0 for level s alone
-    st = ensure(c, reinterpret_cast<void**>(&c->d_partials), &c->partial_bytes, size_t(slots) * n_chunks * 4 * 8);
-    if (st) return st;
-    st = ensure(c, reinterpret_cast<void**>(&c->d_red), &c->red_bytes, size_t(slots) * 4 * 8);
-    if (st) return st;
-    st = ensure(c, reinterpret_cast<void**>(&c->d_seg), &c->seg_bytes, size_t(slots) * 2 * 8);
-    if (st) return st;
-    c->h_seg.assign(size_t(slots) * 2, 0);
-    for (int k = 0; k < slots; ++k) {
-        c->h_seg[size_t(k)] = uint64_t(k) * n_chunks * 4;
-        c->h_seg[size_t(slots + k)] = n_chunks;
-    }
-    HIP_TRY(c, hipMemcpyAsync(c->d_seg, c->h_seg.data(), c->h_seg.size() * 8, hipMemcpyHostToDevice, c->stream));
-    A.first_path = 0;
-    A.n_paths = n_samples;
-    A.n_chunks = n_chunks;
-    A.ppl = ppl;
-    A.hier = hier ? 1 : 0;
-    A.partials = c->d_partials;
-    A.dump = nullptr;
-    const int grid = launch_grid(c, P, n_chunks);
-    HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
-    HIP_TRY(c, launch_amplitude(A, P.kind, P.p, P.U, grid, c->stream));
-    HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
-    HIP_TRY(c, launch_seg_reduce(c->d_partials, c->d_seg, c->d_seg + slots, uint64_t(slots), c->d_red, c->stream));
-    std::vector<double> red(size_t(slots) * 4);
-    HIP_TRY(c, hipMemcpyAsync(red.data(), c->d_red, red.size() * 8, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    float ms = 0.f;
-    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
-    c->last_ms = ms;
-    c->last_chunks = n_chunks;
-    c->last_chunk_paths = chunk_paths;
-    c->last_hier = hier;
-    bool nonfinite = false;
-    for (int n = 1; n < nlev; ++n) {
-        if (!hier && n != P.s) continue;
-        const size_t k = size_t(hier ? n : 0);
-        if (assemble_level(&red[k * 4], std::log(P.pref * P.K0) - P.shift[size_t(n)], out[n])) nonfinite = true;
-    }
-    return nonfinite ? PIMC_WNONFINITE : PIMC_OK;
+    return amplitude_core(c, P, n_samples, seed, stream, flags, out);
 }
 
 int pimc_path_actions(pimc_ctx* c, const pimc_potential* V, double m, double a, double b, double T, uint32_t N,
@@ -478,32 +579,63 @@ int pimc_path_actions(pimc_ctx* c, const pimc_potential* V, double m, double a, 
     char why[256] = "";
     st = build_problem(V, m, a, b, T, N, p, flags, P, why, sizeof(why));
     if (st) return ctx_fail(c, st, "%s", why);
-    const size_t nlev = size_t(P.s + 1);
-    if (P.s == 0) {
-        for (uint64_t i = 0; i < k_paths; ++i) S_out[i] = P.level0_action;
-        return PIMC_OK;
+    return path_actions_core(c, P, seed, stream, flags, first_path, k_paths, S_out);
+}
+
+int pimc_amplitude_mpt(pimc_ctx* c, const pimc_mpt* V, double m, double a, double b, double T, uint32_t N, int p,
+                       uint64_t n_samples, uint64_t seed, uint32_t stream, uint32_t flags, pimc_level_result* out) {
+    int st = check_mpt(V, m, a, b, T, N, p, n_samples);
+    if (st) return c ? ctx_fail(c, st, "%s", g_thread_error) : st;
+    if (!c) { set_thread_error("context is NULL"); return PIMC_EINVAL; }
+    if (!out) return ctx_fail(c, PIMC_EINVAL, "out is NULL");
+    if (flags & ~kKnownFlags) return ctx_fail(c, PIMC_EINVAL, "unknown flags 0x%x", flags & ~kKnownFlags);
+    HIP_TRY(c, hipSetDevice(c->device));
+    Problem P;
+    char why[256] = "";
+    st = build_problem_mpt(V->lambda, V->alpha, m, a, b, T, N, p, flags, P, why, sizeof(why));
+    if (st) return ctx_fail(c, st, "%s", why);
+    return amplitude_core(c, P, n_samples, seed, stream, flags, out);
+}
+
+int pimc_path_actions_mpt(pimc_ctx* c, const pimc_mpt* V, double m, double a, double b, double T, uint32_t N, int p,
+                          uint64_t seed, uint32_t stream, uint32_t flags, uint64_t first_path, uint64_t k_paths,
+                          double* S_out) {
+    int st = check_mpt(V, m, a, b, T, N, p, 2);
+    if (st) return c ? ctx_fail(c, st, "%s", g_thread_error) : st;
+    if (!c) { set_thread_error("context is NULL"); return PIMC_EINVAL; }
+    if (!S_out && k_paths) return ctx_fail(c, PIMC_EINVAL, "S_out is NULL");
+    if (flags & ~kKnownFlags) return ctx_fail(c, PIMC_EINVAL, "unknown flags 0x%x", flags & ~kKnownFlags);
+    if (k_paths == 0) return PIMC_OK;
+    HIP_TRY(c, hipSetDevice(c->device));
+    Problem P;
+    char why[256] = "";
+    st = build_problem_mpt(V->lambda, V->alpha, m, a, b, T, N, p, flags, P, why, sizeof(why));
+    if (st) return ctx_fail(c, st, "%s", why);
+    return path_actions_core(c, P, seed, stream, flags, first_path, k_paths, S_out);
+}
+
+int pimc_level_table_mpt(const pimc_mpt* V, double m, double T, int p, uint32_t level, double* out, size_t cap,
+                         size_t* n_out, int* n_k, int* deg) {
+    int st = check_mpt(V, m, 0.0, 0.0, T, 1u << std::min<uint32_t>(level, PIMC_MAX_S), 1, 2);
+    if (st) return st;
+    if (p < 1 || p > PIMC_MAX_P_SHORT_TIME) {
+        set_thread_error("p = %d outside 1..%d", p, PIMC_MAX_P_SHORT_TIME);
+        return PIMC_EINVAL;
     }
-    AmpArgs A;
-    st = stage_problem(c, P, seed, stream, A);
-    if (st) return st;
-    st = ensure(c, reinterpret_cast<void**>(&c->d_dump), &c->dump_bytes, size_t(k_paths) * nlev * 8);
-    if (st) return st;
-    const uint32_t ppl = paths_per_lane(P.s);
-    const uint64_t chunk_paths = uint64_t(kBlock) * ppl;
-    A.first_path = first_path;
-    A.n_paths = k_paths;
-    A.n_chunks = (k_paths + chunk_paths - 1) / chunk_paths;
-    A.ppl = ppl;
-    A.hier = (flags & PIMC_HIERARCHY) ? 1 : 0;
-    A.partials = nullptr;
-    A.dump = c->d_dump;
-    const int grid = launch_grid(c, P, A.n_chunks);
-    HIP_TRY(c, launch_amplitude(A, P.kind, P.p, P.U, grid, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(S_out, c->d_dump, size_t(k_paths) * nlev * 8, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    // level 0 is the same straight slice for every path: report it for every path
-    for (uint64_t i = 0; i < k_paths; ++i)
-        if (!(flags & PIMC_HIERARCHY)) S_out[i * nlev] = 0.0;
+    if (level > PIMC_MAX_S) { set_thread_error("level > %d", PIMC_MAX_S); return PIMC_EINVAL; }
+    const double am = V->alpha / std::sqrt(m);
+    const Coefficients C = effective_coefficients(PolyD{-V->lambda, 0.0, V->lambda}, p, TanhDerivative{am});
+    const std::vector<int> ydeg = table_xdegrees(C);
+    const LevelTable lt = fold_level(C, true, std::ldexp(T, -int(level)), ydeg);
+    if (n_out) *n_out = lt.coef.size();
+    if (n_k) *n_k = int(lt.deg.size());
+    if (deg)
+        for (size_t k = 0; k < lt.deg.size(); ++k) deg[k] = lt.deg[k];
+    if (!out || cap < lt.coef.size()) {
+        set_thread_error("output capacity %zu < %zu", cap, lt.coef.size());
+        return PIMC_EINVAL;
+    }
+    std::copy(lt.coef.begin(), lt.coef.end(), out);
     return PIMC_OK;
 }
 

@@ -63,12 +63,17 @@ struct Problem {
     std::vector<double> sig;         // s+1
     std::vector<double> shift;       // s+1
     double level0_action = 0.0;      // T W_p((a+b)/2, (b-a)/2; T)
+    double alpha = 0.0;              // Poeschl-Teller: tables in u = tanh^2(alpha mid) (after the mass rescaling)
 };
 
 // Tables, bridge widths and straight-line reference actions of one problem after the mass
 // rescaling; returns a status and a reason in why.
 int build_problem(const pimc_potential* V, double m, double a, double b, double T, uint32_t N, int p, uint32_t flags,
                   Problem& P, char* why, size_t whylen);
+// The same for the modified Poeschl-Teller potential -lambda/cosh^2(alpha x) (tables in
+// u = tanh^2(alpha' mid), alpha' = alpha/sqrt(m)).
+int build_problem_mpt(double lambda, double alpha, double m, double a, double b, double T, uint32_t N, int p,
+                      uint32_t flags, Problem& P, char* why, size_t whylen);
 // Level result from the canonical sums (n, sum d, sum d^2, non-finite count) with d = w - 1 and
 // log prefactor logbase; true when the result is not finite.
 bool assemble_level(const double* red, double logbase, pimc_level_result& r);

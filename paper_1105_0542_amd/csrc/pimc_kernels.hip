@@ -399,6 +399,17 @@ static hipError_t launch_generic(const AmpArgs& A, int U, int grid, hipStream_t 
     }
 }
 
+static hipError_t launch_tanh(const AmpArgs& A, int U, int grid, hipStream_t st) {
+    TanhEval64 ev{A.tab64, A.gdeg, A.gK, A.gstride, A.alpha};
+    switch (U) {
+        case 1: return launch_one<1>(A, ev, grid, st);
+        case 2: return launch_one<2>(A, ev, grid, st);
+        case 3: return launch_one<3>(A, ev, grid, st);
+        case 4: return launch_one<4>(A, ev, grid, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <int P>
 static hipError_t quartic_dispatch(const AmpArgs& A, bool fp32, int p, int grid, hipStream_t st) {
     if constexpr (P <= kMaxP) {
@@ -417,6 +428,7 @@ hipError_t launch_amplitude(const AmpArgs& A, EvalKind kind, int p, int U, int g
             return quartic_dispatch<1>(A, kind == EvalKind::Quartic32, p, grid, st);
         case EvalKind::GenericEven64: return launch_generic<true>(A, U, grid, st);
         case EvalKind::GenericOdd64: return launch_generic<false>(A, U, grid, st);
+        case EvalKind::Tanh64: return launch_tanh(A, U, grid, st);
     }
     return hipErrorInvalidValue;
 }
@@ -500,6 +512,13 @@ int amplitude_resident_blocks(EvalKind kind, int p, int U, size_t lds_bytes, int
                 case 2: return resident_one<2, GenericEval64<true>>(lds_bytes, device);
                 case 3: return resident_one<3, GenericEval64<true>>(lds_bytes, device);
                 default: return resident_one<4, GenericEval64<true>>(lds_bytes, device);
+            }
+        case EvalKind::Tanh64:
+            switch (U) {
+                case 1: return resident_one<1, TanhEval64>(lds_bytes, device);
+                case 2: return resident_one<2, TanhEval64>(lds_bytes, device);
+                case 3: return resident_one<3, TanhEval64>(lds_bytes, device);
+                default: return resident_one<4, TanhEval64>(lds_bytes, device);
             }
     }
     return 256;

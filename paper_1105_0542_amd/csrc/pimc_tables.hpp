@@ -54,23 +54,50 @@ struct Coefficients {
     std::vector<std::vector<PolyD>> c;
 };
 
-inline Coefficients effective_coefficients(const PolyD& V, int p) {
+// d/dx of a polynomial in x.
+struct XDerivative {
+    PolyD operator()(const PolyD& a, int times = 1) const { return poly_der(a, times); }
+};
+
+// d/dx of a polynomial in y = tanh(alpha x): alpha (1 - y^2) d/dy (polynomials in y stay
+// polynomials; the modified Poeschl-Teller potential -lambda/cosh^2(alpha x) is -lambda (1 - y^2)).
+struct TanhDerivative {
+    double alpha;
+    PolyD operator()(const PolyD& a, int times = 1) const {
+        PolyD r = a;
+        for (int t = 0; t < times; ++t) {
+            const PolyD d = poly_der(r);
+            PolyD out(d.size() + 2, 0.0);
+            for (size_t i = 0; i < d.size(); ++i) {
+                out[i] += alpha * d[i];
+                out[i + 2] -= alpha * d[i];
+            }
+            r = poly_trim(out);
+        }
+        return r;
+    }
+};
+
+// eq.(1Drec) and eq.(diagonal) with the derivative `der` (coefficients as polynomials in the
+// variable `der` differentiates).
+template <class Der>
+inline Coefficients effective_coefficients(const PolyD& V, int p, const Der& der) {
     Coefficients C;
     C.p = p;
     C.c.assign(p, std::vector<PolyD>(p));
     C.c[0][0] = poly_trim(V);
     double fact = 1.0;                                           // (2m+1)!
     std::vector<std::vector<PolyD>> d1(p, std::vector<PolyD>(p)); // first derivatives
-    d1[0][0] = poly_der(C.c[0][0]);
+    d1[0][0] = der(C.c[0][0]);
     for (int m = 1; m < p; ++m) {
         fact *= double(2 * m) * double(2 * m + 1);
-        PolyD diag = poly_der(C.c[0][0], 2 * m);                 // eq.(diagonal)
+        PolyD diag = der(C.c[0][0], 2 * m);                      // eq.(diagonal)
         for (double& v : diag) v /= fact;
         C.c[m][m] = poly_trim(diag);
         for (int k = m - 1; k >= 0; --k) {                       // eq.(1Drec)
             PolyD rhs;
             poly_axpy(rhs, double((2 * k + 2) * (2 * k + 1)), C.c[m][k + 1]);
-            poly_axpy(rhs, 1.0, poly_der(C.c[m - 1][k], 2));
+            poly_axpy(rhs, 1.0, der(C.c[m - 1][k], 2));
             for (int l = 0; l <= m - 2; ++l)
                 for (int r = std::max(0, k - m + l + 2); r <= std::min(k, l); ++r)
                     poly_axpy(rhs, -1.0, poly_mul(d1[l][r], d1[m - l - 2][k - r]));
@@ -82,15 +109,18 @@ inline Coefficients effective_coefficients(const PolyD& V, int p) {
             for (double& v : rhs) v /= double(8 * (m + k + 1));
             C.c[m][k] = poly_trim(rhs);
         }
-        for (int k = 0; k <= m; ++k) d1[m][k] = poly_der(C.c[m][k]);
+        for (int k = 0; k <= m; ++k) d1[m][k] = der(C.c[m][k]);
     }
     return C;
 }
+
+inline Coefficients effective_coefficients(const PolyD& V, int p) { return effective_coefficients(V, p, XDerivative{}); }
 
 // Folded table of one level: for k = 0..K-1 the coefficients of P_k(u) from the highest power
 // deg[k] down to 0.
 struct LevelTable {
     bool even = true;
+    double tanh_alpha = 0.0;       // > 0: the variable is u = tanh^2(tanh_alpha * mid)
     std::vector<int> deg;          // per k, in the variable u
     std::vector<double> coef;      // concatenated, highest power first
 };
@@ -159,7 +189,13 @@ inline std::vector<int> table_xdegrees(const Coefficients& C) {
 inline double eval_level(const LevelTable& t, double qa, double qb) {
     const double mid = 0.5 * (qa + qb);
     const double dl = qb - qa;
-    const double u = t.even ? mid * mid : mid;
+    double u;
+    if (t.tanh_alpha > 0.0) {
+        const double y = std::tanh(t.tanh_alpha * mid);
+        u = y * y;
+    } else {
+        u = t.even ? mid * mid : mid;
+    }
     const double z = dl * dl;
     double acc = 0.0;
     size_t off = t.coef.size();

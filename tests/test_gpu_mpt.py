@@ -1,0 +1,96 @@
+"""GPU parity of the modified Poeschl-Teller potential (model-specific ansatz, tables in tanh^2)
+against the oracle (oracle/mpt.py) and a DVR continuum reference.
+
+Tolerances: per-path level actions 1e-12 of max(1, |S|) (both sides FP64; tanh and the tables agree
+to a few ulp); amplitudes on identical samples 1e-10 relative; the continuum check within 5 MC
+standard errors.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import paper_1105_0542_amd as P
+from oracle import closed_forms as cf
+from oracle import mpt
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = P.Context()
+    yield c
+    c.close()
+
+
+CASES = [  # lam, alpha, m, a, b, T, s, p, flags
+    (1.0, 1.0, 1.0, -0.5, 0.5, 1.0, 5, 10, P.FLAG_HIERARCHY),
+    (3.0, 0.75, 2.0, 0.3, -0.2, 2.0, 6, 8, 0),
+    (-1.5, 1.25, 1.0, 0.0, 1.0, 0.5, 3, 12, P.FLAG_HIERARCHY),       # repulsive barrier
+    (2.0, 1.0, 1.0, -1.0, 2.0, 1.0, 7, 4, P.FLAG_HIERARCHY),         # U = 4 subtrees below D = 3 levels
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_path_actions_match_oracle(ctx, case):
+    lam, alpha, m, a, b, T, s, p, flags = case
+    _log(f"mpt actions lam={lam} alpha={alpha} m={m} a={a} b={b} T={T} s={s} p={p} flags={flags}")
+    k = 1500
+    got = ctx.path_actions_mpt(lam, alpha, m, a, b, T, 1 << s, p, 7, 3, flags, 100, k)
+    ref = mpt.path_actions(lam, alpha, m, a, b, T, s, p, 7, 3, np.arange(100, 100 + k))
+    levels = range(1, s + 1) if flags & P.FLAG_HIERARCHY else [s]
+    for n in levels:
+        err = np.abs(got[:, n] - ref[:, n])
+        assert np.all(err <= 1e-12 * np.maximum(1.0, np.abs(ref[:, n]))), (n, err.max())
+
+
+@pytest.mark.parametrize("case", CASES[:3])
+def test_amplitude_matches_oracle_on_identical_samples(ctx, case):
+    lam, alpha, m, a, b, T, s, p, flags = case
+    n = 20000
+    res, st = ctx.amplitude_mpt(lam, alpha, m, a, b, T, 1 << s, p, n, 5, 1, P.FLAG_HIERARCHY)
+    ref = mpt.amplitude(lam, alpha, m, a, b, T, s, p, n, 5, 1)
+    for lev in range(s + 1):
+        assert res[lev].amp == pytest.approx(ref[lev]["amp"], rel=1e-10), lev
+        if lev:
+            assert res[lev].err == pytest.approx(ref[lev]["err"], rel=1e-7), lev
+
+
+def test_hierarchy_levels_equal_separate_runs(ctx):
+    """Level n of an s-run is bitwise the n-run on the same samples (the bisection nests)."""
+    full, _ = ctx.amplitude_mpt(1.0, 1.0, 1.0, -0.5, 0.5, 1.0, 64, 10, 30000, 2, 0, P.FLAG_HIERARCHY)
+    for s in (2, 4, 5):
+        part, _ = ctx.amplitude_mpt(1.0, 1.0, 1.0, -0.5, 0.5, 1.0, 1 << s, 10, 30000, 2, 0, 0)
+        assert part[s].amp == full[s].amp and part[s].err == full[s].err
+
+
+def test_convergence_to_the_continuum(ctx):
+    """The paper's Fig. 2 set-up, lambda = alpha = 1, A(-0.5, 0.5; 1) from one s = 10 run per p:
+    p = 10 agrees with a DVR diagonalization of H at every N >= 16 within the MC error, while p = 1
+    at N = 16 is visibly off (its discretization error is O(1/N))."""
+    V = lambda x: -1.0 / np.cosh(x) ** 2
+    ref = cf.dvr_amplitude(V, -0.5, 0.5, 1.0, L=20.0, h=0.025)
+    n = 2_000_000
+    r10, _ = ctx.amplitude_mpt(1.0, 1.0, 1.0, -0.5, 0.5, 1.0, 1024, 10, n, 11, 0, P.FLAG_HIERARCHY)
+    r1, _ = ctx.amplitude_mpt(1.0, 1.0, 1.0, -0.5, 0.5, 1.0, 1024, 1, n, 11, 0, P.FLAG_HIERARCHY)
+    _log(f"DVR {ref:.8f}; p=10: " + " ".join(f"{r.amp:.6f}" for r in r10[4:]) +
+         "; p=1: " + " ".join(f"{r.amp:.6f}" for r in r1[4:]))
+    for lev in range(4, 11):
+        assert abs(r10[lev].amp - ref) <= 5 * r10[lev].err, (lev, r10[lev].amp, ref, r10[lev].err)
+    assert abs(r1[4].amp - ref) > 10 * r1[4].err
+    assert abs(r1[10].amp - ref) < abs(r1[4].amp - ref)
+
+
+def test_invalid_arguments(ctx):
+    with pytest.raises(P.PimcError):
+        ctx.amplitude_mpt(1.0, 0.0, 1.0, 0.0, 1.0, 1.0, 16, 4, 100, 1)          # alpha must be > 0
+    with pytest.raises(P.PimcError) as e:
+        ctx.amplitude_mpt(1.0, 1.0, 1.0, 0.0, 1.0, 1.0, 16, 4, 100, 1, 0, P.FLAG_FP32_POLY)
+    assert e.value.status == -2

@@ -158,3 +158,29 @@ def test_spectrum_entry_points_validate_without_a_device():
     assert lib.pimc_spectrum(None, ctypes.byref(V), 1.0, 0.02, 21, 8.0, 1024, 4, 100, 1e-10, E, None, None) == -1
     assert lib.pimc_evolution_matrix(None, ctypes.byref(V), 1.0, 0.02, 8, 8.0, 64, None, 64) == -1
     assert lib.pimc_strerror(2)
+
+
+@pytest.mark.parametrize("lam,alpha,m,T,p,level", [
+    (1.0, 1.0, 1.0, 1.0, 10, 4), (3.0, 0.75, 1.0, 2.0, 12, 6), (2.0, 1.5, 2.0, 0.5, 8, 2), (1.0, 1.0, 1.0, 0.05, 21, 0),
+])
+def test_mpt_level_table_matches_exact_oracle(lam, alpha, m, T, p, level):
+    """The Poeschl-Teller tables of the library (FP64 recursion in tanh(alpha x)) agree with the
+    exact rational recursion of the oracle, folded the same way (P_k in u = tanh^2, 4^-k). Since
+    0 <= u < 1, each P_k block is compared against the sum of its |coefficients| (the bound of its
+    value): the FP64 fold cancels large alternating terms where eps is beyond the convergence
+    radius (coarse levels at p >= 14), never in these cases."""
+    from fractions import Fraction
+    from oracle import mpt
+    tab, deg = P.level_table_mpt(lam, alpha, m, T, p, level)
+    am = mpt._alpha_m(alpha, m)
+    Q = mpt.xbar_groups(lam, am, p, Fraction(T) / (1 << level))
+    rdeg = []
+    off = 0
+    for k, q in enumerate(Q):
+        assert all(q[i] == 0 for i in range(1, len(q), 2))
+        blk = np.array([float(q[i] / 4 ** k) for i in range(0, len(q), 2)][::-1])
+        rdeg.append(blk.size - 1)
+        got = tab[off:off + blk.size]
+        off += blk.size
+        assert np.max(np.abs(got - blk)) <= 1e-14 * np.sum(np.abs(blk)), k
+    assert deg == rdeg and off == tab.size
