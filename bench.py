@@ -49,6 +49,9 @@ SPECTRUM = [dict(name="anharmonic A=1 g=48", A=1.0, g=48.0, t=0.02, L=8.0),
             dict(name="double well A=-10 g=12", A=-10.0, g=12.0, t=0.1, L=10.0)]
 SPEC_N, SPEC_P, SPEC_K = 16384, 21, 10
 HBM_PEAK_GBS = 8000.0
+# Modified Poeschl-Teller potential (the paper's Fig. 2): V = -lambda/cosh^2(alpha q), lambda = alpha = 1,
+# A_N^(p)(-0.5, 0.5; 1) for p in {1, 2, 10} from one s = 10 run each (every N = 2^0..2^10).
+MPT = dict(lam=1.0, alpha=1.0, a=-0.5, b=0.5, T=1.0, s=10, ps=(1, 2, 10), samples=100_000_000)
 KERNEL_SOURCES = ["pimc_device.hpp", "pimc_kernels.hip", "pimc_internal.hpp", "pimc_tables.hpp", "pimc_math.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_amplitude_quartic64_p18_s10.json")
 
@@ -133,6 +136,56 @@ def oracle_spectrum_reference():
     for case in SPECTRUM:
         _, E, _ = cf.dvr_eigen(cf.quartic_V(case["A"], case["g"]), L=case["L"], h=0.02)
         out.append([float(v) for v in E[:SPEC_K]])
+    return out
+
+
+def oracle_mpt_reference():
+    """A(-0.5, 0.5; 1) of the Poeschl-Teller workload by the oracle's DVR diagonalization (CPU)."""
+    from oracle import closed_forms as cf
+    lam, alpha = MPT["lam"], MPT["alpha"]
+    return float(cf.dvr_amplitude(lambda x: -lam / np.cosh(alpha * x) ** 2, MPT["a"], MPT["b"], MPT["T"],
+                                  L=20.0, h=0.025))
+
+
+def _fit_continuum(levels, p):
+    """Weighted least squares of eq.(fit), A_N = A + B/N^p + C/N^(p+1), over the given levels
+    (N = 2^n >= 4); returns (A, its standard error)."""
+    rows, rhs, w = [], [], []
+    for n, r in levels:
+        N = float(1 << n)
+        if N < 4 or r.err <= 0:
+            continue
+        rows.append([1.0, N ** -p, N ** -(p + 1)])
+        rhs.append(r.amp)
+        w.append(1.0 / r.err)
+    X = np.array(rows) * np.array(w)[:, None]
+    y = np.array(rhs) * np.array(w)
+    coef, *_ = np.linalg.lstsq(X, y, rcond=None)
+    cov = np.linalg.pinv(X.T @ X)
+    return float(coef[0]), float(math.sqrt(max(cov[0, 0], 0.0)))
+
+
+def mpt_section(P, ctx, dvr):
+    """Convergence of A_N^(p) with N for the Poeschl-Teller potential at p = 1, 2, 10 (Fig. 2),
+    eq.(fit) extrapolations, and the DVR continuum value when given."""
+    M = MPT
+    out = {"workload": f"V=-{M['lam']:g}/cosh^2({M['alpha']:g} q), A_N^(p)({M['a']:g}, {M['b']:g}; {M['T']:g}), "
+                       f"one s={M['s']} run per p (N = 1..{1 << M['s']}), {M['samples']:.0e} samples each",
+           "per_p": {}}
+    for p in M["ps"]:
+        res, st = ctx.amplitude_mpt(M["lam"], M["alpha"], 1.0, M["a"], M["b"], M["T"], 1 << M["s"], p, M["samples"],
+                                    1, 0, P.FLAG_HIERARCHY)
+        ms = ctx.last_kernel_ms()
+        A, dA = _fit_continuum(list(enumerate(res)), p)
+        row = {"A_N": [r.amp for r in res], "err_N": [r.err for r in res], "fit_A": A, "fit_err": dA,
+               "kernel_ms": ms, "slice_evals_per_s": M["samples"] * slices_per_sample(M["s"], True) / (ms / 1e3),
+               "status": st}
+        if dvr is not None:
+            row["A_N_minus_dvr_over_err_at_N1024"] = (res[M["s"]].amp - dvr) / res[M["s"]].err
+            row["fit_minus_dvr_over_err"] = (A - dvr) / dA if dA > 0 else None
+        out["per_p"][str(p)] = row
+    if dvr is not None:
+        out["dvr_continuum"] = dvr
     return out
 
 
@@ -266,6 +319,8 @@ def main():
                     help="run only the timed p=18 sweep (for profiler runs): no other section, no cpu baseline")
     ap.add_argument("--only-proposal", action="store_true",
                     help="run only the proposal section (for profiler runs): no other section, no cpu baseline")
+    ap.add_argument("--only-mpt", action="store_true",
+                    help="run only the Poeschl-Teller convergence section, with its DVR reference")
     ap.add_argument("--only-spectrum", action="store_true",
                     help="run only the spectrum section (for profiler runs), with its DVR reference")
     ap.add_argument("--flow-steps", type=int, default=FLOW["steps"],
@@ -280,10 +335,12 @@ def main():
         sys.exit(2)
 
     # The oracle runs first, in worker processes forked before this process touches the GPU.
-    skip_cpu = args.no_cpu_baseline or args.only_headline or args.only_proposal or args.only_spectrum
+    skip_cpu = (args.no_cpu_baseline or args.only_headline or args.only_proposal or args.only_spectrum or
+                args.only_mpt)
     cpu = None if skip_cpu else cpu_baseline(CPU_SAMPLE_PATHS)
     prec_ref = None if skip_cpu else oracle_precision_reference()
     spec_ref = None if (skip_cpu and not args.only_spectrum) else oracle_spectrum_reference()
+    mpt_ref = None if (skip_cpu and not args.only_mpt) else oracle_mpt_reference()
 
     import paper_1105_0542_amd as P
 
@@ -295,6 +352,10 @@ def main():
         return
     if args.only_spectrum:
         print(json.dumps({"spectrum": spectrum_section(P, ctx, spec_ref)}), flush=True)
+        ctx.close()
+        return
+    if args.only_mpt:
+        print(json.dumps({"mpt": mpt_section(P, ctx, mpt_ref)}), flush=True)
         ctx.close()
         return
     N = 1 << S_DEPTH
@@ -396,6 +457,7 @@ def main():
 
     flow_line = proposal_section(P, ctx, args.flow_steps) if args.flow_steps > 0 else None
     spec_line = spectrum_section(P, ctx, spec_ref)
+    mpt_line = mpt_section(P, ctx, mpt_ref)
 
     line = {
         "metric": "slice-evals/s (p=18, FP64)",
@@ -436,6 +498,7 @@ def main():
     if flow_line is not None:
         line["proposal"] = flow_line
     line["spectrum"] = spec_line
+    line["mpt"] = mpt_line
     if cpu is not None:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
