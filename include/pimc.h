@@ -168,6 +168,34 @@ int pimc_path_actions_mpt(pimc_ctx *ctx, const pimc_mpt *V, double m, double a, 
 int pimc_level_table_mpt(const pimc_mpt *V, double m, double T, int p, uint32_t level, double *out, size_t cap,
                          size_t *n_out, int *n_k, int *deg);
 
+/* ---- general potentials: the effective potential in the derivatives of V ----------------------
+ *
+ * For a general V the coefficients of eq.(ansatz) are expressions in V and its derivatives up to
+ * order 2p-2 (Sec. 3.1/3.2). Here eq.(1Drec)/(diagonal) run once per p on polynomials in the
+ * symbols v_j = V^(j)(x) (d v_j/dx = v_{j+1}); each slice evaluates the folded monomials from the
+ * derivatives of V at its mid-point. The potentials of this mode are
+ *     V(q) = sum_{j <= degree} coef[j] q^j + sum_i A_i / cosh^2(alpha_i q) + sum_i B_i exp(-beta_i q^2)
+ * (derivatives from closed-form recurrences). p in 1..PIMC_GEN_MAX_P, FP64 only; everything else
+ * (mass rescaling, Philox/bisection, outputs, errors) as pimc_amplitude / pimc_path_actions. */
+#define PIMC_GEN_MAX_P 10
+#define PIMC_GEN_MAX_TERMS 4
+
+typedef struct {
+    int degree;                           /* polynomial part, 0..PIMC_MAX_DEGREE                   */
+    double coef[PIMC_MAX_DEGREE + 1];
+    int n_sech2;                          /* 0..PIMC_GEN_MAX_TERMS terms A / cosh^2(alpha q)        */
+    double sech2_A[PIMC_GEN_MAX_TERMS], sech2_alpha[PIMC_GEN_MAX_TERMS];   /* alpha > 0              */
+    int n_gauss;                          /* 0..PIMC_GEN_MAX_TERMS terms B exp(-beta q^2)           */
+    double gauss_B[PIMC_GEN_MAX_TERMS], gauss_beta[PIMC_GEN_MAX_TERMS];    /* beta > 0               */
+} pimc_general_potential;
+
+int pimc_amplitude_general(pimc_ctx *ctx, const pimc_general_potential *V, double m, double a, double b, double T,
+                           uint32_t N, int p, uint64_t n_samples, uint64_t seed, uint32_t stream, uint32_t flags,
+                           pimc_level_result *out);
+int pimc_path_actions_general(pimc_ctx *ctx, const pimc_general_potential *V, double m, double a, double b,
+                              double T, uint32_t N, int p, uint64_t seed, uint32_t stream, uint32_t flags,
+                              uint64_t first_path, uint64_t k_paths, double *S_out);
+
 /* ---- batches: whole grids of endpoints with mixed N, p, T in one graph launch ------------------- */
 
 /* One amplitude of a batch: potential systems[system] with mass m, A_N^(p)(a, b; T) estimated from

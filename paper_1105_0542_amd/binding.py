@@ -48,6 +48,30 @@ class Task(C.Structure):
                 ("N", C.c_uint32), ("p", C.c_int), ("n_samples", C.c_uint64), ("stream", C.c_uint32)]
 
 
+class GeneralPotential(C.Structure):
+    _fields_ = [("degree", C.c_int), ("coef", C.c_double * (MAX_DEGREE + 1)), ("n_sech2", C.c_int),
+                ("sech2_A", C.c_double * 4), ("sech2_alpha", C.c_double * 4), ("n_gauss", C.c_int),
+                ("gauss_B", C.c_double * 4), ("gauss_beta", C.c_double * 4)]
+
+
+def general_potential(poly=(), sech2=(), gauss=()) -> GeneralPotential:
+    """V = sum poly[j] q^j + sum A / cosh^2(alpha q) for (A, alpha) in sech2 + sum B exp(-beta q^2)."""
+    V = GeneralPotential()
+    poly = list(poly)
+    if len(poly) > MAX_DEGREE + 1 or len(sech2) > 4 or len(gauss) > 4:
+        raise ValueError("too many terms")
+    V.degree = max(len(poly) - 1, 0)
+    for j in range(MAX_DEGREE + 1):
+        V.coef[j] = float(poly[j]) if j < len(poly) else 0.0
+    V.n_sech2 = len(sech2)
+    for i, (A, a) in enumerate(sech2):
+        V.sech2_A[i], V.sech2_alpha[i] = float(A), float(a)
+    V.n_gauss = len(gauss)
+    for i, (B, b) in enumerate(gauss):
+        V.gauss_B[i], V.gauss_beta[i] = float(B), float(b)
+    return V
+
+
 class Mpt(C.Structure):
     _fields_ = [("lambda_", C.c_double), ("alpha", C.c_double)]
 
@@ -179,6 +203,14 @@ def load_library():
     lib.pimc_level_table_mpt.restype = C.c_int
     lib.pimc_level_table_mpt.argtypes = [P(Mpt), C.c_double, C.c_double, C.c_int, C.c_uint32, P(C.c_double),
                                          C.c_size_t, P(C.c_size_t), P(C.c_int), P(C.c_int)]
+    lib.pimc_amplitude_general.restype = C.c_int
+    lib.pimc_amplitude_general.argtypes = [vp, P(GeneralPotential), C.c_double, C.c_double, C.c_double, C.c_double,
+                                           C.c_uint32, C.c_int, C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32,
+                                           P(_LevelResult)]
+    lib.pimc_path_actions_general.restype = C.c_int
+    lib.pimc_path_actions_general.argtypes = [vp, P(GeneralPotential), C.c_double, C.c_double, C.c_double,
+                                              C.c_double, C.c_uint32, C.c_int, C.c_uint64, C.c_uint32, C.c_uint32,
+                                              C.c_uint64, C.c_uint64, P(C.c_double)]
     lib.pimc_evolution_matrix.restype = C.c_int
     lib.pimc_evolution_matrix.argtypes = [vp, P(Potential), C.c_double, C.c_double, C.c_int, C.c_double, C.c_uint32,
                                           vp, C.c_uint64]
@@ -318,6 +350,25 @@ class Context:
                                                      flags, out))
         res = [LevelResult(r.amp, r.err, r.log_amp, r.relvar, r.ess, int(r.n), int(r.n_nonfinite)) for r in out]
         return res, st
+
+    def amplitude_general(self, m, a, b, T, N, p, n_samples, seed, stream=0, flags=0, poly=(), sech2=(), gauss=()):
+        """pimc_amplitude_general (derivative-symbol mode) -> (list of LevelResult, status)."""
+        V = general_potential(poly, sech2, gauss)
+        s = int(N).bit_length() - 1
+        out = (_LevelResult * (s + 1))()
+        st = self._check(self.lib.pimc_amplitude_general(self.h, C.byref(V), m, a, b, T, N, p, n_samples, seed,
+                                                         stream, flags, out))
+        res = [LevelResult(r.amp, r.err, r.log_amp, r.relvar, r.ess, int(r.n), int(r.n_nonfinite)) for r in out]
+        return res, st
+
+    def path_actions_general(self, m, a, b, T, N, p, seed, stream, flags, first_path, k_paths, poly=(), sech2=(),
+                             gauss=()):
+        V = general_potential(poly, sech2, gauss)
+        s = int(N).bit_length() - 1
+        out = np.zeros((k_paths, s + 1), dtype=np.float64)
+        self._check(self.lib.pimc_path_actions_general(self.h, C.byref(V), m, a, b, T, N, p, seed, stream, flags,
+                                                       first_path, k_paths, out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
 
     def path_actions_mpt(self, lam, alpha, m, a, b, T, N, p, seed, stream, flags, first_path, k_paths):
         V = Mpt(float(lam), float(alpha))

@@ -275,6 +275,97 @@ struct TanhEval64 {
     }
 };
 
+// General-potential mode: the effective potential as monomials in v_j = V^(j)(mid), j <= J, grouped
+// by the power of dlt^2; the derivatives of V = poly + sum A/cosh^2(a x) + sum B exp(-b x^2) come
+// from tables (see pimc_general.hpp). The derivative values of the slice are kept in lane-private
+// LDS slots and read with the wave-uniform factor numbers of each record (scalar loads).
+constexpr int kGenMaxP = 10;
+constexpr int kGenMaxJ = 2 * kGenMaxP - 2;
+constexpr int kGenMaxTerms = 4;
+constexpr int kGenLanes = 256;                  // threads per workgroup of the estimation kernels
+
+struct GenTables {
+    const GenRecord* rec;                        // all levels
+    const uint32_t* grp;                         // per level K+1 offsets into rec
+    int K, J;
+    const double* dpoly;                         // (J+1) x 9
+    int pdeg;
+    const double* dsech;                         // per term (J+1) x (J+3)
+    int n_sech;
+    int n_gauss;
+    double sech_a[kGenMaxTerms];
+    double gB[kGenMaxTerms], gb[kGenMaxTerms], gsb[kGenMaxTerms];
+};
+
+// Lane-private derivative slots (one LDS array per kernel, whatever the batch widths used).
+__device__ __forceinline__ double* gen_slots() {
+    __shared__ double vbuf[(kGenMaxJ + 1) * kGenLanes];
+    return vbuf + threadIdx.x;
+}
+
+struct GeneralEval64 {
+    GenTables g;
+    __device__ __forceinline__ void launder() {}
+    template <int W>
+    __device__ __forceinline__ void eval(int level, const double (&qa)[W], const double (&qb)[W], double& S) const {
+        double* v = gen_slots();
+        const int J = g.J;
+        const const_ptr<double> dp = as_const(g.dpoly);
+        const const_ptr<double> ds = as_const(g.dsech);
+        const const_ptr<GenRecord> rec = as_const(g.rec);
+        const const_ptr<uint32_t> grp = as_const(g.grp) + level * (g.K + 1);
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            const double x = 0.5 * (qa[i] + qb[i]);
+            const double dl = qb[i] - qa[i];
+            const double z = dl * dl;
+            for (int j = 0; j <= J; ++j) {
+                const int dg = g.pdeg - j;
+                double acc = 0.0;
+                if (dg >= 0) {
+                    acc = dp[j * 9 + dg];
+                    for (int n = dg - 1; n >= 0; --n) acc = fma(acc, x, dp[j * 9 + n]);
+                }
+                v[j * kGenLanes] = acc;
+            }
+            for (int t = 0; t < g.n_sech; ++t) {
+                const double th = tanh(g.sech_a[t] * x);
+                for (int j = 0; j <= J; ++j) {
+                    const int row = (t * (J + 1) + j) * (J + 3);
+                    double acc = ds[row + j + 2];
+                    for (int n = j + 1; n >= 0; --n) acc = fma(acc, th, ds[row + n]);
+                    v[j * kGenLanes] += acc;
+                }
+            }
+            for (int t = 0; t < g.n_gauss; ++t) {
+                const double y = g.gsb[t] * x;
+                double e = g.gB[t] * exp(-g.gb[t] * x * x);
+                double hm = 0.0, h = 1.0;
+                for (int j = 0; j <= J; ++j) {
+                    v[j * kGenLanes] += e * h;
+                    const double hn = 2.0 * y * h - 2.0 * double(j) * hm;
+                    hm = h;
+                    h = hn;
+                    e *= -g.gsb[t];
+                }
+            }
+            double acc = 0.0;
+            for (int k = g.K - 1; k >= 0; --k) {
+                double val = 0.0;
+                const uint32_t r1 = grp[k + 1];
+                for (uint32_t r = grp[k]; r < r1; ++r) {
+                    double t = rec[r].coef;
+                    const int nf = rec[r].nf;
+                    for (int f = 0; f < nf; ++f) t *= v[int(rec[r].f[f]) * kGenLanes];
+                    val += t;
+                }
+                acc = (k == g.K - 1) ? val : fma(acc, z, val);
+            }
+            S += acc;
+        }
+    }
+};
+
 // Any polynomial potential: runtime shape (K polynomials, degrees deg[k]) in u = x^2 (EVEN) or x.
 template <bool EVEN>
 struct GenericEval64 {

@@ -1,0 +1,231 @@
+// General-potential mode (host side): the effective potential in the derivative symbols
+// v_j = V^(j)(x) (Sec. 3.1/3.2: for a general V the c_{m,k} are expressions in V and its
+// derivatives up to order 2p-2). eq.(1Drec) and eq.(diagonal) run on polynomials in v_0..v_J with
+// the derivation d v_j/dx = v_{j+1}; the result does not depend on V and is computed once per p.
+// Per bisection level the polynomials are folded into monomial records grouped by the power of
+// dlt^2 (eps W_p = sum_k dlt^(2k) sum_records coef * prod v_f), which the device evaluates from
+// the derivative values at each slice mid-point.
+//
+// Potentials of this mode: V(x) = sum_n c_n x^n + sum_i A_i / cosh^2(a_i x) + sum_i B_i exp(-b_i x^2),
+// whose derivatives come from tables computed here: the polynomial's derivative coefficients, the
+// polynomials S_j(t) in t = tanh(a x) with d^j/dx^j (A/cosh^2(a x)) = A a^j S_j(t), S_0 = 1 - t^2,
+// S_{j+1} = (1 - t^2) S_j'(t), and Hermite polynomials for the Gaussians.
+#pragma once
+
+#include <cmath>
+#include <cstdint>
+#include <map>
+#include <vector>
+
+#include "pimc_tables.hpp"
+
+namespace pimc {
+
+using SymMono = std::vector<uint8_t>;            // exponent of each symbol v_0..v_{J+1}
+using SymPoly = std::map<SymMono, double>;
+
+inline void sym_axpy(SymPoly& y, double a, const SymPoly& x) {
+    for (const auto& kv : x) {
+        auto it = y.find(kv.first);
+        if (it == y.end())
+            y.emplace(kv.first, a * kv.second);
+        else
+            it->second += a * kv.second;
+    }
+}
+
+inline SymPoly sym_mul(const SymPoly& a, const SymPoly& b) {
+    SymPoly out;
+    for (const auto& ka : a)
+        for (const auto& kb : b) {
+            SymMono m(ka.first.size());
+            for (size_t i = 0; i < m.size(); ++i) m[i] = uint8_t(ka.first[i] + kb.first[i]);
+            out[m] += ka.second * kb.second;
+        }
+    return out;
+}
+
+inline SymPoly sym_der(const SymPoly& a, int times = 1) {
+    SymPoly r = a;
+    for (int t = 0; t < times; ++t) {
+        SymPoly out;
+        for (const auto& kv : r)
+            for (size_t j = 0; j + 1 < kv.first.size(); ++j)
+                if (kv.first[j]) {
+                    SymMono m = kv.first;
+                    m[j] -= 1;
+                    m[j + 1] += 1;
+                    out[m] += kv.second * double(kv.first[j]);
+                }
+        r.swap(out);
+    }
+    return r;
+}
+
+struct SymCoefficients {
+    int p = 0;
+    int J = 0;                                   // highest derivative order, 2p - 2
+    std::vector<std::vector<SymPoly>> c;         // c[m][k]
+};
+
+// eq.(diagonal) then eq.(1Drec) for k = m-1..0 (Fig. 1), c_{0,0} = v_0.
+inline SymCoefficients symbolic_coefficients(int p) {
+    SymCoefficients C;
+    C.p = p;
+    C.J = 2 * p - 2;
+    const size_t nv = size_t(C.J) + 2;
+    C.c.assign(p, std::vector<SymPoly>(p));
+    SymMono v0(nv, 0);
+    v0[0] = 1;
+    C.c[0][0][v0] = 1.0;
+    std::vector<std::vector<SymPoly>> d1(p, std::vector<SymPoly>(p));
+    d1[0][0] = sym_der(C.c[0][0]);
+    double fact = 1.0;
+    for (int m = 1; m < p; ++m) {
+        fact *= double(2 * m) * double(2 * m + 1);
+        SymMono vm(nv, 0);
+        vm[size_t(2 * m)] = 1;
+        C.c[m][m][vm] = 1.0 / fact;
+        for (int k = m - 1; k >= 0; --k) {
+            SymPoly rhs;
+            sym_axpy(rhs, double((2 * k + 2) * (2 * k + 1)), C.c[m][k + 1]);
+            sym_axpy(rhs, 1.0, sym_der(C.c[m - 1][k], 2));
+            for (int l = 0; l <= m - 2; ++l)
+                for (int r = std::max(0, k - m + l + 2); r <= std::min(k, l); ++r)
+                    sym_axpy(rhs, -1.0, sym_mul(d1[l][r], d1[m - l - 2][k - r]));
+            for (int l = 1; l <= m - 2; ++l)
+                for (int r = std::max(0, k - m + l + 2); r <= std::min(k, l); ++r) {
+                    const int f = 2 * r * (2 * k - 2 * r + 2);
+                    if (f) sym_axpy(rhs, -double(f), sym_mul(C.c[l][r], C.c[m - l - 1][k - r + 1]));
+                }
+            SymPoly out;
+            for (const auto& kv : rhs)
+                if (kv.second != 0.0) out.emplace(kv.first, kv.second / double(8 * (m + k + 1)));
+            C.c[m][k].swap(out);
+        }
+        for (int k = 0; k <= m; ++k) d1[m][k] = sym_der(C.c[m][k]);
+    }
+    return C;
+}
+
+// Records of one level (eps = T/2^n): group k = the terms of dlt^(2k), coef = c_{m,k} eps^(m-k+1) 4^-k.
+inline void fold_symbolic(const SymCoefficients& C, double eps, std::vector<GenRecord>& recs,
+                          std::vector<uint32_t>& groups) {
+    groups.clear();
+    for (int k = 0; k < C.p; ++k) {
+        groups.push_back(uint32_t(recs.size()));
+        for (int m = k; m < C.p; ++m) {
+            const double scale = std::pow(eps, double(m - k + 1)) * std::ldexp(1.0, -2 * k);
+            for (const auto& kv : C.c[m][k]) {
+                GenRecord r{};
+                r.coef = kv.second * scale;
+                int nf = 0;
+                for (size_t j = 0; j < kv.first.size(); ++j)
+                    for (int e = 0; e < kv.first[j]; ++e) r.f[nf++] = uint8_t(j);
+                r.nf = uint8_t(nf);
+                recs.push_back(r);
+            }
+        }
+    }
+    groups.push_back(uint32_t(recs.size()));
+}
+
+// Derivative tables of a potential of this mode (after the mass rescaling).
+struct GenPotential {
+    int J = 0;
+    std::vector<double> poly;                    // c_n
+    std::vector<double> dpoly;                   // (J+1) rows x 9: coefficients of V^(j)
+    int pdeg = -1;
+    std::vector<double> sech_A, sech_a;          // terms A / cosh^2(a x)
+    std::vector<double> dsech;                   // per term (J+1) rows x (J+3): A a^j S_j
+    std::vector<double> gauss_B, gauss_b;        // terms B exp(-b x^2)
+};
+
+inline void gen_potential_tables(GenPotential& G) {
+    const int J = G.J;
+    G.pdeg = int(G.poly.size()) - 1;
+    G.dpoly.assign(size_t(J + 1) * 9, 0.0);
+    PolyD d = G.poly;
+    for (int j = 0; j <= J; ++j) {
+        for (size_t n = 0; n < d.size() && n < 9; ++n) G.dpoly[size_t(j) * 9 + n] = d[n];
+        d = poly_der(d);
+    }
+    G.dsech.assign(G.sech_A.size() * size_t(J + 1) * size_t(J + 3), 0.0);
+    for (size_t i = 0; i < G.sech_A.size(); ++i) {
+        PolyD S = {1.0, 0.0, -1.0};                             // S_0 = 1 - t^2
+        double scale = G.sech_A[i];
+        for (int j = 0; j <= J; ++j) {
+            double* row = G.dsech.data() + (i * size_t(J + 1) + size_t(j)) * size_t(J + 3);
+            for (size_t n = 0; n < S.size() && n < size_t(J + 3); ++n) row[n] = scale * S[n];
+            PolyD dS = poly_der(S);                             // S_{j+1} = (1 - t^2) S_j'
+            PolyD nx(dS.size() + 2, 0.0);
+            for (size_t n = 0; n < dS.size(); ++n) {
+                nx[n] += dS[n];
+                nx[n + 2] -= dS[n];
+            }
+            S = poly_trim(nx);
+            scale *= G.sech_a[i];
+        }
+    }
+}
+
+// v_j = V^(j)(x), j = 0..J (the device evaluates the same formulas).
+inline void gen_derivatives(const GenPotential& G, double x, double* v) {
+    const int J = G.J;
+    for (int j = 0; j <= J; ++j) {
+        const int dg = G.pdeg - j;
+        double acc = 0.0;
+        if (dg >= 0) {
+            acc = G.dpoly[size_t(j) * 9 + size_t(dg)];
+            for (int n = dg - 1; n >= 0; --n) acc = std::fma(acc, x, G.dpoly[size_t(j) * 9 + size_t(n)]);
+        }
+        v[j] = acc;
+    }
+    for (size_t i = 0; i < G.sech_A.size(); ++i) {
+        const double t = std::tanh(G.sech_a[i] * x);
+        for (int j = 0; j <= J; ++j) {
+            const double* row = G.dsech.data() + (i * size_t(J + 1) + size_t(j)) * size_t(J + 3);
+            double acc = row[j + 2];
+            for (int n = j + 1; n >= 0; --n) acc = std::fma(acc, t, row[n]);
+            v[j] += acc;
+        }
+    }
+    for (size_t i = 0; i < G.gauss_B.size(); ++i) {
+        // d^j/dx^j B e^{-b x^2} = B (-sqrt b)^j H_j(sqrt(b) x) e^{-b x^2}, H_{j+1} = 2y H_j - 2j H_{j-1}
+        const double sb = std::sqrt(G.gauss_b[i]);
+        const double y = sb * x;
+        double e = G.gauss_B[i] * std::exp(-G.gauss_b[i] * x * x);
+        double hm = 0.0, h = 1.0;
+        for (int j = 0; j <= J; ++j) {
+            v[j] += e * h;
+            const double hn = 2.0 * y * h - 2.0 * double(j) * hm;
+            hm = h;
+            h = hn;
+            e *= -sb;
+        }
+    }
+}
+
+// eps W_p of one slice from the folded records of a level.
+inline double gen_eval_slice(const GenPotential& G, const std::vector<GenRecord>& recs,
+                             const std::vector<uint32_t>& groups, double qa, double qb) {
+    const double x = 0.5 * (qa + qb);
+    const double dl = qb - qa;
+    const double z = dl * dl;
+    std::vector<double> v(size_t(G.J) + 1);
+    gen_derivatives(G, x, v.data());
+    const int K = int(groups.size()) - 1;
+    double acc = 0.0;
+    for (int k = K - 1; k >= 0; --k) {
+        double val = 0.0;
+        for (uint32_t r = groups[size_t(k)]; r < groups[size_t(k) + 1]; ++r) {
+            double t = recs[r].coef;
+            for (int f = 0; f < recs[r].nf; ++f) t *= v[recs[r].f[f]];
+            val += t;
+        }
+        acc = (k == K - 1) ? val : std::fma(acc, z, val);
+    }
+    return acc;
+}
+
+}  // namespace pimc

@@ -288,7 +288,12 @@ int stage_problem(pimc_ctx* c, const Problem& P, uint64_t seed, uint32_t stream,
     const size_t off_tab = 2 * nlev * 8;
     const size_t off_tab32 = off_tab + n_tab * 8;
     const size_t off_deg = (off_tab32 + n_tab * 4 + 15) & ~size_t(15);
-    const size_t total = off_deg + P.deg.size() * 4 + 16;
+    // general-potential mode: records, level offsets, derivative tables
+    const size_t off_rec = (off_deg + P.deg.size() * 4 + 15) & ~size_t(15);
+    const size_t off_grp = off_rec + P.gen_recs.size() * sizeof(GenRecord);
+    const size_t off_dpoly = (off_grp + P.gen_grp.size() * 4 + 15) & ~size_t(15);
+    const size_t off_dsech = off_dpoly + P.gen.dpoly.size() * 8;
+    const size_t total = off_dsech + P.gen.dsech.size() * 8 + 16;
     std::vector<unsigned char> host(total, 0);
     std::memcpy(host.data(), P.sig.data(), nlev * 8);
     std::memcpy(host.data() + off_shift, P.shift.data(), nlev * 8);
@@ -297,6 +302,10 @@ int stage_problem(pimc_ctx* c, const Problem& P, uint64_t seed, uint32_t stream,
         std::memcpy(host.data() + off_tab32, P.tab32.data(), n_tab * 4);
     }
     if (!P.deg.empty()) std::memcpy(host.data() + off_deg, P.deg.data(), P.deg.size() * 4);
+    if (!P.gen_recs.empty()) std::memcpy(host.data() + off_rec, P.gen_recs.data(), P.gen_recs.size() * sizeof(GenRecord));
+    if (!P.gen_grp.empty()) std::memcpy(host.data() + off_grp, P.gen_grp.data(), P.gen_grp.size() * 4);
+    if (!P.gen.dpoly.empty()) std::memcpy(host.data() + off_dpoly, P.gen.dpoly.data(), P.gen.dpoly.size() * 8);
+    if (!P.gen.dsech.empty()) std::memcpy(host.data() + off_dsech, P.gen.dsech.data(), P.gen.dsech.size() * 8);
     int st = ensure(c, &c->d_prm, &c->prm_bytes, total);
     if (st) return st;
     HIP_TRY(c, hipMemcpyAsync(c->d_prm, host.data(), total, hipMemcpyHostToDevice, c->stream));
@@ -314,6 +323,24 @@ int stage_problem(pimc_ctx* c, const Problem& P, uint64_t seed, uint32_t stream,
     A.a = P.a;
     A.b = P.b;
     A.alpha = P.alpha;
+    if (P.kind == EvalKind::General64) {
+        GenTables& g = A.gen;
+        g.rec = reinterpret_cast<const GenRecord*>(base + off_rec);
+        g.grp = reinterpret_cast<const uint32_t*>(base + off_grp);
+        g.K = P.p;
+        g.J = P.gen.J;
+        g.dpoly = reinterpret_cast<const double*>(base + off_dpoly);
+        g.pdeg = P.gen.pdeg;
+        g.dsech = reinterpret_cast<const double*>(base + off_dsech);
+        g.n_sech = int(P.gen.sech_A.size());
+        g.n_gauss = int(P.gen.gauss_B.size());
+        for (int i = 0; i < g.n_sech; ++i) g.sech_a[i] = P.gen.sech_a[size_t(i)];
+        for (int i = 0; i < g.n_gauss; ++i) {
+            g.gB[i] = P.gen.gauss_B[size_t(i)];
+            g.gb[i] = P.gen.gauss_b[size_t(i)];
+            g.gsb[i] = std::sqrt(P.gen.gauss_b[size_t(i)]);
+        }
+    }
     A.key.seed_lo = uint32_t(seed);
     A.key.seed_hi = uint32_t(seed >> 32);
     A.key.stream = stream;
@@ -349,7 +376,7 @@ int check_args(const pimc_potential* V, double m, double a, double b, double T, 
     return PIMC_OK;
 }
 
-const uint32_t kKnownFlags = PIMC_FP32_POLY | PIMC_HIERARCHY;
+extern const uint32_t kKnownFlags = PIMC_FP32_POLY | PIMC_HIERARCHY;
 
 // Estimation of every requested level of a built problem (the body shared by the potentials).
 int amplitude_core(pimc_ctx* c, const Problem& P, uint64_t n_samples, uint64_t seed, uint32_t stream, uint32_t flags,

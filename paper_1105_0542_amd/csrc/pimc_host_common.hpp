@@ -10,6 +10,7 @@
 
 #include "pimc.h"
 #include "pimc_internal.hpp"
+#include "pimc_general.hpp"
 
 struct pimc_ctx {
     int device = 0;
@@ -64,6 +65,10 @@ struct Problem {
     std::vector<double> shift;       // s+1
     double level0_action = 0.0;      // T W_p((a+b)/2, (b-a)/2; T)
     double alpha = 0.0;              // Poeschl-Teller: tables in u = tanh^2(alpha mid) (after the mass rescaling)
+    // general-potential mode
+    pimc::GenPotential gen;                  // derivative tables
+    std::vector<pimc::GenRecord> gen_recs;   // every level's records
+    std::vector<uint32_t> gen_grp;           // per level K+1 offsets into gen_recs
 };
 
 // Tables, bridge widths and straight-line reference actions of one problem after the mass
@@ -74,11 +79,23 @@ int build_problem(const pimc_potential* V, double m, double a, double b, double 
 // u = tanh^2(alpha' mid), alpha' = alpha/sqrt(m)).
 int build_problem_mpt(double lambda, double alpha, double m, double a, double b, double T, uint32_t N, int p,
                       uint32_t flags, Problem& P, char* why, size_t whylen);
+// The same for the general-potential mode (derivative symbols, p <= kGenMaxP).
+int build_problem_general(const pimc_general_potential* V, double m, double a, double b, double T, uint32_t N, int p,
+                          uint32_t flags, Problem& P, char* why, size_t whylen);
+int check_general(const pimc_general_potential* V, double m, double a, double b, double T, uint32_t N, int p,
+                  uint64_t n_samples);
+// Estimation / per-path actions of a built problem (shared by every potential family).
+int amplitude_core(pimc_ctx* c, const Problem& P, uint64_t n_samples, uint64_t seed, uint32_t stream, uint32_t flags,
+                   pimc_level_result* out);
+int path_actions_core(pimc_ctx* c, const Problem& P, uint64_t seed, uint32_t stream, uint32_t flags,
+                      uint64_t first_path, uint64_t k_paths, double* S_out);
+extern const uint32_t kKnownFlags;
 // Level result from the canonical sums (n, sum d, sum d^2, non-finite count) with d = w - 1 and
 // log prefactor logbase; true when the result is not finite.
 bool assemble_level(const double* red, double logbase, pimc_level_result& r);
 int check_args(const pimc_potential* V, double m, double a, double b, double T, uint32_t N, int p,
                uint64_t n_samples);
 uint32_t paths_per_lane(int s);
+int log2_exact(uint32_t N);
 
 }  // namespace pimc_host

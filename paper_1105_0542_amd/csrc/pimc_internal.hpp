@@ -20,6 +20,7 @@ struct AmpArgs {
     int gstride;                       // generic shape: doubles per level table
     double a, b;                       // endpoints (after the mass rescaling)
     double alpha;                      // Poeschl-Teller: tanh argument scale (after the mass rescaling)
+    GenTables gen;                     // general-potential mode: records and derivative tables
     const double* sig;                 // device: sigma_n = sqrt(T / 2^(n+1)), n = 0..s (0 unused)
     const double* shift;               // device: straight-line level action S_ref,n, n = 0..s
     RngKey key;
@@ -34,7 +35,7 @@ struct AmpArgs {
     double* dump;                      // device [path][s+1] or null
 };
 
-enum class EvalKind { Quartic64, Quartic32, GenericEven64, GenericOdd64, Tanh64 };
+enum class EvalKind { Quartic64, Quartic32, GenericEven64, GenericOdd64, Tanh64, General64 };
 
 // Dynamic LDS bytes of the estimation kernel: per lane, 3D+2 slots of the explicit stack; per wave
 // and level, three accumulators.

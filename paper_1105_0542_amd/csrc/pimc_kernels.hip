@@ -410,6 +410,15 @@ static hipError_t launch_tanh(const AmpArgs& A, int U, int grid, hipStream_t st)
     }
 }
 
+static hipError_t launch_general(const AmpArgs& A, int U, int grid, hipStream_t st) {
+    GeneralEval64 ev{A.gen};
+    switch (U) {
+        case 1: return launch_one<1>(A, ev, grid, st);
+        case 2: return launch_one<2>(A, ev, grid, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <int P>
 static hipError_t quartic_dispatch(const AmpArgs& A, bool fp32, int p, int grid, hipStream_t st) {
     if constexpr (P <= kMaxP) {
@@ -429,6 +438,7 @@ hipError_t launch_amplitude(const AmpArgs& A, EvalKind kind, int p, int U, int g
         case EvalKind::GenericEven64: return launch_generic<true>(A, U, grid, st);
         case EvalKind::GenericOdd64: return launch_generic<false>(A, U, grid, st);
         case EvalKind::Tanh64: return launch_tanh(A, U, grid, st);
+        case EvalKind::General64: return launch_general(A, U, grid, st);
     }
     return hipErrorInvalidValue;
 }
@@ -520,6 +530,9 @@ int amplitude_resident_blocks(EvalKind kind, int p, int U, size_t lds_bytes, int
                 case 3: return resident_one<3, TanhEval64>(lds_bytes, device);
                 default: return resident_one<4, TanhEval64>(lds_bytes, device);
             }
+        case EvalKind::General64:
+            return U == 1 ? resident_one<1, GeneralEval64>(lds_bytes, device)
+                          : resident_one<2, GeneralEval64>(lds_bytes, device);
     }
     return 256;
 }

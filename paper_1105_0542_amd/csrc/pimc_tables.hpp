@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstddef>
+#include <cstdint>
 #include <vector>
 
 namespace pimc {
@@ -47,6 +48,14 @@ inline PolyD poly_mul(const PolyD& a, const PolyD& b) {
         for (size_t j = 0; j < b.size(); ++j) r[i + j] += a[i] * b[j];
     return r;
 }
+
+// One monomial of a folded general-potential level: coef * prod_{i < nf} v[f[i]], v_j = V^(j)(mid).
+struct GenRecord {
+    double coef;
+    uint8_t nf;
+    uint8_t f[15];
+};
+static_assert(sizeof(GenRecord) == 24, "record layout");
 
 // c[m][k], 0 <= k <= m < p, FP64.
 struct Coefficients {

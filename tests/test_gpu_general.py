@@ -1,0 +1,111 @@
+"""GPU parity of the general-potential mode (derivative symbols) against the model-specific modes,
+the oracle (oracle/general.py, symbolic derivatives) and a DVR continuum reference.
+
+Tolerances: per-path level actions 1e-11 of max(1, |S|) -- the monomial sums of the derivative
+form and the folded tables of the model-specific forms are different FP64 evaluations of the same
+polynomial (cancellations between monomials cost a few digits more than Horner); amplitudes on
+identical samples 1e-9 relative; the continuum check within 5 MC standard errors.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import paper_1105_0542_amd as P
+from oracle import closed_forms as cf
+from oracle import general as og
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = P.Context()
+    yield c
+    c.close()
+
+
+def _close(got, ref, tol=1e-11):
+    err = np.abs(got - ref)
+    lim = tol * np.maximum(1.0, np.abs(ref))
+    assert np.all(err <= lim), (err / lim).max()
+
+
+@pytest.mark.parametrize("s,p,flags", [(5, 6, P.FLAG_HIERARCHY), (7, 8, 0), (2, 10, P.FLAG_HIERARCHY)])
+def test_polynomial_through_derivatives_equals_polynomial_mode(ctx, s, p, flags):
+    coefs = P.quartic(1.0, 10.0)
+    k = 1000
+    g = ctx.path_actions_general(1.0, 0.0, 1.0, 2.0, 1 << s, p, 4, 2, flags, 0, k, poly=coefs)
+    r = ctx.path_actions(coefs, 1.0, 0.0, 1.0, 2.0, 1 << s, p, 4, 2, flags, 0, k)
+    for n in (range(1, s + 1) if flags else [s]):
+        _close(g[:, n], r[:, n])
+
+
+def test_sech2_through_derivatives_equals_poeschl_teller_mode(ctx):
+    k = 1000
+    g = ctx.path_actions_general(1.3, -0.5, 0.5, 1.0, 64, 8, 9, 1, P.FLAG_HIERARCHY, 0, k, sech2=((-2.0, 1.2),))
+    r = ctx.path_actions_mpt(2.0, 1.2, 1.3, -0.5, 0.5, 1.0, 64, 8, 9, 1, P.FLAG_HIERARCHY, 0, k)
+    for n in range(1, 7):
+        _close(g[:, n], r[:, n])
+
+
+CASES = [  # m, a, b, T, s, p, poly, sech2, gauss
+    (1.0, -0.3, 0.4, 1.0, 5, 6, (0, 0, 0.5), (), ((2.0, 1.0),)),                        # barrier in an oscillator
+    (1.7, 0.2, -0.6, 0.5, 4, 8, (0.1, 0.2, 0.4, 0.0, 0.02), ((-1.0, 0.8),), ((0.5, 2.0), (-0.3, 0.5))),
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_path_actions_match_oracle(ctx, case):
+    m, a, b, T, s, p, poly, sech2, gauss = case
+    _log(f"general actions m={m} a={a} b={b} T={T} s={s} p={p} poly={poly} sech2={sech2} gauss={gauss}")
+    k = 600
+    got = ctx.path_actions_general(m, a, b, T, 1 << s, p, 3, 8, P.FLAG_HIERARCHY, 50, k, poly=poly, sech2=sech2,
+                                   gauss=gauss)
+    ref = og.path_actions(p, T, s, a, b, 3, 8, np.arange(50, 50 + k), poly=poly, sech2=sech2, gauss=gauss, m=m)
+    for n in range(1, s + 1):
+        _close(got[:, n], ref[:, n])
+
+
+def test_amplitude_matches_oracle_on_identical_samples(ctx):
+    m, a, b, T, s, p, poly, sech2, gauss = CASES[0]
+    n = 20000
+    res, _ = ctx.amplitude_general(m, a, b, T, 1 << s, p, n, 6, 0, P.FLAG_HIERARCHY, poly=poly, sech2=sech2,
+                                   gauss=gauss)
+    S = og.path_actions(p, T, s, a, b, 6, 0, np.arange(n), poly=poly, sech2=sech2, gauss=gauss, m=m)
+    import math
+    for lev in range(1, s + 1):
+        M = 1 << lev
+        q = a + (b - a) * np.arange(M + 1) / M
+        d = og.derivative_functions(p, poly, sech2, gauss, m)
+        ref_line = og.eps_W(p, T / M, d, 0.5 * (q[1:] + q[:-1]), 0.5 * (q[1:] - q[:-1])).sum()
+        w = np.expm1(-(S[:, lev] - ref_line))
+        K0 = math.exp(-(b - a) ** 2 / (2 * T)) / math.sqrt(2 * math.pi * T)
+        amp = K0 * math.exp(-ref_line) * (1 + math.fsum(w) / n)
+        assert res[lev].amp == pytest.approx(amp, rel=1e-9), lev
+
+
+def test_gaussian_barrier_converges_to_the_continuum(ctx):
+    """V = q^2/2 + 2 exp(-q^2): A(-0.3, 0.4; 1) at p = 8 against a DVR diagonalization of H."""
+    V = lambda x: 0.5 * x * x + 2.0 * np.exp(-x * x)
+    ref = cf.dvr_amplitude(V, -0.3, 0.4, 1.0, L=8.0, h=0.025 / 2.5)
+    res, _ = ctx.amplitude_general(1.0, -0.3, 0.4, 1.0, 256, 8, 2_000_000, 12, 0, P.FLAG_HIERARCHY,
+                                   poly=(0, 0, 0.5), gauss=((2.0, 1.0),))
+    _log(f"DVR {ref:.8f}; p=8 N=16..256: " + " ".join(f"{r.amp:.7f}+-{r.err:.1e}" for r in res[4:]))
+    for lev in range(4, 9):
+        assert abs(res[lev].amp - ref) <= 5 * res[lev].err, (lev, res[lev].amp, ref)
+
+
+def test_invalid_arguments(ctx):
+    with pytest.raises(P.PimcError):
+        ctx.amplitude_general(1.0, 0, 1, 1, 16, 11, 100, 1, poly=(0, 0, 0.5))       # p > 10
+    with pytest.raises(P.PimcError):
+        ctx.amplitude_general(1.0, 0, 1, 1, 16, 4, 100, 1, gauss=((1.0, -1.0),))     # beta <= 0
+    with pytest.raises(P.PimcError) as e:
+        ctx.amplitude_general(1.0, 0, 1, 1, 16, 4, 100, 1, 0, P.FLAG_FP32_POLY, poly=(0, 0, 0.5))
+    assert e.value.status == -2
