@@ -189,6 +189,31 @@ def mpt_section(P, ctx, dvr):
     return out
 
 
+def general_section(P, ctx):
+    """Cost of the general-potential (derivative-symbol) mode against the specialized quartic
+    kernel on the same problem, and a non-polynomial potential (Gaussian barrier in an oscillator);
+    p = 8, every level of s = 10, 1e7 samples."""
+    n, s, p = 10_000_000, 10, 8
+    rows = {}
+    coefs = P.quartic(1.0, 10.0)
+    res_q, _ = ctx.amplitude(coefs, 1.0, 0.0, 1.0, 1.0, 1 << s, p, n, 1, 0, P.FLAG_HIERARCHY)
+    ms_q = ctx.last_kernel_ms()
+    res_g, _ = ctx.amplitude_general(1.0, 0.0, 1.0, 1.0, 1 << s, p, n, 1, 0, P.FLAG_HIERARCHY, poly=coefs)
+    ms_g = ctx.last_kernel_ms()
+    sl = n * slices_per_sample(s, True)
+    rows["quartic_g10_specialized"] = {"slice_evals_per_s": sl / (ms_q / 1e3), "A_1024": res_q[s].amp,
+                                       "err": res_q[s].err}
+    rows["quartic_g10_general_mode"] = {"slice_evals_per_s": sl / (ms_g / 1e3), "A_1024": res_g[s].amp,
+                                        "err": res_g[s].err,
+                                        "rel_diff_vs_specialized": abs(res_g[s].amp - res_q[s].amp) / res_q[s].amp}
+    res_b, _ = ctx.amplitude_general(1.0, -0.3, 0.4, 1.0, 1 << s, p, n, 1, 0, P.FLAG_HIERARCHY, poly=(0, 0, 0.5),
+                                     gauss=((2.0, 1.0),))
+    ms_b = ctx.last_kernel_ms()
+    rows["gaussian_barrier"] = {"potential": "q^2/2 + 2 exp(-q^2), A(-0.3, 0.4; 1)",
+                                "slice_evals_per_s": sl / (ms_b / 1e3), "A_1024": res_b[s].amp, "err": res_b[s].err}
+    return {"workload": f"p={p}, s={s} (every level), {n:.0e} samples", **rows}
+
+
 def spectrum_section(P, ctx, dvr):
     """Matrix build (ALU: level-p Horner + exp per element) and Lanczos (HBM: one pass over the
     matrix per step) for the spectrum workloads; levels against the DVR reference when given."""
@@ -319,6 +344,7 @@ def main():
                     help="run only the timed p=18 sweep (for profiler runs): no other section, no cpu baseline")
     ap.add_argument("--only-proposal", action="store_true",
                     help="run only the proposal section (for profiler runs): no other section, no cpu baseline")
+    ap.add_argument("--only-general", action="store_true", help="run only the general-potential section")
     ap.add_argument("--only-mpt", action="store_true",
                     help="run only the Poeschl-Teller convergence section, with its DVR reference")
     ap.add_argument("--only-spectrum", action="store_true",
@@ -336,7 +362,7 @@ def main():
 
     # The oracle runs first, in worker processes forked before this process touches the GPU.
     skip_cpu = (args.no_cpu_baseline or args.only_headline or args.only_proposal or args.only_spectrum or
-                args.only_mpt)
+                args.only_mpt or args.only_general)
     cpu = None if skip_cpu else cpu_baseline(CPU_SAMPLE_PATHS)
     prec_ref = None if skip_cpu else oracle_precision_reference()
     spec_ref = None if (skip_cpu and not args.only_spectrum) else oracle_spectrum_reference()
@@ -356,6 +382,10 @@ def main():
         return
     if args.only_mpt:
         print(json.dumps({"mpt": mpt_section(P, ctx, mpt_ref)}), flush=True)
+        ctx.close()
+        return
+    if args.only_general:
+        print(json.dumps({"general": general_section(P, ctx)}), flush=True)
         ctx.close()
         return
     N = 1 << S_DEPTH
@@ -458,6 +488,7 @@ def main():
     flow_line = proposal_section(P, ctx, args.flow_steps) if args.flow_steps > 0 else None
     spec_line = spectrum_section(P, ctx, spec_ref)
     mpt_line = mpt_section(P, ctx, mpt_ref)
+    gen_line = general_section(P, ctx)
 
     line = {
         "metric": "slice-evals/s (p=18, FP64)",
@@ -499,6 +530,7 @@ def main():
         line["proposal"] = flow_line
     line["spectrum"] = spec_line
     line["mpt"] = mpt_line
+    line["general"] = gen_line
     if cpu is not None:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)

@@ -299,7 +299,7 @@ struct GenTables {
 
 // Lane-private derivative slots (one LDS array per kernel, whatever the batch widths used).
 __device__ __forceinline__ double* gen_slots() {
-    __shared__ double vbuf[(kGenMaxJ + 1) * kGenLanes];
+    __shared__ double vbuf[(kGenMaxJ + 2) * kGenLanes];
     return vbuf + threadIdx.x;
 }
 
@@ -349,16 +349,44 @@ struct GeneralEval64 {
                     e *= -g.gsb[t];
                 }
             }
+            v[(J + 1) * kGenLanes] = 1.0;
             double acc = 0.0;
             for (int k = g.K - 1; k >= 0; --k) {
-                double val = 0.0;
+                double val0 = 0.0, val1 = 0.0;
                 const uint32_t r1 = grp[k + 1];
-                for (uint32_t r = grp[k]; r < r1; ++r) {
-                    double t = rec[r].coef;
-                    const int nf = rec[r].nf;
-                    for (int f = 0; f < nf; ++f) t *= v[int(rec[r].f[f]) * kGenLanes];
-                    val += t;
+                uint32_t r = grp[k];
+                // two records at a time, four factors per step (padded with the slot holding 1)
+                for (; r + 1 < r1; r += 2) {
+                    double t0 = rec[r].coef, t1 = rec[r + 1].coef;
+                    const int n0 = rec[r].nf, n1 = rec[r + 1].nf;
+                    const int nmin = n0 < n1 ? n0 : n1;
+                    int f = 0;
+                    for (; f < nmin; f += 4) {
+                        const double a0 = v[int(rec[r].f[f]) * kGenLanes], a1 = v[int(rec[r].f[f + 1]) * kGenLanes];
+                        const double a2 = v[int(rec[r].f[f + 2]) * kGenLanes], a3 = v[int(rec[r].f[f + 3]) * kGenLanes];
+                        const double b0 = v[int(rec[r + 1].f[f]) * kGenLanes], b1 = v[int(rec[r + 1].f[f + 1]) * kGenLanes];
+                        const double b2 = v[int(rec[r + 1].f[f + 2]) * kGenLanes], b3 = v[int(rec[r + 1].f[f + 3]) * kGenLanes];
+                        t0 = t0 * a0 * a1 * a2 * a3;
+                        t1 = t1 * b0 * b1 * b2 * b3;
+                    }
+                    for (int f0 = f; f0 < n0; f0 += 4)
+                        t0 = t0 * v[int(rec[r].f[f0]) * kGenLanes] * v[int(rec[r].f[f0 + 1]) * kGenLanes] *
+                             v[int(rec[r].f[f0 + 2]) * kGenLanes] * v[int(rec[r].f[f0 + 3]) * kGenLanes];
+                    for (int f1 = f; f1 < n1; f1 += 4)
+                        t1 = t1 * v[int(rec[r + 1].f[f1]) * kGenLanes] * v[int(rec[r + 1].f[f1 + 1]) * kGenLanes] *
+                             v[int(rec[r + 1].f[f1 + 2]) * kGenLanes] * v[int(rec[r + 1].f[f1 + 3]) * kGenLanes];
+                    val0 += t0;
+                    val1 += t1;
                 }
+                if (r < r1) {
+                    double t0 = rec[r].coef;
+                    const int n0 = rec[r].nf;
+                    for (int f = 0; f < n0; f += 4)
+                        t0 = t0 * v[int(rec[r].f[f]) * kGenLanes] * v[int(rec[r].f[f + 1]) * kGenLanes] *
+                             v[int(rec[r].f[f + 2]) * kGenLanes] * v[int(rec[r].f[f + 3]) * kGenLanes];
+                    val0 += t0;
+                }
+                const double val = val0 + val1;
                 acc = (k == g.K - 1) ? val : fma(acc, z, val);
             }
             S += acc;

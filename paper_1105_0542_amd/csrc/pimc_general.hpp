@@ -122,6 +122,8 @@ inline void fold_symbolic(const SymCoefficients& C, double eps, std::vector<GenR
                 int nf = 0;
                 for (size_t j = 0; j < kv.first.size(); ++j)
                     for (int e = 0; e < kv.first[j]; ++e) r.f[nf++] = uint8_t(j);
+                // pad to a multiple of four factors with the slot that holds 1 (index J + 1)
+                while (nf % 4) r.f[nf++] = uint8_t(C.J + 1);
                 r.nf = uint8_t(nf);
                 recs.push_back(r);
             }
@@ -212,18 +214,21 @@ inline double gen_eval_slice(const GenPotential& G, const std::vector<GenRecord>
     const double x = 0.5 * (qa + qb);
     const double dl = qb - qa;
     const double z = dl * dl;
-    std::vector<double> v(size_t(G.J) + 1);
+    std::vector<double> v(size_t(G.J) + 2);
     gen_derivatives(G, x, v.data());
+    v[size_t(G.J) + 1] = 1.0;
     const int K = int(groups.size()) - 1;
     double acc = 0.0;
     for (int k = K - 1; k >= 0; --k) {
-        double val = 0.0;
+        double val[2] = {0.0, 0.0};                   // records alternate between two sums
         for (uint32_t r = groups[size_t(k)]; r < groups[size_t(k) + 1]; ++r) {
             double t = recs[r].coef;
-            for (int f = 0; f < recs[r].nf; ++f) t *= v[recs[r].f[f]];
-            val += t;
+            for (int f = 0; f < recs[r].nf; f += 4)
+                t = t * v[recs[r].f[f]] * v[recs[r].f[f + 1]] * v[recs[r].f[f + 2]] * v[recs[r].f[f + 3]];
+            val[(r - groups[size_t(k)]) & 1] += t;
         }
-        acc = (k == K - 1) ? val : std::fma(acc, z, val);
+        const double vk = val[0] + val[1];
+        acc = (k == K - 1) ? vk : std::fma(acc, z, vk);
     }
     return acc;
 }

@@ -49,7 +49,8 @@ inline PolyD poly_mul(const PolyD& a, const PolyD& b) {
     return r;
 }
 
-// One monomial of a folded general-potential level: coef * prod_{i < nf} v[f[i]], v_j = V^(j)(mid).
+// One monomial of a folded general-potential level: coef * prod_{i < nf} v[f[i]], v_j = V^(j)(mid);
+// nf is a multiple of 4, padded with the index of a slot that holds 1.
 struct GenRecord {
     double coef;
     uint8_t nf;
