@@ -330,7 +330,10 @@ int pimc_flow_amplitude(pimc_flow *flow, uint64_t n_samples, uint64_t seed, uint
  * with W~_p the level-p effective potential of V(y/sqrt(m)) (the mass rescaling above; the N = 1
  * amplitude of Sec. 4.2 at T = t)
  * approximates exp(-t H) on the grid; its largest eigenvalues are exp(-t E_n) and its eigenvectors
- * sample the eigenfunctions. No Monte Carlo is involved (N = 1 at level p). */
+ * sample the eigenfunctions. No Monte Carlo is involved (N = 1 at level p). Elements whose
+ * free-particle exponent m (x_j - x_i)^2 / (2t) exceeds 40 are exactly zero: the expansion of W_p in
+ * the half-deviation has a finite radius (Sec. 5), so there the truncated exponent may grow without
+ * bound while the true element is below exp(-40) of the free one. */
 #define PIMC_MAX_P_SHORT_TIME 21   /* highest level p for the short-time matrix                       */
 #define PIMC_MAX_GRID 65536        /* n <= 65536                                                      */
 #define PIMC_MAX_STATES 256        /* eigenpairs per call                                             */

@@ -9,9 +9,13 @@
 namespace pimc {
 
 constexpr int kMatCols = 4;           // matrix elements per thread (consecutive columns)
+constexpr double kGaussCut = 40.0;    // elements with (y_j - y_i)^2 / (2t) > kGaussCut are zero
 
 // Element (i, j): pref * exp(-(y_j - y_i)^2 / (2t) - t W_p((y_i + y_j)/2, (y_j - y_i)/2; t)) with
-// y = sqrt(m) x, x_i = -L + (i + 1/2) D, pref = D sqrt(m) / sqrt(2 pi t).
+// y = sqrt(m) x, x_i = -L + (i + 1/2) D, pref = D sqrt(m) / sqrt(2 pi t); exactly zero where the
+// free-particle exponent (y_j - y_i)^2 / (2t) exceeds kGaussCut. The expansion in the half-deviation
+// has a finite radius (Sec. 5), so far from the diagonal the truncated exponent may grow without
+// bound where the true amplitude is below exp(-kGaussCut) of the free one.
 template <bool EVEN>
 __global__ void __launch_bounds__(256) k_evolution_matrix(SpecTable tb, double L, double D, double sm, double t,
                                                           double pref, uint32_t n, double* __restrict__ M,
@@ -34,7 +38,8 @@ __global__ void __launch_bounds__(256) k_evolution_matrix(SpecTable tb, double L
     for (int c = 0; c < kMatCols; ++c) {
         if (j0 + c < n) {
             const double dl = qb[c] - qa[c];
-            row[j0 + c] = pref * exp(-(dl * dl) / (2.0 * t) - S[c]);
+            const double g = (dl * dl) / (2.0 * t);
+            row[j0 + c] = g > kGaussCut ? 0.0 : pref * exp(-g - S[c]);
         }
     }
 }

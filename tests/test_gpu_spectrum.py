@@ -63,6 +63,9 @@ def test_matrix_matches_oracle(ctx, case):
     assert torch.isnan(buf[:, n:]).all()                  # padding untouched
     ref, _, _ = osp.evolution_matrix(_exact(coefs), m, t, p, L, n)
     assert np.array_equal(got, got.T)                      # exactly symmetric
+    x, _ = osp.grid(L, n)
+    far = m * (x[None, :] - x[:, None]) ** 2 / (2.0 * t) > osp.GAUSS_CUT * (1 + 1e-12)
+    assert far.any() and np.all(got[far] == 0.0)           # the cutoff reading on both sides
     err = np.abs(got - ref)
     lim = 1e-12 * np.abs(ref) + 1e-14 * np.abs(ref).max()
     assert np.all(err <= lim), (err / np.maximum(lim, 1e-300)).max()
