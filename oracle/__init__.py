@@ -18,6 +18,14 @@ Transition Amplitudes via the Effective Action Approach", that it follows):
   of A_N^(p) for any potential, and a sinc-DVR continuum amplitude.
 * ``flow``             -- FP64 affine-coupling proposal (forward, log-det, weights, analytic
   gradient) used to check the GPU flow kernels.
+* ``spectrum``         -- the space-discretized evolution operator of short-time amplitudes and its
+  spectrum (the paper's application, Sec. 5 with Fig. 3).
+* ``mpt``              -- the modified Poeschl-Teller potential through the recursion in tanh(alpha x)
+  (Sec. 3.3, eq.(1D-MPT), eq.(1D-MPTansatz)).
+* ``general``          -- the general-potential mode: c_{m,k} as polynomials in the derivatives of V
+  (Sec. 3.1/3.2).
+* ``vector``           -- several coordinates (Sec. 2.2): eq.(MBrec)/(DIA) component by component and
+  in the rotational invariants, paths in d dimensions, a two-dimensional DVR continuum.
 
 Parity status of every function is stated in its module header.
 """

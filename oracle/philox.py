@@ -77,13 +77,16 @@ def uniforms(seed: int, stream: int, path, pair):
     return odd53(o0, o1), odd53(o2, o3)
 
 
-def node_normals(seed: int, stream: int, path, node):
+def node_normals(seed: int, stream: int, path, node, pair_offset: int = 0):
     """Standard normal z_h for heap node(s) ``node`` (h >= 1) of path(s) ``path``.
 
     Box-Muller on the call's uniform pair; even h takes the cosine output, odd h the sine output.
+    ``pair_offset`` is added to the generator call index (h >> 1): coordinate c of a path in several
+    dimensions draws with offset c * 2^20, above every call index of a one-dimensional path
+    (N <= 2^20), so coordinate 0 is the one-dimensional draw.
     """
     node = np.asarray(node, dtype=np.uint64)
-    u1, u2 = uniforms(seed, stream, path, node >> np.uint64(1))
+    u1, u2 = uniforms(seed, stream, path, (node >> np.uint64(1)) + np.uint64(pair_offset))
     r = np.sqrt(-2.0 * np.log(u1))
     theta = 2.0 * np.pi * u2
     node_b = np.broadcast_to(node, r.shape)
