@@ -196,6 +196,46 @@ int pimc_path_actions_general(pimc_ctx *ctx, const pimc_general_potential *V, do
                               double T, uint32_t N, int p, uint64_t seed, uint32_t stream, uint32_t flags,
                               uint64_t first_path, uint64_t k_paths, double *S_out);
 
+/* ---- several coordinates: rotation-invariant potentials (Sec. 2.2) ----------------------------
+ *
+ * d = D*M coordinates (D dimensions, M particles, no quantum statistics) with
+ *     V(q) = sum_{n <= degree} coef[n] (q.q)^n,   q in R^d
+ * (the 2D anharmonic oscillator of Sec. 3.3 is d = 2, coef = {0, A/2, g/24}). The short-time
+ * amplitude is (2 pi eps)^(-d/2) exp(-(2/eps) xbar.xbar - eps W) with W = sum_{m<p} sum_k eps^(m-k)
+ * W_{m,k}, the full contractions of eq.(EXP); W_{m,k} follow from eq.(MBrec) and eq.(DIA), run on
+ * polynomials in the invariants u = x.x, w = x.xbar, z = xbar.xbar. Paths: d independent bisection
+ * bridges; coordinate c of heap node h takes the normal of Philox call (h >> 1) + c * 2^20 (so
+ * coordinate 0 is the one-dimensional path of the same seed, stream and index). Mass m: coordinates
+ * times sqrt(m), coef[n] times m^(-n), amplitude times m^(d/2).
+ * a and b: host arrays of dim doubles. FP64 only (PIMC_FP32_POLY returns EUNSUPPORTED); outputs,
+ * flags and errors as pimc_amplitude / pimc_path_actions. EINVAL: dim outside 1..PIMC_MAX_DIM,
+ * degree outside 0..PIMC_MAX_RADIAL_DEGREE, non-finite coefficients or endpoints, and the conditions
+ * of pimc_amplitude. */
+#define PIMC_MAX_DIM 3
+#define PIMC_MAX_RADIAL_DEGREE 2   /* up to (q.q)^2: the anharmonic-oscillator family               */
+
+typedef struct {
+    int dim;                               /* d = D*M, 1..PIMC_MAX_DIM                              */
+    int degree;                            /* 0..PIMC_MAX_RADIAL_DEGREE                             */
+    double coef[PIMC_MAX_RADIAL_DEGREE + 1];
+} pimc_radial_potential;
+
+int pimc_amplitude_radial(pimc_ctx *ctx, const pimc_radial_potential *V, double m, const double *a,
+                          const double *b, double T, uint32_t N, int p, uint64_t n_samples, uint64_t seed,
+                          uint32_t stream, uint32_t flags, pimc_level_result *out);
+int pimc_path_actions_radial(pimc_ctx *ctx, const pimc_radial_potential *V, double m, const double *a,
+                             const double *b, double T, uint32_t N, int p, uint64_t seed, uint32_t stream,
+                             uint32_t flags, uint64_t first_path, uint64_t k_paths, double *S_out);
+/* Folded table of one level (eps = T/2^level, after the mass rescaling), unscaled: with
+ * eps W_p = sum_{k,j} (x.xbar)^(2j) (xbar.xbar)^(k-j) Q_{k,j}(x.x), group g holds Q_{k,j} for
+ * k = shape[3g], j = shape[3g+1], with shape[3g+2] coefficients (highest power of x.x first), stored
+ * consecutively in out. Groups are listed for j from high to low and, within j, k from high to low
+ * (the order in which the kernels consume them). *n_groups and *n_out are set; EINVAL if cap or
+ * shape_cap (ints) is too small. No device work. */
+int pimc_level_table_radial(const pimc_radial_potential *V, double m, double T, int p, uint32_t level,
+                            double *out, size_t cap, size_t *n_out, int *shape, size_t shape_cap,
+                            int *n_groups);
+
 /* ---- batches: whole grids of endpoints with mixed N, p, T in one graph launch ------------------- */
 
 /* One amplitude of a batch: potential systems[system] with mass m, A_N^(p)(a, b; T) estimated from

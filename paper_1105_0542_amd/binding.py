@@ -76,6 +76,34 @@ class Mpt(C.Structure):
     _fields_ = [("lambda_", C.c_double), ("alpha", C.c_double)]
 
 
+MAX_DIM = 3
+MAX_RADIAL_DEGREE = 2
+
+
+class RadialPotential(C.Structure):
+    _fields_ = [("dim", C.c_int), ("degree", C.c_int), ("coef", C.c_double * (MAX_RADIAL_DEGREE + 1))]
+
+
+def radial_potential(coefs, dim):
+    """pimc_radial_potential for V = sum_n coefs[n] (q.q)^n in `dim` coordinates."""
+    coefs = list(coefs)
+    if not coefs or len(coefs) > MAX_RADIAL_DEGREE + 1:
+        raise ValueError(f"radial potential needs 1..{MAX_RADIAL_DEGREE + 1} coefficients")
+    V = RadialPotential()
+    V.dim = int(dim)
+    V.degree = len(coefs) - 1
+    for n in range(MAX_RADIAL_DEGREE + 1):
+        V.coef[n] = float(coefs[n]) if n < len(coefs) else 0.0
+    return V
+
+
+def _vec(x, dim):
+    x = [float(v) for v in x]
+    if len(x) != dim:
+        raise ValueError(f"endpoint needs {dim} coordinates")
+    return (C.c_double * dim)(*x)
+
+
 class FlowConfig(C.Structure):
     _fields_ = [("layers", C.c_int), ("batch", C.c_uint32), ("lr", C.c_double), ("beta", C.c_double),
                 ("init_seed", C.c_uint64), ("init_scale", C.c_double)]
@@ -203,6 +231,18 @@ def load_library():
     lib.pimc_level_table_mpt.restype = C.c_int
     lib.pimc_level_table_mpt.argtypes = [P(Mpt), C.c_double, C.c_double, C.c_int, C.c_uint32, P(C.c_double),
                                          C.c_size_t, P(C.c_size_t), P(C.c_int), P(C.c_int)]
+    lib.pimc_amplitude_radial.restype = C.c_int
+    lib.pimc_amplitude_radial.argtypes = [vp, P(RadialPotential), C.c_double, P(C.c_double), P(C.c_double),
+                                          C.c_double, C.c_uint32, C.c_int, C.c_uint64, C.c_uint64, C.c_uint32,
+                                          C.c_uint32, P(_LevelResult)]
+    lib.pimc_path_actions_radial.restype = C.c_int
+    lib.pimc_path_actions_radial.argtypes = [vp, P(RadialPotential), C.c_double, P(C.c_double), P(C.c_double),
+                                             C.c_double, C.c_uint32, C.c_int, C.c_uint64, C.c_uint32, C.c_uint32,
+                                             C.c_uint64, C.c_uint64, P(C.c_double)]
+    lib.pimc_level_table_radial.restype = C.c_int
+    lib.pimc_level_table_radial.argtypes = [P(RadialPotential), C.c_double, C.c_double, C.c_int, C.c_uint32,
+                                            P(C.c_double), C.c_size_t, P(C.c_size_t), P(C.c_int), C.c_size_t,
+                                            P(C.c_int)]
     lib.pimc_amplitude_general.restype = C.c_int
     lib.pimc_amplitude_general.argtypes = [vp, P(GeneralPotential), C.c_double, C.c_double, C.c_double, C.c_double,
                                            C.c_uint32, C.c_int, C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32,
@@ -279,6 +319,22 @@ def level_table_mpt(lam, alpha, m, T, p, level):
     if st != PIMC_OK:
         raise _err(lib, None, st)
     return out, [deg[k] for k in range(nk.value)]
+
+
+def level_table_radial(coefs, dim, m, T, p, level):
+    """(coef array, [(k, j, len) per group]) of pimc_level_table_radial (host-only call)."""
+    lib = load_library()
+    V = radial_potential(coefs, dim)
+    need = C.c_size_t(0)
+    ng = C.c_int(0)
+    lib.pimc_level_table_radial(C.byref(V), m, T, p, level, None, 0, C.byref(need), None, 0, C.byref(ng))
+    out = np.zeros(need.value, dtype=np.float64)
+    shape = (C.c_int * (3 * ng.value))()
+    st = lib.pimc_level_table_radial(C.byref(V), m, T, p, level, out.ctypes.data_as(C.POINTER(C.c_double)),
+                                     out.size, C.byref(need), shape, 3 * ng.value, C.byref(ng))
+    if st != PIMC_OK:
+        raise _err(lib, None, st)
+    return out, [(shape[3 * g], shape[3 * g + 1], shape[3 * g + 2]) for g in range(ng.value)]
 
 
 def _torch_stream_handle() -> Optional[int]:
@@ -368,6 +424,26 @@ class Context:
         out = np.zeros((k_paths, s + 1), dtype=np.float64)
         self._check(self.lib.pimc_path_actions_general(self.h, C.byref(V), m, a, b, T, N, p, seed, stream, flags,
                                                        first_path, k_paths, out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
+
+    def amplitude_radial(self, coefs, dim, m, a, b, T, N, p, n_samples, seed, stream=0, flags=0):
+        """pimc_amplitude_radial (V = sum_n coefs[n] (q.q)^n, q in R^dim) -> (list of LevelResult, status)."""
+        V = radial_potential(coefs, dim)
+        s = int(N).bit_length() - 1
+        out = (_LevelResult * (s + 1))()
+        st = self._check(self.lib.pimc_amplitude_radial(self.h, C.byref(V), m, _vec(a, dim), _vec(b, dim), T, N, p,
+                                                        n_samples, seed, stream, flags, out))
+        res = [LevelResult(r.amp, r.err, r.log_amp, r.relvar, r.ess, int(r.n), int(r.n_nonfinite)) for r in out]
+        return res, st
+
+    def path_actions_radial(self, coefs, dim, m, a, b, T, N, p, seed, stream, flags, first_path, k_paths):
+        """pimc_path_actions_radial -> array [k_paths, s+1]."""
+        V = radial_potential(coefs, dim)
+        s = int(N).bit_length() - 1
+        out = np.zeros((k_paths, s + 1), dtype=np.float64)
+        self._check(self.lib.pimc_path_actions_radial(self.h, C.byref(V), m, _vec(a, dim), _vec(b, dim), T, N, p,
+                                                      seed, stream, flags, first_path, k_paths,
+                                                      out.ctypes.data_as(C.POINTER(C.c_double))))
         return out
 
     def path_actions_mpt(self, lam, alpha, m, a, b, T, N, p, seed, stream, flags, first_path, k_paths):

@@ -16,10 +16,12 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpimc.so")
 CLI = os.path.join(PKG, "pimc")
 
-SOURCES = ["pimc_host.cpp", "pimc_flow_host.cpp", "pimc_spectrum_host.cpp", "pimc_general_host.cpp", "pimc_kernels.hip", "pimc_flow.hip",
-           "pimc_spectrum.hip"]
+SOURCES = ["pimc_kernels.hip", "pimc_vector_d2.hip", "pimc_vector_d3.hip", "pimc_flow.hip", "pimc_spectrum.hip",
+           "pimc_vector_d1.hip", "pimc_host.cpp", "pimc_flow_host.cpp", "pimc_spectrum_host.cpp",
+           "pimc_general_host.cpp", "pimc_vector_host.cpp"]
 HEADERS = ["pimc_tables.hpp", "pimc_device.hpp", "pimc_internal.hpp", "pimc_math.hpp", "pimc_flow.hpp",
-           "pimc_host_common.hpp", "pimc_spectrum.hpp", "pimc_general.hpp"]
+           "pimc_host_common.hpp", "pimc_spectrum.hpp", "pimc_general.hpp", "pimc_vector.hpp",
+           "pimc_vector_impl.hpp"]
 
 # -ffp-contract=off: every fused multiply-add in the kernels is written as fma(); no other
 # expression is contracted, so the arithmetic is exactly what the source states.

@@ -1,0 +1,583 @@
+// Host side of the several-coordinate entry points (pimc_amplitude_radial, pimc_path_actions_radial,
+// pimc_level_table_radial in include/pimc.h): eq.(MBrec)/(DIA) on polynomials in the invariants
+// u = x.x, w = x.xbar, z = xbar.xbar (FP64), the per-level fold into the layout of pimc_vector.hpp,
+// the straight-line reference actions, and the estimation through the vector kernels.
+//
+// Invariant forms of the operators in d dimensions (partial derivatives in u, w, z; chain rule with
+// grad u = 2x, grad w = xbar, gradbar w = x, gradbar z = 2 xbar):
+//     grad^2 f            = 2d f_u + 4u f_uu + 4w f_uw + z f_ww
+//     gradbar^2 f         = 2d f_z + 4z f_zz + 4w f_wz + u f_ww
+//     grad f . grad g     = 4u f_u g_u + 2w (f_u g_w + f_w g_u) + z f_w g_w
+//     gradbar f . gradbar g = u f_w g_w + 2w (f_w g_z + f_z g_w) + 4z f_z g_z
+//     xbar . grad f       = 2w f_u + z f_w
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <iterator>
+#include <map>
+#include <vector>
+
+#include "pimc.h"
+#include "pimc_host_common.hpp"
+#include "pimc_vector.hpp"
+
+using namespace pimc;
+using namespace pimc_host;
+
+static_assert(PIMC_MAX_DIM == kVecMaxDim, "dimension limit of the public header");
+static_assert(PIMC_MAX_RADIAL_DEGREE == 2, "the table shape bound covers u-degree <= 2");
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+using IKey = std::array<int, 3>;                 // exponents of u, w, z
+using IPoly = std::map<IKey, double>;
+
+void axpy(IPoly& y, double a, const IPoly& x) {
+    for (const auto& kv : x) y[kv.first] += a * kv.second;
+}
+
+IPoly der(const IPoly& f, int var) {
+    IPoly out;
+    for (const auto& kv : f)
+        if (kv.first[size_t(var)]) {
+            IKey k = kv.first;
+            k[size_t(var)] -= 1;
+            out[k] += kv.second * double(kv.first[size_t(var)]);
+        }
+    return out;
+}
+
+IPoly times(const IPoly& f, int var, double s) {
+    IPoly out;
+    for (const auto& kv : f) {
+        IKey k = kv.first;
+        k[size_t(var)] += 1;
+        out[k] = kv.second * s;
+    }
+    return out;
+}
+
+IPoly mul(const IPoly& a, const IPoly& b) {
+    IPoly out;
+    for (const auto& ka : a)
+        for (const auto& kb : b)
+            out[IKey{ka.first[0] + kb.first[0], ka.first[1] + kb.first[1], ka.first[2] + kb.first[2]}] +=
+                ka.second * kb.second;
+    return out;
+}
+
+constexpr int U_ = 0, W_ = 1, Z_ = 2;
+
+IPoly lap(const IPoly& f, int d) {
+    const IPoly fu = der(f, U_), fw = der(f, W_);
+    IPoly out;
+    axpy(out, 2.0 * d, fu);
+    axpy(out, 1.0, times(der(fu, U_), U_, 4.0));
+    axpy(out, 1.0, times(der(fu, W_), W_, 4.0));
+    axpy(out, 1.0, times(der(fw, W_), Z_, 1.0));
+    return out;
+}
+
+IPoly lapbar(const IPoly& f, int d) {
+    const IPoly fz = der(f, Z_), fw = der(f, W_);
+    IPoly out;
+    axpy(out, 2.0 * d, fz);
+    axpy(out, 1.0, times(der(fz, Z_), Z_, 4.0));
+    axpy(out, 1.0, times(der(fz, W_), W_, 4.0));
+    axpy(out, 1.0, times(der(fw, W_), U_, 1.0));
+    return out;
+}
+
+IPoly gdot(const IPoly& f, const IPoly& g) {
+    const IPoly fu = der(f, U_), fw = der(f, W_), gu = der(g, U_), gw = der(g, W_);
+    IPoly out = times(mul(fu, gu), U_, 4.0);
+    IPoly cross = mul(fu, gw);
+    axpy(cross, 1.0, mul(fw, gu));
+    axpy(out, 1.0, times(cross, W_, 2.0));
+    axpy(out, 1.0, times(mul(fw, gw), Z_, 1.0));
+    return out;
+}
+
+IPoly gbdot(const IPoly& f, const IPoly& g) {
+    const IPoly fz = der(f, Z_), fw = der(f, W_), gz = der(g, Z_), gw = der(g, W_);
+    IPoly out = times(mul(fw, gw), U_, 1.0);
+    IPoly cross = mul(fw, gz);
+    axpy(cross, 1.0, mul(fz, gw));
+    axpy(out, 1.0, times(cross, W_, 2.0));
+    axpy(out, 1.0, times(mul(fz, gz), Z_, 4.0));
+    return out;
+}
+
+IPoly xbar_grad(const IPoly& f) {
+    IPoly out = times(der(f, U_), W_, 2.0);
+    axpy(out, 1.0, times(der(f, W_), Z_, 1.0));
+    return out;
+}
+
+void prune(IPoly& f) {
+    for (auto it = f.begin(); it != f.end();)
+        it = (it->second == 0.0) ? f.erase(it) : std::next(it);
+}
+
+// W[m][k], 0 <= k <= m <= p-1: eq.(DIA) on the diagonal, then eq.(MBrec) for k = m-1..0 (Fig. 1).
+std::vector<std::vector<IPoly>> radial_coefficients(const std::vector<double>& a, int d, int p) {
+    std::vector<std::vector<IPoly>> W(static_cast<size_t>(p), std::vector<IPoly>(static_cast<size_t>(p)));
+    IPoly V;
+    for (size_t n = 0; n < a.size(); ++n)
+        if (a[n] != 0.0) V[IKey{int(n), 0, 0}] = a[n];
+    W[0][0] = V;
+    double fact = 1.0;
+    for (int m = 1; m < p; ++m) {
+        fact *= double(2 * m) * double(2 * m + 1);
+        IPoly t = V;
+        for (int i = 0; i < 2 * m; ++i) t = xbar_grad(t);
+        IPoly diag;
+        axpy(diag, 1.0 / fact, t);
+        prune(diag);
+        W[size_t(m)][size_t(m)] = diag;
+        for (int k = m - 1; k >= 0; --k) {
+            IPoly rhs = lap(W[size_t(m - 1)][size_t(k)], d);
+            axpy(rhs, 1.0, lapbar(W[size_t(m)][size_t(k + 1)], d));
+            for (int l = 0; l <= m - 2; ++l)
+                for (int r = std::max(0, k - m + l + 2); r <= std::min(k, l); ++r)
+                    axpy(rhs, -1.0, gdot(W[size_t(l)][size_t(r)], W[size_t(m - l - 2)][size_t(k - r)]));
+            for (int l = 1; l <= m - 2; ++l)
+                for (int r = std::max(0, k - m + l + 2); r <= std::min(k, l); ++r)
+                    axpy(rhs, -1.0, gbdot(W[size_t(l)][size_t(r)], W[size_t(m - l - 1)][size_t(k - r + 1)]));
+            IPoly out;
+            axpy(out, 1.0 / double(8 * (m + k + 1)), rhs);
+            prune(out);
+            W[size_t(m)][size_t(k)] = out;
+        }
+    }
+    return W;
+}
+
+struct Group {
+    int j, l, len, off;
+};
+
+// Groups of the layout in consumption order.
+std::vector<Group> layout_groups(int p) {
+    std::vector<Group> g;
+    int off = 0;
+    for (int j = radial_nj(p) - 1; j >= 0; --j)
+        for (int l = radial_nl(p, j) - 1; l >= 0; --l) {
+            const int len = radial_len(p, j + l, j);
+            g.push_back(Group{j, l, len, off});
+            off += len;
+        }
+    return g;
+}
+
+// The level table at eps (unscaled, consumption order, highest power of u first); false if a
+// coefficient falls outside the shape bound.
+bool fold_radial(const std::vector<std::vector<IPoly>>& W, int p, double eps, std::vector<double>& tab) {
+    const std::vector<Group> groups = layout_groups(p);
+    tab.assign(size_t(radial_size(p)), 0.0);
+    std::map<std::pair<int, int>, const Group*> where;
+    for (const Group& g : groups) where[{g.j + g.l, g.j}] = &g;
+    for (int m = 0; m < p; ++m)
+        for (int k = 0; k <= m; ++k) {
+            const double f = std::pow(eps, double(m - k + 1));
+            for (const auto& kv : W[size_t(m)][size_t(k)]) {
+                const int i = kv.first[0], jw = kv.first[1], lz = kv.first[2];
+                if (jw % 2 != 0 || jw / 2 + lz != k) return false;
+                auto it = where.find({k, jw / 2});
+                if (it == where.end() || i >= it->second->len) return false;
+                const Group& g = *it->second;
+                tab[size_t(g.off + g.len - 1 - i)] += kv.second * f;
+            }
+        }
+    return true;
+}
+
+// eps W_p of one slice from an unscaled table (the kernels' order: Horner in u, z, w^2).
+double eval_slice(const std::vector<double>& tab, int p, const double* x, const double* xb, int d) {
+    double u = 0.0, w = 0.0, z = 0.0;
+    for (int c = 0; c < d; ++c) {
+        u = std::fma(x[c], x[c], u);
+        w = std::fma(x[c], xb[c], w);
+        z = std::fma(xb[c], xb[c], z);
+    }
+    const double w2 = w * w;
+    const int nj = radial_nj(p);
+    size_t off = 0;
+    double acc = 0.0;
+    for (int j = nj - 1; j >= 0; --j) {
+        const int nl = radial_nl(p, j);
+        double zs = 0.0;
+        for (int l = nl - 1; l >= 0; --l) {
+            const int len = radial_len(p, j + l, j);
+            double v = 0.0;
+            if (len > 0) {
+                v = tab[off];
+                for (int e = 1; e < len; ++e) v = std::fma(v, u, tab[off + size_t(e)]);
+            }
+            off += size_t(len);
+            zs = (l == nl - 1) ? v : std::fma(zs, z, v);
+        }
+        acc = (j == nj - 1) ? zs : std::fma(acc, w2, zs);
+    }
+    return acc;
+}
+
+// Device copy: coefficient of u^i (w^2)^j z^l times 4^-(i + 2j + l).
+std::vector<double> scale_for_sums(const std::vector<double>& tab, int p) {
+    std::vector<double> out = tab;
+    for (const Group& g : layout_groups(p))
+        for (int e = 0; e < g.len; ++e) {
+            const int i = g.len - 1 - e;
+            out[size_t(g.off + e)] = std::ldexp(tab[size_t(g.off + e)], -2 * (i + 2 * g.j + g.l));
+        }
+    return out;
+}
+
+std::vector<int> shape_array(int p) {
+    const int nj = radial_nj(p);
+    std::vector<int> sh{nj};
+    for (int j = 0; j < nj; ++j) sh.push_back(radial_nl(p, j));
+    for (const Group& g : layout_groups(p)) sh.push_back(g.len);
+    return sh;
+}
+
+struct VecProblem {
+    int dim = 1, s = 0, p = 1, U = 0, D = 0;
+    bool specialized = false;
+    double a[kVecMaxDim] = {0, 0, 0}, b[kVecMaxDim] = {0, 0, 0};
+    double T = 0, pref = 1.0, K0 = 0.0;
+    int stride = 0;
+    std::vector<double> tab, tab_dev;            // (s+1) * stride
+    std::vector<int> shape;
+    std::vector<double> sig, shift;
+    double level0_action = 0.0;
+};
+
+int check_radial(const pimc_radial_potential* V, double m, const double* a, const double* b, double T, uint32_t N,
+                 int p, uint64_t n_samples) {
+    if (!V) { set_thread_error("potential is NULL"); return PIMC_EINVAL; }
+    if (V->dim < 1 || V->dim > PIMC_MAX_DIM) {
+        set_thread_error("dim = %d outside 1..%d", V->dim, PIMC_MAX_DIM);
+        return PIMC_EINVAL;
+    }
+    if (V->degree < 0 || V->degree > PIMC_MAX_RADIAL_DEGREE) {
+        set_thread_error("radial degree %d outside 0..%d", V->degree, PIMC_MAX_RADIAL_DEGREE);
+        return PIMC_EINVAL;
+    }
+    for (int n = 0; n <= V->degree; ++n)
+        if (!std::isfinite(V->coef[n])) { set_thread_error("coefficient %d is not finite", n); return PIMC_EINVAL; }
+    if (!a || !b) { set_thread_error("endpoint array is NULL"); return PIMC_EINVAL; }
+    for (int c = 0; c < V->dim; ++c)
+        if (!std::isfinite(a[c]) || !std::isfinite(b[c])) { set_thread_error("endpoints must be finite"); return PIMC_EINVAL; }
+    pimc_potential zero{};
+    return check_args(&zero, m, 0.0, 0.0, T, N, p, n_samples);
+}
+
+std::vector<double> rescaled(const pimc_radial_potential* V, double m) {
+    std::vector<double> a(size_t(V->degree) + 1);
+    for (int n = 0; n <= V->degree; ++n) a[size_t(n)] = V->coef[n] * std::pow(1.0 / m, double(n));
+    return a;
+}
+
+int build_vector_problem(const pimc_radial_potential* V, double m, const double* a, const double* b, double T,
+                         uint32_t N, int p, uint32_t flags, VecProblem& P, char* why, size_t whylen) {
+    if (flags & PIMC_FP32_POLY) {
+        std::snprintf(why, whylen, "the several-coordinate kernels evaluate in FP64 only");
+        return PIMC_EUNSUPPORTED;
+    }
+    P.dim = V->dim;
+    P.s = log2_exact(N);
+    P.p = p;
+    P.T = T;
+    const double sm = std::sqrt(m);
+    double r2 = 0.0;
+    for (int c = 0; c < P.dim; ++c) {
+        P.a[c] = a[c] * sm;
+        P.b[c] = b[c] * sm;
+        r2 += (P.b[c] - P.a[c]) * (P.b[c] - P.a[c]);
+    }
+    P.pref = std::pow(sm, double(P.dim));
+    P.K0 = std::exp(-r2 / (2.0 * T)) / std::pow(2.0 * kPi * T, 0.5 * double(P.dim));
+    P.U = std::min(P.s, kVecU);
+    P.D = P.s - P.U;
+    P.specialized = (P.dim >= 2 && P.U == kVecU);
+    const auto W = radial_coefficients(rescaled(V, m), P.dim, p);
+    P.stride = radial_size(p);
+    P.tab.assign(size_t(P.s + 1) * size_t(P.stride), 0.0);
+    P.tab_dev.assign(P.tab.size(), 0.0);
+    P.shift.assign(size_t(P.s + 1), 0.0);
+    std::vector<double> lt;
+    for (int n = 0; n <= P.s; ++n) {
+        if (!fold_radial(W, p, std::ldexp(T, -n), lt)) {
+            std::snprintf(why, whylen, "internal: a coefficient falls outside the radial table shape");
+            return PIMC_EUNSUPPORTED;
+        }
+        std::copy(lt.begin(), lt.end(), P.tab.begin() + size_t(n) * size_t(P.stride));
+        const std::vector<double> sc = scale_for_sums(lt, p);
+        std::copy(sc.begin(), sc.end(), P.tab_dev.begin() + size_t(n) * size_t(P.stride));
+        // straight line q_k = a + (b - a) k / 2^n
+        const int M = 1 << n;
+        double S = 0.0;
+        for (int k = 0; k < M; ++k) {
+            double x[kVecMaxDim], xb[kVecMaxDim];
+            for (int c = 0; c < P.dim; ++c) {
+                const double q0 = P.a[c] + (P.b[c] - P.a[c]) * double(k) / double(M);
+                const double q1 = P.a[c] + (P.b[c] - P.a[c]) * double(k + 1) / double(M);
+                x[c] = 0.5 * (q0 + q1);
+                xb[c] = 0.5 * (q1 - q0);
+            }
+            S += eval_slice(lt, p, x, xb, P.dim);
+        }
+        P.shift[size_t(n)] = S;
+    }
+    P.level0_action = P.shift[0];
+    P.shape = shape_array(p);
+    P.sig.assign(size_t(P.s + 1), 0.0);
+    for (int n = 1; n <= P.s; ++n) P.sig[size_t(n)] = std::sqrt(T / std::ldexp(1.0, n + 1));
+    return PIMC_OK;
+}
+
+int stage_vector(pimc_ctx* c, const VecProblem& P, uint64_t seed, uint32_t stream, VecArgs& A) {
+    const size_t nlev = size_t(P.s + 1);
+    const size_t n_tab = P.tab_dev.size();
+    const size_t off_shift = nlev * 8;
+    const size_t off_tab = 2 * nlev * 8;
+    const size_t off_shape = off_tab + n_tab * 8;
+    const size_t total = off_shape + P.shape.size() * 4 + 16;
+    std::vector<unsigned char> host(total, 0);
+    std::memcpy(host.data(), P.sig.data(), nlev * 8);
+    std::memcpy(host.data() + off_shift, P.shift.data(), nlev * 8);
+    std::memcpy(host.data() + off_tab, P.tab_dev.data(), n_tab * 8);
+    std::memcpy(host.data() + off_shape, P.shape.data(), P.shape.size() * 4);
+    int st = ensure(c, &c->d_prm, &c->prm_bytes, total);
+    if (st) return st;
+    HIP_TRY(c, hipMemcpyAsync(c->d_prm, host.data(), total, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));     // the host vector must outlive the copy
+    unsigned char* base = static_cast<unsigned char*>(c->d_prm);
+    std::memset(&A, 0, sizeof(A));
+    A.sig = reinterpret_cast<const double*>(base);
+    A.shift = reinterpret_cast<const double*>(base + off_shift);
+    A.tab = reinterpret_cast<const double*>(base + off_tab);
+    A.shape = reinterpret_cast<const int*>(base + off_shape);
+    A.stride = P.stride;
+    for (int k = 0; k < kVecMaxDim; ++k) {
+        A.a[k] = k < P.dim ? P.a[k] : 0.0;
+        A.b[k] = k < P.dim ? P.b[k] : 0.0;
+    }
+    A.key.seed_lo = uint32_t(seed);
+    A.key.seed_hi = uint32_t(seed >> 32);
+    A.key.stream = stream;
+    A.s = P.s;
+    A.D = P.D;
+    return PIMC_OK;
+}
+
+// The walk keeps (D + (D+1)*dim) doubles per lane in LDS: refuse a launch the device cannot hold.
+int check_lds(pimc_ctx* c, const VecProblem& P) {
+    int max_lds = 0;
+    HIP_TRY(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
+    const size_t need = vec_lds_bytes(P.dim, P.D, P.s);
+    if (need > size_t(max_lds))
+        return ctx_fail(c, PIMC_EUNSUPPORTED, "N = 2^%d in %d coordinates needs %zu bytes of LDS per workgroup (device limit %d)",
+                        P.s, P.dim, need, max_lds);
+    return PIMC_OK;
+}
+
+int vector_grid(pimc_ctx* c, const VecProblem& P, uint64_t n_chunks) {
+    const int resident = vector_resident_blocks(P.dim, P.p, P.U, P.specialized, vec_lds_bytes(P.dim, P.D, P.s),
+                                                c->device);
+    const uint64_t g = std::min<uint64_t>(n_chunks, uint64_t(std::max(resident, 1)));
+    return int(std::max<uint64_t>(g, 1));
+}
+
+int vector_amplitude_core(pimc_ctx* c, const VecProblem& P, uint64_t n_samples, uint64_t seed, uint32_t stream,
+                          uint32_t flags, pimc_level_result* out) {
+    const int nlev = P.s + 1;
+    const bool hier = (flags & PIMC_HIERARCHY) != 0;
+    for (int n = 0; n < nlev; ++n) out[n] = pimc_level_result{};
+    out[0].log_amp = std::log(P.pref * P.K0) - P.level0_action;
+    out[0].amp = std::exp(out[0].log_amp);
+    out[0].n = n_samples;
+    out[0].ess = double(n_samples);
+    c->last_s = P.s;
+    c->last_shift = P.shift;
+    if (P.s == 0) return PIMC_OK;
+    int st = check_lds(c, P);
+    if (st) return st;
+    VecArgs A;
+    st = stage_vector(c, P, seed, stream, A);
+    if (st) return st;
+    const uint32_t ppl = paths_per_lane(P.s);
+    const uint64_t chunk_paths = uint64_t(kVecBlock) * ppl;
+    const uint64_t n_chunks = (n_samples + chunk_paths - 1) / chunk_paths;
+    const int slots = hier ? nlev : 1;
+    st = ensure(c, reinterpret_cast<void**>(&c->d_partials), &c->partial_bytes, size_t(slots) * n_chunks * 4 * 8);
+    if (st) return st;
+    st = ensure(c, reinterpret_cast<void**>(&c->d_red), &c->red_bytes, size_t(slots) * 4 * 8);
+    if (st) return st;
+    st = ensure(c, reinterpret_cast<void**>(&c->d_seg), &c->seg_bytes, size_t(slots) * 2 * 8);
+    if (st) return st;
+    c->h_seg.assign(size_t(slots) * 2, 0);
+    for (int k = 0; k < slots; ++k) {
+        c->h_seg[size_t(k)] = uint64_t(k) * n_chunks * 4;
+        c->h_seg[size_t(slots + k)] = n_chunks;
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->d_seg, c->h_seg.data(), c->h_seg.size() * 8, hipMemcpyHostToDevice, c->stream));
+    A.first_path = 0;
+    A.n_paths = n_samples;
+    A.n_chunks = n_chunks;
+    A.ppl = ppl;
+    A.hier = hier ? 1 : 0;
+    A.partials = c->d_partials;
+    A.dump = nullptr;
+    const int grid = vector_grid(c, P, n_chunks);
+    HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
+    HIP_TRY(c, launch_vector(A, P.dim, P.p, P.U, P.specialized, grid, c->stream));
+    HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
+    HIP_TRY(c, launch_seg_reduce(c->d_partials, c->d_seg, c->d_seg + slots, uint64_t(slots), c->d_red, c->stream));
+    std::vector<double> red(size_t(slots) * 4);
+    HIP_TRY(c, hipMemcpyAsync(red.data(), c->d_red, red.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    float ms = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    c->last_ms = ms;
+    c->last_chunks = n_chunks;
+    c->last_chunk_paths = chunk_paths;
+    c->last_hier = hier;
+    bool nonfinite = false;
+    for (int n = 1; n < nlev; ++n) {
+        if (!hier && n != P.s) continue;
+        const size_t k = size_t(hier ? n : 0);
+        if (assemble_level(&red[k * 4], std::log(P.pref * P.K0) - P.shift[size_t(n)], out[n])) nonfinite = true;
+    }
+    return nonfinite ? PIMC_WNONFINITE : PIMC_OK;
+}
+
+int vector_path_actions_core(pimc_ctx* c, const VecProblem& P, uint64_t seed, uint32_t stream, uint32_t flags,
+                             uint64_t first_path, uint64_t k_paths, double* S_out) {
+    const size_t nlev = size_t(P.s + 1);
+    if (P.s == 0) {
+        for (uint64_t i = 0; i < k_paths; ++i) S_out[i] = P.level0_action;
+        return PIMC_OK;
+    }
+    int st = check_lds(c, P);
+    if (st) return st;
+    VecArgs A;
+    st = stage_vector(c, P, seed, stream, A);
+    if (st) return st;
+    st = ensure(c, reinterpret_cast<void**>(&c->d_dump), &c->dump_bytes, size_t(k_paths) * nlev * 8);
+    if (st) return st;
+    const uint32_t ppl = paths_per_lane(P.s);
+    const uint64_t chunk_paths = uint64_t(kVecBlock) * ppl;
+    A.first_path = first_path;
+    A.n_paths = k_paths;
+    A.n_chunks = (k_paths + chunk_paths - 1) / chunk_paths;
+    A.ppl = ppl;
+    A.hier = (flags & PIMC_HIERARCHY) ? 1 : 0;
+    A.partials = nullptr;
+    A.dump = c->d_dump;
+    const int grid = vector_grid(c, P, A.n_chunks);
+    HIP_TRY(c, launch_vector(A, P.dim, P.p, P.U, P.specialized, grid, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(S_out, c->d_dump, size_t(k_paths) * nlev * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return PIMC_OK;
+}
+
+}  // namespace
+
+namespace pimc {
+
+hipError_t launch_vector(const VecArgs& A, int dim, int p, int U, bool specialized, int grid, hipStream_t st) {
+    switch (dim) {
+        case 1: return launch_vector_d1(A, p, U, specialized, grid, st);
+        case 2: return launch_vector_d2(A, p, U, specialized, grid, st);
+        case 3: return launch_vector_d3(A, p, U, specialized, grid, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+int vector_resident_blocks(int dim, int p, int U, bool specialized, size_t lds_bytes, int device) {
+    switch (dim) {
+        case 1: return vector_resident_d1(p, U, specialized, lds_bytes, device);
+        case 2: return vector_resident_d2(p, U, specialized, lds_bytes, device);
+        case 3: return vector_resident_d3(p, U, specialized, lds_bytes, device);
+        default: return 256;
+    }
+}
+
+}  // namespace pimc
+
+// ============================================================================================ C ABI
+extern "C" {
+
+int pimc_amplitude_radial(pimc_ctx* c, const pimc_radial_potential* V, double m, const double* a, const double* b,
+                          double T, uint32_t N, int p, uint64_t n_samples, uint64_t seed, uint32_t stream,
+                          uint32_t flags, pimc_level_result* out) {
+    int st = check_radial(V, m, a, b, T, N, p, n_samples);
+    if (st) return c ? ctx_fail(c, st, "%s", g_thread_error) : st;
+    if (!c) { set_thread_error("context is NULL"); return PIMC_EINVAL; }
+    if (!out) return ctx_fail(c, PIMC_EINVAL, "out is NULL");
+    if (flags & ~kKnownFlags) return ctx_fail(c, PIMC_EINVAL, "unknown flags 0x%x", flags & ~kKnownFlags);
+    HIP_TRY(c, hipSetDevice(c->device));
+    VecProblem P;
+    char why[256] = "";
+    st = build_vector_problem(V, m, a, b, T, N, p, flags, P, why, sizeof(why));
+    if (st) return ctx_fail(c, st, "%s", why);
+    return vector_amplitude_core(c, P, n_samples, seed, stream, flags, out);
+}
+
+int pimc_path_actions_radial(pimc_ctx* c, const pimc_radial_potential* V, double m, const double* a, const double* b,
+                             double T, uint32_t N, int p, uint64_t seed, uint32_t stream, uint32_t flags,
+                             uint64_t first_path, uint64_t k_paths, double* S_out) {
+    int st = check_radial(V, m, a, b, T, N, p, 2);
+    if (st) return c ? ctx_fail(c, st, "%s", g_thread_error) : st;
+    if (!c) { set_thread_error("context is NULL"); return PIMC_EINVAL; }
+    if (!S_out && k_paths) return ctx_fail(c, PIMC_EINVAL, "S_out is NULL");
+    if (flags & ~kKnownFlags) return ctx_fail(c, PIMC_EINVAL, "unknown flags 0x%x", flags & ~kKnownFlags);
+    if (k_paths == 0) return PIMC_OK;
+    HIP_TRY(c, hipSetDevice(c->device));
+    VecProblem P;
+    char why[256] = "";
+    st = build_vector_problem(V, m, a, b, T, N, p, flags, P, why, sizeof(why));
+    if (st) return ctx_fail(c, st, "%s", why);
+    return vector_path_actions_core(c, P, seed, stream, flags, first_path, k_paths, S_out);
+}
+
+int pimc_level_table_radial(const pimc_radial_potential* V, double m, double T, int p, uint32_t level, double* out,
+                            size_t cap, size_t* n_out, int* shape, size_t shape_cap, int* n_groups) {
+    const double zero[PIMC_MAX_DIM] = {0.0, 0.0, 0.0};
+    int st = check_radial(V, m, zero, zero, T, 1u, p, 2);
+    if (st) return st;
+    if (level > PIMC_MAX_S) { set_thread_error("level > %d", PIMC_MAX_S); return PIMC_EINVAL; }
+    const auto W = radial_coefficients(rescaled(V, m), V->dim, p);
+    std::vector<double> tab;
+    if (!fold_radial(W, p, std::ldexp(T, -int(level)), tab)) {
+        set_thread_error("internal: a coefficient falls outside the radial table shape");
+        return PIMC_EUNSUPPORTED;
+    }
+    const std::vector<Group> groups = layout_groups(p);
+    if (n_out) *n_out = tab.size();
+    if (n_groups) *n_groups = int(groups.size());
+    if (!out || cap < tab.size()) {
+        set_thread_error("output capacity %zu < %zu", cap, tab.size());
+        return PIMC_EINVAL;
+    }
+    if (!shape || shape_cap < 3 * groups.size()) {
+        set_thread_error("shape capacity %zu < %zu", shape_cap, 3 * groups.size());
+        return PIMC_EINVAL;
+    }
+    std::copy(tab.begin(), tab.end(), out);
+    for (size_t g = 0; g < groups.size(); ++g) {
+        shape[3 * g] = groups[g].j + groups[g].l;
+        shape[3 * g + 1] = groups[g].j;
+        shape[3 * g + 2] = groups[g].len;
+    }
+    return PIMC_OK;
+}
+
+}  // extern "C"

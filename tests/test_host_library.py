@@ -184,3 +184,57 @@ def test_mpt_level_table_matches_exact_oracle(lam, alpha, m, T, p, level):
         off += blk.size
         assert np.max(np.abs(got - blk)) <= 1e-14 * np.sum(np.abs(blk)), k
     assert deg == rdeg and off == tab.size
+
+
+@pytest.mark.parametrize("coefs,dim,m,T,p,level", [
+    ((0.0, 0.5, 10 / 24), 2, 1.0, 1.0, 18, 3), ((0.0, 0.5, 10 / 24), 2, 1.0, 2.0, 10, 0),
+    ((0.3, 0.5, 1 / 24), 3, 2.0, 1.0, 12, 5), ((0.25, 1.0, 0.125), 1, 1.0, 0.5, 8, 2), ((1.0,), 2, 1.0, 1.0, 4, 1),
+])
+def test_radial_level_table_matches_exact_oracle(coefs, dim, m, T, p, level):
+    """Several coordinates: the library's FP64 invariant recursion folded per level agrees with the
+    oracle's exact tables (component-pinned), group by group; every exact coefficient lies inside
+    the compile-time shape."""
+    from oracle import vector as ov
+    tab, shape = P.level_table_radial(coefs, dim, m, T, p, level)
+    a = ov.rescale_mass([Fraction(c) for c in coefs], m)
+    Q = ov.level_groups(a, dim, p, Fraction(T) / (1 << level))
+    seen = set()
+    off = 0
+    for k, j, ln in shape:
+        ref = [float(c) for c in reversed(Q[k][j])] if k < len(Q) else []
+        assert len(ref) <= ln, (k, j)
+        ref = np.array([0.0] * (ln - len(ref)) + ref)
+        got = tab[off:off + ln]
+        off += ln
+        assert np.all(np.abs(got - ref) <= 1e-14 * (np.abs(ref) + np.max(np.abs(tab)))), (k, j)
+        seen.add((k, j))
+    assert off == tab.size
+    for k, row in enumerate(Q):
+        for j, q in enumerate(row):
+            if any(c != 0 for c in q):
+                assert (k, j) in seen, (k, j)
+
+
+def test_radial_entry_points_validate_without_a_device():
+    lib = P.load_library()
+    a = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
+    b = (ctypes.c_double * 3)(1.0, 0.0, 0.0)
+    out = (ctypes.c_double * 16)()
+    for dim, coefs in ((0, (0, 0.5)), (4, (0, 0.5)), (2, (0, 0.5, 0.1))):
+        V = P.binding.RadialPotential()
+        V.dim = dim
+        V.degree = len(coefs) - 1
+        for n, c in enumerate(coefs):
+            V.coef[n] = c
+        st = lib.pimc_path_actions_radial(None, ctypes.byref(V), 1.0, a, b, 1.0, 16, 4, 1, 0, 0, 0, 1, out)
+        assert st == -1
+    V = P.radial_potential((0, 0.5, float("nan")), 2)
+    assert lib.pimc_path_actions_radial(None, ctypes.byref(V), 1.0, a, b, 1.0, 16, 4, 1, 0, 0, 0, 1, out) == -1
+    V = P.radial_potential((0, 0.5), 2)
+    assert lib.pimc_path_actions_radial(None, ctypes.byref(V), 1.0, a, b, 1.0, 15, 4, 1, 0, 0, 0, 1, out) == -1
+    V.degree = 3
+    need = ctypes.c_size_t(0)
+    assert lib.pimc_level_table_radial(ctypes.byref(V), 1.0, 1.0, 4, 0, None, 0, ctypes.byref(need), None, 0,
+                                       None) == -1
+    with pytest.raises(ValueError):
+        P.radial_potential((0, 0.5, 0.1, 0.01), 2)
