@@ -48,6 +48,11 @@ FLOW = dict(g=10.0, p=12, s=7, T=2.0, layers=8, batch=4096, lr=1e-3, beta=0.9, s
 SPECTRUM = [dict(name="anharmonic A=1 g=48", A=1.0, g=48.0, t=0.02, L=8.0),
             dict(name="double well A=-10 g=12", A=-10.0, g=12.0, t=0.1, L=10.0)]
 SPEC_N, SPEC_P, SPEC_K = 16384, 21, 10
+# Several coordinates (Sec. 2.2): the 2D anharmonic oscillator of Sec. 3.3, V = r^2/2 + g r^4/24, and its
+# 3D analogue, at p = 18, every level of s = 10, 1e8 samples; the 2D value against a tensor-product DVR.
+VECTOR = dict(g=10.0, T=1.0, s=10, p=18, samples=100_000_000,
+              ends={2: ((0.0, 0.0), (1.0, 0.4)), 3: ((0.0, 0.0, 0.0), (1.0, 0.4, -0.2))})
+RADIAL_E = {18: 102}                     # coefficients of the (u, z, w^2) table at p = 18
 HBM_PEAK_GBS = 8000.0
 # Modified Poeschl-Teller potential (the paper's Fig. 2): V = -lambda/cosh^2(alpha q), lambda = alpha = 1,
 # A_N^(p)(-0.5, 0.5; 1) for p in {1, 2, 10} from one s = 10 run each (every N = 2^0..2^10).
@@ -147,6 +152,15 @@ def oracle_mpt_reference():
                                   L=20.0, h=0.025))
 
 
+def oracle_vector_reference():
+    """A((0,0), (1,0.4); 1) of the 2D workload by the oracle's tensor-product DVR (CPU)."""
+    from oracle import vector as ov
+    g = VECTOR["g"]
+    a, b = VECTOR["ends"][2]
+    return float(ov.dvr_amplitude_2d(lambda X, Y: 0.5 * (X * X + Y * Y) + g / 24.0 * (X * X + Y * Y) ** 2,
+                                     a, b, VECTOR["T"], L=6.0, h=0.2))
+
+
 def _fit_continuum(levels, p):
     """Weighted least squares of eq.(fit), A_N = A + B/N^p + C/N^(p+1), over the given levels
     (N = 2^n >= 4); returns (A, its standard error)."""
@@ -212,6 +226,31 @@ def general_section(P, ctx):
     rows["gaussian_barrier"] = {"potential": "q^2/2 + 2 exp(-q^2), A(-0.3, 0.4; 1)",
                                 "slice_evals_per_s": sl / (ms_b / 1e3), "A_1024": res_b[s].amp, "err": res_b[s].err}
     return {"workload": f"p={p}, s={s} (every level), {n:.0e} samples", **rows}
+
+
+def vector_section(P, ctx, dvr):
+    """Several coordinates: A_N^(18) of the 2D and 3D anharmonic oscillators from one s = 10 run each
+    (every level), the kernel rate against the FP64 vector peak, and the 2D value against the DVR."""
+    V = VECTOR
+    coefs = (0.0, 0.5, V["g"] / 24.0)
+    out = {"workload": f"V=r^2/2+{V['g']:g} r^4/24 in d=2 and d=3, p={V['p']}, s={V['s']} (every level), "
+                       f"T={V['T']:g}, {V['samples']:.0e} samples", "per_dim": {}}
+    for dim in (2, 3):
+        a, b = V["ends"][dim]
+        ctx.amplitude_radial(coefs, dim, 1.0, a, b, V["T"], 1 << V["s"], V["p"], 1 << 20, 1, 0, P.FLAG_HIERARCHY)
+        res, st = ctx.amplitude_radial(coefs, dim, 1.0, a, b, V["T"], 1 << V["s"], V["p"], V["samples"], 1, 0,
+                                       P.FLAG_HIERARCHY)
+        ms = ctx.last_kernel_ms()
+        rate = V["samples"] * slices_per_sample(V["s"], True) / (ms / 1e3)
+        flop = 2 * (RADIAL_E[V["p"]] - 1) + 8 * dim + 2
+        row = {"a": a, "b": b, "A_N": [r.amp for r in res], "err_N": [r.err for r in res], "status": st,
+               "kernel_ms": ms, "slice_evals_per_s": rate, "flop_per_slice": flop,
+               "fp64_frac": rate * flop / 1e12 / FP64_PEAK_TFLOPS}
+        if dim == 2 and dvr is not None:
+            row["dvr_continuum"] = dvr
+            row["A_N_minus_dvr_over_err"] = [(r.amp - dvr) / r.err if r.err > 0 else None for r in res]
+        out["per_dim"][str(dim)] = row
+    return out
 
 
 def spectrum_section(P, ctx, dvr):
@@ -347,6 +386,8 @@ def main():
     ap.add_argument("--only-general", action="store_true", help="run only the general-potential section")
     ap.add_argument("--only-mpt", action="store_true",
                     help="run only the Poeschl-Teller convergence section, with its DVR reference")
+    ap.add_argument("--only-vector", action="store_true",
+                    help="run only the several-coordinate section, with its DVR reference")
     ap.add_argument("--only-spectrum", action="store_true",
                     help="run only the spectrum section (for profiler runs), with its DVR reference")
     ap.add_argument("--flow-steps", type=int, default=FLOW["steps"],
@@ -362,11 +403,12 @@ def main():
 
     # The oracle runs first, in worker processes forked before this process touches the GPU.
     skip_cpu = (args.no_cpu_baseline or args.only_headline or args.only_proposal or args.only_spectrum or
-                args.only_mpt or args.only_general)
+                args.only_mpt or args.only_general or args.only_vector)
     cpu = None if skip_cpu else cpu_baseline(CPU_SAMPLE_PATHS)
     prec_ref = None if skip_cpu else oracle_precision_reference()
     spec_ref = None if (skip_cpu and not args.only_spectrum) else oracle_spectrum_reference()
     mpt_ref = None if (skip_cpu and not args.only_mpt) else oracle_mpt_reference()
+    vec_ref = None if (skip_cpu and not args.only_vector) else oracle_vector_reference()
 
     import paper_1105_0542_amd as P
 
@@ -386,6 +428,10 @@ def main():
         return
     if args.only_general:
         print(json.dumps({"general": general_section(P, ctx)}), flush=True)
+        ctx.close()
+        return
+    if args.only_vector:
+        print(json.dumps({"vector": vector_section(P, ctx, vec_ref)}), flush=True)
         ctx.close()
         return
     N = 1 << S_DEPTH
@@ -489,6 +535,7 @@ def main():
     spec_line = spectrum_section(P, ctx, spec_ref)
     mpt_line = mpt_section(P, ctx, mpt_ref)
     gen_line = general_section(P, ctx)
+    vec_line = vector_section(P, ctx, vec_ref)
 
     line = {
         "metric": "slice-evals/s (p=18, FP64)",
@@ -531,6 +578,7 @@ def main():
     line["spectrum"] = spec_line
     line["mpt"] = mpt_line
     line["general"] = gen_line
+    line["vector"] = vec_line
     if cpu is not None:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
