@@ -16,12 +16,16 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpimc.so")
 CLI = os.path.join(PKG, "pimc")
 
-SOURCES = ["pimc_kernels.hip", "pimc_vector_d2.hip", "pimc_vector_d3.hip", "pimc_flow.hip", "pimc_spectrum.hip",
-           "pimc_vector_d1.hip", "pimc_host.cpp", "pimc_flow_host.cpp", "pimc_spectrum_host.cpp",
+SOURCES = ["pimc_kernels.hip", "pimc_vector_d2.hip", "pimc_vector_d3.hip", "pimc_general_kernels.hip", "pimc_flow.hip",
+           "pimc_spectrum.hip", "pimc_vector_d1.hip", "pimc_host.cpp", "pimc_flow_host.cpp", "pimc_spectrum_host.cpp",
            "pimc_general_host.cpp", "pimc_vector_host.cpp"]
-HEADERS = ["pimc_tables.hpp", "pimc_device.hpp", "pimc_internal.hpp", "pimc_math.hpp", "pimc_flow.hpp",
-           "pimc_host_common.hpp", "pimc_spectrum.hpp", "pimc_general.hpp", "pimc_vector.hpp",
-           "pimc_vector_impl.hpp"]
+HEADERS = ["pimc_tables.hpp", "pimc_device.hpp", "pimc_internal.hpp", "pimc_math.hpp", "pimc_walker.hpp",
+           "pimc_flow.hpp", "pimc_host_common.hpp", "pimc_spectrum.hpp", "pimc_general.hpp",
+           "pimc_general_device.hpp", "pimc_vector.hpp", "pimc_vector_impl.hpp"]
+# Build-time generator of the general-potential evaluators: host C++ (the recursion of pimc_general.hpp)
+# that writes pimc_general_gen.hpp into the object directory.
+CODEGEN = "pimc_gen_codegen.cpp"
+GENERATED = "pimc_general_gen.hpp"
 
 # -ffp-contract=off: every fused multiply-add in the kernels is written as fma(); no other
 # expression is contracted, so the arithmetic is exactly what the source states.
@@ -45,7 +49,11 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     t0 = time.time()
     objdir = os.path.join(PKG, "_build")
     os.makedirs(objdir, exist_ok=True)
-    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC, "-I", objdir]
+    gen_exe = os.path.join(objdir, "pimc_gen_codegen")
+    subprocess.run(["g++", "-O2", "-std=c++17", "-Wall", "-I", CSRC, os.path.join(CSRC, CODEGEN), "-o", gen_exe],
+                   check=True)
+    subprocess.run([gen_exe, os.path.join(objdir, GENERATED)], check=True)
     procs = []
     objs = []
     for src in SOURCES:

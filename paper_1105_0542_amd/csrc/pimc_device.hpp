@@ -275,123 +275,17 @@ struct TanhEval64 {
     }
 };
 
-// General-potential mode: the effective potential as monomials in v_j = V^(j)(mid), j <= J, grouped
-// by the power of dlt^2; the derivatives of V = poly + sum A/cosh^2(a x) + sum B exp(-b x^2) come
-// from tables (see pimc_general.hpp). The derivative values of the slice are kept in lane-private
-// LDS slots and read with the wave-uniform factor numbers of each record (scalar loads).
-constexpr int kGenMaxP = 10;
-constexpr int kGenMaxJ = 2 * kGenMaxP - 2;
-constexpr int kGenMaxTerms = 4;
-constexpr int kGenLanes = 256;                  // threads per workgroup of the estimation kernels
-
+// General-potential mode: the derivative tables of V = poly + sum A/cosh^2(a x) + sum B exp(-b x^2)
+// (see pimc_general.hpp); the slice evaluators themselves are generated per p at build time
+// (pimc_general_device.hpp).
 struct GenTables {
-    const GenRecord* rec;                        // all levels
-    const uint32_t* grp;                         // per level K+1 offsets into rec
-    int K, J;
-    const double* dpoly;                         // (J+1) x 9
-    int pdeg;
-    const double* dsech;                         // per term (J+1) x (J+3)
+    const double* dpoly;                         // (J+1) x 9: coefficients of V^(j) of the polynomial part
+    int pdeg;                                    // degree of the polynomial part (-1: none)
+    const double* dsech;                         // per term (J+1) x (J+3): A a^j S_j(t)
     int n_sech;
     int n_gauss;
     double sech_a[kGenMaxTerms];
     double gB[kGenMaxTerms], gb[kGenMaxTerms], gsb[kGenMaxTerms];
-};
-
-// Lane-private derivative slots (one LDS array per kernel, whatever the batch widths used).
-__device__ __forceinline__ double* gen_slots() {
-    __shared__ double vbuf[(kGenMaxJ + 2) * kGenLanes];
-    return vbuf + threadIdx.x;
-}
-
-struct GeneralEval64 {
-    GenTables g;
-    __device__ __forceinline__ void launder() {}
-    template <int W>
-    __device__ __forceinline__ void eval(int level, const double (&qa)[W], const double (&qb)[W], double& S) const {
-        double* v = gen_slots();
-        const int J = g.J;
-        const const_ptr<double> dp = as_const(g.dpoly);
-        const const_ptr<double> ds = as_const(g.dsech);
-        const const_ptr<GenRecord> rec = as_const(g.rec);
-        const const_ptr<uint32_t> grp = as_const(g.grp) + level * (g.K + 1);
-#pragma unroll
-        for (int i = 0; i < W; ++i) {
-            const double x = 0.5 * (qa[i] + qb[i]);
-            const double dl = qb[i] - qa[i];
-            const double z = dl * dl;
-            for (int j = 0; j <= J; ++j) {
-                const int dg = g.pdeg - j;
-                double acc = 0.0;
-                if (dg >= 0) {
-                    acc = dp[j * 9 + dg];
-                    for (int n = dg - 1; n >= 0; --n) acc = fma(acc, x, dp[j * 9 + n]);
-                }
-                v[j * kGenLanes] = acc;
-            }
-            for (int t = 0; t < g.n_sech; ++t) {
-                const double th = tanh(g.sech_a[t] * x);
-                for (int j = 0; j <= J; ++j) {
-                    const int row = (t * (J + 1) + j) * (J + 3);
-                    double acc = ds[row + j + 2];
-                    for (int n = j + 1; n >= 0; --n) acc = fma(acc, th, ds[row + n]);
-                    v[j * kGenLanes] += acc;
-                }
-            }
-            for (int t = 0; t < g.n_gauss; ++t) {
-                const double y = g.gsb[t] * x;
-                double e = g.gB[t] * exp(-g.gb[t] * x * x);
-                double hm = 0.0, h = 1.0;
-                for (int j = 0; j <= J; ++j) {
-                    v[j * kGenLanes] += e * h;
-                    const double hn = 2.0 * y * h - 2.0 * double(j) * hm;
-                    hm = h;
-                    h = hn;
-                    e *= -g.gsb[t];
-                }
-            }
-            v[(J + 1) * kGenLanes] = 1.0;
-            double acc = 0.0;
-            for (int k = g.K - 1; k >= 0; --k) {
-                double val0 = 0.0, val1 = 0.0;
-                const uint32_t r1 = grp[k + 1];
-                uint32_t r = grp[k];
-                // two records at a time, four factors per step (padded with the slot holding 1)
-                for (; r + 1 < r1; r += 2) {
-                    double t0 = rec[r].coef, t1 = rec[r + 1].coef;
-                    const int n0 = rec[r].nf, n1 = rec[r + 1].nf;
-                    const int nmin = n0 < n1 ? n0 : n1;
-                    int f = 0;
-                    for (; f < nmin; f += 4) {
-                        const double a0 = v[int(rec[r].f[f]) * kGenLanes], a1 = v[int(rec[r].f[f + 1]) * kGenLanes];
-                        const double a2 = v[int(rec[r].f[f + 2]) * kGenLanes], a3 = v[int(rec[r].f[f + 3]) * kGenLanes];
-                        const double b0 = v[int(rec[r + 1].f[f]) * kGenLanes], b1 = v[int(rec[r + 1].f[f + 1]) * kGenLanes];
-                        const double b2 = v[int(rec[r + 1].f[f + 2]) * kGenLanes], b3 = v[int(rec[r + 1].f[f + 3]) * kGenLanes];
-                        t0 = t0 * a0 * a1 * a2 * a3;
-                        t1 = t1 * b0 * b1 * b2 * b3;
-                    }
-                    for (int f0 = f; f0 < n0; f0 += 4)
-                        t0 = t0 * v[int(rec[r].f[f0]) * kGenLanes] * v[int(rec[r].f[f0 + 1]) * kGenLanes] *
-                             v[int(rec[r].f[f0 + 2]) * kGenLanes] * v[int(rec[r].f[f0 + 3]) * kGenLanes];
-                    for (int f1 = f; f1 < n1; f1 += 4)
-                        t1 = t1 * v[int(rec[r + 1].f[f1]) * kGenLanes] * v[int(rec[r + 1].f[f1 + 1]) * kGenLanes] *
-                             v[int(rec[r + 1].f[f1 + 2]) * kGenLanes] * v[int(rec[r + 1].f[f1 + 3]) * kGenLanes];
-                    val0 += t0;
-                    val1 += t1;
-                }
-                if (r < r1) {
-                    double t0 = rec[r].coef;
-                    const int n0 = rec[r].nf;
-                    for (int f = 0; f < n0; f += 4)
-                        t0 = t0 * v[int(rec[r].f[f]) * kGenLanes] * v[int(rec[r].f[f + 1]) * kGenLanes] *
-                             v[int(rec[r].f[f + 2]) * kGenLanes] * v[int(rec[r].f[f + 3]) * kGenLanes];
-                    val0 += t0;
-                }
-                const double val = val0 + val1;
-                acc = (k == g.K - 1) ? val : fma(acc, z, val);
-            }
-            S += acc;
-        }
-    }
 };
 
 // Any polynomial potential: runtime shape (K polynomials, degrees deg[k]) in u = x^2 (EVEN) or x.

@@ -2,9 +2,9 @@
 // v_j = V^(j)(x) (Sec. 3.1/3.2: for a general V the c_{m,k} are expressions in V and its
 // derivatives up to order 2p-2). eq.(1Drec) and eq.(diagonal) run on polynomials in v_0..v_J with
 // the derivation d v_j/dx = v_{j+1}; the result does not depend on V and is computed once per p.
-// Per bisection level the polynomials are folded into monomial records grouped by the power of
-// dlt^2 (eps W_p = sum_k dlt^(2k) sum_records coef * prod v_f), which the device evaluates from
-// the derivative values at each slice mid-point.
+// Per bisection level the monomials get their coefficients (powers of eps folded in); the device
+// evaluators, generated from the same canonical monomial order at build time, form the products
+// of the derivative values at each slice mid-point and sum eps W_p = sum_k dlt^(2k) sum coef prod v_f.
 //
 // Potentials of this mode: V(x) = sum_n c_n x^n + sum_i A_i / cosh^2(a_i x) + sum_i B_i exp(-b_i x^2),
 // whose derivatives come from tables computed here: the polynomial's derivative coefficients, the
@@ -12,6 +12,7 @@
 // S_{j+1} = (1 - t^2) S_j'(t), and Hermite polynomials for the Gaussians.
 #pragma once
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <map>
@@ -108,28 +109,42 @@ inline SymCoefficients symbolic_coefficients(int p) {
     return C;
 }
 
-// Records of one level (eps = T/2^n): group k = the terms of dlt^(2k), coef = c_{m,k} eps^(m-k+1) 4^-k.
-inline void fold_symbolic(const SymCoefficients& C, double eps, std::vector<GenRecord>& recs,
-                          std::vector<uint32_t>& groups) {
-    groups.clear();
-    for (int k = 0; k < C.p; ++k) {
-        groups.push_back(uint32_t(recs.size()));
-        for (int m = k; m < C.p; ++m) {
-            const double scale = std::pow(eps, double(m - k + 1)) * std::ldexp(1.0, -2 * k);
-            for (const auto& kv : C.c[m][k]) {
-                GenRecord r{};
-                r.coef = kv.second * scale;
-                int nf = 0;
+// One monomial of the level-p effective potential: coefficient c of prod_i v_{f[i]} in c_{m,k}.
+struct GenMono {
+    int k = 0, m = 0;
+    std::vector<uint8_t> f;                      // factor indices, ascending (v_j repeated e_j times)
+    double c = 0.0;
+};
+
+// Every monomial of every c_{m,k} in the order in which the compiled evaluators consume them:
+// k from p-1 down to 0 (Horner in dlt^2), then factor lists in lexicographic order, so that
+// consecutive monomials share the longest possible prefix of factors (a prefix tree walked depth
+// first). A factor list determines m (its weight is 2m + 2), so the order is total.
+inline std::vector<GenMono> canonical_monomials(const SymCoefficients& C) {
+    std::vector<GenMono> out;
+    for (int k = C.p - 1; k >= 0; --k) {
+        std::vector<GenMono> grp;
+        for (int m = k; m < C.p; ++m)
+            for (const auto& kv : C.c[size_t(m)][size_t(k)]) {
+                GenMono g;
+                g.k = k;
+                g.m = m;
+                g.c = kv.second;
                 for (size_t j = 0; j < kv.first.size(); ++j)
-                    for (int e = 0; e < kv.first[j]; ++e) r.f[nf++] = uint8_t(j);
-                // pad to a multiple of four factors with the slot that holds 1 (index J + 1)
-                while (nf % 4) r.f[nf++] = uint8_t(C.J + 1);
-                r.nf = uint8_t(nf);
-                recs.push_back(r);
+                    for (int e = 0; e < kv.first[j]; ++e) g.f.push_back(uint8_t(j));
+                grp.push_back(std::move(g));
             }
-        }
+        std::sort(grp.begin(), grp.end(), [](const GenMono& a, const GenMono& b) { return a.f < b.f; });
+        out.insert(out.end(), grp.begin(), grp.end());
     }
-    groups.push_back(uint32_t(recs.size()));
+    return out;
+}
+
+// Coefficients of one level (eps = T/2^n) in canonical order: c eps^(m-k+1) 4^-k, so that
+// eps W_p = sum_k dlt^(2k) sum_{monomials of k} coef prod v_f with dlt the full slice deviation.
+inline void level_coefficients(const std::vector<GenMono>& M, double eps, double* out) {
+    for (size_t r = 0; r < M.size(); ++r)
+        out[r] = M[r].c * std::pow(eps, double(M[r].m - M[r].k + 1)) * std::ldexp(1.0, -2 * M[r].k);
 }
 
 // Derivative tables of a potential of this mode (after the mass rescaling).
@@ -208,28 +223,33 @@ inline void gen_derivatives(const GenPotential& G, double x, double* v) {
     }
 }
 
-// eps W_p of one slice from the folded records of a level.
-inline double gen_eval_slice(const GenPotential& G, const std::vector<GenRecord>& recs,
-                             const std::vector<uint32_t>& groups, double qa, double qb) {
+// eps W_p of one slice from the canonical monomials and one level's coefficients, with the products
+// formed as the compiled evaluators form them (prefix products left to right).
+inline double gen_eval_slice(const GenPotential& G, const std::vector<GenMono>& M, const double* coef, double qa,
+                             double qb) {
     const double x = 0.5 * (qa + qb);
     const double dl = qb - qa;
     const double z = dl * dl;
-    std::vector<double> v(size_t(G.J) + 2);
+    std::vector<double> v(size_t(G.J) + 1);
     gen_derivatives(G, x, v.data());
-    v[size_t(G.J) + 1] = 1.0;
-    const int K = int(groups.size()) - 1;
-    double acc = 0.0;
-    for (int k = K - 1; k >= 0; --k) {
-        double val[2] = {0.0, 0.0};                   // records alternate between two sums
-        for (uint32_t r = groups[size_t(k)]; r < groups[size_t(k) + 1]; ++r) {
-            double t = recs[r].coef;
-            for (int f = 0; f < recs[r].nf; f += 4)
-                t = t * v[recs[r].f[f]] * v[recs[r].f[f + 1]] * v[recs[r].f[f + 2]] * v[recs[r].f[f + 3]];
-            val[(r - groups[size_t(k)]) & 1] += t;
+    double acc = 0.0, g = 0.0;
+    int k_cur = M.empty() ? -1 : M[0].k;
+    bool first = true;
+    for (size_t r = 0; r <= M.size(); ++r) {
+        if (r == M.size() || M[r].k != k_cur) {
+            acc = first ? g : std::fma(acc, z, g);
+            first = false;
+            if (r == M.size()) break;
+            for (int k = k_cur - 1; k > M[r].k; --k) acc = acc * z;   // an empty group in between
+            k_cur = M[r].k;
+            g = 0.0;
         }
-        const double vk = val[0] + val[1];
-        acc = (k == K - 1) ? vk : std::fma(acc, z, vk);
+        const std::vector<uint8_t>& f = M[r].f;
+        double t = v[f[0]];
+        for (size_t i = 1; i < f.size(); ++i) t = t * v[f[i]];
+        g = std::fma(coef[r], t, g);
     }
+    for (int k = k_cur - 1; k >= 0; --k) acc = acc * z;
     return acc;
 }
 

@@ -1,0 +1,98 @@
+// General-potential mode on the device: per slice, the derivatives v_j = V^(j)(mid), j <= J = 2p-2,
+// in registers (from the tables of pimc_general.hpp: the polynomial part by Horner per derivative,
+// one tanh per sech^2 term with the polynomials S_j(tanh), one exp per Gaussian term with the
+// Hermite recurrence), then eps W_p = sum_k dlt^(2k) sum coef prod v_f by the straight-line code
+// generated for level p at build time (GenCompiled<p>, pimc_general_gen.hpp), whose coefficients
+// are the level's table in the canonical monomial order (scalar loads).
+#pragma once
+
+#include "pimc_device.hpp"
+
+namespace pimc {
+template <int P>
+struct GenCompiled;
+}  // namespace pimc
+
+#include "pimc_general_gen.hpp"
+
+namespace pimc {
+
+// Slices evaluated together by the generated code (each holds J+1 derivative values in registers).
+#ifndef PIMC_GEN_SLICES
+#define PIMC_GEN_SLICES 2
+#endif
+constexpr int kGenSlices = PIMC_GEN_SLICES;
+
+template <int J>
+__device__ __forceinline__ void gen_derivatives_dev(const GenTables& g, double x, double (&v)[J + 1]) {
+    const const_ptr<double> dp = as_const(g.dpoly);
+#pragma unroll
+    for (int j = 0; j <= J; ++j) {
+        const int dg = g.pdeg - j;
+        double acc = 0.0;
+        if (dg >= 0) {
+            acc = dp[j * 9 + dg];
+            for (int n = dg - 1; n >= 0; --n) acc = fma(acc, x, dp[j * 9 + n]);
+        }
+        v[j] = acc;
+    }
+    const const_ptr<double> ds = as_const(g.dsech);
+    for (int t = 0; t < g.n_sech; ++t) {
+        const double th = tanh(g.sech_a[t] * x);
+#pragma unroll
+        for (int j = 0; j <= J; ++j) {
+            const int row = (t * (J + 1) + j) * (J + 3);
+            double acc = ds[row + j + 2];
+#pragma unroll
+            for (int n = j + 1; n >= 0; --n) acc = fma(acc, th, ds[row + n]);
+            v[j] += acc;
+        }
+    }
+    for (int t = 0; t < g.n_gauss; ++t) {
+        // d^j/dx^j B e^{-b x^2} = B (-sqrt b)^j H_j(sqrt(b) x) e^{-b x^2}, H_{j+1} = 2y H_j - 2j H_{j-1}
+        const double y = g.gsb[t] * x;
+        double e = g.gB[t] * exp(-g.gb[t] * x * x);
+        double hm = 0.0, h = 1.0;
+#pragma unroll
+        for (int j = 0; j <= J; ++j) {
+            v[j] += e * h;
+            const double hn = 2.0 * y * h - 2.0 * double(j) * hm;
+            hm = h;
+            h = hn;
+            e *= -g.gsb[t];
+        }
+    }
+}
+
+template <int P>
+struct GenCompiledEval {
+    static constexpr int J = 2 * P - 2;
+    const double* __restrict__ tab;      // level-major, GenCompiled<P>::NREC coefficients per level
+    GenTables g;
+    __device__ __forceinline__ void launder() { asm volatile("" : "+s"(tab)); }
+    template <int W>
+    __device__ __forceinline__ void eval(int level, const double (&qa)[W], const double (&qb)[W], double& S) const {
+        static_assert(GenCompiled<P>::J == J, "generated evaluator of another level");
+        // the level is wave-uniform (the walk does not depend on the lane): keep the table address in
+        // scalar registers
+        const int lv = __builtin_amdgcn_readfirstlane(level);
+        const_ptr<double> t = as_const(tab) + lv * GenCompiled<P>::NREC;
+        constexpr int B = W < kGenSlices ? W : kGenSlices;
+#pragma unroll
+        for (int b0 = 0; b0 < W; b0 += B) {
+            double v[B][J + 1], z[B], acc[B];
+#pragma unroll
+            for (int i = 0; i < B; ++i) {
+                const double x = 0.5 * (qa[b0 + i] + qb[b0 + i]);
+                const double dl = qb[b0 + i] - qa[b0 + i];
+                z[i] = dl * dl;
+                gen_derivatives_dev<J>(g, x, v[i]);
+            }
+            GenCompiled<P>::template eval<B>(t, v, z, acc);
+#pragma unroll
+            for (int i = 0; i < B; ++i) S += acc[i];
+        }
+    }
+};
+
+}  // namespace pimc

@@ -1,8 +1,9 @@
 // Host side of the general-potential entry points (pimc_amplitude_general, pimc_path_actions_general
 // in include/pimc.h): the derivative-symbol coefficients of eq.(1Drec)/(diagonal), computed once
-// per p and cached, folded per bisection level into monomial records; the derivative tables of the
-// potential after the mass rescaling; the straight-line reference actions. Estimation and per-path
-// actions then run through the shared walker kernels.
+// per p and cached, their monomials in the canonical order of the evaluators generated at build time,
+// one coefficient table per bisection level; the derivative tables of the potential after the mass
+// rescaling; the straight-line reference actions. Estimation and per-path actions then run through
+// the shared walker kernels with the evaluator of level p.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -22,24 +23,34 @@ static_assert(PIMC_GEN_MAX_TERMS == kGenMaxTerms, "general-mode term limit of th
 
 namespace {
 
-const SymCoefficients& cached_coefficients(int p) {
+struct LevelMonomials {
+    SymCoefficients C;
+    std::vector<GenMono> M;
+};
+
+// The symbolic coefficients and canonical monomials of level p, computed once per process.
+const LevelMonomials& cached_monomials(int p) {
     static std::mutex mu;
-    static std::map<int, std::unique_ptr<SymCoefficients>> cache;
+    static std::map<int, std::unique_ptr<LevelMonomials>> cache;
     std::lock_guard<std::mutex> lock(mu);
     auto it = cache.find(p);
-    if (it == cache.end())
-        it = cache.emplace(p, std::make_unique<SymCoefficients>(symbolic_coefficients(p))).first;
+    if (it == cache.end()) {
+        auto L = std::make_unique<LevelMonomials>();
+        L->C = symbolic_coefficients(p);
+        L->M = canonical_monomials(L->C);
+        it = cache.emplace(p, std::move(L)).first;
+    }
     return *it->second;
 }
 
-double straight_line_general(const GenPotential& G, const std::vector<GenRecord>& recs,
-                             const std::vector<uint32_t>& grp, double a, double b, int n) {
-    const int M = 1 << n;
+double straight_line_general(const GenPotential& G, const std::vector<GenMono>& M, const double* coef, double a,
+                             double b, int n) {
+    const int N = 1 << n;
     double acc = 0.0;
-    for (int k = 0; k < M; ++k) {
-        const double q0 = a + (b - a) * double(k) / double(M);
-        const double q1 = a + (b - a) * double(k + 1) / double(M);
-        acc += gen_eval_slice(G, recs, grp, q0, q1);
+    for (int k = 0; k < N; ++k) {
+        const double q0 = a + (b - a) * double(k) / double(N);
+        const double q1 = a + (b - a) * double(k + 1) / double(N);
+        acc += gen_eval_slice(G, M, coef, q0, q1);
     }
     return acc;
 }
@@ -122,26 +133,25 @@ int build_problem_general(const pimc_general_potential* V, double m, double a, d
         G.gauss_b.push_back(V->gauss_beta[i] / m);
     }
     gen_potential_tables(G);
-    const SymCoefficients& C = cached_coefficients(p);
-    P.gen_recs.clear();
-    P.gen_grp.clear();
-    std::vector<std::vector<uint32_t>> level_grp;
-    for (int n = 0; n <= P.s; ++n) {
-        std::vector<uint32_t> grp;
-        fold_symbolic(C, std::ldexp(T, -n), P.gen_recs, grp);
-        P.gen_grp.insert(P.gen_grp.end(), grp.begin(), grp.end());
-        level_grp.push_back(std::move(grp));
+    const LevelMonomials& L = cached_monomials(p);
+    const int nrec = int(L.M.size());
+    if (general_compiled_nrec(p) != nrec) {
+        std::snprintf(why, whylen, "internal: the evaluator compiled for p = %d expects %d monomials, the recursion gives %d",
+                      p, general_compiled_nrec(p), nrec);
+        return PIMC_EUNSUPPORTED;
     }
     P.deg.clear();
-    P.stride = 0;
-    P.tab.clear();
-    P.tab_dev.clear();
-    P.tab32.clear();
+    P.stride = nrec;
+    P.tab.assign(size_t(P.s + 1) * size_t(nrec), 0.0);
+    for (int n = 0; n <= P.s; ++n) level_coefficients(L.M, std::ldexp(T, -n), P.tab.data() + size_t(n) * size_t(nrec));
+    P.tab_dev = P.tab;
+    P.tab32.assign(P.tab.size(), 0.0f);
     P.sig.assign(size_t(P.s + 1), 0.0);
     for (int n = 1; n <= P.s; ++n) P.sig[size_t(n)] = std::sqrt(T / std::ldexp(1.0, n + 1));
     P.shift.assign(size_t(P.s + 1), 0.0);
     for (int n = 0; n <= P.s; ++n)
-        P.shift[size_t(n)] = straight_line_general(G, P.gen_recs, level_grp[size_t(n)], P.a, P.b, n);
+        P.shift[size_t(n)] =
+            straight_line_general(G, L.M, P.tab.data() + size_t(n) * size_t(nrec), P.a, P.b, n);
     P.level0_action = P.shift[0];
     return PIMC_OK;
 }

@@ -1,0 +1,57 @@
+// Estimation kernels of the general-potential mode: the walker (pimc_walker.hpp) instantiated with
+// the evaluators generated for p = 1..kGenMaxP (pimc_general_device.hpp), U = 1 or 2 (measured best: larger subtrees or slice batches
+// raise the register pressure of the generated code and run slower).
+#include <hip/hip_runtime.h>
+
+#include "pimc_general_device.hpp"
+#include "pimc_walker.hpp"
+
+namespace pimc {
+
+namespace {
+
+template <int P>
+hipError_t launch_p(const AmpArgs& A, int p, int U, int grid, hipStream_t st) {
+    if constexpr (P <= kGenMaxP) {
+        if (p != P) return launch_p<P + 1>(A, p, U, grid, st);
+        const GenCompiledEval<P> ev{A.tab64, A.gen};
+        switch (U) {
+            case 1: return launch_one<1>(A, ev, grid, st);
+            case 2: return launch_one<2>(A, ev, grid, st);
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        return hipErrorInvalidValue;
+    }
+}
+
+template <int P>
+int resident_p(int p, int U, size_t lds, int device) {
+    if constexpr (P <= kGenMaxP) {
+        if (p != P) return resident_p<P + 1>(p, U, lds, device);
+        return U == 1 ? resident_one<1, GenCompiledEval<P>>(lds, device) : resident_one<2, GenCompiledEval<P>>(lds, device);
+    } else {
+        return 256;
+    }
+}
+
+template <int P>
+int nrec_p(int p) {
+    if constexpr (P <= kGenMaxP) {
+        return p == P ? GenCompiled<P>::NREC : nrec_p<P + 1>(p);
+    } else {
+        return -1;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_general_compiled(const AmpArgs& A, int p, int U, int grid, hipStream_t st) {
+    return launch_p<1>(A, p, U, grid, st);
+}
+
+int general_compiled_resident(int p, int U, size_t lds_bytes, int device) { return resident_p<1>(p, U, lds_bytes, device); }
+
+int general_compiled_nrec(int p) { return nrec_p<1>(p); }
+
+}  // namespace pimc

@@ -288,10 +288,8 @@ int stage_problem(pimc_ctx* c, const Problem& P, uint64_t seed, uint32_t stream,
     const size_t off_tab = 2 * nlev * 8;
     const size_t off_tab32 = off_tab + n_tab * 8;
     const size_t off_deg = (off_tab32 + n_tab * 4 + 15) & ~size_t(15);
-    // general-potential mode: records, level offsets, derivative tables
-    const size_t off_rec = (off_deg + P.deg.size() * 4 + 15) & ~size_t(15);
-    const size_t off_grp = off_rec + P.gen_recs.size() * sizeof(GenRecord);
-    const size_t off_dpoly = (off_grp + P.gen_grp.size() * 4 + 15) & ~size_t(15);
+    // general-potential mode: derivative tables
+    const size_t off_dpoly = (off_deg + P.deg.size() * 4 + 15) & ~size_t(15);
     const size_t off_dsech = off_dpoly + P.gen.dpoly.size() * 8;
     const size_t total = off_dsech + P.gen.dsech.size() * 8 + 16;
     std::vector<unsigned char> host(total, 0);
@@ -302,8 +300,6 @@ int stage_problem(pimc_ctx* c, const Problem& P, uint64_t seed, uint32_t stream,
         std::memcpy(host.data() + off_tab32, P.tab32.data(), n_tab * 4);
     }
     if (!P.deg.empty()) std::memcpy(host.data() + off_deg, P.deg.data(), P.deg.size() * 4);
-    if (!P.gen_recs.empty()) std::memcpy(host.data() + off_rec, P.gen_recs.data(), P.gen_recs.size() * sizeof(GenRecord));
-    if (!P.gen_grp.empty()) std::memcpy(host.data() + off_grp, P.gen_grp.data(), P.gen_grp.size() * 4);
     if (!P.gen.dpoly.empty()) std::memcpy(host.data() + off_dpoly, P.gen.dpoly.data(), P.gen.dpoly.size() * 8);
     if (!P.gen.dsech.empty()) std::memcpy(host.data() + off_dsech, P.gen.dsech.data(), P.gen.dsech.size() * 8);
     int st = ensure(c, &c->d_prm, &c->prm_bytes, total);
@@ -325,10 +321,6 @@ int stage_problem(pimc_ctx* c, const Problem& P, uint64_t seed, uint32_t stream,
     A.alpha = P.alpha;
     if (P.kind == EvalKind::General64) {
         GenTables& g = A.gen;
-        g.rec = reinterpret_cast<const GenRecord*>(base + off_rec);
-        g.grp = reinterpret_cast<const uint32_t*>(base + off_grp);
-        g.K = P.p;
-        g.J = P.gen.J;
         g.dpoly = reinterpret_cast<const double*>(base + off_dpoly);
         g.pdeg = P.gen.pdeg;
         g.dsech = reinterpret_cast<const double*>(base + off_dsech);

@@ -66,9 +66,7 @@ struct Problem {
     double level0_action = 0.0;      // T W_p((a+b)/2, (b-a)/2; T)
     double alpha = 0.0;              // Poeschl-Teller: tables in u = tanh^2(alpha mid) (after the mass rescaling)
     // general-potential mode
-    pimc::GenPotential gen;                  // derivative tables
-    std::vector<pimc::GenRecord> gen_recs;   // every level's records
-    std::vector<uint32_t> gen_grp;           // per level K+1 offsets into gen_recs
+    pimc::GenPotential gen;                  // derivative tables (coefficients in tab)
 };
 
 // Tables, bridge widths and straight-line reference actions of one problem after the mass

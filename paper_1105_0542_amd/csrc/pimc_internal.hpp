@@ -20,7 +20,7 @@ struct AmpArgs {
     int gstride;                       // generic shape: doubles per level table
     double a, b;                       // endpoints (after the mass rescaling)
     double alpha;                      // Poeschl-Teller: tanh argument scale (after the mass rescaling)
-    GenTables gen;                     // general-potential mode: records and derivative tables
+    GenTables gen;                     // general-potential mode: derivative tables (coefficients in tab64)
     const double* sig;                 // device: sigma_n = sqrt(T / 2^(n+1)), n = 0..s (0 unused)
     const double* shift;               // device: straight-line level action S_ref,n, n = 0..s
     RngKey key;
@@ -46,6 +46,12 @@ inline size_t amp_lds_bytes(int D, int s) {
 // Launch the estimation kernel; p selects the quartic specialization, U = s - D the unrolled
 // subtree depth. Returns hipErrorInvalidValue for an unsupported combination.
 hipError_t launch_amplitude(const AmpArgs& A, EvalKind kind, int p, int U, int grid, hipStream_t st);
+
+// General-potential mode (pimc_general_kernels.hip): the evaluators generated for level p; the
+// number of monomials of the level-p table (-1 outside 1..kGenMaxP).
+hipError_t launch_general_compiled(const AmpArgs& A, int p, int U, int grid, hipStream_t st);
+int general_compiled_resident(int p, int U, size_t lds_bytes, int device);
+int general_compiled_nrec(int p);
 
 // Raw standard normals of heap nodes 1..n_nodes for k_paths paths: out[path][node-1] (device).
 hipError_t launch_normals(const RngKey& key, uint64_t first_path, uint64_t k_paths, uint32_t n_nodes, double* out,

@@ -49,14 +49,10 @@ inline PolyD poly_mul(const PolyD& a, const PolyD& b) {
     return r;
 }
 
-// One monomial of a folded general-potential level: coef * prod_{i < nf} v[f[i]], v_j = V^(j)(mid);
-// nf is a multiple of 4, padded with the index of a slot that holds 1.
-struct GenRecord {
-    double coef;
-    uint8_t nf;
-    uint8_t f[15];
-};
-static_assert(sizeof(GenRecord) == 24, "record layout");
+// General-potential mode: highest level p, derivative order and number of sech^2 / Gaussian terms.
+constexpr int kGenMaxP = 10;
+constexpr int kGenMaxJ = 2 * kGenMaxP - 2;
+constexpr int kGenMaxTerms = 4;
 
 // c[m][k], 0 <= k <= m < p, FP64.
 struct Coefficients {
