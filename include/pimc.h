@@ -395,8 +395,9 @@ int pimc_evolution_matrix(pimc_ctx *ctx, const pimc_potential *V, double m, doub
 
 /* Lowest k energies E_n = -ln(lambda_n)/t of that matrix (host array E[k], ascending) and, if psi
  * is not NULL, the eigenfunctions on the grid (host psi[k][n], sum_i psi(x_i)^2 D = 1, the largest
- * |psi| positive). Lanczos with full reorthogonalization on the device (the matrix, n x n doubles,
- * and max_iter + 1 Lanczos vectors are allocated for the call), checked every 16 steps; stops when
+ * |psi| positive). Lanczos with full reorthogonalization on the device (the matrix as its upper
+ * 64 x 64 tiles, about n^2/2 doubles since it is exactly symmetric, and max_iter + 1 Lanczos vectors
+ * are allocated for the call), checked every 16 steps; stops when
  * every requested pair has |M y - theta y| <= tol * theta_0 (returns PIMC_OK) or after max_iter
  * steps (returns PIMC_WNOTCONVERGED with the best values). k in 1..min(n, PIMC_MAX_STATES),
  * max_iter in k+1..min(n, PIMC_MAX_LANCZOS), 0 < tol < 1. info may be NULL. */

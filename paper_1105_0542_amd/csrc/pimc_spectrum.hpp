@@ -22,6 +22,16 @@ struct SpecTable {
 // y = sm x, i, j < n (device M, ld >= n).
 hipError_t launch_evolution_matrix(const SpecTable& tb, double L, double D, double sm, double t, double pref,
                                    uint32_t n, double* M, uint64_t ld, hipStream_t st);
+// Packed symmetric storage: tiles (I, J), I <= J, of kTile x kTile doubles, row-major within a tile,
+// tile t at M + t * kTile^2 with map[t] = I << 16 | J in the order t = I*nb - I(I-1)/2 + (J - I),
+// nb = ceil(n / kTile); elements beyond n are zero.
+constexpr int kTile = 64;
+hipError_t launch_evolution_tiles(const SpecTable& tb, double L, double D, double sm, double t, double pref,
+                                  uint32_t n, const uint32_t* map, uint32_t ntiles, double* M, hipStream_t st);
+// y = M x from the packed tiles: partial products per tile (prow, pcol: ntiles * kTile doubles each)
+// then a fixed-order reduction per row block; x is read for indices < n only.
+hipError_t launch_symv_tiles(const double* M, const uint32_t* map, uint32_t ntiles, uint32_t nb, uint32_t n,
+                             const double* x, double* prow, double* pcol, double* y, hipStream_t st);
 // y = M x (ld even; M and x 16-byte aligned).
 hipError_t launch_gemv(const double* M, uint64_t ld, uint32_t n, const double* x, double* y, hipStream_t st);
 // out[c] = <Q_c, w>, c < ncols (Q_c = Q + c*ldq).

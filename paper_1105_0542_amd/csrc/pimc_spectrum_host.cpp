@@ -4,9 +4,10 @@
 // matrix of short-time transition amplitudes (Sec. 2, Sec. 5 with Fig. 3): on the grid
 // x_i = -L + (i + 1/2) D, D = 2L/n, M_ij = D A_1^(p)(x_i, x_j; t) approximates exp(-t H), so its
 // largest eigenvalues are exp(-t E_n). The matrix is built on the device from the level-p table at
-// eps = t; its largest eigenpairs come from a Lanczos iteration with full reorthogonalization
-// (classical Gram-Schmidt applied twice) run on the device, with the small tridiagonal problem
-// solved on the host by Sturm-sequence bisection (eigenvalues) and inverse iteration (vectors).
+// eps = t (for the eigenvalue iteration only its upper tiles: the matrix is exactly symmetric); its
+// largest eigenpairs come from a Lanczos iteration with full reorthogonalization (classical
+// Gram-Schmidt applied twice) run on the device, with the small tridiagonal problem solved on the
+// host by Sturm-sequence bisection (eigenvalues) and inverse iteration (vectors).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -180,9 +181,10 @@ int dev_alloc(pimc_ctx* c, DevBuf& b, size_t bytes) {
     return PIMC_OK;
 }
 
-// Problem, table upload and launch of the matrix kernel on the context stream.
+// Problem, table upload and launch of the matrix kernel on the context stream: the full matrix
+// (M, ld) or, with map != nullptr, the packed upper tiles.
 int build_matrix(pimc_ctx* c, const pimc_potential* V, double m, double t, int p, double L, uint32_t n, double* M,
-                 uint64_t ld, DevBuf& tabbuf) {
+                 uint64_t ld, DevBuf& tabbuf, const uint32_t* map = nullptr, uint32_t ntiles = 0) {
     Problem P;
     char why[256] = "";
     int st = build_problem(V, m, 0.0, 0.0, t, 1, p, 0, P, why, sizeof(why));
@@ -203,7 +205,10 @@ int build_matrix(pimc_ctx* c, const pimc_potential* V, double m, double t, int p
     const double D = 2.0 * L / double(n);
     const double sm = std::sqrt(m);
     const double pref = D * sm / std::sqrt(2.0 * M_PI * t);
-    HIP_TRY(c, launch_evolution_matrix(tb, L, D, sm, t, pref, n, M, ld, c->stream));
+    if (map)
+        HIP_TRY(c, launch_evolution_tiles(tb, L, D, sm, t, pref, n, map, ntiles, M, c->stream));
+    else
+        HIP_TRY(c, launch_evolution_matrix(tb, L, D, sm, t, pref, n, M, ld, c->stream));
     return PIMC_OK;
 }
 
@@ -242,8 +247,17 @@ int pimc_spectrum(pimc_ctx* c, const pimc_potential* V, double m, double t, int 
     if (!(tol > 0.0 && tol < 1.0)) return ctx_fail(c, PIMC_EINVAL, "tol outside (0, 1)");
     HIP_TRY(c, hipSetDevice(c->device));
     const uint64_t ld = (uint64_t(n) + 63) / 64 * 64;
-    DevBuf Mb, Qb, wb, ab, bb, hb, tab;
-    if ((st = dev_alloc(c, Mb, size_t(ld) * n * 8))) return st;
+    // the matrix as packed upper tiles (it is exactly symmetric): half the bytes per product
+    const uint32_t nb = (n + kTile - 1) / kTile;
+    const uint32_t ntiles = nb * (nb + 1) / 2;
+    std::vector<uint32_t> map(ntiles);
+    for (uint32_t I = 0, q = 0; I < nb; ++I)
+        for (uint32_t J = I; J < nb; ++J) map[q++] = (I << 16) | J;
+    DevBuf Mb, Qb, wb, ab, bb, hb, tab, mapb, prb, pcb;
+    if ((st = dev_alloc(c, Mb, size_t(ntiles) * kTile * kTile * 8))) return st;
+    if ((st = dev_alloc(c, mapb, size_t(ntiles) * 4))) return st;
+    if ((st = dev_alloc(c, prb, size_t(ntiles) * kTile * 8))) return st;
+    if ((st = dev_alloc(c, pcb, size_t(ntiles) * kTile * 8))) return st;
     if ((st = dev_alloc(c, Qb, size_t(ld) * (max_iter + 1) * 8))) return st;
     if ((st = dev_alloc(c, wb, size_t(ld) * 8))) return st;
     if ((st = dev_alloc(c, ab, size_t(max_iter) * 8))) return st;
@@ -255,8 +269,12 @@ int pimc_spectrum(pimc_ctx* c, const pimc_potential* V, double m, double t, int 
     double* alpha = static_cast<double*>(ab.p);
     double* beta = static_cast<double*>(bb.p);
     double* h = static_cast<double*>(hb.p);
+    const uint32_t* dmap = static_cast<const uint32_t*>(mapb.p);
+    double* prow = static_cast<double*>(prb.p);
+    double* pcol = static_cast<double*>(pcb.p);
+    HIP_TRY(c, hipMemcpyAsync(mapb.p, map.data(), map.size() * 4, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
-    if ((st = build_matrix(c, V, m, t, p, L, n, M, ld, tab))) return st;
+    if ((st = build_matrix(c, V, m, t, p, L, n, M, ld, tab, dmap, ntiles))) return st;
     HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
     // start vector: fixed pseudo-random, normalized on the host
     std::vector<double> q0(n);
@@ -280,7 +298,7 @@ int pimc_spectrum(pimc_ctx* c, const pimc_potential* V, double m, double t, int 
     const uint32_t check_every = 16;
     for (uint32_t j = 0; j < max_iter; ++j) {
         double* qj = Q + uint64_t(j) * ld;
-        HIP_TRY(c, launch_gemv(M, ld, n, qj, w, c->stream));
+        HIP_TRY(c, launch_symv_tiles(M, dmap, ntiles, nb, n, qj, prow, pcol, w, c->stream));
         HIP_TRY(c, launch_col_dots(qj, ld, n, 1, w, alpha + j, c->stream));
         HIP_TRY(c, launch_lanczos_recur(w, Q, ld, n, j, alpha, beta, c->stream));
         for (int pass = 0; pass < 2; ++pass) {
