@@ -145,6 +145,83 @@ def oracle_spectrum_reference():
     return out
 
 
+def _oracle_vector_worker(args):
+    dim, first, count = args
+    import numpy as np
+    from oracle import vector as ov
+    a, b = VECTOR["ends"][dim]
+    idx = np.arange(first, first + count, dtype=np.uint64)
+    ov.path_actions([0.0, 0.5, VECTOR["g"] / 24.0], dim, 1.0, a, b, VECTOR["T"], VECTOR["s"], VECTOR["p"], 1, 0, idx)
+    return count
+
+
+def _oracle_mpt_worker(args):
+    p, first, count = args
+    import numpy as np
+    from oracle import mpt
+    idx = np.arange(first, first + count, dtype=np.uint64)
+    mpt.path_actions(MPT["lam"], MPT["alpha"], 1.0, MPT["a"], MPT["b"], MPT["T"], MPT["s"], p, 1, 0, idx)
+    return count
+
+
+def _oracle_general_worker(args):
+    p, first, count = args
+    import numpy as np
+    from oracle import effective_action as ea
+    from oracle import general as og
+    idx = np.arange(first, first + count, dtype=np.uint64)
+    og.path_actions(p, 1.0, 10, 0.0, 1.0, 1, 0, idx, poly=[float(c) for c in ea.quartic(1, 10)])
+    return count
+
+
+def _timed_pool(worker, jobs):
+    import multiprocessing as mp
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        done = sum(pool.map(worker, jobs))
+    return done, time.perf_counter() - t0, cores
+
+
+def oracle_section_baselines(which):
+    """The oracle as it stands, timed on the host cores on bounded samples of the workloads of the
+    several-coordinate, Poeschl-Teller, general-potential and spectrum sections (each a few seconds)."""
+    out = {}
+    sl = slices_per_sample(10, True)
+    if "vector" in which:
+        out["vector"] = {}
+        for dim in (2, 3):
+            n, dt, cores = _timed_pool(_oracle_vector_worker, [(dim, 256 * i, 256) for i in range(16)])
+            out["vector"][str(dim)] = {"value": n * sl / dt, "unit": "slice-evals/s", "cores": cores, "kind": "oracle",
+                                       "sample": f"first {n} paths of the d={dim} workload (p=18, s=10, every level), "
+                                                 f"{dt:.1f} s wall"}
+    if "mpt" in which:
+        n, dt, cores = _timed_pool(_oracle_mpt_worker, [(10, 1024 * i, 1024) for i in range(16)])
+        out["mpt"] = {"value": n * sl / dt, "unit": "slice-evals/s", "cores": cores, "kind": "oracle",
+                      "sample": f"first {n} paths at p=10 (s=10, every level), {dt:.1f} s wall"}
+    if "general" in which:
+        n, dt, cores = _timed_pool(_oracle_general_worker, [(8, 512 * i, 512) for i in range(16)])
+        out["general"] = {"value": n * sl / dt, "unit": "slice-evals/s", "cores": cores, "kind": "oracle",
+                          "sample": f"first {n} paths of the quartic in the derivative-symbol mode (p=8, s=10, "
+                                    f"every level), {dt:.1f} s wall"}
+    if "spectrum" in which:
+        import numpy as np
+        from oracle import effective_action as ea
+        from oracle import spectrum as osp
+        n = 2048
+        case = SPECTRUM[0]
+        t0 = time.perf_counter()
+        M, _, _ = osp.evolution_matrix(ea.quartic(case["A"], case["g"]), 1.0, case["t"], SPEC_P, case["L"], n)
+        t1 = time.perf_counter()
+        np.linalg.eigh(M)
+        t2 = time.perf_counter()
+        out["spectrum"] = {"value": n * (n + 1) / 2 / (t1 - t0), "unit": "distinct matrix elements/s", "cores": 1,
+                           "kind": "oracle", "eigh_s": t2 - t1,
+                           "sample": f"{case['name']} at n={n} (the matrix of the oracle, then numpy's dense eigh), "
+                                     f"{t1 - t0:.1f} s + {t2 - t1:.1f} s wall"}
+    return out
+
+
 def oracle_mpt_reference():
     """A(-0.5, 0.5; 1) of the Poeschl-Teller workload by the oracle's DVR diagonalization (CPU)."""
     from oracle import closed_forms as cf
@@ -180,7 +257,7 @@ def _fit_continuum(levels, p):
     return float(coef[0]), float(math.sqrt(max(cov[0, 0], 0.0)))
 
 
-def mpt_section(P, ctx, dvr):
+def mpt_section(P, ctx, dvr, base=None):
     """Convergence of A_N^(p) with N for the Poeschl-Teller potential at p = 1, 2, 10 (Fig. 2),
     eq.(fit) extrapolations, and the DVR continuum value when given."""
     M = MPT
@@ -201,10 +278,12 @@ def mpt_section(P, ctx, dvr):
         out["per_p"][str(p)] = row
     if dvr is not None:
         out["dvr_continuum"] = dvr
+    if base is not None:
+        out["cpu_baseline"] = base
     return out
 
 
-def general_section(P, ctx):
+def general_section(P, ctx, base=None):
     """Cost of the general-potential (derivative-symbol) mode against the specialized quartic
     kernel on the same problem, and a non-polynomial potential (Gaussian barrier in an oscillator);
     p = 8, every level of s = 10, 1e7 samples."""
@@ -226,10 +305,13 @@ def general_section(P, ctx):
     ms_b = ctx.last_kernel_ms()
     rows["gaussian_barrier"] = {"potential": "q^2/2 + 2 exp(-q^2), A(-0.3, 0.4; 1)",
                                 "slice_evals_per_s": sl / (ms_b / 1e3), "A_1024": res_b[s].amp, "err": res_b[s].err}
-    return {"workload": f"p={p}, s={s} (every level), {n:.0e} samples", **rows}
+    out = {"workload": f"p={p}, s={s} (every level), {n:.0e} samples", **rows}
+    if base is not None:
+        out["cpu_baseline"] = base
+    return out
 
 
-def vector_section(P, ctx, dvr):
+def vector_section(P, ctx, dvr, base=None):
     """Several coordinates: A_N^(18) of the 2D and 3D anharmonic oscillators from one s = 10 run each
     (every level), the kernel rate against the FP64 vector peak, and the 2D value against the DVR."""
     V = VECTOR
@@ -250,11 +332,13 @@ def vector_section(P, ctx, dvr):
         if dim == 2 and dvr is not None:
             row["dvr_continuum"] = dvr
             row["A_N_minus_dvr_over_err"] = [(r.amp - dvr) / r.err if r.err > 0 else None for r in res]
+        if base is not None:
+            row["cpu_baseline"] = base[str(dim)]
         out["per_dim"][str(dim)] = row
     return out
 
 
-def spectrum_section(P, ctx, dvr):
+def spectrum_section(P, ctx, dvr, base=None):
     """Matrix build (ALU: level-p Horner + exp per element) and Lanczos (HBM: one pass over the
     matrix per step) for the spectrum workloads; levels against the DVR reference when given."""
     rows = []
@@ -285,6 +369,8 @@ def spectrum_section(P, ctx, dvr):
         if dvr is not None:
             ref = np.asarray(dvr[ci])
             row["max_abs_diff_vs_dvr"] = float(np.max(np.abs(np.asarray(E) - ref)))
+        if base is not None and ci == 0:
+            row["cpu_baseline"] = base
         rows.append(row)
     return rows
 
@@ -413,6 +499,12 @@ def main():
     spec_ref = None if (skip_cpu and not args.only_spectrum) else oracle_spectrum_reference()
     mpt_ref = None if (skip_cpu and not args.only_mpt) else oracle_mpt_reference()
     vec_ref = None if (skip_cpu and not args.only_vector) else oracle_vector_reference()
+    wanted = []
+    for name, only in (("vector", args.only_vector), ("mpt", args.only_mpt), ("general", args.only_general),
+                       ("spectrum", args.only_spectrum)):
+        if (not skip_cpu or only) and not args.no_cpu_baseline:
+            wanted.append(name)
+    bases = oracle_section_baselines(wanted) if wanted else {}
 
     import paper_1105_0542_amd as P
 
@@ -423,19 +515,19 @@ def main():
         ctx.close()
         return
     if args.only_spectrum:
-        print(json.dumps({"spectrum": spectrum_section(P, ctx, spec_ref)}), flush=True)
+        print(json.dumps({"spectrum": spectrum_section(P, ctx, spec_ref, bases.get("spectrum"))}), flush=True)
         ctx.close()
         return
     if args.only_mpt:
-        print(json.dumps({"mpt": mpt_section(P, ctx, mpt_ref)}), flush=True)
+        print(json.dumps({"mpt": mpt_section(P, ctx, mpt_ref, bases.get("mpt"))}), flush=True)
         ctx.close()
         return
     if args.only_general:
-        print(json.dumps({"general": general_section(P, ctx)}), flush=True)
+        print(json.dumps({"general": general_section(P, ctx, bases.get("general"))}), flush=True)
         ctx.close()
         return
     if args.only_vector:
-        print(json.dumps({"vector": vector_section(P, ctx, vec_ref)}), flush=True)
+        print(json.dumps({"vector": vector_section(P, ctx, vec_ref, bases.get("vector"))}), flush=True)
         ctx.close()
         return
     N = 1 << S_DEPTH
@@ -536,10 +628,10 @@ def main():
         bt.close()
 
     flow_line = proposal_section(P, ctx, args.flow_steps) if args.flow_steps > 0 else None
-    spec_line = spectrum_section(P, ctx, spec_ref)
-    mpt_line = mpt_section(P, ctx, mpt_ref)
-    gen_line = general_section(P, ctx)
-    vec_line = vector_section(P, ctx, vec_ref)
+    spec_line = spectrum_section(P, ctx, spec_ref, bases.get("spectrum"))
+    mpt_line = mpt_section(P, ctx, mpt_ref, bases.get("mpt"))
+    gen_line = general_section(P, ctx, bases.get("general"))
+    vec_line = vector_section(P, ctx, vec_ref, bases.get("vector"))
 
     line = {
         "metric": "slice-evals/s (p=18, FP64)",
