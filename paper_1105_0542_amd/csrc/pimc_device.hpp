@@ -275,6 +275,50 @@ struct TanhEval64 {
     }
 };
 
+// The same tables with their shape fixed at compile time: the Poeschl-Teller fold has K = P groups
+// P_k(u) of degree P each (P(P+1) coefficients per level), so the Horner loops unroll and each
+// group's coefficients are scalar-loaded where they are used. Same operations in the same order as
+// TanhEval64 (bitwise equal results).
+template <int P>
+struct TanhEvalP {
+    static constexpr int E = P * (P + 1);
+    const double* __restrict__ tab;
+    double alpha;
+    __device__ __forceinline__ void launder() { asm volatile("" : "+s"(tab)); }
+    template <int W>
+    __device__ __forceinline__ void eval(int level, const double (&qa)[W], const double (&qb)[W], double& S) const {
+        const_ptr<double> t = as_const(tab) + level * E;
+        double u[W], z[W], acc[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            const double mid = 0.5 * (qa[i] + qb[i]);
+            const double dl = qb[i] - qa[i];
+            const double y = tanh(alpha * mid);
+            u[i] = y * y;
+            z[i] = dl * dl;
+            acc[i] = 0.0;
+        }
+#pragma unroll
+        for (int k = P - 1; k >= 0; --k) {
+            asm volatile("" : "+s"(t));
+            double v[W];
+            const double c0 = t[k * (P + 1)];
+#pragma unroll
+            for (int i = 0; i < W; ++i) v[i] = c0;
+#pragma unroll
+            for (int e = 1; e <= P; ++e) {
+                const double c = t[k * (P + 1) + e];
+#pragma unroll
+                for (int i = 0; i < W; ++i) v[i] = fma(v[i], u[i], c);
+            }
+#pragma unroll
+            for (int i = 0; i < W; ++i) acc[i] = (k == P - 1) ? v[i] : fma(acc[i], z[i], v[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < W; ++i) S += acc[i];
+    }
+};
+
 // General-potential mode: the derivative tables of V = poly + sum A/cosh^2(a x) + sum B exp(-b x^2)
 // (see pimc_general.hpp); the slice evaluators themselves are generated per p at build time
 // (pimc_general_device.hpp).

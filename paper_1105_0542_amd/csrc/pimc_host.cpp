@@ -251,6 +251,10 @@ int build_problem_mpt(double lambda, double alpha, double m, double a, double b,
     for (int d : ydeg) P.deg.push_back(d / 2);
     P.stride = 0;
     for (int d : P.deg) P.stride += d + 1;
+    // the usual shape (K = p groups of degree p) has compile-time kernels for N >= 16
+    bool fixed = P.U == 4 && p <= PIMC_MAX_P && int(P.deg.size()) == p;
+    for (int d : P.deg) fixed = fixed && d == p;
+    if (fixed) P.kind = EvalKind::Tanh64P;
     P.tab.assign(size_t(P.s + 1) * size_t(P.stride), 0.0);
     std::vector<LevelTable> levels;
     for (int n = 0; n <= P.s; ++n) {

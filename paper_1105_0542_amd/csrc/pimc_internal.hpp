@@ -35,7 +35,9 @@ struct AmpArgs {
     double* dump;                      // device [path][s+1] or null
 };
 
-enum class EvalKind { Quartic64, Quartic32, GenericEven64, GenericOdd64, Tanh64, General64 };
+// Tanh64P: the Poeschl-Teller tables with the compile-time shape of level p (K = p groups of degree
+// p), U = 4.
+enum class EvalKind { Quartic64, Quartic32, GenericEven64, GenericOdd64, Tanh64, Tanh64P, General64 };
 
 // Dynamic LDS bytes of the estimation kernel: per lane, 3D+2 slots of the explicit stack; per wave
 // and level, three accumulators.

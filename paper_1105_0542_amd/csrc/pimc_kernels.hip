@@ -160,6 +160,27 @@ static hipError_t launch_generic(const AmpArgs& A, int U, int grid, hipStream_t 
     }
 }
 
+template <int P>
+static hipError_t launch_tanh_fixed(const AmpArgs& A, int p, int grid, hipStream_t st) {
+    if constexpr (P <= kMaxP) {
+        if (p != P) return launch_tanh_fixed<P + 1>(A, p, grid, st);
+        TanhEvalP<P> ev{A.tab64, A.alpha};
+        return launch_one<4>(A, ev, grid, st);
+    } else {
+        return hipErrorInvalidValue;
+    }
+}
+
+template <int P>
+static int resident_tanh_fixed(int p, size_t lds, int device) {
+    if constexpr (P <= kMaxP) {
+        if (p != P) return resident_tanh_fixed<P + 1>(p, lds, device);
+        return resident_one<4, TanhEvalP<P>>(lds, device);
+    } else {
+        return 256;
+    }
+}
+
 static hipError_t launch_tanh(const AmpArgs& A, int U, int grid, hipStream_t st) {
     TanhEval64 ev{A.tab64, A.gdeg, A.gK, A.gstride, A.alpha};
     switch (U) {
@@ -191,6 +212,9 @@ hipError_t launch_amplitude(const AmpArgs& A, EvalKind kind, int p, int U, int g
         case EvalKind::GenericEven64: return launch_generic<true>(A, U, grid, st);
         case EvalKind::GenericOdd64: return launch_generic<false>(A, U, grid, st);
         case EvalKind::Tanh64: return launch_tanh(A, U, grid, st);
+        case EvalKind::Tanh64P:
+            if (U != 4) return hipErrorInvalidValue;
+            return launch_tanh_fixed<1>(A, p, grid, st);
         case EvalKind::General64: return launch_general_compiled(A, p, U, grid, st);
     }
     return hipErrorInvalidValue;
@@ -275,6 +299,8 @@ int amplitude_resident_blocks(EvalKind kind, int p, int U, size_t lds_bytes, int
                 case 3: return resident_one<3, TanhEval64>(lds_bytes, device);
                 default: return resident_one<4, TanhEval64>(lds_bytes, device);
             }
+        case EvalKind::Tanh64P:
+            return resident_tanh_fixed<1>(p, lds_bytes, device);
         case EvalKind::General64:
             return general_compiled_resident(p, U, lds_bytes, device);
     }
