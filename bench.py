@@ -57,7 +57,7 @@ HBM_PEAK_GBS = 8000.0
 # Modified Poeschl-Teller potential (the paper's Fig. 2): V = -lambda/cosh^2(alpha q), lambda = alpha = 1,
 # A_N^(p)(-0.5, 0.5; 1) for p in {1, 2, 10} from one s = 10 run each (every N = 2^0..2^10).
 MPT = dict(lam=1.0, alpha=1.0, a=-0.5, b=0.5, T=1.0, s=10, ps=(1, 2, 10), samples=100_000_000)
-KERNEL_SOURCES = ["pimc_device.hpp", "pimc_kernels.hip", "pimc_walker.hpp", "pimc_internal.hpp", "pimc_tables.hpp",
+KERNEL_SOURCES = ["pimc_device.hpp", "pimc_kernels_q64.hip", "pimc_walker.hpp", "pimc_internal.hpp", "pimc_tables.hpp",
                   "pimc_math.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_amplitude_quartic64_p18_s10.json")
 

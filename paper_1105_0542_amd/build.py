@@ -16,7 +16,8 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpimc.so")
 CLI = os.path.join(PKG, "pimc")
 
-SOURCES = ["pimc_kernels.hip", "pimc_vector_d2.hip", "pimc_vector_d3.hip", "pimc_general_kernels.hip", "pimc_flow.hip",
+SOURCES = ["pimc_kernels_q64.hip", "pimc_kernels_q32.hip", "pimc_kernels_tanh.hip", "pimc_kernels_batch.hip",
+           "pimc_vector_d2.hip", "pimc_vector_d3.hip", "pimc_general_kernels.hip", "pimc_kernels.hip", "pimc_flow.hip",
            "pimc_spectrum.hip", "pimc_vector_d1.hip", "pimc_host.cpp", "pimc_flow_host.cpp", "pimc_spectrum_host.cpp",
            "pimc_general_host.cpp", "pimc_vector_host.cpp"]
 HEADERS = ["pimc_tables.hpp", "pimc_device.hpp", "pimc_internal.hpp", "pimc_math.hpp", "pimc_walker.hpp",

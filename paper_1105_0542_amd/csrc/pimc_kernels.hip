@@ -1,73 +1,13 @@
-// Estimation kernels of the bisection PIMC amplitude (Sec. 4 of Balaz et al.) for gfx950: the
-// instantiations of the walker (pimc_walker.hpp) for the polynomial, Poeschl-Teller and FP32 slice
-// evaluators, the persistent batched kernel, raw normals, the canonical chunk reduction and the
-// launch dispatch.
+// Estimation kernels of the bisection PIMC amplitude (Sec. 4 of Balaz et al.) for gfx950: the walker
+// (pimc_walker.hpp) with the runtime-shaped evaluators (any polynomial, Poeschl-Teller), raw normals,
+// the canonical chunk reduction and the launch dispatch. The compile-time shapes are instantiated
+// in pimc_kernels_fixed.hip (one translation unit per evaluator family, built in parallel) and the
+// batched kernel in pimc_kernels_batch.hip.
 #include <hip/hip_runtime.h>
 
 #include "pimc_walker.hpp"
 
 namespace pimc {
-
-// ---------------------------------------------------------------------------- batched tasks
-// Persistent kernel over the (task, chunk) items of one effective-action level p: each workgroup
-// takes `grab` consecutive items at a time from an atomic counter until the queue is empty (every
-// wave of every workgroup reaches the exit test with the same value). Items are numbered task by
-// task (task t owns items item0[t] .. item0[t] + n_chunks[t] - 1), so an item maps to its task by
-// binary search over the wave-uniform task records; the chunk itself is processed by the same code
-// as a single-task launch, so results do not depend on which workgroup took which item.
-__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
-    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(v));
-    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(v >> 32));
-    return (uint64_t(hi) << 32) | lo;
-}
-
-template <int U, class Eval>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PIMC_WAVES_PER_EU)))
-k_batch(const BatchTask* __restrict__ tasks, int n_tasks, uint64_t n_items, unsigned long long* queue,
-        uint32_t grab, RngKey key, int hier, Eval ev0) {
-    extern __shared__ double smem[];
-    __shared__ unsigned long long s_item;
-    const const_ptr<BatchTask> T = as_const(tasks);
-    while (true) {
-        __syncthreads();
-        if (threadIdx.x == 0) s_item = atomicAdd(queue, (unsigned long long)grab);
-        __syncthreads();
-        const uint64_t first = uniform_u64(s_item);
-        if (first >= n_items) break;
-        const uint64_t last = first + grab < n_items ? first + grab : n_items;
-        for (uint64_t item = first; item < last; ++item) {
-            int lo = 0, hi = n_tasks - 1;                  // last task with item0 <= item
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (T[mid].item0 <= item) lo = mid; else hi = mid - 1;
-            }
-            AmpArgs A;
-            A.tab64 = T[lo].tab;
-            A.tab32 = nullptr;
-            A.gdeg = nullptr;
-            A.gK = 0;
-            A.gstride = 0;
-            A.a = T[lo].a;
-            A.b = T[lo].b;
-            A.sig = T[lo].sig;
-            A.shift = T[lo].shift;
-            A.key = key;
-            A.key.stream = T[lo].stream;
-            A.first_path = 0;
-            A.n_paths = T[lo].n_paths;
-            A.n_chunks = T[lo].n_chunks;
-            A.ppl = T[lo].ppl;
-            A.s = T[lo].s;
-            A.D = T[lo].s - U;
-            A.hier = hier;
-            A.partials = T[lo].partials;
-            A.dump = nullptr;
-            Eval ev = ev0;
-            ev.tab = T[lo].tab;
-            process_chunk<U, Eval>(ev, A, item - T[lo].item0, smem);
-        }
-    }
-}
 
 __global__ void k_fill_u64(unsigned long long* p, int n, unsigned long long v) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -138,16 +78,6 @@ __global__ void __launch_bounds__(kBlock) k_seg_reduce(const double* __restrict_
 
 // ---------------------------------------------------------------------------- dispatch
 
-template <int P>
-static hipError_t launch_quartic(const AmpArgs& A, bool fp32, int grid, hipStream_t st) {
-    if (fp32) {
-        QuarticEval32<P> ev{A.tab32};
-        return launch_one<4>(A, ev, grid, st);
-    }
-    QuarticEval64<P> ev{A.tab64};
-    return launch_one<4>(A, ev, grid, st);
-}
-
 template <bool EVEN>
 static hipError_t launch_generic(const AmpArgs& A, int U, int grid, hipStream_t st) {
     GenericEval64<EVEN> ev{A.tab64, A.gdeg, A.gK, A.gstride};
@@ -157,27 +87,6 @@ static hipError_t launch_generic(const AmpArgs& A, int U, int grid, hipStream_t 
         case 3: return launch_one<3>(A, ev, grid, st);
         case 4: return launch_one<4>(A, ev, grid, st);
         default: return hipErrorInvalidValue;
-    }
-}
-
-template <int P>
-static hipError_t launch_tanh_fixed(const AmpArgs& A, int p, int grid, hipStream_t st) {
-    if constexpr (P <= kMaxP) {
-        if (p != P) return launch_tanh_fixed<P + 1>(A, p, grid, st);
-        TanhEvalP<P> ev{A.tab64, A.alpha};
-        return launch_one<4>(A, ev, grid, st);
-    } else {
-        return hipErrorInvalidValue;
-    }
-}
-
-template <int P>
-static int resident_tanh_fixed(int p, size_t lds, int device) {
-    if constexpr (P <= kMaxP) {
-        if (p != P) return resident_tanh_fixed<P + 1>(p, lds, device);
-        return resident_one<4, TanhEvalP<P>>(lds, device);
-    } else {
-        return 256;
     }
 }
 
@@ -193,28 +102,18 @@ static hipError_t launch_tanh(const AmpArgs& A, int U, int grid, hipStream_t st)
 }
 
 
-template <int P>
-static hipError_t quartic_dispatch(const AmpArgs& A, bool fp32, int p, int grid, hipStream_t st) {
-    if constexpr (P <= kMaxP) {
-        if (p == P) return launch_quartic<P>(A, fp32, grid, st);
-        return quartic_dispatch<P + 1>(A, fp32, p, grid, st);
-    } else {
-        return hipErrorInvalidValue;
-    }
-}
-
 hipError_t launch_amplitude(const AmpArgs& A, EvalKind kind, int p, int U, int grid, hipStream_t st) {
     switch (kind) {
         case EvalKind::Quartic64:
         case EvalKind::Quartic32:
             if (U != 4) return hipErrorInvalidValue;
-            return quartic_dispatch<1>(A, kind == EvalKind::Quartic32, p, grid, st);
+            return kind == EvalKind::Quartic32 ? launch_quartic32(A, p, grid, st) : launch_quartic64(A, p, grid, st);
         case EvalKind::GenericEven64: return launch_generic<true>(A, U, grid, st);
         case EvalKind::GenericOdd64: return launch_generic<false>(A, U, grid, st);
         case EvalKind::Tanh64: return launch_tanh(A, U, grid, st);
         case EvalKind::Tanh64P:
             if (U != 4) return hipErrorInvalidValue;
-            return launch_tanh_fixed<1>(A, p, grid, st);
+            return launch_tanh_fixed(A, p, grid, st);
         case EvalKind::General64: return launch_general_compiled(A, p, U, grid, st);
     }
     return hipErrorInvalidValue;
@@ -233,57 +132,12 @@ hipError_t launch_fill_u64(unsigned long long* p, int n, unsigned long long v, h
     return hipGetLastError();
 }
 
-template <int P>
-static hipError_t batch_quartic(const BatchTask* tasks, int n_tasks, uint64_t n_items, unsigned long long* queue,
-                                uint32_t grab, RngKey key, int hier, int p, int grid, size_t lds, hipStream_t st) {
-    if constexpr (P <= kMaxP) {
-        if (p != P) return batch_quartic<P + 1>(tasks, n_tasks, n_items, queue, grab, key, hier, p, grid, lds, st);
-        QuarticEval64<P> ev{nullptr};
-        hipLaunchKernelGGL((k_batch<4, QuarticEval64<P>>), dim3(grid), dim3(kBlock), lds, st, tasks, n_tasks, n_items,
-                           queue, grab, key, hier, ev);
-        return hipGetLastError();
-    } else {
-        return hipErrorInvalidValue;
-    }
-}
 
-hipError_t launch_batch(const BatchTask* tasks, int n_tasks, uint64_t n_items, unsigned long long* queue, uint32_t grab,
-                        const RngKey& key, int hier, int p, int grid, size_t lds, hipStream_t st) {
-    return batch_quartic<1>(tasks, n_tasks, n_items, queue, grab, key, hier, p, grid, lds, st);
-}
-
-template <int P>
-static int batch_resident(int p, size_t lds, int device) {
-    if constexpr (P <= kMaxP) {
-        if (p != P) return batch_resident<P + 1>(p, lds, device);
-        int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<4, QuarticEval64<P>>, kBlock, lds) != hipSuccess)
-            per_cu = 1;
-        int ncu = 0;
-        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) ncu = 256;
-        return (per_cu < 1 ? 1 : per_cu) * ncu;
-    } else {
-        return 256;
-    }
-}
-
-int batch_resident_blocks(int p, size_t lds_bytes, int device) { return batch_resident<1>(p, lds_bytes, device); }
-
-
-template <int P>
-static int resident_quartic(bool fp32, int p, size_t lds, int device) {
-    if constexpr (P <= kMaxP) {
-        if (p == P) return fp32 ? resident_one<4, QuarticEval32<P>>(lds, device) : resident_one<4, QuarticEval64<P>>(lds, device);
-        return resident_quartic<P + 1>(fp32, p, lds, device);
-    } else {
-        return 256;
-    }
-}
 
 int amplitude_resident_blocks(EvalKind kind, int p, int U, size_t lds_bytes, int device) {
     switch (kind) {
-        case EvalKind::Quartic64: return resident_quartic<1>(false, p, lds_bytes, device);
-        case EvalKind::Quartic32: return resident_quartic<1>(true, p, lds_bytes, device);
+        case EvalKind::Quartic64: return resident_quartic64(p, lds_bytes, device);
+        case EvalKind::Quartic32: return resident_quartic32(p, lds_bytes, device);
         case EvalKind::GenericEven64:
         case EvalKind::GenericOdd64:
             switch (U) {
@@ -300,7 +154,7 @@ int amplitude_resident_blocks(EvalKind kind, int p, int U, size_t lds_bytes, int
                 default: return resident_one<4, TanhEval64>(lds_bytes, device);
             }
         case EvalKind::Tanh64P:
-            return resident_tanh_fixed<1>(p, lds_bytes, device);
+            return resident_tanh_fixed(p, lds_bytes, device);
         case EvalKind::General64:
             return general_compiled_resident(p, U, lds_bytes, device);
     }

@@ -25,7 +25,14 @@ namespace pimc {
 
 constexpr int kVecMaxDim = 3;
 constexpr int kVecBlock = 256;          // lanes of a workgroup and of a canonical chunk
-constexpr int kVecU = 3;                // bisection levels of a register subtree (s >= 3)
+#ifndef PIMC_VEC_U
+#define PIMC_VEC_U 4
+#endif
+#ifndef PIMC_VEC_BATCH
+#define PIMC_VEC_BATCH 8
+#endif
+constexpr int kVecU = PIMC_VEC_U;       // bisection levels of a register subtree (s >= kVecU)
+constexpr int kVecBatch = PIMC_VEC_BATCH;   // slices evaluated together, coefficient-major
 constexpr uint32_t kCoordPairStride = 1u << 20;   // generator-call offset of coordinate c: c * 2^20
 
 // x-degree bound of W_{m,k}, m < P (the one-dimensional quartic degree table, maximized over m).

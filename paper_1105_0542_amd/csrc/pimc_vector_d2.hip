@@ -1,5 +1,5 @@
-// Vector estimation kernels, 2 coordinates: the compile-time shapes p = 1..18 (s >= 3) and the
-// shape-array evaluator (any p, s < 3).
+// Vector estimation kernels, 2 coordinates: the compile-time shapes p = 1..18 (s >= kVecU) and the
+// shape-array evaluator (any p, s < kVecU).
 #include "pimc_vector_impl.hpp"
 
 namespace pimc {

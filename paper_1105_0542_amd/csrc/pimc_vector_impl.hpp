@@ -203,7 +203,7 @@ __device__ __forceinline__ void level_sum(const Eval& ev, int level, const doubl
                                           double& S) {
     constexpr int W = 1 << L;
     constexpr int ST = 1 << (U - L);
-    constexpr int B = W < 8 ? W : 8;
+    constexpr int B = W < kVecBatch ? W : kVecBatch;
 #pragma unroll
     for (int b0 = 0; b0 < W; b0 += B) {
         double qa[B][DIM], qb[B][DIM];
@@ -442,6 +442,7 @@ inline hipError_t launch_rt(const VecArgs& A, int U, int grid, hipStream_t st) {
         case 1: return launch_one<DIM, 1>(A, ev, grid, st);
         case 2: return launch_one<DIM, 2>(A, ev, grid, st);
         case 3: return launch_one<DIM, 3>(A, ev, grid, st);
+        case 4: return launch_one<DIM, 4>(A, ev, grid, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -451,7 +452,8 @@ inline int resident_rt(int U, size_t lds, int device) {
     switch (U) {
         case 1: return resident_one<DIM, 1, RadialEvalRT<DIM>>(lds, device);
         case 2: return resident_one<DIM, 2, RadialEvalRT<DIM>>(lds, device);
-        default: return resident_one<DIM, 3, RadialEvalRT<DIM>>(lds, device);
+        case 3: return resident_one<DIM, 3, RadialEvalRT<DIM>>(lds, device);
+        default: return resident_one<DIM, 4, RadialEvalRT<DIM>>(lds, device);
     }
 }
 

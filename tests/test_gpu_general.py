@@ -46,6 +46,19 @@ def test_polynomial_through_derivatives_equals_polynomial_mode(ctx, s, p, flags)
         _close(g[:, n], r[:, n])
 
 
+@pytest.mark.parametrize("p", range(1, 11))
+def test_every_generated_level_equals_polynomial_mode(ctx, p):
+    """Every evaluator generated at build time (p = 1..10), with one-level (U = 1) and deeper walks,
+    on a degree-8 polynomial with odd terms, against the polynomial tables."""
+    coefs = [0.3, -0.2, 0.5, 0.1, 0.05, 0.0, 0.01, 0.0, 0.002]
+    k = 512
+    for s in (1, 3):
+        g = ctx.path_actions_general(1.0, -0.2, 0.7, 1.0, 1 << s, p, 6, 1, P.FLAG_HIERARCHY, 0, k, poly=coefs)
+        r = ctx.path_actions(coefs, 1.0, -0.2, 0.7, 1.0, 1 << s, p, 6, 1, P.FLAG_HIERARCHY, 0, k)
+        for n in range(0, s + 1):
+            _close(g[:, n], r[:, n])
+
+
 def test_sech2_through_derivatives_equals_poeschl_teller_mode(ctx):
     k = 1000
     g = ctx.path_actions_general(1.3, -0.5, 0.5, 1.0, 64, 8, 9, 1, P.FLAG_HIERARCHY, 0, k, sech2=((-2.0, 1.2),))
@@ -57,6 +70,8 @@ def test_sech2_through_derivatives_equals_poeschl_teller_mode(ctx):
 CASES = [  # m, a, b, T, s, p, poly, sech2, gauss
     (1.0, -0.3, 0.4, 1.0, 5, 6, (0, 0, 0.5), (), ((2.0, 1.0),)),                        # barrier in an oscillator
     (1.7, 0.2, -0.6, 0.5, 4, 8, (0.1, 0.2, 0.4, 0.0, 0.02), ((-1.0, 0.8),), ((0.5, 2.0), (-0.3, 0.5))),
+    (1.0, 0.1, 0.3, 0.5, 3, 4, (0, 0, 0.5), ((-1.0, 0.8), (0.5, 1.5), (-0.2, 2.0), (0.3, 0.5)),   # every term slot
+     ((0.5, 2.0), (-0.3, 0.5), (0.2, 1.0), (0.1, 3.0))),
 ]
 
 

@@ -38,6 +38,7 @@ CASES = [  # coefs, dim, m, a, b, T, s, p, flags, k
     (AHO6, 2, 1.0, (0.0, 0.0), (0.5, 0.3), 1.0, 5, 10, P.FLAG_HIERARCHY, 1500),        # compile-time shape
     ((0.3, 0.5, 1 / 24), 3, 2.0, (0.1, -0.2, 0.3), (0.4, 0.1, -0.5), 2.0, 6, 8, 0, 1500),
     ((0.0, 0.5), 2, 1.0, (0.2, 0.1), (-0.3, 0.6), 0.5, 2, 4, P.FLAG_HIERARCHY, 1500),  # shape array, U = 2
+    (AHO6, 2, 1.0, (0.1, 0.0), (0.3, -0.4), 1.0, 3, 9, P.FLAG_HIERARCHY, 1500),  # shape array, U = 3
     ((0.25, 1.0, 0.125), 1, 1.0, (0.3,), (-0.4,), 1.0, 7, 12, P.FLAG_HIERARCHY, 1500),  # one coordinate
     (AHO6, 3, 1.0, (0.0, 0.2, 0.0), (0.5, 0.0, -0.1), 0.7, 1, 18, P.FLAG_HIERARCHY, 1500),  # U = 1, p = 18
     ((0.0, 0.5, 48 / 24), 2, 1.0, (0.0, 0.0), (1.0, 0.0), 1.0, 10, 18, P.FLAG_HIERARCHY, 300),  # full size
@@ -85,7 +86,7 @@ def test_one_coordinate_equals_the_one_dimensional_kernel(ctx):
 
 def test_hierarchy_levels_equal_separate_runs(ctx):
     """Level n of an s-run is bitwise the n-run on the same paths (the bisection nests), across the
-    compile-time (s >= 3) and the shape-array (s < 3) evaluators. The amplitudes agree to rounding
+    compile-time (s >= 4) and the shape-array (s < 4) evaluators. The amplitudes agree to rounding
     (the canonical chunk holds 256 * 2^max(0, 10-s) paths, so the summation order depends on s)."""
     big = ctx.path_actions_radial(AHO6, 2, 1.0, (0.0, 0.0), (0.5, 0.3), 1.0, 64, 10, 2, 0, P.FLAG_HIERARCHY, 0, 3000)
     full, _ = ctx.amplitude_radial(AHO6, 2, 1.0, (0.0, 0.0), (0.5, 0.3), 1.0, 64, 10, 30000, 2, 0, P.FLAG_HIERARCHY)
@@ -105,7 +106,7 @@ def test_single_slice_is_the_short_time_amplitude(ctx):
 
 
 def test_largest_size_nests(ctx):
-    """Three coordinates at N = 2^20 (the deepest walk, 71 LDS slots per lane): levels 0..8 of the
+    """Three coordinates at N = 2^20 (the deepest walk, 67 LDS slots per lane): levels 0..8 of the
     per-path actions equal an s = 8 run of the same paths bitwise, and the finest level is finite."""
     big = ctx.path_actions_radial(AHO6, 3, 1.0, (0.0, 0.1, 0.0), (0.3, 0.0, 0.2), 1.0, 1 << 20, 6, 3, 1,
                                   P.FLAG_HIERARCHY, 0, 256)
