@@ -283,6 +283,13 @@ def mpt_section(P, ctx, dvr, base=None):
     return out
 
 
+# FP64 operations per slice of the general-mode evaluator at p = 8 for a polynomial potential, counted
+# in the code generated for that level: the monomial sums (173 fma, 226 products, 19 additions of
+# partial sums and Horner steps), 36 fma for the derivatives of the polynomial (degree-8 rows),
+# 15 + 1 level scalings, and mid-point, deviation, its square and the accumulation (4).
+GENERAL_FLOP_PER_SLICE_P8 = 2 * 173 + 226 + 19 + 2 * 36 + 16 + 4
+
+
 def general_section(P, ctx, base=None):
     """Cost of the general-potential (derivative-symbol) mode against the specialized quartic
     kernel on the same problem, and a non-polynomial potential (Gaussian barrier in an oscillator);
@@ -297,9 +304,13 @@ def general_section(P, ctx, base=None):
     sl = n * slices_per_sample(s, True)
     rows["quartic_g10_specialized"] = {"slice_evals_per_s": sl / (ms_q / 1e3), "A_1024": res_q[s].amp,
                                        "err": res_q[s].err}
+    tflops = sl * GENERAL_FLOP_PER_SLICE_P8 / (ms_g / 1e3) / 1e12
     rows["quartic_g10_general_mode"] = {"slice_evals_per_s": sl / (ms_g / 1e3), "A_1024": res_g[s].amp,
                                         "err": res_g[s].err,
-                                        "rel_diff_vs_specialized": abs(res_g[s].amp - res_q[s].amp) / res_q[s].amp}
+                                        "rel_diff_vs_specialized": abs(res_g[s].amp - res_q[s].amp) / res_q[s].amp,
+                                        "roofline": {"bound": "alu", "achieved": tflops, "peak": FP64_PEAK_TFLOPS,
+                                                     "unit": "TFLOP/s", "frac": tflops / FP64_PEAK_TFLOPS,
+                                                     "flop_per_slice": GENERAL_FLOP_PER_SLICE_P8}}
     res_b, _ = ctx.amplitude_general(1.0, -0.3, 0.4, 1.0, 1 << s, p, n, 1, 0, P.FLAG_HIERARCHY, poly=(0, 0, 0.5),
                                      gauss=((2.0, 1.0),))
     ms_b = ctx.last_kernel_ms()

@@ -2,9 +2,10 @@
 // v_j = V^(j)(x) (Sec. 3.1/3.2: for a general V the c_{m,k} are expressions in V and its
 // derivatives up to order 2p-2). eq.(1Drec) and eq.(diagonal) run on polynomials in v_0..v_J with
 // the derivation d v_j/dx = v_{j+1}; the result does not depend on V and is computed once per p.
-// Per bisection level the monomials get their coefficients (powers of eps folded in); the device
-// evaluators, generated from the same canonical monomial order at build time, form the products
-// of the derivative values at each slice mid-point and sum eps W_p = sum_k dlt^(2k) sum coef prod v_f.
+// In the dimensionless form (level_scales) the coefficients are the same at every bisection level and
+// only the derivative values and dlt^2 are scaled per level; the device evaluators, generated from the
+// same canonical monomial order at build time with the coefficients as constants, form the products
+// of the scaled derivative values at each slice mid-point and sum eps W_p.
 //
 // Potentials of this mode: V(x) = sum_n c_n x^n + sum_i A_i / cosh^2(a_i x) + sum_i B_i exp(-b_i x^2),
 // whose derivatives come from tables computed here: the polynomial's derivative coefficients, the
@@ -140,11 +141,14 @@ inline std::vector<GenMono> canonical_monomials(const SymCoefficients& C) {
     return out;
 }
 
-// Coefficients of one level (eps = T/2^n) in canonical order: c eps^(m-k+1) 4^-k, so that
-// eps W_p = sum_k dlt^(2k) sum_{monomials of k} coef prod v_f with dlt the full slice deviation.
-inline void level_coefficients(const std::vector<GenMono>& M, double eps, double* out) {
-    for (size_t r = 0; r < M.size(); ++r)
-        out[r] = M[r].c * std::pow(eps, double(M[r].m - M[r].k + 1)) * std::ldexp(1.0, -2 * M[r].k);
+// Per-level scale factors of the dimensionless form. A monomial of c_{m,k} with factor list f has
+// weight sum_f (j_f + 2) = 2m + 2, so its term eps^(m-k+1) 4^-k dlt^(2k) prod_f v_(j_f) equals
+// (dlt^2 / (4 eps))^k prod_f (eps^(1 + j_f/2) v_(j_f)): with the scaled derivatives
+// vt_j = eps^(1 + j/2) v_j and zt = dlt^2 / (4 eps), eps W_p = sum_k zt^k sum c prod vt_f, whose
+// coefficients c do not depend on the level. out[j] = eps^(1 + j/2) for j <= J, out[J+1] = 1/(4 eps).
+inline void level_scales(int J, double eps, double* out) {
+    for (int j = 0; j <= J; ++j) out[j] = std::pow(eps, 1.0 + 0.5 * double(j));
+    out[J + 1] = 0.25 / eps;
 }
 
 // Derivative tables of a potential of this mode (after the mass rescaling).
@@ -223,33 +227,57 @@ inline void gen_derivatives(const GenPotential& G, double x, double* v) {
     }
 }
 
-// eps W_p of one slice from the canonical monomials and one level's coefficients, with the products
-// formed as the compiled evaluators form them (prefix products left to right).
-inline double gen_eval_slice(const GenPotential& G, const std::vector<GenMono>& M, const double* coef, double qa,
+// Partial sums per power of zt in the generated evaluators: monomial r of a group goes to sum
+// r mod kGenAcc (its first term by a product, later ones by fma), and the sums are added pairwise,
+// (g0 + g1) + (g2 + g3).
+constexpr int kGenAcc = 4;
+
+inline double gen_group_sum(const double* g, int n) {
+    double t[kGenAcc];
+    for (int a = 0; a < n; ++a) t[a] = g[a];
+    while (n > 1) {
+        int m = 0;
+        for (int a = 0; a + 1 < n; a += 2) t[m++] = t[a] + t[a + 1];
+        if (n % 2) t[m++] = t[n - 1];
+        n = m;
+    }
+    return t[0];
+}
+
+// eps W_p of one slice from the canonical monomials and one level's scale factors (level_scales),
+// with the products and sums formed as the compiled evaluators form them (scaled derivatives, prefix
+// products left to right, kGenAcc partial sums per power of zt, Horner in zt).
+inline double gen_eval_slice(const GenPotential& G, const std::vector<GenMono>& M, const double* scales, double qa,
                              double qb) {
     const double x = 0.5 * (qa + qb);
     const double dl = qb - qa;
-    const double z = dl * dl;
+    const double z = dl * dl * scales[G.J + 1];
     std::vector<double> v(size_t(G.J) + 1);
     gen_derivatives(G, x, v.data());
-    double acc = 0.0, g = 0.0;
-    int k_cur = M.empty() ? -1 : M[0].k;
+    for (int j = 0; j <= G.J; ++j) v[size_t(j)] *= scales[j];
+    double acc = 0.0;
+    int k_prev = -1;
     bool first = true;
-    for (size_t r = 0; r <= M.size(); ++r) {
-        if (r == M.size() || M[r].k != k_cur) {
-            acc = first ? g : std::fma(acc, z, g);
-            first = false;
-            if (r == M.size()) break;
-            for (int k = k_cur - 1; k > M[r].k; --k) acc = acc * z;   // an empty group in between
-            k_cur = M[r].k;
-            g = 0.0;
+    for (size_t r0 = 0; r0 < M.size();) {
+        size_t r1 = r0;
+        while (r1 < M.size() && M[r1].k == M[r0].k) ++r1;
+        if (!first)
+            for (int k = k_prev - 1; k > M[r0].k; --k) acc = acc * z;   // a k without monomials
+        double g[kGenAcc] = {};
+        for (size_t r = r0; r < r1; ++r) {
+            const std::vector<uint8_t>& f = M[r].f;
+            double t = v[f[0]];
+            for (size_t i = 1; i < f.size(); ++i) t = t * v[f[i]];
+            const size_t a = (r - r0) % size_t(kGenAcc);
+            g[a] = r - r0 < size_t(kGenAcc) ? M[r].c * t : std::fma(M[r].c, t, g[a]);
         }
-        const std::vector<uint8_t>& f = M[r].f;
-        double t = v[f[0]];
-        for (size_t i = 1; i < f.size(); ++i) t = t * v[f[i]];
-        g = std::fma(coef[r], t, g);
+        const double sum = gen_group_sum(g, int(std::min(r1 - r0, size_t(kGenAcc))));
+        acc = first ? sum : std::fma(acc, z, sum);
+        first = false;
+        k_prev = M[r0].k;
+        r0 = r1;
     }
-    for (int k = k_cur - 1; k >= 0; --k) acc = acc * z;
+    for (int k = k_prev - 1; k >= 0; --k) acc = acc * z;
     return acc;
 }
 

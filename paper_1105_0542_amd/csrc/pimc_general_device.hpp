@@ -1,9 +1,10 @@
 // General-potential mode on the device: per slice, the derivatives v_j = V^(j)(mid), j <= J = 2p-2,
 // in registers (from the tables of pimc_general.hpp: the polynomial part by Horner per derivative,
 // one tanh per sech^2 term with the polynomials S_j(tanh), one exp per Gaussian term with the
-// Hermite recurrence), then eps W_p = sum_k dlt^(2k) sum coef prod v_f by the straight-line code
-// generated for level p at build time (GenCompiled<p>, pimc_general_gen.hpp), whose coefficients
-// are the level's table in the canonical monomial order (scalar loads).
+// Hermite recurrence), scaled per bisection level to vt_j = eps^(1 + j/2) v_j, then
+// eps W_p = sum_k zt^k sum c prod vt_f with zt = dlt^2 / (4 eps) by the straight-line code generated
+// for level p at build time (GenCompiled<p>, pimc_general_gen.hpp), whose coefficients c are
+// compile-time constants (the same at every level); the per-level scale factors are scalar loads.
 #pragma once
 
 #include "pimc_device.hpp"
@@ -17,25 +18,22 @@ struct GenCompiled;
 
 namespace pimc {
 
-// Slices evaluated together by the generated code (each holds J+1 derivative values in registers).
-#ifndef PIMC_GEN_SLICES
-#define PIMC_GEN_SLICES 2
-#endif
-constexpr int kGenSlices = PIMC_GEN_SLICES;
-
 template <int J>
 __device__ __forceinline__ void gen_derivatives_dev(const GenTables& g, double x, double (&v)[J + 1]) {
+    // V^(j) of the polynomial part (degree <= 8, zero-padded rows: a leading zero coefficient leaves
+    // the Horner value unchanged), fully unrolled so that the wave-uniform coefficients are
+    // independent scalar loads
     const const_ptr<double> dp = as_const(g.dpoly);
+    constexpr int JP = J < 8 ? J : 8;
 #pragma unroll
-    for (int j = 0; j <= J; ++j) {
-        const int dg = g.pdeg - j;
-        double acc = 0.0;
-        if (dg >= 0) {
-            acc = dp[j * 9 + dg];
-            for (int n = dg - 1; n >= 0; --n) acc = fma(acc, x, dp[j * 9 + n]);
-        }
+    for (int j = 0; j <= JP; ++j) {
+        double acc = dp[j * 9 + 8 - j];
+#pragma unroll
+        for (int n = 7 - j; n >= 0; --n) acc = fma(acc, x, dp[j * 9 + n]);
         v[j] = acc;
     }
+#pragma unroll
+    for (int j = JP + 1; j <= J; ++j) v[j] = 0.0;
     const const_ptr<double> ds = as_const(g.dsech);
     for (int t = 0; t < g.n_sech; ++t) {
         const double th = tanh(g.sech_a[t] * x);
@@ -67,7 +65,7 @@ __device__ __forceinline__ void gen_derivatives_dev(const GenTables& g, double x
 template <int P>
 struct GenCompiledEval {
     static constexpr int J = 2 * P - 2;
-    const double* __restrict__ tab;      // level-major, GenCompiled<P>::NREC coefficients per level
+    const double* __restrict__ tab;      // level-major, J + 2 per level: eps^(1 + j/2), j <= J, then 1/(4 eps)
     GenTables g;
     __device__ __forceinline__ void launder() { asm volatile("" : "+s"(tab)); }
     template <int W>
@@ -76,8 +74,9 @@ struct GenCompiledEval {
         // the level is wave-uniform (the walk does not depend on the lane): keep the table address in
         // scalar registers
         const int lv = __builtin_amdgcn_readfirstlane(level);
-        const_ptr<double> t = as_const(tab) + lv * GenCompiled<P>::NREC;
-        constexpr int B = W < kGenSlices ? W : kGenSlices;
+        const_ptr<double> t = as_const(tab) + lv * (J + 2);
+        // slices evaluated together (each holds J+1 derivative values in registers)
+        constexpr int B = W < gen_block_slices(P) ? W : gen_block_slices(P);
 #pragma unroll
         for (int b0 = 0; b0 < W; b0 += B) {
             double v[B][J + 1], z[B], acc[B];
@@ -85,10 +84,12 @@ struct GenCompiledEval {
             for (int i = 0; i < B; ++i) {
                 const double x = 0.5 * (qa[b0 + i] + qb[b0 + i]);
                 const double dl = qb[b0 + i] - qa[b0 + i];
-                z[i] = dl * dl;
+                z[i] = dl * dl * t[J + 1];
                 gen_derivatives_dev<J>(g, x, v[i]);
+#pragma unroll
+                for (int j = 0; j <= J; ++j) v[i][j] *= t[j];
             }
-            GenCompiled<P>::template eval<B>(t, v, z, acc);
+            GenCompiled<P>::template eval<B>(v, z, acc);
 #pragma unroll
             for (int i = 0; i < B; ++i) S += acc[i];
         }

@@ -1,7 +1,7 @@
 // Host side of the general-potential entry points (pimc_amplitude_general, pimc_path_actions_general
 // in include/pimc.h): the derivative-symbol coefficients of eq.(1Drec)/(diagonal), computed once
 // per p and cached, their monomials in the canonical order of the evaluators generated at build time,
-// one coefficient table per bisection level; the derivative tables of the potential after the mass
+// the scale factors of each bisection level; the derivative tables of the potential after the mass
 // rescaling; the straight-line reference actions. Estimation and per-path actions then run through
 // the shared walker kernels with the evaluator of level p.
 #include <hip/hip_runtime.h>
@@ -43,14 +43,14 @@ const LevelMonomials& cached_monomials(int p) {
     return *it->second;
 }
 
-double straight_line_general(const GenPotential& G, const std::vector<GenMono>& M, const double* coef, double a,
+double straight_line_general(const GenPotential& G, const std::vector<GenMono>& M, const double* scales, double a,
                              double b, int n) {
     const int N = 1 << n;
     double acc = 0.0;
     for (int k = 0; k < N; ++k) {
         const double q0 = a + (b - a) * double(k) / double(N);
         const double q1 = a + (b - a) * double(k + 1) / double(N);
-        acc += gen_eval_slice(G, M, coef, q0, q1);
+        acc += gen_eval_slice(G, M, scales, q0, q1);
     }
     return acc;
 }
@@ -107,7 +107,7 @@ int build_problem_general(const pimc_general_potential* V, double m, double a, d
     P.K0 = std::exp(-(P.b - P.a) * (P.b - P.a) / (2.0 * T)) / std::sqrt(2.0 * M_PI * T);
     P.even = false;
     P.kind = EvalKind::General64;
-    P.U = std::min(P.s, 2);
+    P.U = std::min(P.s, gen_subtree_levels(p));
     if (P.s == 0) P.U = 0;
     P.D = P.s - P.U;
     // the potential after the mass rescaling V(y / sqrt(m))
@@ -141,9 +141,10 @@ int build_problem_general(const pimc_general_potential* V, double m, double a, d
         return PIMC_EUNSUPPORTED;
     }
     P.deg.clear();
-    P.stride = nrec;
-    P.tab.assign(size_t(P.s + 1) * size_t(nrec), 0.0);
-    for (int n = 0; n <= P.s; ++n) level_coefficients(L.M, std::ldexp(T, -n), P.tab.data() + size_t(n) * size_t(nrec));
+    const int stride = G.J + 2;
+    P.stride = stride;
+    P.tab.assign(size_t(P.s + 1) * size_t(stride), 0.0);
+    for (int n = 0; n <= P.s; ++n) level_scales(G.J, std::ldexp(T, -n), P.tab.data() + size_t(n) * size_t(stride));
     P.tab_dev = P.tab;
     P.tab32.assign(P.tab.size(), 0.0f);
     P.sig.assign(size_t(P.s + 1), 0.0);
@@ -151,7 +152,7 @@ int build_problem_general(const pimc_general_potential* V, double m, double a, d
     P.shift.assign(size_t(P.s + 1), 0.0);
     for (int n = 0; n <= P.s; ++n)
         P.shift[size_t(n)] =
-            straight_line_general(G, L.M, P.tab.data() + size_t(n) * size_t(nrec), P.a, P.b, n);
+            straight_line_general(G, L.M, P.tab.data() + size_t(n) * size_t(stride), P.a, P.b, n);
     P.level0_action = P.shift[0];
     return PIMC_OK;
 }

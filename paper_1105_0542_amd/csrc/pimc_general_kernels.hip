@@ -1,6 +1,6 @@
 // Estimation kernels of the general-potential mode: the walker (pimc_walker.hpp) instantiated with
-// the evaluators generated for p = 1..kGenMaxP (pimc_general_device.hpp), U = 1 or 2 (measured best: larger subtrees or slice batches
-// raise the register pressure of the generated code and run slower).
+// the evaluators generated for p = 1..kGenMaxP (pimc_general_device.hpp), subtrees of
+// U = 1..gen_subtree_levels(p) levels.
 #include <hip/hip_runtime.h>
 
 #include "pimc_general_device.hpp"
@@ -17,9 +17,10 @@ hipError_t launch_p(const AmpArgs& A, int p, int U, int grid, hipStream_t st) {
         const GenCompiledEval<P> ev{A.tab64, A.gen};
         switch (U) {
             case 1: return launch_one<1>(A, ev, grid, st);
-            case 2: return launch_one<2>(A, ev, grid, st);
-            default: return hipErrorInvalidValue;
+            case 2: if constexpr (gen_subtree_levels(P) >= 2) return launch_one<2>(A, ev, grid, st); else break;
+            default: break;
         }
+        return hipErrorInvalidValue;
     } else {
         return hipErrorInvalidValue;
     }
@@ -29,7 +30,11 @@ template <int P>
 int resident_p(int p, int U, size_t lds, int device) {
     if constexpr (P <= kGenMaxP) {
         if (p != P) return resident_p<P + 1>(p, U, lds, device);
-        return U == 1 ? resident_one<1, GenCompiledEval<P>>(lds, device) : resident_one<2, GenCompiledEval<P>>(lds, device);
+        switch (U) {
+            case 2: if constexpr (gen_subtree_levels(P) >= 2) return resident_one<2, GenCompiledEval<P>>(lds, device); else break;
+            default: break;
+        }
+        return resident_one<1, GenCompiledEval<P>>(lds, device);
     } else {
         return 256;
     }

@@ -24,4 +24,28 @@ def test_generated_evaluators_equal_direct_evaluation(tmp_path):
     out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split()
     errs = [float(x) for x in out]
     assert len(errs) == 10
-    assert max(errs) < 1e-15, errs
+    assert max(errs) < 1e-14, errs
+
+
+def test_general_flop_count_of_bench_matches_generated_code():
+    """The FP64 operation count per slice that the bench uses for the general mode at p = 8 is the
+    count of the operations in the code generated for that level (plus the fixed per-slice work)."""
+    import re
+    import sys
+    gen = os.path.join(BUILD, "pimc_general_gen.hpp")
+    if not os.path.exists(gen):
+        pytest.skip("library not built")
+    src = open(gen).read()
+    body = src[src.index("struct GenCompiled<8>"):]
+    body = body[:body.index("};")]
+    lines = [ln for ln in body.splitlines() if "for (int i" in ln]
+    fma = sum(ln.count("fma(") for ln in lines)
+    mul = sum(ln.count(" * ") for ln in lines)
+    add = sum(ln.count(" + ") for ln in lines)
+    J = 14
+    poly = sum(8 - j for j in range(min(J, 8) + 1))
+    expected = 2 * fma + mul + add + 2 * poly + (J + 1) + 1 + 4
+    sys.path.insert(0, ROOT)
+    import bench
+    assert bench.GENERAL_FLOP_PER_SLICE_P8 == expected, (fma, mul, add)
+    assert re.search(r"NREC = 193;", body)
