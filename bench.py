@@ -269,9 +269,14 @@ def mpt_section(P, ctx, dvr, base=None):
                                     1, 0, P.FLAG_HIERARCHY)
         ms = ctx.last_kernel_ms()
         A, dA = _fit_continuum(list(enumerate(res)), p)
+        rate = M["samples"] * slices_per_sample(M["s"], True) / (ms / 1e3)
+        # FP64 operations per slice of the Poeschl-Teller evaluator: p groups of degree p in
+        # u = tanh^2 (p^2 fma), p - 1 Horner steps in dlt^2, mid-point, deviation, the two squares and
+        # the accumulation (6); the tanh itself (about 40 operations) is not counted
+        flop = 2 * p * p + 2 * (p - 1) + 6
         row = {"A_N": [r.amp for r in res], "err_N": [r.err for r in res], "fit_A": A, "fit_err": dA,
-               "kernel_ms": ms, "slice_evals_per_s": M["samples"] * slices_per_sample(M["s"], True) / (ms / 1e3),
-               "status": st}
+               "kernel_ms": ms, "slice_evals_per_s": rate, "flop_per_slice": flop,
+               "fp64_frac": rate * flop / 1e12 / FP64_PEAK_TFLOPS, "status": st}
         if dvr is not None:
             row["A_N_minus_dvr_over_err_at_N1024"] = (res[M["s"]].amp - dvr) / res[M["s"]].err
             row["fit_minus_dvr_over_err"] = (A - dvr) / dA if dA > 0 else None

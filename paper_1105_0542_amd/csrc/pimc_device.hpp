@@ -249,7 +249,7 @@ struct TanhEval64 {
         for (int i = 0; i < W; ++i) {
             const double mid = 0.5 * (qa[i] + qb[i]);
             const double dl = qb[i] - qa[i];
-            const double y = tanh(alpha * mid);
+            const double y = tanh_fp64(alpha * mid);
             u[i] = y * y;
             z[i] = dl * dl;
             acc[i] = 0.0;
@@ -293,7 +293,7 @@ struct TanhEvalP {
         for (int i = 0; i < W; ++i) {
             const double mid = 0.5 * (qa[i] + qb[i]);
             const double dl = qb[i] - qa[i];
-            const double y = tanh(alpha * mid);
+            const double y = tanh_fp64(alpha * mid);
             u[i] = y * y;
             z[i] = dl * dl;
             acc[i] = 0.0;

@@ -36,7 +36,7 @@ __device__ __forceinline__ void gen_derivatives_dev(const GenTables& g, double x
     for (int j = JP + 1; j <= J; ++j) v[j] = 0.0;
     const const_ptr<double> ds = as_const(g.dsech);
     for (int t = 0; t < g.n_sech; ++t) {
-        const double th = tanh(g.sech_a[t] * x);
+        const double th = tanh_fp64(g.sech_a[t] * x);
 #pragma unroll
         for (int j = 0; j <= J; ++j) {
             const int row = (t * (J + 1) + j) * (J + 3);
@@ -49,7 +49,7 @@ __device__ __forceinline__ void gen_derivatives_dev(const GenTables& g, double x
     for (int t = 0; t < g.n_gauss; ++t) {
         // d^j/dx^j B e^{-b x^2} = B (-sqrt b)^j H_j(sqrt(b) x) e^{-b x^2}, H_{j+1} = 2y H_j - 2j H_{j-1}
         const double y = g.gsb[t] * x;
-        double e = g.gB[t] * exp(-g.gb[t] * x * x);
+        double e = g.gB[t] * exp_fp64(-g.gb[t] * x * x);
         double hm = 0.0, h = 1.0;
 #pragma unroll
         for (int j = 0; j <= J; ++j) {

@@ -1,4 +1,5 @@
-// FP64 elementary functions for the Box-Muller step, specialized to the arguments it sees.
+// FP64 elementary functions for the Box-Muller step, specialized to the arguments it sees, and the
+// tanh and exp of the slice evaluators of non-polynomial potentials.
 //
 // The bisection offsets need r = sqrt(-2 ln u1) and (cos, sin)(2 pi u2) for uniforms u = K 2^-53
 // with K odd, 1 <= K < 2^53 (so 2^-53 <= u <= 1 - 2^-53). Knowing the argument ranges removes the
@@ -101,6 +102,58 @@ __device__ __forceinline__ void sincos_2pi(double t, double& sn, double& cs) {
     double c = (q & 1) ? S : C;                     // cos(2 pi r + q pi/2)
     sn = (q & 2) ? -a : a;
     cs = ((q + 1) & 2) ? -c : c;
+}
+
+// 1/k!, k = 2..13 (each rounded once to nearest): e^r - 1 = r + r^2 sum_k r^(k-2)/k!. For
+// |r| <= ln2/2 the first omitted term r^14/14! is below 5e-18 relative to r.
+__device__ constexpr double kExpC[12] = {
+    0x1.0000000000000p-1, 0x1.5555555555555p-3, 0x1.5555555555555p-5, 0x1.1111111111111p-7,
+    0x1.6c16c16c16c17p-10, 0x1.a01a01a01a01ap-13, 0x1.a01a01a01a01ap-16, 0x1.71de3a556c734p-19,
+    0x1.27e4fb7789f5cp-22, 0x1.ae64567f544e4p-26, 0x1.1eed8eff8d898p-29, 0x1.6124613a86d09p-33};
+constexpr double kLog2e = 0x1.71547652b82fep+0;
+
+// e^r - 1 for |r| <= ln2/2 (plus the rounding of the reduction), without cancellation.
+__device__ __forceinline__ double expm1_reduced(double r) {
+    double q = kExpC[11];
+#pragma unroll
+    for (int k = 10; k >= 0; --k) q = fma(q, r, kExpC[k]);
+    return fma(r * r, q, r);
+}
+
+// Cody-Waite reduction x = n ln2 + r, |r| <= ln2/2 (n * kLn2Hi exact for |n| < 2^21).
+__device__ __forceinline__ double reduce_ln2(double x, double& n) {
+    n = rint(x * kLog2e);
+    const double r = fma(-n, kLn2Hi, x);
+    return fma(-n, kLn2Lo, r);
+}
+
+// tanh(y) = sign(y) e/(e + 2) with e = e^(2|y|) - 1 = 2^n expm1(r) + (2^n - 1) (both terms exact,
+// one rounding, no cancellation for small |y|); the quotient from the hardware reciprocal estimate
+// refined by Newton steps. For |y| > 19, 1 - tanh|y| < 2^-54 and the result is 1. A few ulp.
+__device__ __forceinline__ double tanh_fp64(double y) {
+    const double a = fabs(y);
+    const double ac = a > 19.0 ? 19.0 : a;           // keeps n in range; NaN passes through
+    double n;
+    const double r = reduce_ln2(ac + ac, n);
+    const int ni = int(n);
+    const double e = ldexp(expm1_reduced(r), ni) + (ldexp(1.0, ni) - 1.0);
+    const double d = e + 2.0;
+    double rc = __builtin_amdgcn_rcp(d);
+    rc = fma(rc, fma(-d, rc, 1.0), rc);
+    rc = fma(rc, fma(-d, rc, 1.0), rc);
+    double t = e * rc;
+    t = fma(rc, fma(-d, t, e), t);
+    t = a > 19.0 ? 1.0 : t;
+    return copysign(t, y);
+}
+
+// e^x for finite x: 2^n (1 + expm1(r)); 0 below -746 (where e^x rounds to zero), infinity above
+// 710. About 1 ulp for normal results.
+__device__ __forceinline__ double exp_fp64(double x) {
+    double n;
+    const double r = reduce_ln2(x < -746.0 ? -746.0 : (x > 710.0 ? 710.0 : x), n);
+    const double e = ldexp(1.0 + expm1_reduced(r), int(n));
+    return x < -746.0 ? 0.0 : e;
 }
 
 }  // namespace pimc
