@@ -324,7 +324,6 @@ struct TanhEvalP {
 // (pimc_general_device.hpp).
 struct GenTables {
     const double* dpoly;                         // (J+1) x 9: coefficients of V^(j) of the polynomial part
-    int pdeg;                                    // degree of the polynomial part (-1: none)
     const double* dsech;                         // per term (J+1) x (J+3): A a^j S_j(t)
     int n_sech;
     int n_gauss;

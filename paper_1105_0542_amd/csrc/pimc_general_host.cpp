@@ -20,6 +20,7 @@ using namespace pimc_host;
 
 static_assert(PIMC_GEN_MAX_P == kGenMaxP, "general-mode level limit of the public header");
 static_assert(PIMC_GEN_MAX_TERMS == kGenMaxTerms, "general-mode term limit of the public header");
+static_assert(PIMC_MAX_DEGREE == 8, "the derivative tables and their device evaluation hold rows of degree 8");
 
 namespace {
 

@@ -326,7 +326,6 @@ int stage_problem(pimc_ctx* c, const Problem& P, uint64_t seed, uint32_t stream,
     if (P.kind == EvalKind::General64) {
         GenTables& g = A.gen;
         g.dpoly = reinterpret_cast<const double*>(base + off_dpoly);
-        g.pdeg = P.gen.pdeg;
         g.dsech = reinterpret_cast<const double*>(base + off_dsech);
         g.n_sech = int(P.gen.sech_A.size());
         g.n_gauss = int(P.gen.gauss_B.size());

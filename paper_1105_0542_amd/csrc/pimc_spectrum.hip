@@ -45,7 +45,7 @@ __global__ void __launch_bounds__(256) k_evolution_matrix(SpecTable tb, double L
         if (j0 + c < n) {
             const double dl = qb[c] - qa[c];
             const double g = (dl * dl) / (2.0 * t);
-            row[j0 + c] = g > kGaussCut ? 0.0 : pref * exp(-g - S[c]);
+            row[j0 + c] = g > kGaussCut ? 0.0 : pref * exp_fp64(-g - S[c]);
         }
     }
 }
@@ -88,7 +88,7 @@ __global__ void __launch_bounds__(256) k_evolution_tiles(SpecTable tb, double L,
             if (i < n && j < n) {
                 const double dl = qb[c] - qa[c];
                 const double g = (dl * dl) / (2.0 * t);
-                v = g > kGaussCut ? 0.0 : pref * exp(-g - S[c]);
+                v = g > kGaussCut ? 0.0 : pref * exp_fp64(-g - S[c]);
             }
             tile[r * kTile + c0 + c] = v;
         }
@@ -233,13 +233,28 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 }
 
 // out[c] = sum_i Q[c*ldq + i] w[i], c = 0..ncols-1: one workgroup per column.
+// This thread's part of sum_i a[i] b[i] over i = threadIdx.x + 256 k: eight independent partial
+// sums (eight loads in flight), combined pairwise in a fixed order.
+__device__ __forceinline__ double dot_strided(const double* __restrict__ a, const double* __restrict__ b,
+                                              uint32_t n) {
+    double p[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    uint32_t i = threadIdx.x;
+    for (; i + 7u * 256u < n; i += 8u * 256u) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) p[u] = fma(a[i + u * 256u], b[i + u * 256u], p[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+        if (i + u * 256u < n) p[u] = fma(a[i + u * 256u], b[i + u * 256u], p[u]);
+    return ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
+}
+
 __global__ void __launch_bounds__(256) k_col_dots(const double* __restrict__ Q, uint64_t ldq, uint32_t n,
                                                   const double* __restrict__ w, double* __restrict__ out) {
     __shared__ double red[256];
     const uint32_t c = blockIdx.x;
     const double* q = Q + uint64_t(c) * ldq;
-    double s = 0.0;
-    for (uint32_t i = threadIdx.x; i < n; i += 256u) s = fma(q[i], w[i], s);
+    double s = dot_strided(q, w, n);
     s = block_sum(s, red);
     if (threadIdx.x == 0) out[c] = s;
 }
@@ -269,8 +284,7 @@ __global__ void k_combine_cols(const double* __restrict__ Q, uint64_t ldq, uint3
 __global__ void __launch_bounds__(256) k_normalize(const double* __restrict__ w, uint32_t n, double* __restrict__ beta,
                                                    uint32_t j, double* __restrict__ qnext) {
     __shared__ double red[256];
-    double s = 0.0;
-    for (uint32_t i = threadIdx.x; i < n; i += 256u) s = fma(w[i], w[i], s);
+    double s = dot_strided(w, w, n);
     s = block_sum(s, red);
     __shared__ double nrm;
     if (threadIdx.x == 0) {
