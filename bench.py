@@ -289,10 +289,10 @@ def mpt_section(P, ctx, dvr, base=None):
 
 
 # FP64 operations per slice of the general-mode evaluator at p = 8 for a polynomial potential, counted
-# in the code generated for that level: the monomial sums (173 fma, 226 products, 19 additions of
-# partial sums and Horner steps), 36 fma for the derivatives of the polynomial (degree-8 rows),
-# 15 + 1 level scalings, and mid-point, deviation, its square and the accumulation (4).
-GENERAL_FLOP_PER_SLICE_P8 = 2 * 173 + 226 + 19 + 2 * 36 + 16 + 4
+# in the code generated for that level: the prefix-tree sums of the monomials (192 fma, 63 products),
+# 36 fma for the derivatives of the polynomial (degree-8 rows), 15 + 1 level scalings, and mid-point,
+# deviation, its square and the accumulation (4).
+GENERAL_FLOP_PER_SLICE_P8 = 2 * 192 + 63 + 2 * 36 + 16 + 4
 
 
 def general_section(P, ctx, base=None):

@@ -1,9 +1,9 @@
 // Build-time generator of the general-potential slice evaluators (the counterpart of the generated
 // Wp() functions of Sec. 3.1/3.2): for every level p = 1..kGenMaxP it runs eq.(1Drec)/(diagonal) on
 // polynomials in the derivative symbols v_j = V^(j) (pimc_general.hpp), takes the monomials in
-// canonical order and writes straight-line device code that forms their products from the scaled
-// derivative values held in registers and sums them, coefficient by coefficient, into the Horner
-// scheme in zt = dlt^2 / (4 eps):
+// canonical order and writes straight-line device code that sums them from the scaled derivative
+// values held in registers, per power of zt = dlt^2 / (4 eps) by a multivariate Horner scheme over the
+// prefix tree of their factor lists, and then by the Horner scheme in zt:
 //
 //   template <> struct GenCompiled<p> {
 //       static constexpr int J, NREC;        // highest derivative, number of monomials
@@ -11,11 +11,10 @@
 //   };
 //
 // In this dimensionless form (pimc_general.hpp: level_scales) the coefficients do not depend on the
-// bisection level, so they are written into the code as exact hexadecimal constants. Consecutive
-// monomials share prefixes of their factor lists; the prefix products are kept (q2, q3, ...:
-// products of the first 2, 3, ... factors) and formed again only when the prefix changes. The
-// monomials of one power of zt go round-robin into kGenAcc partial sums (independent dependency
-// chains), added pairwise at the end of the group.
+// bisection level, so they are written into the code as exact hexadecimal constants. The monomials of
+// one power of zt, in lexicographic order of their factor lists, are the depth-first walk of a prefix
+// tree; a node's value is its own coefficient plus v_j times the value of each child j, so every tree
+// edge costs one fma and only one partial sum per depth (a0, a1, ...) is live.
 // Usage: pimc_gen_codegen <output header>.
 #include <cstdio>
 #include <string>
@@ -28,23 +27,45 @@ using namespace pimc;
 namespace {
 
 std::string vref(int factor) { return "v[i][" + std::to_string(factor) + "]"; }
+std::string aref(int depth) { return "a" + std::to_string(depth) + "[i]"; }
 
-// Expression of the product of the first d factors of f (d >= 1).
-std::string prefix(const std::vector<uint8_t>& f, int d) {
-    return d == 1 ? vref(f[0]) : "q" + std::to_string(d) + "[i]";
-}
-
-// Sum of the first n partial accumulators of a group, pairwise in a fixed order (gen_group_sum).
-std::string group_sum(int n) {
-    std::vector<std::string> t;
-    for (int a = 0; a < n; ++a) t.push_back("g" + std::to_string(a) + "[i]");
-    while (t.size() > 1) {
-        std::vector<std::string> u;
-        for (size_t a = 0; a + 1 < t.size(); a += 2) u.push_back("(" + t[a] + " + " + t[a + 1] + ")");
-        if (t.size() % 2) u.push_back(t.back());
-        t.swap(u);
+// Emits the value T of the prefix-tree node at depth d whose monomials are M[r0..r1) (all share
+// their first d factors) into a<d>, following gen_tree_node: the node's own coefficient (a monomial
+// of exactly d factors, first in lexicographic order) starts the sum, then each child j adds
+// v_j T(child), a leaf child with its constant directly.
+void emit_node(FILE* o, const std::vector<GenMono>& M, size_t r0, size_t r1, size_t d, const std::string& ind) {
+    std::string init;                             // the node's coefficient, if it has one
+    if (M[r0].f.size() == d) {
+        char buf[64];
+        std::snprintf(buf, sizeof(buf), "%a", M[r0].c);
+        init = buf;
+        ++r0;
     }
-    return t[0];
+    bool first = true;
+    for (size_t c0 = r0; c0 < r1;) {
+        const int j = M[c0].f[d];
+        size_t c1 = c0;
+        while (c1 < r1 && M[c1].f[d] == j) ++c1;
+        std::string t;                            // T(child)
+        if (c1 - c0 == 1 && M[c0].f.size() == d + 1) {
+            char buf[64];
+            std::snprintf(buf, sizeof(buf), "%a", M[c0].c);
+            t = buf;
+            std::fprintf(o, "%s// monomial %zu\n", ind.c_str(), c0);
+        } else {
+            emit_node(o, M, c0, c1, d + 1, ind);
+            t = aref(int(d + 1));
+        }
+        std::string rhs;
+        if (first && init.empty())
+            rhs = vref(j) + " * " + t;
+        else
+            rhs = "fma(" + vref(j) + ", " + t + ", " + (first ? init : aref(int(d))) + ")";
+        std::fprintf(o, "%s#pragma unroll\n%sfor (int i = 0; i < W; ++i) %s = %s;\n", ind.c_str(), ind.c_str(),
+                     aref(int(d)).c_str(), rhs.c_str());
+        first = false;
+        c0 = c1;
+    }
 }
 
 void emit_level(FILE* o, int p) {
@@ -57,9 +78,8 @@ void emit_level(FILE* o, int p) {
     std::fprintf(o, "    template <int W>\n");
     std::fprintf(o, "    __device__ __forceinline__ static void eval(const double (&v)[W][J + 1], const double (&z)[W],\n"
                     "                                                double (&acc)[W]) {\n");
-    for (int a = 0; a < kGenAcc; ++a) std::fprintf(o, "        double g%d[W];\n", a);
-    for (size_t d = 2; d < maxdeg; ++d) std::fprintf(o, "        double q%zu[W];\n", d);
-    std::vector<std::vector<uint8_t>> held(maxdeg + 1);   // held[d]: the factors whose product q<d> holds
+    for (size_t d = 0; d < maxdeg; ++d) std::fprintf(o, "        double a%zu[W];\n", d);
+    const std::string ind = "        ";
     int k_prev = -1;
     bool first_group = true;
     for (size_t r0 = 0; r0 < M.size();) {
@@ -69,28 +89,9 @@ void emit_level(FILE* o, int p) {
             for (int k = k_prev - 1; k > M[r0].k; --k)   // a k without monomials
                 std::fprintf(o, "#pragma unroll\n        for (int i = 0; i < W; ++i) acc[i] = acc[i] * z[i];\n");
         std::fprintf(o, "        // k = %d\n", M[r0].k);
-        for (size_t r = r0; r < r1; ++r) {
-            const GenMono& g = M[r];
-            const int a = int((r - r0) % size_t(kGenAcc));
-            const bool first_use = r - r0 < size_t(kGenAcc);
-            // prefix products still held from earlier monomials are reused; the others are formed
-            const size_t n = g.f.size();
-            std::string body;
-            for (size_t d = 2; d + 1 <= n; ++d) {
-                const std::vector<uint8_t> want(g.f.begin(), g.f.begin() + long(d));
-                if (held[d] == want) continue;
-                body += "q" + std::to_string(d) + "[i] = " + prefix(g.f, int(d - 1)) + " * " + vref(g.f[d - 1]) + "; ";
-                held[d] = want;
-            }
-            const std::string val = n == 1 ? vref(g.f[0]) : prefix(g.f, int(n - 1)) + " * " + vref(g.f[n - 1]);
-            const std::string ga = "g" + std::to_string(a) + "[i]";
-            body += first_use ? ga + " = c * (" + val + ");" : ga + " = fma(c, " + val + ", " + ga + ");";
-            std::fprintf(o, "        {\n            const double c = %a;   // monomial %zu\n#pragma unroll\n"
-                            "            for (int i = 0; i < W; ++i) { %s }\n        }\n", g.c, r, body.c_str());
-        }
-        const std::string sum = group_sum(int(std::min(r1 - r0, size_t(kGenAcc))));
+        emit_node(o, M, r0, r1, 0, ind);
         std::fprintf(o, "#pragma unroll\n        for (int i = 0; i < W; ++i) acc[i] = %s;\n",
-                     first_group ? sum.c_str() : ("fma(acc[i], z[i], " + sum + ")").c_str());
+                     first_group ? "a0[i]" : "fma(acc[i], z[i], a0[i])");
         first_group = false;
         k_prev = M[r0].k;
         r0 = r1;

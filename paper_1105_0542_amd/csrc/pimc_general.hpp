@@ -227,26 +227,35 @@ inline void gen_derivatives(const GenPotential& G, double x, double* v) {
     }
 }
 
-// Partial sums per power of zt in the generated evaluators: monomial r of a group goes to sum
-// r mod kGenAcc (its first term by a product, later ones by fma), and the sums are added pairwise,
-// (g0 + g1) + (g2 + g3).
-constexpr int kGenAcc = 4;
-
-inline double gen_group_sum(const double* g, int n) {
-    double t[kGenAcc];
-    for (int a = 0; a < n; ++a) t[a] = g[a];
-    while (n > 1) {
-        int m = 0;
-        for (int a = 0; a + 1 < n; a += 2) t[m++] = t[a] + t[a + 1];
-        if (n % 2) t[m++] = t[n - 1];
-        n = m;
+// Value of the prefix-tree node at depth d whose monomials are M[r0..r1) (all share their first d
+// factors, in lexicographic order): its own coefficient (the monomial of exactly d factors, which
+// comes first) plus v_j times the value of each child j; a leaf child contributes its coefficient.
+// The generated evaluators do the same operations in the same order.
+inline double gen_tree_node(const std::vector<GenMono>& M, size_t r0, size_t r1, size_t d, const double* v) {
+    bool has_c = false;
+    double c = 0.0;
+    if (M[r0].f.size() == d) {
+        has_c = true;
+        c = M[r0].c;
+        ++r0;
     }
-    return t[0];
+    double a = 0.0;
+    bool first = true;
+    for (size_t c0 = r0; c0 < r1;) {
+        const int j = M[c0].f[d];
+        size_t c1 = c0;
+        while (c1 < r1 && M[c1].f[d] == j) ++c1;
+        const double t = (c1 - c0 == 1 && M[c0].f.size() == d + 1) ? M[c0].c : gen_tree_node(M, c0, c1, d + 1, v);
+        a = (first && !has_c) ? v[j] * t : std::fma(v[j], t, first ? c : a);
+        first = false;
+        c0 = c1;
+    }
+    return a;
 }
 
 // eps W_p of one slice from the canonical monomials and one level's scale factors (level_scales),
-// with the products and sums formed as the compiled evaluators form them (scaled derivatives, prefix
-// products left to right, kGenAcc partial sums per power of zt, Horner in zt).
+// formed as the compiled evaluators form it: scaled derivatives, per power of zt the prefix-tree sum
+// (gen_tree_node), Horner in zt.
 inline double gen_eval_slice(const GenPotential& G, const std::vector<GenMono>& M, const double* scales, double qa,
                              double qb) {
     const double x = 0.5 * (qa + qb);
@@ -263,16 +272,8 @@ inline double gen_eval_slice(const GenPotential& G, const std::vector<GenMono>& 
         while (r1 < M.size() && M[r1].k == M[r0].k) ++r1;
         if (!first)
             for (int k = k_prev - 1; k > M[r0].k; --k) acc = acc * z;   // a k without monomials
-        double g[kGenAcc] = {};
-        for (size_t r = r0; r < r1; ++r) {
-            const std::vector<uint8_t>& f = M[r].f;
-            double t = v[f[0]];
-            for (size_t i = 1; i < f.size(); ++i) t = t * v[f[i]];
-            const size_t a = (r - r0) % size_t(kGenAcc);
-            g[a] = r - r0 < size_t(kGenAcc) ? M[r].c * t : std::fma(M[r].c, t, g[a]);
-        }
-        const double sum = gen_group_sum(g, int(std::min(r1 - r0, size_t(kGenAcc))));
-        acc = first ? sum : std::fma(acc, z, sum);
+        const double g = gen_tree_node(M, r0, r1, 0, v.data());
+        acc = first ? g : std::fma(acc, z, g);
         first = false;
         k_prev = M[r0].k;
         r0 = r1;

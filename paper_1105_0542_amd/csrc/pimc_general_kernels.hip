@@ -18,6 +18,8 @@ hipError_t launch_p(const AmpArgs& A, int p, int U, int grid, hipStream_t st) {
         switch (U) {
             case 1: return launch_one<1>(A, ev, grid, st);
             case 2: if constexpr (gen_subtree_levels(P) >= 2) return launch_one<2>(A, ev, grid, st); else break;
+            case 3: if constexpr (gen_subtree_levels(P) >= 3) return launch_one<3>(A, ev, grid, st); else break;
+            case 4: if constexpr (gen_subtree_levels(P) >= 4) return launch_one<4>(A, ev, grid, st); else break;
             default: break;
         }
         return hipErrorInvalidValue;
@@ -32,6 +34,8 @@ int resident_p(int p, int U, size_t lds, int device) {
         if (p != P) return resident_p<P + 1>(p, U, lds, device);
         switch (U) {
             case 2: if constexpr (gen_subtree_levels(P) >= 2) return resident_one<2, GenCompiledEval<P>>(lds, device); else break;
+            case 3: if constexpr (gen_subtree_levels(P) >= 3) return resident_one<3, GenCompiledEval<P>>(lds, device); else break;
+            case 4: if constexpr (gen_subtree_levels(P) >= 4) return resident_one<4, GenCompiledEval<P>>(lds, device); else break;
             default: break;
         }
         return resident_one<1, GenCompiledEval<P>>(lds, device);

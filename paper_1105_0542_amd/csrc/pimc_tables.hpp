@@ -54,12 +54,16 @@ constexpr int kGenMaxP = 10;
 constexpr int kGenMaxJ = 2 * kGenMaxP - 2;
 constexpr int kGenMaxTerms = 4;
 // General mode, per level p: bisection levels of a subtree held in registers and slices evaluated
-// together by the generated code. Measured on MI355X (quartic and Gaussian barrier, s = 10): from
-// p = 5 on the generated code holds so many registers that one slice at a time in one-level subtrees
-// runs fastest (p = 8: 3.9e10 slice-evals/s against 1.9e10 for two slices in two-level subtrees);
-// below, four slices in two-level subtrees.
-constexpr int gen_subtree_levels(int p) { return p <= 4 ? 2 : 1; }
-constexpr int gen_block_slices(int p) { return p <= 4 ? 4 : 1; }
+// together by the generated code (for p >= 5: PIMC_GEN_U_HI, PIMC_GEN_B_HI).
+#ifndef PIMC_GEN_U_HI
+#define PIMC_GEN_U_HI 1
+#endif
+#ifndef PIMC_GEN_B_HI
+#define PIMC_GEN_B_HI 2
+#endif
+constexpr int gen_subtree_levels(int p) { return p <= 4 ? 2 : PIMC_GEN_U_HI; }
+constexpr int gen_block_slices(int p) { return p <= 4 ? 4 : PIMC_GEN_B_HI; }
+static_assert(PIMC_GEN_U_HI >= 1 && PIMC_GEN_U_HI <= 4, "general-mode subtree levels");
 
 // c[m][k], 0 <= k <= m < p, FP64.
 struct Coefficients {
