@@ -275,9 +275,23 @@ struct TanhEval64 {
     }
 };
 
+// v = c[0] u^D + c[1] u^(D-1) + ... + c[D], by Horner from the leading coefficient.
+template <int W, int D>
+__device__ __forceinline__ void horner_group(const_ptr<double> c, const double (&u)[W], double (&v)[W]) {
+    const double c0 = c[0];
+#pragma unroll
+    for (int i = 0; i < W; ++i) v[i] = c0;
+#pragma unroll
+    for (int e = 1; e <= D; ++e) {
+        const double ce = c[e];
+#pragma unroll
+        for (int i = 0; i < W; ++i) v[i] = fma(v[i], u[i], ce);
+    }
+}
+
 // The same tables with their shape fixed at compile time: the Poeschl-Teller fold has K = P groups
-// P_k(u) of degree P each (P(P+1) coefficients per level), so the Horner loops unroll and each
-// group's coefficients are scalar-loaded where they are used. Same operations in the same order as
+// P_k(u) of degree P each (P(P+1) coefficients per level), so each group's Horner scheme unrolls and
+// its coefficients are scalar-loaded where they are used. Same operations in the same order as
 // TanhEval64 (bitwise equal results).
 template <int P>
 struct TanhEvalP {
@@ -298,21 +312,16 @@ struct TanhEvalP {
             z[i] = dl * dl;
             acc[i] = 0.0;
         }
-#pragma unroll
-        for (int k = P - 1; k >= 0; --k) {
-            asm volatile("" : "+s"(t));
+        // group P-1, then the others in a loop that is not unrolled: each group's P+1 coefficients
+        // are loaded in its own iteration, so a level's table (P(P+1) doubles) is never held in
+        // scalar registers (unrolled, the compiler loaded it whole and spilled it into VGPR lanes)
+        horner_group<W, P>(t + (P - 1) * (P + 1), u, acc);
+#pragma unroll 1
+        for (int k = P - 2; k >= 0; --k) {
             double v[W];
-            const double c0 = t[k * (P + 1)];
+            horner_group<W, P>(t + k * (P + 1), u, v);
 #pragma unroll
-            for (int i = 0; i < W; ++i) v[i] = c0;
-#pragma unroll
-            for (int e = 1; e <= P; ++e) {
-                const double c = t[k * (P + 1) + e];
-#pragma unroll
-                for (int i = 0; i < W; ++i) v[i] = fma(v[i], u[i], c);
-            }
-#pragma unroll
-            for (int i = 0; i < W; ++i) acc[i] = (k == P - 1) ? v[i] : fma(acc[i], z[i], v[i]);
+            for (int i = 0; i < W; ++i) acc[i] = fma(acc[i], z[i], v[i]);
         }
 #pragma unroll
         for (int i = 0; i < W; ++i) S += acc[i];
