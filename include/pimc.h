@@ -172,8 +172,9 @@ int pimc_level_table_mpt(const pimc_mpt *V, double m, double T, int p, uint32_t 
  *
  * For a general V the coefficients of eq.(ansatz) are expressions in V and its derivatives up to
  * order 2p-2 (Sec. 3.1/3.2). Here eq.(1Drec)/(diagonal) run once per p on polynomials in the
- * symbols v_j = V^(j)(x) (d v_j/dx = v_{j+1}); each slice evaluates the folded monomials from the
- * derivatives of V at its mid-point. The potentials of this mode are
+ * symbols v_j = V^(j)(x) (d v_j/dx = v_{j+1}); each slice evaluates the monomials (in a dimensionless
+ * form whose coefficients are the same at every bisection level) from the derivatives of V at its
+ * mid-point. The potentials of this mode are
  *     V(q) = sum_{j <= degree} coef[j] q^j + sum_i A_i / cosh^2(alpha_i q) + sum_i B_i exp(-beta_i q^2)
  * (derivatives from closed-form recurrences). p in 1..PIMC_GEN_MAX_P, FP64 only; everything else
  * (mass rescaling, Philox/bisection, outputs, errors) as pimc_amplitude / pimc_path_actions. */
