@@ -503,8 +503,8 @@ def main():
         copy_probe()
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding of path ranges is a design "
-                                   "note only", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the library runs on one GPU per process; splitting path ranges over "
+                                   "several GPUs is not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
     # The oracle runs first, in worker processes forked before this process touches the GPU.
@@ -607,7 +607,7 @@ def main():
         "rel_diff_fp32_vs_fp64_gpu": abs(prec["fp32"]["A_512"] - prec["fp64"]["A_512"]) / prec["fp64"]["A_512"],
         "rel_stat_err": prec["fp64"]["err"] / prec["fp64"]["A_512"],
         "fp32_frac_of_fp32_peak": prec["fp32"]["slice_evals_per_s"] * FLOP_PER_SLICE / 1e12 / 157.3,
-        "note": "FP32 polynomials run as non-packed FP32 (packed FP32 instructions are disabled in this build), "
+        "note": "FP32 polynomials run as non-packed FP32 (packed FP32 instructions are disabled at compile time), "
                 "whose issue rate equals FP64 on MI355X; the 157.3 TFLOP/s FP32 peak needs packed FP32",
     }
     if prec_ref is not None:
