@@ -333,7 +333,7 @@ struct TanhEvalP {
 // (pimc_general_device.hpp).
 struct GenTables {
     const double* dpoly;                         // (J+1) x 9: coefficients of V^(j) of the polynomial part
-    const double* dsech;                         // per term (J+1) x (J+3): A a^j S_j(t)
+    const double* dsech;                         // per term (J+1) x (J+1): A a^j R_j(t)
     int n_sech;
     int n_gauss;
     double sech_a[kGenMaxTerms];

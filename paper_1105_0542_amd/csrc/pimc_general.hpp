@@ -10,7 +10,9 @@
 // Potentials of this mode: V(x) = sum_n c_n x^n + sum_i A_i / cosh^2(a_i x) + sum_i B_i exp(-b_i x^2),
 // whose derivatives come from tables computed here: the polynomial's derivative coefficients, the
 // polynomials S_j(t) in t = tanh(a x) with d^j/dx^j (A/cosh^2(a x)) = A a^j S_j(t), S_0 = 1 - t^2,
-// S_{j+1} = (1 - t^2) S_j'(t), and Hermite polynomials for the Gaussians.
+// S_{j+1} = (1 - t^2) S_j'(t), kept as S_j = sech^2(a x) R_j(t) with R_0 = 1,
+// R_{j+1} = -2t R_j + (1 - t^2) R_j' (sech^2 from e^(-2|a x|), accurate where tanh^2 rounds to 1),
+// and Hermite polynomials for the Gaussians.
 #pragma once
 
 #include <algorithm>
@@ -158,7 +160,7 @@ struct GenPotential {
     std::vector<double> dpoly;                   // (J+1) rows x 9: coefficients of V^(j)
     int pdeg = -1;
     std::vector<double> sech_A, sech_a;          // terms A / cosh^2(a x)
-    std::vector<double> dsech;                   // per term (J+1) rows x (J+3): A a^j S_j
+    std::vector<double> dsech;                   // per term (J+1) rows x (J+1): A a^j R_j
     std::vector<double> gauss_B, gauss_b;        // terms B exp(-b x^2)
 };
 
@@ -171,23 +173,33 @@ inline void gen_potential_tables(GenPotential& G) {
         for (size_t n = 0; n < d.size() && n < 9; ++n) G.dpoly[size_t(j) * 9 + n] = d[n];
         d = poly_der(d);
     }
-    G.dsech.assign(G.sech_A.size() * size_t(J + 1) * size_t(J + 3), 0.0);
+    G.dsech.assign(G.sech_A.size() * size_t(J + 1) * size_t(J + 1), 0.0);
     for (size_t i = 0; i < G.sech_A.size(); ++i) {
-        PolyD S = {1.0, 0.0, -1.0};                             // S_0 = 1 - t^2
+        PolyD R = {1.0};                                        // R_0 = 1
         double scale = G.sech_A[i];
         for (int j = 0; j <= J; ++j) {
-            double* row = G.dsech.data() + (i * size_t(J + 1) + size_t(j)) * size_t(J + 3);
-            for (size_t n = 0; n < S.size() && n < size_t(J + 3); ++n) row[n] = scale * S[n];
-            PolyD dS = poly_der(S);                             // S_{j+1} = (1 - t^2) S_j'
-            PolyD nx(dS.size() + 2, 0.0);
-            for (size_t n = 0; n < dS.size(); ++n) {
-                nx[n] += dS[n];
-                nx[n + 2] -= dS[n];
+            double* row = G.dsech.data() + (i * size_t(J + 1) + size_t(j)) * size_t(J + 1);
+            for (size_t n = 0; n < R.size() && n <= size_t(J); ++n) row[n] = scale * R[n];
+            // S_j = (1 - t^2) R_j and S_{j+1} = (1 - t^2) S_j' give R_{j+1} = -2t R_j + (1 - t^2) R_j'
+            const PolyD dR = poly_der(R);
+            PolyD nx(std::max(R.size() + 1, dR.size() + 2), 0.0);
+            for (size_t n = 0; n < R.size(); ++n) nx[n + 1] -= 2.0 * R[n];
+            for (size_t n = 0; n < dR.size(); ++n) {
+                nx[n] += dR[n];
+                nx[n + 2] -= dR[n];
             }
-            S = poly_trim(nx);
+            R = poly_trim(nx);
             scale *= G.sech_a[i];
         }
     }
+}
+
+// sech^2(y) = 4w / (1 + w)^2 with w = e^(-2|y|): no cancellation anywhere (1 - tanh^2 loses every
+// digit once tanh rounds towards 1), no overflow for large |y|.
+inline double sech2_of(double y) {
+    const double w = std::exp(-2.0 * std::fabs(y));
+    const double d = 1.0 + w;
+    return 4.0 * w / (d * d);
 }
 
 // v_j = V^(j)(x), j = 0..J (the device evaluates the same formulas).
@@ -203,12 +215,14 @@ inline void gen_derivatives(const GenPotential& G, double x, double* v) {
         v[j] = acc;
     }
     for (size_t i = 0; i < G.sech_A.size(); ++i) {
-        const double t = std::tanh(G.sech_a[i] * x);
+        const double y = G.sech_a[i] * x;
+        const double t = std::tanh(y);
+        const double s2 = sech2_of(y);
         for (int j = 0; j <= J; ++j) {
-            const double* row = G.dsech.data() + (i * size_t(J + 1) + size_t(j)) * size_t(J + 3);
-            double acc = row[j + 2];
-            for (int n = j + 1; n >= 0; --n) acc = std::fma(acc, t, row[n]);
-            v[j] += acc;
+            const double* row = G.dsech.data() + (i * size_t(J + 1) + size_t(j)) * size_t(J + 1);
+            double acc = row[j];
+            for (int n = j - 1; n >= 0; --n) acc = std::fma(acc, t, row[n]);
+            v[j] = std::fma(s2, acc, v[j]);
         }
     }
     for (size_t i = 0; i < G.gauss_B.size(); ++i) {

@@ -1,7 +1,7 @@
 // General-potential mode on the device: per slice, the derivatives v_j = V^(j)(mid), j <= J = 2p-2,
 // in registers (from the tables of pimc_general.hpp: the polynomial part by Horner per derivative,
-// one tanh per sech^2 term with the polynomials S_j(tanh), one exp per Gaussian term with the
-// Hermite recurrence), scaled per bisection level to vt_j = eps^(1 + j/2) v_j, then
+// one tanh and one exp per sech^2 term with sech^2 times the polynomials R_j(tanh), one exp per
+// Gaussian term with the Hermite recurrence), scaled per bisection level to vt_j = eps^(1 + j/2) v_j, then
 // eps W_p = sum_k zt^k sum c prod vt_f with zt = dlt^2 / (4 eps) by the straight-line code generated
 // for level p at build time (GenCompiled<p>, pimc_general_gen.hpp), whose coefficients c are
 // compile-time constants (the same at every level); the per-level scale factors are scalar loads.
@@ -36,14 +36,19 @@ __device__ __forceinline__ void gen_derivatives_dev(const GenTables& g, double x
     for (int j = JP + 1; j <= J; ++j) v[j] = 0.0;
     const const_ptr<double> ds = as_const(g.dsech);
     for (int t = 0; t < g.n_sech; ++t) {
-        const double th = tanh_fp64(g.sech_a[t] * x);
+        // A a^j S_j(tanh) = sech^2 * (A a^j R_j(tanh)), sech^2 = 4w/(1+w)^2 with w = e^(-2|a x|)
+        const double y = g.sech_a[t] * x;
+        const double th = tanh_fp64(y);
+        const double w = exp_fp64(-2.0 * fabs(y));
+        const double dw = 1.0 + w;
+        const double s2 = 4.0 * w / (dw * dw);
 #pragma unroll
         for (int j = 0; j <= J; ++j) {
-            const int row = (t * (J + 1) + j) * (J + 3);
-            double acc = ds[row + j + 2];
+            const int row = (t * (J + 1) + j) * (J + 1);
+            double acc = ds[row + j];
 #pragma unroll
-            for (int n = j + 1; n >= 0; --n) acc = fma(acc, th, ds[row + n]);
-            v[j] += acc;
+            for (int n = j - 1; n >= 0; --n) acc = fma(acc, th, ds[row + n]);
+            v[j] = fma(s2, acc, v[j]);
         }
     }
     for (int t = 0; t < g.n_gauss; ++t) {

@@ -129,10 +129,11 @@ __device__ __forceinline__ double reduce_ln2(double x, double& n) {
 
 // tanh(y) = sign(y) e/(e + 2) with e = e^(2|y|) - 1 = 2^n expm1(r) + (2^n - 1) (both terms exact,
 // one rounding, no cancellation for small |y|); the quotient from the hardware reciprocal estimate
-// refined by Newton steps. For |y| > 19, 1 - tanh|y| < 2^-54 and the result is 1. A few ulp.
+// refined by Newton steps. For |y| > 20, 1 - tanh|y| < 2^-56 and the result is 1 (the formula
+// itself already rounds to 1 above 55 ln2 / 2 = 19.06). A few ulp.
 __device__ __forceinline__ double tanh_fp64(double y) {
     const double a = fabs(y);
-    const double ac = a > 19.0 ? 19.0 : a;           // keeps n in range; NaN passes through
+    const double ac = a > 20.0 ? 20.0 : a;           // keeps n in range; NaN passes through
     double n;
     const double r = reduce_ln2(ac + ac, n);
     const int ni = int(n);
@@ -143,7 +144,7 @@ __device__ __forceinline__ double tanh_fp64(double y) {
     rc = fma(rc, fma(-d, rc, 1.0), rc);
     double t = e * rc;
     t = fma(rc, fma(-d, t, e), t);
-    t = a > 19.0 ? 1.0 : t;
+    t = a > 20.0 ? 1.0 : t;
     return copysign(t, y);
 }
 

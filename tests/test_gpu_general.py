@@ -72,6 +72,7 @@ CASES = [  # m, a, b, T, s, p, poly, sech2, gauss
     (1.7, 0.2, -0.6, 0.5, 4, 8, (0.1, 0.2, 0.4, 0.0, 0.02), ((-1.0, 0.8),), ((0.5, 2.0), (-0.3, 0.5))),
     (1.0, 0.1, 0.3, 0.5, 3, 4, (0, 0, 0.5), ((-1.0, 0.8), (0.5, 1.5), (-0.2, 2.0), (0.3, 0.5)),   # every term slot
      ((0.5, 2.0), (-0.3, 0.5), (0.2, 1.0), (0.1, 3.0))),
+    (1.0, -9.0, 11.0, 1.0, 5, 5, (0, 0, 0.5), ((-1.0, 3.0),), ((2.0, 4.0),)),   # saturated tanh, tiny Gaussian
 ]
 
 

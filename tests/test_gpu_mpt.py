@@ -35,6 +35,9 @@ CASES = [  # lam, alpha, m, a, b, T, s, p, flags
     (3.0, 0.75, 2.0, 0.3, -0.2, 2.0, 6, 8, 0),
     (-1.5, 1.25, 1.0, 0.0, 1.0, 0.5, 3, 12, P.FLAG_HIERARCHY),       # repulsive barrier
     (2.0, 1.0, 1.0, -1.0, 2.0, 1.0, 7, 4, P.FLAG_HIERARCHY),         # U = 4 subtrees below D = 3 levels
+    # far in the wing, alpha q from about -22 to -19, where tanh rounds to -1 or just above it: the
+    # actions are at the tables' rounding level (~1e-16), checked to the absolute tolerance
+    (1.0, 2.0, 1.5, -11.0, -9.5, 1.0, 6, 6, P.FLAG_HIERARCHY),
 ]
 
 
