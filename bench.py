@@ -672,7 +672,7 @@ def main():
         "roofline": {
             "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic(args.samples),
-            "kernel": "k_amplitude<4, QuarticEval64<18>>", "kernel_avg_ms": kernel_avg_s * 1e3,
+            "kernel": "k_amplitude<5, QuarticEval64<18>>", "kernel_avg_ms": kernel_avg_s * 1e3,
             "flop_per_slice": FLOP_PER_SLICE, "flop_per_launch": flop_per_launch,
         },
         "level_s_only": {"slice_evals_per_s": level_s_rate,
