@@ -169,9 +169,9 @@ int build_problem(const pimc_potential* V, double m, double a, double b, double 
     if (P.even && dV <= 4 && P.s >= 4) {
         P.kind = fp32 ? EvalKind::Quartic32 : EvalKind::Quartic64;
         xdeg = quartic_xdegrees(p);
-        // subtrees of 5 levels in FP64 (measured 4 % faster than 4 at p = 18, s = 10), 4 for N = 16
-        // and for the FP32 polynomials
-        P.U = (!fp32 && P.s >= 5) ? 5 : 4;
+        // subtrees of 5 levels (measured 4 % faster than 4 in FP64 at p = 18, s = 10, 2 % in FP32),
+        // 4 for N = 16
+        P.U = P.s >= 5 ? 5 : 4;
     } else {
         if (fp32) {
             std::snprintf(why, whylen, "FP32 polynomials need an even potential of degree <= 4 and N >= 16");

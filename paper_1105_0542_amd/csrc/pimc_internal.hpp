@@ -52,10 +52,10 @@ hipError_t launch_amplitude(const AmpArgs& A, EvalKind kind, int p, int U, int g
 // The compile-time shapes of level p with U = 4 (pimc_kernels_q64.hip, pimc_kernels_q32.hip,
 // pimc_kernels_tanh.hip): hipErrorInvalidValue / 256 for p outside 1..kMaxP.
 hipError_t launch_quartic64(const AmpArgs& A, int p, int U, int grid, hipStream_t st);
-hipError_t launch_quartic32(const AmpArgs& A, int p, int grid, hipStream_t st);
+hipError_t launch_quartic32(const AmpArgs& A, int p, int U, int grid, hipStream_t st);
 hipError_t launch_tanh_fixed(const AmpArgs& A, int p, int grid, hipStream_t st);
 int resident_quartic64(int p, int U, size_t lds_bytes, int device);
-int resident_quartic32(int p, size_t lds_bytes, int device);
+int resident_quartic32(int p, int U, size_t lds_bytes, int device);
 int resident_tanh_fixed(int p, size_t lds_bytes, int device);
 
 // General-potential mode (pimc_general_kernels.hip): the evaluators generated for level p; the

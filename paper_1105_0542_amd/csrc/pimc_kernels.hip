@@ -105,9 +105,7 @@ static hipError_t launch_tanh(const AmpArgs& A, int U, int grid, hipStream_t st)
 hipError_t launch_amplitude(const AmpArgs& A, EvalKind kind, int p, int U, int grid, hipStream_t st) {
     switch (kind) {
         case EvalKind::Quartic64: return launch_quartic64(A, p, U, grid, st);
-        case EvalKind::Quartic32:
-            if (U != 4) return hipErrorInvalidValue;
-            return launch_quartic32(A, p, grid, st);
+        case EvalKind::Quartic32: return launch_quartic32(A, p, U, grid, st);
         case EvalKind::GenericEven64: return launch_generic<true>(A, U, grid, st);
         case EvalKind::GenericOdd64: return launch_generic<false>(A, U, grid, st);
         case EvalKind::Tanh64: return launch_tanh(A, U, grid, st);
@@ -137,7 +135,7 @@ hipError_t launch_fill_u64(unsigned long long* p, int n, unsigned long long v, h
 int amplitude_resident_blocks(EvalKind kind, int p, int U, size_t lds_bytes, int device) {
     switch (kind) {
         case EvalKind::Quartic64: return resident_quartic64(p, U, lds_bytes, device);
-        case EvalKind::Quartic32: return resident_quartic32(p, lds_bytes, device);
+        case EvalKind::Quartic32: return resident_quartic32(p, U, lds_bytes, device);
         case EvalKind::GenericEven64:
         case EvalKind::GenericOdd64:
             switch (U) {

@@ -1,5 +1,5 @@
-// Estimation kernels with the compile-time table shapes of level p = 1..kMaxP (the quartic family with FP32 polynomials); one
-// translation unit per evaluator family so that they compile in parallel.
+// Estimation kernels with the compile-time table shapes of level p = 1..kMaxP (the quartic family with FP32 polynomials),
+// subtrees of 5 levels (N >= 32) or 4 (N = 16); one translation unit per evaluator family so that they compile in parallel.
 #include <hip/hip_runtime.h>
 
 #include "pimc_walker.hpp"
@@ -9,21 +9,25 @@ namespace pimc {
 namespace {
 
 template <int P>
-hipError_t launch_p(const AmpArgs& A, int p, int grid, hipStream_t st) {
+hipError_t launch_p(const AmpArgs& A, int p, int U, int grid, hipStream_t st) {
     if constexpr (P <= kMaxP) {
-        if (p != P) return launch_p<P + 1>(A, p, grid, st);
+        if (p != P) return launch_p<P + 1>(A, p, U, grid, st);
         const QuarticEval32<P> ev{A.tab32};
-        return launch_one<4>(A, ev, grid, st);
+        switch (U) {
+            case 4: return launch_one<4>(A, ev, grid, st);
+            case 5: return launch_one<5>(A, ev, grid, st);
+            default: return hipErrorInvalidValue;
+        }
     } else {
         return hipErrorInvalidValue;
     }
 }
 
 template <int P>
-int resident_p(int p, size_t lds, int device) {
+int resident_p(int p, int U, size_t lds, int device) {
     if constexpr (P <= kMaxP) {
-        if (p != P) return resident_p<P + 1>(p, lds, device);
-        return resident_one<4, QuarticEval32<P>>(lds, device);
+        if (p != P) return resident_p<P + 1>(p, U, lds, device);
+        return U == 5 ? resident_one<5, QuarticEval32<P>>(lds, device) : resident_one<4, QuarticEval32<P>>(lds, device);
     } else {
         return 256;
     }
@@ -31,8 +35,10 @@ int resident_p(int p, size_t lds, int device) {
 
 }  // namespace
 
-hipError_t launch_quartic32(const AmpArgs& A, int p, int grid, hipStream_t st) { return launch_p<1>(A, p, grid, st); }
+hipError_t launch_quartic32(const AmpArgs& A, int p, int U, int grid, hipStream_t st) {
+    return launch_p<1>(A, p, U, grid, st);
+}
 
-int resident_quartic32(int p, size_t lds_bytes, int device) { return resident_p<1>(p, lds_bytes, device); }
+int resident_quartic32(int p, int U, size_t lds_bytes, int device) { return resident_p<1>(p, U, lds_bytes, device); }
 
 }  // namespace pimc
