@@ -730,6 +730,7 @@ struct pimc_batch {
     // p classes
     struct Class {
         int p;
+        int U;                                 // subtree levels of the kernel (s - U levels on the stack)
         int n_tasks;
         size_t first;                          // first position in the device task array
         uint64_t n_items;
@@ -795,8 +796,8 @@ int capture_graph(pimc_batch* b) {
     for (size_t k = 0; k < b->classes.size() && e == hipSuccess; ++k) {
         const auto& C = b->classes[k];
         const int grid = std::max(1, C.resident * b->grid_mult_x2 / 2);
-        e = launch_batch(b->d_tasks + C.first, C.n_tasks, C.n_items, b->d_queue + k, b->grab, key, hier, C.p, grid,
-                         C.lds, b->stream);
+        e = launch_batch(b->d_tasks + C.first, C.n_tasks, C.n_items, b->d_queue + k, b->grab, key, hier, C.p, C.U,
+                         grid, C.lds, b->stream);
     }
     if (e == hipSuccess)
         e = launch_seg_reduce(b->d_partials, b->d_seg, b->d_seg + b->n_seg, b->n_seg, b->d_red, b->stream);
@@ -879,10 +880,14 @@ int pimc_batch_create(pimc_ctx* c, const pimc_potential* systems, int n_systems,
             scale_for_endpoint_sum(blob.data() + at, lv.back().deg);     // quartic evaluator form
         }
     }
-    // ---- per task: sigma, S_ref, chunking; device order grouped by p
+    // ---- per task: sigma, S_ref, chunking; device order grouped by p, then by subtree depth (the
+    // single-call kernels' choice: 5 levels for N >= 32, 4 for N = 16)
+    auto subtree_levels = [&](size_t i) { return tasks[i].N >= 32 ? 5 : 4; };
     std::vector<size_t> order(n_tasks);
     for (size_t i = 0; i < n_tasks; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return tasks[x].p < tasks[y].p; });
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+        return tasks[x].p != tasks[y].p ? tasks[x].p < tasks[y].p : subtree_levels(x) < subtree_levels(y);
+    });
     b->t_s.resize(n_tasks);
     b->t_logpref.resize(n_tasks);
     b->t_level0.resize(n_tasks);
@@ -981,20 +986,22 @@ int pimc_batch_create(pimc_ctx* c, const pimc_potential* systems, int n_systems,
     // classes and item numbering
     for (size_t pos = 0; pos < n_tasks;) {
         const int p = tasks[order[pos]].p;
-        pimc_batch::Class C{p, 0, pos, 0, 0, 0};
+        const int U = subtree_levels(order[pos]);
+        pimc_batch::Class C{p, U, 0, pos, 0, 0, 0};
         int dmax = 0;
-        while (pos < n_tasks && tasks[order[pos]].p == p) {
+        while (pos < n_tasks && tasks[order[pos]].p == p && subtree_levels(order[pos]) == U) {
             dt[pos].item0 = C.n_items;
             C.n_items += dt[pos].n_chunks;
-            dmax = std::max(dmax, dt[pos].s - 4);
+            dmax = std::max(dmax, dt[pos].s - U);
             ++C.n_tasks;
             ++pos;
         }
-        C.lds = amp_lds_bytes(dmax, dmax + 4);
-        C.resident = batch_resident_blocks(p, C.lds, c->device);
+        C.lds = amp_lds_bytes(dmax, dmax + U);
+        C.resident = batch_resident_blocks(p, U, C.lds, c->device);
         b->classes.push_back(C);
     }
-    if (b->classes.size() > 64) return fail(batch_fail(b, PIMC_EUNSUPPORTED, "more than 64 distinct levels p"));
+    if (b->classes.size() > 64)
+        return fail(batch_fail(b, PIMC_EUNSUPPORTED, "more than 64 kernel classes (levels p x subtree depths)"));
     std::vector<uint64_t> seg(b->n_seg * 2);
     std::copy(seg_base.begin(), seg_base.end(), seg.begin());
     std::copy(seg_len.begin(), seg_len.end(), seg.begin() + b->n_seg);
@@ -1058,7 +1065,7 @@ int pimc_batch_autotune(pimc_batch* b, const char* cache_path, int* grid_mult_x2
     HIP_TRY_B(b, hipGetDeviceProperties(&prop, b->ctx->device));
     std::ostringstream key;
     key << prop.gcnArchName << "|p";
-    for (const auto& C : b->classes) key << ":" << C.p;
+    for (const auto& C : b->classes) key << ":" << C.p << "u" << C.U;
     key << "|s" << b->s_max << "|f" << b->flags;
     if (cache_path) {
         std::ifstream in(cache_path);

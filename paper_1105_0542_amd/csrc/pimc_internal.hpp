@@ -89,10 +89,11 @@ struct BatchTask {
     int pad;
 };
 
-// Persistent batched estimation for one level p (quartic kernels, U = 4, s >= 4).
+// Persistent batched estimation for one level p and subtree depth U (quartic kernels, U = 4 for
+// s = 4, U = 5 for s >= 5).
 hipError_t launch_batch(const BatchTask* tasks, int n_tasks, uint64_t n_items, unsigned long long* queue, uint32_t grab,
-                        const RngKey& key, int hier, int p, int grid, size_t lds, hipStream_t st);
-int batch_resident_blocks(int p, size_t lds_bytes, int device);
+                        const RngKey& key, int hier, int p, int U, int grid, size_t lds, hipStream_t st);
+int batch_resident_blocks(int p, int U, size_t lds_bytes, int device);
 hipError_t launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t st);
 
 // Occupancy-derived number of resident workgroups of the estimation kernel on this device.

@@ -69,12 +69,18 @@ k_batch(const BatchTask* __restrict__ tasks, int n_tasks, uint64_t n_items, unsi
 
 template <int P>
 static hipError_t batch_quartic(const BatchTask* tasks, int n_tasks, uint64_t n_items, unsigned long long* queue,
-                                uint32_t grab, RngKey key, int hier, int p, int grid, size_t lds, hipStream_t st) {
+                                uint32_t grab, RngKey key, int hier, int p, int U, int grid, size_t lds, hipStream_t st) {
     if constexpr (P <= kMaxP) {
-        if (p != P) return batch_quartic<P + 1>(tasks, n_tasks, n_items, queue, grab, key, hier, p, grid, lds, st);
+        if (p != P) return batch_quartic<P + 1>(tasks, n_tasks, n_items, queue, grab, key, hier, p, U, grid, lds, st);
         QuarticEval64<P> ev{nullptr};
-        hipLaunchKernelGGL((k_batch<4, QuarticEval64<P>>), dim3(grid), dim3(kBlock), lds, st, tasks, n_tasks, n_items,
-                           queue, grab, key, hier, ev);
+        if (U == 5)
+            hipLaunchKernelGGL((k_batch<5, QuarticEval64<P>>), dim3(grid), dim3(kBlock), lds, st, tasks, n_tasks,
+                               n_items, queue, grab, key, hier, ev);
+        else if (U == 4)
+            hipLaunchKernelGGL((k_batch<4, QuarticEval64<P>>), dim3(grid), dim3(kBlock), lds, st, tasks, n_tasks,
+                               n_items, queue, grab, key, hier, ev);
+        else
+            return hipErrorInvalidValue;
         return hipGetLastError();
     } else {
         return hipErrorInvalidValue;
@@ -82,17 +88,19 @@ static hipError_t batch_quartic(const BatchTask* tasks, int n_tasks, uint64_t n_
 }
 
 hipError_t launch_batch(const BatchTask* tasks, int n_tasks, uint64_t n_items, unsigned long long* queue, uint32_t grab,
-                        const RngKey& key, int hier, int p, int grid, size_t lds, hipStream_t st) {
-    return batch_quartic<1>(tasks, n_tasks, n_items, queue, grab, key, hier, p, grid, lds, st);
+                        const RngKey& key, int hier, int p, int U, int grid, size_t lds, hipStream_t st) {
+    return batch_quartic<1>(tasks, n_tasks, n_items, queue, grab, key, hier, p, U, grid, lds, st);
 }
 
 template <int P>
-static int batch_resident(int p, size_t lds, int device) {
+static int batch_resident(int p, int U, size_t lds, int device) {
     if constexpr (P <= kMaxP) {
-        if (p != P) return batch_resident<P + 1>(p, lds, device);
+        if (p != P) return batch_resident<P + 1>(p, U, lds, device);
         int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<4, QuarticEval64<P>>, kBlock, lds) != hipSuccess)
-            per_cu = 1;
+        const hipError_t e =
+            U == 5 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<5, QuarticEval64<P>>, kBlock, lds)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<4, QuarticEval64<P>>, kBlock, lds);
+        if (e != hipSuccess) per_cu = 1;
         int ncu = 0;
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) ncu = 256;
         return (per_cu < 1 ? 1 : per_cu) * ncu;
@@ -101,6 +109,8 @@ static int batch_resident(int p, size_t lds, int device) {
     }
 }
 
-int batch_resident_blocks(int p, size_t lds_bytes, int device) { return batch_resident<1>(p, lds_bytes, device); }
+int batch_resident_blocks(int p, int U, size_t lds_bytes, int device) {
+    return batch_resident<1>(p, U, lds_bytes, device);
+}
 
 }  // namespace pimc
