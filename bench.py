@@ -474,6 +474,34 @@ def proposal_section(P, ctx, steps):
     return out
 
 
+def batched_section(P, ctx, samples):
+    """Batched grid: 2 systems x 3 T x 3 p x 128 x 128 endpoints, mixed N, one graph replay, with the
+    autotuned and the default launch shape."""
+    from paper_1105_0542_amd import workloads
+    t0b = time.perf_counter()
+    systems, rows = workloads.evolution_matrix_tasks(samples=samples)
+    bt = P.Batch(ctx, systems, rows, seed=1, flags=0)
+    t_plan = time.perf_counter() - t0b
+    tune_path = os.path.join(os.environ.get("TMPDIR", "/tmp"), "pimc_batch_tune.txt")
+    choice = bt.autotune(tune_path)
+    out, ms, st = bt.run()
+    bt.set_tuning(2, 1)
+    _, default_ms, _ = bt.run()
+    bt.set_tuning(*choice)
+    slices = sum(r[7] * r[5] for r in rows)
+    nonfinite = int((out["n_nonfinite"]).sum())
+    line = {
+        "workload": "128x128 endpoint grid on [-4,4]^2, (A,g) in {(1,1),(-1,4)}, T in {0.5,1,2}, p in {8,12,18}, "
+                    f"N in 16..512 by a fixed hash, {samples} samples per task, level N only",
+        "tasks": len(rows), "graph_ms": ms, "slice_evals_per_s": slices / (ms / 1e3),
+        "default_shape_graph_ms": default_ms, "autotuned": {"grid_mult_x2": choice[0], "grab": choice[1]},
+        "plan_s": t_plan, "tasks_with_nonfinite_weights": int((out["n_nonfinite"].sum(axis=1) > 0).sum()),
+        "nonfinite_weights": nonfinite,
+    }
+    bt.close()
+    return line
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -494,6 +522,8 @@ def main():
                     help="run only the Poeschl-Teller convergence section, with its DVR reference")
     ap.add_argument("--only-vector", action="store_true",
                     help="run only the several-coordinate section, with its DVR reference")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="run only the batched-grid section (for profiler runs): no other section, no cpu baseline")
     ap.add_argument("--only-spectrum", action="store_true",
                     help="run only the spectrum section (for profiler runs), with its DVR reference")
     ap.add_argument("--flow-steps", type=int, default=FLOW["steps"],
@@ -509,7 +539,7 @@ def main():
 
     # The oracle runs first, in worker processes forked before this process touches the GPU.
     skip_cpu = (args.no_cpu_baseline or args.only_headline or args.only_proposal or args.only_spectrum or
-                args.only_mpt or args.only_general or args.only_vector)
+                args.only_mpt or args.only_general or args.only_vector or args.only_batched)
     cpu = None if skip_cpu else cpu_baseline(CPU_SAMPLE_PATHS)
     prec_ref = None if skip_cpu else oracle_precision_reference()
     spec_ref = None if (skip_cpu and not args.only_spectrum) else oracle_spectrum_reference()
@@ -528,6 +558,10 @@ def main():
     H = P.FLAG_HIERARCHY
     if args.only_proposal:
         print(json.dumps({"proposal": proposal_section(P, ctx, args.flow_steps)}), flush=True)
+        ctx.close()
+        return
+    if args.only_batched:
+        print(json.dumps({"batched": batched_section(P, ctx, args.batch_samples)}), flush=True)
         ctx.close()
         return
     if args.only_spectrum:
@@ -616,32 +650,7 @@ def main():
             "rel_diff_fp64_gpu": abs(small["fp64"] - prec_ref) / prec_ref,
             "rel_diff_fp32_gpu": abs(small["fp32"] - prec_ref) / prec_ref}
 
-    # batched grid: 2 systems x 3 T x 3 p x 128 x 128 endpoints, mixed N, one graph replay
-    batch_line = None
-    if args.batch_samples > 0:
-        from paper_1105_0542_amd import workloads
-        t0b = time.perf_counter()
-        systems, rows = workloads.evolution_matrix_tasks(samples=args.batch_samples)
-        bt = P.Batch(ctx, systems, rows, seed=1, flags=0)
-        t_plan = time.perf_counter() - t0b
-        tune_path = os.path.join(os.environ.get("TMPDIR", "/tmp"), "pimc_batch_tune.txt")
-        choice = bt.autotune(tune_path)
-        out, ms, st = bt.run()
-        default_ms = None
-        bt.set_tuning(2, 1)
-        _, default_ms, _ = bt.run()
-        bt.set_tuning(*choice)
-        slices = sum(r[7] * r[5] for r in rows)
-        nonfinite = int((out["n_nonfinite"]).sum())
-        batch_line = {
-            "workload": "128x128 endpoint grid on [-4,4]^2, (A,g) in {(1,1),(-1,4)}, T in {0.5,1,2}, p in {8,12,18}, "
-                        f"N in 16..512 by a fixed hash, {args.batch_samples} samples per task, level N only",
-            "tasks": len(rows), "graph_ms": ms, "slice_evals_per_s": slices / (ms / 1e3),
-            "default_shape_graph_ms": default_ms, "autotuned": {"grid_mult_x2": choice[0], "grab": choice[1]},
-            "plan_s": t_plan, "tasks_with_nonfinite_weights": int((out["n_nonfinite"].sum(axis=1) > 0).sum()),
-            "nonfinite_weights": nonfinite,
-        }
-        bt.close()
+    batch_line = batched_section(P, ctx, args.batch_samples) if args.batch_samples > 0 else None
 
     flow_line = proposal_section(P, ctx, args.flow_steps) if args.flow_steps > 0 else None
     spec_line = spectrum_section(P, ctx, spec_ref, bases.get("spectrum"))
