@@ -155,6 +155,16 @@ def test_actions_large_path_indices(ctx):
     check_actions(ctx, P.quartic(1, 10), 1.0, 0.0, 1.0, 2.0, 5, 12, 3, 1, P.FLAG_HIERARCHY, (1 << 33) + 17, 300)
 
 
+def test_largest_n_nests_bitwise(ctx):
+    """N = 2^20 (the largest): levels 0..10 of every path equal the N = 2^10 run bit for bit (the
+    deepest walk, 15 stack levels above the register subtrees), and every level is finite."""
+    _log("largest N nesting")
+    big = ctx.path_actions(P.quartic(1, 10), 1.0, 0.0, 1.0, 1.0, 1 << 20, 18, 5, 1, P.FLAG_HIERARCHY, 0, 256)
+    small = ctx.path_actions(P.quartic(1, 10), 1.0, 0.0, 1.0, 1.0, 1 << 10, 18, 5, 1, P.FLAG_HIERARCHY, 0, 256)
+    assert np.array_equal(big[:, :11], small)
+    assert np.all(np.isfinite(big))
+
+
 def test_hierarchy_level_equals_separate_run(ctx):
     """Level n of an s-run is bitwise the n-run on the same samples."""
     big = ctx.path_actions(P.quartic(1, 10), 1.0, 0.0, 1.0, 1.0, 1 << 8, 18, 1, 0, P.FLAG_HIERARCHY, 0, 2000)
