@@ -280,20 +280,23 @@ __global__ void k_combine_cols(const double* __restrict__ Q, uint64_t ldq, uint3
     y[i] = subtract ? y[i] - s : s;
 }
 
-// beta[j] = |w|, q_{j+1} = w / beta[j] (one workgroup; zero vector if |w| = 0).
-__global__ void __launch_bounds__(256) k_normalize(const double* __restrict__ w, uint32_t n, double* __restrict__ beta,
-                                                   uint32_t j, double* __restrict__ qnext) {
+// beta[j] = |w| (one workgroup).
+__global__ void __launch_bounds__(256) k_norm(const double* __restrict__ w, uint32_t n, double* __restrict__ beta,
+                                              uint32_t j) {
     __shared__ double red[256];
     double s = dot_strided(w, w, n);
     s = block_sum(s, red);
-    __shared__ double nrm;
-    if (threadIdx.x == 0) {
-        nrm = sqrt(s);
-        beta[j] = nrm;
-    }
-    __syncthreads();
+    if (threadIdx.x == 0) beta[j] = sqrt(s);
+}
+
+// q_{j+1} = w / beta[j] (zero vector if |w| = 0), over the whole vector in parallel.
+__global__ void k_scale_by_norm(const double* __restrict__ w, uint32_t n, const double* __restrict__ beta, uint32_t j,
+                                double* __restrict__ qnext) {
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i >= n) return;
+    const double nrm = beta[j];
     const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-    for (uint32_t i = threadIdx.x; i < n; i += 256u) qnext[i] = w[i] * inv;
+    qnext[i] = w[i] * inv;
 }
 
 static inline uint32_t cdiv(uint64_t a, uint64_t b) { return uint32_t((a + b - 1) / b); }
@@ -357,7 +360,8 @@ hipError_t launch_combine_cols(const double* Q, uint64_t ldq, uint32_t n, uint32
 }
 
 hipError_t launch_normalize(const double* w, uint32_t n, double* beta, uint32_t j, double* qnext, hipStream_t st) {
-    hipLaunchKernelGGL(k_normalize, dim3(1), dim3(256), 0, st, w, n, beta, j, qnext);
+    hipLaunchKernelGGL(k_norm, dim3(1), dim3(256), 0, st, w, n, beta, j);
+    hipLaunchKernelGGL(k_scale_by_norm, dim3(cdiv(n, 256)), dim3(256), 0, st, w, n, beta, j, qnext);
     return hipGetLastError();
 }
 
