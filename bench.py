@@ -32,7 +32,7 @@ N_SAMPLES = 100_000_000
 POINTS = [(g, T) for g in (1.0, 10.0, 48.0) for T in (1.0, 2.0, 5.0)]
 # Algorithmic FP64 work of one slice evaluation at p = 18: E = 48 table entries -> 47 FMA (94 FLOP)
 # plus mid-point (2), deviation (1), two squares (2) and the accumulation (1): 100 FLOP.
-E_TABLE = {18: 48}
+E_TABLE = {8: 16, 12: 27, 18: 48}       # quartic level-table entries per p (pimc_level_table)
 FLOP_PER_SLICE = 2 * (E_TABLE[P_LEVEL] - 1) + 6
 FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector: 256 CU x 64 lanes x 2 FLOP x 2.4 GHz
 CPU_SAMPLE_PATHS = 2048          # per point, for the oracle timing
@@ -489,11 +489,14 @@ def batched_section(P, ctx, samples):
     _, default_ms, _ = bt.run()
     bt.set_tuning(*choice)
     slices = sum(r[7] * r[5] for r in rows)
+    # FP64 operations: per slice 2 (E_p - 1) for the Horner chains plus 6, as for the headline kernel
+    flops = sum(r[7] * r[5] * (2 * (E_TABLE[r[6]] - 1) + 6) for r in rows)
     nonfinite = int((out["n_nonfinite"]).sum())
     line = {
         "workload": "128x128 endpoint grid on [-4,4]^2, (A,g) in {(1,1),(-1,4)}, T in {0.5,1,2}, p in {8,12,18}, "
                     f"N in 16..512 by a fixed hash, {samples} samples per task, level N only",
         "tasks": len(rows), "graph_ms": ms, "slice_evals_per_s": slices / (ms / 1e3),
+        "fp64_frac": flops / (ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
         "default_shape_graph_ms": default_ms, "autotuned": {"grid_mult_x2": choice[0], "grab": choice[1]},
         "plan_s": t_plan, "tasks_with_nonfinite_weights": int((out["n_nonfinite"].sum(axis=1) > 0).sum()),
         "nonfinite_weights": nonfinite,
