@@ -364,7 +364,7 @@ int pimc_flow_amplitude(pimc_flow *flow, uint64_t n_samples, uint64_t seed, uint
 
 /* ---- spectrum from the space-discretized evolution operator ----------------------------------
  *
- * The paper's application of short-time amplitudes (Sec. 2; Sec. 5 with Fig. 3): on the grid
+ * The paper's application of short-time amplitudes (Sec. 2; Sec. 4.2 with Fig. 3): on the grid
  * x_i = -L + (i + 1/2) D, D = 2L/n (symmetric about 0), the matrix
  *     M_ij = D A_1^(p)(x_i, x_j; t),  A_1^(p)(a,b;t) = sqrt(m) (2 pi t)^(-1/2)
  *            exp(-m (b-a)^2/(2t) - t W~_p(sqrt(m)(a+b)/2, sqrt(m)(b-a)/2; t))
@@ -373,7 +373,7 @@ int pimc_flow_amplitude(pimc_flow *flow, uint64_t n_samples, uint64_t seed, uint
  * approximates exp(-t H) on the grid; its largest eigenvalues are exp(-t E_n) and its eigenvectors
  * sample the eigenfunctions. No Monte Carlo is involved (N = 1 at level p). Elements whose
  * free-particle exponent m (x_j - x_i)^2 / (2t) exceeds 40 are exactly zero: the expansion of W_p in
- * the half-deviation has a finite radius (Sec. 5), so there the truncated exponent may grow without
+ * the half-deviation has a finite radius (Sec. 4), so there the truncated exponent may grow without
  * bound while the true element is below exp(-40) of the free one. */
 #define PIMC_MAX_P_SHORT_TIME 21   /* highest level p for the short-time matrix                       */
 #define PIMC_MAX_GRID 65536        /* n <= 65536                                                      */

@@ -19,7 +19,7 @@ Transition Amplitudes via the Effective Action Approach", that it follows):
 * ``flow``             -- FP64 affine-coupling proposal (forward, log-det, weights, analytic
   gradient) used to check the GPU flow kernels.
 * ``spectrum``         -- the space-discretized evolution operator of short-time amplitudes and its
-  spectrum (the paper's application, Sec. 5 with Fig. 3).
+  spectrum (the paper's application, Sec. 4.2 with Fig. 3).
 * ``mpt``              -- the modified Poeschl-Teller potential through the recursion in tanh(alpha x)
   (Sec. 3.3, eq.(1D-MPT), eq.(1D-MPTansatz)).
 * ``general``          -- the general-potential mode: c_{m,k} as polynomials in the derivatives of V

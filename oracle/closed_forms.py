@@ -12,6 +12,8 @@ Test infrastructure only (see ``oracle/__init__``).
 * ``transfer_discretized`` -- A_N^(p) for any potential by repeated quadrature of the product of
                        short-time amplitudes (eq.(AMC) with the level-p short-time amplitude), on a
                        uniform grid (trapezoid rule, exponentially accurate for these integrands).
+* ``transfer_product`` / ``short_time_from_epsW`` -- the same quadrature for a short-time kernel
+                       given as a callable (any effective potential, e.g. the general mode's).
 * ``dvr_amplitude`` -- continuum A(a,b;T) = <b|exp(-T H)|a> from a sinc-DVR diagonalization
                        (Colbert and Miller, J. Chem. Phys. 96, 1982 (1992)) of H = p^2/2 + V.
 """
@@ -127,18 +129,41 @@ def transfer_discretized(V: ea.Poly, p: int, a: float, b: float, T: float, N: in
     """
     eps = T / N
     tab = ea.xbar_groups_float(V, p, Fraction(eps))
+    return transfer_product(lambda q, qp: short_time_amplitude(tab, eps, q, qp), a, b, N, L, h)
+
+
+def transfer_product(kernel: Callable, a: float, b: float, N: int, L: float = 8.0, h: float = 0.02) -> float:
+    """int dq_1..dq_{N-1} prod_k kernel(q_k, q_{k+1}), q_0 = a, q_N = b, by the trapezoid rule on the
+    grid -L..L with spacing h (the discretized amplitude of Sec. 4 for any short-time kernel)."""
     if N == 1:
-        return float(short_time_amplitude(tab, eps, a, b))
+        return float(kernel(a, b))
     x = np.arange(-L, L + 0.5 * h, h)
-    left = short_time_amplitude(tab, eps, a, x) * h            # row vector over q_1
-    right = short_time_amplitude(tab, eps, x, b)               # column over q_{N-1}
+    left = kernel(a, x) * h                                     # row vector over q_1
+    right = kernel(x, b)                                        # column over q_{N-1}
     if N == 2:
         return float(left @ right)
-    K = short_time_amplitude(tab, eps, x[:, None], x[None, :]) * h
+    K = kernel(x[:, None], x[None, :]) * h
     vec = left
     for _ in range(N - 2):
         vec = vec @ K
     return float(vec @ right)
+
+
+def short_time_from_epsW(epsW: Callable, eps: float, q, qp, cutoff: float = 40.0):
+    """(2 pi eps)^(-1/2) exp(-(q'-q)^2/(2 eps) - epsW(x, xbar)) with x the mid-point and xbar the
+    half-deviation (Sec. 2.1), for an effective potential given as a callable.
+
+    The short-time expansion has a finite radius in xbar (Sec. 4): where the free factor
+    exp(-(q'-q)^2/(2 eps)) is below exp(-cutoff) the kernel is set to 0 (there the truncated
+    exponent may grow without bound while the true amplitude is negligible).
+    """
+    q = np.asarray(q, dtype=np.float64)
+    qp = np.asarray(qp, dtype=np.float64)
+    free = (qp - q) ** 2 / (2 * eps)
+    with np.errstate(over="ignore", invalid="ignore"):
+        ew = epsW(0.5 * (q + qp), 0.5 * (qp - q))
+        val = np.exp(-free - ew) / math.sqrt(2 * math.pi * eps)
+    return np.where(free > cutoff, 0.0, val)
 
 
 def dvr_eigen(V: Callable[[np.ndarray], np.ndarray], L: float = 10.0, h: float = 0.025):

@@ -2,7 +2,7 @@
 
 Test infrastructure only (see ``oracle/__init__``).
 
-The paper's application of short-time amplitudes (Sec. 5, Fig. 3; Sec. 2): on a grid x_i the
+The paper's application of short-time amplitudes (Sec. 4.2, Fig. 3; Sec. 2): on a grid x_i the
 matrix of transition amplitudes A(x_i, x_j; t) times the spacing is the discretized evolution
 operator exp(-t H); its eigenvalues are exp(-t E_n) and its eigenvectors sample the eigenfunctions.
 For a short time t the level-p amplitude is used directly (N = 1, no Monte Carlo):
@@ -15,7 +15,7 @@ estimator: coordinates times sqrt(m), coefficient j of V times m^(-j/2), amplitu
 Grid reading (the paper states L and the spacing only): x_i = -L + (i + 1/2) D, i = 0..n-1,
 D = 2L/n -- symmetric about 0, so parity is kept exactly.
 
-Cutoff reading: the short-time expansion in the half-deviation xbar has a finite radius (Sec. 5;
+Cutoff reading: the short-time expansion in the half-deviation xbar has a finite radius (Sec. 4;
 for the Poeschl-Teller potential the poles of 1/cosh^2), so far from the diagonal the truncated
 exponent can grow without bound where the true amplitude is negligible. Elements whose
 free-particle factor exp(-(x_j - x_i)^2 / (2t)) is below exp(-40) (4e-18) are set to zero.

@@ -1,4 +1,4 @@
-// Command-line front end of libpimc.so with the argument order of the paper's program (Sec. 5):
+// Command-line front end of libpimc.so with the argument order of the paper's program (Sec. 4.2):
 // propagation time T, endpoints a and b, largest bisection level s, number of Monte Carlo samples,
 // seed, then the potential's coefficients V(q) = sum_j coef_j q^j. The effective-action level p,
 // the mass and the precision are options (the paper fixes p at compile time). Prints the amplitude

@@ -20,7 +20,7 @@ constexpr double kGaussCut = 40.0;    // elements with (y_j - y_i)^2 / (2t) > kG
 // Element (i, j): pref * exp(-(y_j - y_i)^2 / (2t) - t W_p((y_i + y_j)/2, (y_j - y_i)/2; t)) with
 // y = sqrt(m) x, x_i = -L + (i + 1/2) D, pref = D sqrt(m) / sqrt(2 pi t); exactly zero where the
 // free-particle exponent (y_j - y_i)^2 / (2t) exceeds kGaussCut. The expansion in the half-deviation
-// has a finite radius (Sec. 5), so far from the diagonal the truncated exponent may grow without
+// has a finite radius (Sec. 4), so far from the diagonal the truncated exponent may grow without
 // bound where the true amplitude is below exp(-kGaussCut) of the free one.
 template <bool EVEN>
 __global__ void __launch_bounds__(256) k_evolution_matrix(SpecTable tb, double L, double D, double sm, double t,

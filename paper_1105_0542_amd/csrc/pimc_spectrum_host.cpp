@@ -1,7 +1,7 @@
 // Host side of the spectrum entry points (pimc_evolution_matrix, pimc_spectrum in include/pimc.h).
 //
 // The paper computes energy eigenvalues and eigenfunctions by diagonalizing the space-discretized
-// matrix of short-time transition amplitudes (Sec. 2, Sec. 5 with Fig. 3): on the grid
+// matrix of short-time transition amplitudes (Sec. 2; Sec. 4.2 with Fig. 3): on the grid
 // x_i = -L + (i + 1/2) D, D = 2L/n, M_ij = D A_1^(p)(x_i, x_j; t) approximates exp(-t H), so its
 // largest eigenvalues are exp(-t E_n). The matrix is built on the device from the level-p table at
 // eps = t (for the eigenvalue iteration only its upper tiles: the matrix is exactly symmetric); its

@@ -36,6 +36,29 @@ def test_dvr_reproduces_mehler():
         cf.mehler(-0.5, 1.0, 0.7, A=4), rel=1e-11)
 
 
+def test_mehler_effective_potential_reproduces_the_kernel():
+    """The exact oscillator effective potential W*(x, xbar; T) in the ideal-action form of Sec. 2.1:
+    (2 pi T)^(-1/2) exp(-(b-a)^2/(2T) - T W*) is the Mehler kernel."""
+    for a, b, T in ((0.0, 1.0, 1.0), (-0.7, 0.4, 0.3), (1.5, 2.0, 2.5)):
+        x, xb = 0.5 * (a + b), 0.5 * (b - a)
+        got = math.exp(-(b - a) ** 2 / (2 * T) - T * cf.mehler_W(x, xb, T)) / math.sqrt(2 * math.pi * T)
+        assert got == pytest.approx(cf.mehler(a, b, T), rel=1e-14)
+
+
+@pytest.mark.parametrize("p", [2, 4, 6])
+def test_level_tables_approach_the_exact_oscillator_potential(p):
+    """eps W_p agrees with eps W* to order eps^p (the error of the level-p action is O(eps^(p+1)),
+    Sec. 2.1): halving eps divides the difference by 2^(p+1)."""
+    x = np.array([-1.3, 0.2, 0.9])
+    xb = np.array([0.05, -0.2, 0.1])
+    diffs = []
+    for eps in (0.1, 0.05):
+        tab = pimc.level_tables(ea.quartic(1, 0), p, eps, 0)[0]
+        exact = np.array([eps * cf.mehler_W(xi, xbi, eps) for xi, xbi in zip(x, xb)])
+        diffs.append(np.abs(pimc.eps_W(tab, x, xb) - exact))
+    assert np.all(np.abs(np.log2(diffs[0] / diffs[1]) - (p + 1)) < 0.15), diffs
+
+
 @pytest.mark.parametrize("p,slope", [(1, 1.0), (2, 2.0), (4, 4.0)])
 def test_gaussian_discretized_converges_to_mehler(p, slope):
     """Exact A_N^(p) of the oscillator approaches the Mehler value as 1/N^p (Sec. 2.1)."""
