@@ -35,7 +35,13 @@ POINTS = [(g, T) for g in (1.0, 10.0, 48.0) for T in (1.0, 2.0, 5.0)]
 E_TABLE = {8: 16, 12: 27, 18: 48}       # quartic level-table entries per p (pimc_level_table)
 FLOP_PER_SLICE = 2 * (E_TABLE[P_LEVEL] - 1) + 6
 FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector: 256 CU x 64 lanes x 2 FLOP x 2.4 GHz
-CPU_SAMPLE_PATHS = 2048          # per point, for the oracle timing
+CPU_SAMPLE_PATHS = 24576         # per point, for the oracle timing (about 10-20 s of the host's cores)
+# Convergence sweep (every point of the configured grid): g in {1, 10, 48} x p in {1, 2, 4, 8, 12, 18} x
+# T in {1, 2, 5}, 1e8 samples per point, one s = 10 run with every level per point; plus g = 0 at every p
+# (T = 1) against the exact discretized Gaussian amplitude and the Mehler kernel.
+C2 = dict(gs=(1.0, 10.0, 48.0), ps=(1, 2, 4, 8, 12, 18), Ts=(1.0, 2.0, 5.0), s=10, samples=100_000_000)
+C3_SAMPLES = 1_000_000           # samples per task of the batched grid (the configured size)
+C3_TUNE_SAMPLES = 10_000         # the same grid with fewer samples, for the autotuner
 # Precision workload: FP32 slice polynomials against FP64, g = 10, p = 18, N = 512, T = 1.
 PREC = dict(g=10.0, p=18, s=9, T=1.0, samples=1_000_000_000, oracle_paths=20_000)
 # Learned proposal: the anharmonic oscillator g = 10 at p = 12, N = 128, T = 2, a = 0, b = 1; 8 couplings,
@@ -60,6 +66,7 @@ MPT = dict(lam=1.0, alpha=1.0, a=-0.5, b=0.5, T=1.0, s=10, ps=(1, 2, 10), sample
 KERNEL_SOURCES = ["pimc_device.hpp", "pimc_kernels_q64.hip", "pimc_walker.hpp", "pimc_internal.hpp", "pimc_tables.hpp",
                   "pimc_math.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_amplitude_quartic64_p18_s10.json")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_k_amplitude_quartic64_p18_s10.json")
 
 
 def kernel_source_hash() -> str:
@@ -84,6 +91,18 @@ def measured_traffic(samples: int):
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
     return rec["bytes_per_sample"] * samples
+
+
+def measured_counter_flops():
+    """FP64 VALU FLOPs per sample of the headline kernel from the committed rocprofv3 counter record
+    (SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes), or None when the kernel sources changed since."""
+    import json as _json
+    if not os.path.exists(COUNTERS_FILE):
+        return None
+    rec = _json.load(open(COUNTERS_FILE))
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec
 
 
 def copy_probe():
@@ -391,8 +410,14 @@ def spectrum_section(P, ctx, dvr, base=None):
     return rows
 
 
+def _host_cpus():
+    return {"host_cpus": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0))}
+
+
 def cpu_baseline(paths_per_point: int):
-    """The oracle as it stands, on the host cores: level actions of the first paths of each point."""
+    """The oracle as it stands, on the host cores: level actions of the first paths of each point.
+    `cores` is the number of worker processes actually used (at most 16, the GPU box's CPU share);
+    the host's own counts are reported beside it."""
     import multiprocessing as mp
     cores = min(len(os.sched_getaffinity(0)), 16)
     chunk = 256
@@ -402,9 +427,88 @@ def cpu_baseline(paths_per_point: int):
         pool.map(_oracle_worker, jobs)
     dt = time.perf_counter() - t0
     n_slices = len(POINTS) * paths_per_point * slices_per_sample(S_DEPTH, True)
-    return {"value": n_slices / dt, "unit": "slice-evals/s", "cores": cores, "kind": "oracle",
+    return {"value": n_slices / dt, "unit": "slice-evals/s", "cores": cores, "kind": "oracle", **_host_cpus(),
             "sample": f"first {paths_per_point} paths of each of the {len(POINTS)} points (p=18, s=10, every level), "
                       f"{dt:.1f} s wall"}
+
+
+def c2_references():
+    """CPU references of the convergence sweep, computed before the GPU is touched: the sinc-DVR
+    continuum A(0, 1; T) of each (g, T), and for g = 0 (T = 1) the exact discretized amplitude
+    A_N^(p) of every level (mpmath Gaussian integral) and the Mehler kernel."""
+    from oracle import closed_forms as cf
+    cont = {f"{g:g},{T:g}": float(cf.dvr_amplitude(cf.quartic_V(1.0, g), 0.0, 1.0, T))
+            for g in C2["gs"] for T in C2["Ts"]}
+    exact0 = {str(p): [cf.gaussian_discretized(0.0, 1.0, 1.0, 1 << n, p) for n in range(C2["s"] + 1)]
+              for p in C2["ps"]}
+    return {"continuum": cont, "g0_exact": exact0, "mehler": cf.mehler(0.0, 1.0, 1.0)}
+
+
+def _slope_fit(levels, ref, p):
+    """Convergence order from |A_N - A| against N on the levels whose deviation exceeds 3 sigma (and
+    1e-11 relative, the accuracy of the reference): least squares of log|A_N - A| on log N over the
+    longest run of such consecutive levels (N >= 2) that ends at the finest significant level. Returns
+    (slope, N range, points)."""
+    sig = [n for n, r in levels if n >= 1 and r.err > 0 and abs(r.amp - ref) > max(3 * r.err, 1e-11 * abs(ref))]
+    if len(sig) < 2:
+        return None, [], len(sig)
+    run = [sig[-1]]
+    for n in reversed(sig[:-1]):
+        if n == run[-1] - 1:
+            run.append(n)
+        else:
+            break
+    run = sorted(run)
+    if len(run) < 2:
+        return None, [], 1
+    x = np.array([math.log(2.0 ** n) for n in run])
+    y = np.array([math.log(abs(levels[n][1].amp - ref)) for n in run])
+    k = float(np.polyfit(x, y, 1)[0])
+    return -k, [1 << run[0], 1 << run[-1]], len(run)
+
+
+def c2_section(P, ctx, refs):
+    """Every point of the convergence sweep on the GPU: A_N^(p) for N = 1..1024 from one s = 10 run
+    per (g, p, T) (1e8 samples), the 1/N^p order fitted against the DVR continuum, the eq.(fit)
+    extrapolation, and g = 0 against the exact discretized amplitude and the Mehler kernel."""
+    C = C2
+    s = C["s"]
+    rows = {}
+    tot_slices, tot_s = 0.0, 0.0
+    for gi, g in enumerate(C["gs"]):
+        for T in C["Ts"]:
+            A_cont = refs["continuum"][f"{g:g},{T:g}"] if refs else None
+            for p in C["ps"]:
+                stream = 1000 + len(rows)
+                res, st = ctx.amplitude(P.quartic(1.0, g), 1.0, 0.0, 1.0, T, 1 << s, p, C["samples"], 1, stream,
+                                        P.FLAG_HIERARCHY)
+                ms = ctx.last_kernel_ms()
+                tot_slices += C["samples"] * slices_per_sample(s, True)
+                tot_s += ms / 1e3
+                row = {"A_N": [r.amp for r in res], "err_N": [r.err for r in res], "status": st,
+                       "nonfinite": [int(r.n_nonfinite) for r in res], "kernel_ms": ms}
+                if A_cont is not None:
+                    slope, nrange, npts = _slope_fit(list(enumerate(res)), A_cont, p)
+                    A, dA = _fit_continuum([(n, r) for n, r in enumerate(res) if math.isfinite(r.err)], p)
+                    row.update({"continuum_dvr": A_cont, "slope": slope, "slope_N_range": nrange,
+                                "slope_points": npts, "fit_A": A, "fit_err": dA,
+                                "z_N1024": (res[s].amp - A_cont) / res[s].err if res[s].err > 0 else None})
+                rows[f"g={g:g},p={p},T={T:g}"] = row
+    g0 = {}
+    if refs:
+        for p in C["ps"]:
+            res, st = ctx.amplitude(P.quartic(1.0, 0.0), 1.0, 0.0, 1.0, 1.0, 1 << s, p, C["samples"], 1, 2000 + p,
+                                    P.FLAG_HIERARCHY)
+            ex = refs["g0_exact"][str(p)]
+            z = [(res[n].amp - ex[n]) / res[n].err for n in range(1, s + 1)]
+            exact_slope, _, _ = _slope_fit([(n, P.LevelResult(ex[n], 1e-300, 0, 0, 0, 0, 0)) for n in range(s + 1)],
+                                           refs["mehler"], p)
+            g0[str(p)] = {"max_abs_z_vs_exact_discretized": float(np.max(np.abs(z))), "z": z,
+                          "A_1024": res[s].amp, "exact_1024": ex[s], "mehler": refs["mehler"],
+                          "exact_slope_vs_mehler": exact_slope, "status": st}
+    return {"workload": f"V=q^2/2+g q^4/24, g in {list(C['gs'])}, p in {list(C['ps'])}, T in {list(C['Ts'])}, a=0, b=1, "
+                        f"one s={s} run per point with every level, {C['samples']:.0e} samples each; g=0 at T=1",
+            "points": rows, "g0": g0, "slice_evals_per_s": tot_slices / tot_s, "device_s": tot_s}
 
 
 def _train_and_estimate(P, ctx, coefs, N, batch, steps, est_stream, run_to_target):
@@ -474,34 +578,55 @@ def proposal_section(P, ctx, steps):
     return out
 
 
-def batched_section(P, ctx, samples):
-    """Batched grid: 2 systems x 3 T x 3 p x 128 x 128 endpoints, mixed N, one graph replay, with the
-    autotuned and the default launch shape."""
+def batched_section(P, ctx, samples, tune_samples):
+    """Batched grid: 2 systems x 3 T x 3 p x 128 x 128 endpoints, mixed N, one graph replay. The
+    autotuner picks a launch shape per kernel class (and the grid and grab) on the same grid with
+    tune_samples per task; the choice is cached and applied to the grid with `samples` per task,
+    which is replayed once."""
     from paper_1105_0542_amd import workloads
-    t0b = time.perf_counter()
+    tune_path = os.path.join(os.environ.get("TMPDIR", "/tmp"), f"pimc_batch_tune_{os.getpid()}.txt")
+    t0 = time.perf_counter()
+    systems, rows_t = workloads.evolution_matrix_tasks(samples=tune_samples)
+    bt = P.Batch(ctx, systems, rows_t, seed=1, flags=0)
+    choice = bt.autotune(tune_path)
+    tuned_classes = bt.classes()
+    _, tuned_small_ms, _ = bt.run()
+    for k in range(len(tuned_classes)):
+        bt.set_shape(k, 0)
+    bt.set_tuning(2, 1)
+    _, default_small_ms, _ = bt.run()
+    bt.close()
+    t_tune = time.perf_counter() - t0
+    t0 = time.perf_counter()
     systems, rows = workloads.evolution_matrix_tasks(samples=samples)
     bt = P.Batch(ctx, systems, rows, seed=1, flags=0)
-    t_plan = time.perf_counter() - t0b
-    tune_path = os.path.join(os.environ.get("TMPDIR", "/tmp"), "pimc_batch_tune.txt")
-    choice = bt.autotune(tune_path)
+    applied = bt.autotune(tune_path)                     # the cached choice: no timing
+    t_plan = time.perf_counter() - t0
     out, ms, st = bt.run()
-    bt.set_tuning(2, 1)
-    _, default_ms, _ = bt.run()
-    bt.set_tuning(*choice)
     slices = sum(r[7] * r[5] for r in rows)
     # FP64 operations: per slice 2 (E_p - 1) for the Horner chains plus 6, as for the headline kernel
     flops = sum(r[7] * r[5] * (2 * (E_TABLE[r[6]] - 1) + 6) for r in rows)
-    nonfinite = int((out["n_nonfinite"]).sum())
+    classes = [{"p": c["p"], "N": "16" if c["n16"] else "32..512", "tasks": c["n_tasks"],
+                "shape": {"subtree_levels": c["subtree_levels"], "block": c["block"],
+                          "waves_per_eu": c["waves_per_eu"], "slice_batch": c["slice_batch"]},
+                "candidates": c["n_shapes"], "tuned_ms": c["tuned_ms"], "default_ms": c["default_ms"],
+                "gain": c["default_ms"] / c["tuned_ms"] if c["tuned_ms"] > 0 else None} for c in tuned_classes]
     line = {
         "workload": "128x128 endpoint grid on [-4,4]^2, (A,g) in {(1,1),(-1,4)}, T in {0.5,1,2}, p in {8,12,18}, "
                     f"N in 16..512 by a fixed hash, {samples} samples per task, level N only",
-        "tasks": len(rows), "graph_ms": ms, "slice_evals_per_s": slices / (ms / 1e3),
+        "tasks": len(rows), "samples_per_task": samples, "graph_ms": ms, "slice_evals_per_s": slices / (ms / 1e3),
         "fp64_frac": flops / (ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
-        "default_shape_graph_ms": default_ms, "autotuned": {"grid_mult_x2": choice[0], "grab": choice[1]},
-        "plan_s": t_plan, "tasks_with_nonfinite_weights": int((out["n_nonfinite"].sum(axis=1) > 0).sum()),
-        "nonfinite_weights": nonfinite,
+        "autotune": {"tuned_on_samples_per_task": tune_samples, "tune_s": t_tune, "grid_mult_x2": choice[0],
+                     "grab": choice[1], "applied": list(applied), "classes": classes,
+                     "graph_ms_tuned": tuned_small_ms, "graph_ms_default": default_small_ms},
+        "plan_s": t_plan, "tasks_with_nonfinite_weights": int((out["n_nonfinite"] > 0).sum()),
+        "nonfinite_weights": int(out["n_nonfinite"].sum()), "status": st,
     }
     bt.close()
+    try:
+        os.remove(tune_path)
+    except OSError:
+        pass
     return line
 
 
@@ -513,8 +638,13 @@ def main():
     ap.add_argument("--samples", type=int, default=N_SAMPLES)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision-samples", type=int, default=PREC["samples"])
-    ap.add_argument("--batch-samples", type=int, default=10_000,
+    ap.add_argument("--batch-samples", type=int, default=C3_SAMPLES,
                     help="samples per task of the batched 128x128 grid (0 skips it)")
+    ap.add_argument("--batch-tune-samples", type=int, default=C3_TUNE_SAMPLES,
+                    help="samples per task of the grid the autotuner times")
+    ap.add_argument("--c2-samples", type=int, default=C2["samples"],
+                    help="samples per point of the convergence sweep (0 skips it)")
+    ap.add_argument("--only-c2", action="store_true", help="run only the convergence sweep, with its CPU references")
     ap.add_argument("--copy-probe", action="store_true", help="only run the 512 MiB copy used to scale HBM counters")
     ap.add_argument("--only-headline", action="store_true",
                     help="run only the timed p=18 sweep (for profiler runs): no other section, no cpu baseline")
@@ -542,7 +672,9 @@ def main():
 
     # The oracle runs first, in worker processes forked before this process touches the GPU.
     skip_cpu = (args.no_cpu_baseline or args.only_headline or args.only_proposal or args.only_spectrum or
-                args.only_mpt or args.only_general or args.only_vector or args.only_batched)
+                args.only_mpt or args.only_general or args.only_vector or args.only_batched or args.only_c2)
+    C2["samples"] = args.c2_samples
+    c2_refs = c2_references() if ((not skip_cpu or args.only_c2) and args.c2_samples > 0) else None
     cpu = None if skip_cpu else cpu_baseline(CPU_SAMPLE_PATHS)
     prec_ref = None if skip_cpu else oracle_precision_reference()
     spec_ref = None if (skip_cpu and not args.only_spectrum) else oracle_spectrum_reference()
@@ -564,7 +696,11 @@ def main():
         ctx.close()
         return
     if args.only_batched:
-        print(json.dumps({"batched": batched_section(P, ctx, args.batch_samples)}), flush=True)
+        print(json.dumps({"batched": batched_section(P, ctx, args.batch_samples, args.batch_tune_samples)}), flush=True)
+        ctx.close()
+        return
+    if args.only_c2:
+        print(json.dumps({"c2": c2_section(P, ctx, c2_refs)}), flush=True)
         ctx.close()
         return
     if args.only_spectrum:
@@ -653,7 +789,9 @@ def main():
             "rel_diff_fp64_gpu": abs(small["fp64"] - prec_ref) / prec_ref,
             "rel_diff_fp32_gpu": abs(small["fp32"] - prec_ref) / prec_ref}
 
-    batch_line = batched_section(P, ctx, args.batch_samples) if args.batch_samples > 0 else None
+    batch_line = (batched_section(P, ctx, args.batch_samples, args.batch_tune_samples)
+                  if args.batch_samples > 0 else None)
+    c2_line = c2_section(P, ctx, c2_refs) if args.c2_samples > 0 else None
 
     flow_line = proposal_section(P, ctx, args.flow_steps) if args.flow_steps > 0 else None
     spec_line = spectrum_section(P, ctx, spec_ref, bases.get("spectrum"))
@@ -661,6 +799,18 @@ def main():
     gen_line = general_section(P, ctx, bases.get("general"))
     vec_line = vector_section(P, ctx, vec_ref, bases.get("vector"))
 
+    counters = measured_counter_flops()
+    roofline = {
+        "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+        "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic(args.samples),
+        "kernel": "k_amplitude<Shape<5,256,2,16>, QuarticEval64<18>>", "kernel_avg_ms": kernel_avg_s * 1e3,
+        "flop_per_slice": FLOP_PER_SLICE, "flop_per_launch": flop_per_launch,
+    }
+    if counters is not None:
+        # hardware FP64 FLOPs (all of them: slices, Box-Muller, bridge, reductions) per launch at this size
+        hw = counters["fp64_flops_per_sample"] * args.samples
+        roofline["counter_frac"] = hw / kernel_avg_s / 1e12 / FP64_PEAK_TFLOPS
+        roofline["counter_valu_insts_per_sample"] = counters["valu_insts_per_sample"]
     line = {
         "metric": "slice-evals/s (p=18, FP64)",
         "value": value,
@@ -681,32 +831,92 @@ def main():
             "p": P_LEVEL, "s": S_DEPTH, "samples_per_point": args.samples, "points": len(POINTS),
             "slice_evals_per_sample": slices_per_sample(S_DEPTH, True),
         },
-        "roofline": {
-            "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic(args.samples),
-            "kernel": "k_amplitude<5, QuarticEval64<18>>", "kernel_avg_ms": kernel_avg_s * 1e3,
-            "flop_per_slice": FLOP_PER_SLICE, "flop_per_launch": flop_per_launch,
-        },
-        "level_s_only": {"slice_evals_per_s": level_s_rate,
-                         "frac": level_s_rate * FLOP_PER_SLICE / 1e12 / FP64_PEAK_TFLOPS,
-                         "note": "same point g=10 T=1 without the coarser levels: 1024 slices per sample"},
+        "roofline": roofline,
         "results": {f"g={g:g},T={T:g}": {"A_1024": r[S_DEPTH].amp, "err": r[S_DEPTH].err,
                                           "relvar": r[S_DEPTH].relvar, "nonfinite": r[S_DEPTH].n_nonfinite}
                     for (g, T, r) in last},
     }
-    line["precision"] = prec_line
-    if batch_line is not None:
-        line["batched"] = batch_line
-    if flow_line is not None:
-        line["proposal"] = flow_line
+    # detailed sections first (long arrays), then a compact summary of every section last, so that the
+    # end of the line -- what a log tail keeps -- carries every figure
+    if c2_line is not None:
+        line["c2"] = c2_line
     line["spectrum"] = spec_line
     line["mpt"] = mpt_line
     line["general"] = gen_line
     line["vector"] = vec_line
+    if flow_line is not None:
+        line["proposal"] = flow_line
+    if batch_line is not None:
+        line["batched"] = batch_line
+    line["precision"] = prec_line
+    line["level_s_only"] = {"slice_evals_per_s": level_s_rate,
+                            "frac": level_s_rate * FLOP_PER_SLICE / 1e12 / FP64_PEAK_TFLOPS,
+                            "note": "same point g=10 T=1 without the coarser levels: 1024 slices per sample"}
+    line["summary"] = summarize(line)
     if cpu is not None:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
     ctx.close()
+
+
+def _r(x, d=4):
+    return None if x is None else float(f"{x:.{d}g}")
+
+
+def summarize(line):
+    """Compact figures of every section (a few KB) for the end of the line."""
+    out = {"headline": {"value": _r(line["value"]), "frac": _r(line["roofline"]["frac"]),
+                        "counter_frac": _r(line["roofline"].get("counter_frac")),
+                        "kernel_avg_ms": _r(line["roofline"]["kernel_avg_ms"])},
+           "level_s_only": {"value": _r(line["level_s_only"]["slice_evals_per_s"]),
+                            "frac": _r(line["level_s_only"]["frac"])}}
+    pr = line.get("precision")
+    if pr:
+        out["precision"] = {"fp64_rate": _r(pr["fp64"]["slice_evals_per_s"]), "fp32_rate": _r(pr["fp32"]["slice_evals_per_s"]),
+                            "rel_diff_fp32_vs_fp64_gpu": _r(pr["rel_diff_fp32_vs_fp64_gpu"]),
+                            "rel_stat_err": _r(pr["rel_stat_err"])}
+        for k, v in pr.items():
+            if k.startswith("oracle_first_"):
+                out["precision"][k] = {kk: _r(vv) for kk, vv in v.items()}
+    b = line.get("batched")
+    if b:
+        out["batched"] = {"samples_per_task": b["samples_per_task"], "graph_s": _r(b["graph_ms"] / 1e3),
+                          "slice_evals_per_s": _r(b["slice_evals_per_s"]), "fp64_frac": _r(b["fp64_frac"]),
+                          "graph_ms_tuned_vs_default_small": [_r(b["autotune"]["graph_ms_tuned"]),
+                                                              _r(b["autotune"]["graph_ms_default"])],
+                          "classes": [[c["p"], c["N"], [c["shape"][k] for k in ("subtree_levels", "block",
+                                                                                  "waves_per_eu", "slice_batch")],
+                                       _r(c["gain"], 3)] for c in b["autotune"]["classes"]]}
+    f = line.get("proposal")
+    if f:
+        out["proposal"] = {"plain": {"relvar": _r(f["plain"]["relvar"]), "t_1e-5_s": _r(f["plain"]["time_to_rel_err_1e-5_s"]),
+                                     "run_s": _r(f["plain"]["run_to_target"]["device_s"])}}
+        for key in ("proposal", "proposal_wide_batch"):
+            if key in f:
+                g = f[key]
+                out["proposal"][key] = {"batch": g["batch"], "train_s": _r(g["train_ms"] / 1e3), "relvar": _r(g["relvar"]),
+                                        "ess_frac": _r(g["ess_frac"]),
+                                        "t_1e-5_s": _r(g["time_to_rel_err_1e-5_s"]["estimation"]),
+                                        "t_1e-5_with_training_s": _r(g["time_to_rel_err_1e-5_s"]["with_training"]),
+                                        "run_s": _r(g["run_to_target"]["device_s"]) if g.get("run_to_target") else None,
+                                        "agreement_sigma": _r(g["agreement_sigma"], 3)}
+    c = line.get("c2")
+    if c:
+        slopes = {}
+        for key, r in c["points"].items():
+            g, p, T = key.split(",")
+            slopes.setdefault(f"{g},{T}", {})[p.split("=")[1]] = _r(r.get("slope"), 3)
+        out["c2"] = {"slice_evals_per_s": _r(c["slice_evals_per_s"]), "slopes": slopes,
+                     "g0_max_abs_z": {p: _r(v["max_abs_z_vs_exact_discretized"], 3) for p, v in c["g0"].items()},
+                     "max_abs_z_N1024_vs_dvr": _r(max(abs(r["z_N1024"]) for r in c["points"].values()
+                                                      if r.get("z_N1024") is not None), 3)}
+    out["mpt"] = {p: {"rate": _r(r["slice_evals_per_s"]), "frac": _r(r["fp64_frac"])} for p, r in line["mpt"]["per_p"].items()}
+    gq = line["general"]["quartic_g10_general_mode"]
+    out["general"] = {"rate": _r(gq["slice_evals_per_s"]), "frac": _r(gq["roofline"]["frac"])}
+    out["vector"] = {d: {"rate": _r(r["slice_evals_per_s"]), "frac": _r(r["fp64_frac"])} for d, r in line["vector"]["per_dim"].items()}
+    out["spectrum"] = [{"matrix_ms": _r(r["matrix_ms"]), "lanczos_ms_per_step": _r(r["lanczos_ms_per_step"]),
+                        "max_abs_diff_vs_dvr": _r(r.get("max_abs_diff_vs_dvr"), 3)} for r in line["spectrum"]]
+    return out
 
 
 if __name__ == "__main__":

@@ -59,6 +59,7 @@ enum {
 #define PIMC_MAX_DEGREE 8      /* highest power of q in a potential                                 */
 #define PIMC_MAX_P 18          /* highest effective-action level                                    */
 #define PIMC_MAX_S 20          /* N <= 2^20                                                         */
+#define PIMC_CHUNK_PATHS 4096  /* paths per canonical chunk of the estimators' sums                 */
 
 /* V(q) = sum_{j=0..degree} coef[j] q^j. The paper's anharmonic oscillator (Sec. 3.3)
  * V = A q^2/2 + g q^4/24 is coef[2] = A/2, coef[4] = g/24. */
@@ -116,6 +117,9 @@ int pimc_destroy(pimc_ctx *ctx);
  * path indices 0..n_samples-1 (Sec. 4.1: trajectories by bisection, action eq.(SNp), e^{-S}
  * averaged, error per level). Without PIMC_HIERARCHY only levels 0 and s are estimated (entries
  * 1..s-1 have n = 0). out: caller-owned host array of log2(N)+1 entries.
+ * The sums over paths are taken in canonical chunks of PIMC_CHUNK_PATHS consecutive path indices
+ * (groups of 64 paths in a fixed order, then the chunks in index order), so results are bitwise
+ * reproducible, independent of the launch, and level n of an s-run equals the n-run bitwise.
  * Returns PIMC_WNONFINITE (> 0) if any weight was not finite. */
 int pimc_amplitude(pimc_ctx *ctx, const pimc_potential *V, double m, double a, double b, double T,
                    uint32_t N, int p, uint64_t n_samples, uint64_t seed, uint32_t stream,
@@ -257,8 +261,10 @@ typedef struct pimc_batch pimc_batch;
 /* Plan a batch: validates every task, builds one table set per (system, m, p, T), numbers every
  * task's canonical chunks (the same chunks as a single pimc_amplitude call, so a task's result is
  * bitwise the single-call result), uploads everything and captures one HIP graph: queue reset, one
- * persistent launch per distinct p, the canonical reduction and the copy of the sums to pinned host
- * memory. flags: 0 or PIMC_HIERARCHY (FP64 only). The batch owns its device memory and stream. */
+ * persistent launch per kernel class (the tasks of one p with N = 16, or with N >= 32), the
+ * canonical reduction and the copy of the sums to pinned host memory. flags: 0 or PIMC_HIERARCHY
+ * (FP64 only). The batch owns its device memory and stream. Each class starts with its default
+ * launch shape. */
 int pimc_batch_create(pimc_ctx *ctx, const pimc_potential *systems, int n_systems, const pimc_task *tasks,
                       size_t n_tasks, uint64_t seed, uint32_t flags, pimc_batch **out);
 
@@ -267,22 +273,51 @@ int pimc_batch_create(pimc_ctx *ctx, const pimc_potential *systems, int n_system
  * time of the replay. Returns PIMC_WNONFINITE if any task had non-finite weights. */
 int pimc_batch_run(pimc_batch *batch, pimc_level_result *out, double *ms);
 
-/* Launch shape of the persistent kernels: grid = resident workgroups * grid_mult_x2 / 2
+/* The same with the results written to device memory when out_on_device is nonzero: out is then a
+ * caller-owned device buffer of n_tasks * (s_max+1) records (for example a torch tensor), filled by
+ * a copy on the context's stream that has completed when the call returns. */
+int pimc_batch_run_to(pimc_batch *batch, pimc_level_result *out, int out_on_device, double *ms);
+
+/* Scheduling of the persistent kernels: grid = resident workgroups * grid_mult_x2 / 2
  * (grid_mult_x2 in 1..8), each queue grab takes `grab` consecutive chunks (1..64). Changes only
  * scheduling: results are bitwise identical for every setting. Re-captures the graph. */
 int pimc_batch_set_tuning(pimc_batch *batch, int grid_mult_x2, uint32_t grab);
 
-/* Time every candidate launch shape with one replay each, keep the fastest, and append it to the
- * text cache file cache_path (may be NULL) under a key of (GPU architecture, p values, largest s,
- * flags); a later call with a matching key reuses the cached choice without timing. */
+/* A kernel class of a batch and its launch shape: subtree levels held in registers, workgroup
+ * size, occupancy target (waves per SIMD) and slices evaluated together. Levels p = 8, 12 and 18
+ * have several compiled shapes (8 for tasks with N >= 32, 5 for N = 16), every other level one.
+ * tuned_ms / default_ms: the autotuner's device time of the class alone with the chosen and with
+ * the default shape (0 before tuning). */
+typedef struct {
+    int p;
+    int n16;                     /* 1: the tasks with N = 16; 0: the tasks with N >= 32 */
+    uint64_t n_tasks, n_items;   /* tasks, canonical chunks */
+    int shape, n_shapes;         /* chosen shape index (0 = default), number of candidates */
+    int subtree_levels, block, waves_per_eu, slice_batch;
+    double tuned_ms, default_ms;
+} pimc_batch_class;
+int pimc_batch_n_classes(const pimc_batch *batch);
+int pimc_batch_class_info(const pimc_batch *batch, int k, pimc_batch_class *out);
+
+/* Select launch shape `shape` (0..n_shapes-1) for class k. Every shape gives the same bits: the
+ * canonical chunks fix the order of every sum. Re-captures the graph. */
+int pimc_batch_set_shape(pimc_batch *batch, int k, int shape);
+
+/* Autotuner: for every class, time each candidate launch shape on the class alone (one launch
+ * each) and keep the fastest; then time grid_mult_x2 in {1, 2, 4} x grab in {1, 4, 16} on whole
+ * replays. The choice is appended to the text cache file cache_path (may be NULL) under a key of
+ * (GPU architecture, the classes, largest s, flags); a later call with a matching key -- for
+ * example on a batch of the same tasks with more samples each -- applies the cached choice without
+ * timing. */
 int pimc_batch_autotune(pimc_batch *batch, const char *cache_path, int *grid_mult_x2, uint32_t *grab);
 
 int pimc_batch_destroy(pimc_batch *batch);
 const char *pimc_batch_last_error(const pimc_batch *batch);
 
-/* Create, run once and destroy: out as in pimc_batch_run. */
+/* Create, run once and destroy: out as in pimc_batch_run_to (host memory, or a caller-owned device
+ * buffer when out_on_device is nonzero). */
 int pimc_amplitude_batch(pimc_ctx *ctx, const pimc_potential *systems, int n_systems, const pimc_task *tasks,
-                         size_t n_tasks, uint64_t seed, uint32_t flags, pimc_level_result *out);
+                         size_t n_tasks, uint64_t seed, uint32_t flags, pimc_level_result *out, int out_on_device);
 
 /* ---- learned proposal: affine couplings over the bisection normals -------------------------------
  *

@@ -18,6 +18,7 @@ PIMC_ENOMEM = -3
 PIMC_EDEVICE = -4
 PIMC_WNONFINITE = 1
 PIMC_WNOTCONVERGED = 2
+PIMC_CHUNK_PATHS = 4096          # paths per canonical chunk (include/pimc.h)
 
 FLAG_FP64 = 0
 FLAG_FP32_POLY = 1
@@ -119,6 +120,13 @@ class _LevelResult(C.Structure):
                 ("ess", C.c_double), ("n", C.c_uint64), ("n_nonfinite", C.c_uint64)]
 
 
+class BatchClass(C.Structure):
+    _fields_ = [("p", C.c_int), ("n16", C.c_int), ("n_tasks", C.c_uint64), ("n_items", C.c_uint64),
+                ("shape", C.c_int), ("n_shapes", C.c_int), ("subtree_levels", C.c_int), ("block", C.c_int),
+                ("waves_per_eu", C.c_int), ("slice_batch", C.c_int), ("tuned_ms", C.c_double),
+                ("default_ms", C.c_double)]
+
+
 @dataclass
 class LevelResult:
     amp: float
@@ -196,7 +204,15 @@ def load_library():
     lib.pimc_batch_last_error.argtypes = [vp]
     lib.pimc_amplitude_batch.restype = C.c_int
     lib.pimc_amplitude_batch.argtypes = [vp, P(Potential), C.c_int, P(Task), C.c_size_t, C.c_uint64, C.c_uint32,
-                                         P(_LevelResult)]
+                                         vp, C.c_int]
+    lib.pimc_batch_run_to.restype = C.c_int
+    lib.pimc_batch_run_to.argtypes = [vp, vp, C.c_int, P(C.c_double)]
+    lib.pimc_batch_n_classes.restype = C.c_int
+    lib.pimc_batch_n_classes.argtypes = [vp]
+    lib.pimc_batch_class_info.restype = C.c_int
+    lib.pimc_batch_class_info.argtypes = [vp, C.c_int, P(BatchClass)]
+    lib.pimc_batch_set_shape.restype = C.c_int
+    lib.pimc_batch_set_shape.argtypes = [vp, C.c_int, C.c_int]
     lib.pimc_last_kernel_ms.restype = C.c_int
     lib.pimc_last_kernel_ms.argtypes = [vp, P(C.c_double)]
     lib.pimc_flow_create.restype = C.c_int
@@ -552,8 +568,32 @@ class Batch:
         arr = np.frombuffer(self._out, dtype=_RESULT_DTYPE).reshape(self.n_tasks, self.s_max + 1).copy()
         return arr, ms.value, st
 
+    def run_to_device(self, out):
+        """One graph replay with the results written into the caller's device buffer `out` (a
+        contiguous torch CUDA tensor of at least n_tasks * (s_max+1) * 56 bytes, e.g. float64 of
+        shape [n_tasks, s_max+1, 7]: amp, err, log_amp, relvar, ess, then n and n_nonfinite as
+        64-bit integers). Returns (device ms, status)."""
+        need = self.n_tasks * (self.s_max + 1) * C.sizeof(_LevelResult)
+        if not out.is_cuda or not out.is_contiguous() or out.numel() * out.element_size() < need:
+            raise ValueError(f"need a contiguous device tensor of at least {need} bytes")
+        ms = C.c_double(0)
+        st = self._check(self.lib.pimc_batch_run_to(self.h, C.c_void_p(out.data_ptr()), 1, C.byref(ms)))
+        return ms.value, st
+
     def set_tuning(self, grid_mult_x2: int, grab: int):
         self._check(self.lib.pimc_batch_set_tuning(self.h, grid_mult_x2, grab))
+
+    def classes(self):
+        """Kernel classes (p, N = 16 or not) with their launch shapes and autotuner timings."""
+        out = []
+        for k in range(self.lib.pimc_batch_n_classes(self.h)):
+            ci = BatchClass()
+            self._check(self.lib.pimc_batch_class_info(self.h, k, C.byref(ci)))
+            out.append({f: getattr(ci, f) for f, _ in BatchClass._fields_})
+        return out
+
+    def set_shape(self, k: int, shape: int):
+        self._check(self.lib.pimc_batch_set_shape(self.h, k, shape))
 
     def autotune(self, cache_path=None):
         g = C.c_int(0)

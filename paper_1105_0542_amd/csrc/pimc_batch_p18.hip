@@ -1,0 +1,6 @@
+// Launch-shape variants of the batched kernel at level p = 18 (see pimc_batch.hpp).
+#include "pimc_batch.hpp"
+
+namespace pimc {
+PIMC_BATCH_TUNED_DEF(18)
+}  // namespace pimc

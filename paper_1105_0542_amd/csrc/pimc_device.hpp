@@ -3,14 +3,14 @@
 //  * normal_pair: one Philox4x32-10 call (Salmon et al., SC'11) per pair of heap nodes (2j, 2j+1)
 //    of a path, counter (j, path_lo32, path_hi32, stream), key (seed_lo32, seed_hi32); two 53-bit
 //    uniforms u = ((b >> 11) | 1) 2^-53 (open interval, no ln 0); Box-Muller r = sqrt(-2 ln u1),
-//    theta = 2 pi u2; node 2j gets r cos(theta), node 2j+1 gets r sin(theta). This replaces the
+//    theta = 2 pi u2; node 2j gets r cos(theta), node 2j+1 gets r sin(theta). ln, sin and cos use
+//    the table reductions of pimc_math.hpp with the table in LDS. This replaces the
 //    SPRNG uniforms and cosine-only Box-Muller of Sec. 4.1 with a generator that any lane can
 //    evaluate for any node without state.
 //    Within one wave the node index j and the stream are uniform, and the path words are constant
 //    over a path: the first two Philox rounds therefore need no per-node vector multiply (their
 //    multiplications are either scalar or hoisted per path), leaving 16 of 20 per-lane 32x32->64
 //    products per call; each round's two three-input xors are single v_bitop3 instructions.
-//    ln, sqrt, sin and cos come from pimc_math.hpp (argument-range-specific polynomials).
 //  * Bisection (Sec. 4.1): the point of heap node h (level n = floor(log2 h)+1, offset
 //    i = h - 2^(n-1)) is sigma_n z_h + (left + right)/2 with sigma_n^2 = T/2^(n+1), the conditional
 //    (Brownian-bridge) width that makes the kinetic term and normalizations integrate out to the
@@ -111,21 +111,22 @@ __device__ __forceinline__ void philox_node_pair(const RngKey& key, const PathRn
     o0 = c0; o1 = c1; o2 = c2; o3 = c3;
 }
 
-// Odd multiple of 2^-53 from the 64-bit word lo | hi << 32: exact in FP64.
-__device__ __forceinline__ double odd53(uint32_t lo, uint32_t hi) {
-    return double(hi) * 0x1p-32 + double((lo >> 11) | 1u) * 0x1p-53;
-}
-
-// Standard normals of heap nodes 2j (even) and 2j+1 (odd).
-__device__ __forceinline__ void normal_pair(const RngKey& key, const PathRng& pr, uint32_t j,
+// Standard normals of heap nodes 2j (even) and 2j+1 (odd); bm: the Box-Muller table (LDS).
+__device__ __forceinline__ void normal_pair(const RngKey& key, const PathRng& pr, uint32_t j, const double* bm,
                                             double& z_even, double& z_odd) {
     uint32_t o0, o1, o2, o3;
     philox_node_pair(key, pr, j, o0, o1, o2, o3);
-    const double r = sqrt_pos(neg2_log_odd53(o0, o1));
+    const double r = sqrt_pos(neg2_log_u53(o0, o1, bm));
     double sn, cs;
-    sincos_2pi(odd53(o2, o3), sn, cs);
+    sincos_2pi_u53(o2, o3, bm, sn, cs);
     z_even = r * cs;
     z_odd = r * sn;
+}
+
+// Copy the Box-Muller table into LDS: every thread of the workgroup (nthreads of them) takes part;
+// a barrier must follow before the first normal is drawn.
+__device__ __forceinline__ void load_bm_table(double* lds, int nthreads) {
+    for (int i = threadIdx.x; i < kBoxMullerTable; i += nthreads) lds[i] = kBMTable[i];
 }
 
 // Normal sources of the bisection walker: pair(j, z_even, z_odd) gives the normals of heap nodes
@@ -133,7 +134,8 @@ __device__ __forceinline__ void normal_pair(const RngKey& key, const PathRng& pr
 struct PhiloxSource {
     RngKey key;
     PathRng pr;
-    __device__ __forceinline__ void pair(uint32_t j, double& ze, double& zo) const { normal_pair(key, pr, j, ze, zo); }
+    const double* bm;
+    __device__ __forceinline__ void pair(uint32_t j, double& ze, double& zo) const { normal_pair(key, pr, j, bm, ze, zo); }
 };
 
 // Normals held in device memory, feature-major: node h of path `path` at z[(h-1)*ld + path].

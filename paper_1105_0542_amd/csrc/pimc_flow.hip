@@ -1,12 +1,12 @@
 // Learned-proposal kernels (gfx950): affine couplings over the bisection normals.
 //
 // Per-path tensors are feature-major, X[(h-1)*ld + path] for heap node h, so every per-coordinate
-// access of consecutive paths is coalesced. A coupling workgroup takes a tile of 64 paths: the
-// conditioner inputs are rounded to bfloat16 into LDS, the two MLP layers run on
-// v_mfma_f32_16x16x32_bf16 (wave w owns paths 16w..16w+15; operand lanes: A[l%16][8(l/16)+i],
-// B[8(l/16)+i][l%16], C[4(l/16)+j][l%16]), and the MFMA output layout puts s_hat and t of the same
-// (path, coordinate) in the same lane, so the FP64 affine update and log-det follow without
-// another exchange.
+// access of consecutive paths is coalesced. The conditioner inputs are rounded to bfloat16, the two
+// MLP layers run on v_mfma_f32_16x16x32_bf16 as weights x activations (operand lanes:
+// A[l%16][8(l/16)+i], B[8(l/16)+i][l%16], C[4(l/16)+j][l%16]), and the MFMA output layout puts
+// s_hat and t of the same (coordinate, path) in the same lane, so the FP64 affine update and
+// log-det follow without another exchange. The training backward uses v_mfma_f32_16x16x4f32
+// (A[l%16][l/16], B[l/16][l%16], the same C layout).
 #include <hip/hip_runtime.h>
 
 #include "pimc_flow.hpp"
@@ -19,9 +19,6 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-constexpr int kLdK = kFlowK + 8;      // LDS row strides (elements), multiples of 8 (16 B)
-constexpr int kLdH = kFlowH + 8;
-constexpr int kLdP = kFlowTile + 8;
 
 // C(16x16) += A(16 rows x K) * BT(16 rows x K)^T; rows K-contiguous, strides in elements.
 __device__ __forceinline__ floatx4 mma16(const __bf16* A, int lda, const __bf16* BT, int ldb, int K, floatx4 c) {
@@ -67,262 +64,311 @@ __device__ __forceinline__ double exp_logscale(double s) {
     return ldexp(p, int(k));
 }
 
-// ------------------------------------------------------------------------------------ base normals
-// u = the plain sampler's bisection normals (node h of path first_path + i), |u|^2/2, log det = 0.
-__global__ void __launch_bounds__(kBlock) k_flow_base(RngKey key, const int* step, uint64_t first_path, uint64_t n,
-                                                      int D, double* __restrict__ X, uint64_t ld,
+// ------------------------------------------------------------------------------------ training
+// The training step works on tiles of kTP = 16 paths (256 workgroups at a batch of 4096, one per CU):
+//  * k_train_fwd carries a tile through the base normals and every coupling in LDS -- the same
+//    bf16 MFMA products and FP64 affine update as the fused estimation kernel -- and keeps each
+//    layer's input X_c (FP64 planes [h-1][path]) for the backward;
+//  * k_train_bwd recomputes each layer from X_c with the same products and back-propagates through
+//    it on FP32 MFMA (v_mfma_f32_16x16x4f32): the bf16 weights and activations of the forward enter
+//    as exact FP32 values, so the gradient is the derivative of the map the forward computes, up to
+//    FP32 accumulation. It writes, per layer, the output and pre-activation gradients (FP32) and the
+//    conditioner inputs and hidden activations (bf16) as [row][path] planes;
+//  * k_flow_wgrad forms the parameter gradients from those planes: each 16 x 16 block of a weight
+//    gradient and each bias row is summed over the batch by one workgroup in a fixed order.
+constexpr int kTP = 16;                        // paths per training tile
+constexpr int kFusedMaxD = 127;                // coordinates of a tile (N <= 128)
+constexpr int kTLdA = kFlowK + 8;              // xa [P][in] row stride (bf16 elements)
+constexpr int kTLdH = kFlowH + 8;              // hs [P][hid] row stride (bf16 elements)
+constexpr int kTLdG = kFlowH + 4;              // go, gp [P][row] row stride (floats)
+
+// C(16x16) += A(16 rows x K) * BT(16 rows x K)^T on FP32 MFMA: A rows bf16 in global memory
+// (converted exactly), BT rows FP32; K a multiple of 32.
+__device__ __forceinline__ floatx4 mma16_f32_bf16A(const __bf16* A, int lda, const float* BT, int ldb, int K, floatx4 c) {
+    const int l = threadIdx.x & 63;
+    const __bf16* ar = A + (l & 15) * lda + (l >> 4);
+    const float* br = BT + (l & 15) * ldb + (l >> 4);
+    for (int ks = 0; ks < K; ks += 32) {
+        float a[8], bv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            a[q] = float(ar[ks + 4 * q]);
+            bv[q] = br[ks + 4 * q];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], bv[q], c, 0, 0, 0);
+    }
+    return c;
+}
+
+// x_A tile of layer L: bf16 [P][in] from the FP64 tile X[(h-1)*kTP + P] (inputs beyond dA are 0).
+__device__ __forceinline__ void train_xa(const FlowLayerDev& L, const double* X, __bf16* xa) {
+    for (int i = threadIdx.x; i < kTP * kFlowK; i += kBlock) {
+        const int P = i % kTP, k = i / kTP;
+        xa[P * kTLdA + k] = (__bf16)(float)(k < L.dA ? X[L.Aidx[k] * kTP + P] : 0.0);
+    }
+}
+
+// Hidden layer of the tile: wave w computes hidden rows 32w..32w+31 for the 16 paths; pre-activation
+// (with bias) returned in pre[mb][j] for hid = 32w + 16mb + 4(l>>4) + j, path l & 15; h = silu(pre)
+// stored to hs [P][hid] as bf16.
+__device__ __forceinline__ void train_hidden(const FlowLayerDev& L, const __bf16* xa, __bf16* hs, floatx4 (&pre)[2]) {
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+        const int h0 = 32 * w + 16 * mb;
+        pre[mb] = mma16(L.W1 + h0 * kFlowK, kFlowK, xa, kTLdA, kFlowK, floatx4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int hid = h0 + 4 * (l >> 4) + j;
+            pre[mb][j] += L.b1[hid];
+            hs[(l & 15) * kTLdH + hid] = (__bf16)silu(pre[mb][j]);
+        }
+    }
+}
+
+// Output layer: wave w computes s_hat rows 16w..16w+15 (os) and t rows 64+16w.. (ot) for the tile;
+// lane l, slot j holds coordinate 16w + 4(l>>4) + j of path l & 15 (bias not added).
+__device__ __forceinline__ void train_output(const FlowLayerDev& L, const __bf16* hs, floatx4& os, floatx4& ot) {
+    const int w = threadIdx.x >> 6;
+    os = mma16(L.W2 + (16 * w) * kFlowH, kFlowH, hs, kTLdH, kFlowH, floatx4{0.f, 0.f, 0.f, 0.f});
+    ot = mma16(L.W2 + (64 + 16 * w) * kFlowH, kFlowH, hs, kTLdH, kFlowH, floatx4{0.f, 0.f, 0.f, 0.f});
+}
+
+// Base normals (the plain sampler's, stream key.stream + *step), every coupling; X_c (c = 0..L) to
+// the planes Xg + c*plane ([h-1][path], ld), |u|^2/2 and log det per path.
+__global__ void __launch_bounds__(kBlock) k_train_fwd(FlowNet net, RngKey key, const int* step, uint64_t n, int D,
+                                                      double* __restrict__ Xg, uint64_t ld, uint64_t plane,
                                                       double* __restrict__ hu2, double* __restrict__ logdet) {
-    const uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
-    if (i >= n) return;
-    RngKey k = key;
-    if (step) k.stream += uint32_t(*step);
-    const PathRng pr = path_rng(k, first_path + i);
-    double z2 = 0.0;
-    for (int j = 0; 2 * j <= D; ++j) {
-        double ze, zo;
-        normal_pair(k, pr, uint32_t(j), ze, zo);
-        if (j > 0) {
-            X[uint64_t(2 * j - 1) * ld + i] = ze;
-            z2 += ze * ze;
+    __shared__ double X[kFusedMaxD * kTP];
+    __shared__ __attribute__((aligned(16))) __bf16 xa[kTP * kTLdA];
+    __shared__ __attribute__((aligned(16))) __bf16 hs[kTP * kTLdH];      // also the Box-Muller table at first
+    __shared__ double red[kTP][kTP];
+    __shared__ double redl[4][kTP];
+    static_assert(sizeof(hs) >= kBoxMullerTable * sizeof(double), "table fits the hidden tile");
+    const int t = threadIdx.x, l = t & 63, w = t >> 6;
+    const uint64_t p0 = uint64_t(blockIdx.x) * kTP;
+    {   // base normals: thread (P = t & 15, g = t >> 4) takes node pairs j = g, g + 16, ...
+        double* bm = reinterpret_cast<double*>(hs);
+        load_bm_table(bm, kBlock);
+        __syncthreads();
+        RngKey k = key;
+        if (step) k.stream += uint32_t(*step);
+        const int P = t & 15, g = t >> 4;
+        const PathRng pr = path_rng(k, p0 + uint64_t(P));
+        double u2 = 0.0;
+        for (int j = g; 2 * j <= D; j += 16) {
+            double ze, zo;
+            normal_pair(k, pr, uint32_t(j), bm, ze, zo);
+            if (j > 0) {
+                X[(2 * j - 1) * kTP + P] = ze;
+                u2 += ze * ze;
+            }
+            if (2 * j + 1 <= D) {
+                X[(2 * j) * kTP + P] = zo;
+                u2 += zo * zo;
+            }
         }
-        if (2 * j + 1 <= D) {
-            X[uint64_t(2 * j) * ld + i] = zo;
-            z2 += zo * zo;
-        }
+        red[g][P] = u2;
     }
-    hu2[i] = 0.5 * z2;
-    logdet[i] = 0.0;
-}
-
-// ------------------------------------------------------------------------------------ coupling forward
-// y[B] = x[B] exp(s) + t, y[A] = x[A]; log det += sum s. In place when Xout == Xin (copyA = 0).
-__global__ void __launch_bounds__(kBlock) k_coupling_fwd(FlowLayerDev L, const double* Xin, double* Xout, uint64_t ld,
-                                                         uint64_t n, double* __restrict__ logdet, int copyA) {
-    __shared__ __attribute__((aligned(16))) __bf16 xa[kFlowTile * kLdK];
-    __shared__ __attribute__((aligned(16))) __bf16 hs[kFlowTile * kLdH];
-    const int t = threadIdx.x, w = t >> 6, l = t & 63;
-    const uint64_t p0 = uint64_t(blockIdx.x) * kFlowTile;
-    for (int i = t; i < kFlowTile * kFlowK; i += kBlock) {
-        const int k = i / kFlowTile, P = i % kFlowTile;
+    double ldet = 0.0;                               // this wave's share of log det of path l & 15
+    for (int c = 0; c < net.n_layers; ++c) {
+        const FlowLayerDev& L = net.layer[c];
+        __syncthreads();                             // X complete; hs, xa free
+        for (int i = t; i < D * kTP; i += kBlock) {
+            const uint64_t P = p0 + uint64_t(i % kTP);
+            if (P < n) Xg[uint64_t(c) * plane + uint64_t(i / kTP) * ld + P] = X[i];
+        }
+        train_xa(L, X, xa);
+        __syncthreads();
+        floatx4 pre[2];
+        train_hidden(L, xa, hs, pre);
+        __syncthreads();
+        floatx4 os, ot;
+        train_output(L, hs, os, ot);
         double v = 0.0;
-        if (k < L.dA && p0 + P < n) v = Xin[uint64_t(L.Aidx[k]) * ld + p0 + P];
-        xa[P * kLdK + k] = (__bf16)(float)v;
-    }
-    __syncthreads();
-    floatx4 acc[8];
-#pragma unroll
-    for (int nb = 0; nb < 8; ++nb) {
-        acc[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-        acc[nb] = mma16(xa + 16 * w * kLdK, kLdK, L.W1 + 16 * nb * kFlowK, kFlowK, kFlowK, acc[nb]);
-    }
-#pragma unroll
-    for (int nb = 0; nb < 8; ++nb)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int P = 16 * w + 4 * (l >> 4) + j, hid = 16 * nb + (l & 15);
-            hs[P * kLdH + hid] = (__bf16)silu(acc[nb][j] + L.b1[hid]);
-        }
-    __syncthreads();
-#pragma unroll
-    for (int nb = 0; nb < 8; ++nb) {
-        acc[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-        acc[nb] = mma16(hs + 16 * w * kLdH, kLdH, L.W2 + 16 * nb * kFlowH, kFlowH, kFlowH, acc[nb]);
-    }
-    double lsum[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int nb = 0; nb < 4; ++nb)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int k = 16 * nb + (l & 15);
-            const uint64_t P = p0 + 16 * w + 4 * (l >> 4) + j;
+            const int k = 16 * w + 4 * (l >> 4) + j;
             if (k < L.dB) {
-                const float sh = acc[nb][j] + L.b2[k];
-                const float tt = acc[nb + 4][j] + L.b2[64 + k];
-                const float s = 2.0f * tanh_fast(0.5f * sh);
-                if (P < n) {
-                    const uint64_t a = uint64_t(L.Bidx[k]) * ld + P;
-                    Xout[a] = Xin[a] * exp_logscale(double(s)) + double(tt);
-                }
-                lsum[j] += double(s);
+                const float sv = 2.0f * tanh_fast(0.5f * (os[j] + L.b2[k]));
+                const int a = L.Bidx[k] * kTP + (l & 15);
+                X[a] = X[a] * exp_logscale(double(sv)) + double(ot[j] + L.b2[64 + k]);
+                v += double(sv);
             }
         }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        double v = lsum[j];
-        v += __shfl_xor(v, 8, 64);
-        v += __shfl_xor(v, 4, 64);
-        v += __shfl_xor(v, 2, 64);
-        v += __shfl_xor(v, 1, 64);
-        const uint64_t P = p0 + 16 * w + 4 * (l >> 4) + j;
-        if ((l & 15) == 0 && P < n) logdet[P] += v;
+        v += __shfl_xor(v, 16, 64);
+        v += __shfl_xor(v, 32, 64);
+        ldet += v;
     }
-    if (copyA) {
-        for (int i = t; i < kFlowTile * kFlowK; i += kBlock) {
-            const int k = i / kFlowTile, P = i % kFlowTile;
-            if (k < L.dA && p0 + P < n) {
-                const uint64_t a = uint64_t(L.Aidx[k]) * ld + p0 + P;
-                Xout[a] = Xin[a];
-            }
-        }
+    if (l < kTP) redl[w][l] = ldet;
+    __syncthreads();
+    for (int i = t; i < D * kTP; i += kBlock) {
+        const uint64_t P = p0 + uint64_t(i % kTP);
+        if (P < n) Xg[uint64_t(net.n_layers) * plane + uint64_t(i / kTP) * ld + P] = X[i];
+    }
+    if (t < kTP && p0 + t < n) {
+        double u2 = 0.0, ld2 = 0.0;
+        for (int g = 0; g < kTP; ++g) u2 += red[g][t];
+        for (int q = 0; q < 4; ++q) ld2 += redl[q][t];
+        hu2[p0 + t] = 0.5 * u2;
+        logdet[p0 + t] = ld2;
     }
 }
 
-// ------------------------------------------------------------------------------------ coupling backward
-// Given G = d(sum_i alpha_i l_i)/dy for this layer's output and its input x, recompute the layer,
-// overwrite G with the gradient for x and write this tile's parameter gradient to gpart (FP32,
-// [W1 | b1 | W2 | b2] of this layer at gpart + tile*stride + layer_off).
-__global__ void __launch_bounds__(kBlock) k_coupling_bwd(FlowLayerDev L, const double* __restrict__ Xin, double* G,
-                                                         uint64_t ld, uint64_t n, const double* __restrict__ alpha,
-                                                         float* __restrict__ gpart, uint64_t gstride, int layer_off) {
-    extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
-    __bf16* xa = reinterpret_cast<__bf16*>(lds_raw);                  // [P][in]      64 x kLdK
-    __bf16* xaT = xa + kFlowTile * kLdK;                               // [in][P]      64 x kLdP
-    __bf16* hs = xaT + kFlowK * kLdP;                                  // [P][hid], later g_o [P][out]
-    __bf16* hT = hs + kFlowTile * kLdH;                                // [hid][P]     128 x kLdP
-    __bf16* goT = hT + kFlowH * kLdP;                                  // [out][P]
-    __bf16* gp = goT + kFlowH * kLdP;                                  // [P][hid]
-    __bf16* gpT = gp + kFlowTile * kLdH;                               // [hid][P]
-    float* bsum = reinterpret_cast<float*>(gpT + kFlowH * kLdP);       // [4 waves][2][128]
-    const int t = threadIdx.x, w = t >> 6, l = t & 63;
-    const uint64_t p0 = uint64_t(blockIdx.x) * kFlowTile;
-    float* gout = gpart + uint64_t(blockIdx.x) * gstride + layer_off;
-    for (int i = t; i < kFlowTile * kFlowK; i += kBlock) {
-        const int k = i / kFlowTile, P = i % kFlowTile;
-        double v = 0.0;
-        if (k < L.dA && p0 + P < n) v = Xin[uint64_t(L.Aidx[k]) * ld + p0 + P];
-        const __bf16 bv = (__bf16)(float)v;
-        xa[P * kLdK + k] = bv;
-        xaT[k * kLdP + P] = bv;
+// Backward through every layer, last first: G (d sum_i alpha_i l_i / d layer output, [h-1][path])
+// becomes the gradient for the layer input; the planes of TrainPlanes are written for k_flow_wgrad.
+__global__ void __launch_bounds__(kBlock) k_train_bwd(FlowNet net, const double* __restrict__ Xg, double* __restrict__ Gg,
+                                                      uint64_t ld, uint64_t plane, uint64_t n, int D,
+                                                      const double* __restrict__ alpha, TrainPlanes pl) {
+    __shared__ double G[kFusedMaxD * kTP];
+    __shared__ double X[kFusedMaxD * kTP];
+    __shared__ __attribute__((aligned(16))) __bf16 xa[kTP * kTLdA];
+    __shared__ __attribute__((aligned(16))) __bf16 hs[kTP * kTLdH];
+    __shared__ float go[kTP * kTLdG];
+    __shared__ float gp[kTP * kTLdG];
+    const int t = threadIdx.x, l = t & 63, w = t >> 6;
+    const int P = l & 15;
+    const uint64_t p0 = uint64_t(blockIdx.x) * kTP;
+    const bool valid = p0 + uint64_t(P) < n;
+    const double al = valid ? alpha[p0 + P] : 0.0;
+    for (int i = t; i < D * kTP; i += kBlock) {
+        const uint64_t Pi = p0 + uint64_t(i % kTP);
+        G[i] = Pi < n ? Gg[uint64_t(i / kTP) * ld + Pi] : 0.0;
     }
-    __syncthreads();
-    floatx4 pre[8], acc[8];
-#pragma unroll
-    for (int nb = 0; nb < 8; ++nb) {
-        pre[nb] = mma16(xa + 16 * w * kLdK, kLdK, L.W1 + 16 * nb * kFlowK, kFlowK, kFlowK, floatx4{0.f, 0.f, 0.f, 0.f});
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int P = 16 * w + 4 * (l >> 4) + j, hid = 16 * nb + (l & 15);
-            pre[nb][j] += L.b1[hid];
-            const __bf16 hv = (__bf16)silu(pre[nb][j]);
-            hs[P * kLdH + hid] = hv;
-            hT[hid * kLdP + P] = hv;
+    for (int c = net.n_layers - 1; c >= 0; --c) {
+        const FlowLayerDev& L = net.layer[c];
+        float* goT = pl.goT + uint64_t(c) * pl.g_stride;
+        float* gpT = pl.gpT + uint64_t(c) * pl.g_stride;
+        __bf16* hT = pl.hT + uint64_t(c) * pl.h_stride;
+        __bf16* xaT = pl.xaT + uint64_t(c) * pl.xa_stride;
+        __syncthreads();                             // G complete; X, xa, hs, go, gp free
+        for (int i = t; i < D * kTP; i += kBlock) {
+            const uint64_t Pi = p0 + uint64_t(i % kTP);
+            X[i] = Pi < n ? Xg[uint64_t(c) * plane + uint64_t(i / kTP) * ld + Pi] : 0.0;
         }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int nb = 0; nb < 8; ++nb)
-        acc[nb] = mma16(hs + 16 * w * kLdH, kLdH, L.W2 + 16 * nb * kFlowH, kFlowH, kFlowH, floatx4{0.f, 0.f, 0.f, 0.f});
-    __syncthreads();                                                   // hs is reused for g_o below
-    __bf16* go = hs;
-    float gb2[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};          // per nb: sum over this lane's 4 paths
-#pragma unroll
-    for (int nb = 0; nb < 4; ++nb)
+        __syncthreads();
+        train_xa(L, X, xa);
+        __syncthreads();
+        for (int i = t; i < kTP * kFlowK; i += kBlock) {
+            const int Pi = i % kTP, k = i / kTP;
+            if (p0 + uint64_t(Pi) < n) xaT[uint64_t(k) * ld + p0 + Pi] = xa[Pi * kTLdA + k];
+        }
+        floatx4 pre[2];
+        train_hidden(L, xa, hs, pre);
+        __syncthreads();
+        for (int i = t; i < kTP * kFlowH; i += kBlock) {
+            const int Pi = i % kTP, k = i / kTP;
+            if (p0 + uint64_t(Pi) < n) hT[uint64_t(k) * ld + p0 + Pi] = hs[Pi * kTLdH + k];
+        }
+        floatx4 os, ot;
+        train_output(L, hs, os, ot);
+        // affine backward of coordinate k of path P (this lane's slots)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int k = 16 * nb + (l & 15);
-            const int Pl = 16 * w + 4 * (l >> 4) + j;
-            const uint64_t P = p0 + Pl;
+            const int k = 16 * w + 4 * (l >> 4) + j;
             float gsh = 0.f, gt = 0.f;
-            if (k < L.dB && P < n) {
-                const float sh = acc[nb][j] + L.b2[k];
-                const float th = tanh_fast(0.5f * sh);
-                const float s = 2.0f * th;
-                const uint64_t a = uint64_t(L.Bidx[k]) * ld + P;
-                const double es = exp_logscale(double(s));
+            if (k < L.dB && valid) {
+                const float th = tanh_fast(0.5f * (os[j] + L.b2[k]));
+                const float sv = 2.0f * th;
+                const int a = L.Bidx[k] * kTP + P;
+                const double es = exp_logscale(double(sv));
                 const double gy = G[a];
                 G[a] = gy * es;
-                const double gs = gy * Xin[a] * es + alpha[P];
+                const double gs = gy * X[a] * es + al;
                 gsh = float(gs * (1.0 - double(th) * double(th)));
                 gt = float(gy);
             }
-            const __bf16 b_sh = (__bf16)gsh, b_t = (__bf16)gt;
-            go[Pl * kLdH + k] = b_sh;
-            go[Pl * kLdH + 64 + k] = b_t;
-            goT[k * kLdP + Pl] = b_sh;
-            goT[(64 + k) * kLdP + Pl] = b_t;
-            gb2[nb] += gsh;
-            gb2[nb + 4] += gt;
+            go[P * kTLdG + k] = gsh;
+            go[P * kTLdG + 64 + k] = gt;
+            if (valid) {
+                goT[uint64_t(k) * ld + p0 + P] = gsh;
+                goT[uint64_t(64 + k) * ld + p0 + P] = gt;
+            }
         }
-    __syncthreads();
-    // g_h = g_o W2 (A = g_o [P][out], BT = W2T [hid][out]); g_pre = g_h silu'(pre)
-    float gb1[8];
+        __syncthreads();
+        // g_h = W2^T g_o (A = W2T [hid][out]), g_pre = g_h silu'(pre)
 #pragma unroll
-    for (int nb = 0; nb < 8; ++nb) {
-        const floatx4 gh = mma16(go + 16 * w * kLdH, kLdH, L.W2T + 16 * nb * kFlowH, kFlowH, kFlowH,
-                                 floatx4{0.f, 0.f, 0.f, 0.f});
-        gb1[nb] = 0.f;
+        for (int mb = 0; mb < 2; ++mb) {
+            const int h0 = 32 * w + 16 * mb;
+            const floatx4 gh = mma16_f32_bf16A(L.W2T + h0 * kFlowH, kFlowH, go, kTLdG, kFlowH, floatx4{0.f, 0.f, 0.f, 0.f});
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int Pl = 16 * w + 4 * (l >> 4) + j, hid = 16 * nb + (l & 15);
-            const float v = pre[nb][j];
-            const float sg = sigmoid_fast(v);
-            const float g = (p0 + Pl < n) ? gh[j] * (sg * (1.0f + v * (1.0f - sg))) : 0.f;
-            const __bf16 bg = (__bf16)g;
-            gp[Pl * kLdH + hid] = bg;
-            gpT[hid * kLdP + Pl] = bg;
-            gb1[nb] += g;
+            for (int j = 0; j < 4; ++j) {
+                const int hid = h0 + 4 * (l >> 4) + j;
+                const float v = pre[mb][j];
+                const float sg = sigmoid_fast(v);
+                const float g = valid ? gh[j] * (sg * (1.0f + v * (1.0f - sg))) : 0.f;
+                gp[P * kTLdG + hid] = g;
+                if (valid) gpT[uint64_t(hid) * ld + p0 + P] = g;
+            }
         }
-    }
-    __syncthreads();
-    // g_xa = g_pre W1 (A = g_pre [P][hid], BT = W1T [in][hid]) into G[A]
+        __syncthreads();
+        // g_xa = W1^T g_pre (A = W1T [in][hid]) into G of the conditioner coordinates
+        {
+            const floatx4 gx = mma16_f32_bf16A(L.W1T + (16 * w) * kFlowH, kFlowH, gp, kTLdG, kFlowH,
+                                               floatx4{0.f, 0.f, 0.f, 0.f});
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb) {
-        const floatx4 gx = mma16(gp + 16 * w * kLdH, kLdH, L.W1T + 16 * nb * kFlowH, kFlowH, kFlowH,
-                                 floatx4{0.f, 0.f, 0.f, 0.f});
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int k = 16 * nb + (l & 15);
-            const uint64_t P = p0 + 16 * w + 4 * (l >> 4) + j;
-            if (k < L.dA && P < n) G[uint64_t(L.Aidx[k]) * ld + P] += double(gx[j]);
+            for (int j = 0; j < 4; ++j) {
+                const int k = 16 * w + 4 * (l >> 4) + j;
+                if (k < L.dA && valid) G[L.Aidx[k] * kTP + P] += double(gx[j]);
+            }
         }
     }
-    // weight gradients of this tile: wave w owns output rows 32w..32w+31
-    // g_W2[out][hid] = sum_P g_o[P][out] h[P][hid]: A = goT [out][P], BT = hT [hid][P]
-#pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-        for (int nb = 0; nb < 8; ++nb) {
-            const int r0 = 32 * w + 16 * mb;
-            const floatx4 c = mma16(goT + r0 * kLdP, kLdP, hT + 16 * nb * kLdP, kLdP, kFlowTile,
-                                    floatx4{0.f, 0.f, 0.f, 0.f});
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                gout[kFlowOffW2 + (r0 + 4 * (l >> 4) + j) * kFlowH + 16 * nb + (l & 15)] = c[j];
+}
+
+// Parameter gradients of every layer from the planes: blockIdx.y < 64 a 16 x 16 block of g_W2
+// (rows out, columns hid), < 96 a block of g_W1 (rows hid, columns in), else 16 bias rows (b2 rows
+// 0..127, b1 rows 128..255). A weight block: wave w sums paths [w q, (w+1) q) on FP32 MFMA, then the
+// four partial blocks are added in wave order. A bias row: lane-strided sums in FP64, then a wave
+// butterfly. grad: [layer][kFlowNP] FP32.
+__global__ void __launch_bounds__(kBlock) k_flow_wgrad(TrainPlanes pl, uint64_t ld, uint64_t n, float* __restrict__ grad) {
+    __shared__ float part[4][256];
+    const int t = threadIdx.x, l = t & 63, w = t >> 6;
+    const int c = blockIdx.x, b = blockIdx.y;
+    const float* goT = pl.goT + uint64_t(c) * pl.g_stride;
+    const float* gpT = pl.gpT + uint64_t(c) * pl.g_stride;
+    const __bf16* hT = pl.hT + uint64_t(c) * pl.h_stride;
+    const __bf16* xaT = pl.xaT + uint64_t(c) * pl.xa_stride;
+    float* gl = grad + uint64_t(c) * kFlowNP;
+    if (b < 96) {
+        const bool w2 = b < 64;
+        const int r0 = w2 ? 16 * (b / 8) : 16 * ((b - 64) / 4);
+        const int c0 = w2 ? 16 * (b % 8) : 16 * ((b - 64) % 4);
+        const float* A = (w2 ? goT : gpT) + uint64_t(r0 + (l & 15)) * ld;
+        const __bf16* B = (w2 ? hT : xaT) + uint64_t(c0 + (l & 15)) * ld;
+        const uint64_t q = ((n + 15) / 16) * 4;      // paths per wave, a multiple of 4
+        const uint64_t k0 = uint64_t(w) * q, k1 = k0 + q < n ? k0 + q : n;
+        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+        for (uint64_t k = k0; k < k1; k += 4) {
+            const uint64_t kk = k + uint64_t(l >> 4);
+            const float a = kk < k1 ? A[kk] : 0.f;
+            const float bv = kk < k1 ? float(B[kk]) : 0.f;
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc, 0, 0, 0);
         }
-    // g_W1[hid][in] = sum_P g_pre[P][hid] xa[P][in]: A = gpT [hid][P], BT = xaT [in][P]
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-        for (int nb = 0; nb < 4; ++nb) {
-            const int r0 = 32 * w + 16 * mb;
-            const floatx4 c = mma16(gpT + r0 * kLdP, kLdP, xaT + 16 * nb * kLdP, kLdP, kFlowTile,
-                                    floatx4{0.f, 0.f, 0.f, 0.f});
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                gout[(r0 + 4 * (l >> 4) + j) * kFlowK + 16 * nb + (l & 15)] = c[j];
+        for (int j = 0; j < 4; ++j) part[w][(4 * (l >> 4) + j) * 16 + (l & 15)] = acc[j];
+        __syncthreads();
+        const int r = t >> 4, col = t & 15;
+        const float v = ((part[0][t] + part[1][t]) + part[2][t]) + part[3][t];
+        if (w2)
+            gl[kFlowOffW2 + (r0 + r) * kFlowH + c0 + col] = v;
+        else
+            gl[(r0 + r) * kFlowK + c0 + col] = v;
+    } else {
+        const int rb = b - 96;
+        for (int i = 0; i < 4; ++i) {
+            const int row = 16 * rb + 4 * w + i;
+            const float* src = row < 128 ? goT + uint64_t(row) * ld : gpT + uint64_t(row - 128) * ld;
+            double sacc = 0.0;
+            for (uint64_t k = uint64_t(l); k < n; k += 64) sacc += double(src[k]);
+            sacc = wave_sum(sacc);
+            if (l == 0) {
+                if (row < 128)
+                    gl[kFlowOffB2 + row] = float(sacc);
+                else
+                    gl[kFlowOffB1 + row - 128] = float(sacc);
+            }
         }
-    // bias gradients: lanes with equal (l & 15) hold the same column; add the 4 row groups, then waves
-#pragma unroll
-    for (int nb = 0; nb < 8; ++nb) {
-        float a = gb1[nb], b = gb2[nb];
-        a += __shfl_xor(a, 16, 64);
-        a += __shfl_xor(a, 32, 64);
-        b += __shfl_xor(b, 16, 64);
-        b += __shfl_xor(b, 32, 64);
-        if (l < 16) {
-            bsum[(w * 2 + 0) * kFlowH + 16 * nb + l] = a;
-            bsum[(w * 2 + 1) * kFlowH + 16 * nb + l] = b;
-        }
-    }
-    __syncthreads();
-    if (t < kFlowH) {
-        float a = 0.f, b = 0.f;
-        for (int ww = 0; ww < 4; ++ww) {
-            a += bsum[(ww * 2 + 0) * kFlowH + t];
-            b += bsum[(ww * 2 + 1) * kFlowH + t];
-        }
-        gout[kFlowOffB1 + t] = a;
-        gout[kFlowOffB2 + t] = b;
     }
 }
 
@@ -430,29 +476,32 @@ __global__ void __launch_bounds__(kBlock) k_flow_action_grad(const double* __res
     }
 }
 
-// One workgroup per canonical chunk: lane t adds d = expm1(l) of paths c*CH + r*kBlock + t,
-// r = 0..ppl-1, in order; then the waves and the four wave sums in a fixed order.
+// One workgroup per canonical chunk (the order of the plain estimator, pimc_internal.hpp): wave w
+// takes the groups of 64 paths g = w, w + 4, ... of the chunk, adds each group's wave sums of
+// d = expm1(l), d^2 and the non-finite count to its slot in order, and the chunk sum is the slots
+// added in slot order.
 __global__ void __launch_bounds__(kBlock) k_flow_partials(const double* __restrict__ ell, uint64_t ell_first_path,
-                                                          uint64_t n_total, uint64_t first_chunk, uint32_t ppl,
+                                                          uint64_t n_total, uint64_t first_chunk,
                                                           double* __restrict__ partials) {
-    __shared__ double red[4][3];
+    static_assert(kBlock / 64 == kChunkSlots, "one wave per accumulator slot");
+    __shared__ double red[kChunkSlots][3];
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
     const uint64_t c = first_chunk + blockIdx.x;
-    const uint64_t CH = uint64_t(kBlock) * ppl;
-    double s1 = 0.0, s2 = 0.0;
-    int bad = 0;
-    for (uint32_t r = 0; r < ppl; ++r) {
-        const uint64_t path = c * CH + uint64_t(r) * kBlock + t;
-        if (path < n_total) {
-            const double d = expm1(ell[path - ell_first_path]);
-            s1 += d;
-            s2 += d * d;
-            bad += isfinite(d) ? 0 : 1;
-        }
+    const uint64_t first = c * kChunkPaths;
+    double s1 = 0.0, s2 = 0.0, nb = 0.0;
+    for (int g = w; g < kChunkGroups; g += kChunkSlots) {
+        const uint64_t path = first + uint64_t(g) * 64 + uint64_t(l);
+        if (first + uint64_t(g) * 64 >= n_total) break;         // wave-uniform
+        const bool valid = path < n_total;
+        const double d = valid ? expm1(ell[path - ell_first_path]) : 0.0;
+        const bool bad = valid && !isfinite(d);
+        const double sd = wave_sum(d);
+        const double sd2 = wave_sum(d * d);
+        const unsigned long long badmask = __ballot(bad);
+        s1 += sd;
+        s2 += sd2;
+        nb += double(__popcll(badmask));
     }
-    s1 = wave_sum(s1);
-    s2 = wave_sum(s2);
-    double nb = wave_sum(double(bad));
     if (l == 0) {
         red[w][0] = s1;
         red[w][1] = s2;
@@ -461,14 +510,14 @@ __global__ void __launch_bounds__(kBlock) k_flow_partials(const double* __restri
     __syncthreads();
     if (t == 0) {
         double a = 0.0, b = 0.0, e = 0.0;
-        for (int ww = 0; ww < kBlock / 64; ++ww) {
-            a += red[ww][0];
-            b += red[ww][1];
-            e += red[ww][2];
+        for (int q = 0; q < kChunkSlots; ++q) {
+            a += red[q][0];
+            b += red[q][1];
+            e += red[q][2];
         }
-        const uint64_t rem = n_total - c * CH;
+        const uint64_t rem = n_total - first;
         double* o = partials + c * 4;
-        o[0] = double(rem < CH ? rem : CH);
+        o[0] = double(rem < kChunkPaths ? rem : kChunkPaths);
         o[1] = a;
         o[2] = b;
         o[3] = e;
@@ -526,15 +575,6 @@ __global__ void k_flow_seed(double* __restrict__ G, const double* __restrict__ a
 }
 
 // ------------------------------------------------------------------------------------ parameters
-__global__ void k_grad_reduce(const float* __restrict__ gpart, int tiles, uint64_t stride, uint64_t count,
-                              float* __restrict__ grad) {
-    const uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
-    if (i >= count) return;
-    double s = 0.0;
-    for (int t = 0; t < tiles; ++t) s += double(gpart[uint64_t(t) * stride + i]);
-    grad[i] = float(s);
-}
-
 __device__ __forceinline__ void store_bf16_copies(int layer, int off, float v, __bf16* W1, __bf16* W2, __bf16* W1T,
                                                   __bf16* W2T) {
     const __bf16 b = (__bf16)v;
@@ -590,7 +630,6 @@ __global__ void k_step_inc(int* step) { *step += 1; }
 // activations are shared through LDS. In the output layout a lane holds s_hat and t of the same
 // (coordinate, path) in the same register slot.
 constexpr int kFusedPaths = 64;
-constexpr int kFusedMaxD = 127;
 constexpr int kLdXa = kFlowK + 8;                 // x_A tile [path][in], padded rows
 
 // Hidden tile [path][hidden] without padding: 16-byte chunk c of row P is stored at chunk
@@ -619,10 +658,14 @@ k_flow_fused(FlowNet net, RngKey key, uint64_t first_path, uint64_t n, int s, co
     // ---- base normals: group w takes node pairs j = w, w+4, ...; |u|^2 in that order
     double u2 = 0.0;
     {
+        // the Box-Muller table lives in the activation tile until the first coupling needs it
+        double* bm = reinterpret_cast<double*>(act);
+        load_bm_table(bm, kBlock);
+        __syncthreads();
         const PathRng pr = path_rng(key, first_path + local);
         for (int j = w; 2 * j <= D; j += 4) {
             double ze, zo;
-            normal_pair(key, pr, uint32_t(j), ze, zo);
+            normal_pair(key, pr, uint32_t(j), bm, ze, zo);
             if (j > 0) {
                 X[(2 * j - 1) * kFusedPaths + P] = ze;
                 u2 += ze * ze;
@@ -799,30 +842,28 @@ k_flow_fused(FlowNet net, RngKey key, uint64_t first_path, uint64_t n, int s, co
 // ------------------------------------------------------------------------------------ launchers
 static inline uint32_t blocks_for(uint64_t n) { return uint32_t((n + kBlock - 1) / kBlock); }
 
-hipError_t launch_flow_base(const RngKey& key, const int* step, uint64_t first_path, uint64_t n, int D, double* X,
-                            uint64_t ld, double* hu2, double* logdet, hipStream_t st) {
-    hipLaunchKernelGGL(k_flow_base, dim3(blocks_for(n)), dim3(kBlock), 0, st, key, step, first_path, n, D, X, ld, hu2,
+hipError_t launch_train_fwd(const FlowNet& net, const RngKey& key, const int* step, uint64_t n, int D, double* Xg,
+                            uint64_t ld, uint64_t plane, double* hu2, double* logdet, hipStream_t st) {
+    const uint64_t tiles = (n + kTP - 1) / kTP;
+    if (D > kFusedMaxD || tiles == 0 || tiles > 0x7fffffffull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_train_fwd, dim3(uint32_t(tiles)), dim3(kBlock), 0, st, net, key, step, n, D, Xg, ld, plane, hu2,
                        logdet);
     return hipGetLastError();
 }
 
-hipError_t launch_coupling_fwd(const FlowLayerDev& L, const double* Xin, double* Xout, uint64_t ld, uint64_t n,
-                               double* logdet, int copyA, hipStream_t st) {
-    const uint32_t tiles = uint32_t((n + kFlowTile - 1) / kFlowTile);
-    hipLaunchKernelGGL(k_coupling_fwd, dim3(tiles), dim3(kBlock), 0, st, L, Xin, Xout, ld, n, logdet, copyA);
+hipError_t launch_train_bwd(const FlowNet& net, const double* Xg, double* G, uint64_t ld, uint64_t plane, uint64_t n,
+                            int D, const double* alpha, const TrainPlanes& planes, hipStream_t st) {
+    const uint64_t tiles = (n + kTP - 1) / kTP;
+    if (D > kFusedMaxD || tiles == 0 || tiles > 0x7fffffffull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_train_bwd, dim3(uint32_t(tiles)), dim3(kBlock), 0, st, net, Xg, G, ld, plane, n, D, alpha,
+                       planes);
     return hipGetLastError();
 }
 
-size_t coupling_bwd_lds_bytes() {
-    return size_t(kFlowTile * kLdK + kFlowK * kLdP + kFlowTile * kLdH + kFlowH * kLdP + kFlowH * kLdP +
-                  kFlowTile * kLdH + kFlowH * kLdP) * sizeof(__bf16) + size_t(4 * 2 * kFlowH) * sizeof(float);
-}
-
-hipError_t launch_coupling_bwd(const FlowLayerDev& L, const double* Xin, double* G, uint64_t ld, uint64_t n,
-                               const double* alpha, float* gpart, uint64_t gstride, int layer_off, hipStream_t st) {
-    const uint32_t tiles = uint32_t((n + kFlowTile - 1) / kFlowTile);
-    hipLaunchKernelGGL(k_coupling_bwd, dim3(tiles), dim3(kBlock), coupling_bwd_lds_bytes(), st, L, Xin, G, ld, n,
-                       alpha, gpart, gstride, layer_off);
+hipError_t launch_flow_wgrad(const TrainPlanes& planes, int layers, uint64_t ld, uint64_t n, float* grad,
+                             hipStream_t st) {
+    if (layers < 1 || layers > kFlowMaxLayers) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_flow_wgrad, dim3(uint32_t(layers), 96 + 16), dim3(kBlock), 0, st, planes, ld, n, grad);
     return hipGetLastError();
 }
 
@@ -837,9 +878,9 @@ hipError_t launch_flow_action_grad(const double* tab, const int* deg, int K, int
 }
 
 hipError_t launch_flow_partials(const double* ell, uint64_t ell_first_path, uint64_t n_total, uint64_t first_chunk,
-                                uint64_t n_chunks, uint32_t ppl, double* partials, hipStream_t st) {
+                                uint64_t n_chunks, double* partials, hipStream_t st) {
     hipLaunchKernelGGL(k_flow_partials, dim3(uint32_t(n_chunks)), dim3(kBlock), 0, st, ell, ell_first_path, n_total,
-                       first_chunk, ppl, partials);
+                       first_chunk, partials);
     return hipGetLastError();
 }
 
@@ -855,11 +896,6 @@ hipError_t launch_flow_fused(const FlowNet& net, const RngKey& key, uint64_t fir
     return hipGetLastError();
 }
 
-hipError_t flow_prepare() {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_coupling_bwd),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, int(coupling_bwd_lds_bytes()));
-}
-
 hipError_t launch_flow_alpha(const double* ell, uint64_t n, double beta, double* alpha, double* loss_out,
                              const int* step, hipStream_t st) {
     hipLaunchKernelGGL(k_flow_alpha, dim3(1), dim3(kBlock), 0, st, ell, n, beta, alpha, loss_out, step);
@@ -868,12 +904,6 @@ hipError_t launch_flow_alpha(const double* ell, uint64_t n, double beta, double*
 
 hipError_t launch_flow_seed(double* G, const double* alpha, int D, uint64_t ld, uint64_t n, hipStream_t st) {
     hipLaunchKernelGGL(k_flow_seed, dim3(blocks_for(uint64_t(D) * n)), dim3(kBlock), 0, st, G, alpha, D, ld, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_grad_reduce(const float* gpart, int tiles, uint64_t stride, uint64_t count, float* grad,
-                              hipStream_t st) {
-    hipLaunchKernelGGL(k_grad_reduce, dim3(blocks_for(count)), dim3(kBlock), 0, st, gpart, tiles, stride, count, grad);
     return hipGetLastError();
 }
 

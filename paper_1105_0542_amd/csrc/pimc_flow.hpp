@@ -19,7 +19,6 @@ constexpr int kFlowNP = kFlowH * kFlowK + kFlowH + kFlowH * kFlowH + kFlowH;   /
 constexpr int kFlowOffB1 = kFlowH * kFlowK;
 constexpr int kFlowOffW2 = kFlowOffB1 + kFlowH;
 constexpr int kFlowOffB2 = kFlowOffW2 + kFlowH * kFlowH;
-constexpr int kFlowTile = 64;                     // paths per workgroup of the coupling kernels
 constexpr int kFlowMaxLayers = 16;
 
 // One coupling layer as the kernels read it.
@@ -49,32 +48,41 @@ hipError_t launch_flow_fused(const FlowNet& net, const RngKey& key, uint64_t fir
                              double a, double b, double* ell, double* logdet, double* z, uint64_t zld,
                              hipStream_t st);
 
-// Base normals u (the plain sampler's, stream key.stream + *step when step is not null), |u|^2/2,
-// log det = 0.
-hipError_t launch_flow_base(const RngKey& key, const int* step, uint64_t first_path, uint64_t n, int D, double* X,
-                            uint64_t ld, double* hu2, double* logdet, hipStream_t st);
-hipError_t launch_coupling_fwd(const FlowLayerDev& L, const double* Xin, double* Xout, uint64_t ld, uint64_t n,
-                               double* logdet, int copyA, hipStream_t st);
-hipError_t launch_coupling_bwd(const FlowLayerDev& L, const double* Xin, double* G, uint64_t ld, uint64_t n,
-                               const double* alpha, float* gpart, uint64_t gpart_stride, int layer_off,
-                               hipStream_t st);
+// Per-layer gradient planes of the training backward (ld paths per row): output gradients
+// goT [128 out][ld] and pre-activation gradients gpT [128 hid][ld] in FP32, hidden activations
+// hT [128 hid][ld] and conditioner inputs xaT [64 in][ld] in bf16; layer c starts at c * *_stride.
+struct TrainPlanes {
+    float* goT;
+    float* gpT;
+    __bf16* hT;
+    __bf16* xaT;
+    uint64_t g_stride, h_stride, xa_stride;
+};
+
+// Training forward on tiles of 16 paths: base normals (the plain sampler's, stream key.stream +
+// *step when step is not null), every coupling; the input of layer c (c = 0..L, L = the output) in
+// the plane Xg + c * plane ([h-1][path], ld), |u|^2/2 and log det per path.
+hipError_t launch_train_fwd(const FlowNet& net, const RngKey& key, const int* step, uint64_t n, int D, double* Xg,
+                            uint64_t ld, uint64_t plane, double* hu2, double* logdet, hipStream_t st);
+// Training backward, last layer first: G (the seeded gradient for the output, [h-1][path]) and
+// alpha (per-path loss weights); writes the gradient planes for launch_flow_wgrad.
+hipError_t launch_train_bwd(const FlowNet& net, const double* Xg, double* G, uint64_t ld, uint64_t plane, uint64_t n,
+                            int D, const double* alpha, const TrainPlanes& planes, hipStream_t st);
+// Parameter gradients [layer][kFlowNP] (FP32) from the planes, in a fixed order.
+hipError_t launch_flow_wgrad(const TrainPlanes& planes, int layers, uint64_t ld, uint64_t n, float* grad,
+                             hipStream_t st);
 // Level-s action of the paths in X (N <= 128), log weights ell and G = d ell / dz.
 hipError_t launch_flow_action_grad(const double* tab, const int* deg, int K, int even, const double* sig, double shift,
                                    double a, double b, int s, const double* X, uint64_t ld, uint64_t n,
                                    const double* hu2, const double* logdet, double* ell, double* G, hipStream_t st);
 // Canonical chunk sums (n, sum d, sum d^2, non-finite count), d = expm1(ell), of chunks
-// first_chunk .. first_chunk + n_chunks - 1 of ell (chunk = kBlock * ppl paths, the last one may be
-// short: n_total paths in all) into partials[chunk][4].
+// first_chunk .. first_chunk + n_chunks - 1 of ell (canonical chunks of kChunkPaths paths, the last
+// one may be short: n_total paths in all) into partials[chunk][4].
 hipError_t launch_flow_partials(const double* ell, uint64_t ell_first_path, uint64_t n_total, uint64_t first_chunk,
-                                uint64_t n_chunks, uint32_t ppl, double* partials, hipStream_t st);
-// Dynamic LDS of the coupling backward kernel; flow_prepare raises the kernel's LDS limit to it.
-size_t coupling_bwd_lds_bytes();
-hipError_t flow_prepare();
+                                uint64_t n_chunks, double* partials, hipStream_t st);
 hipError_t launch_flow_alpha(const double* ell, uint64_t n, double beta, double* alpha, double* loss_out,
                              const int* step, hipStream_t st);
 hipError_t launch_flow_seed(double* G, const double* alpha, int D, uint64_t ld, uint64_t n, hipStream_t st);
-hipError_t launch_grad_reduce(const float* gpart, int tiles, uint64_t stride, uint64_t count, float* grad,
-                              hipStream_t st);
 hipError_t launch_adam(float* theta, float* m, float* v, const float* grad, int layers, const int* step, float lr,
                        __bf16* W1, __bf16* W2, __bf16* W1T, __bf16* W2T, hipStream_t st);
 hipError_t launch_params_to_bf16(const float* theta, int layers, __bf16* W1, __bf16* W2, __bf16* W1T, __bf16* W2T,

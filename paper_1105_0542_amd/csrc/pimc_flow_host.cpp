@@ -38,7 +38,8 @@ struct pimc_flow {
     float* d_m = nullptr;
     float* d_v = nullptr;
     float* d_grad = nullptr;
-    float* d_gpart = nullptr;            // tiles * L * NP
+    void* d_planes = nullptr;            // gradient planes of the training backward (TrainPlanes)
+    TrainPlanes planes{};
     __bf16* d_W1 = nullptr;              // L * 128 * 64
     __bf16* d_W2 = nullptr;              // L * 128 * 128
     __bf16* d_W1T = nullptr;
@@ -125,30 +126,23 @@ FlowLayerDev layer_dev(const pimc_flow* f, int c) {
     return L;
 }
 
-uint32_t tiles_of(uint64_t n) { return uint32_t((n + kFlowTile - 1) / kFlowTile); }
-
-// Forward of every layer, the action, the loss weights and the backward into d_gpart / d_grad.
-// With step != null (training) the base stream and the loss slot follow the device step counter.
+// Forward of every layer, the action, the loss weights, the backward and the parameter gradients
+// into d_grad. With step != null (training) the base stream and the loss slot follow the device
+// step counter.
 hipError_t enqueue_grad(pimc_flow* f, const RngKey& key, const int* step, double* loss) {
     const Problem& P = f->P;
     const uint64_t B = f->B;
     const size_t plane = size_t(f->D) * B;
     hipStream_t st = f->ctx->stream;
-    hipError_t e = launch_flow_base(key, step, 0, B, f->D, f->d_X, B, f->d_hu2, f->d_logdet, st);
-    for (int c = 0; c < f->L && e == hipSuccess; ++c)
-        e = launch_coupling_fwd(layer_dev(f, c), f->d_X + c * plane, f->d_X + (c + 1) * plane, B, B, f->d_logdet, 1,
-                                st);
+    hipError_t e = launch_train_fwd(f->net, key, step, B, f->D, f->d_X, B, plane, f->d_hu2, f->d_logdet, st);
     if (e == hipSuccess)
         e = launch_flow_action_grad(f->d_tab, f->d_deg, int(P.deg.size()), P.even ? 1 : 0, f->d_sig,
                                     P.shift[size_t(P.s)], P.a, P.b, P.s, f->d_X + size_t(f->L) * plane, B, B,
                                     f->d_hu2, f->d_logdet, f->d_ell, f->d_G, st);
     if (e == hipSuccess) e = launch_flow_alpha(f->d_ell, B, f->beta, f->d_alpha, loss, step, st);
     if (e == hipSuccess) e = launch_flow_seed(f->d_G, f->d_alpha, f->D, B, B, st);
-    const uint64_t stride = uint64_t(f->L) * kFlowNP;
-    for (int c = f->L - 1; c >= 0 && e == hipSuccess; --c)
-        e = launch_coupling_bwd(layer_dev(f, c), f->d_X + c * plane, f->d_G, B, B, f->d_alpha, f->d_gpart, stride,
-                                c * kFlowNP, st);
-    if (e == hipSuccess) e = launch_grad_reduce(f->d_gpart, int(tiles_of(B)), stride, stride, f->d_grad, st);
+    if (e == hipSuccess) e = launch_train_bwd(f->net, f->d_X, f->d_G, B, plane, B, f->D, f->d_alpha, f->planes, st);
+    if (e == hipSuccess) e = launch_flow_wgrad(f->planes, f->L, B, B, f->d_grad, st);
     return e;
 }
 
@@ -199,7 +193,7 @@ int reset_optimizer(pimc_flow* f) {
 
 void free_flow(pimc_flow* f) {
     destroy_graph(f);
-    void* ptrs[] = {f->d_sig, f->d_tab, f->d_deg, f->d_mask, f->d_theta, f->d_m, f->d_v, f->d_grad, f->d_gpart,
+    void* ptrs[] = {f->d_sig, f->d_tab, f->d_deg, f->d_mask, f->d_theta, f->d_m, f->d_v, f->d_grad, f->d_planes,
                     f->d_W1, f->d_W2, f->d_W1T, f->d_W2T, f->d_step, f->d_X, f->d_G, f->d_hu2, f->d_logdet,
                     f->d_ell, f->d_alpha, f->d_loss, f->d_gloss, f->d_EX, f->d_Elogdet, f->d_Eell};
     for (void* p : ptrs)
@@ -295,7 +289,20 @@ int pimc_flow_create(pimc_ctx* c, const pimc_potential* V, double m, double a, d
     if ((st = dev_alloc(c, &f->d_m, np))) return fail(st);
     if ((st = dev_alloc(c, &f->d_v, np))) return fail(st);
     if ((st = dev_alloc(c, &f->d_grad, np))) return fail(st);
-    if ((st = dev_alloc(c, &f->d_gpart, size_t(tiles_of(Bs)) * np))) return fail(st);
+    {   // gradient planes: goT, gpT (FP32) and hT (bf16), 128 rows each, and xaT (bf16), 64 rows, per layer
+        const size_t L = size_t(f->L);
+        const size_t bytes = L * Bs * (128 * 4 + 128 * 4 + 128 * 2 + 64 * 2);
+        unsigned char* base = nullptr;
+        if ((st = dev_alloc(c, &base, bytes))) return fail(st);
+        f->d_planes = base;
+        f->planes.goT = reinterpret_cast<float*>(base);
+        f->planes.gpT = f->planes.goT + L * 128 * Bs;
+        f->planes.hT = reinterpret_cast<__bf16*>(f->planes.gpT + L * 128 * Bs);
+        f->planes.xaT = f->planes.hT + L * 128 * Bs;
+        f->planes.g_stride = 128 * Bs;
+        f->planes.h_stride = 128 * Bs;
+        f->planes.xa_stride = 64 * Bs;
+    }
     if ((st = dev_alloc(c, &f->d_W1, size_t(f->L) * kFlowH * kFlowK))) return fail(st);
     if ((st = dev_alloc(c, &f->d_W2, size_t(f->L) * kFlowH * kFlowH))) return fail(st);
     if ((st = dev_alloc(c, &f->d_W1T, size_t(f->L) * kFlowH * kFlowK))) return fail(st);
@@ -312,8 +319,6 @@ int pimc_flow_create(pimc_ctx* c, const pimc_potential* V, double m, double a, d
     if ((st = dev_alloc(c, &f->d_gloss, 1))) return fail(st);
     if (hipEventCreate(&f->e0) != hipSuccess || hipEventCreate(&f->e1) != hipSuccess)
         return fail(ctx_fail(c, PIMC_EDEVICE, "hipEventCreate failed"));
-    if (flow_prepare() != hipSuccess)
-        return fail(ctx_fail(c, PIMC_EDEVICE, "cannot raise the LDS limit of the coupling backward kernel"));
     // masks
     std::vector<int> mask(4 * 128, 0);
     for (int t = 0; t < 4; ++t) {
@@ -515,8 +520,7 @@ int pimc_flow_amplitude(pimc_flow* f, uint64_t n_samples, uint64_t seed, uint32_
     if (n_samples < 2) return ctx_fail(c, PIMC_EINVAL, "need at least 2 samples");
     HIP_TRY(c, hipSetDevice(c->device));
     const Problem& P = f->P;
-    const uint32_t ppl = paths_per_lane(P.s);
-    const uint64_t CH = uint64_t(kBlock) * ppl;
+    const uint64_t CH = kChunkPaths;
     const uint64_t n_chunks = (n_samples + CH - 1) / CH;
     const uint64_t eb = std::min<uint64_t>(n_chunks * CH, kEstimationBatch);   // a multiple of CH
     int st = ensure_estimation(f, eb, 0);
@@ -535,8 +539,8 @@ int pimc_flow_amplitude(pimc_flow* f, uint64_t n_samples, uint64_t seed, uint32_
     for (uint64_t first = 0; first < n_samples; first += step) {
         const uint64_t n = std::min<uint64_t>(step, n_samples - first);
         HIP_TRY(c, enqueue_log_weights(f, key, first, n, false));
-        HIP_TRY(c, launch_flow_partials(f->d_Eell, first, n_samples, first / CH, (n + CH - 1) / CH, ppl,
-                                        c->d_partials, c->stream));
+        HIP_TRY(c, launch_flow_partials(f->d_Eell, first, n_samples, first / CH, (n + CH - 1) / CH, c->d_partials,
+                                        c->stream));
     }
     HIP_TRY(c, launch_seg_reduce(c->d_partials, c->d_seg, c->d_seg + 1, 1, c->d_red, c->stream));
     HIP_TRY(c, hipEventRecord(f->e1, c->stream));
@@ -547,6 +551,7 @@ int pimc_flow_amplitude(pimc_flow* f, uint64_t n_samples, uint64_t seed, uint32_
     HIP_TRY(c, hipEventElapsedTime(&t, f->e0, f->e1));
     if (ms) *ms = t;
     c->last_ms = t;
+    c->last_partials_ptr = c->d_partials;
     c->last_chunks = n_chunks;
     c->last_chunk_paths = CH;
     c->last_s = P.s;

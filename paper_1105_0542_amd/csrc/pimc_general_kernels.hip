@@ -16,10 +16,10 @@ hipError_t launch_p(const AmpArgs& A, int p, int U, int grid, hipStream_t st) {
         if (p != P) return launch_p<P + 1>(A, p, U, grid, st);
         const GenCompiledEval<P> ev{A.tab64, A.gen};
         switch (U) {
-            case 1: return launch_one<1>(A, ev, grid, st);
-            case 2: if constexpr (gen_subtree_levels(P) >= 2) return launch_one<2>(A, ev, grid, st); else break;
-            case 3: if constexpr (gen_subtree_levels(P) >= 3) return launch_one<3>(A, ev, grid, st); else break;
-            case 4: if constexpr (gen_subtree_levels(P) >= 4) return launch_one<4>(A, ev, grid, st); else break;
+            case 1: return launch_one<DefaultShape<1>>(A, ev, grid, st);
+            case 2: if constexpr (gen_subtree_levels(P) >= 2) return launch_one<DefaultShape<2>>(A, ev, grid, st); else break;
+            case 3: if constexpr (gen_subtree_levels(P) >= 3) return launch_one<DefaultShape<3>>(A, ev, grid, st); else break;
+            case 4: if constexpr (gen_subtree_levels(P) >= 4) return launch_one<DefaultShape<4>>(A, ev, grid, st); else break;
             default: break;
         }
         return hipErrorInvalidValue;
@@ -33,12 +33,12 @@ int resident_p(int p, int U, size_t lds, int device) {
     if constexpr (P <= kGenMaxP) {
         if (p != P) return resident_p<P + 1>(p, U, lds, device);
         switch (U) {
-            case 2: if constexpr (gen_subtree_levels(P) >= 2) return resident_one<2, GenCompiledEval<P>>(lds, device); else break;
-            case 3: if constexpr (gen_subtree_levels(P) >= 3) return resident_one<3, GenCompiledEval<P>>(lds, device); else break;
-            case 4: if constexpr (gen_subtree_levels(P) >= 4) return resident_one<4, GenCompiledEval<P>>(lds, device); else break;
+            case 2: if constexpr (gen_subtree_levels(P) >= 2) return resident_one<DefaultShape<2>, GenCompiledEval<P>>(lds, device); else break;
+            case 3: if constexpr (gen_subtree_levels(P) >= 3) return resident_one<DefaultShape<3>, GenCompiledEval<P>>(lds, device); else break;
+            case 4: if constexpr (gen_subtree_levels(P) >= 4) return resident_one<DefaultShape<4>, GenCompiledEval<P>>(lds, device); else break;
             default: break;
         }
-        return resident_one<1, GenCompiledEval<P>>(lds, device);
+        return resident_one<DefaultShape<1>, GenCompiledEval<P>>(lds, device);
     } else {
         return 256;
     }

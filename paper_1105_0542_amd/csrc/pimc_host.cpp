@@ -169,9 +169,8 @@ int build_problem(const pimc_potential* V, double m, double a, double b, double 
     if (P.even && dV <= 4 && P.s >= 4) {
         P.kind = fp32 ? EvalKind::Quartic32 : EvalKind::Quartic64;
         xdeg = quartic_xdegrees(p);
-        // subtrees of 5 levels (measured 4 % faster than 4 in FP64 at p = 18, s = 10, 2 % in FP32),
-        // 4 for N = 16
-        P.U = P.s >= 5 ? 5 : 4;
+        // subtrees of 4 levels (the default launch shape; the batch autotuner also times 5)
+        P.U = 4;
     } else {
         if (fp32) {
             std::snprintf(why, whylen, "FP32 polynomials need an even potential of degree <= 4 and N >= 16");
@@ -283,10 +282,10 @@ int check_mpt(const pimc_mpt* V, double m, double a, double b, double T, uint32_
     return check_args(&zero, m, a, b, T, N, p, n_samples);
 }
 
-uint32_t paths_per_lane(int s) { return s >= 10 ? 1u : (1u << (10 - s)); }
-
-// Upload tables and per-level constants; fill the kernel arguments except the output pointers.
-int stage_problem(pimc_ctx* c, const Problem& P, uint64_t seed, uint32_t stream, AmpArgs& A) {
+// Upload tables and per-level constants (into the context's buffer, or into work->prm); fill the
+// kernel arguments except the output pointers.
+int stage_problem(pimc_ctx* c, const Problem& P, uint64_t seed, uint32_t stream, AmpArgs& A,
+                  const DeviceWork* work = nullptr) {
     const size_t nlev = size_t(P.s + 1);
     const size_t n_tab = P.tab.size();
     // layout: sig[nlev] shift[nlev] tab64[n_tab] tab32[n_tab] deg[K]
@@ -297,7 +296,9 @@ int stage_problem(pimc_ctx* c, const Problem& P, uint64_t seed, uint32_t stream,
     // general-potential mode: derivative tables
     const size_t off_dpoly = (off_deg + P.deg.size() * 4 + 15) & ~size_t(15);
     const size_t off_dsech = off_dpoly + P.gen.dpoly.size() * 8;
-    const size_t total = off_dsech + P.gen.dsech.size() * 8 + 16;
+    // the chunk counter of the persistent kernel, on its own 256-byte line
+    const size_t off_queue = (off_dsech + P.gen.dsech.size() * 8 + 255) & ~size_t(255);
+    const size_t total = off_queue + 256;
     std::vector<unsigned char> host(total, 0);
     std::memcpy(host.data(), P.sig.data(), nlev * 8);
     std::memcpy(host.data() + off_shift, P.shift.data(), nlev * 8);
@@ -308,18 +309,27 @@ int stage_problem(pimc_ctx* c, const Problem& P, uint64_t seed, uint32_t stream,
     if (!P.deg.empty()) std::memcpy(host.data() + off_deg, P.deg.data(), P.deg.size() * 4);
     if (!P.gen.dpoly.empty()) std::memcpy(host.data() + off_dpoly, P.gen.dpoly.data(), P.gen.dpoly.size() * 8);
     if (!P.gen.dsech.empty()) std::memcpy(host.data() + off_dsech, P.gen.dsech.data(), P.gen.dsech.size() * 8);
-    int st = ensure(c, &c->d_prm, &c->prm_bytes, total);
-    if (st) return st;
-    HIP_TRY(c, hipMemcpyAsync(c->d_prm, host.data(), total, hipMemcpyHostToDevice, c->stream));
+    void* prm = nullptr;
+    if (work) {
+        if (total > work->prm_cap)
+            return ctx_fail(c, PIMC_EINVAL, "tables need %zu bytes, the workspace holds %zu", total, work->prm_cap);
+        prm = work->prm;
+    } else {
+        const int st = ensure(c, &c->d_prm, &c->prm_bytes, total);
+        if (st) return st;
+        prm = c->d_prm;
+    }
+    HIP_TRY(c, hipMemcpyAsync(prm, host.data(), total, hipMemcpyHostToDevice, c->stream));
     // the host vector must stay valid until the copy has read it
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    unsigned char* base = static_cast<unsigned char*>(c->d_prm);
+    unsigned char* base = static_cast<unsigned char*>(prm);
     std::memset(&A, 0, sizeof(A));
     A.sig = reinterpret_cast<const double*>(base);
     A.shift = reinterpret_cast<const double*>(base + off_shift);
     A.tab64 = reinterpret_cast<const double*>(base + off_tab);
     A.tab32 = reinterpret_cast<const float*>(base + off_tab32);
     A.gdeg = reinterpret_cast<const int*>(base + off_deg);
+    A.queue = reinterpret_cast<unsigned long long*>(base + off_queue);
     A.gK = int(P.deg.size());
     A.gstride = P.stride;
     A.a = P.a;
@@ -347,7 +357,7 @@ int stage_problem(pimc_ctx* c, const Problem& P, uint64_t seed, uint32_t stream,
 }
 
 int launch_grid(pimc_ctx* c, const Problem& P, uint64_t n_chunks) {
-    const int resident = amplitude_resident_blocks(P.kind, P.p, P.U, amp_lds_bytes(P.D, P.s), c->device);
+    const int resident = amplitude_resident_blocks(P.kind, P.p, P.U, amp_lds_bytes(P.D, P.s, 256), c->device);
     const uint64_t g = std::min<uint64_t>(n_chunks, uint64_t(std::max(resident, 1)));
     return int(std::max<uint64_t>(g, 1));
 }
@@ -375,9 +385,10 @@ int check_args(const pimc_potential* V, double m, double a, double b, double T, 
 
 extern const uint32_t kKnownFlags = PIMC_FP32_POLY | PIMC_HIERARCHY;
 
-// Estimation of every requested level of a built problem (the body shared by the potentials).
+// Estimation of every requested level of a built problem (the body shared by the potentials), with
+// the context's device buffers or the fixed ones of `work`.
 int amplitude_core(pimc_ctx* c, const Problem& P, uint64_t n_samples, uint64_t seed, uint32_t stream, uint32_t flags,
-                   pimc_level_result* out) {
+                   pimc_level_result* out, const DeviceWork* work) {
     int st;
     const int nlev = P.s + 1;
     const bool hier = (flags & PIMC_HIERARCHY) != 0;
@@ -391,43 +402,60 @@ int amplitude_core(pimc_ctx* c, const Problem& P, uint64_t n_samples, uint64_t s
     c->last_shift = P.shift;
     if (P.s == 0) return PIMC_OK;
 
-    AmpArgs A;
-    st = stage_problem(c, P, seed, stream, A);
-    if (st) return st;
-    const uint32_t ppl = paths_per_lane(P.s);
-    const uint64_t chunk_paths = uint64_t(kBlock) * ppl;
+    const uint64_t chunk_paths = kChunkPaths;
     const uint64_t n_chunks = (n_samples + chunk_paths - 1) / chunk_paths;
     const int slots = hier ? nlev : 1;            // partial slot of level n: n, or 0 for level s alone
-    st = ensure(c, reinterpret_cast<void**>(&c->d_partials), &c->partial_bytes, size_t(slots) * n_chunks * 4 * 8);
-    if (st) return st;
-    st = ensure(c, reinterpret_cast<void**>(&c->d_red), &c->red_bytes, size_t(slots) * 4 * 8);
-    if (st) return st;
-    st = ensure(c, reinterpret_cast<void**>(&c->d_seg), &c->seg_bytes, size_t(slots) * 2 * 8);
+    const size_t partial_bytes = size_t(slots) * n_chunks * 4 * 8;
+    double* partials;
+    double* red_dev;
+    uint64_t* seg;
+    if (work) {
+        if (partial_bytes > work->partial_cap || size_t(slots) * 32 > work->red_cap || size_t(slots) * 16 > work->seg_cap)
+            return ctx_fail(c, PIMC_EINVAL,
+                            "%llu samples x %d levels need %zu bytes of chunk sums, the workspace holds %zu",
+                            (unsigned long long)n_samples, slots, partial_bytes, work->partial_cap);
+        partials = work->partials;
+        red_dev = work->red;
+        seg = work->seg;
+    } else {
+        st = ensure(c, reinterpret_cast<void**>(&c->d_partials), &c->partial_bytes, partial_bytes);
+        if (st) return st;
+        st = ensure(c, reinterpret_cast<void**>(&c->d_red), &c->red_bytes, size_t(slots) * 4 * 8);
+        if (st) return st;
+        st = ensure(c, reinterpret_cast<void**>(&c->d_seg), &c->seg_bytes, size_t(slots) * 2 * 8);
+        if (st) return st;
+        partials = c->d_partials;
+        red_dev = c->d_red;
+        seg = c->d_seg;
+    }
+    AmpArgs A;
+    st = stage_problem(c, P, seed, stream, A, work);
     if (st) return st;
     c->h_seg.assign(size_t(slots) * 2, 0);
     for (int k = 0; k < slots; ++k) {
         c->h_seg[size_t(k)] = uint64_t(k) * n_chunks * 4;
         c->h_seg[size_t(slots + k)] = n_chunks;
     }
-    HIP_TRY(c, hipMemcpyAsync(c->d_seg, c->h_seg.data(), c->h_seg.size() * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(seg, c->h_seg.data(), c->h_seg.size() * 8, hipMemcpyHostToDevice, c->stream));
     A.first_path = 0;
     A.n_paths = n_samples;
     A.n_chunks = n_chunks;
-    A.ppl = ppl;
     A.hier = hier ? 1 : 0;
-    A.partials = c->d_partials;
+    A.partials = partials;
     A.dump = nullptr;
     const int grid = launch_grid(c, P, n_chunks);
+    HIP_TRY(c, launch_fill_u64(A.queue, 1, 0ull, c->stream));
     HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
     HIP_TRY(c, launch_amplitude(A, P.kind, P.p, P.U, grid, c->stream));
     HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
-    HIP_TRY(c, launch_seg_reduce(c->d_partials, c->d_seg, c->d_seg + slots, uint64_t(slots), c->d_red, c->stream));
-    std::vector<double> red(size_t(slots) * 4);
-    HIP_TRY(c, hipMemcpyAsync(red.data(), c->d_red, red.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, launch_seg_reduce(partials, seg, seg + slots, uint64_t(slots), red_dev, c->stream));
+    double red[4 * (PIMC_MAX_S + 1)];
+    HIP_TRY(c, hipMemcpyAsync(red, red_dev, size_t(slots) * 4 * 8, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     float ms = 0.f;
     HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
     c->last_ms = ms;
+    c->last_partials_ptr = partials;
     c->last_chunks = n_chunks;
     c->last_chunk_paths = chunk_paths;
     c->last_hier = hier;
@@ -455,16 +483,15 @@ int path_actions_core(pimc_ctx* c, const Problem& P, uint64_t seed, uint32_t str
     if (st) return st;
     st = ensure(c, reinterpret_cast<void**>(&c->d_dump), &c->dump_bytes, size_t(k_paths) * nlev * 8);
     if (st) return st;
-    const uint32_t ppl = paths_per_lane(P.s);
-    const uint64_t chunk_paths = uint64_t(kBlock) * ppl;
+    const uint64_t chunk_paths = kChunkPaths;
     A.first_path = first_path;
     A.n_paths = k_paths;
     A.n_chunks = (k_paths + chunk_paths - 1) / chunk_paths;
-    A.ppl = ppl;
     A.hier = (flags & PIMC_HIERARCHY) ? 1 : 0;
     A.partials = nullptr;
     A.dump = c->d_dump;
     const int grid = launch_grid(c, P, A.n_chunks);
+    HIP_TRY(c, launch_fill_u64(A.queue, 1, 0ull, c->stream));
     HIP_TRY(c, launch_amplitude(A, P.kind, P.p, P.U, grid, c->stream));
     HIP_TRY(c, hipMemcpyAsync(S_out, c->d_dump, size_t(k_paths) * nlev * 8, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -666,7 +693,7 @@ int pimc_level_table_mpt(const pimc_mpt* V, double m, double T, int p, uint32_t 
 int pimc_last_partials(pimc_ctx* c, uint32_t level, uint64_t first_chunk, uint64_t n_chunks, double* out,
                        uint64_t* chunk_paths, uint64_t* total_chunks, double* shift) {
     if (!c) { set_thread_error("context is NULL"); return PIMC_EINVAL; }
-    if (c->last_s < 1 || !c->d_partials) return ctx_fail(c, PIMC_EINVAL, "no estimation has run on this context");
+    if (c->last_s < 1 || !c->last_partials_ptr) return ctx_fail(c, PIMC_EINVAL, "no estimation has run on this context");
     if (int(level) > c->last_s) return ctx_fail(c, PIMC_EINVAL, "level %u > s = %d", level, c->last_s);
     if (!c->last_hier && int(level) != c->last_s)
         return ctx_fail(c, PIMC_EINVAL, "the last run estimated level %d only", c->last_s);
@@ -679,7 +706,7 @@ int pimc_last_partials(pimc_ctx* c, uint32_t level, uint64_t first_chunk, uint64
     if (n_chunks == 0) return PIMC_OK;
     if (!out) return ctx_fail(c, PIMC_EINVAL, "out is NULL");
     HIP_TRY(c, hipSetDevice(c->device));
-    const double* src = c->d_partials + (slot * c->last_chunks + first_chunk) * 4;
+    const double* src = c->last_partials_ptr + (slot * c->last_chunks + first_chunk) * 4;
     HIP_TRY(c, hipMemcpyAsync(out, src, n_chunks * 4 * 8, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return PIMC_OK;
@@ -727,15 +754,19 @@ struct pimc_batch {
     std::vector<uint64_t> t_n;
     std::vector<std::vector<double>> t_shift;  // S_ref,n
     std::vector<uint64_t> t_seg;               // first segment of the task
-    // p classes
+    // kernel classes: the tasks of one level p with N = 16, or with N >= 32
     struct Class {
         int p;
-        int U;                                 // subtree levels of the kernel (s - U levels on the stack)
-        int n_tasks;
-        size_t first;                          // first position in the device task array
-        uint64_t n_items;
-        size_t lds;
-        int resident;
+        bool n16;
+        int shape = 0;                         // launch shape (batch_shape)
+        ShapeDesc d{};
+        int n_tasks = 0;
+        size_t first = 0;                      // first position in the device task array
+        uint64_t n_items = 0;
+        int smax = 0;                          // largest s of the class
+        size_t lds = 0;
+        int resident = 0;
+        double tuned_ms = 0.0, default_ms = 0.0;
     };
     std::vector<Class> classes;
     // device
@@ -746,6 +777,7 @@ struct pimc_batch {
     double* d_red = nullptr;
     unsigned long long* d_queue = nullptr;
     double* h_red = nullptr;                   // pinned
+    pimc_level_result* h_out = nullptr;        // pinned staging of results bound for device memory
     uint64_t n_seg = 0;
     // graph
     hipGraph_t graph = nullptr;
@@ -785,20 +817,39 @@ void destroy_graph(pimc_batch* b) {
     b->graph = nullptr;
 }
 
-// Capture: reset the queues (a fill kernel, no memset node), one persistent launch per p class,
-// the canonical reduction, and the copy of the sums to pinned host memory.
+int class_grid(const pimc_batch* b, const pimc_batch::Class& C) { return std::max(1, C.resident * b->grid_mult_x2 / 2); }
+
+// The launch of class k's persistent kernel on `st` (its queue must be reset first).
+hipError_t launch_class(pimc_batch* b, size_t k, hipStream_t st) {
+    const auto& C = b->classes[k];
+    RngKey key{uint32_t(b->seed), uint32_t(b->seed >> 32), 0u};
+    const int hier = (b->flags & PIMC_HIERARCHY) ? 1 : 0;
+    return launch_batch(b->d_tasks + C.first, C.n_tasks, C.n_items, b->d_queue + k, b->grab, key, hier, C.p, C.n16,
+                        C.shape, class_grid(b, C), C.lds, st);
+}
+
+// Shape idx for class k: its description, LDS bytes and resident workgroups.
+int set_class_shape(pimc_batch* b, size_t k, int idx) {
+    auto& C = b->classes[k];
+    ShapeDesc d;
+    if (!batch_shape(C.p, C.n16, idx, d))
+        return batch_fail(b, PIMC_EINVAL, "class %zu (p = %d): shape %d outside 0..%d", k, C.p, idx,
+                          batch_shape_count(C.p, C.n16) - 1);
+    C.shape = idx;
+    C.d = d;
+    C.lds = amp_lds_bytes(C.smax - d.U, C.smax, d.BS);
+    C.resident = batch_resident_blocks(C.p, C.n16, idx, C.lds, b->ctx->device);
+    if (C.resident <= 0) return batch_fail(b, PIMC_EDEVICE, "class %zu: no resident workgroups for shape %d", k, idx);
+    return PIMC_OK;
+}
+
+// Capture: reset the queues (a fill kernel, no memset node), one persistent launch per class, the
+// canonical reduction, and the copy of the sums to pinned host memory.
 int capture_graph(pimc_batch* b) {
     destroy_graph(b);
     HIP_TRY_B(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = launch_fill_u64(b->d_queue, int(b->classes.size()), 0ull, b->stream);
-    RngKey key{uint32_t(b->seed), uint32_t(b->seed >> 32), 0u};
-    const int hier = (b->flags & PIMC_HIERARCHY) ? 1 : 0;
-    for (size_t k = 0; k < b->classes.size() && e == hipSuccess; ++k) {
-        const auto& C = b->classes[k];
-        const int grid = std::max(1, C.resident * b->grid_mult_x2 / 2);
-        e = launch_batch(b->d_tasks + C.first, C.n_tasks, C.n_items, b->d_queue + k, b->grab, key, hier, C.p, C.U,
-                         grid, C.lds, b->stream);
-    }
+    for (size_t k = 0; k < b->classes.size() && e == hipSuccess; ++k) e = launch_class(b, k, b->stream);
     if (e == hipSuccess)
         e = launch_seg_reduce(b->d_partials, b->d_seg, b->d_seg + b->n_seg, b->n_seg, b->d_red, b->stream);
     if (e == hipSuccess)
@@ -812,6 +863,20 @@ int capture_graph(pimc_batch* b) {
     if (e2 != hipSuccess) return batch_fail(b, PIMC_EDEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(e2));
     b->graph = g;
     HIP_TRY_B(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    return PIMC_OK;
+}
+
+// Device time of class k alone with its current shape: queue reset, one launch (eager, on the
+// batch stream).
+int time_class(pimc_batch* b, size_t k, double* ms) {
+    HIP_TRY_B(b, launch_fill_u64(b->d_queue + k, 1, 0ull, b->stream));
+    HIP_TRY_B(b, hipEventRecord(b->e0, b->stream));
+    HIP_TRY_B(b, launch_class(b, k, b->stream));
+    HIP_TRY_B(b, hipEventRecord(b->e1, b->stream));
+    HIP_TRY_B(b, hipStreamSynchronize(b->stream));
+    float f = 0.f;
+    HIP_TRY_B(b, hipEventElapsedTime(&f, b->e0, b->e1));
+    *ms = f;
     return PIMC_OK;
 }
 
@@ -880,13 +945,12 @@ int pimc_batch_create(pimc_ctx* c, const pimc_potential* systems, int n_systems,
             scale_for_endpoint_sum(blob.data() + at, lv.back().deg);     // quartic evaluator form
         }
     }
-    // ---- per task: sigma, S_ref, chunking; device order grouped by p, then by subtree depth (the
-    // single-call kernels' choice: 5 levels for N >= 32, 4 for N = 16)
-    auto subtree_levels = [&](size_t i) { return tasks[i].N >= 32 ? 5 : 4; };
+    // ---- per task: sigma, S_ref, chunking; device order grouped by p, then N = 16 before N >= 32
+    auto is_n16 = [&](size_t i) { return tasks[i].N == 16; };
     std::vector<size_t> order(n_tasks);
     for (size_t i = 0; i < n_tasks; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
-        return tasks[x].p != tasks[y].p ? tasks[x].p < tasks[y].p : subtree_levels(x) < subtree_levels(y);
+        return tasks[x].p != tasks[y].p ? tasks[x].p < tasks[y].p : (is_n16(x) && !is_n16(y));
     });
     b->t_s.resize(n_tasks);
     b->t_logpref.resize(n_tasks);
@@ -934,8 +998,7 @@ int pimc_batch_create(pimc_ctx* c, const pimc_potential* systems, int n_systems,
     std::vector<uint64_t> seg_base, seg_len;
     for (size_t pos = 0; pos < n_tasks; ++pos) {
         const size_t i = order[pos];
-        const uint64_t chunk_paths = uint64_t(kBlock) * paths_per_lane(b->t_s[i]);
-        t_chunks[i] = (tasks[i].n_samples + chunk_paths - 1) / chunk_paths;
+        t_chunks[i] = (tasks[i].n_samples + kChunkPaths - 1) / kChunkPaths;
         const int slots = hier ? b->t_s[i] + 1 : 1;
         t_part_off[i] = part_total;
         b->t_seg[i] = seg_base.size();
@@ -978,30 +1041,27 @@ int pimc_batch_create(pimc_ctx* c, const pimc_potential* systems, int n_systems,
         r.b = t.b * sm;
         r.n_paths = t.n_samples;
         r.n_chunks = t_chunks[i];
-        r.ppl = paths_per_lane(b->t_s[i]);
         r.stream = t.stream;
         r.s = b->t_s[i];
-        r.pad = 0;
     }
     // classes and item numbering
     for (size_t pos = 0; pos < n_tasks;) {
-        const int p = tasks[order[pos]].p;
-        const int U = subtree_levels(order[pos]);
-        pimc_batch::Class C{p, U, 0, pos, 0, 0, 0};
-        int dmax = 0;
-        while (pos < n_tasks && tasks[order[pos]].p == p && subtree_levels(order[pos]) == U) {
+        pimc_batch::Class C;
+        C.p = tasks[order[pos]].p;
+        C.n16 = is_n16(order[pos]);
+        C.first = pos;
+        while (pos < n_tasks && tasks[order[pos]].p == C.p && is_n16(order[pos]) == C.n16) {
             dt[pos].item0 = C.n_items;
             C.n_items += dt[pos].n_chunks;
-            dmax = std::max(dmax, dt[pos].s - U);
+            C.smax = std::max(C.smax, dt[pos].s);
             ++C.n_tasks;
             ++pos;
         }
-        C.lds = amp_lds_bytes(dmax, dmax + U);
-        C.resident = batch_resident_blocks(p, U, C.lds, c->device);
         b->classes.push_back(C);
     }
-    if (b->classes.size() > 64)
-        return fail(batch_fail(b, PIMC_EUNSUPPORTED, "more than 64 kernel classes (levels p x subtree depths)"));
+    if (b->classes.size() > 64) return fail(batch_fail(b, PIMC_EUNSUPPORTED, "more than 64 kernel classes"));
+    for (size_t k = 0; k < b->classes.size(); ++k)
+        if ((st = set_class_shape(b, k, 0))) return fail(st);
     std::vector<uint64_t> seg(b->n_seg * 2);
     std::copy(seg_base.begin(), seg_base.end(), seg.begin());
     std::copy(seg_len.begin(), seg_len.end(), seg.begin() + b->n_seg);
@@ -1026,18 +1086,42 @@ int pimc_batch_set_tuning(pimc_batch* b, int grid_mult_x2, uint32_t grab) {
     return capture_graph(b);
 }
 
-int pimc_batch_run(pimc_batch* b, pimc_level_result* out, double* ms) {
+int pimc_batch_n_classes(const pimc_batch* b) { return b ? int(b->classes.size()) : 0; }
+
+int pimc_batch_class_info(const pimc_batch* b, int k, pimc_batch_class* out) {
+    if (!b || !out) { set_thread_error("NULL argument"); return PIMC_EINVAL; }
+    if (k < 0 || size_t(k) >= b->classes.size()) {
+        set_thread_error("class %d outside 0..%zu", k, b->classes.size() - 1);
+        return PIMC_EINVAL;
+    }
+    const auto& C = b->classes[size_t(k)];
+    out->p = C.p;
+    out->n16 = C.n16 ? 1 : 0;
+    out->n_tasks = uint64_t(C.n_tasks);
+    out->n_items = C.n_items;
+    out->shape = C.shape;
+    out->n_shapes = batch_shape_count(C.p, C.n16);
+    out->subtree_levels = C.d.U;
+    out->block = C.d.BS;
+    out->waves_per_eu = C.d.WPE;
+    out->slice_batch = C.d.BATCH;
+    out->tuned_ms = C.tuned_ms;
+    out->default_ms = C.default_ms;
+    return PIMC_OK;
+}
+
+int pimc_batch_set_shape(pimc_batch* b, int k, int shape) {
     if (!b) { set_thread_error("batch is NULL"); return PIMC_EINVAL; }
-    if (!out) return batch_fail(b, PIMC_EINVAL, "out is NULL");
+    if (k < 0 || size_t(k) >= b->classes.size())
+        return batch_fail(b, PIMC_EINVAL, "class %d outside 0..%zu", k, b->classes.size() - 1);
     HIP_TRY_B(b, hipSetDevice(b->ctx->device));
-    HIP_TRY_B(b, hipEventRecord(b->e0, b->stream));
-    HIP_TRY_B(b, hipGraphLaunch(b->exec, b->stream));
-    HIP_TRY_B(b, hipEventRecord(b->e1, b->stream));
-    HIP_TRY_B(b, hipStreamSynchronize(b->stream));
-    float fms = 0.f;
-    HIP_TRY_B(b, hipEventElapsedTime(&fms, b->e0, b->e1));
-    b->last_ms = fms;
-    if (ms) *ms = fms;
+    const int st = set_class_shape(b, size_t(k), shape);
+    if (st) return st;
+    return capture_graph(b);
+}
+
+// Assemble every task from the reduced sums into out (host memory).
+static int batch_assemble(pimc_batch* b, pimc_level_result* out) {
     const bool hier = (b->flags & PIMC_HIERARCHY) != 0;
     const size_t stride = size_t(b->s_max + 1);
     bool nonfinite = false;
@@ -1058,27 +1142,87 @@ int pimc_batch_run(pimc_batch* b, pimc_level_result* out, double* ms) {
     return nonfinite ? PIMC_WNONFINITE : PIMC_OK;
 }
 
+int pimc_batch_run_to(pimc_batch* b, pimc_level_result* out, int out_on_device, double* ms) {
+    if (!b) { set_thread_error("batch is NULL"); return PIMC_EINVAL; }
+    if (!out) return batch_fail(b, PIMC_EINVAL, "out is NULL");
+    HIP_TRY_B(b, hipSetDevice(b->ctx->device));
+    HIP_TRY_B(b, hipEventRecord(b->e0, b->stream));
+    HIP_TRY_B(b, hipGraphLaunch(b->exec, b->stream));
+    HIP_TRY_B(b, hipEventRecord(b->e1, b->stream));
+    HIP_TRY_B(b, hipStreamSynchronize(b->stream));
+    float fms = 0.f;
+    HIP_TRY_B(b, hipEventElapsedTime(&fms, b->e0, b->e1));
+    b->last_ms = fms;
+    if (ms) *ms = fms;
+    if (!out_on_device) return batch_assemble(b, out);
+    const size_t count = b->n_tasks * size_t(b->s_max + 1);
+    if (!b->h_out) {
+        const hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&b->h_out), count * sizeof(pimc_level_result), 0);
+        if (e != hipSuccess) return batch_fail(b, PIMC_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
+    }
+    const int st = batch_assemble(b, b->h_out);
+    pimc_ctx* c = b->ctx;
+    HIP_TRY_B(b, hipMemcpyAsync(out, b->h_out, count * sizeof(pimc_level_result), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY_B(b, hipStreamSynchronize(c->stream));            // the staging buffer is reused by the next run
+    return st;
+}
+
+int pimc_batch_run(pimc_batch* b, pimc_level_result* out, double* ms) { return pimc_batch_run_to(b, out, 0, ms); }
+
 int pimc_batch_autotune(pimc_batch* b, const char* cache_path, int* grid_mult_x2, uint32_t* grab) {
     if (!b) { set_thread_error("batch is NULL"); return PIMC_EINVAL; }
-    // cache key: device architecture, the p classes, the largest s, flags
+    HIP_TRY_B(b, hipSetDevice(b->ctx->device));
+    // cache key: device architecture, the classes (p, N = 16 or not), the largest s, flags
     hipDeviceProp_t prop;
     HIP_TRY_B(b, hipGetDeviceProperties(&prop, b->ctx->device));
     std::ostringstream key;
-    key << prop.gcnArchName << "|p";
-    for (const auto& C : b->classes) key << ":" << C.p << "u" << C.U;
+    key << prop.gcnArchName << "|c";
+    for (const auto& C : b->classes) key << ":" << C.p << (C.n16 ? "n16" : "n32");
     key << "|s" << b->s_max << "|f" << b->flags;
+    const size_t nc = b->classes.size();
+    int st;
     if (cache_path) {
         std::ifstream in(cache_path);
-        std::string k;
-        int g;
-        unsigned gr;
-        while (in >> k >> g >> gr)
-            if (k == key.str()) {
-                if (grid_mult_x2) *grid_mult_x2 = g;
-                if (grab) *grab = gr;
-                return pimc_batch_set_tuning(b, g, gr);
-            }
+        std::string line;
+        while (std::getline(in, line)) {
+            std::istringstream ls(line);
+            std::string k;
+            int g;
+            unsigned gr;
+            if (!(ls >> k >> g >> gr) || k != key.str()) continue;
+            std::vector<int> shapes(nc);
+            bool ok = true;
+            for (size_t i = 0; i < nc && ok; ++i) ok = bool(ls >> shapes[i]);
+            if (!ok) continue;
+            for (size_t i = 0; i < nc; ++i)
+                if ((st = set_class_shape(b, i, shapes[i]))) return st;
+            if (grid_mult_x2) *grid_mult_x2 = g;
+            if (grab) *grab = gr;
+            return pimc_batch_set_tuning(b, g, gr);
+        }
     }
+    // 1. per class: every candidate shape, timed alone (default grid and grab)
+    b->grid_mult_x2 = 2;
+    b->grab = 1;
+    for (size_t k = 0; k < nc; ++k) {
+        auto& C = b->classes[k];
+        const int n = batch_shape_count(C.p, C.n16);
+        double best = 1e300;
+        int best_i = 0;
+        for (int i = 0; i < n; ++i) {
+            if ((st = set_class_shape(b, k, i))) return st;
+            double ms = 0.0;
+            if ((st = time_class(b, k, &ms))) return st;
+            if (i == 0) C.default_ms = ms;
+            if (ms < best) {
+                best = ms;
+                best_i = i;
+            }
+        }
+        if ((st = set_class_shape(b, k, best_i))) return st;
+        C.tuned_ms = best;
+    }
+    // 2. grid size and grab over the whole graph with the chosen shapes
     std::vector<pimc_level_result> scratch(b->n_tasks * size_t(b->s_max + 1));
     double best = 1e300;
     int best_g = 2;
@@ -1087,8 +1231,7 @@ int pimc_batch_autotune(pimc_batch* b, const char* cache_path, int* grid_mult_x2
     const uint32_t grs[] = {1, 4, 16};
     for (int g : gs)
         for (uint32_t gr : grs) {
-            int st = pimc_batch_set_tuning(b, g, gr);
-            if (st) return st;
+            if ((st = pimc_batch_set_tuning(b, g, gr))) return st;
             double ms = 0;
             st = pimc_batch_run(b, scratch.data(), &ms);
             if (st < 0) return st;
@@ -1100,7 +1243,9 @@ int pimc_batch_autotune(pimc_batch* b, const char* cache_path, int* grid_mult_x2
         }
     if (cache_path) {
         std::ofstream o(cache_path, std::ios::app);
-        o << key.str() << " " << best_g << " " << best_gr << "\n";
+        o << key.str() << " " << best_g << " " << best_gr;
+        for (const auto& C : b->classes) o << " " << C.shape;
+        o << "\n";
     }
     if (grid_mult_x2) *grid_mult_x2 = best_g;
     if (grab) *grab = best_gr;
@@ -1119,6 +1264,7 @@ int pimc_batch_destroy(pimc_batch* b) {
     (void)hipFree(b->d_red);
     (void)hipFree(b->d_queue);
     if (b->h_red) (void)hipHostFree(b->h_red);
+    if (b->h_out) (void)hipHostFree(b->h_out);
     if (b->e0) (void)hipEventDestroy(b->e0);
     if (b->e1) (void)hipEventDestroy(b->e1);
     if (b->stream) (void)hipStreamDestroy(b->stream);
@@ -1129,11 +1275,11 @@ int pimc_batch_destroy(pimc_batch* b) {
 const char* pimc_batch_last_error(const pimc_batch* b) { return b ? b->err : g_thread_error; }
 
 int pimc_amplitude_batch(pimc_ctx* c, const pimc_potential* systems, int n_systems, const pimc_task* tasks,
-                         size_t n_tasks, uint64_t seed, uint32_t flags, pimc_level_result* out) {
+                         size_t n_tasks, uint64_t seed, uint32_t flags, pimc_level_result* out, int out_on_device) {
     pimc_batch* b = nullptr;
     int st = pimc_batch_create(c, systems, n_systems, tasks, n_tasks, seed, flags, &b);
     if (st) return st;
-    st = pimc_batch_run(b, out, nullptr);
+    st = pimc_batch_run_to(b, out, out_on_device, nullptr);
     pimc_batch_destroy(b);
     return st;
 }

@@ -26,6 +26,7 @@ struct pimc_ctx {
     double* d_dump = nullptr;       size_t dump_bytes = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // last estimation
+    const double* last_partials_ptr = nullptr;   // chunk partials of the last run (context buffer or workspace)
     uint64_t last_chunks = 0, last_chunk_paths = 0;
     int last_s = -1;
     bool last_hier = false;
@@ -83,8 +84,16 @@ int build_problem_general(const pimc_general_potential* V, double m, double a, d
 int check_general(const pimc_general_potential* V, double m, double a, double b, double T, uint32_t N, int p,
                   uint64_t n_samples);
 // Estimation / per-path actions of a built problem (shared by every potential family).
+// Fixed device buffers of one estimation (the no-allocation entry point's workspace) instead of
+// the context's growable ones; the capacities are checked, never grown.
+struct DeviceWork {
+    void* prm = nullptr;            size_t prm_cap = 0;
+    double* partials = nullptr;     size_t partial_cap = 0;
+    double* red = nullptr;          size_t red_cap = 0;
+    uint64_t* seg = nullptr;        size_t seg_cap = 0;
+};
 int amplitude_core(pimc_ctx* c, const Problem& P, uint64_t n_samples, uint64_t seed, uint32_t stream, uint32_t flags,
-                   pimc_level_result* out);
+                   pimc_level_result* out, const DeviceWork* work = nullptr);
 int path_actions_core(pimc_ctx* c, const Problem& P, uint64_t seed, uint32_t stream, uint32_t flags,
                       uint64_t first_path, uint64_t k_paths, double* S_out);
 extern const uint32_t kKnownFlags;
@@ -93,7 +102,6 @@ extern const uint32_t kKnownFlags;
 bool assemble_level(const double* red, double logbase, pimc_level_result& r);
 int check_args(const pimc_potential* V, double m, double a, double b, double T, uint32_t N, int p,
                uint64_t n_samples);
-uint32_t paths_per_lane(int s);
 int log2_exact(uint32_t N);
 
 }  // namespace pimc_host

@@ -4,11 +4,41 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "pimc.h"
 #include "pimc_device.hpp"
 
 namespace pimc {
 
-constexpr int kBlock = 256;            // threads per workgroup (4 waves); also the lanes of a chunk
+constexpr int kBlock = 256;            // threads per workgroup of the auxiliary kernels (4 waves)
+
+// Canonical chunk of the estimators: kChunkPaths consecutive path indices, in kChunkGroups groups of
+// 64 consecutive paths (the lanes of one wave). A group's per-level sums are a wave butterfly;
+// group g is added to accumulator slot g mod kChunkSlots, each slot in increasing g, and the chunk
+// sum is slot 0 + slot 1 + slot 2 + slot 3. The order is fixed by the path indices alone, so the
+// chunk sums -- and the amplitudes -- do not depend on the workgroup size (64, 128 or 256 lanes:
+// wave w of a workgroup of W waves takes groups w, w + W, ..., and no two waves share a slot), on
+// the subtree depth or slice batch of the walker, on N (level n of an s-run is bitwise the n-run),
+// or on which workgroup ran the chunk.
+constexpr uint32_t kChunkPaths = PIMC_CHUNK_PATHS;
+constexpr int kChunkGroups = int(kChunkPaths / 64);
+constexpr int kChunkSlots = 4;
+
+// Launch shape of the estimation walker: U bisection levels of each subtree in registers
+// (2^U + 1 points), BS threads per workgroup, occupancy target WPE waves per SIMD (register budget
+// 512/WPE), slices evaluated together coefficient-major (BATCH). Every shape gives the same bits.
+template <int U_, int BS_, int WPE_, int BATCH_>
+struct Shape {
+    static constexpr int U = U_;
+    static constexpr int BS = BS_;
+    static constexpr int WPE = WPE_;
+    static constexpr int BATCH = BATCH_;
+    static_assert(BS_ == 64 || BS_ == 128 || BS_ == 256, "workgroup of 1, 2 or 4 waves");
+};
+// The default shapes: 256 threads, 2 waves per SIMD, 16 slices at once, U-level subtrees (the
+// quartic kernels use U = 4: measured fastest on MI355X at p = 8, 12 and 18 for N from 64 to 1024;
+// U = 5 needs more registers than 2 waves per SIMD leave and spills to scratch).
+template <int U>
+using DefaultShape = Shape<U, 256, 2, 16>;
 
 // Arguments of one estimation launch (passed by value in the kernel argument segment, so every
 // field is wave-uniform and scalar-loaded).
@@ -26,23 +56,25 @@ struct AmpArgs {
     RngKey key;
     uint64_t first_path;               // path index of local path 0
     uint64_t n_paths;                  // local paths 0..n_paths-1
-    uint64_t n_chunks;                 // ceil(n_paths / (kBlock * ppl))
-    uint32_t ppl;                      // paths per lane per chunk
+    uint64_t n_chunks;                 // ceil(n_paths / kChunkPaths)
     int s;                             // N = 2^s
     int D;                             // s - U: levels walked with the explicit stack
     int hier;                          // evaluate every level (else level s only)
     double* partials;                  // device [level][chunk][4] or null
     double* dump;                      // device [path][s+1] or null
+    unsigned long long* queue;         // device chunk counter, 0 at launch (persistent kernel), or null
+                                       // for a grid-stride loop over the chunks
 };
 
 // Tanh64P: the Poeschl-Teller tables with the compile-time shape of level p (K = p groups of degree
 // p), U = 4.
 enum class EvalKind { Quartic64, Quartic32, GenericEven64, GenericOdd64, Tanh64, Tanh64P, General64 };
 
-// Dynamic LDS bytes of the estimation kernel: per lane, 3D+2 slots of the explicit stack; per wave
-// and level, three accumulators.
-inline size_t amp_lds_bytes(int D, int s) {
-    return (size_t(3 * D + 2) * kBlock + size_t(4 * (s + 1) * 3)) * sizeof(double);
+// Dynamic LDS bytes of the estimation kernel: the Box-Muller table; per lane, 3D+2 slots of the
+// explicit stack; per accumulator slot and level, three sums.
+inline size_t amp_lds_bytes(int D, int s, int BS) {
+    return (size_t(kBoxMullerTable) + size_t(3 * D + 2) * size_t(BS) + size_t(kChunkSlots * (s + 1) * 3)) *
+           sizeof(double);
 }
 
 // Launch the estimation kernel; p selects the quartic specialization, U = s - D the unrolled
@@ -83,17 +115,24 @@ struct BatchTask {
     uint64_t n_paths;
     uint64_t n_chunks;
     uint64_t item0;                    // queue index of the task's chunk 0
-    uint32_t ppl;
     uint32_t stream;
     int s;
-    int pad;
 };
 
-// Persistent batched estimation for one level p and subtree depth U (quartic kernels, U = 4 for
-// s = 4, U = 5 for s >= 5).
+// A launch shape as the host sees it.
+struct ShapeDesc {
+    int U, BS, WPE, BATCH;
+};
+
+// Batched estimation (pimc_kernels_batch.hip). A class is the tasks of one level p with N = 16
+// (n16: subtrees of at most 4 levels) or with N >= 32; shape selects one of its compiled launch
+// shapes (0 = the default; levels 8, 12 and 18 have several for the autotuner, every other level
+// only the default).
+int batch_shape_count(int p, bool n16);
+bool batch_shape(int p, bool n16, int idx, ShapeDesc& d);
 hipError_t launch_batch(const BatchTask* tasks, int n_tasks, uint64_t n_items, unsigned long long* queue, uint32_t grab,
-                        const RngKey& key, int hier, int p, int U, int grid, size_t lds, hipStream_t st);
-int batch_resident_blocks(int p, int U, size_t lds_bytes, int device);
+                        const RngKey& key, int hier, int p, bool n16, int shape, int grid, size_t lds, hipStream_t st);
+int batch_resident_blocks(int p, bool n16, int shape, size_t lds_bytes, int device);
 hipError_t launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t st);
 
 // Occupancy-derived number of resident workgroups of the estimation kernel on this device.

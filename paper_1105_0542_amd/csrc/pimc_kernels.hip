@@ -1,8 +1,9 @@
 // Estimation kernels of the bisection PIMC amplitude (Sec. 4 of Balaz et al.) for gfx950: the walker
 // (pimc_walker.hpp) with the runtime-shaped evaluators (any polynomial, Poeschl-Teller), raw normals,
-// the canonical chunk reduction and the launch dispatch. The compile-time shapes are instantiated
-// in pimc_kernels_fixed.hip (one translation unit per evaluator family, built in parallel) and the
-// batched kernel in pimc_kernels_batch.hip.
+// the canonical chunk reduction and the launch dispatch. The compile-time table shapes are
+// instantiated in pimc_kernels_q64.hip, pimc_kernels_q32.hip, pimc_kernels_tanh.hip and
+// pimc_general_kernels.hip (one translation unit per evaluator family, built in parallel) and the
+// batched kernel in pimc_kernels_batch.hip and pimc_batch_p*.hip.
 #include <hip/hip_runtime.h>
 
 #include "pimc_walker.hpp"
@@ -19,6 +20,9 @@ __global__ void k_fill_u64(unsigned long long* p, int n, unsigned long long v) {
 // 1 <= node <= n_nodes.
 __global__ void __launch_bounds__(kBlock) k_normals(RngKey key, uint64_t first_path, uint64_t k_paths,
                                                     uint32_t n_nodes, double* __restrict__ out) {
+    __shared__ double bm[kBoxMullerTable];
+    load_bm_table(bm, kBlock);
+    __syncthreads();
     const uint32_t pairs = n_nodes / 2 + 1;
     const uint64_t gid = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
     if (gid >= k_paths * pairs) return;
@@ -26,7 +30,7 @@ __global__ void __launch_bounds__(kBlock) k_normals(RngKey key, uint64_t first_p
     const uint32_t j = uint32_t(gid % pairs);
     const PathRng pr = path_rng(key, first_path + i);
     double ze, zo;
-    normal_pair(key, pr, j, ze, zo);
+    normal_pair(key, pr, j, bm, ze, zo);
     double* o = out + i * n_nodes;
     const uint32_t he = 2 * j, ho = 2 * j + 1;
     if (he >= 1 && he <= n_nodes) o[he - 1] = ze;
@@ -82,10 +86,10 @@ template <bool EVEN>
 static hipError_t launch_generic(const AmpArgs& A, int U, int grid, hipStream_t st) {
     GenericEval64<EVEN> ev{A.tab64, A.gdeg, A.gK, A.gstride};
     switch (U) {
-        case 1: return launch_one<1>(A, ev, grid, st);
-        case 2: return launch_one<2>(A, ev, grid, st);
-        case 3: return launch_one<3>(A, ev, grid, st);
-        case 4: return launch_one<4>(A, ev, grid, st);
+        case 1: return launch_one<DefaultShape<1>>(A, ev, grid, st);
+        case 2: return launch_one<DefaultShape<2>>(A, ev, grid, st);
+        case 3: return launch_one<DefaultShape<3>>(A, ev, grid, st);
+        case 4: return launch_one<DefaultShape<4>>(A, ev, grid, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -93,10 +97,10 @@ static hipError_t launch_generic(const AmpArgs& A, int U, int grid, hipStream_t 
 static hipError_t launch_tanh(const AmpArgs& A, int U, int grid, hipStream_t st) {
     TanhEval64 ev{A.tab64, A.gdeg, A.gK, A.gstride, A.alpha};
     switch (U) {
-        case 1: return launch_one<1>(A, ev, grid, st);
-        case 2: return launch_one<2>(A, ev, grid, st);
-        case 3: return launch_one<3>(A, ev, grid, st);
-        case 4: return launch_one<4>(A, ev, grid, st);
+        case 1: return launch_one<DefaultShape<1>>(A, ev, grid, st);
+        case 2: return launch_one<DefaultShape<2>>(A, ev, grid, st);
+        case 3: return launch_one<DefaultShape<3>>(A, ev, grid, st);
+        case 4: return launch_one<DefaultShape<4>>(A, ev, grid, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -139,17 +143,17 @@ int amplitude_resident_blocks(EvalKind kind, int p, int U, size_t lds_bytes, int
         case EvalKind::GenericEven64:
         case EvalKind::GenericOdd64:
             switch (U) {
-                case 1: return resident_one<1, GenericEval64<true>>(lds_bytes, device);
-                case 2: return resident_one<2, GenericEval64<true>>(lds_bytes, device);
-                case 3: return resident_one<3, GenericEval64<true>>(lds_bytes, device);
-                default: return resident_one<4, GenericEval64<true>>(lds_bytes, device);
+                case 1: return resident_one<DefaultShape<1>, GenericEval64<true>>(lds_bytes, device);
+                case 2: return resident_one<DefaultShape<2>, GenericEval64<true>>(lds_bytes, device);
+                case 3: return resident_one<DefaultShape<3>, GenericEval64<true>>(lds_bytes, device);
+                default: return resident_one<DefaultShape<4>, GenericEval64<true>>(lds_bytes, device);
             }
         case EvalKind::Tanh64:
             switch (U) {
-                case 1: return resident_one<1, TanhEval64>(lds_bytes, device);
-                case 2: return resident_one<2, TanhEval64>(lds_bytes, device);
-                case 3: return resident_one<3, TanhEval64>(lds_bytes, device);
-                default: return resident_one<4, TanhEval64>(lds_bytes, device);
+                case 1: return resident_one<DefaultShape<1>, TanhEval64>(lds_bytes, device);
+                case 2: return resident_one<DefaultShape<2>, TanhEval64>(lds_bytes, device);
+                case 3: return resident_one<DefaultShape<3>, TanhEval64>(lds_bytes, device);
+                default: return resident_one<DefaultShape<4>, TanhEval64>(lds_bytes, device);
             }
         case EvalKind::Tanh64P:
             return resident_tanh_fixed(p, lds_bytes, device);

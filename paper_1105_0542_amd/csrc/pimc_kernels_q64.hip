@@ -1,5 +1,5 @@
 // Estimation kernels with the compile-time table shapes of level p = 1..kMaxP (the quartic family in FP64),
-// subtrees of 5 levels (N >= 32) or 4 (N = 16); one translation unit per evaluator family so that they
+// subtrees of 4 levels; one translation unit per evaluator family so that they
 // compile in parallel.
 #include <hip/hip_runtime.h>
 
@@ -15,8 +15,7 @@ hipError_t launch_p(const AmpArgs& A, int p, int U, int grid, hipStream_t st) {
         if (p != P) return launch_p<P + 1>(A, p, U, grid, st);
         const QuarticEval64<P> ev{A.tab64};
         switch (U) {
-            case 4: return launch_one<4>(A, ev, grid, st);
-            case 5: return launch_one<5>(A, ev, grid, st);
+            case 4: return launch_one<DefaultShape<4>>(A, ev, grid, st);
             default: return hipErrorInvalidValue;
         }
     } else {
@@ -28,7 +27,7 @@ template <int P>
 int resident_p(int p, int U, size_t lds, int device) {
     if constexpr (P <= kMaxP) {
         if (p != P) return resident_p<P + 1>(p, U, lds, device);
-        return U == 5 ? resident_one<5, QuarticEval64<P>>(lds, device) : resident_one<4, QuarticEval64<P>>(lds, device);
+        return U == 4 ? resident_one<DefaultShape<4>, QuarticEval64<P>>(lds, device) : 0;
     } else {
         return 256;
     }

@@ -13,7 +13,7 @@ hipError_t launch_p(const AmpArgs& A, int p, int grid, hipStream_t st) {
     if constexpr (P <= kMaxP) {
         if (p != P) return launch_p<P + 1>(A, p, grid, st);
         const TanhEvalP<P> ev{A.tab64, A.alpha};
-        return launch_one<4>(A, ev, grid, st);
+        return launch_one<DefaultShape<4>>(A, ev, grid, st);
     } else {
         return hipErrorInvalidValue;
     }
@@ -23,7 +23,7 @@ template <int P>
 int resident_p(int p, size_t lds, int device) {
     if constexpr (P <= kMaxP) {
         if (p != P) return resident_p<P + 1>(p, lds, device);
-        return resident_one<4, TanhEvalP<P>>(lds, device);
+        return resident_one<DefaultShape<4>, TanhEvalP<P>>(lds, device);
     } else {
         return 256;
     }

@@ -20,11 +20,12 @@
 #include <stdint.h>
 
 #include "pimc_device.hpp"
+#include "pimc_internal.hpp"
 
 namespace pimc {
 
 constexpr int kVecMaxDim = 3;
-constexpr int kVecBlock = 256;          // lanes of a workgroup and of a canonical chunk
+constexpr int kVecBlock = 256;          // lanes of a workgroup
 #ifndef PIMC_VEC_U
 #define PIMC_VEC_U 4
 #endif
@@ -93,8 +94,7 @@ struct VecArgs {
     RngKey key;
     uint64_t first_path;
     uint64_t n_paths;
-    uint64_t n_chunks;
-    uint32_t ppl;                      // paths per lane per chunk
+    uint64_t n_chunks;                 // ceil(n_paths / kChunkPaths)
     int s;                             // N = 2^s
     int D;                             // s - U: levels walked with the explicit stack
     int hier;                          // every level (else level s only)
@@ -102,10 +102,11 @@ struct VecArgs {
     double* dump;                      // device [path][s+1] or null
 };
 
-// Dynamic LDS bytes: per lane D level sums and (D+1)*dim pending right endpoints; per wave and level
-// three accumulators.
+// Dynamic LDS bytes: the Box-Muller table; per lane D level sums and (D+1)*dim pending right
+// endpoints; per accumulator slot and level three sums.
 inline size_t vec_lds_bytes(int dim, int D, int s) {
-    return (size_t(D + (D + 1) * dim) * kVecBlock + size_t(4 * (s + 1) * 3)) * sizeof(double);
+    return (size_t(kBoxMullerTable) + size_t(D + (D + 1) * dim) * kVecBlock + size_t(kChunkSlots * (s + 1) * 3)) *
+           sizeof(double);
 }
 
 // Launch the vector estimation kernel: dim 1..3; U = min(s, kVecU); `specialized` selects the

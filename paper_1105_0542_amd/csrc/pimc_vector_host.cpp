@@ -412,8 +412,7 @@ int vector_amplitude_core(pimc_ctx* c, const VecProblem& P, uint64_t n_samples, 
     VecArgs A;
     st = stage_vector(c, P, seed, stream, A);
     if (st) return st;
-    const uint32_t ppl = paths_per_lane(P.s);
-    const uint64_t chunk_paths = uint64_t(kVecBlock) * ppl;
+    const uint64_t chunk_paths = kChunkPaths;
     const uint64_t n_chunks = (n_samples + chunk_paths - 1) / chunk_paths;
     const int slots = hier ? nlev : 1;
     st = ensure(c, reinterpret_cast<void**>(&c->d_partials), &c->partial_bytes, size_t(slots) * n_chunks * 4 * 8);
@@ -431,7 +430,6 @@ int vector_amplitude_core(pimc_ctx* c, const VecProblem& P, uint64_t n_samples, 
     A.first_path = 0;
     A.n_paths = n_samples;
     A.n_chunks = n_chunks;
-    A.ppl = ppl;
     A.hier = hier ? 1 : 0;
     A.partials = c->d_partials;
     A.dump = nullptr;
@@ -446,6 +444,7 @@ int vector_amplitude_core(pimc_ctx* c, const VecProblem& P, uint64_t n_samples, 
     float ms = 0.f;
     HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
     c->last_ms = ms;
+    c->last_partials_ptr = c->d_partials;
     c->last_chunks = n_chunks;
     c->last_chunk_paths = chunk_paths;
     c->last_hier = hier;
@@ -472,12 +471,10 @@ int vector_path_actions_core(pimc_ctx* c, const VecProblem& P, uint64_t seed, ui
     if (st) return st;
     st = ensure(c, reinterpret_cast<void**>(&c->d_dump), &c->dump_bytes, size_t(k_paths) * nlev * 8);
     if (st) return st;
-    const uint32_t ppl = paths_per_lane(P.s);
-    const uint64_t chunk_paths = uint64_t(kVecBlock) * ppl;
+    const uint64_t chunk_paths = kChunkPaths;
     A.first_path = first_path;
     A.n_paths = k_paths;
     A.n_chunks = (k_paths + chunk_paths - 1) / chunk_paths;
-    A.ppl = ppl;
     A.hier = (flags & PIMC_HIERARCHY) ? 1 : 0;
     A.partials = nullptr;
     A.dump = c->d_dump;

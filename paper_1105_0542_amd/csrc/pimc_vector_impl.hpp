@@ -10,8 +10,8 @@
 // coordinate for every 2^U leaves; it halves the LDS per lane).
 //
 // Per level, each path's weight enters as d = exp(-(S_n - S_ref,n)) - 1, summed per canonical chunk
-// of kVecBlock * ppl paths in a fixed order (the one-dimensional reduction), then over chunks by
-// k_seg_reduce: the result does not depend on the grid.
+// (kChunkPaths paths, the order of the one-dimensional kernels, pimc_internal.hpp), then over chunks
+// by k_seg_reduce: the result does not depend on the grid.
 #pragma once
 
 #include "pimc_vector.hpp"
@@ -23,17 +23,18 @@ template <int DIM>
 struct VecSource {
     RngKey key;
     PathRng pr;
+    const double* bm;                  // Box-Muller table (LDS)
     // Normals of heap nodes 2j and 2j+1 in every coordinate.
     __device__ __forceinline__ void pair(uint32_t j, double (&ze)[DIM], double (&zo)[DIM]) const {
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) normal_pair(key, pr, j + uint32_t(c) * kCoordPairStride, ze[c], zo[c]);
+        for (int c = 0; c < DIM; ++c) normal_pair(key, pr, j + uint32_t(c) * kCoordPairStride, bm, ze[c], zo[c]);
     }
     // Normal of heap node h in every coordinate.
     __device__ __forceinline__ void node(uint32_t h, double (&z)[DIM]) const {
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
             double e, o;
-            normal_pair(key, pr, (h >> 1) + uint32_t(c) * kCoordPairStride, e, o);
+            normal_pair(key, pr, (h >> 1) + uint32_t(c) * kCoordPairStride, bm, e, o);
             z[c] = (h & 1u) ? o : e;
         }
     }
@@ -333,43 +334,46 @@ __device__ __forceinline__ void walk_path(const Eval& ev, const VecArgs& A, cons
 }
 
 // ---------------------------------------------------------------------------- estimation kernel
-__device__ __forceinline__ void reduce_level(const VecArgs& A, double* acc, int nlev, int wave, int lane, int n,
-                                             double S, bool valid) {
+__device__ __forceinline__ void reduce_level(const VecArgs& A, double* a, int lane, int n, double S, bool valid) {
     const double d = valid ? expm1(-(S - as_const(A.shift)[n])) : 0.0;
     const bool bad = valid && !isfinite(d);
     const double sd = wave_sum(d);
     const double sd2 = wave_sum(d * d);
     const unsigned long long badmask = __ballot(bad);
     if (lane == 0) {
-        double* a = acc + (wave * nlev + n) * 3;
         a[0] += sd;
         a[1] += sd2;
         a[2] += double(__popcll(badmask));
     }
 }
 
-// One canonical chunk c: paths c*CH .. c*CH+CH-1 (CH = kVecBlock * ppl), lane tid takes paths
-// c*CH + r*kVecBlock + tid for r = 0..ppl-1 in order; writes the chunk's four sums per evaluated level
-// to A.partials[(slot * n_chunks + c) * 4] and/or the per-path level actions to A.dump.
+// One canonical chunk c: paths c*kChunkPaths + 64 g + lane, groups g = wave, wave + 4, ... (the
+// order of the one-dimensional kernels); writes the chunk's four sums per evaluated level to
+// A.partials[(slot * n_chunks + c) * 4] and/or the per-path level actions to A.dump. smem: the
+// Box-Muller table, the per-lane stack, the accumulator slots.
 template <int DIM, int U, class Eval>
 __device__ __forceinline__ void process_chunk(const Eval& ev, const VecArgs& A, uint64_t c, double* smem) {
+    constexpr int WAVES = kVecBlock / 64;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int D = A.D;
     const int nlev = A.s + 1;
-    double* top = smem + tid;
-    double* acc = smem + size_t(D + (D + 1) * DIM) * kVecBlock;
-    const uint64_t CH = uint64_t(kVecBlock) * A.ppl;
+    const double* bm = smem;
+    double* top = smem + kBoxMullerTable + tid;
+    double* acc = smem + kBoxMullerTable + size_t(D + (D + 1) * DIM) * kVecBlock;
+    const uint64_t first = c * kChunkPaths;
     if (A.partials) {
-        for (int i = tid; i < 4 * nlev * 3; i += kVecBlock) acc[i] = 0.0;
+        for (int i = tid; i < kChunkSlots * nlev * 3; i += kVecBlock) acc[i] = 0.0;
         __syncthreads();
     }
-    for (uint32_t r = 0; r < A.ppl; ++r) {
-        const uint64_t local = c * CH + uint64_t(r) * kVecBlock + uint64_t(tid);
+    for (int g = wave; g < kChunkGroups; g += WAVES) {
+        const uint64_t group0 = first + uint64_t(g) * 64;
+        if (group0 >= A.n_paths) break;                   // wave-uniform: the rest of the chunk is empty
+        const uint64_t local = group0 + uint64_t(lane);
         const bool valid = local < A.n_paths;
         double Ssub[U + 1];
-        const VecSource<DIM> src{A.key, path_rng(A.key, A.first_path + local)};
+        const VecSource<DIM> src{A.key, path_rng(A.key, A.first_path + local), bm};
         walk_path<DIM, U, Eval>(ev, A, src, top, Ssub);
         if (A.dump && valid) {
             double* o = A.dump + local * uint64_t(nlev);
@@ -378,12 +382,13 @@ __device__ __forceinline__ void process_chunk(const Eval& ev, const VecArgs& A, 
             for (int j = 0; j <= U; ++j) o[D + j] = (A.hier || j == U) ? Ssub[j] : 0.0;
         }
         if (A.partials) {
+            double* a = acc + (g % kChunkSlots) * nlev * 3;
             if (A.hier) {
-                for (int n = 0; n < D; ++n) reduce_level(A, acc, nlev, wave, lane, n, top[n * kVecBlock], valid);
+                for (int n = 0; n < D; ++n) reduce_level(A, a + n * 3, lane, n, top[n * kVecBlock], valid);
 #pragma unroll
-                for (int j = 0; j < U; ++j) reduce_level(A, acc, nlev, wave, lane, D + j, Ssub[j], valid);
+                for (int j = 0; j < U; ++j) reduce_level(A, a + (D + j) * 3, lane, D + j, Ssub[j], valid);
             }
-            reduce_level(A, acc, nlev, wave, lane, D + U, Ssub[U], valid);
+            reduce_level(A, a + (D + U) * 3, lane, D + U, Ssub[U], valid);
         }
     }
     if (A.partials) {
@@ -391,11 +396,11 @@ __device__ __forceinline__ void process_chunk(const Eval& ev, const VecArgs& A, 
         const int slots = A.hier ? nlev : 1;
         if (tid < slots) {
             const int lev = A.hier ? tid : nlev - 1;
-            const uint64_t rem = A.n_paths - c * CH;
-            const double cnt = double(rem < CH ? rem : CH);
+            const uint64_t rem = A.n_paths - first;
+            const double cnt = double(rem < kChunkPaths ? rem : kChunkPaths);
             double s1 = 0.0, s2 = 0.0, nb = 0.0;
-            for (int w = 0; w < kVecBlock / 64; ++w) {
-                const double* a = acc + (w * nlev + lev) * 3;
+            for (int q = 0; q < kChunkSlots; ++q) {
+                const double* a = acc + (q * nlev + lev) * 3;
                 s1 += a[0];
                 s2 += a[1];
                 nb += a[2];
@@ -414,6 +419,8 @@ template <int DIM, int U, class Eval>
 __global__ void __launch_bounds__(kVecBlock) __attribute__((amdgpu_waves_per_eu(2)))
 k_amplitude_vec(VecArgs A, Eval ev) {
     extern __shared__ double smem[];
+    load_bm_table(smem, kVecBlock);
+    __syncthreads();
     for (uint64_t c = blockIdx.x; c < A.n_chunks; c += gridDim.x) process_chunk<DIM, U, Eval>(ev, A, c, smem);
 }
 

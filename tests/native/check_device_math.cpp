@@ -2,7 +2,9 @@
 // CPU. The hardware reciprocal and reciprocal-square-root estimates are replaced by the exact values
 // perturbed by a relative 2^-22 (the estimates are accurate to about 2^-23), so the Newton steps are
 // exercised. Prints the worst error in units of the last place (against long double references) of
-// tanh_fp64, exp_fp64, -2 ln u, sqrt and (sin, cos)(2 pi t) over their argument ranges.
+// tanh_fp64, exp_fp64, -2 ln u, sqrt and (sin, cos)(2 pi u) over their argument ranges (the
+// Box-Muller pair with the table of pimc_math.hpp, read from host memory here), with the extreme
+// and bucket-boundary uniforms added to the random ones.
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -34,19 +36,24 @@ int main() {
         w_exp = std::max(w_exp, ulp_err(exp_fp64(x), std::exp((long double)x)));
         const double xs = std::uniform_real_distribution<double>(-3.0, 3.0)(rng);
         w_exp = std::max(w_exp, ulp_err(exp_fp64(xs), std::exp((long double)xs)));
-        // -2 ln u for u = K 2^-53 from two 32-bit words
-        const uint64_t bits = rng();
+        // -2 ln u and (sin, cos)(2 pi u) for u = K 2^-53 from two 32-bit words
+        uint64_t bits = rng();
+        if (i < 4096) {
+            // extremes (u -> 0, u -> 1) and the neighbourhoods of the table's bucket boundaries
+            const uint64_t K0 = (i & 1) ? (uint64_t(1) << 53) - 1 - 2 * uint64_t(i) : 1 + 2 * uint64_t(i);
+            const uint64_t Kb = ((uint64_t(64 + (i >> 6)) << 46) + (uint64_t(i & 63) - 32)) | 1;   // near c-bucket edges
+            const uint64_t K = (i & 2) ? K0 : (Kb >> (i % 7));
+            bits = ((K | 1) << 11) | (rng() & 0x7FF);
+        }
         const uint32_t lo = uint32_t(bits), hi = uint32_t(bits >> 32);
         const uint64_t K = ((uint64_t(hi) << 32 | lo) >> 11) | 1u;
         const long double u = (long double)K * 0x1p-53L;
-        const double L = neg2_log_odd53(lo, hi);
+        const double L = neg2_log_u53(lo, hi, kBMTable);
         w_log = std::max(w_log, ulp_err(L, -2.0L * std::log(u)));
         w_sqrt = std::max(w_sqrt, ulp_err(sqrt_pos(L), std::sqrt((long double)L)));
-        // (sin, cos)(2 pi t) for t a multiple of 2^-53 in [0, 1)
-        const double t = double(rng() >> 11) * 0x1p-53;
         double sn, cs;
-        sincos_2pi(t, sn, cs);
-        const long double a = 2.0L * 3.14159265358979323846264338327950288L * (long double)t;
+        sincos_2pi_u53(lo, hi, kBMTable, sn, cs);
+        const long double a = 2.0L * 3.14159265358979323846264338327950288L * u;
         // absolute error in ulps of 1 (the normals use r * sin, r * cos; near zeros relative error is
         // not meaningful)
         w_sc = std::max(w_sc, double(std::fabs((long double)sn - std::sin(a)) / 0x1p-53L));

@@ -56,14 +56,50 @@ def test_batch_equals_single_calls_bitwise(ctx, flags):
 
 
 def test_batch_launch_shape_does_not_change_bits(ctx):
+    """Every compiled launch shape of every class (subtree depth, workgroup size, waves per SIMD,
+    slice batch) and every grid and grab give the same bits: the canonical chunks fix the order of
+    every sum."""
     systems, rows = small_grid()
-    bt = P.Batch(ctx, systems, rows, seed=3, flags=0)
+    bt = P.Batch(ctx, systems, rows, seed=3, flags=P.FLAG_HIERARCHY)
     base, _, _ = bt.run()
+    classes = bt.classes()
+    assert {c["p"] for c in classes} == {8, 12, 18}
+    for k, c in enumerate(classes):
+        assert c["n_shapes"] == (5 if c["n16"] else 8)
+        for shape in range(1, c["n_shapes"]):
+            bt.set_shape(k, shape)
+            info = bt.classes()[k]
+            print(f"class {k} (p={c['p']}, n16={c['n16']}): shape {shape} U={info['subtree_levels']} "
+                  f"block={info['block']} waves/EU={info['waves_per_eu']} batch={info['slice_batch']}", flush=True)
+            out, _, _ = bt.run()
+            assert np.array_equal(out["amp"], base["amp"], equal_nan=True), (k, shape)
+            assert np.array_equal(out["err"], base["err"], equal_nan=True), (k, shape)
+        bt.set_shape(k, 0)
     for g, grab in [(1, 1), (2, 4), (4, 16), (8, 64), (3, 7)]:
         bt.set_tuning(g, grab)
         out, _, _ = bt.run()
         assert np.array_equal(out["amp"], base["amp"], equal_nan=True), (g, grab)
         assert np.array_equal(out["err"], base["err"], equal_nan=True), (g, grab)
+    bt.close()
+
+
+def test_batch_results_into_device_memory(ctx):
+    """The results of a replay written into a caller-owned device buffer (a torch tensor) equal the
+    host-memory results bit for bit."""
+    import torch
+    systems, rows = small_grid(samples=1000)
+    bt = P.Batch(ctx, systems, rows, seed=2, flags=P.FLAG_HIERARCHY)
+    host, _, _ = bt.run()
+    out = torch.full((len(rows), bt.s_max + 1, 7), float("nan"), dtype=torch.float64, device="cuda")
+    ms, st = bt.run_to_device(out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    for j, name in enumerate(("amp", "err", "log_amp", "relvar", "ess")):
+        assert np.array_equal(got[..., j], host[name], equal_nan=True), name
+    for j, name in ((5, "n"), (6, "n_nonfinite")):
+        assert np.array_equal(np.ascontiguousarray(got[..., j]).view(np.uint64), host[name]), name
+    with pytest.raises(ValueError):
+        bt.run_to_device(torch.empty(3, dtype=torch.float64, device="cuda"))
     bt.close()
 
 

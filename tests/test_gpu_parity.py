@@ -231,13 +231,14 @@ def test_full_size_c2_point_sampled_chunks(ctx):
     assert total == (n + cp - 1) // cp
     rng = np.random.default_rng(0)
     picks = [0, int(rng.integers(1, total - 1)), total - 1]
-    for lv in (10, 7, 3):
-        sh_all = [ctx.last_partials(l, 0, 0)[3] for l in range(11)]
-        for c in picks:
+    assert cp == P.binding.PIMC_CHUNK_PATHS
+    sh_all = [ctx.last_partials(l, 0, 0)[3] for l in range(11)]
+    for c in picks:
+        first = c * cp
+        cnt = min(cp, n - first)
+        ref = opimc.chunk_sums(ea.quartic(1, 10), 1, 0.0, 1.0, 1.0, 10, 18, 1, 0, first, cnt, sh_all)
+        for lv in (10, 7, 3):
             got = ctx.last_partials(lv, c, 1)[0][0]
-            first = c * cp
-            cnt = min(cp, n - first)
-            ref = opimc.chunk_sums(ea.quartic(1, 10), 1, 0.0, 1.0, 1.0, 10, 18, 1, 0, first, cnt, sh_all)
             assert got[0] == cnt
             assert got[1] == pytest.approx(ref[lv][1], rel=1e-9, abs=1e-12 * cnt)
             assert got[2] == pytest.approx(ref[lv][2], rel=1e-9, abs=1e-12 * cnt)
