@@ -125,6 +125,24 @@ int pimc_amplitude(pimc_ctx *ctx, const pimc_potential *V, double m, double a, d
                    uint32_t N, int p, uint64_t n_samples, uint64_t seed, uint32_t stream,
                    uint32_t flags, pimc_level_result *out);
 
+/* pimc_amplitude for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same computation, kernels and results
+ * (bit for bit), with every device buffer -- tables, chunk sums, segment list, reduced sums -- in a
+ * static workspace of PIMC_NOALLOC_BYTES that the library holds on each GPU it runs on until the
+ * process ends. No hipMalloc, hipFree or other device or pinned allocation is made (host-side
+ * temporaries of the table construction use the C++ heap). Limit: the chunk sums need
+ * 32 * (levels) * ceil(n_samples / PIMC_CHUNK_PATHS) bytes, levels = log2(N)+1 with
+ * PIMC_HIERARCHY, else 1; at most 16,513,792 bytes (the workspace less 263,424 bytes of tables,
+ * segment list and sums: about 2.1e9 samples for one level, 1.9e8 with every level of N = 1024);
+ * larger requests return PIMC_EINVAL with the
+ * sizes in pimc_last_error, as do tables beyond 256 KiB. All calls on one GPU share the workspace:
+ * calls that overlap on one GPU (several host threads or streams) race, and pimc_last_partials
+ * after this call reads the workspace, so it is valid until the next such call on that GPU. */
+#define PIMC_NOALLOC_BYTES (16u << 20)
+int pimc_amplitude_noalloc(pimc_ctx *ctx, const pimc_potential *V, double m, double a, double b, double T,
+                           uint32_t N, int p, uint64_t n_samples, uint64_t seed, uint32_t stream,
+                           uint32_t flags, pimc_level_result *out);
+
 /* Per-path level actions sum_k eps_n W_p(x_k, xbar_k; eps_n) (the potential part of eq.(SNp); the
  * kinetic part is absorbed by the bisection sampling) of paths first_path..first_path+k_paths-1,
  * computed by the same kernels as pimc_amplitude.  S_out: caller-owned host array

@@ -181,6 +181,10 @@ def load_library():
     lib.pimc_amplitude.restype = C.c_int
     lib.pimc_amplitude.argtypes = [vp, P(Potential), C.c_double, C.c_double, C.c_double, C.c_double, C.c_uint32,
                                    C.c_int, C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32, P(_LevelResult)]
+    lib.pimc_amplitude_noalloc.restype = C.c_int
+    lib.pimc_amplitude_noalloc.argtypes = [vp, P(Potential), C.c_double, C.c_double, C.c_double, C.c_double,
+                                           C.c_uint32, C.c_int, C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32,
+                                           P(_LevelResult)]
     lib.pimc_path_actions.restype = C.c_int
     lib.pimc_path_actions.argtypes = [vp, P(Potential), C.c_double, C.c_double, C.c_double, C.c_double,
                                       C.c_uint32, C.c_int, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64,
@@ -410,6 +414,17 @@ class Context:
         out = (_LevelResult * (s + 1))()
         st = self._check(self.lib.pimc_amplitude(self.h, C.byref(V), m, a, b, T, N, p, n_samples, seed, stream,
                                                  flags, out))
+        res = [LevelResult(r.amp, r.err, r.log_amp, r.relvar, r.ess, int(r.n), int(r.n_nonfinite)) for r in out]
+        return res, st
+
+    def amplitude_noalloc(self, coefs, m, a, b, T, N, p, n_samples, seed, stream=0, flags=0):
+        """pimc_amplitude_noalloc (no device allocation: the library's static workspace) -> (list of
+        LevelResult for n = 0..s, status)."""
+        V = potential_from_coefs(coefs)
+        s = int(N).bit_length() - 1
+        out = (_LevelResult * (s + 1))()
+        st = self._check(self.lib.pimc_amplitude_noalloc(self.h, C.byref(V), m, a, b, T, N, p, n_samples, seed,
+                                                         stream, flags, out))
         res = [LevelResult(r.amp, r.err, r.log_amp, r.relvar, r.ess, int(r.n), int(r.n_nonfinite)) for r in out]
         return res, st
 

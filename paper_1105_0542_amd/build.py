@@ -20,7 +20,7 @@ SOURCES = ["pimc_batch_p18.hip", "pimc_batch_p12.hip", "pimc_batch_p8.hip",
            "pimc_kernels_q64.hip", "pimc_kernels_q32.hip", "pimc_kernels_tanh.hip", "pimc_kernels_batch.hip",
            "pimc_vector_d2.hip", "pimc_vector_d3.hip", "pimc_general_kernels.hip", "pimc_kernels.hip", "pimc_flow.hip",
            "pimc_spectrum.hip", "pimc_vector_d1.hip", "pimc_host.cpp", "pimc_flow_host.cpp", "pimc_spectrum_host.cpp",
-           "pimc_general_host.cpp", "pimc_vector_host.cpp"]
+           "pimc_general_host.cpp", "pimc_vector_host.cpp", "pimc_noalloc.cpp"]
 HEADERS = ["pimc_tables.hpp", "pimc_device.hpp", "pimc_internal.hpp", "pimc_math.hpp", "pimc_walker.hpp",
            "pimc_flow.hpp", "pimc_host_common.hpp", "pimc_spectrum.hpp", "pimc_general.hpp",
            "pimc_general_device.hpp", "pimc_vector.hpp", "pimc_vector_impl.hpp", "pimc_batch.hpp"]

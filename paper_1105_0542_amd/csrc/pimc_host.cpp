@@ -576,6 +576,7 @@ int pimc_create(pimc_ctx** out, int device, void* hip_stream) {
     }
     if (e == hipSuccess) e = hipEventCreate(&c->ev0);
     if (e == hipSuccess) e = hipEventCreate(&c->ev1);
+    if (e == hipSuccess) noalloc_setup(device);
     if (e != hipSuccess) {
         set_thread_error("context setup failed: %s", hipGetErrorString(e));
         pimc_destroy(c);

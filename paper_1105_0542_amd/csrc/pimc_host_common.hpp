@@ -102,6 +102,9 @@ extern const uint32_t kKnownFlags;
 bool assemble_level(const double* red, double logbase, pimc_level_result& r);
 int check_args(const pimc_potential* V, double m, double a, double b, double T, uint32_t N, int p,
                uint64_t n_samples);
+// With `device` current: look up the device address of the no-allocation workspace once per device
+// (pimc_noalloc.cpp); called by pimc_create.
+void noalloc_setup(int device);
 int log2_exact(uint32_t N);
 
 }  // namespace pimc_host
