@@ -65,7 +65,8 @@ __device__ __forceinline__ double exp_logscale(double s) {
 }
 
 // ------------------------------------------------------------------------------------ training
-// The training step works on tiles of kTP = 16 paths (256 workgroups at a batch of 4096, one per CU):
+// The training step works on tiles of kTP = 16 paths, the MFMA's column count (256 workgroups of
+// four waves at a batch of 4096):
 //  * k_train_fwd carries a tile through the base normals and every coupling in LDS -- the same
 //    bf16 MFMA products and FP64 affine update as the fused estimation kernel -- and keeps each
 //    layer's input X_c (FP64 planes [h-1][path]) for the backward;
@@ -74,65 +75,153 @@ __device__ __forceinline__ double exp_logscale(double s) {
 //    as exact FP32 values, so the gradient is the derivative of the map the forward computes, up to
 //    FP32 accumulation. It writes, per layer, the output and pre-activation gradients (FP32) and the
 //    conditioner inputs and hidden activations (bf16) as [row][path] planes;
-//  * k_flow_wgrad forms the parameter gradients from those planes: each 16 x 16 block of a weight
-//    gradient and each bias row is summed over the batch by one workgroup in a fixed order.
+//  * k_flow_wgrad_part / k_flow_wgrad_sum form the parameter gradients from those planes, split
+//    over batch slices and summed in a fixed order.
+// One tile per CU leaves no other workgroup to cover a memory wait, so both tile kernels keep
+// their global loads off the critical path: each wave holds its weight fragments of a layer in
+// registers (bf16x8 operand vectors, 48 VGPRs forward, 96 backward plus the biases) and reloads
+// them for the next layer right after their last use, and the backward loads the next layer's
+// input X_{c-1} into registers at the start of layer c and moves it to LDS at the end.
 constexpr int kTP = 16;                        // paths per training tile
 constexpr int kFusedMaxD = 127;                // coordinates of a tile (N <= 128)
+constexpr int kTileRegs = (kFusedMaxD * kTP + kBlock - 1) / kBlock;   // tile doubles per thread
 constexpr int kTLdA = kFlowK + 8;              // xa [P][in] row stride (bf16 elements)
 constexpr int kTLdH = kFlowH + 8;              // hs [P][hid] row stride (bf16 elements)
 constexpr int kTLdG = kFlowH + 4;              // go, gp [P][row] row stride (floats)
 
-// C(16x16) += A(16 rows x K) * BT(16 rows x K)^T on FP32 MFMA: A rows bf16 in global memory
-// (converted exactly), BT rows FP32; K a multiple of 32.
-__device__ __forceinline__ floatx4 mma16_f32_bf16A(const __bf16* A, int lda, const float* BT, int ldb, int K, floatx4 c) {
+// Operand vector of a 16 x 32 block of a row-major bf16 matrix: rows r0 + (l & 15), columns
+// k0 + 8 (l >> 4) .. + 7 (the A layout of the bf16 MFMA; the FP32 products below take the same
+// vector, see fma16_f32).
+__device__ __forceinline__ bf16x8 frag(const __bf16* M, int ld, int r0, int k0) {
     const int l = threadIdx.x & 63;
-    const __bf16* ar = A + (l & 15) * lda + (l >> 4);
-    const float* br = BT + (l & 15) * ldb + (l >> 4);
-    for (int ks = 0; ks < K; ks += 32) {
-        float a[8], bv[8];
+    return *reinterpret_cast<const bf16x8*>(M + (r0 + (l & 15)) * ld + k0 + 8 * (l >> 4));
+}
+
+// Weight operands of one layer held by a wave: hidden rows 32w + 16mb (W1), output rows 16w (s_hat)
+// and 64 + 16w (t) of W2, and the biases of this lane's output slots.
+struct FwdFrags {
+    bf16x8 w1[2][2];        // [mb][k block of 32 inputs]
+    bf16x8 w2[2][4];        // [s, t][k block of 32 hidden]
+    float b1[2][4];         // hidden 32w + 16mb + 4(l>>4) + j
+    float b2[2][4];         // output 16w + 4(l>>4) + j (s_hat), 64 + ... (t)
+};
+struct BwdFrags {
+    bf16x8 w2t[2][4];       // W2T rows 32w + 16mb, k block of 32 outputs
+    bf16x8 w1t[4];          // W1T rows 16w, k block of 32 hidden
+};
+
+__device__ __forceinline__ void load_w1(FwdFrags& F, const FlowLayerDev& L) {
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            a[q] = float(ar[ks + 4 * q]);
-            bv[q] = br[ks + 4 * q];
-        }
+    for (int mb = 0; mb < 2; ++mb) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], bv[q], c, 0, 0, 0);
+        for (int kb = 0; kb < 2; ++kb) F.w1[mb][kb] = frag(L.W1, kFlowK, 32 * w + 16 * mb, 32 * kb);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) F.b1[mb][j] = L.b1[32 * w + 16 * mb + 4 * (l >> 4) + j];
+    }
+}
+__device__ __forceinline__ void load_w2(FwdFrags& F, const FlowLayerDev& L) {
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 0; o < 2; ++o) {
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) F.w2[o][kb] = frag(L.W2, kFlowH, 64 * o + 16 * w, 32 * kb);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) F.b2[o][j] = L.b2[64 * o + 16 * w + 4 * (l >> 4) + j];
+    }
+}
+__device__ __forceinline__ void load_w2t(BwdFrags& F, const FlowLayerDev& L) {
+    const int w = threadIdx.x >> 6;
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) F.w2t[mb][kb] = frag(L.W2T, kFlowH, 32 * w + 16 * mb, 32 * kb);
+}
+__device__ __forceinline__ void load_w1t(BwdFrags& F, const FlowLayerDev& L) {
+    const int w = threadIdx.x >> 6;
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) F.w1t[kb] = frag(L.W1T, kFlowH, 16 * w, 32 * kb);
+}
+
+// C(16 x 16) += A(16 x 128) B, A from fragments (bf16, exact in FP32) and B^T rows from LDS (FP32,
+// [column][k], stride ldb), on v_mfma_f32_16x16x4f32. The k index is permuted against the
+// instruction's own order: in product q of k block kb, lane l supplies k = 32kb + 8(l>>4) + q for
+// both operands, so each lane reads 8 consecutive k of A (one fragment) and of B (two 16-byte LDS
+// reads); the sum over k is the same, in another rounding order.
+__device__ __forceinline__ floatx4 fma16_f32(const bf16x8 (&a)[4], const float* BT, int ldb, floatx4 c) {
+    const int l = threadIdx.x & 63;
+    const float* br = BT + (l & 15) * ldb + 8 * (l >> 4);
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+        const floatx4 b0 = *reinterpret_cast<const floatx4*>(br + 32 * kb);
+        const floatx4 b1 = *reinterpret_cast<const floatx4*>(br + 32 * kb + 4);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) c = __builtin_amdgcn_mfma_f32_16x16x4f32(float(a[kb][q]), b0[q], c, 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) c = __builtin_amdgcn_mfma_f32_16x16x4f32(float(a[kb][4 + q]), b1[q], c, 0, 0, 0);
     }
     return c;
 }
 
+// The masks of every layer type into LDS: masks[type][0..63] conditioner coordinates, [64..127]
+// transformed coordinates (heap node - 1).
+__device__ __forceinline__ void train_masks(const FlowNet& net, int* masks) {
+    int v[2];
+#pragma unroll
+    for (int it = 0; it < 2; ++it) v[it] = net.masks[threadIdx.x + it * kBlock];
+#pragma unroll
+    for (int it = 0; it < 2; ++it) masks[threadIdx.x + it * kBlock] = v[it];
+}
+static_assert(2 * kBlock == 4 * 128, "two mask entries per thread");
+
 // x_A tile of layer L: bf16 [P][in] from the FP64 tile X[(h-1)*kTP + P] (inputs beyond dA are 0).
-__device__ __forceinline__ void train_xa(const FlowLayerDev& L, const double* X, __bf16* xa) {
+__device__ __forceinline__ void train_xa(const FlowLayerDev& L, const int* am, const double* X, __bf16* xa) {
     for (int i = threadIdx.x; i < kTP * kFlowK; i += kBlock) {
         const int P = i % kTP, k = i / kTP;
-        xa[P * kTLdA + k] = (__bf16)(float)(k < L.dA ? X[L.Aidx[k] * kTP + P] : 0.0);
+        xa[P * kTLdA + k] = (__bf16)(float)(k < L.dA ? X[am[k] * kTP + P] : 0.0);
     }
 }
 
-// Hidden layer of the tile: wave w computes hidden rows 32w..32w+31 for the 16 paths; pre-activation
-// (with bias) returned in pre[mb][j] for hid = 32w + 16mb + 4(l>>4) + j, path l & 15; h = silu(pre)
-// stored to hs [P][hid] as bf16.
-__device__ __forceinline__ void train_hidden(const FlowLayerDev& L, const __bf16* xa, __bf16* hs, floatx4 (&pre)[2]) {
+// Hidden layer of the tile: wave w computes hidden rows 32w..32w+31 for the 16 paths;
+// pre-activation (with bias) returned in pre[mb][j] for hid = 32w + 16mb + 4(l>>4) + j, path
+// l & 15; h = silu(pre) stored to hs [P][hid] as bf16.
+__device__ __forceinline__ void train_hidden(const FwdFrags& F, const __bf16* xa, __bf16* hs, floatx4 (&pre)[2]) {
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const __bf16* xr = xa + (l & 15) * kTLdA + 8 * (l >> 4);
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb) {
-        const int h0 = 32 * w + 16 * mb;
-        pre[mb] = mma16(L.W1 + h0 * kFlowK, kFlowK, xa, kTLdA, kFlowK, floatx4{0.f, 0.f, 0.f, 0.f});
+        floatx4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.w1[mb][kb], *reinterpret_cast<const bf16x8*>(xr + 32 * kb), c,
+                                                        0, 0, 0);
+        pre[mb] = c;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int hid = h0 + 4 * (l >> 4) + j;
-            pre[mb][j] += L.b1[hid];
+            const int hid = 32 * w + 16 * mb + 4 * (l >> 4) + j;
+            pre[mb][j] += F.b1[mb][j];
             hs[(l & 15) * kTLdH + hid] = (__bf16)silu(pre[mb][j]);
         }
     }
 }
 
-// Output layer: wave w computes s_hat rows 16w..16w+15 (os) and t rows 64+16w.. (ot) for the tile;
-// lane l, slot j holds coordinate 16w + 4(l>>4) + j of path l & 15 (bias not added).
-__device__ __forceinline__ void train_output(const FlowLayerDev& L, const __bf16* hs, floatx4& os, floatx4& ot) {
-    const int w = threadIdx.x >> 6;
-    os = mma16(L.W2 + (16 * w) * kFlowH, kFlowH, hs, kTLdH, kFlowH, floatx4{0.f, 0.f, 0.f, 0.f});
-    ot = mma16(L.W2 + (64 + 16 * w) * kFlowH, kFlowH, hs, kTLdH, kFlowH, floatx4{0.f, 0.f, 0.f, 0.f});
+// Output layer: wave w computes s_hat rows 16w..16w+15 (os) and t rows 64+16w.. (ot); lane l, slot
+// j holds coordinate 16w + 4(l>>4) + j of path l & 15, bias included.
+__device__ __forceinline__ void train_output(const FwdFrags& F, const __bf16* hs, floatx4& os, floatx4& ot) {
+    const int l = threadIdx.x & 63;
+    const __bf16* hr = hs + (l & 15) * kTLdH + 8 * (l >> 4);
+    floatx4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+        const bf16x8 h = *reinterpret_cast<const bf16x8*>(hr + 32 * kb);
+        c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.w2[0][kb], h, c0, 0, 0, 0);
+        c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.w2[1][kb], h, c1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        os[j] = c0[j] + F.b2[0][j];
+        ot[j] = c1[j] + F.b2[1][j];
+    }
 }
 
 // Base normals (the plain sampler's, stream key.stream + *step), every coupling; X_c (c = 0..L) to
@@ -140,60 +229,71 @@ __device__ __forceinline__ void train_output(const FlowLayerDev& L, const __bf16
 __global__ void __launch_bounds__(kBlock) k_train_fwd(FlowNet net, RngKey key, const int* step, uint64_t n, int D,
                                                       double* __restrict__ Xg, uint64_t ld, uint64_t plane,
                                                       double* __restrict__ hu2, double* __restrict__ logdet) {
+    constexpr int kG = kBlock / kTP;             // thread groups of the normals
     __shared__ double X[kFusedMaxD * kTP];
     __shared__ __attribute__((aligned(16))) __bf16 xa[kTP * kTLdA];
     __shared__ __attribute__((aligned(16))) __bf16 hs[kTP * kTLdH];      // also the Box-Muller table at first
-    __shared__ double red[kTP][kTP];
+    __shared__ int masks[4 * 128];
+    __shared__ double red[kG][kTP];
     __shared__ double redl[4][kTP];
     static_assert(sizeof(hs) >= kBoxMullerTable * sizeof(double), "table fits the hidden tile");
     const int t = threadIdx.x, l = t & 63, w = t >> 6;
+    const int P = l & 15;
     const uint64_t p0 = uint64_t(blockIdx.x) * kTP;
-    {   // base normals: thread (P = t & 15, g = t >> 4) takes node pairs j = g, g + 16, ...
+    FwdFrags F;
+    load_w1(F, net.layer[0]);
+    load_w2(F, net.layer[0]);
+    train_masks(net, masks);
+    {   // base normals: thread (Pn = t % kTP, g = t / kTP) takes node pairs j = g, g + kG, ...
         double* bm = reinterpret_cast<double*>(hs);
         load_bm_table(bm, kBlock);
         __syncthreads();
         RngKey k = key;
         if (step) k.stream += uint32_t(*step);
-        const int P = t & 15, g = t >> 4;
-        const PathRng pr = path_rng(k, p0 + uint64_t(P));
+        const int Pn = t % kTP, g = t / kTP;
+        const PathRng pr = path_rng(k, p0 + uint64_t(Pn));
         double u2 = 0.0;
-        for (int j = g; 2 * j <= D; j += 16) {
+        for (int j = g; 2 * j <= D; j += kG) {
             double ze, zo;
             normal_pair(k, pr, uint32_t(j), bm, ze, zo);
             if (j > 0) {
-                X[(2 * j - 1) * kTP + P] = ze;
+                X[(2 * j - 1) * kTP + Pn] = ze;
                 u2 += ze * ze;
             }
             if (2 * j + 1 <= D) {
-                X[(2 * j) * kTP + P] = zo;
+                X[(2 * j) * kTP + Pn] = zo;
                 u2 += zo * zo;
             }
         }
-        red[g][P] = u2;
+        red[g][Pn] = u2;
     }
-    double ldet = 0.0;                               // this wave's share of log det of path l & 15
+    double ldet = 0.0;                               // this wave's share of log det of path P
     for (int c = 0; c < net.n_layers; ++c) {
         const FlowLayerDev& L = net.layer[c];
+        const FlowLayerDev& Ln = net.layer[c + 1 < net.n_layers ? c + 1 : c];
+        const int* am = masks + (c % 4) * 128;
         __syncthreads();                             // X complete; hs, xa free
         for (int i = t; i < D * kTP; i += kBlock) {
-            const uint64_t P = p0 + uint64_t(i % kTP);
-            if (P < n) Xg[uint64_t(c) * plane + uint64_t(i / kTP) * ld + P] = X[i];
+            const uint64_t Pi = p0 + uint64_t(i % kTP);
+            if (Pi < n) Xg[uint64_t(c) * plane + uint64_t(i / kTP) * ld + Pi] = X[i];
         }
-        train_xa(L, X, xa);
+        train_xa(L, am, X, xa);
         __syncthreads();
         floatx4 pre[2];
-        train_hidden(L, xa, hs, pre);
+        train_hidden(F, xa, hs, pre);
+        load_w1(F, Ln);
         __syncthreads();
         floatx4 os, ot;
-        train_output(L, hs, os, ot);
+        train_output(F, hs, os, ot);
+        load_w2(F, Ln);
         double v = 0.0;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int k = 16 * w + 4 * (l >> 4) + j;
             if (k < L.dB) {
-                const float sv = 2.0f * tanh_fast(0.5f * (os[j] + L.b2[k]));
-                const int a = L.Bidx[k] * kTP + (l & 15);
-                X[a] = X[a] * exp_logscale(double(sv)) + double(ot[j] + L.b2[64 + k]);
+                const float sv = 2.0f * tanh_fast(0.5f * os[j]);
+                const int a = am[64 + k] * kTP + P;
+                X[a] = X[a] * exp_logscale(double(sv)) + double(ot[j]);
                 v += double(sv);
             }
         }
@@ -204,74 +304,110 @@ __global__ void __launch_bounds__(kBlock) k_train_fwd(FlowNet net, RngKey key, c
     if (l < kTP) redl[w][l] = ldet;
     __syncthreads();
     for (int i = t; i < D * kTP; i += kBlock) {
-        const uint64_t P = p0 + uint64_t(i % kTP);
-        if (P < n) Xg[uint64_t(net.n_layers) * plane + uint64_t(i / kTP) * ld + P] = X[i];
+        const uint64_t Pi = p0 + uint64_t(i % kTP);
+        if (Pi < n) Xg[uint64_t(net.n_layers) * plane + uint64_t(i / kTP) * ld + Pi] = X[i];
     }
     if (t < kTP && p0 + t < n) {
         double u2 = 0.0, ld2 = 0.0;
-        for (int g = 0; g < kTP; ++g) u2 += red[g][t];
+        for (int g = 0; g < kG; ++g) u2 += red[g][t];
         for (int q = 0; q < 4; ++q) ld2 += redl[q][t];
         hu2[p0 + t] = 0.5 * u2;
         logdet[p0 + t] = ld2;
     }
 }
 
-// Backward through every layer, last first: G (d sum_i alpha_i l_i / d layer output, [h-1][path])
-// becomes the gradient for the layer input; the planes of TrainPlanes are written for k_flow_wgrad.
-__global__ void __launch_bounds__(kBlock) k_train_bwd(FlowNet net, const double* __restrict__ Xg, double* __restrict__ Gg,
+// Backward through every layer, last first: G = alpha_i d l_i / d z (the action gradient Gg scaled
+// by the path's loss weight as it is loaded) becomes the gradient for each layer's input; the planes
+// of TrainPlanes (leading dimension pl.ld) are written for the weight gradients.
+__global__ void __launch_bounds__(kBlock) k_train_bwd(FlowNet net, const double* __restrict__ Xg, const double* __restrict__ Gg,
                                                       uint64_t ld, uint64_t plane, uint64_t n, int D,
                                                       const double* __restrict__ alpha, TrainPlanes pl) {
     __shared__ double G[kFusedMaxD * kTP];
-    __shared__ double X[kFusedMaxD * kTP];
+    __shared__ double Xb[2][kFusedMaxD * kTP];
     __shared__ __attribute__((aligned(16))) __bf16 xa[kTP * kTLdA];
     __shared__ __attribute__((aligned(16))) __bf16 hs[kTP * kTLdH];
-    __shared__ float go[kTP * kTLdG];
-    __shared__ float gp[kTP * kTLdG];
+    __shared__ __attribute__((aligned(16))) float go[kTP * kTLdG];
+    __shared__ __attribute__((aligned(16))) float gp[kTP * kTLdG];
+    __shared__ int masks[4 * 128];
     const int t = threadIdx.x, l = t & 63, w = t >> 6;
     const int P = l & 15;
     const uint64_t p0 = uint64_t(blockIdx.x) * kTP;
     const bool valid = p0 + uint64_t(P) < n;
     const double al = valid ? alpha[p0 + P] : 0.0;
-    for (int i = t; i < D * kTP; i += kBlock) {
-        const uint64_t Pi = p0 + uint64_t(i % kTP);
-        G[i] = Pi < n ? Gg[uint64_t(i / kTP) * ld + Pi] : 0.0;
+    const uint64_t pld = pl.ld;
+    const int L0 = net.n_layers - 1;
+    FwdFrags F;
+    BwdFrags B;
+    load_w1(F, net.layer[L0]);
+    load_w2(F, net.layer[L0]);
+    load_w2t(B, net.layer[L0]);
+    load_w1t(B, net.layer[L0]);
+    train_masks(net, masks);
+    {   // thread t always takes path t % kTP of the tile (kBlock is a multiple of kTP)
+        static_assert(kBlock % kTP == 0, "tile columns per thread");
+        const uint64_t Pt = p0 + uint64_t(t % kTP);
+        const double at = Pt < n ? alpha[Pt] : 0.0;
+        double gv[kTileRegs], xv[kTileRegs];
+#pragma unroll
+        for (int it = 0; it < kTileRegs; ++it) {
+            const int i = t + it * kBlock;
+            const bool ok = i < D * kTP && Pt < n;
+            const uint64_t o = uint64_t(i / kTP) * ld + Pt;
+            gv[it] = ok ? Gg[o] : 0.0;
+            xv[it] = ok ? Xg[uint64_t(L0) * plane + o] : 0.0;
+        }
+#pragma unroll
+        for (int it = 0; it < kTileRegs; ++it) {
+            const int i = t + it * kBlock;
+            if (i < D * kTP) {
+                G[i] = gv[it] * at;
+                Xb[L0 & 1][i] = xv[it];
+            }
+        }
     }
-    for (int c = net.n_layers - 1; c >= 0; --c) {
+    for (int c = L0; c >= 0; --c) {
         const FlowLayerDev& L = net.layer[c];
+        const FlowLayerDev& Ln = net.layer[c > 0 ? c - 1 : 0];
+        const int* am = masks + (c % 4) * 128;
+        const double* X = Xb[c & 1];
         float* goT = pl.goT + uint64_t(c) * pl.g_stride;
         float* gpT = pl.gpT + uint64_t(c) * pl.g_stride;
         __bf16* hT = pl.hT + uint64_t(c) * pl.h_stride;
         __bf16* xaT = pl.xaT + uint64_t(c) * pl.xa_stride;
-        __syncthreads();                             // G complete; X, xa, hs, go, gp free
-        for (int i = t; i < D * kTP; i += kBlock) {
+        __syncthreads();                             // G and X_c complete; xa, hs, go, gp free
+        double xn[kTileRegs];                        // X_{c-1}, stored to the other buffer at the end
+#pragma unroll
+        for (int it = 0; it < kTileRegs; ++it) {
+            const int i = t + it * kBlock;
             const uint64_t Pi = p0 + uint64_t(i % kTP);
-            X[i] = Pi < n ? Xg[uint64_t(c) * plane + uint64_t(i / kTP) * ld + Pi] : 0.0;
+            xn[it] = c > 0 && i < D * kTP && Pi < n ? Xg[uint64_t(c - 1) * plane + uint64_t(i / kTP) * ld + Pi] : 0.0;
         }
-        __syncthreads();
-        train_xa(L, X, xa);
+        train_xa(L, am, X, xa);
         __syncthreads();
         for (int i = t; i < kTP * kFlowK; i += kBlock) {
             const int Pi = i % kTP, k = i / kTP;
-            if (p0 + uint64_t(Pi) < n) xaT[uint64_t(k) * ld + p0 + Pi] = xa[Pi * kTLdA + k];
+            if (p0 + uint64_t(Pi) < n) xaT[uint64_t(k) * pld + p0 + Pi] = xa[Pi * kTLdA + k];
         }
         floatx4 pre[2];
-        train_hidden(L, xa, hs, pre);
+        train_hidden(F, xa, hs, pre);
+        load_w1(F, Ln);
         __syncthreads();
         for (int i = t; i < kTP * kFlowH; i += kBlock) {
             const int Pi = i % kTP, k = i / kTP;
-            if (p0 + uint64_t(Pi) < n) hT[uint64_t(k) * ld + p0 + Pi] = hs[Pi * kTLdH + k];
+            if (p0 + uint64_t(Pi) < n) hT[uint64_t(k) * pld + p0 + Pi] = hs[Pi * kTLdH + k];
         }
         floatx4 os, ot;
-        train_output(L, hs, os, ot);
+        train_output(F, hs, os, ot);
+        load_w2(F, Ln);
         // affine backward of coordinate k of path P (this lane's slots)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int k = 16 * w + 4 * (l >> 4) + j;
             float gsh = 0.f, gt = 0.f;
             if (k < L.dB && valid) {
-                const float th = tanh_fast(0.5f * (os[j] + L.b2[k]));
+                const float th = tanh_fast(0.5f * os[j]);
                 const float sv = 2.0f * th;
-                const int a = L.Bidx[k] * kTP + P;
+                const int a = am[64 + k] * kTP + P;
                 const double es = exp_logscale(double(sv));
                 const double gy = G[a];
                 G[a] = gy * es;
@@ -282,94 +418,160 @@ __global__ void __launch_bounds__(kBlock) k_train_bwd(FlowNet net, const double*
             go[P * kTLdG + k] = gsh;
             go[P * kTLdG + 64 + k] = gt;
             if (valid) {
-                goT[uint64_t(k) * ld + p0 + P] = gsh;
-                goT[uint64_t(64 + k) * ld + p0 + P] = gt;
+                goT[uint64_t(k) * pld + p0 + P] = gsh;
+                goT[uint64_t(64 + k) * pld + p0 + P] = gt;
             }
         }
         __syncthreads();
-        // g_h = W2^T g_o (A = W2T [hid][out]), g_pre = g_h silu'(pre)
+        // g_h = W2^T g_o, g_pre = g_h silu'(pre)
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb) {
-            const int h0 = 32 * w + 16 * mb;
-            const floatx4 gh = mma16_f32_bf16A(L.W2T + h0 * kFlowH, kFlowH, go, kTLdG, kFlowH, floatx4{0.f, 0.f, 0.f, 0.f});
+            const floatx4 gh = fma16_f32(B.w2t[mb], go, kTLdG, floatx4{0.f, 0.f, 0.f, 0.f});
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int hid = h0 + 4 * (l >> 4) + j;
+                const int hid = 32 * w + 16 * mb + 4 * (l >> 4) + j;
                 const float v = pre[mb][j];
                 const float sg = sigmoid_fast(v);
                 const float g = valid ? gh[j] * (sg * (1.0f + v * (1.0f - sg))) : 0.f;
                 gp[P * kTLdG + hid] = g;
-                if (valid) gpT[uint64_t(hid) * ld + p0 + P] = g;
+                if (valid) gpT[uint64_t(hid) * pld + p0 + P] = g;
             }
         }
+        load_w2t(B, Ln);
         __syncthreads();
-        // g_xa = W1^T g_pre (A = W1T [in][hid]) into G of the conditioner coordinates
+        // g_xa = W1^T g_pre into G of the conditioner coordinates
         {
-            const floatx4 gx = mma16_f32_bf16A(L.W1T + (16 * w) * kFlowH, kFlowH, gp, kTLdG, kFlowH,
-                                               floatx4{0.f, 0.f, 0.f, 0.f});
+            const floatx4 gx = fma16_f32(B.w1t, gp, kTLdG, floatx4{0.f, 0.f, 0.f, 0.f});
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int k = 16 * w + 4 * (l >> 4) + j;
-                if (k < L.dA && valid) G[L.Aidx[k] * kTP + P] += double(gx[j]);
+                if (k < L.dA && valid) G[am[k] * kTP + P] += double(gx[j]);
+            }
+        }
+        load_w1t(B, Ln);
+        if (c > 0) {
+            double* Xn = Xb[(c - 1) & 1];            // last read by layer c + 1
+#pragma unroll
+            for (int it = 0; it < kTileRegs; ++it) {
+                const int i = t + it * kBlock;
+                if (i < D * kTP) Xn[i] = xn[it];
             }
         }
     }
 }
 
-// Parameter gradients of every layer from the planes: blockIdx.y < 64 a 16 x 16 block of g_W2
-// (rows out, columns hid), < 96 a block of g_W1 (rows hid, columns in), else 16 bias rows (b2 rows
-// 0..127, b1 rows 128..255). A weight block: wave w sums paths [w q, (w+1) q) on FP32 MFMA, then the
-// four partial blocks are added in wave order. A bias row: lane-strided sums in FP64, then a wave
-// butterfly. grad: [layer][kFlowNP] FP32.
-__global__ void __launch_bounds__(kBlock) k_flow_wgrad(TrainPlanes pl, uint64_t ld, uint64_t n, float* __restrict__ grad) {
-    __shared__ float part[4][256];
+// Parameter gradients from the planes (leading dimension pl.ld, a multiple of kWgChunk, zero beyond
+// the batch), split over batch slices and summed in a fixed order. k_flow_wgrad_part: grid (layer,
+// output block, slice); output block b < 16 is the 32 x 32 block (b / 4, b % 4) of g_W2 (rows out,
+// columns hid), b < 24 a block of g_W1 (rows hid, columns in); slice k takes the chunks of 128 paths
+// [k nc / S, (k+1) nc / S). The workgroup stages a chunk of its 32 A rows (FP32) and 32 B rows (bf16)
+// through LDS with 16-byte loads, the next chunk's loads in flight while the current one is
+// multiplied; wave w accumulates the 16 x 16 sub-block (w / 2, w % 2) on FP32 MFMA. The blocks of
+// column 0 also sum their A rows over the slice (FP64, fixed order): the b2 gradient from the output
+// gradient rows, b1 from the pre-activation rows. k_flow_wgrad_sum adds the slices in slice order.
+constexpr int kWgSlices = 8;                   // batch slices of the weight gradients (at most)
+constexpr int kWgChunk = 128;                  // paths staged per step
+constexpr int kWgLd = kWgChunk + 4;            // LDS row stride (floats)
+
+__device__ __forceinline__ void wg_load(const float* A, const __bf16* B, uint64_t ld, uint64_t kc, floatx4 (&ra)[4],
+                                        bf16x8 (&rb)[2]) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+        const int i = t + it * kBlock;                         // row i >> 5, 4 paths (i & 31)
+        ra[it] = *reinterpret_cast<const floatx4*>(A + uint64_t(i >> 5) * ld + kc + 4 * (i & 31));
+    }
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const int i = t + it * kBlock;                         // row i >> 4, 8 paths (i & 15)
+        rb[it] = *reinterpret_cast<const bf16x8*>(B + uint64_t(i >> 4) * ld + kc + 8 * (i & 15));
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_flow_wgrad_part(TrainPlanes pl, int slices, float* __restrict__ part) {
+    __shared__ __attribute__((aligned(16))) float As[32 * kWgLd];
+    __shared__ __attribute__((aligned(16))) float Bs[32 * kWgLd];
     const int t = threadIdx.x, l = t & 63, w = t >> 6;
-    const int c = blockIdx.x, b = blockIdx.y;
-    const float* goT = pl.goT + uint64_t(c) * pl.g_stride;
-    const float* gpT = pl.gpT + uint64_t(c) * pl.g_stride;
-    const __bf16* hT = pl.hT + uint64_t(c) * pl.h_stride;
-    const __bf16* xaT = pl.xaT + uint64_t(c) * pl.xa_stride;
-    float* gl = grad + uint64_t(c) * kFlowNP;
-    if (b < 96) {
-        const bool w2 = b < 64;
-        const int r0 = w2 ? 16 * (b / 8) : 16 * ((b - 64) / 4);
-        const int c0 = w2 ? 16 * (b % 8) : 16 * ((b - 64) % 4);
-        const float* A = (w2 ? goT : gpT) + uint64_t(r0 + (l & 15)) * ld;
-        const __bf16* B = (w2 ? hT : xaT) + uint64_t(c0 + (l & 15)) * ld;
-        const uint64_t q = ((n + 15) / 16) * 4;      // paths per wave, a multiple of 4
-        const uint64_t k0 = uint64_t(w) * q, k1 = k0 + q < n ? k0 + q : n;
-        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-        for (uint64_t k = k0; k < k1; k += 4) {
-            const uint64_t kk = k + uint64_t(l >> 4);
-            const float a = kk < k1 ? A[kk] : 0.f;
-            const float bv = kk < k1 ? float(B[kk]) : 0.f;
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc, 0, 0, 0);
+    const int c = blockIdx.x, b = blockIdx.y, sl = blockIdx.z;
+    const uint64_t ld = pl.ld;
+    const bool w2 = b < 16;
+    const int r0 = w2 ? 32 * (b / 4) : 32 * ((b - 16) / 2);
+    const int c0 = w2 ? 32 * (b % 4) : 32 * ((b - 16) % 2);
+    const bool bias = c0 == 0;
+    const float* A = (w2 ? pl.goT : pl.gpT) + uint64_t(c) * pl.g_stride + uint64_t(r0) * ld;
+    const __bf16* B = (w2 ? pl.hT + uint64_t(c) * pl.h_stride : pl.xaT + uint64_t(c) * pl.xa_stride) + uint64_t(c0) * ld;
+    const uint64_t nc = ld / kWgChunk;
+    const uint64_t q0 = uint64_t(sl) * nc / uint64_t(slices), q1 = uint64_t(sl + 1) * nc / uint64_t(slices);
+    const int wr = 16 * (w >> 1), wc = 16 * (w & 1);
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    double bsum = 0.0;                               // row t >> 3, paths 16 (t & 7) .. of each chunk
+    floatx4 ra[4];
+    bf16x8 rb[2];
+    if (q0 < q1) wg_load(A, B, ld, q0 * kWgChunk, ra, rb);
+    for (uint64_t q = q0; q < q1; ++q) {
+        __syncthreads();                             // the previous chunk's reads are done
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+            const int i = t + it * kBlock;
+            *reinterpret_cast<floatx4*>(As + (i >> 5) * kWgLd + 4 * (i & 31)) = ra[it];
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) part[w][(4 * (l >> 4) + j) * 16 + (l & 15)] = acc[j];
+        for (int it = 0; it < 2; ++it) {
+            const int i = t + it * kBlock;
+            float* d = Bs + (i >> 4) * kWgLd + 8 * (i & 15);
+            *reinterpret_cast<floatx4*>(d) = floatx4{float(rb[it][0]), float(rb[it][1]), float(rb[it][2]), float(rb[it][3])};
+            *reinterpret_cast<floatx4*>(d + 4) =
+                floatx4{float(rb[it][4]), float(rb[it][5]), float(rb[it][6]), float(rb[it][7])};
+        }
         __syncthreads();
-        const int r = t >> 4, col = t & 15;
-        const float v = ((part[0][t] + part[1][t]) + part[2][t]) + part[3][t];
-        if (w2)
-            gl[kFlowOffW2 + (r0 + r) * kFlowH + c0 + col] = v;
-        else
-            gl[(r0 + r) * kFlowK + c0 + col] = v;
-    } else {
-        const int rb = b - 96;
-        for (int i = 0; i < 4; ++i) {
-            const int row = 16 * rb + 4 * w + i;
-            const float* src = row < 128 ? goT + uint64_t(row) * ld : gpT + uint64_t(row - 128) * ld;
-            double sacc = 0.0;
-            for (uint64_t k = uint64_t(l); k < n; k += 64) sacc += double(src[k]);
-            sacc = wave_sum(sacc);
-            if (l == 0) {
-                if (row < 128)
-                    gl[kFlowOffB2 + row] = float(sacc);
-                else
-                    gl[kFlowOffB1 + row - 128] = float(sacc);
-            }
+        if (q + 1 < q1) wg_load(A, B, ld, (q + 1) * kWgChunk, ra, rb);
+        const float* ar = As + (wr + (l & 15)) * kWgLd + 8 * (l >> 4);
+        const float* br = Bs + (wc + (l & 15)) * kWgLd + 8 * (l >> 4);
+#pragma unroll
+        for (int kb = 0; kb < kWgChunk / 32; ++kb) {
+            const floatx4 a0 = *reinterpret_cast<const floatx4*>(ar + 32 * kb);
+            const floatx4 a1 = *reinterpret_cast<const floatx4*>(ar + 32 * kb + 4);
+            const floatx4 b0 = *reinterpret_cast<const floatx4*>(br + 32 * kb);
+            const floatx4 b1 = *reinterpret_cast<const floatx4*>(br + 32 * kb + 4);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[j], b0[j], acc, 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[j], b1[j], acc, 0, 0, 0);
+        }
+        if (bias) {
+            const float* rr = As + (t >> 3) * kWgLd + 16 * (t & 7);
+#pragma unroll
+            for (int j = 0; j < 16; ++j) bsum += double(rr[j]);
         }
     }
+    float* o = part + (uint64_t(sl) * gridDim.x + uint64_t(c)) * kFlowNP;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int r = r0 + wr + 4 * (l >> 4) + j, col = c0 + wc + (l & 15);
+        if (w2)
+            o[kFlowOffW2 + r * kFlowH + col] = acc[j];
+        else
+            o[r * kFlowK + col] = acc[j];
+    }
+    if (bias) {
+        bsum += __shfl_xor(bsum, 1, 64);
+        bsum += __shfl_xor(bsum, 2, 64);
+        bsum += __shfl_xor(bsum, 4, 64);
+        if ((t & 7) == 0) o[(w2 ? kFlowOffB2 : kFlowOffB1) + r0 + (t >> 3)] = float(bsum);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_flow_wgrad_sum(const float* __restrict__ part, int slices, uint64_t total,
+                                                           float* __restrict__ grad) {
+    const uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= total) return;
+    float v[kWgSlices];
+#pragma unroll
+    for (int k = 0; k < kWgSlices; ++k) v[k] = k < slices ? part[uint64_t(k) * total + i] : 0.f;
+    float s = v[0];
+#pragma unroll
+    for (int k = 1; k < kWgSlices; ++k) s += v[k];
+    grad[i] = s;
 }
 
 // ------------------------------------------------------------------------------------ action and its gradient
@@ -393,10 +595,25 @@ __global__ void __launch_bounds__(kBlock) k_flow_action_grad(const double* __res
     __shared__ double SA[kAgMaxN * kAgPaths];           // slice k: d/dq_k
     __shared__ double SB[kAgMaxN * kAgPaths];           // slice k: d/dq_{k+1}
     __shared__ double red[2][16][kAgPaths];
+    __shared__ double Z[(kAgMaxN - 1) * kAgPaths];      // the tile's normals z[(h-1)*16 + P]
     const int t = threadIdx.x, P = t & 15, g = t >> 4;
     const uint64_t path = uint64_t(blockIdx.x) * kAgPaths + uint64_t(P);
     const bool valid = path < n;
     const int N = 1 << s;
+    {   // every load of the tile in flight at once: thread t takes node h - 1 = g + 16 it of path P
+        constexpr int kRegs = (kAgMaxN - 1 + 15) / 16;
+        double zv[kRegs];
+#pragma unroll
+        for (int it = 0; it < kRegs; ++it) {
+            const int h1 = g + 16 * it;
+            zv[it] = valid && h1 < N - 1 ? X[uint64_t(h1) * ld + path] : 0.0;
+        }
+#pragma unroll
+        for (int it = 0; it < kRegs; ++it) {
+            const int h1 = g + 16 * it;
+            if (h1 < N - 1) Z[h1 * kAgPaths + P] = zv[it];
+        }
+    }
     if (g == 0) {
         Q[P] = a;
         Q[N * kAgPaths + P] = b;
@@ -406,7 +623,7 @@ __global__ void __launch_bounds__(kBlock) k_flow_action_grad(const double* __res
         const int step = 1 << (s - lev), cnt = 1 << (lev - 1);
         for (int i = g; i < cnt; i += 16) {
             const int h = cnt + i, pos = (2 * i + 1) * step;
-            const double z = valid ? X[uint64_t(h - 1) * ld + path] : 0.0;
+            const double z = Z[(h - 1) * kAgPaths + P];
             Q[pos * kAgPaths + P] = sig[lev] * z + 0.5 * (Q[(pos - step) * kAgPaths + P] + Q[(pos + step) * kAgPaths + P]);
         }
         __syncthreads();
@@ -448,10 +665,7 @@ __global__ void __launch_bounds__(kBlock) k_flow_action_grad(const double* __res
         const int step = 1 << (s - lev), cnt = 1 << (lev - 1);
         for (int i = g; i < cnt; i += 16) {
             const int h = cnt + i, pos = (2 * i + 1) * step;
-            if (valid) {
-                const double z = X[uint64_t(h - 1) * ld + path];
-                G[uint64_t(h - 1) * ld + path] = -sig[lev] * Q[pos * kAgPaths + P] - z;
-            }
+            if (valid) G[uint64_t(h - 1) * ld + path] = -sig[lev] * Q[pos * kAgPaths + P] - Z[(h - 1) * kAgPaths + P];
         }
         // the node points at this level depend on the two neighbouring coarser points
         for (int p2 = 2 * step * (1 + g); p2 < N; p2 += 2 * step * 16)
@@ -460,7 +674,7 @@ __global__ void __launch_bounds__(kBlock) k_flow_action_grad(const double* __res
         __syncthreads();
     }
     for (int h = 1 + g; h < N; h += 16) {
-        const double z = valid ? X[uint64_t(h - 1) * ld + path] : 0.0;
+        const double z = Z[(h - 1) * kAgPaths + P];
         z2p += z * z;
     }
     red[0][g][P] = Sp;
@@ -533,6 +747,7 @@ __global__ void __launch_bounds__(kBlock) k_flow_alpha(const double* __restrict_
     __shared__ double red[kBlock];
     const int t = threadIdx.x;
     double mx = -HUGE_VAL;
+#pragma unroll 16
     for (uint64_t i = t; i < n; i += kBlock) mx = fmax(mx, 2.0 * ell[i]);
     red[t] = mx;
     __syncthreads();
@@ -543,6 +758,7 @@ __global__ void __launch_bounds__(kBlock) k_flow_alpha(const double* __restrict_
     mx = red[0];
     __syncthreads();
     double se = 0.0, sl = 0.0;
+#pragma unroll 16
     for (uint64_t i = t; i < n; i += kBlock) {
         se += exp(2.0 * ell[i] - mx);
         sl += ell[i];
@@ -562,16 +778,10 @@ __global__ void __launch_bounds__(kBlock) k_flow_alpha(const double* __restrict_
         __syncthreads();
     }
     sl = red[0];
+#pragma unroll 16
     for (uint64_t i = t; i < n; i += kBlock)
         alpha[i] = (1.0 - beta) * 2.0 * exp(2.0 * ell[i] - mx) / se - beta / double(n);
     if (t == 0 && loss) loss[step ? *step : 0] = (1.0 - beta) * (mx + log(se / double(n))) - beta * sl / double(n);
-}
-
-__global__ void k_flow_seed(double* __restrict__ G, const double* __restrict__ alpha, int D, uint64_t ld, uint64_t n) {
-    const uint64_t g = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
-    if (g >= uint64_t(D) * n) return;
-    const uint64_t h = g / n, i = g % n;
-    G[h * ld + i] *= alpha[i];
 }
 
 // ------------------------------------------------------------------------------------ parameters
@@ -851,7 +1061,7 @@ hipError_t launch_train_fwd(const FlowNet& net, const RngKey& key, const int* st
     return hipGetLastError();
 }
 
-hipError_t launch_train_bwd(const FlowNet& net, const double* Xg, double* G, uint64_t ld, uint64_t plane, uint64_t n,
+hipError_t launch_train_bwd(const FlowNet& net, const double* Xg, const double* G, uint64_t ld, uint64_t plane, uint64_t n,
                             int D, const double* alpha, const TrainPlanes& planes, hipStream_t st) {
     const uint64_t tiles = (n + kTP - 1) / kTP;
     if (D > kFusedMaxD || tiles == 0 || tiles > 0x7fffffffull) return hipErrorInvalidValue;
@@ -860,12 +1070,24 @@ hipError_t launch_train_bwd(const FlowNet& net, const double* Xg, double* G, uin
     return hipGetLastError();
 }
 
-hipError_t launch_flow_wgrad(const TrainPlanes& planes, int layers, uint64_t ld, uint64_t n, float* grad,
-                             hipStream_t st) {
-    if (layers < 1 || layers > kFlowMaxLayers) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_flow_wgrad, dim3(uint32_t(layers), 96 + 16), dim3(kBlock), 0, st, planes, ld, n, grad);
+static int wgrad_slices(uint64_t ld) {
+    const uint64_t nc = ld / kWgChunk;
+    return int(nc < uint64_t(kWgSlices) ? nc : uint64_t(kWgSlices));
+}
+
+hipError_t launch_flow_wgrad(const TrainPlanes& planes, int layers, float* part, float* grad, hipStream_t st) {
+    if (layers < 1 || layers > kFlowMaxLayers || planes.ld == 0 || planes.ld % kWgChunk) return hipErrorInvalidValue;
+    const int slices = wgrad_slices(planes.ld);
+    hipLaunchKernelGGL(k_flow_wgrad_part, dim3(uint32_t(layers), 24, uint32_t(slices)), dim3(kBlock), 0, st, planes,
+                       slices, part);
+    const uint64_t total = uint64_t(layers) * kFlowNP;
+    hipLaunchKernelGGL(k_flow_wgrad_sum, dim3(uint32_t((total + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, part,
+                       slices, total, grad);
     return hipGetLastError();
 }
+
+size_t flow_wgrad_part_floats(int layers) { return size_t(kWgSlices) * size_t(layers) * kFlowNP; }
+uint64_t flow_plane_ld(uint64_t batch) { return (batch + kWgChunk - 1) / kWgChunk * kWgChunk; }
 
 hipError_t launch_flow_action_grad(const double* tab, const int* deg, int K, int even, const double* sig, double shift,
                                    double a, double b, int s, const double* X, uint64_t ld, uint64_t n,
@@ -899,11 +1121,6 @@ hipError_t launch_flow_fused(const FlowNet& net, const RngKey& key, uint64_t fir
 hipError_t launch_flow_alpha(const double* ell, uint64_t n, double beta, double* alpha, double* loss_out,
                              const int* step, hipStream_t st) {
     hipLaunchKernelGGL(k_flow_alpha, dim3(1), dim3(kBlock), 0, st, ell, n, beta, alpha, loss_out, step);
-    return hipGetLastError();
-}
-
-hipError_t launch_flow_seed(double* G, const double* alpha, int D, uint64_t ld, uint64_t n, hipStream_t st) {
-    hipLaunchKernelGGL(k_flow_seed, dim3(blocks_for(uint64_t(D) * n)), dim3(kBlock), 0, st, G, alpha, D, ld, n);
     return hipGetLastError();
 }
 

@@ -37,6 +37,7 @@ struct FlowLayerDev {
 // Every layer of a proposal, passed by value (kernel arguments: scalar loads).
 struct FlowNet {
     FlowLayerDev layer[kFlowMaxLayers];
+    const int* masks;      // [4][128]: the Aidx and Bidx arrays of the four layer types, zero-padded
     int n_layers;
 };
 
@@ -48,29 +49,34 @@ hipError_t launch_flow_fused(const FlowNet& net, const RngKey& key, uint64_t fir
                              double a, double b, double* ell, double* logdet, double* z, uint64_t zld,
                              hipStream_t st);
 
-// Per-layer gradient planes of the training backward (ld paths per row): output gradients
-// goT [128 out][ld] and pre-activation gradients gpT [128 hid][ld] in FP32, hidden activations
-// hT [128 hid][ld] and conditioner inputs xaT [64 in][ld] in bf16; layer c starts at c * *_stride.
+// Per-layer gradient planes of the training backward (ld paths per row, a multiple of 128 of at
+// least the batch, zero beyond the batch): output gradients goT [128 out][ld] and pre-activation
+// gradients gpT [128 hid][ld] in FP32, hidden activations hT [128 hid][ld] and conditioner inputs
+// xaT [64 in][ld] in bf16; layer c starts at c * *_stride.
 struct TrainPlanes {
     float* goT;
     float* gpT;
     __bf16* hT;
     __bf16* xaT;
+    uint64_t ld;
     uint64_t g_stride, h_stride, xa_stride;
 };
+// Leading dimension of the planes for a batch.
+uint64_t flow_plane_ld(uint64_t batch);
 
 // Training forward on tiles of 16 paths: base normals (the plain sampler's, stream key.stream +
 // *step when step is not null), every coupling; the input of layer c (c = 0..L, L = the output) in
 // the plane Xg + c * plane ([h-1][path], ld), |u|^2/2 and log det per path.
 hipError_t launch_train_fwd(const FlowNet& net, const RngKey& key, const int* step, uint64_t n, int D, double* Xg,
                             uint64_t ld, uint64_t plane, double* hu2, double* logdet, hipStream_t st);
-// Training backward, last layer first: G (the seeded gradient for the output, [h-1][path]) and
+// Training backward, last layer first, from G (d l / d z of the output, [h-1][path]; read only) and
 // alpha (per-path loss weights); writes the gradient planes for launch_flow_wgrad.
-hipError_t launch_train_bwd(const FlowNet& net, const double* Xg, double* G, uint64_t ld, uint64_t plane, uint64_t n,
-                            int D, const double* alpha, const TrainPlanes& planes, hipStream_t st);
-// Parameter gradients [layer][kFlowNP] (FP32) from the planes, in a fixed order.
-hipError_t launch_flow_wgrad(const TrainPlanes& planes, int layers, uint64_t ld, uint64_t n, float* grad,
-                             hipStream_t st);
+hipError_t launch_train_bwd(const FlowNet& net, const double* Xg, const double* G, uint64_t ld, uint64_t plane,
+                            uint64_t n, int D, const double* alpha, const TrainPlanes& planes, hipStream_t st);
+// Parameter gradients [layer][kFlowNP] (FP32) from the planes, in a fixed order; part: scratch of
+// flow_wgrad_part_floats(layers) floats (per-slice partial sums).
+hipError_t launch_flow_wgrad(const TrainPlanes& planes, int layers, float* part, float* grad, hipStream_t st);
+size_t flow_wgrad_part_floats(int layers);
 // Level-s action of the paths in X (N <= 128), log weights ell and G = d ell / dz.
 hipError_t launch_flow_action_grad(const double* tab, const int* deg, int K, int even, const double* sig, double shift,
                                    double a, double b, int s, const double* X, uint64_t ld, uint64_t n,
@@ -82,7 +88,6 @@ hipError_t launch_flow_partials(const double* ell, uint64_t ell_first_path, uint
                                 uint64_t n_chunks, double* partials, hipStream_t st);
 hipError_t launch_flow_alpha(const double* ell, uint64_t n, double beta, double* alpha, double* loss_out,
                              const int* step, hipStream_t st);
-hipError_t launch_flow_seed(double* G, const double* alpha, int D, uint64_t ld, uint64_t n, hipStream_t st);
 hipError_t launch_adam(float* theta, float* m, float* v, const float* grad, int layers, const int* step, float lr,
                        __bf16* W1, __bf16* W2, __bf16* W1T, __bf16* W2T, hipStream_t st);
 hipError_t launch_params_to_bf16(const float* theta, int layers, __bf16* W1, __bf16* W2, __bf16* W1T, __bf16* W2T,

@@ -39,6 +39,7 @@ struct pimc_flow {
     float* d_v = nullptr;
     float* d_grad = nullptr;
     void* d_planes = nullptr;            // gradient planes of the training backward (TrainPlanes)
+    float* d_wpart = nullptr;            // per-slice partial weight gradients
     TrainPlanes planes{};
     __bf16* d_W1 = nullptr;              // L * 128 * 64
     __bf16* d_W2 = nullptr;              // L * 128 * 128
@@ -140,9 +141,8 @@ hipError_t enqueue_grad(pimc_flow* f, const RngKey& key, const int* step, double
                                     P.shift[size_t(P.s)], P.a, P.b, P.s, f->d_X + size_t(f->L) * plane, B, B,
                                     f->d_hu2, f->d_logdet, f->d_ell, f->d_G, st);
     if (e == hipSuccess) e = launch_flow_alpha(f->d_ell, B, f->beta, f->d_alpha, loss, step, st);
-    if (e == hipSuccess) e = launch_flow_seed(f->d_G, f->d_alpha, f->D, B, B, st);
     if (e == hipSuccess) e = launch_train_bwd(f->net, f->d_X, f->d_G, B, plane, B, f->D, f->d_alpha, f->planes, st);
-    if (e == hipSuccess) e = launch_flow_wgrad(f->planes, f->L, B, B, f->d_grad, st);
+    if (e == hipSuccess) e = launch_flow_wgrad(f->planes, f->L, f->d_wpart, f->d_grad, st);
     return e;
 }
 
@@ -193,7 +193,7 @@ int reset_optimizer(pimc_flow* f) {
 
 void free_flow(pimc_flow* f) {
     destroy_graph(f);
-    void* ptrs[] = {f->d_sig, f->d_tab, f->d_deg, f->d_mask, f->d_theta, f->d_m, f->d_v, f->d_grad, f->d_planes,
+    void* ptrs[] = {f->d_sig, f->d_tab, f->d_deg, f->d_mask, f->d_theta, f->d_m, f->d_v, f->d_grad, f->d_planes, f->d_wpart,
                     f->d_W1, f->d_W2, f->d_W1T, f->d_W2T, f->d_step, f->d_X, f->d_G, f->d_hu2, f->d_logdet,
                     f->d_ell, f->d_alpha, f->d_loss, f->d_gloss, f->d_EX, f->d_Elogdet, f->d_Eell};
     for (void* p : ptrs)
@@ -289,19 +289,25 @@ int pimc_flow_create(pimc_ctx* c, const pimc_potential* V, double m, double a, d
     if ((st = dev_alloc(c, &f->d_m, np))) return fail(st);
     if ((st = dev_alloc(c, &f->d_v, np))) return fail(st);
     if ((st = dev_alloc(c, &f->d_grad, np))) return fail(st);
-    {   // gradient planes: goT, gpT (FP32) and hT (bf16), 128 rows each, and xaT (bf16), 64 rows, per layer
+    {   // gradient planes: goT, gpT (FP32) and hT (bf16), 128 rows each, and xaT (bf16), 64 rows, per
+        // layer; rows padded to a multiple of 128 paths and zeroed once (the padding is never written)
         const size_t L = size_t(f->L);
-        const size_t bytes = L * Bs * (128 * 4 + 128 * 4 + 128 * 2 + 64 * 2);
+        const size_t ldp = flow_plane_ld(Bs);
+        const size_t bytes = L * ldp * (128 * 4 + 128 * 4 + 128 * 2 + 64 * 2);
         unsigned char* base = nullptr;
         if ((st = dev_alloc(c, &base, bytes))) return fail(st);
         f->d_planes = base;
+        if (hipMemsetAsync(base, 0, bytes, c->stream) != hipSuccess)
+            return fail(ctx_fail(c, PIMC_EDEVICE, "clearing the gradient planes failed"));
         f->planes.goT = reinterpret_cast<float*>(base);
-        f->planes.gpT = f->planes.goT + L * 128 * Bs;
-        f->planes.hT = reinterpret_cast<__bf16*>(f->planes.gpT + L * 128 * Bs);
-        f->planes.xaT = f->planes.hT + L * 128 * Bs;
-        f->planes.g_stride = 128 * Bs;
-        f->planes.h_stride = 128 * Bs;
-        f->planes.xa_stride = 64 * Bs;
+        f->planes.gpT = f->planes.goT + L * 128 * ldp;
+        f->planes.hT = reinterpret_cast<__bf16*>(f->planes.gpT + L * 128 * ldp);
+        f->planes.xaT = f->planes.hT + L * 128 * ldp;
+        f->planes.ld = ldp;
+        f->planes.g_stride = 128 * ldp;
+        f->planes.h_stride = 128 * ldp;
+        f->planes.xa_stride = 64 * ldp;
+        if ((st = dev_alloc(c, &f->d_wpart, flow_wgrad_part_floats(f->L)))) return fail(st);
     }
     if ((st = dev_alloc(c, &f->d_W1, size_t(f->L) * kFlowH * kFlowK))) return fail(st);
     if ((st = dev_alloc(c, &f->d_W2, size_t(f->L) * kFlowH * kFlowH))) return fail(st);
@@ -347,6 +353,7 @@ int pimc_flow_create(pimc_ctx* c, const pimc_potential* V, double m, double a, d
         return fail(ctx_fail(c, PIMC_EDEVICE, "upload of the proposal's constants failed"));
     if ((st = reset_optimizer(f))) return fail(st);     // synchronizes: the host vectors may go
     f->net.n_layers = f->L;
+    f->net.masks = f->d_mask;
     for (int l = 0; l < f->L; ++l) f->net.layer[l] = layer_dev(f, l);
     *out = f;
     return PIMC_OK;

@@ -9,8 +9,12 @@ Tolerances, from the arithmetic:
   after 8 layers; the second happens for a few per cent of paths and moves them by up to ~1e-3.
   So: at least 95 % of paths within 1e-4 (a wrong index, mask, transpose or sign moves every path
   by O(1)), every path within 5e-2.
-* Gradients (sums over paths of the same quantities): relative L2 error per layer <= 2e-2 and
-  cosine >= 0.999 against the oracle's FP64 reverse mode on the same operands.
+* Gradients (sums over paths of the same quantities, FP32 backward): against the oracle's FP64
+  reverse mode on the same operands, each block of a layer (W1, b1, W2, b2) and the whole layer in
+  relative L2. The bounds are twice the worst measured over the cases below at N = 8, 16 and 128,
+  batches 200 and 4096 (measured worst: W1 2.7e-3, b1 2.0e-3, W2 2.0e-3, b2 7.4e-4, layer 2.0e-3,
+  1 - cosine 1.9e-6); the bf16 boundary crossings above set their size (a few 1e-3), and a wrong
+  bias row, transpose or path weight gives O(1).
 * Identity map (W2 = b2 = 0): s = t = 0 exactly, so log w is the plain estimator's -(S - S_ref)
   up to the FP64 action (relative 1e-12 of the action scale).
 """
@@ -28,6 +32,12 @@ from oracle import pimc as opimc
 pytestmark = pytest.mark.gpu
 
 QUARTIC = P.quartic(1.0, 10.0)
+# one layer's parameters (include/pimc.h): W1 [128][64], b1 [128], W2 [128][128], b2 [128]
+OFF_B1 = 128 * 64
+OFF_W2 = OFF_B1 + 128
+OFF_B2 = OFF_W2 + 128 * 128
+NP = P.binding.FLOW_NPARAM
+assert OFF_B2 + 128 == NP
 ODD = [0.0, 0.3, 0.5, 0.1, 0.05]
 
 
@@ -122,6 +132,9 @@ def test_identity_map_is_the_plain_estimator(ctx, case):
     f.close()
 
 
+GRAD_BOUNDS = {"W1": 5.5e-3, "b1": 4e-3, "W2": 4e-3, "b2": 1.5e-3}
+
+
 @pytest.mark.parametrize("beta", [0.0, 0.5])
 @pytest.mark.parametrize("case", [CASES[0], CASES[2], CASES[1]])
 def test_gradient_matches_oracle(ctx, case, beta):
@@ -139,13 +152,20 @@ def test_gradient_matches_oracle(ctx, case, beta):
                                                       shift, beta, quantize=True)
     _near(ell, l_ref)
     assert loss == pytest.approx(loss_ref, rel=1e-3, abs=1e-4)
+    blocks = {"W1": slice(0, OFF_B1), "b1": slice(OFF_B1, OFF_W2), "W2": slice(OFF_W2, OFF_B2), "b2": slice(OFF_B2, NP)}
     for c in range(L):
         gr = g_ref[c]
         gg = g[c].astype(np.float64)
         rel = np.linalg.norm(gg - gr) / np.linalg.norm(gr)
         cos = gg @ gr / (np.linalg.norm(gg) * np.linalg.norm(gr))
-        _log(f"  layer {c}: rel L2 {rel:.2e} cos {cos:.8f}")
-        assert rel <= 2e-2 and cos >= 0.999, (c, rel, cos)
+        per = {}
+        for name, sl in blocks.items():
+            d = np.linalg.norm(gr[sl])
+            per[name] = np.linalg.norm(gg[sl] - gr[sl]) / d if d > 0 else np.linalg.norm(gg[sl])
+        _log(f"  layer {c}: rel L2 {rel:.2e} cos {cos:.8f} " + " ".join(f"{k} {v:.2e}" for k, v in per.items()))
+        assert rel <= 4e-3 and cos >= 1.0 - 4e-6, (c, rel, cos)
+        for name, bound in GRAD_BOUNDS.items():
+            assert per[name] <= bound, (c, name, per[name])
     f.close()
 
 
