@@ -42,6 +42,7 @@ CPU_SAMPLE_PATHS = 24576         # per point, for the oracle timing (about 10-20
 C2 = dict(gs=(1.0, 10.0, 48.0), ps=(1, 2, 4, 8, 12, 18), Ts=(1.0, 2.0, 5.0), s=10, samples=100_000_000)
 C3_SAMPLES = 1_000_000           # samples per task of the batched grid (the configured size)
 C3_TUNE_SAMPLES = 10_000         # the same grid with fewer samples, for the autotuner
+C3_REPLAY_SAMPLES = 100_000      # samples per task of one graph replay (about 12 s of device time)
 # Precision workload: FP32 slice polynomials against FP64, g = 10, p = 18, N = 512, T = 1.
 PREC = dict(g=10.0, p=18, s=9, T=1.0, samples=1_000_000_000, oracle_paths=20_000)
 # Learned proposal: the anharmonic oscillator g = 10 at p = 12, N = 128, T = 2, a = 0, b = 1; 8 couplings,
@@ -67,6 +68,11 @@ KERNEL_SOURCES = ["pimc_device.hpp", "pimc_kernels_q64.hip", "pimc_walker.hpp", 
                   "pimc_math.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_amplitude_quartic64_p18_s10.json")
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_k_amplitude_quartic64_p18_s10.json")
+
+
+def _progress(msg):
+    """One line per finished step of the bench, on stderr (the JSON line is the only stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_source_hash() -> str:
@@ -579,10 +585,11 @@ def proposal_section(P, ctx, steps):
 
 
 def batched_section(P, ctx, samples, tune_samples):
-    """Batched grid: 2 systems x 3 T x 3 p x 128 x 128 endpoints, mixed N, one graph replay. The
-    autotuner picks a launch shape per kernel class (and the grid and grab) on the same grid with
-    tune_samples per task; the choice is cached and applied to the grid with `samples` per task,
-    which is replayed once."""
+    """Batched grid: 2 systems x 3 T x 3 p x 128 x 128 endpoints, mixed N. The autotuner picks a
+    launch shape per kernel class (and the grid and grab) on the same grid with tune_samples per
+    task; the choice is cached and applied to the grid with `samples` per task, run as graph replays
+    of at most C3_REPLAY_SAMPLES per task on disjoint streams and merged per task (equal counts: the
+    mean of the replay estimates, their errors added in quadrature)."""
     from paper_1105_0542_amd import workloads
     tune_path = os.path.join(os.environ.get("TMPDIR", "/tmp"), f"pimc_batch_tune_{os.getpid()}.txt")
     t0 = time.perf_counter()
@@ -597,15 +604,40 @@ def batched_section(P, ctx, samples, tune_samples):
     _, default_small_ms, _ = bt.run()
     bt.close()
     t_tune = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    systems, rows = workloads.evolution_matrix_tasks(samples=samples)
-    bt = P.Batch(ctx, systems, rows, seed=1, flags=0)
-    applied = bt.autotune(tune_path)                     # the cached choice: no timing
-    t_plan = time.perf_counter() - t0
-    out, ms, st = bt.run()
-    slices = sum(r[7] * r[5] for r in rows)
+    _progress(f"batched: autotuned in {t_tune:.1f} s")
+    n_tasks = len(rows_t)
+    replays = max(1, -(-samples // C3_REPLAY_SAMPLES))
+    per = -(-samples // replays)
+    amp_sum = err2 = None
+    n_tot = nonfinite = None
+    ms_total = t_plan = 0.0
+    st = 0
+    for r in range(replays):
+        t0 = time.perf_counter()
+        systems, rows = workloads.evolution_matrix_tasks(samples=per, stream_base=r * n_tasks)
+        bt = P.Batch(ctx, systems, rows, seed=1, flags=0)
+        applied = bt.autotune(tune_path)                 # the cached choice: no timing
+        t_plan += time.perf_counter() - t0
+        out, ms, st_r = bt.run()
+        bt.close()
+        st = st or st_r
+        ms_total += ms
+        lev = np.array([int(row[5]).bit_length() - 1 for row in rows])
+        res = out[np.arange(len(rows)), lev]
+        if amp_sum is None:
+            amp_sum, err2 = np.zeros(len(rows)), np.zeros(len(rows))
+            n_tot, nonfinite = np.zeros(len(rows), dtype=np.int64), np.zeros(len(rows), dtype=np.int64)
+        amp_sum += res["amp"]
+        err2 += res["err"] ** 2
+        n_tot += res["n"].astype(np.int64)
+        nonfinite += res["n_nonfinite"].astype(np.int64)
+        _progress(f"batched: replay {r + 1}/{replays} ({per} samples per task) {ms / 1e3:.1f} s")
+    amp = amp_sum / replays
+    err = np.sqrt(err2) / replays
+    rel = err / np.abs(amp)
+    slices = sum(row[7] * row[5] for row in rows) * replays
     # FP64 operations: per slice 2 (E_p - 1) for the Horner chains plus 6, as for the headline kernel
-    flops = sum(r[7] * r[5] * (2 * (E_TABLE[r[6]] - 1) + 6) for r in rows)
+    flops = sum(row[7] * row[5] * (2 * (E_TABLE[row[6]] - 1) + 6) for row in rows) * replays
     classes = [{"p": c["p"], "N": "16" if c["n16"] else "32..512", "tasks": c["n_tasks"],
                 "shape": {"subtree_levels": c["subtree_levels"], "block": c["block"],
                           "waves_per_eu": c["waves_per_eu"], "slice_batch": c["slice_batch"]},
@@ -613,16 +645,18 @@ def batched_section(P, ctx, samples, tune_samples):
                 "gain": c["default_ms"] / c["tuned_ms"] if c["tuned_ms"] > 0 else None} for c in tuned_classes]
     line = {
         "workload": "128x128 endpoint grid on [-4,4]^2, (A,g) in {(1,1),(-1,4)}, T in {0.5,1,2}, p in {8,12,18}, "
-                    f"N in 16..512 by a fixed hash, {samples} samples per task, level N only",
-        "tasks": len(rows), "samples_per_task": samples, "graph_ms": ms, "slice_evals_per_s": slices / (ms / 1e3),
-        "fp64_frac": flops / (ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
+                    f"N in 16..512 by a fixed hash, {per * replays} samples per task, level N only",
+        "tasks": n_tasks, "samples_per_task": per * replays, "replays": replays, "samples_per_replay": per,
+        "graph_ms": ms_total, "slice_evals_per_s": slices / (ms_total / 1e3),
+        "fp64_frac": flops / (ms_total / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
+        "rel_err_median": float(np.median(rel)), "rel_err_p99": float(np.quantile(rel, 0.99)),
+        "samples_counted": int(n_tot.sum()),
         "autotune": {"tuned_on_samples_per_task": tune_samples, "tune_s": t_tune, "grid_mult_x2": choice[0],
                      "grab": choice[1], "applied": list(applied), "classes": classes,
                      "graph_ms_tuned": tuned_small_ms, "graph_ms_default": default_small_ms},
-        "plan_s": t_plan, "tasks_with_nonfinite_weights": int((out["n_nonfinite"] > 0).sum()),
-        "nonfinite_weights": int(out["n_nonfinite"].sum()), "status": st,
+        "plan_s": t_plan, "tasks_with_nonfinite_weights": int((nonfinite > 0).sum()),
+        "nonfinite_weights": int(nonfinite.sum()), "status": st,
     }
-    bt.close()
     try:
         os.remove(tune_path)
     except OSError:
@@ -675,7 +709,11 @@ def main():
                 args.only_mpt or args.only_general or args.only_vector or args.only_batched or args.only_c2)
     C2["samples"] = args.c2_samples
     c2_refs = c2_references() if ((not skip_cpu or args.only_c2) and args.c2_samples > 0) else None
+    if c2_refs is not None:
+        _progress("convergence-sweep references done")
     cpu = None if skip_cpu else cpu_baseline(CPU_SAMPLE_PATHS)
+    if cpu is not None:
+        _progress(f"cpu baseline done ({cpu['value']:.3g} {cpu['unit']})")
     prec_ref = None if skip_cpu else oracle_precision_reference()
     spec_ref = None if (skip_cpu and not args.only_spectrum) else oracle_spectrum_reference()
     mpt_ref = None if (skip_cpu and not args.only_mpt) else oracle_mpt_reference()
@@ -686,6 +724,8 @@ def main():
         if (not skip_cpu or only) and not args.no_cpu_baseline:
             wanted.append(name)
     bases = oracle_section_baselines(wanted) if wanted else {}
+    if not skip_cpu:
+        _progress("oracle references and section baselines done")
 
     import paper_1105_0542_amd as P
 
@@ -743,6 +783,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
+    _progress(f"headline: {args.steps} timed steps in {wall:.2f} s")
     slices_step = len(POINTS) * args.samples * slices_per_sample(S_DEPTH, True)
     value = slices_step * args.steps / wall
     launches = args.steps * len(POINTS)
@@ -789,21 +830,25 @@ def main():
             "rel_diff_fp64_gpu": abs(small["fp64"] - prec_ref) / prec_ref,
             "rel_diff_fp32_gpu": abs(small["fp32"] - prec_ref) / prec_ref}
 
+    _progress("level-s-only and precision sections done")
     batch_line = (batched_section(P, ctx, args.batch_samples, args.batch_tune_samples)
                   if args.batch_samples > 0 else None)
     c2_line = c2_section(P, ctx, c2_refs) if args.c2_samples > 0 else None
-
+    _progress("convergence sweep done")
     flow_line = proposal_section(P, ctx, args.flow_steps) if args.flow_steps > 0 else None
+    _progress("proposal section done")
     spec_line = spectrum_section(P, ctx, spec_ref, bases.get("spectrum"))
     mpt_line = mpt_section(P, ctx, mpt_ref, bases.get("mpt"))
+    _progress("spectrum and Poeschl-Teller sections done")
     gen_line = general_section(P, ctx, bases.get("general"))
     vec_line = vector_section(P, ctx, vec_ref, bases.get("vector"))
+    _progress("general and vector sections done")
 
     counters = measured_counter_flops()
     roofline = {
         "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
         "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic(args.samples),
-        "kernel": "k_amplitude<Shape<5,256,2,16>, QuarticEval64<18>>", "kernel_avg_ms": kernel_avg_s * 1e3,
+        "kernel": "k_amplitude<Shape<4,256,2,16>, QuarticEval64<18>>", "kernel_avg_ms": kernel_avg_s * 1e3,
         "flop_per_slice": FLOP_PER_SLICE, "flop_per_launch": flop_per_launch,
     }
     if counters is not None:
@@ -880,7 +925,8 @@ def summarize(line):
                 out["precision"][k] = {kk: _r(vv) for kk, vv in v.items()}
     b = line.get("batched")
     if b:
-        out["batched"] = {"samples_per_task": b["samples_per_task"], "graph_s": _r(b["graph_ms"] / 1e3),
+        out["batched"] = {"samples_per_task": b["samples_per_task"], "replays": b.get("replays"),
+                          "graph_s": _r(b["graph_ms"] / 1e3), "rel_err_median": _r(b.get("rel_err_median")),
                           "slice_evals_per_s": _r(b["slice_evals_per_s"]), "fp64_frac": _r(b["fp64_frac"]),
                           "graph_ms_tuned_vs_default_small": [_r(b["autotune"]["graph_ms_tuned"]),
                                                               _r(b["autotune"]["graph_ms_default"])],

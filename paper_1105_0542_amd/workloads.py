@@ -31,10 +31,12 @@ def endpoint_grid(n: int = 128, lo: float = -4.0, hi: float = 4.0) -> List[float
 
 def evolution_matrix_tasks(n_grid: int = 128, samples: int = 10_000, seed: int = 1,
                            systems: Tuple[Tuple[float, float], ...] = ((1.0, 1.0), (-1.0, 4.0)),
-                           times=(0.5, 1.0, 2.0), levels=(8, 12, 18), s_choices=(4, 5, 6, 7, 8, 9)):
+                           times=(0.5, 1.0, 2.0), levels=(8, 12, 18), s_choices=(4, 5, 6, 7, 8, 9),
+                           stream_base: int = 0):
     """Batched grid: every (system, T, p, a_i, b_j), N = 2^s with s from a fixed hash of the task
     index (s = s_choices[splitmix64(seed*2^32 + j) mod len]). Returns (system coefficient lists,
-    task rows (system, m, a, b, T, N, p, samples, stream)); stream = task index."""
+    task rows (system, m, a, b, T, N, p, samples, stream)); stream = stream_base + task index, so
+    that runs with stream bases a task count apart draw disjoint samples."""
     xs = endpoint_grid(n_grid)
     sys_coefs = [quartic_coefs(A, g) for (A, g) in systems]
     rows = []
@@ -45,6 +47,6 @@ def evolution_matrix_tasks(n_grid: int = 128, samples: int = 10_000, seed: int =
                 for a in xs:
                     for b in xs:
                         s = s_choices[splitmix64(((seed & 0xFFFFFFFF) << 32) + j) % len(s_choices)]
-                        rows.append((si, 1.0, a, b, T, 1 << s, p, samples, j))
+                        rows.append((si, 1.0, a, b, T, 1 << s, p, samples, stream_base + j))
                         j += 1
     return sys_coefs, rows
