@@ -954,8 +954,12 @@ def summarize(line):
             slopes.setdefault(f"{g},{T}", {})[p.split("=")[1]] = _r(r.get("slope"), 3)
         out["c2"] = {"slice_evals_per_s": _r(c["slice_evals_per_s"]), "slopes": slopes,
                      "g0_max_abs_z": {p: _r(v["max_abs_z_vs_exact_discretized"], 3) for p, v in c["g0"].items()},
-                     "max_abs_z_N1024_vs_dvr": _r(max(abs(r["z_N1024"]) for r in c["points"].values()
-                                                      if r.get("z_N1024") is not None), 3)}
+                     "max_abs_z_N1024_vs_dvr": {}}
+        for key, r in c["points"].items():
+            if r.get("z_N1024") is not None:
+                p_key = key.split(",")[1].split("=")[1]
+                zmax = out["c2"]["max_abs_z_N1024_vs_dvr"]
+                zmax[p_key] = max(zmax.get(p_key, 0.0), _r(abs(r["z_N1024"]), 3))
     out["mpt"] = {p: {"rate": _r(r["slice_evals_per_s"]), "frac": _r(r["fp64_frac"])} for p, r in line["mpt"]["per_p"].items()}
     gq = line["general"]["quartic_g10_general_mode"]
     out["general"] = {"rate": _r(gq["slice_evals_per_s"]), "frac": _r(gq["roofline"]["frac"])}
