@@ -318,6 +318,9 @@ def mpt_section(P, ctx, dvr, base=None):
 # 36 fma for the derivatives of the polynomial (degree-8 rows), 15 + 1 level scalings, and mid-point,
 # deviation, its square and the accumulation (4).
 GENERAL_FLOP_PER_SLICE_P8 = 2 * 192 + 63 + 2 * 36 + 16 + 4
+# p = 18: the out-of-line evaluator's 24,195 fma and 6,185 multiplications (24,196 monomials), the
+# polynomial rows of the derivatives, the scaling of the 35 derivatives and the fixed slice work
+GENERAL_FLOP_PER_SLICE_P18 = 2 * 24195 + 6185 + 2 * 36 + 35 + 4
 
 
 def general_section(P, ctx, base=None):
@@ -346,7 +349,20 @@ def general_section(P, ctx, base=None):
     ms_b = ctx.last_kernel_ms()
     rows["gaussian_barrier"] = {"potential": "q^2/2 + 2 exp(-q^2), A(-0.3, 0.4; 1)",
                                 "slice_evals_per_s": sl / (ms_b / 1e3), "A_1024": res_b[s].amp, "err": res_b[s].err}
-    out = {"workload": f"p={p}, s={s} (every level), {n:.0e} samples", **rows}
+    # the paper's highest level for a general potential: 24,196 monomials per slice
+    n18 = 200_000
+    res_h, _ = ctx.amplitude_general(1.0, -0.3, 0.4, 1.0, 1 << s, 18, n18, 1, 0, P.FLAG_HIERARCHY, poly=(0, 0, 0.5),
+                                     gauss=((2.0, 1.0),))
+    ms_h = ctx.last_kernel_ms()
+    sl18 = n18 * slices_per_sample(s, True)
+    tf18 = sl18 * GENERAL_FLOP_PER_SLICE_P18 / (ms_h / 1e3) / 1e12
+    rows["gaussian_barrier_p18"] = {
+        "potential": "q^2/2 + 2 exp(-q^2), A(-0.3, 0.4; 1)", "p": 18, "samples": n18,
+        "slice_evals_per_s": sl18 / (ms_h / 1e3), "A_1024": res_h[s].amp, "err": res_h[s].err,
+        "diff_vs_p8_in_sigma": abs(res_h[s].amp - res_b[s].amp) / math.hypot(res_h[s].err, res_b[s].err),
+        "roofline": {"bound": "alu", "achieved": tf18, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": tf18 / FP64_PEAK_TFLOPS, "flop_per_slice": GENERAL_FLOP_PER_SLICE_P18}}
+    out = {"workload": f"p={p}, s={s} (every level), {n:.0e} samples; p=18 on {n18:.0e} samples", **rows}
     if base is not None:
         out["cpu_baseline"] = base
     return out
@@ -963,6 +979,10 @@ def summarize(line):
     out["mpt"] = {p: {"rate": _r(r["slice_evals_per_s"]), "frac": _r(r["fp64_frac"])} for p, r in line["mpt"]["per_p"].items()}
     gq = line["general"]["quartic_g10_general_mode"]
     out["general"] = {"rate": _r(gq["slice_evals_per_s"]), "frac": _r(gq["roofline"]["frac"])}
+    g18 = line["general"].get("gaussian_barrier_p18")
+    if g18:
+        out["general"]["p18"] = {"rate": _r(g18["slice_evals_per_s"]), "frac": _r(g18["roofline"]["frac"]),
+                                 "diff_vs_p8_sigma": _r(g18["diff_vs_p8_in_sigma"], 3)}
     out["vector"] = {d: {"rate": _r(r["slice_evals_per_s"]), "frac": _r(r["fp64_frac"])} for d, r in line["vector"]["per_dim"].items()}
     out["spectrum"] = [{"matrix_ms": _r(r["matrix_ms"]), "lanczos_ms_per_step": _r(r["lanczos_ms_per_step"]),
                         "max_abs_diff_vs_dvr": _r(r.get("max_abs_diff_vs_dvr"), 3)} for r in line["spectrum"]]

@@ -200,7 +200,7 @@ int pimc_level_table_mpt(const pimc_mpt *V, double m, double T, int p, uint32_t 
  *     V(q) = sum_{j <= degree} coef[j] q^j + sum_i A_i / cosh^2(alpha_i q) + sum_i B_i exp(-beta_i q^2)
  * (derivatives from closed-form recurrences). p in 1..PIMC_GEN_MAX_P, FP64 only; everything else
  * (mass rescaling, Philox/bisection, outputs, errors) as pimc_amplitude / pimc_path_actions. */
-#define PIMC_GEN_MAX_P 10
+#define PIMC_GEN_MAX_P 18
 #define PIMC_GEN_MAX_TERMS 4
 
 typedef struct {

@@ -182,13 +182,14 @@ def eps_W(p, eps, dfun, x, xbar):
     return total
 
 
-def path_actions(p, T, s, a, b, seed, stream, paths, poly=(), sech2=(), gauss=(), m=1.0):
-    """Per-path level actions (rows: paths, columns: n = 0..s) after the mass rescaling."""
+def path_actions(p, T, s, a, b, seed, stream, paths, poly=(), sech2=(), gauss=(), m=1.0, levels=None):
+    """Per-path level actions (rows: paths, columns: n = 0..s) after the mass rescaling; only the
+    columns in `levels` (default: every level) are computed, the others are left 0."""
     dfun = derivative_functions(p, poly, sech2, gauss, m)
     sm = math.sqrt(m)
     q = opimc.bisection_paths(a * sm, b * sm, T, s, seed, stream, paths)
     out = np.zeros((q.shape[0], s + 1))
-    for n in range(s + 1):
+    for n in (range(s + 1) if levels is None else levels):
         step = 1 << (s - n)
         qa = q[:, 0:-1:step]
         qb = q[:, step::step]

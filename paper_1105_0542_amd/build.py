@@ -25,9 +25,13 @@ HEADERS = ["pimc_tables.hpp", "pimc_device.hpp", "pimc_internal.hpp", "pimc_math
            "pimc_flow.hpp", "pimc_host_common.hpp", "pimc_spectrum.hpp", "pimc_general.hpp",
            "pimc_general_device.hpp", "pimc_vector.hpp", "pimc_vector_impl.hpp", "pimc_batch.hpp"]
 # Build-time generator of the general-potential evaluators: host C++ (the recursion of pimc_general.hpp)
-# that writes pimc_general_gen.hpp into the object directory.
+# that writes pimc_general_gen.hpp (levels 1..10) and pimc_general_gen_p<p>.hpp (p = 11..18) into the
+# object directory.
 CODEGEN = "pimc_gen_codegen.cpp"
 GENERATED = "pimc_general_gen.hpp"
+# One translation unit per out-of-line general-mode level: (source, defines, object name).
+GEN_HI_LEVELS = range(11, 19)
+VARIANTS = [("pimc_general_hi.hip", [f"-DPIMC_GEN_P={p}"], f"pimc_general_hi_p{p}") for p in GEN_HI_LEVELS]
 
 # -ffp-contract=off: every fused multiply-add in the kernels is written as fma(); no other
 # expression is contracted, so the arithmetic is exactly what the source states.
@@ -55,15 +59,17 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     gen_exe = os.path.join(objdir, "pimc_gen_codegen")
     subprocess.run(["g++", "-O2", "-std=c++17", "-Wall", "-I", CSRC, os.path.join(CSRC, CODEGEN), "-o", gen_exe],
                    check=True)
-    subprocess.run([gen_exe, os.path.join(objdir, GENERATED)], check=True)
+    subprocess.run([gen_exe, os.path.join(objdir, GENERATED), objdir], check=True)
     procs = []
     objs = []
-    for src in SOURCES:
-        obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
+    # the largest units first, so that they start before the small ones
+    units = [(v[0], v[1], v[2]) for v in reversed(VARIANTS)] + [(s, [], os.path.splitext(s)[0]) for s in SOURCES]
+    for src, defs, name in units:
+        obj = os.path.join(objdir, name + ".o")
         objs.append(obj)
-        cmd = [hipcc()] + HIP_FLAGS + inc + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc()] + HIP_FLAGS + defs + inc + ["-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
-            cmd = [hipcc(), "-x", "hip"] + HIP_FLAGS + inc + ["-c", os.path.join(CSRC, src), "-o", obj]
+            cmd = [hipcc(), "-x", "hip"] + HIP_FLAGS + defs + inc + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))

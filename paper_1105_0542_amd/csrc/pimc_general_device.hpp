@@ -5,6 +5,9 @@
 // eps W_p = sum_k zt^k sum c prod vt_f with zt = dlt^2 / (4 eps) by the straight-line code generated
 // for level p at build time (GenCompiled<p>, pimc_general_gen.hpp), whose coefficients c are
 // compile-time constants (the same at every level); the per-level scale factors are scalar loads.
+// Levels above kGenInlineMaxP (GenSliceEval) evaluate one slice per call of an out-of-line function
+// gen_slice_hi<p>, instantiated only in the translation unit that includes that level's generated
+// header (pimc_general_hi.hip), so that its straight-line code is emitted once per kernel.
 #pragma once
 
 #include "pimc_device.hpp"
@@ -97,6 +100,63 @@ struct GenCompiledEval {
             GenCompiled<P>::template eval<B>(v, z, acc);
 #pragma unroll
             for (int i = 0; i < B; ++i) S += acc[i];
+        }
+    }
+};
+
+// eps W_p of one slice (qa, qb) at the level whose scale factors are t[0..J+1] (p > kGenInlineMaxP).
+template <int P>
+__device__ __forceinline__ void gen_scaled_derivatives(const GenTables& g, const double* t, double qa, double qb,
+                                                       double (&v)[2 * P - 1], double& z) {
+    constexpr int J = 2 * P - 2;
+    const double x = 0.5 * (qa + qb);
+    const double dl = qb - qa;
+    gen_derivatives_dev<J>(g, x, v);
+#pragma unroll
+    for (int j = 0; j <= J; ++j) v[j] *= t[j];
+    z = dl * dl * t[J + 1];
+}
+
+template <int P>
+__device__ __noinline__ double gen_slice_hi(const GenTables g, const double* t, double qa, double qb) {
+    static_assert(GenCompiled<P>::J == 2 * P - 2, "generated evaluator of another level");
+    double v[2 * P - 1], z;
+    gen_scaled_derivatives<P>(g, t, qa, qb, v, z);
+    return GenCompiled<P>::eval1(v, z);
+}
+
+// Two slices per call, each formed exactly as gen_slice_hi forms it (the same bits): every
+// instruction of the long straight-line code then serves two slices.
+template <int P>
+__device__ __noinline__ void gen_slices2_hi(const GenTables g, const double* t, double qa0, double qb0, double qa1,
+                                            double qb1, double& r0, double& r1) {
+    double v0[2 * P - 1], v1[2 * P - 1], z0, z1;
+    gen_scaled_derivatives<P>(g, t, qa0, qb0, v0, z0);
+    gen_scaled_derivatives<P>(g, t, qa1, qb1, v1, z1);
+    GenCompiled<P>::eval2(v0, v1, z0, z1, r0, r1);
+}
+
+template <int P>
+struct GenSliceEval {
+    static constexpr int J = 2 * P - 2;
+    const double* __restrict__ tab;      // level-major, J + 2 per level: eps^(1 + j/2), j <= J, then 1/(4 eps)
+    GenTables g;
+    __device__ __forceinline__ void launder() { asm volatile("" : "+s"(tab)); }
+    template <int W>
+    __device__ __forceinline__ void eval(int level, const double (&qa)[W], const double (&qb)[W], double& S) const {
+        const int lv = __builtin_amdgcn_readfirstlane(level);
+        const double* t = tab + lv * (J + 2);
+        if constexpr (W == 1) {
+            S += gen_slice_hi<P>(g, t, qa[0], qb[0]);
+        } else {
+            static_assert(W % 2 == 0, "slices in pairs");
+#pragma unroll
+            for (int i = 0; i < W; i += 2) {
+                double r0, r1;
+                gen_slices2_hi<P>(g, t, qa[i], qb[i], qa[i + 1], qb[i + 1], r0, r1);
+                S += r0;
+                S += r1;
+            }
         }
     }
 };

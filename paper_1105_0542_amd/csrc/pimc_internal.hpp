@@ -95,6 +95,30 @@ int resident_tanh_fixed(int p, size_t lds_bytes, int device);
 hipError_t launch_general_compiled(const AmpArgs& A, int p, int U, int grid, hipStream_t st);
 int general_compiled_resident(int p, int U, size_t lds_bytes, int device);
 int general_compiled_nrec(int p);
+// The levels above kGenInlineMaxP, one translation unit each (pimc_general_hi.hip built with
+// PIMC_GEN_P = p): launch, resident workgroups per CU and monomial count of that level's evaluator.
+template <int P>
+hipError_t gen_hi_launch(const AmpArgs& A, int U, int grid, hipStream_t st);
+template <int P>
+int gen_hi_resident(int U, size_t lds_bytes, int device);
+template <int P>
+int gen_hi_nrec();
+#define PIMC_GEN_HI_DECLARE(P)                                                         \
+    template <>                                                                         \
+    hipError_t gen_hi_launch<P>(const AmpArgs& A, int U, int grid, hipStream_t st);    \
+    template <>                                                                         \
+    int gen_hi_resident<P>(int U, size_t lds_bytes, int device);                        \
+    template <>                                                                         \
+    int gen_hi_nrec<P>();
+PIMC_GEN_HI_DECLARE(11)
+PIMC_GEN_HI_DECLARE(12)
+PIMC_GEN_HI_DECLARE(13)
+PIMC_GEN_HI_DECLARE(14)
+PIMC_GEN_HI_DECLARE(15)
+PIMC_GEN_HI_DECLARE(16)
+PIMC_GEN_HI_DECLARE(17)
+PIMC_GEN_HI_DECLARE(18)
+#undef PIMC_GEN_HI_DECLARE
 
 // Raw standard normals of heap nodes 1..n_nodes for k_paths paths: out[path][node-1] (device).
 hipError_t launch_normals(const RngKey& key, uint64_t first_path, uint64_t k_paths, uint32_t n_nodes, double* out,

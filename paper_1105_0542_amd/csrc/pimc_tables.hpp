@@ -50,18 +50,23 @@ inline PolyD poly_mul(const PolyD& a, const PolyD& b) {
 }
 
 // General-potential mode: highest level p, derivative order and number of sech^2 / Gaussian terms.
-constexpr int kGenMaxP = 10;
+// Levels up to kGenInlineMaxP use evaluators inlined into the walker over several slices at once;
+// the higher ones (up to 24,196 monomials at p = 18) one out-of-line function per level that takes
+// one slice, so that each level's straight-line code exists once per kernel.
+constexpr int kGenMaxP = 18;
+constexpr int kGenInlineMaxP = 10;
 constexpr int kGenMaxJ = 2 * kGenMaxP - 2;
 constexpr int kGenMaxTerms = 4;
 // General mode, per level p: bisection levels of a subtree held in registers and slices evaluated
-// together by the generated code (for p >= 5: PIMC_GEN_U_HI, PIMC_GEN_B_HI).
+// together by the generated code (for 5 <= p <= kGenInlineMaxP: PIMC_GEN_U_HI, PIMC_GEN_B_HI; above,
+// subtrees of 3 levels whose slices go to the out-of-line evaluator in pairs).
 #ifndef PIMC_GEN_U_HI
 #define PIMC_GEN_U_HI 1
 #endif
 #ifndef PIMC_GEN_B_HI
 #define PIMC_GEN_B_HI 2
 #endif
-constexpr int gen_subtree_levels(int p) { return p <= 4 ? 2 : PIMC_GEN_U_HI; }
+constexpr int gen_subtree_levels(int p) { return p <= 4 ? 2 : p <= kGenInlineMaxP ? PIMC_GEN_U_HI : 3; }
 constexpr int gen_block_slices(int p) { return p <= 4 ? 4 : PIMC_GEN_B_HI; }
 static_assert(PIMC_GEN_U_HI >= 1 && PIMC_GEN_U_HI <= 4, "general-mode subtree levels");
 

@@ -18,12 +18,20 @@ def test_generated_evaluators_equal_direct_evaluation(tmp_path):
         pytest.skip("library not built")
     if shutil.which("g++") is None:
         pytest.skip("no host compiler")
-    exe = str(tmp_path / "check")
-    subprocess.run(["g++", "-O1", "-std=c++17", "-I", CSRC, "-I", BUILD,
-                    os.path.join(ROOT, "tests", "native", "check_general_codegen.cpp"), "-o", exe], check=True)
-    out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split()
-    errs = [float(x) for x in out]
-    assert len(errs) == 10
+    src = os.path.join(ROOT, "tests", "native", "check_general_codegen.cpp")
+    parts = [None] + list(range(11, 19))           # the inline levels 1..10, then each out-of-line level
+    procs = []
+    for lev in parts:
+        exe = str(tmp_path / f"check_{lev or 'inline'}")
+        defs = [] if lev is None else [f"-DCHECK_LEVEL={lev}"]
+        cmd = ["g++", "-O0", "-std=c++17", "-I", CSRC, "-I", BUILD] + defs + [src, "-o", exe]
+        procs.append((exe, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
+    errs = []
+    for exe, pr in procs:
+        out, _ = pr.communicate()
+        assert pr.returncode == 0, out
+        errs += [float(x) for x in subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split()]
+    assert len(errs) == 18
     assert max(errs) < 1e-14, errs
 
 
@@ -49,3 +57,25 @@ def test_general_flop_count_of_bench_matches_generated_code():
     import bench
     assert bench.GENERAL_FLOP_PER_SLICE_P8 == expected, (fma, mul, add)
     assert re.search(r"NREC = 193;", body)
+
+
+def test_general_flop_count_of_bench_matches_generated_code_p18():
+    """The same for the out-of-line evaluator of p = 18 (one slice, no loops over slices)."""
+    import sys
+    gen = os.path.join(BUILD, "pimc_general_gen_p18.hpp")
+    if not os.path.exists(gen):
+        pytest.skip("library not built")
+    src = open(gen).read()
+    body = src[src.index("struct GenCompiled<18>"):]
+    one = body[body.index("eval1("):body.index("eval2(")]     # the one-slice form
+    lines = [ln for ln in one.splitlines() if " = " in ln and not ln.strip().startswith(("static", "//", "const"))]
+    fma = sum(ln.count("fma(") for ln in lines)
+    mul = sum(ln.count(" * ") for ln in lines)
+    add = sum(ln.count(" + ") for ln in lines)
+    J = 34
+    poly = sum(8 - j for j in range(min(J, 8) + 1))
+    expected = 2 * fma + mul + add + 2 * poly + (J + 1) + 4
+    sys.path.insert(0, ROOT)
+    import bench
+    assert bench.GENERAL_FLOP_PER_SLICE_P18 == expected, (fma, mul, add)
+    assert "NREC = 24196;" in body

@@ -46,10 +46,10 @@ def test_polynomial_through_derivatives_equals_polynomial_mode(ctx, s, p, flags)
         _close(g[:, n], r[:, n])
 
 
-@pytest.mark.parametrize("p", range(1, 11))
+@pytest.mark.parametrize("p", range(1, 19))
 def test_every_generated_level_equals_polynomial_mode(ctx, p):
-    """Every evaluator generated at build time (p = 1..10), with one-level (U = 1) and deeper walks,
-    on a degree-8 polynomial with odd terms, against the polynomial tables."""
+    """Every evaluator generated at build time (p = 1..10 inline, 11..18 out of line), with one-level
+    (U = 1) and deeper walks, on a degree-8 polynomial with odd terms, against the polynomial tables."""
     coefs = [0.3, -0.2, 0.5, 0.1, 0.05, 0.0, 0.01, 0.0, 0.002]
     k = 512
     for s in (1, 3):
@@ -67,6 +67,21 @@ def test_sech2_through_derivatives_equals_poeschl_teller_mode(ctx):
         _close(g[:, n], r[:, n])
 
 
+@pytest.mark.parametrize("p", [12, 14, 18])
+def test_high_levels_sech2_equal_poeschl_teller_mode(ctx, p):
+    """The out-of-line evaluators on -lambda/cosh^2(alpha q) against the model-specific tanh ansatz
+    (an independent form of the same level-p action), at the levels where the series converges
+    well (eps = T/N <= 1/32)."""
+    k = 256
+    s = 5
+    _log(f"general p={p} sech2 vs Poeschl-Teller mode, N={1 << s}, {k} paths")
+    g = ctx.path_actions_general(1.3, -0.5, 0.5, 1.0, 1 << s, p, 9, 1, 0, 0, k, sech2=((-2.0, 1.2),))
+    r = ctx.path_actions_mpt(2.0, 1.2, 1.3, -0.5, 0.5, 1.0, 1 << s, p, 9, 1, 0, 0, k)
+    d = np.abs(g[:, s] - r[:, s]) / np.maximum(1.0, np.abs(r[:, s]))
+    _log(f"  max relative difference {d.max():.2e}")
+    _close(g[:, s], r[:, s])
+
+
 CASES = [  # m, a, b, T, s, p, poly, sech2, gauss
     (1.0, -0.3, 0.4, 1.0, 5, 6, (0, 0, 0.5), (), ((2.0, 1.0),)),                        # barrier in an oscillator
     (1.7, 0.2, -0.6, 0.5, 4, 8, (0.1, 0.2, 0.4, 0.0, 0.02), ((-1.0, 0.8),), ((0.5, 2.0), (-0.3, 0.5))),
@@ -74,6 +89,26 @@ CASES = [  # m, a, b, T, s, p, poly, sech2, gauss
      ((0.5, 2.0), (-0.3, 0.5), (0.2, 1.0), (0.1, 3.0))),
     (1.0, -9.0, 11.0, 1.0, 5, 5, (0, 0, 0.5), ((-1.0, 3.0),), ((2.0, 4.0),)),   # saturated tanh, tiny Gaussian
 ]
+
+
+CASES_HI = [  # m, a, b, T, s, p, poly, sech2, gauss: the out-of-line levels, level s only (eps = T/N)
+    (1.0, -0.3, 0.4, 0.5, 4, 12, (0, 0, 0.5), ((-1.0, 0.8),), ((2.0, 1.0),)),
+    (1.7, 0.2, -0.6, 0.5, 4, 14, (0.1, 0.2, 0.4, 0.0, 0.02), ((-1.0, 0.8),), ((0.5, 2.0), (-0.3, 0.5))),
+    (1.0, -0.3, 0.4, 0.5, 4, 18, (0, 0, 0.5), ((-1.0, 0.8),), ((2.0, 1.0),)),
+]
+
+
+@pytest.mark.parametrize("case", CASES_HI)
+def test_high_level_path_actions_match_oracle(ctx, case):
+    m, a, b, T, s, p, poly, sech2, gauss = case
+    _log(f"general actions (out of line) m={m} a={a} b={b} T={T} s={s} p={p} poly={poly} sech2={sech2} gauss={gauss}")
+    k = 128
+    got = ctx.path_actions_general(m, a, b, T, 1 << s, p, 3, 8, 0, 50, k, poly=poly, sech2=sech2, gauss=gauss)
+    ref = og.path_actions(p, T, s, a, b, 3, 8, np.arange(50, 50 + k), poly=poly, sech2=sech2, gauss=gauss, m=m,
+                          levels=[s])
+    d = np.abs(got[:, s] - ref[:, s]) / np.maximum(1.0, np.abs(ref[:, s]))
+    _log(f"  max relative difference {d.max():.2e}")
+    _close(got[:, s], ref[:, s])
 
 
 @pytest.mark.parametrize("case", CASES)
@@ -119,7 +154,7 @@ def test_gaussian_barrier_converges_to_the_continuum(ctx):
 
 def test_invalid_arguments(ctx):
     with pytest.raises(P.PimcError):
-        ctx.amplitude_general(1.0, 0, 1, 1, 16, 11, 100, 1, poly=(0, 0, 0.5))       # p > 10
+        ctx.amplitude_general(1.0, 0, 1, 1, 16, 19, 100, 1, poly=(0, 0, 0.5))       # p > 18
     with pytest.raises(P.PimcError):
         ctx.amplitude_general(1.0, 0, 1, 1, 16, 4, 100, 1, gauss=((1.0, -1.0),))     # beta <= 0
     with pytest.raises(P.PimcError) as e:
