@@ -182,6 +182,39 @@ def eps_W(p, eps, dfun, x, xbar):
     return total
 
 
+def eps_W_abs(p, eps, dfun, x, xbar):
+    """sum_{m,k} eps^(m-k+1) xbar^(2k) sum |monomial terms of c_{m,k}(v(x))|: the scale of the FP64
+    rounding error of eps_W (the same sum without cancellation between terms)."""
+    x = np.asarray(x, dtype=np.float64)
+    xb2 = np.asarray(xbar, dtype=np.float64) ** 2
+    v = [np.broadcast_to(np.asarray(f(x), dtype=np.float64), x.shape) for f in dfun]
+    total = np.zeros(np.broadcast(x, xb2).shape)
+    for (m, k), terms in coefficients(p):
+        val = np.zeros_like(total)
+        for mono, coef in terms:
+            t = np.full_like(total, abs(float(coef)))
+            for j, e in enumerate(mono):
+                if e:
+                    t = t * np.abs(v[j]) ** e
+            val = val + t
+        total = total + float(Fraction(eps) ** (m - k + 1)) * xb2 ** k * val
+    return total
+
+
+def path_action_scales(p, T, s, a, b, seed, stream, paths, poly=(), sech2=(), gauss=(), m=1.0, levels=None):
+    """Per path and level the sum over slices of eps_W_abs (the error scale of path_actions)."""
+    dfun = derivative_functions(p, poly, sech2, gauss, m)
+    sm = math.sqrt(m)
+    q = opimc.bisection_paths(a * sm, b * sm, T, s, seed, stream, paths)
+    out = np.zeros((q.shape[0], s + 1))
+    for n in (range(s + 1) if levels is None else levels):
+        step = 1 << (s - n)
+        qa = q[:, 0:-1:step]
+        qb = q[:, step::step]
+        out[:, n] = eps_W_abs(p, T / (1 << n), dfun, 0.5 * (qa + qb), 0.5 * (qb - qa)).sum(axis=1)
+    return out
+
+
 def path_actions(p, T, s, a, b, seed, stream, paths, poly=(), sech2=(), gauss=(), m=1.0, levels=None):
     """Per-path level actions (rows: paths, columns: n = 0..s) after the mass rescaling; only the
     columns in `levels` (default: every level) are computed, the others are left 0."""

@@ -1,10 +1,13 @@
 """GPU parity of the general-potential mode (derivative symbols) against the model-specific modes,
 the oracle (oracle/general.py, symbolic derivatives) and a DVR continuum reference.
 
-Tolerances: per-path level actions 1e-11 of max(1, |S|) -- the monomial sums of the derivative
+Tolerances: per-path level actions 1e-12 of max(1, |S|) -- the monomial sums of the derivative
 form and the folded tables of the model-specific forms are different FP64 evaluations of the same
-polynomial (cancellations between monomials cost a few digits more than Horner); amplitudes on
-identical samples 1e-9 relative; the continuum check within 5 MC standard errors.
+polynomial (the largest difference measured over these cases is logged by each test). Against the
+oracle, whose derivatives come from other formulas (symbolic differentiation), 1e-12 of the sum of
+the absolute monomial terms, the scale of the rounding error where terms cancel (at the coarse
+levels of paths far from the origin that sum is up to 80 times |S|). Amplitudes on identical
+samples 1e-10 relative; the continuum check within 5 MC standard errors.
 """
 import sys
 
@@ -30,9 +33,13 @@ def ctx():
     c.close()
 
 
-def _close(got, ref, tol=1e-11):
+def _close(got, ref, tol=1e-12, scale=None):
+    """|got - ref| <= tol * max(1, scale), scale = |ref| or the sum of the absolute monomial terms
+    (oracle path_action_scales) where the terms cancel."""
     err = np.abs(got - ref)
-    lim = tol * np.maximum(1.0, np.abs(ref))
+    sc = np.maximum(1.0, np.abs(ref) if scale is None else scale)
+    lim = tol * sc
+    _log(f"  max |diff| / max(1, scale) = {(err / sc).max():.2e}")
     assert np.all(err <= lim), (err / lim).max()
 
 
@@ -119,8 +126,10 @@ def test_path_actions_match_oracle(ctx, case):
     got = ctx.path_actions_general(m, a, b, T, 1 << s, p, 3, 8, P.FLAG_HIERARCHY, 50, k, poly=poly, sech2=sech2,
                                    gauss=gauss)
     ref = og.path_actions(p, T, s, a, b, 3, 8, np.arange(50, 50 + k), poly=poly, sech2=sech2, gauss=gauss, m=m)
+    scale = og.path_action_scales(p, T, s, a, b, 3, 8, np.arange(50, 50 + k), poly=poly, sech2=sech2, gauss=gauss,
+                                  m=m)
     for n in range(1, s + 1):
-        _close(got[:, n], ref[:, n])
+        _close(got[:, n], ref[:, n], scale=scale[:, n])
 
 
 def test_amplitude_matches_oracle_on_identical_samples(ctx):
@@ -138,7 +147,7 @@ def test_amplitude_matches_oracle_on_identical_samples(ctx):
         w = np.expm1(-(S[:, lev] - ref_line))
         K0 = math.exp(-(b - a) ** 2 / (2 * T)) / math.sqrt(2 * math.pi * T)
         amp = K0 * math.exp(-ref_line) * (1 + math.fsum(w) / n)
-        assert res[lev].amp == pytest.approx(amp, rel=1e-9), lev
+        assert res[lev].amp == pytest.approx(amp, rel=1e-10), lev
 
 
 def test_gaussian_barrier_converges_to_the_continuum(ctx):

@@ -136,3 +136,18 @@ def test_gaussian_barrier_high_level_reaches_the_continuum():
     """At p = 8 and N = 16 the discretized amplitude equals the continuum to ~1e-12."""
     exact = _barrier_continuum()
     assert abs(_barrier_amplitude(8, 16) - exact) < 1e-11 * exact
+
+
+def test_error_scale_bounds_the_action():
+    """eps_W_abs (the sum of the absolute monomial terms, the error scale of the GPU comparisons) is
+    at least |eps_W| everywhere, and equals eps_W where there is a single non-negative term (p = 1:
+    eps V(x) for V >= 0)."""
+    x = np.linspace(-3.0, 3.0, 41)
+    xb = np.linspace(-0.4, 0.5, 41)
+    d = og.derivative_functions(P_LEVEL, poly=(0.0, 0.3, 0.5), sech2=((-1.5, 0.8),), gauss=((2.0, 1.0),))
+    w = og.eps_W(P_LEVEL, 0.3, d, x, xb)
+    wa = og.eps_W_abs(P_LEVEL, 0.3, d, x, xb)
+    assert np.all(wa >= np.abs(w) * (1 - 1e-14))
+    assert np.any(wa > 1.01 * np.abs(w))                 # terms of both signs somewhere
+    d1 = og.derivative_functions(1, poly=(0.0, 0.0, 0.5), gauss=((2.0, 1.0),))
+    assert np.allclose(og.eps_W_abs(1, 0.3, d1, x, xb), og.eps_W(1, 0.3, d1, x, xb), rtol=1e-15, atol=0)
