@@ -27,7 +27,7 @@ namespace pimc {
 constexpr int kVecMaxDim = 3;
 constexpr int kVecBlock = 256;          // lanes of a workgroup
 #ifndef PIMC_VEC_U
-#define PIMC_VEC_U 4
+#define PIMC_VEC_U 3
 #endif
 #ifndef PIMC_VEC_BATCH
 #define PIMC_VEC_BATCH 8
