@@ -489,10 +489,65 @@ def _slope_fit(levels, ref, p):
     return -k, [1 << run[0], 1 << run[-1]], len(run)
 
 
+C2_PAIR_PATHS = 1 << 18     # paths whose per-path level actions give the paired differences' spread
+
+
+def _pair_slope(P, ctx, g, T, p, stream, res):
+    """Convergence order from the paired differences A_N - A_2N of one hierarchical run (both levels
+    from the same samples, so most of the Monte Carlo noise cancels): the differences from the
+    full run, their standard errors from the spread of w_N - w_2N (w = K_0 e^{-S}, the per-path
+    weights) over the first C2_PAIR_PATHS paths of the same stream; least squares of log|A_N - A_2N|
+    on log N over the longest run of consecutive levels that ends at the finest level whose
+    difference exceeds 3 standard errors, within which every difference exceeds 3 standard errors,
+    has the same sign and is smaller than the one before, then without the coarse levels whose
+    local order departs by more than 1 from the median local order of the finer ones (the
+    asymptotic regime); at least 3 levels, else no slope. Returns (slope, N range, points)."""
+    s = C2["s"]
+    S = ctx.path_actions(P.quartic(1.0, g), 1.0, 0.0, 1.0, T, 1 << s, p, 1, stream, P.FLAG_HIERARCHY, 0, C2_PAIR_PATHS)
+    K0 = math.exp(-1.0 / (2.0 * T)) / math.sqrt(2.0 * math.pi * T)
+    with np.errstate(over="ignore", invalid="ignore"):
+        w = K0 * np.exp(-S)
+    n_all = C2["samples"]
+    sig = []
+    np_err = np.seterr(over="ignore", invalid="ignore")
+    for n in range(1, s):
+        dw = w[:, n] - w[:, n + 1]
+        if not np.all(np.isfinite(dw)):
+            continue
+        se = float(np.std(dw, ddof=1)) / math.sqrt(n_all)
+        diff = res[n].amp - res[n + 1].amp
+        if math.isfinite(diff) and math.isfinite(se) and se > 0 and abs(diff) > 3 * se:
+            sig.append((n, diff))
+    np.seterr(**np_err)
+    if not sig:
+        return None, [], 0
+    run = [sig[-1]]
+    for item in reversed(sig[:-1]):
+        prev = run[-1]
+        if item[0] == prev[0] - 1 and (item[1] > 0) == (prev[1] > 0) and abs(item[1]) > abs(prev[1]):
+            run.append(item)
+        else:
+            break
+    run = sorted(run)
+    # the asymptotic regime: drop coarse levels while their local order (log2 of the ratio of
+    # successive differences) is more than 1 away from the median local order of the finer ones
+    while len(run) >= 3:
+        loc = [math.log2(abs(run[i][1]) / abs(run[i + 1][1])) for i in range(len(run) - 1)]
+        if abs(loc[0] - float(np.median(loc[1:]))) <= 1.0:
+            break
+        run = run[1:]
+    if len(run) < 3:
+        return None, [], len(run)
+    x = np.array([n * math.log(2.0) for n, _ in run])
+    y = np.array([math.log(abs(d)) for _, d in run])
+    return -float(np.polyfit(x, y, 1)[0]), [1 << run[0][0], 1 << run[-1][0]], len(run)
+
+
 def c2_section(P, ctx, refs):
     """Every point of the convergence sweep on the GPU: A_N^(p) for N = 1..1024 from one s = 10 run
-    per (g, p, T) (1e8 samples), the 1/N^p order fitted against the DVR continuum, the eq.(fit)
-    extrapolation, and g = 0 against the exact discretized amplitude and the Mehler kernel."""
+    per (g, p, T) (1e8 samples), the 1/N^p order fitted against the DVR continuum and from the paired
+    differences A_N - A_2N, the eq.(fit) extrapolation, and g = 0 against the exact discretized
+    amplitude and the Mehler kernel."""
     C = C2
     s = C["s"]
     rows = {}
@@ -509,6 +564,8 @@ def c2_section(P, ctx, refs):
                 tot_s += ms / 1e3
                 row = {"A_N": [r.amp for r in res], "err_N": [r.err for r in res], "status": st,
                        "nonfinite": [int(r.n_nonfinite) for r in res], "kernel_ms": ms}
+                ps_, pr_, pn_ = _pair_slope(P, ctx, g, T, p, stream, res)
+                row.update({"pair_slope": ps_, "pair_N_range": pr_, "pair_points": pn_})
                 if A_cont is not None:
                     slope, nrange, npts = _slope_fit(list(enumerate(res)), A_cont, p)
                     A, dA = _fit_continuum([(n, r) for n, r in enumerate(res) if math.isfinite(r.err)], p)
@@ -965,10 +1022,12 @@ def summarize(line):
     c = line.get("c2")
     if c:
         slopes = {}
+        pair = {}
         for key, r in c["points"].items():
             g, p, T = key.split(",")
             slopes.setdefault(f"{g},{T}", {})[p.split("=")[1]] = _r(r.get("slope"), 3)
-        out["c2"] = {"slice_evals_per_s": _r(c["slice_evals_per_s"]), "slopes": slopes,
+            pair.setdefault(f"{g},{T}", {})[p.split("=")[1]] = _r(r.get("pair_slope"), 3)
+        out["c2"] = {"slice_evals_per_s": _r(c["slice_evals_per_s"]), "slopes": slopes, "pair_slopes": pair,
                      "g0_max_abs_z": {p: _r(v["max_abs_z_vs_exact_discretized"], 3) for p, v in c["g0"].items()},
                      "max_abs_z_N1024_vs_dvr": {}}
         for key, r in c["points"].items():
