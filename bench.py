@@ -438,7 +438,8 @@ def _host_cpus():
 
 def cpu_baseline(paths_per_point: int):
     """The oracle as it stands, on the host cores: level actions of the first paths of each point.
-    `cores` is the number of worker processes actually used (at most 16, the GPU box's CPU share);
+    `cores` is the number of worker processes actually used (at most 16, the host's CPU share for one
+    GPU);
     the host's own counts are reported beside it."""
     import multiprocessing as mp
     cores = min(len(os.sched_getaffinity(0)), 16)
