@@ -60,6 +60,17 @@ SPEC_N, SPEC_P, SPEC_K = 16384, 21, 10
 VECTOR = dict(g=10.0, T=1.0, s=10, p=18, samples=100_000_000,
               ends={2: ((0.0, 0.0), (1.0, 0.4)), 3: ((0.0, 0.0, 0.0), (1.0, 0.4, -0.2))})
 RADIAL_E = {18: 102}                     # coefficients of the (u, z, w^2) table at p = 18
+# Any polynomial V (component route): two particles on a line with a quartic pair interaction
+# 0.1 (q1 - q2)^4 in an anisotropic trap with a field (d = 2, p = 10), and an anisotropic 3D trap with
+# cubic and quartic couplings (d = 3, p = 8); one s = 10 run each (every level).
+COMPONENT = dict(T=1.0, s=10, samples=10_000_000, cases=[
+    dict(name="pair (q1-q2)^4 + trap, d=2", dim=2, p=10, a=(0.0, 0.0), b=(1.0, 0.4),
+         terms=[(0.5, (2, 0)), (0.7, (0, 2)), (0.1, (4, 0)), (-0.4, (3, 1)), (0.6, (2, 2)), (-0.4, (1, 3)),
+                (0.1, (0, 4)), (0.3, (1, 0)), (0.2, (1, 1))]),
+    dict(name="anisotropic 3D trap, cubic + quartic couplings", dim=3, p=8, a=(0.0, 0.0, 0.0), b=(1.0, 0.4, -0.2),
+         terms=[(0.5, (2, 0, 0)), (0.4, (0, 2, 0)), (0.3, (0, 0, 2)), (0.2, (0, 2, 1)), (0.05, (1, 1, 2)),
+                (0.05, (0, 0, 4)), (0.1, (2, 2, 0)), (0.1, (0, 0, 1))]),
+])
 HBM_PEAK_GBS = 8000.0
 # Modified Poeschl-Teller potential (the paper's Fig. 2): V = -lambda/cosh^2(alpha q), lambda = alpha = 1,
 # A_N^(p)(-0.5, 0.5; 1) for p in {1, 2, 10} from one s = 10 run each (every N = 2^0..2^10).
@@ -392,7 +403,30 @@ def vector_section(P, ctx, dvr, base=None):
         if base is not None:
             row["cpu_baseline"] = base[str(dim)]
         out["per_dim"][str(dim)] = row
+    out["component"] = component_rows(P, ctx)
     return out
+
+
+def component_rows(P, ctx):
+    """Any polynomial V through the component evaluator: the rate, and the FP64 fraction counting one
+    FMA (2 flops) per monomial of eps W_p, the least any Horner scheme over the monomials does."""
+    C = COMPONENT
+    rows = []
+    for case in C["cases"]:
+        args = (case["terms"], case["dim"], 1.0, case["a"], case["b"], C["T"], 1 << C["s"], case["p"])
+        ctx.amplitude_poly(*args, 1 << 20, 1, 0, P.FLAG_HIERARCHY)
+        res, st = ctx.amplitude_poly(*args, C["samples"], 1, 0, P.FLAG_HIERARCHY)
+        ms = ctx.last_kernel_ms()
+        rate = C["samples"] * slices_per_sample(C["s"], True) / (ms / 1e3)
+        coef, _ = P.level_table_poly(case["terms"], case["dim"], 1.0, C["T"], case["p"], C["s"])
+        flop = 2 * coef.size
+        rows.append({"workload": f"{case['name']}, p={case['p']}, s={C['s']} (every level), T={C['T']:g}, "
+                                 f"{C['samples']:.0e} samples", "status": st,
+                     "A_N": [r.amp for r in res], "err_N": [r.err for r in res], "kernel_ms": ms,
+                     "slice_evals_per_s": rate, "monomials": int(coef.size), "flop_per_slice": flop,
+                     "fp64_frac": rate * flop / 1e12 / FP64_PEAK_TFLOPS})
+        _progress(f"component {case['name']}: {rate:.3e} slice-evals/s")
+    return rows
 
 
 def spectrum_section(P, ctx, dvr, base=None):

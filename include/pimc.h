@@ -259,6 +259,45 @@ int pimc_level_table_radial(const pimc_radial_potential *V, double m, double T, 
                             double *out, size_t cap, size_t *n_out, int *shape, size_t shape_cap,
                             int *n_groups);
 
+/* ---- several coordinates: any polynomial potential (Sec. 2.2) ---------------------------------
+ *
+ * The same as the radial entry points for a potential without rotational symmetry (anisotropic
+ * traps, pair interactions such as (q_1 - q_2)^4 of two particles on a line):
+ *     V(q) = sum_t coef[t] q_1^exps[t][0] q_2^exps[t][1] q_3^exps[t][2],   q in R^dim
+ * (exponents of coordinates beyond dim must be 0). eq.(MBrec) and eq.(DIA) run on polynomials in
+ * the 2 dim components of x and xbar (FP64); each level's eps W_p is a polynomial in those
+ * components, evaluated by a multivariate Horner scheme over the prefix tree of its monomials.
+ * Paths, mass rescaling (coef[t] times m^(-total degree / 2)), outputs, flags and errors as
+ * pimc_amplitude_radial. EINVAL: dim outside 1..PIMC_MAX_DIM, n_terms outside 0..PIMC_POLY_MAX_TERMS,
+ * a term of total degree above PIMC_POLY_MAX_DEGREE or with a negative exponent, non-finite
+ * coefficients or endpoints, and the conditions of pimc_amplitude. EUNSUPPORTED: a level polynomial
+ * with more than PIMC_POLY_MAX_MONOMIALS monomials. The recursion for one (V, m, p) is computed once
+ * per process and cached. */
+#define PIMC_POLY_MAX_TERMS 35      /* every monomial of total degree <= 4 in 3 coordinates         */
+#define PIMC_POLY_MAX_DEGREE 4
+#define PIMC_POLY_MAX_MONOMIALS 65536
+
+typedef struct {
+    int dim;                               /* 1..PIMC_MAX_DIM                                       */
+    int n_terms;                           /* 0..PIMC_POLY_MAX_TERMS                                */
+    double coef[PIMC_POLY_MAX_TERMS];
+    int exps[PIMC_POLY_MAX_TERMS][PIMC_MAX_DIM];
+} pimc_poly_potential;
+
+int pimc_amplitude_poly(pimc_ctx *ctx, const pimc_poly_potential *V, double m, const double *a, const double *b,
+                        double T, uint32_t N, int p, uint64_t n_samples, uint64_t seed, uint32_t stream,
+                        uint32_t flags, pimc_level_result *out);
+int pimc_path_actions_poly(pimc_ctx *ctx, const pimc_poly_potential *V, double m, const double *a,
+                           const double *b, double T, uint32_t N, int p, uint64_t seed, uint32_t stream,
+                           uint32_t flags, uint64_t first_path, uint64_t k_paths, double *S_out);
+/* eps W_p at one level (eps = T/2^level, after the mass rescaling) as monomials in the components:
+ * term i is coef[i] * prod_c x_c^exps[2 dim i + c] * prod_c xbar_c^exps[2 dim i + dim + c] (x the
+ * mid-point, xbar the half-deviation of a slice), in the order the kernels consume them. *n_out is
+ * set to the number of terms; EINVAL if cap (doubles) or exps_cap (ints, 2 dim per term) is too
+ * small. No device work. */
+int pimc_level_table_poly(const pimc_poly_potential *V, double m, double T, int p, uint32_t level, double *coef,
+                          size_t cap, int *exps, size_t exps_cap, size_t *n_out);
+
 /* ---- batches: whole grids of endpoints with mixed N, p, T in one graph launch ------------------- */
 
 /* One amplitude of a batch: potential systems[system] with mass m, A_N^(p)(a, b; T) estimated from

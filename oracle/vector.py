@@ -410,6 +410,135 @@ def amplitude(a, d, m, qa, qb, T, s, p, n_samples, seed, stream, batch=2048) -> 
     return out
 
 
+# ------------------------------------------------------------------------- any polynomial V (components)
+def terms_to_components(terms, d: int, m=1.0) -> CPoly:
+    """V(q) = sum coef q_1^e_1 .. q_d^e_d from ``terms`` = [(coef, (e_1, .., e_d))], after the mass
+    rescaling V(y / sqrt m): each coefficient times m^(-total degree / 2), rounded to FP64 as the
+    library does (an irrational factor for odd degree)."""
+    out: CPoly = {}
+    for c, e in terms:
+        e = tuple(int(x) for x in e) + (0,) * (d - len(e))
+        deg = sum(e)
+        k = e[:d] + (0,) * d
+        out[k] = out.get(k, 0) + Fraction(float(c) * float(m) ** (-0.5 * deg))
+    return {k: v for k, v in out.items() if v != 0}
+
+
+@lru_cache(maxsize=16)
+def _component_cached(V: Tuple, d: int, p: int):
+    W = component_coefficients(dict(V), d, p)
+    return tuple(sorted((key, tuple(sorted(poly.items()))) for key, poly in W.items()))
+
+
+def component_level_terms(V: CPoly, d: int, p: int, eps) -> CPoly:
+    """eps W_p = sum_{k <= m < p} eps^(m-k+1) W_{m,k} as one exact polynomial in the components."""
+    eps = Fraction(eps)
+    out: CPoly = {}
+    for (m, k), poly in _component_cached(tuple(sorted(V.items())), int(d), int(p)):
+        out = _add(out, _scale(dict(poly), eps ** (m - k + 1)))
+    return out
+
+
+def component_tables(V: CPoly, d: int, p: int, T: float, s: int):
+    """Per level n = 0..s: (exponent array [terms, 2d], FP64 coefficients) of eps_n W_p, eps_n = T/2^n."""
+    out = []
+    for n in range(s + 1):
+        f = component_level_terms(V, d, p, Fraction(T) / (1 << n))
+        keys = sorted(f)
+        out.append((np.array(keys, dtype=np.int64).reshape(len(keys), 2 * d),
+                    np.array([float(f[k]) for k in keys], dtype=np.float64)))
+    return out
+
+
+def _component_terms(tab, x: np.ndarray, xbar: np.ndarray):
+    """Each term c_t prod_i x_i^e_ti xbar_i^e_t(d+i) (last axis = coordinates), in table order (FP64;
+    the powers of each variable are tabulated once)."""
+    exps, coef = tab
+    y = np.concatenate([x, xbar], axis=-1)
+    top = int(exps.max()) if exps.size else 0
+    pw = [[np.ones(y.shape[:-1])] for _ in range(y.shape[-1])]
+    for v in range(y.shape[-1]):
+        for _ in range(top):
+            pw[v].append(pw[v][-1] * y[..., v])
+    for e, c in zip(exps, coef):
+        t = np.full(y.shape[:-1], c)
+        for v, ev in enumerate(e):
+            if ev:
+                t = t * pw[v][ev]
+        yield t
+
+
+def component_eps_W(tab, x: np.ndarray, xbar: np.ndarray) -> np.ndarray:
+    """sum_t c_t prod_i x_i^e_ti xbar_i^e_t(d+i), term by term (FP64)."""
+    total = np.zeros(np.broadcast_shapes(x.shape, xbar.shape)[:-1])
+    for t in _component_terms(tab, x, xbar):
+        total = total + t
+    return total
+
+
+def component_eps_W_abs(tab, x: np.ndarray, xbar: np.ndarray) -> np.ndarray:
+    """sum_t |c_t prod_i x_i^e_ti xbar_i^e_t(d+i)|: the scale of the rounding error of any order of
+    summation of the terms."""
+    total = np.zeros(np.broadcast_shapes(x.shape, xbar.shape)[:-1])
+    for t in _component_terms(tab, x, xbar):
+        total = total + np.abs(t)
+    return total
+
+
+def _component_level_sums(q: np.ndarray, s: int, tables):
+    """Per path and level: (sum over slices of eps_n W_p, sum over slices of the absolute terms)."""
+    S = np.zeros((q.shape[0], s + 1))
+    A = np.zeros((q.shape[0], s + 1))
+    for n in range(s + 1):
+        sub = q[:, :: 1 << (s - n), :]
+        x = 0.5 * (sub[:, 1:, :] + sub[:, :-1, :])
+        xbar = 0.5 * (sub[:, 1:, :] - sub[:, :-1, :])
+        tot = np.zeros(x.shape[:-1])
+        ab = np.zeros(x.shape[:-1])
+        for t in _component_terms(tables[n], x, xbar):
+            tot = tot + t
+            ab = ab + np.abs(t)
+        S[:, n] = tot.sum(axis=1)
+        A[:, n] = ab.sum(axis=1)
+    return S, A
+
+
+def poly_path_actions(terms, d, m, qa, qb, T, s, p, seed, stream, paths, with_scale=False):
+    """Level actions [path, n] of the level-s paths for any polynomial V (component route); with
+    ``with_scale`` also the sums of the absolute monomial terms (the rounding-error scale)."""
+    sm = math.sqrt(float(m))
+    V = terms_to_components(terms, d, m)
+    tabs = component_tables(V, d, p, T, s)
+    q = bisection_paths([x * sm for x in qa], [x * sm for x in qb], T, s, seed, stream, paths)
+    S, A = _component_level_sums(q, s, tabs)
+    return (S, A) if with_scale else S
+
+
+def poly_amplitude(terms, d, m, qa, qb, T, s, p, n_samples, seed, stream, batch=2048) -> List[Dict]:
+    """A_{2^n} and its MC error per level n = 0..s for any polynomial V (as ``amplitude``)."""
+    sm = math.sqrt(float(m))
+    at, bt = [x * sm for x in qa], [x * sm for x in qb]
+    V = terms_to_components(terms, d, m)
+    tabs = component_tables(V, d, p, T, s)
+    K0 = sm ** d * free_kernel(at, bt, T)
+    ws = [[] for _ in range(s + 1)]
+    for start in range(0, n_samples, batch):
+        idx = np.arange(start, min(start + batch, n_samples), dtype=np.uint64)
+        S, _ = _component_level_sums(bisection_paths(at, bt, T, s, seed, stream, idx), s, tabs)
+        for n in range(s + 1):
+            ws[n].append(np.exp(-S[:, n]))
+    out = []
+    for n in range(s + 1):
+        w = np.concatenate(ws[n])
+        if n == 0:
+            out.append(dict(amp=K0 * float(w[0]), err=0.0))
+            continue
+        mean = math.fsum(w) / w.size
+        var = math.fsum((w - mean) ** 2) / (w.size - 1)
+        out.append(dict(amp=K0 * mean, err=K0 * math.sqrt(var / w.size)))
+    return out
+
+
 # ------------------------------------------------------------------------- continuum reference
 def dvr_amplitude_2d(V, qa, qb, T, L=6.0, h=0.2) -> float:
     """<b| exp(-T H) |a> for H = -(1/2) grad^2 + V(x, y) from a tensor-product sinc-DVR (Colbert and

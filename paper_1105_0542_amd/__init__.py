@@ -7,6 +7,6 @@ paper_1105_0542_amd.build``). There is no CPU fallback.
 """
 from .binding import (  # noqa: F401
     FLAG_FP32_POLY, FLAG_HIERARCHY, FLOW_NPARAM, Batch, Context, Flow, LevelResult, PimcError, PimcLibraryMissing,
-    check_problem, level_table, level_table_mpt, level_table_radial, lib_path, load_library, make_tasks,
-    potential_from_coefs, quartic, radial_potential,
+    check_problem, level_table, level_table_mpt, level_table_poly, level_table_radial, lib_path, load_library,
+    make_tasks, poly_potential, potential_from_coefs, quartic, radial_potential,
 )

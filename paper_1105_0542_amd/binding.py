@@ -78,11 +78,34 @@ class Mpt(C.Structure):
 
 
 MAX_DIM = 3
+POLY_MAX_TERMS = 35
+POLY_MAX_DEGREE = 4
 MAX_RADIAL_DEGREE = 2
 
 
 class RadialPotential(C.Structure):
     _fields_ = [("dim", C.c_int), ("degree", C.c_int), ("coef", C.c_double * (MAX_RADIAL_DEGREE + 1))]
+
+
+class PolyPotential(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n_terms", C.c_int), ("coef", C.c_double * POLY_MAX_TERMS),
+                ("exps", (C.c_int * MAX_DIM) * POLY_MAX_TERMS)]
+
+
+def poly_potential(terms, dim):
+    """pimc_poly_potential for V(q) = sum coef q_1^e1 q_2^e2 q_3^e3 from ``terms`` = [(coef, (e1, ..))]."""
+    terms = list(terms)
+    if len(terms) > POLY_MAX_TERMS:
+        raise ValueError(f"at most {POLY_MAX_TERMS} terms")
+    V = PolyPotential()
+    V.dim = int(dim)
+    V.n_terms = len(terms)
+    for t, (c, e) in enumerate(terms):
+        V.coef[t] = float(c)
+        e = list(e) + [0] * (MAX_DIM - len(e))
+        for k in range(MAX_DIM):
+            V.exps[t][k] = int(e[k])
+    return V
 
 
 def radial_potential(coefs, dim):
@@ -259,6 +282,17 @@ def load_library():
     lib.pimc_path_actions_radial.argtypes = [vp, P(RadialPotential), C.c_double, P(C.c_double), P(C.c_double),
                                              C.c_double, C.c_uint32, C.c_int, C.c_uint64, C.c_uint32, C.c_uint32,
                                              C.c_uint64, C.c_uint64, P(C.c_double)]
+    lib.pimc_amplitude_poly.restype = C.c_int
+    lib.pimc_amplitude_poly.argtypes = [vp, P(PolyPotential), C.c_double, P(C.c_double), P(C.c_double),
+                                        C.c_double, C.c_uint32, C.c_int, C.c_uint64, C.c_uint64, C.c_uint32,
+                                        C.c_uint32, P(_LevelResult)]
+    lib.pimc_path_actions_poly.restype = C.c_int
+    lib.pimc_path_actions_poly.argtypes = [vp, P(PolyPotential), C.c_double, P(C.c_double), P(C.c_double),
+                                           C.c_double, C.c_uint32, C.c_int, C.c_uint64, C.c_uint32, C.c_uint32,
+                                           C.c_uint64, C.c_uint64, P(C.c_double)]
+    lib.pimc_level_table_poly.restype = C.c_int
+    lib.pimc_level_table_poly.argtypes = [P(PolyPotential), C.c_double, C.c_double, C.c_int, C.c_uint32,
+                                          vp, C.c_size_t, vp, C.c_size_t, P(C.c_size_t)]
     lib.pimc_level_table_radial.restype = C.c_int
     lib.pimc_level_table_radial.argtypes = [P(RadialPotential), C.c_double, C.c_double, C.c_int, C.c_uint32,
                                             P(C.c_double), C.c_size_t, P(C.c_size_t), P(C.c_int), C.c_size_t,
@@ -355,6 +389,22 @@ def level_table_radial(coefs, dim, m, T, p, level):
     if st != PIMC_OK:
         raise _err(lib, None, st)
     return out, [(shape[3 * g], shape[3 * g + 1], shape[3 * g + 2]) for g in range(ng.value)]
+
+
+def level_table_poly(terms, dim, m, T, p, level):
+    """(coef array, exps array [terms, 2 dim]) of pimc_level_table_poly (host-only call)."""
+    lib = load_library()
+    V = poly_potential(terms, dim)
+    need = C.c_size_t(0)
+    lib.pimc_level_table_poly(C.byref(V), m, T, p, level, None, 0, None, 0, C.byref(need))
+    n = need.value
+    out = np.zeros(n, dtype=np.float64)
+    exps = np.zeros((n, 2 * dim), dtype=np.int32)
+    st = lib.pimc_level_table_poly(C.byref(V), m, T, p, level, out.ctypes.data_as(C.POINTER(C.c_double)), n,
+                                   exps.ctypes.data_as(C.POINTER(C.c_int)), exps.size, C.byref(need))
+    if st != PIMC_OK:
+        raise _err(lib, None, st)
+    return out, exps
 
 
 def _torch_stream_handle() -> Optional[int]:
@@ -475,6 +525,26 @@ class Context:
         self._check(self.lib.pimc_path_actions_radial(self.h, C.byref(V), m, _vec(a, dim), _vec(b, dim), T, N, p,
                                                       seed, stream, flags, first_path, k_paths,
                                                       out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
+
+    def amplitude_poly(self, terms, dim, m, a, b, T, N, p, n_samples, seed, stream=0, flags=0):
+        """pimc_amplitude_poly (V = sum coef prod_c q_c^e_c, q in R^dim) -> (list of LevelResult, status)."""
+        V = poly_potential(terms, dim)
+        s = int(N).bit_length() - 1
+        out = (_LevelResult * (s + 1))()
+        st = self._check(self.lib.pimc_amplitude_poly(self.h, C.byref(V), m, _vec(a, dim), _vec(b, dim), T, N, p,
+                                                      n_samples, seed, stream, flags, out))
+        res = [LevelResult(r.amp, r.err, r.log_amp, r.relvar, r.ess, int(r.n), int(r.n_nonfinite)) for r in out]
+        return res, st
+
+    def path_actions_poly(self, terms, dim, m, a, b, T, N, p, seed, stream, flags, first_path, k_paths):
+        """pimc_path_actions_poly -> array [k_paths, s+1]."""
+        V = poly_potential(terms, dim)
+        s = int(N).bit_length() - 1
+        out = np.zeros((k_paths, s + 1), dtype=np.float64)
+        self._check(self.lib.pimc_path_actions_poly(self.h, C.byref(V), m, _vec(a, dim), _vec(b, dim), T, N, p,
+                                                    seed, stream, flags, first_path, k_paths,
+                                                    out.ctypes.data_as(C.POINTER(C.c_double))))
         return out
 
     def path_actions_mpt(self, lam, alpha, m, a, b, T, N, p, seed, stream, flags, first_path, k_paths):

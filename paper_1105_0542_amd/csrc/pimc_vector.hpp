@@ -109,11 +109,20 @@ inline size_t vec_lds_bytes(int dim, int D, int s) {
            sizeof(double);
 }
 
+// Component evaluator (any polynomial V): per level, records of 16 bytes {op word, pad, coefficient}
+// (layout in pimc_vector_impl.hpp, PolyEvalRT), consumed kPolyRecordGroup at a time.
+constexpr int kPolyRecordGroup = 4;
+constexpr int kPolyMaxRecords = 1 << 18;
+
 // Launch the vector estimation kernel: dim 1..3; U = min(s, kVecU); `specialized` selects the
 // evaluator with the compile-time shape of level p (dim 2 or 3, U = kVecU), else the evaluator
 // that reads the shape array. hipErrorInvalidValue for an unsupported combination.
 hipError_t launch_vector(const VecArgs& A, int dim, int p, int U, bool specialized, int grid, hipStream_t st);
 int vector_resident_blocks(int dim, int p, int U, bool specialized, size_t lds_bytes, int device);
+
+// The component evaluator: A.tab = records (A.stride doubles per level, 2 per record).
+hipError_t launch_vector_poly(const VecArgs& A, int dim, int U, int grid, hipStream_t st);
+int vector_poly_resident(int dim, int U, size_t lds_bytes, int device);
 
 // Per-dimension halves (one translation unit each).
 hipError_t launch_vector_d1(const VecArgs& A, int p, int U, bool specialized, int grid, hipStream_t st);
@@ -122,5 +131,11 @@ hipError_t launch_vector_d3(const VecArgs& A, int p, int U, bool specialized, in
 int vector_resident_d1(int p, int U, bool specialized, size_t lds, int device);
 int vector_resident_d2(int p, int U, bool specialized, size_t lds, int device);
 int vector_resident_d3(int p, int U, bool specialized, size_t lds, int device);
+hipError_t launch_vector_poly_d1(const VecArgs& A, int U, int grid, hipStream_t st);
+hipError_t launch_vector_poly_d2(const VecArgs& A, int U, int grid, hipStream_t st);
+hipError_t launch_vector_poly_d3(const VecArgs& A, int U, int grid, hipStream_t st);
+int vector_poly_resident_d1(int U, size_t lds, int device);
+int vector_poly_resident_d2(int U, size_t lds, int device);
+int vector_poly_resident_d3(int U, size_t lds, int device);
 
 }  // namespace pimc

@@ -1,7 +1,9 @@
 // Host side of the several-coordinate entry points (pimc_amplitude_radial, pimc_path_actions_radial,
-// pimc_level_table_radial in include/pimc.h): eq.(MBrec)/(DIA) on polynomials in the invariants
-// u = x.x, w = x.xbar, z = xbar.xbar (FP64), the per-level fold into the layout of pimc_vector.hpp,
-// the straight-line reference actions, and the estimation through the vector kernels.
+// pimc_level_table_radial and the *_poly variants in include/pimc.h): eq.(MBrec)/(DIA) on polynomials
+// in the invariants u = x.x, w = x.xbar, z = xbar.xbar (FP64) for rotation-invariant potentials, or
+// in the 2d components of x and xbar for any polynomial potential; the per-level fold (the table
+// layout of pimc_vector.hpp, or the records of the component evaluator), the straight-line reference
+// actions, and the estimation through the vector kernels.
 //
 // Invariant forms of the operators in d dimensions (partial derivatives in u, w, z; chain rule with
 // grad u = 2x, grad w = xbar, gradbar w = x, gradbar z = 2 xbar):
@@ -12,12 +14,16 @@
 //     xbar . grad f       = 2w f_u + z f_w
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <iterator>
 #include <map>
+#include <memory>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "pimc.h"
@@ -29,6 +35,7 @@ using namespace pimc_host;
 
 static_assert(PIMC_MAX_DIM == kVecMaxDim, "dimension limit of the public header");
 static_assert(PIMC_MAX_RADIAL_DEGREE == 2, "the table shape bound covers u-degree <= 2");
+static_assert(PIMC_POLY_MAX_MONOMIALS <= kPolyMaxRecords, "records of the component evaluator");
 
 namespace {
 
@@ -249,6 +256,7 @@ std::vector<int> shape_array(int p) {
 struct VecProblem {
     int dim = 1, s = 0, p = 1, U = 0, D = 0;
     bool specialized = false;
+    bool poly = false;                           // component evaluator (tab: records per level)
     double a[kVecMaxDim] = {0, 0, 0}, b[kVecMaxDim] = {0, 0, 0};
     double T = 0, pref = 1.0, K0 = 0.0;
     int stride = 0;
@@ -389,8 +397,9 @@ int check_lds(pimc_ctx* c, const VecProblem& P) {
 }
 
 int vector_grid(pimc_ctx* c, const VecProblem& P, uint64_t n_chunks) {
-    const int resident = vector_resident_blocks(P.dim, P.p, P.U, P.specialized, vec_lds_bytes(P.dim, P.D, P.s),
-                                                c->device);
+    const size_t lds = vec_lds_bytes(P.dim, P.D, P.s);
+    const int resident = P.poly ? vector_poly_resident(P.dim, P.U, lds, c->device)
+                                : vector_resident_blocks(P.dim, P.p, P.U, P.specialized, lds, c->device);
     const uint64_t g = std::min<uint64_t>(n_chunks, uint64_t(std::max(resident, 1)));
     return int(std::max<uint64_t>(g, 1));
 }
@@ -435,7 +444,8 @@ int vector_amplitude_core(pimc_ctx* c, const VecProblem& P, uint64_t n_samples, 
     A.dump = nullptr;
     const int grid = vector_grid(c, P, n_chunks);
     HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
-    HIP_TRY(c, launch_vector(A, P.dim, P.p, P.U, P.specialized, grid, c->stream));
+    HIP_TRY(c, P.poly ? launch_vector_poly(A, P.dim, P.U, grid, c->stream)
+                      : launch_vector(A, P.dim, P.p, P.U, P.specialized, grid, c->stream));
     HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
     HIP_TRY(c, launch_seg_reduce(c->d_partials, c->d_seg, c->d_seg + slots, uint64_t(slots), c->d_red, c->stream));
     std::vector<double> red(size_t(slots) * 4);
@@ -479,9 +489,388 @@ int vector_path_actions_core(pimc_ctx* c, const VecProblem& P, uint64_t seed, ui
     A.partials = nullptr;
     A.dump = c->d_dump;
     const int grid = vector_grid(c, P, A.n_chunks);
-    HIP_TRY(c, launch_vector(A, P.dim, P.p, P.U, P.specialized, grid, c->stream));
+    HIP_TRY(c, P.poly ? launch_vector_poly(A, P.dim, P.U, grid, c->stream)
+                      : launch_vector(A, P.dim, P.p, P.U, P.specialized, grid, c->stream));
     HIP_TRY(c, hipMemcpyAsync(S_out, c->d_dump, size_t(k_paths) * nlev * 8, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return PIMC_OK;
+}
+
+// ============================================================================ component route
+// eq.(MBrec)/(DIA) with W_{m,k} as polynomials in the components x_1..x_3 (slots 0..2) and
+// xbar_1..xbar_3 (slots 3..5); every derivative is taken component by component, so any polynomial V.
+using MKey = std::array<uint8_t, 6>;
+using MPoly = std::map<MKey, double>;
+constexpr int kXb = 3;                            // slot of xbar_1
+
+void maxpy(MPoly& y, double a, const MPoly& x) {
+    for (const auto& kv : x) y[kv.first] += a * kv.second;
+}
+
+MPoly mder(const MPoly& f, int var) {
+    MPoly out;
+    for (const auto& kv : f)
+        if (kv.first[size_t(var)]) {
+            MKey k = kv.first;
+            k[size_t(var)] -= 1;
+            out[k] += kv.second * double(kv.first[size_t(var)]);
+        }
+    return out;
+}
+
+MPoly mtimes(const MPoly& f, int var) {
+    MPoly out;
+    for (const auto& kv : f) {
+        MKey k = kv.first;
+        k[size_t(var)] += 1;
+        out[k] += kv.second;
+    }
+    return out;
+}
+
+MPoly mmul(const MPoly& a, const MPoly& b) {
+    MPoly out;
+    for (const auto& ka : a)
+        for (const auto& kb : b) {
+            MKey k;
+            for (size_t i = 0; i < k.size(); ++i) k[i] = uint8_t(ka.first[i] + kb.first[i]);
+            out[k] += ka.second * kb.second;
+        }
+    return out;
+}
+
+void mprune(MPoly& f) {
+    for (auto it = f.begin(); it != f.end();)
+        it = (it->second == 0.0) ? f.erase(it) : std::next(it);
+}
+
+// grad^2 (off = 0) or gradbar^2 (off = kXb)
+MPoly mlap(const MPoly& f, int d, int off) {
+    MPoly out;
+    for (int i = 0; i < d; ++i) maxpy(out, 1.0, mder(mder(f, off + i), off + i));
+    return out;
+}
+
+// grad f . grad g (off = 0) or gradbar f . gradbar g (off = kXb)
+MPoly mgdot(const MPoly& f, const MPoly& g, int d, int off) {
+    MPoly out;
+    for (int i = 0; i < d; ++i) maxpy(out, 1.0, mmul(mder(f, off + i), mder(g, off + i)));
+    return out;
+}
+
+// xbar . grad f
+MPoly mxbar_grad(const MPoly& f, int d) {
+    MPoly out;
+    for (int i = 0; i < d; ++i) maxpy(out, 1.0, mtimes(mder(f, i), kXb + i));
+    return out;
+}
+
+// W[m][k], 0 <= k <= m <= p-1, in components: eq.(DIA), then eq.(MBrec) for k = m-1..0 (Fig. 1).
+std::vector<std::vector<MPoly>> component_coefficients(const MPoly& V, int d, int p) {
+    std::vector<std::vector<MPoly>> W(static_cast<size_t>(p), std::vector<MPoly>(static_cast<size_t>(p)));
+    W[0][0] = V;
+    double fact = 1.0;
+    for (int m = 1; m < p; ++m) {
+        fact *= double(2 * m) * double(2 * m + 1);
+        MPoly t = V;
+        for (int i = 0; i < 2 * m; ++i) t = mxbar_grad(t, d);
+        MPoly diag;
+        maxpy(diag, 1.0 / fact, t);
+        mprune(diag);
+        W[size_t(m)][size_t(m)] = diag;
+        for (int k = m - 1; k >= 0; --k) {
+            MPoly rhs = mlap(W[size_t(m - 1)][size_t(k)], d, 0);
+            maxpy(rhs, 1.0, mlap(W[size_t(m)][size_t(k + 1)], d, kXb));
+            for (int l = 0; l <= m - 2; ++l)
+                for (int r = std::max(0, k - m + l + 2); r <= std::min(k, l); ++r)
+                    maxpy(rhs, -1.0, mgdot(W[size_t(l)][size_t(r)], W[size_t(m - l - 2)][size_t(k - r)], d, 0));
+            for (int l = 1; l <= m - 2; ++l)
+                for (int r = std::max(0, k - m + l + 2); r <= std::min(k, l); ++r)
+                    maxpy(rhs, -1.0, mgdot(W[size_t(l)][size_t(r)], W[size_t(m - l - 1)][size_t(k - r + 1)], d, kXb));
+            MPoly out;
+            maxpy(out, 1.0 / double(8 * (m + k + 1)), rhs);
+            mprune(out);
+            W[size_t(m)][size_t(k)] = out;
+        }
+    }
+    return W;
+}
+
+// The recursion of one (V after the mass rescaling, d, p), computed once per process.
+struct PolyCoefficients {
+    int d = 1, p = 1;
+    std::vector<std::vector<MPoly>> W;
+    std::vector<MKey> keys;                      // every monomial of any W_{m,k}, in consumption order
+};
+
+// Device variables of a slice: y_c = qb_c - qa_c = 2 xbar_c (c < d), y_{d+c} = qa_c + qb_c = 2 x_c.
+// Exponent of device variable v in a monomial.
+int var_exp(const MKey& k, int d, int v) { return v < d ? k[size_t(kXb + v)] : k[size_t(v - d)]; }
+
+// Records of the component evaluator (pimc_vector_impl.hpp, PolyEvalRT): a post-order walk of the
+// prefix tree of the monomials ordered by the exponents of y_0, y_1, ... from high to low. A node at
+// depth v sums its children (one per exponent k of y_v, descending) by Horner in y_v; a leaf child
+// is a coefficient, an internal child the finished node value a_{v+1} y_{v+1}^tail.
+struct RecTree {
+    std::vector<uint32_t> ops;                   // op word per record
+    std::vector<int> leaf;                       // per record: index into keys of its coefficient, or -1
+};
+
+int emit_poly_node(const std::vector<MKey>& keys, size_t r0, size_t r1, int v, int nv, int d, RecTree& T, bool& ok) {
+    int prev = -1;
+    bool first = true;
+    for (size_t g0 = r0; g0 < r1;) {
+        const int k = var_exp(keys[g0], d, v);
+        size_t g1 = g0;
+        while (g1 < r1 && var_exp(keys[g1], d, v) == k) ++g1;
+        uint32_t op = uint32_t(v);
+        int tail = 0, leaf = -1;
+        if (v == nv - 1) {
+            if (g1 - g0 != 1) ok = false;        // a leaf group holds exactly one monomial
+            op |= 8u;
+            leaf = int(g0);
+        } else {
+            tail = emit_poly_node(keys, g0, g1, v + 1, nv, d, T, ok);
+        }
+        const int gap = first ? 0 : prev - k;
+        if (gap > 63 || tail > 63) ok = false;
+        if (first) op |= 16u;
+        op |= uint32_t(gap) << 5;
+        op |= uint32_t(tail) << 11;
+        T.ops.push_back(op);
+        T.leaf.push_back(leaf);
+        prev = k;
+        first = false;
+        g0 = g1;
+    }
+    return prev;                                 // the node's lowest exponent of y_v
+}
+
+// Post-order records of the whole polynomial, ending with the finish record (op 7) and padded with
+// no-op records (op 6) to a multiple of kPolyRecordGroup.
+bool build_records(const std::vector<MKey>& keys, int d, RecTree& T) {
+    T.ops.clear();
+    T.leaf.clear();
+    bool ok = true;
+    const int nv = 2 * d;
+    int tail0 = 0;
+    if (!keys.empty()) tail0 = emit_poly_node(keys, 0, keys.size(), 0, nv, d, T, ok);
+    if (tail0 > 63) ok = false;
+    if (!keys.empty()) {
+        T.ops.push_back(7u | (uint32_t(tail0) << 11));
+        T.leaf.push_back(-1);
+    }
+    while (T.ops.size() % kPolyRecordGroup) {
+        T.ops.push_back(6u);
+        T.leaf.push_back(-1);
+    }
+    return ok;
+}
+
+// The same arithmetic as PolyEvalRT on one slice (y as defined above), for the reference actions.
+double eval_records(const std::vector<uint32_t>& ops, const std::vector<double>& coef, const double* y) {
+    double a[2 * kVecMaxDim] = {0, 0, 0, 0, 0, 0};
+    double S = 0.0;
+    for (size_t o = 0; o < ops.size(); ++o) {
+        const uint32_t w = ops[o];
+        const int v = int(w & 7u);
+        const int gap = int((w >> 5) & 63u), tail = int((w >> 11) & 63u);
+        if (v == 6) continue;
+        if (v == 7) {
+            double x = a[0];
+            for (int e = 0; e < tail; ++e) x *= y[0];
+            S += x;
+            continue;
+        }
+        double t;
+        if (w & 8u) {
+            t = coef[o];
+        } else {
+            t = a[v + 1];
+            for (int e = 0; e < tail; ++e) t *= y[v + 1];
+        }
+        if (w & 16u) {
+            a[v] = t;
+        } else {
+            double yp = y[v];
+            for (int e = 1; e < gap; ++e) yp *= y[v];
+            a[v] = std::fma(a[v], yp, t);
+        }
+    }
+    return S;
+}
+
+std::string poly_cache_key(const pimc_poly_potential* V, double m, int p) {
+    std::string k;
+    auto put = [&k](const void* q, size_t n) { k.append(static_cast<const char*>(q), n); };
+    put(&V->dim, sizeof(int));
+    put(&V->n_terms, sizeof(int));
+    put(&m, sizeof(double));
+    put(&p, sizeof(int));
+    for (int t = 0; t < V->n_terms; ++t) {
+        put(&V->coef[t], sizeof(double));
+        put(V->exps[t], sizeof(int) * PIMC_MAX_DIM);
+    }
+    return k;
+}
+
+const PolyCoefficients& cached_poly(const pimc_poly_potential* V, double m, int p) {
+    static std::mutex mu;
+    static std::map<std::string, std::unique_ptr<PolyCoefficients>> cache;
+    const std::string key = poly_cache_key(V, m, p);
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return *it->second;
+    auto C = std::make_unique<PolyCoefficients>();
+    C->d = V->dim;
+    C->p = p;
+    MPoly Vm;                                    // V(y / sqrt(m)): coef times m^(-degree/2)
+    for (int t = 0; t < V->n_terms; ++t) {
+        MKey k{};
+        int deg = 0;
+        for (int c = 0; c < V->dim; ++c) {
+            k[size_t(c)] = uint8_t(V->exps[t][c]);
+            deg += V->exps[t][c];
+        }
+        Vm[k] += V->coef[t] * std::pow(m, -0.5 * double(deg));
+    }
+    mprune(Vm);
+    C->W = component_coefficients(Vm, V->dim, p);
+    MPoly all;
+    for (const auto& row : C->W)
+        for (const MPoly& f : row)
+            for (const auto& kv : f) all[kv.first] = 1.0;
+    for (const auto& kv : all) C->keys.push_back(kv.first);
+    const int d = V->dim;
+    std::sort(C->keys.begin(), C->keys.end(), [d](const MKey& x, const MKey& y) {
+        for (int v = 0; v < 2 * d; ++v) {
+            const int ex = var_exp(x, d, v), ey = var_exp(y, d, v);
+            if (ex != ey) return ex > ey;
+        }
+        return false;
+    });
+    return *cache.emplace(key, std::move(C)).first->second;
+}
+
+// eps W_p at level eps: the coefficient of each monomial of keys (unscaled).
+std::vector<double> fold_poly(const PolyCoefficients& C, double eps) {
+    std::map<MKey, double> f;
+    for (int m = 0; m < C.p; ++m)
+        for (int k = 0; k <= m; ++k) {
+            const double e = std::pow(eps, double(m - k + 1));
+            for (const auto& kv : C.W[size_t(m)][size_t(k)]) f[kv.first] += kv.second * e;
+        }
+    std::vector<double> out(C.keys.size());
+    for (size_t i = 0; i < C.keys.size(); ++i) out[i] = f[C.keys[i]];
+    return out;
+}
+
+int check_poly(const pimc_poly_potential* V, double m, const double* a, const double* b, double T, uint32_t N, int p,
+               uint64_t n_samples) {
+    if (!V) { set_thread_error("potential is NULL"); return PIMC_EINVAL; }
+    if (V->dim < 1 || V->dim > PIMC_MAX_DIM) {
+        set_thread_error("dim = %d outside 1..%d", V->dim, PIMC_MAX_DIM);
+        return PIMC_EINVAL;
+    }
+    if (V->n_terms < 0 || V->n_terms > PIMC_POLY_MAX_TERMS) {
+        set_thread_error("n_terms = %d outside 0..%d", V->n_terms, PIMC_POLY_MAX_TERMS);
+        return PIMC_EINVAL;
+    }
+    for (int t = 0; t < V->n_terms; ++t) {
+        if (!std::isfinite(V->coef[t])) { set_thread_error("coefficient %d is not finite", t); return PIMC_EINVAL; }
+        int deg = 0;
+        for (int c = 0; c < PIMC_MAX_DIM; ++c) {
+            const int e = V->exps[t][c];
+            if (e < 0 || (c >= V->dim && e != 0)) {
+                set_thread_error("term %d: exponent %d of coordinate %d (dim %d)", t, e, c + 1, V->dim);
+                return PIMC_EINVAL;
+            }
+            deg += e;
+        }
+        if (deg > PIMC_POLY_MAX_DEGREE) {
+            set_thread_error("term %d has total degree %d > %d", t, deg, PIMC_POLY_MAX_DEGREE);
+            return PIMC_EINVAL;
+        }
+    }
+    if (!a || !b) { set_thread_error("endpoint array is NULL"); return PIMC_EINVAL; }
+    for (int c = 0; c < V->dim; ++c)
+        if (!std::isfinite(a[c]) || !std::isfinite(b[c])) { set_thread_error("endpoints must be finite"); return PIMC_EINVAL; }
+    pimc_potential zero{};
+    return check_args(&zero, m, 0.0, 0.0, T, N, p, n_samples);
+}
+
+int build_poly_problem(const pimc_poly_potential* V, double m, const double* a, const double* b, double T, uint32_t N,
+                       int p, uint32_t flags, VecProblem& P, char* why, size_t whylen) {
+    if (flags & PIMC_FP32_POLY) {
+        std::snprintf(why, whylen, "the several-coordinate kernels evaluate in FP64 only");
+        return PIMC_EUNSUPPORTED;
+    }
+    P.poly = true;
+    P.dim = V->dim;
+    P.s = log2_exact(N);
+    P.p = p;
+    P.T = T;
+    const double sm = std::sqrt(m);
+    double r2 = 0.0;
+    for (int c = 0; c < P.dim; ++c) {
+        P.a[c] = a[c] * sm;
+        P.b[c] = b[c] * sm;
+        r2 += (P.b[c] - P.a[c]) * (P.b[c] - P.a[c]);
+    }
+    P.pref = std::pow(sm, double(P.dim));
+    P.K0 = std::exp(-r2 / (2.0 * T)) / std::pow(2.0 * kPi * T, 0.5 * double(P.dim));
+    P.U = std::min(P.s, kVecU);
+    P.D = P.s - P.U;
+    P.specialized = false;
+    const PolyCoefficients& C = cached_poly(V, m, p);
+    if (C.keys.size() > size_t(PIMC_POLY_MAX_MONOMIALS)) {
+        std::snprintf(why, whylen, "eps W_p has %zu monomials (limit %d)", C.keys.size(), PIMC_POLY_MAX_MONOMIALS);
+        return PIMC_EUNSUPPORTED;
+    }
+    RecTree R;
+    if (!build_records(C.keys, P.dim, R)) {
+        std::snprintf(why, whylen, "internal: a monomial exponent above 63");
+        return PIMC_EUNSUPPORTED;
+    }
+    const size_t nrec = R.ops.size();
+    P.stride = int(2 * nrec);                    // doubles per level: (op word, coefficient) per record
+    P.tab.assign(size_t(P.s + 1) * size_t(P.stride), 0.0);
+    P.shift.assign(size_t(P.s + 1), 0.0);
+    std::vector<double> coef(nrec, 0.0);
+    for (int n = 0; n <= P.s; ++n) {
+        const std::vector<double> f = fold_poly(C, std::ldexp(T, -n));
+        for (size_t o = 0; o < nrec; ++o) {
+            coef[o] = 0.0;
+            if (R.leaf[o] >= 0) {
+                const MKey& k = C.keys[size_t(R.leaf[o])];
+                int deg = 0;
+                for (int c = 0; c < 2 * kVecMaxDim; ++c) deg += k[size_t(c)];
+                coef[o] = std::ldexp(f[size_t(R.leaf[o])], -deg);   // y = 2 x, 2 xbar
+            }
+            double* rec = P.tab.data() + size_t(n) * size_t(P.stride) + 2 * o;
+            uint64_t bits = R.ops[o];
+            std::memcpy(&rec[0], &bits, 8);
+            rec[1] = coef[o];
+        }
+        const int M = 1 << n;
+        double S = 0.0;
+        for (int k = 0; k < M; ++k) {
+            double y[2 * kVecMaxDim] = {0, 0, 0, 0, 0, 0};
+            for (int c = 0; c < P.dim; ++c) {
+                const double q0 = P.a[c] + (P.b[c] - P.a[c]) * double(k) / double(M);
+                const double q1 = P.a[c] + (P.b[c] - P.a[c]) * double(k + 1) / double(M);
+                y[c] = q1 - q0;
+                y[P.dim + c] = q0 + q1;
+            }
+            S += eval_records(R.ops, coef, y);
+        }
+        P.shift[size_t(n)] = S;
+    }
+    P.tab_dev = P.tab;
+    P.level0_action = P.shift[0];
+    P.shape.assign(1, int(nrec));
+    P.sig.assign(size_t(P.s + 1), 0.0);
+    for (int n = 1; n <= P.s; ++n) P.sig[size_t(n)] = std::sqrt(T / std::ldexp(1.0, n + 1));
     return PIMC_OK;
 }
 
@@ -495,6 +884,24 @@ hipError_t launch_vector(const VecArgs& A, int dim, int p, int U, bool specializ
         case 2: return launch_vector_d2(A, p, U, specialized, grid, st);
         case 3: return launch_vector_d3(A, p, U, specialized, grid, st);
         default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_vector_poly(const VecArgs& A, int dim, int U, int grid, hipStream_t st) {
+    switch (dim) {
+        case 1: return launch_vector_poly_d1(A, U, grid, st);
+        case 2: return launch_vector_poly_d2(A, U, grid, st);
+        case 3: return launch_vector_poly_d3(A, U, grid, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+int vector_poly_resident(int dim, int U, size_t lds_bytes, int device) {
+    switch (dim) {
+        case 1: return vector_poly_resident_d1(U, lds_bytes, device);
+        case 2: return vector_poly_resident_d2(U, lds_bytes, device);
+        case 3: return vector_poly_resident_d3(U, lds_bytes, device);
+        default: return 256;
     }
 }
 
@@ -573,6 +980,72 @@ int pimc_level_table_radial(const pimc_radial_potential* V, double m, double T, 
         shape[3 * g] = groups[g].j + groups[g].l;
         shape[3 * g + 1] = groups[g].j;
         shape[3 * g + 2] = groups[g].len;
+    }
+    return PIMC_OK;
+}
+
+int pimc_amplitude_poly(pimc_ctx* c, const pimc_poly_potential* V, double m, const double* a, const double* b, double T,
+                        uint32_t N, int p, uint64_t n_samples, uint64_t seed, uint32_t stream, uint32_t flags,
+                        pimc_level_result* out) {
+    int st = check_poly(V, m, a, b, T, N, p, n_samples);
+    if (st) return c ? ctx_fail(c, st, "%s", g_thread_error) : st;
+    if (!c) { set_thread_error("context is NULL"); return PIMC_EINVAL; }
+    if (!out) return ctx_fail(c, PIMC_EINVAL, "out is NULL");
+    if (flags & ~kKnownFlags) return ctx_fail(c, PIMC_EINVAL, "unknown flags 0x%x", flags & ~kKnownFlags);
+    HIP_TRY(c, hipSetDevice(c->device));
+    VecProblem P;
+    char why[256] = "";
+    st = build_poly_problem(V, m, a, b, T, N, p, flags, P, why, sizeof(why));
+    if (st) return ctx_fail(c, st, "%s", why);
+    return vector_amplitude_core(c, P, n_samples, seed, stream, flags, out);
+}
+
+int pimc_path_actions_poly(pimc_ctx* c, const pimc_poly_potential* V, double m, const double* a, const double* b,
+                           double T, uint32_t N, int p, uint64_t seed, uint32_t stream, uint32_t flags,
+                           uint64_t first_path, uint64_t k_paths, double* S_out) {
+    int st = check_poly(V, m, a, b, T, N, p, 2);
+    if (st) return c ? ctx_fail(c, st, "%s", g_thread_error) : st;
+    if (!c) { set_thread_error("context is NULL"); return PIMC_EINVAL; }
+    if (!S_out && k_paths) return ctx_fail(c, PIMC_EINVAL, "S_out is NULL");
+    if (flags & ~kKnownFlags) return ctx_fail(c, PIMC_EINVAL, "unknown flags 0x%x", flags & ~kKnownFlags);
+    if (k_paths == 0) return PIMC_OK;
+    HIP_TRY(c, hipSetDevice(c->device));
+    VecProblem P;
+    char why[256] = "";
+    st = build_poly_problem(V, m, a, b, T, N, p, flags, P, why, sizeof(why));
+    if (st) return ctx_fail(c, st, "%s", why);
+    return vector_path_actions_core(c, P, seed, stream, flags, first_path, k_paths, S_out);
+}
+
+int pimc_level_table_poly(const pimc_poly_potential* V, double m, double T, int p, uint32_t level, double* coef,
+                          size_t cap, int* exps, size_t exps_cap, size_t* n_out) {
+    const double zero[PIMC_MAX_DIM] = {0.0, 0.0, 0.0};
+    int st = check_poly(V, m, zero, zero, T, 1u, p, 2);
+    if (st) return st;
+    if (level > PIMC_MAX_S) { set_thread_error("level > %d", PIMC_MAX_S); return PIMC_EINVAL; }
+    if (!n_out) { set_thread_error("n_out is NULL"); return PIMC_EINVAL; }
+    const PolyCoefficients& C = cached_poly(V, m, p);
+    RecTree R;
+    if (!build_records(C.keys, V->dim, R)) { set_thread_error("internal: a monomial exponent above 63"); return PIMC_EUNSUPPORTED; }
+    const std::vector<double> f = fold_poly(C, std::ldexp(T, -int(level)));
+    size_t n = 0;
+    for (int l : R.leaf) n += l >= 0 ? 1 : 0;
+    *n_out = n;
+    const size_t nv = size_t(2 * V->dim);
+    if (cap < n || exps_cap < n * nv || !coef || !exps) {
+        set_thread_error("need %zu doubles and %zu ints", n, n * nv);
+        return PIMC_EINVAL;
+    }
+    size_t i = 0;
+    for (int l : R.leaf) {
+        if (l < 0) continue;
+        const MKey& k = C.keys[size_t(l)];
+        coef[i] = f[size_t(l)];
+        for (int c = 0; c < V->dim; ++c) {
+            exps[i * nv + size_t(c)] = k[size_t(c)];
+            exps[i * nv + size_t(V->dim + c)] = k[size_t(kXb + c)];
+        }
+        ++i;
     }
     return PIMC_OK;
 }

@@ -174,6 +174,112 @@ struct RadialEvalRT {
     }
 };
 
+// Any polynomial V (component route): eps W_p of a slice is a polynomial in the 2 DIM variables
+// y_c = qb_c - qa_c (c < DIM) and y_{DIM+c} = qa_c + qb_c, given as records {op, pad, coefficient} in
+// a post-order walk of the prefix tree of its monomials (exponents of y_0, y_1, ... from high to low).
+// op bits: 0..2 the depth v (6: no-op, 7: finish), 3 leaf, 4 first, 5..10 gap, 11..16 tail. A record
+// at depth v adds one child to the Horner sum a_v over the exponents of y_v:
+//     t = leaf ? coefficient : a_{v+1} y_{v+1}^tail,   a_v = first ? t : a_v y_v^gap + t,
+// and the finish record adds a_0 y_0^tail to S. Records are read kPolyRecordGroup at a time (one
+// 64-byte scalar load); the depth selects the accumulator through a switch (wave-uniform).
+struct PolyRec {
+    int op;
+    int pad;
+    double c;
+};
+
+template <int DIM>
+struct PolyEvalRT {
+    static constexpr int NV = 2 * DIM;
+    const double* __restrict__ tab;      // level-major records, stride doubles per level
+    int stride;
+    __device__ __forceinline__ void launder() { asm volatile("" : "+s"(tab)); }
+
+    template <int V, int B>
+    __device__ __forceinline__ static void step(uint32_t w, double c, double (&a)[NV][B], const double (&y)[NV][B]) {
+        const int gap = int((w >> 5) & 63u), tail = int((w >> 11) & 63u);
+        double t[B];
+        if (w & 8u) {
+#pragma unroll
+            for (int i = 0; i < B; ++i) t[i] = c;
+        } else {
+            if constexpr (V + 1 < NV) {
+#pragma unroll
+                for (int i = 0; i < B; ++i) {
+                    double x = a[V + 1][i];
+                    for (int e = 0; e < tail; ++e) x *= y[V + 1][i];
+                    t[i] = x;
+                }
+            }
+        }
+        if (w & 16u) {
+#pragma unroll
+            for (int i = 0; i < B; ++i) a[V][i] = t[i];
+        } else {
+#pragma unroll
+            for (int i = 0; i < B; ++i) {
+                double yp = y[V][i];
+                for (int e = 1; e < gap; ++e) yp *= y[V][i];
+                a[V][i] = fma(a[V][i], yp, t[i]);
+            }
+        }
+    }
+
+    template <int B>
+    __device__ __forceinline__ static void apply(const PolyRec& r, double (&a)[NV][B], const double (&y)[NV][B],
+                                                 double (&Sl)[B]) {
+        const uint32_t w = uint32_t(r.op);
+        switch (w & 7u) {
+            case 0: step<0, B>(w, r.c, a, y); break;
+            case 1: step<1, B>(w, r.c, a, y); break;
+            case 2: if constexpr (NV > 2) { step<2, B>(w, r.c, a, y); } break;
+            case 3: if constexpr (NV > 3) { step<3, B>(w, r.c, a, y); } break;
+            case 4: if constexpr (NV > 4) { step<4, B>(w, r.c, a, y); } break;
+            case 5: if constexpr (NV > 5) { step<5, B>(w, r.c, a, y); } break;
+            case 7: {
+                const int tail = int((w >> 11) & 63u);
+#pragma unroll
+                for (int i = 0; i < B; ++i) {
+                    double x = a[0][i];
+                    for (int e = 0; e < tail; ++e) x *= y[0][i];
+                    Sl[i] = x;
+                }
+                break;
+            }
+            default: break;
+        }
+    }
+
+    template <int B>
+    __device__ __forceinline__ void eval(int level, const double (&qa)[B][DIM], const double (&qb)[B][DIM],
+                                         double& S) const {
+        const int lv = __builtin_amdgcn_readfirstlane(level);
+        const PolyRec* R = reinterpret_cast<const PolyRec*>(tab + lv * stride);
+        const int n = stride / 2;
+        double y[NV][B], a[NV][B], Sl[B];
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                y[c][i] = qb[i][c] - qa[i][c];
+                y[DIM + c][i] = qa[i][c] + qb[i][c];
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) a[v][i] = 0.0;
+            Sl[i] = 0.0;
+        }
+        for (int o = 0; o < n; o += kPolyRecordGroup) {
+            PolyRec r[kPolyRecordGroup];
+#pragma unroll
+            for (int q = 0; q < kPolyRecordGroup; ++q) r[q] = R[o + q];
+#pragma unroll
+            for (int q = 0; q < kPolyRecordGroup; ++q) apply<B>(r[q], a, y, Sl);
+        }
+#pragma unroll
+        for (int i = 0; i < B; ++i) S += Sl[i];
+    }
+};
+
 // ---------------------------------------------------------------------------- subtree (registers)
 template <int DIM, int U, int L>
 __device__ __forceinline__ void gen_level(const VecArgs& A, const VecSource<DIM>& src, uint32_t root, int D,
@@ -461,6 +567,26 @@ inline int resident_rt(int U, size_t lds, int device) {
         case 2: return resident_one<DIM, 2, RadialEvalRT<DIM>>(lds, device);
         case 3: return resident_one<DIM, 3, RadialEvalRT<DIM>>(lds, device);
         default: return resident_one<DIM, 4, RadialEvalRT<DIM>>(lds, device);
+    }
+}
+
+template <int DIM>
+inline hipError_t launch_poly(const VecArgs& A, int U, int grid, hipStream_t st) {
+    const PolyEvalRT<DIM> ev{A.tab, A.stride};
+    switch (U) {
+        case 1: return launch_one<DIM, 1>(A, ev, grid, st);
+        case 2: return launch_one<DIM, 2>(A, ev, grid, st);
+        case 3: return launch_one<DIM, 3>(A, ev, grid, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int DIM>
+inline int resident_poly(int U, size_t lds, int device) {
+    switch (U) {
+        case 1: return resident_one<DIM, 1, PolyEvalRT<DIM>>(lds, device);
+        case 2: return resident_one<DIM, 2, PolyEvalRT<DIM>>(lds, device);
+        default: return resident_one<DIM, 3, PolyEvalRT<DIM>>(lds, device);
     }
 }
 

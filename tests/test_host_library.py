@@ -215,6 +215,62 @@ def test_radial_level_table_matches_exact_oracle(coefs, dim, m, T, p, level):
                 assert (k, j) in seen, (k, j)
 
 
+COUPLED_2D = [(0.5, (2, 0)), (0.7, (0, 2)), (0.1, (4, 0)), (-0.4, (3, 1)), (0.6, (2, 2)), (-0.4, (1, 3)),
+              (0.1, (0, 4)), (0.3, (1, 0)), (0.2, (1, 1))]        # 0.1 (q1 - q2)^4 + quadratic and linear
+
+
+@pytest.mark.parametrize("terms,dim,m,T,p,level", [
+    (COUPLED_2D, 2, 1.0, 1.0, 6, 2), (COUPLED_2D, 2, 4.0, 2.0, 5, 0),
+    ([(0.5, (2, 0, 0)), (0.2, (0, 2, 1)), (0.05, (1, 1, 2)), (0.3, (0, 0, 2)), (0.1, (0, 0, 1))], 3, 2.0, 1.0, 4, 3),
+    ([(0.2, (0,)), (-0.3, (1,)), (0.5, (2,)), (0.25, (4,))], 1, 1.0, 0.5, 7, 1),
+])
+def test_poly_level_table_matches_exact_oracle(terms, dim, m, T, p, level):
+    """Any polynomial V: the library's FP64 component recursion folded per level agrees monomial by
+    monomial with the oracle's exact eps W_p (the component route), and lists every monomial once."""
+    from oracle import vector as ov
+    coef, exps = P.level_table_poly(terms, dim, m, T, p, level)
+    V = ov.terms_to_components(terms, dim, m)
+    ref = ov.component_level_terms(V, dim, p, Fraction(T) / (1 << level))
+    keys = [tuple(int(x) for x in e) for e in exps]
+    assert len(set(keys)) == len(keys)
+    got = dict(zip(keys, coef))
+    top = max(abs(float(v)) for v in ref.values())
+    for k, v in ref.items():
+        assert abs(got.get(k, 0.0) - float(v)) <= 1e-14 * (abs(float(v)) + top), k
+    for k, c in got.items():
+        if k not in ref:
+            assert abs(c) <= 1e-14 * top, k
+
+
+def test_poly_entry_points_validate_without_a_device():
+    lib = P.load_library()
+    a = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
+    b = (ctypes.c_double * 3)(1.0, 0.0, 0.0)
+    out = (ctypes.c_double * 16)()
+
+    def st(V, N=16, p=4):
+        return lib.pimc_path_actions_poly(None, ctypes.byref(V), 1.0, a, b, 1.0, N, p, 1, 0, 0, 0, 1, out)
+
+    assert st(P.poly_potential([(0.5, (2, 0))], 0)) == -1                  # dim
+    assert st(P.poly_potential([(0.5, (2, 0))], 4)) == -1
+    assert st(P.poly_potential([(0.5, (2, 1, 1))], 2)) == -1               # exponent beyond dim
+    assert st(P.poly_potential([(0.5, (3, 2))], 2)) == -1                  # total degree 5
+    assert st(P.poly_potential([(0.5, (-1, 2))], 2)) == -1                 # negative exponent
+    assert st(P.poly_potential([(float("nan"), (2, 0))], 2)) == -1
+    assert st(P.poly_potential([(0.5, (2, 0))], 2), N=15) == -1
+    assert st(P.poly_potential([(0.5, (2, 0))], 2), p=0) == -1
+    V = P.poly_potential([(0.5, (2, 0))], 2)
+    V.n_terms = 36
+    assert st(V) == -1
+    with pytest.raises(ValueError):
+        P.poly_potential([(0.1, (1, 0))] * 36, 2)
+    need = ctypes.c_size_t(0)
+    V = P.poly_potential([(0.5, (2, 0))], 2)
+    assert lib.pimc_level_table_poly(ctypes.byref(V), 1.0, 1.0, 4, 0, None, 0, None, 0, ctypes.byref(need)) == -1
+    assert need.value == 3                       # x_1^2, xbar_1^2 and the constant of W_{1,0}
+    assert lib.pimc_level_table_poly(ctypes.byref(V), 1.0, 1.0, 4, 0, None, 0, None, 0, None) == -1
+
+
 def test_radial_entry_points_validate_without_a_device():
     lib = P.load_library()
     a = (ctypes.c_double * 3)(0.0, 0.0, 0.0)

@@ -274,3 +274,86 @@ def test_mass_rescaling():
     a = ov.short_time_amplitude(ov.aho2d(1, 0), 2, m, (0.3, -0.2), (0.5, 0.4), 0.4, 12)
     ref = cf.mehler(0.3, 0.5, 0.4, 1.0, m) * cf.mehler(-0.2, 0.4, 0.4, 1.0, m)
     assert abs(a / ref - 1) < 1e-10
+
+
+# ----------------------------------------------------------------------------- any polynomial V
+def _terms_of(C, d):
+    """[(coef, exponents of q)] of a component polynomial with no xbar part."""
+    return [(float(c), k[:d]) for k, c in C.items()]
+
+
+@pytest.mark.parametrize("d,p", [(2, 6), (3, 4)])
+def test_component_slice_action_of_a_radial_V_is_the_invariant_one(d, p):
+    """For V = sum a_n (q.q)^n written out in components, the component-route slice action (fold over
+    m, k of the exact W_{m,k} and term-by-term evaluation) equals the invariant-route tables evaluated
+    by Horner in (u, w^2, z)."""
+    a = (F(1, 3), F(1, 2), F(-1, 4), F(1, 12))
+    V = ov.terms_to_components(_terms_of(ov.radial_to_components(a, d), d), d)
+    rng = np.random.default_rng(3)
+    x = rng.uniform(-1.5, 1.5, (40, d))
+    xb = rng.uniform(-0.4, 0.4, (40, d))
+    for eps in (F(1), F(1, 8)):
+        tab = ov.component_tables(V, d, p, float(eps), 0)[0]
+        got = ov.component_eps_W(tab, x, xb)
+        ref = ov.eps_W(ov.level_tables(a, d, p, float(eps), 0)[0], x, xb)
+        scale = ov.component_eps_W_abs(tab, x, xb)
+        assert np.all(np.abs(got - ref) <= 1e-13 * scale), np.max(np.abs(got - ref) / scale)
+        assert np.all(scale >= np.abs(got) * (1 - 1e-14))
+
+
+def test_component_slice_action_of_a_rotated_separable_V():
+    """Two particles on a line with a pair interaction, V = a (q1 - q2)^4 + c (q1 - q2)^2 + b (q1 + q2)^2,
+    separate in r = (q1 - q2)/sqrt 2, s = (q1 + q2)/sqrt 2 into 4a r^4 + 2c r^2 and 2b s^2. The
+    effective action is covariant under the rotation, so the component route (every cross term
+    q1^i q2^j of W) equals the sum of the one-dimensional actions at the rotated x and xbar."""
+    a, b, c = F(1, 10), F(1, 4), F(1, 8)
+    V = {}
+    for i in range(5):                                    # (q1 - q2)^4
+        V[(i, 4 - i, 0, 0)] = V.get((i, 4 - i, 0, 0), 0) + a * comb(4, i) * (-1) ** (4 - i)
+    for i in range(3):                                    # (q1 - q2)^2 and (q1 + q2)^2
+        V[(i, 2 - i, 0, 0)] = V.get((i, 2 - i, 0, 0), 0) + (c * (-1) ** (2 - i) + b) * comb(2, i)
+    V = {k: v for k, v in V.items() if v}
+    p, eps = 6, 0.3
+    tab = ov.component_tables(V, 2, p, eps, 0)[0]
+    rng = np.random.default_rng(5)
+    x = rng.uniform(-1.5, 1.5, (40, 2))
+    xb = rng.uniform(-0.4, 0.4, (40, 2))
+    got = ov.component_eps_W(tab, x, xb)
+    r2 = math.sqrt(2.0)
+    tr = opimc.level_tables(ea.poly([0, 0, 2 * c, 0, 4 * a]), p, eps, 0)[0]
+    ts = opimc.level_tables(ea.poly([0, 0, 2 * b]), p, eps, 0)[0]
+    ref = (opimc.eps_W(tr, (x[:, 0] - x[:, 1]) / r2, (xb[:, 0] - xb[:, 1]) / r2)
+           + opimc.eps_W(ts, (x[:, 0] + x[:, 1]) / r2, (xb[:, 0] + xb[:, 1]) / r2))
+    scale = ov.component_eps_W_abs(tab, x, xb)
+    assert np.all(np.abs(got - ref) <= 1e-13 * scale + 1e-15), np.max(np.abs(got - ref))
+    # the cross terms matter: dropping them changes the action
+    keep = np.array([not (e[0] and e[1]) and not (e[2] and e[3]) for e in tab[0]])
+    part = ov.component_eps_W((tab[0][keep], tab[1][keep]), x, xb)
+    assert np.max(np.abs(part - ref)) > 1e-3
+
+
+def test_component_paths_and_mass_equal_the_radial_route():
+    """Path actions of the component route for a rotation-invariant V (mass 4, d = 2) equal those of
+    the invariant route level by level (same paths, same tables up to rounding); the level-0 amplitude
+    is the short-time amplitude."""
+    a = (0.0, 0.5, 0.25)
+    d, m, qa, qb, T, s, p = 2, 4.0, (0.1, -0.2), (0.3, 0.4), 1.0, 4, 6
+    terms = _terms_of(ov.radial_to_components(a, d), d)
+    S, scale = ov.poly_path_actions(terms, d, m, qa, qb, T, s, p, 7, 3, np.arange(20, 84), with_scale=True)
+    ref = ov.path_actions(a, d, m, qa, qb, T, s, p, 7, 3, np.arange(20, 84))
+    assert np.all(np.abs(S - ref) <= 1e-13 * scale)
+    amp = ov.poly_amplitude(terms, d, m, qa, qb, T, 2, p, 256, 7, 3)
+    assert amp[0]["amp"] == pytest.approx(ov.short_time_amplitude(a, d, m, qa, qb, T, p), rel=1e-13)
+    ref_amp = ov.amplitude(a, d, m, qa, qb, T, 2, p, 256, 7, 3)
+    for n in (1, 2):
+        assert amp[n]["amp"] == pytest.approx(ref_amp[n]["amp"], rel=1e-12)
+
+
+def test_one_coordinate_component_route_is_the_one_dimensional_path_action():
+    """d = 1: the component route on V = sum c_n q^n gives the one-dimensional path actions (same
+    paths: coordinate 0 draws the one-dimensional normals)."""
+    coefs = [0.2, -0.3, 0.5, 0.1, 0.25]
+    terms = [(c, (n,)) for n, c in enumerate(coefs)]
+    S, scale = ov.poly_path_actions(terms, 1, 2.0, (0.3,), (-0.4,), 1.0, 4, 5, 9, 1, np.arange(40), with_scale=True)
+    ref = opimc.path_actions(ea.poly(coefs), 2.0, 0.3, -0.4, 1.0, 4, 5, 9, 1, np.arange(40))
+    assert np.all(np.abs(S - ref) <= 1e-13 * scale)
