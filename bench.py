@@ -63,7 +63,7 @@ RADIAL_E = {18: 102}                     # coefficients of the (u, z, w^2) table
 # Any polynomial V (component route): two particles on a line with a quartic pair interaction
 # 0.1 (q1 - q2)^4 in an anisotropic trap with a field (d = 2, p = 10), and an anisotropic 3D trap with
 # cubic and quartic couplings (d = 3, p = 8); one s = 10 run each (every level).
-COMPONENT = dict(T=1.0, s=10, samples=10_000_000, cases=[
+COMPONENT = dict(T=1.0, s=10, samples=4_000_000, cases=[
     dict(name="pair (q1-q2)^4 + trap, d=2", dim=2, p=10, a=(0.0, 0.0), b=(1.0, 0.4),
          terms=[(0.5, (2, 0)), (0.7, (0, 2)), (0.1, (4, 0)), (-0.4, (3, 1)), (0.6, (2, 2)), (-0.4, (1, 3)),
                 (0.1, (0, 4)), (0.3, (1, 0)), (0.2, (1, 1))]),

@@ -109,10 +109,14 @@ inline size_t vec_lds_bytes(int dim, int D, int s) {
            sizeof(double);
 }
 
-// Component evaluator (any polynomial V): per level, records of 16 bytes {op word, pad, coefficient}
-// (layout in pimc_vector_impl.hpp, PolyEvalRT), consumed kPolyRecordGroup at a time.
-constexpr int kPolyRecordGroup = 4;
-constexpr int kPolyMaxRecords = 1 << 18;
+// Component evaluator (any polynomial V): a level-independent structure stream (A.shape, ints) and
+// per-level coefficient arrays (A.tab, A.stride doubles per level); layout in pimc_vector_impl.hpp,
+// PolyEvalRT.
+#ifndef PIMC_POLY_U
+#define PIMC_POLY_U 3
+#endif
+constexpr int kPolyU = PIMC_POLY_U;     // register-subtree levels of the component evaluator
+constexpr int kPolyMaxSlots = 1 << 20;  // coefficient slots per level
 
 // Launch the vector estimation kernel: dim 1..3; U = min(s, kVecU); `specialized` selects the
 // evaluator with the compile-time shape of level p (dim 2 or 3, U = kVecU), else the evaluator
@@ -120,7 +124,7 @@ constexpr int kPolyMaxRecords = 1 << 18;
 hipError_t launch_vector(const VecArgs& A, int dim, int p, int U, bool specialized, int grid, hipStream_t st);
 int vector_resident_blocks(int dim, int p, int U, bool specialized, size_t lds_bytes, int device);
 
-// The component evaluator: A.tab = records (A.stride doubles per level, 2 per record).
+// The component evaluator: A.tab = coefficients, A.shape = structure stream.
 hipError_t launch_vector_poly(const VecArgs& A, int dim, int U, int grid, hipStream_t st);
 int vector_poly_resident(int dim, int U, size_t lds_bytes, int device);
 

@@ -35,7 +35,6 @@ using namespace pimc_host;
 
 static_assert(PIMC_MAX_DIM == kVecMaxDim, "dimension limit of the public header");
 static_assert(PIMC_MAX_RADIAL_DEGREE == 2, "the table shape bound covers u-degree <= 2");
-static_assert(PIMC_POLY_MAX_MONOMIALS <= kPolyMaxRecords, "records of the component evaluator");
 
 namespace {
 
@@ -607,97 +606,93 @@ struct PolyCoefficients {
 // Exponent of device variable v in a monomial.
 int var_exp(const MKey& k, int d, int v) { return v < d ? k[size_t(kXb + v)] : k[size_t(v - d)]; }
 
-// Records of the component evaluator (pimc_vector_impl.hpp, PolyEvalRT): a post-order walk of the
-// prefix tree of the monomials ordered by the exponents of y_0, y_1, ... from high to low. A node at
-// depth v sums its children (one per exponent k of y_v, descending) by Horner in y_v; a leaf child
-// is a coefficient, an internal child the finished node value a_{v+1} y_{v+1}^tail.
-struct RecTree {
-    std::vector<uint32_t> ops;                   // op word per record
-    std::vector<int> leaf;                       // per record: index into keys of its coefficient, or -1
+// Structure stream and coefficient slots of the component evaluator (pimc_vector_impl.hpp,
+// PolyEvalRT): the prefix tree of the monomials ordered by the exponents of y_0, y_1, ... from high
+// to low, in pre-order; the last variable's chains are dense (absent exponents get a zero slot).
+struct PolyCode {
+    std::vector<int> code;                       // structure stream
+    std::vector<int> slot;                       // per coefficient slot: index into keys, or -1 (zero)
 };
 
-int emit_poly_node(const std::vector<MKey>& keys, size_t r0, size_t r1, int v, int nv, int d, RecTree& T, bool& ok) {
+// Emit the node over keys[r0, r1) at depth v; returns its lowest exponent of y_v (the tail its
+// parent applies).
+int emit_poly_node(const std::vector<MKey>& keys, size_t r0, size_t r1, int v, int nv, int d, PolyCode& P, bool& ok) {
+    if (v == nv - 1) {
+        const int hi = var_exp(keys[r0], d, v), lo = var_exp(keys[r1 - 1], d, v);
+        P.code.push_back(hi - lo + 1);
+        size_t g = r0;
+        for (int e = hi; e >= lo; --e) {
+            if (g < r1 && var_exp(keys[g], d, v) == e) {
+                P.slot.push_back(int(g));
+                ++g;
+            } else {
+                P.slot.push_back(-1);
+            }
+        }
+        if (g != r1) ok = false;                 // two monomials with one exponent vector
+        return lo;
+    }
+    int groups = 0;
+    for (size_t g0 = r0; g0 < r1; ++groups) {
+        const int k = var_exp(keys[g0], d, v);
+        while (g0 < r1 && var_exp(keys[g0], d, v) == k) ++g0;
+    }
+    P.code.push_back(groups);
     int prev = -1;
-    bool first = true;
     for (size_t g0 = r0; g0 < r1;) {
         const int k = var_exp(keys[g0], d, v);
         size_t g1 = g0;
         while (g1 < r1 && var_exp(keys[g1], d, v) == k) ++g1;
-        uint32_t op = uint32_t(v);
-        int tail = 0, leaf = -1;
-        if (v == nv - 1) {
-            if (g1 - g0 != 1) ok = false;        // a leaf group holds exactly one monomial
-            op |= 8u;
-            leaf = int(g0);
-        } else {
-            tail = emit_poly_node(keys, g0, g1, v + 1, nv, d, T, ok);
-        }
-        const int gap = first ? 0 : prev - k;
-        if (gap > 63 || tail > 63) ok = false;
-        if (first) op |= 16u;
-        op |= uint32_t(gap) << 5;
-        op |= uint32_t(tail) << 11;
-        T.ops.push_back(op);
-        T.leaf.push_back(leaf);
+        const size_t h = P.code.size();
+        P.code.push_back(0);
+        const int tail = emit_poly_node(keys, g0, g1, v + 1, nv, d, P, ok);
+        const int gap = prev < 0 ? 1 : prev - k;
+        if (gap < 1 || gap > 255 || tail > 255) ok = false;
+        P.code[h] = gap | (tail << 8);
         prev = k;
-        first = false;
         g0 = g1;
     }
-    return prev;                                 // the node's lowest exponent of y_v
+    return prev;
 }
 
-// Post-order records of the whole polynomial, ending with the finish record (op 7) and padded with
-// no-op records (op 6) to a multiple of kPolyRecordGroup.
-bool build_records(const std::vector<MKey>& keys, int d, RecTree& T) {
-    T.ops.clear();
-    T.leaf.clear();
+bool build_poly_code(const std::vector<MKey>& keys, int d, PolyCode& P) {
+    P.code.assign(1, 0);
+    P.slot.clear();
     bool ok = true;
-    const int nv = 2 * d;
-    int tail0 = 0;
-    if (!keys.empty()) tail0 = emit_poly_node(keys, 0, keys.size(), 0, nv, d, T, ok);
-    if (tail0 > 63) ok = false;
-    if (!keys.empty()) {
-        T.ops.push_back(7u | (uint32_t(tail0) << 11));
-        T.leaf.push_back(-1);
+    if (keys.empty()) {
+        P.code.push_back(0);                     // a root without children: eps W_p = 0
+        return true;
     }
-    while (T.ops.size() % kPolyRecordGroup) {
-        T.ops.push_back(6u);
-        T.leaf.push_back(-1);
-    }
+    P.code[0] = emit_poly_node(keys, 0, keys.size(), 0, 2 * d, d, P, ok);
     return ok;
 }
 
 // The same arithmetic as PolyEvalRT on one slice (y as defined above), for the reference actions.
-double eval_records(const std::vector<uint32_t>& ops, const std::vector<double>& coef, const double* y) {
-    double a[2 * kVecMaxDim] = {0, 0, 0, 0, 0, 0};
-    double S = 0.0;
-    for (size_t o = 0; o < ops.size(); ++o) {
-        const uint32_t w = ops[o];
-        const int v = int(w & 7u);
-        const int gap = int((w >> 5) & 63u), tail = int((w >> 11) & 63u);
-        if (v == 6) continue;
-        if (v == 7) {
-            double x = a[0];
-            for (int e = 0; e < tail; ++e) x *= y[0];
-            S += x;
-            continue;
-        }
-        double t;
-        if (w & 8u) {
-            t = coef[o];
-        } else {
-            t = a[v + 1];
-            for (int e = 0; e < tail; ++e) t *= y[v + 1];
-        }
-        if (w & 16u) {
-            a[v] = t;
-        } else {
-            double yp = y[v];
-            for (int e = 1; e < gap; ++e) yp *= y[v];
-            a[v] = std::fma(a[v], yp, t);
-        }
+double eval_poly_node(const std::vector<int>& code, size_t& s, const double* coef, size_t& c, const double* y, int v,
+                      int nv) {
+    double a = 0.0;
+    if (v == nv - 1) {
+        const int L = code[s++];
+        for (int j = 0; j < L; ++j) a = std::fma(a, y[v], coef[c + size_t(j)]);
+        c += size_t(L);
+        return a;
     }
-    return S;
+    const int n = code[s++];
+    for (int k = 0; k < n; ++k) {
+        const int h = code[s++];
+        for (int e = 1; e < (h & 255); ++e) a *= y[v];
+        double t = eval_poly_node(code, s, coef, c, y, v + 1, nv);
+        for (int e = 0; e < (h >> 8); ++e) t *= y[v + 1];
+        a = std::fma(a, y[v], t);
+    }
+    return a;
+}
+
+double eval_poly_code(const std::vector<int>& code, const double* coef, const double* y, int nv) {
+    size_t s = 1, c = 0;
+    double x = eval_poly_node(code, s, coef, c, y, 0, nv);
+    for (int e = 0; e < code[0]; ++e) x *= y[0];
+    return x;
 }
 
 std::string poly_cache_key(const pimc_poly_potential* V, double m, int p) {
@@ -819,7 +814,7 @@ int build_poly_problem(const pimc_poly_potential* V, double m, const double* a, 
     }
     P.pref = std::pow(sm, double(P.dim));
     P.K0 = std::exp(-r2 / (2.0 * T)) / std::pow(2.0 * kPi * T, 0.5 * double(P.dim));
-    P.U = std::min(P.s, kVecU);
+    P.U = std::min(P.s, kPolyU);
     P.D = P.s - P.U;
     P.specialized = false;
     const PolyCoefficients& C = cached_poly(V, m, p);
@@ -827,30 +822,25 @@ int build_poly_problem(const pimc_poly_potential* V, double m, const double* a, 
         std::snprintf(why, whylen, "eps W_p has %zu monomials (limit %d)", C.keys.size(), PIMC_POLY_MAX_MONOMIALS);
         return PIMC_EUNSUPPORTED;
     }
-    RecTree R;
-    if (!build_records(C.keys, P.dim, R)) {
-        std::snprintf(why, whylen, "internal: a monomial exponent above 63");
+    PolyCode R;
+    if (!build_poly_code(C.keys, P.dim, R) || R.slot.size() > size_t(kPolyMaxSlots)) {
+        std::snprintf(why, whylen, "internal: the monomials do not fit the component evaluator");
         return PIMC_EUNSUPPORTED;
     }
-    const size_t nrec = R.ops.size();
-    P.stride = int(2 * nrec);                    // doubles per level: (op word, coefficient) per record
-    P.tab.assign(size_t(P.s + 1) * size_t(P.stride), 0.0);
+    const size_t nslot = R.slot.size();
+    P.stride = int(nslot);                       // coefficient slots per level
+    P.tab.assign(size_t(P.s + 1) * nslot, 0.0);
     P.shift.assign(size_t(P.s + 1), 0.0);
-    std::vector<double> coef(nrec, 0.0);
+    const int nv = 2 * P.dim;
     for (int n = 0; n <= P.s; ++n) {
         const std::vector<double> f = fold_poly(C, std::ldexp(T, -n));
-        for (size_t o = 0; o < nrec; ++o) {
-            coef[o] = 0.0;
-            if (R.leaf[o] >= 0) {
-                const MKey& k = C.keys[size_t(R.leaf[o])];
-                int deg = 0;
-                for (int c = 0; c < 2 * kVecMaxDim; ++c) deg += k[size_t(c)];
-                coef[o] = std::ldexp(f[size_t(R.leaf[o])], -deg);   // y = 2 x, 2 xbar
-            }
-            double* rec = P.tab.data() + size_t(n) * size_t(P.stride) + 2 * o;
-            uint64_t bits = R.ops[o];
-            std::memcpy(&rec[0], &bits, 8);
-            rec[1] = coef[o];
+        double* coef = P.tab.data() + size_t(n) * nslot;
+        for (size_t o = 0; o < nslot; ++o) {
+            if (R.slot[o] < 0) continue;
+            const MKey& k = C.keys[size_t(R.slot[o])];
+            int deg = 0;
+            for (int c = 0; c < 2 * kVecMaxDim; ++c) deg += k[size_t(c)];
+            coef[o] = std::ldexp(f[size_t(R.slot[o])], -deg);   // y = 2 x, 2 xbar
         }
         const int M = 1 << n;
         double S = 0.0;
@@ -862,13 +852,13 @@ int build_poly_problem(const pimc_poly_potential* V, double m, const double* a, 
                 y[c] = q1 - q0;
                 y[P.dim + c] = q0 + q1;
             }
-            S += eval_records(R.ops, coef, y);
+            S += eval_poly_code(R.code, coef, y, nv);
         }
         P.shift[size_t(n)] = S;
     }
     P.tab_dev = P.tab;
     P.level0_action = P.shift[0];
-    P.shape.assign(1, int(nrec));
+    P.shape = R.code;
     P.sig.assign(size_t(P.s + 1), 0.0);
     for (int n = 1; n <= P.s; ++n) P.sig[size_t(n)] = std::sqrt(T / std::ldexp(1.0, n + 1));
     return PIMC_OK;
@@ -1025,11 +1015,14 @@ int pimc_level_table_poly(const pimc_poly_potential* V, double m, double T, int 
     if (level > PIMC_MAX_S) { set_thread_error("level > %d", PIMC_MAX_S); return PIMC_EINVAL; }
     if (!n_out) { set_thread_error("n_out is NULL"); return PIMC_EINVAL; }
     const PolyCoefficients& C = cached_poly(V, m, p);
-    RecTree R;
-    if (!build_records(C.keys, V->dim, R)) { set_thread_error("internal: a monomial exponent above 63"); return PIMC_EUNSUPPORTED; }
+    PolyCode R;
+    if (!build_poly_code(C.keys, V->dim, R)) {
+        set_thread_error("internal: the monomials do not fit the component evaluator");
+        return PIMC_EUNSUPPORTED;
+    }
     const std::vector<double> f = fold_poly(C, std::ldexp(T, -int(level)));
     size_t n = 0;
-    for (int l : R.leaf) n += l >= 0 ? 1 : 0;
+    for (int l : R.slot) n += l >= 0 ? 1 : 0;
     *n_out = n;
     const size_t nv = size_t(2 * V->dim);
     if (cap < n || exps_cap < n * nv || !coef || !exps) {
@@ -1037,7 +1030,7 @@ int pimc_level_table_poly(const pimc_poly_potential* V, double m, double T, int 
         return PIMC_EINVAL;
     }
     size_t i = 0;
-    for (int l : R.leaf) {
+    for (int l : R.slot) {
         if (l < 0) continue;
         const MKey& k = C.keys[size_t(l)];
         coef[i] = f[size_t(l)];

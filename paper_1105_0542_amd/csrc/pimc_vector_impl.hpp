@@ -175,108 +175,101 @@ struct RadialEvalRT {
 };
 
 // Any polynomial V (component route): eps W_p of a slice is a polynomial in the 2 DIM variables
-// y_c = qb_c - qa_c (c < DIM) and y_{DIM+c} = qa_c + qb_c, given as records {op, pad, coefficient} in
-// a post-order walk of the prefix tree of its monomials (exponents of y_0, y_1, ... from high to low).
-// op bits: 0..2 the depth v (6: no-op, 7: finish), 3 leaf, 4 first, 5..10 gap, 11..16 tail. A record
-// at depth v adds one child to the Horner sum a_v over the exponents of y_v:
-//     t = leaf ? coefficient : a_{v+1} y_{v+1}^tail,   a_v = first ? t : a_v y_v^gap + t,
-// and the finish record adds a_0 y_0^tail to S. Records are read kPolyRecordGroup at a time (one
-// 64-byte scalar load); the depth selects the accumulator through a switch (wave-uniform).
-struct PolyRec {
-    int op;
-    int pad;
-    double c;
-};
-
+// y_c = qb_c - qa_c (c < DIM) and y_{DIM+c} = qa_c + qb_c, evaluated by a multivariate Horner scheme
+// over the prefix tree of its monomials (exponents of y_0, y_1, ... from high to low). The tree is a
+// level-independent structure stream of ints (pre-order); only the coefficients depend on the level.
+//   node at depth v < 2 DIM - 1:  [n children] then per child [gap | tail << 8] and the child's node;
+//       a_v = 0; per child: a_v = a_v y_v^gap + (child value) y_{v+1}^tail  (gap = 1 for the first);
+//   node at depth 2 DIM - 1:      [L]: the dense Horner chain in y_{2 DIM - 1} over the next L
+//       coefficients of the level's array (zeros fill the exponents that are absent);
+//   stream head: [tail of the root]; the slice value is a_0 y_0^tail.
+// Every count and exponent is wave-uniform (scalar loads through the constant address space), so the
+// depth-nested loops are scalar branches around B-wide vector FMAs; a_v and the running pointers have
+// one register home per depth (no interpreter dispatch, no copies between depths).
 template <int DIM>
 struct PolyEvalRT {
     static constexpr int NV = 2 * DIM;
-    const double* __restrict__ tab;      // level-major records, stride doubles per level
+    const double* __restrict__ tab;      // coefficients, level-major, stride doubles per level
+    const int* __restrict__ code;        // structure stream
     int stride;
-    __device__ __forceinline__ void launder() { asm volatile("" : "+s"(tab)); }
+    __device__ __forceinline__ void launder() { asm volatile("" : "+s"(tab), "+s"(code)); }
 
-    template <int V, int B>
-    __device__ __forceinline__ static void step(uint32_t w, double c, double (&a)[NV][B], const double (&y)[NV][B]) {
-        const int gap = int((w >> 5) & 63u), tail = int((w >> 11) & 63u);
-        double t[B];
-        if (w & 8u) {
+    // x[i] *= y[i]^e for a wave-uniform e >= 0 (a scalar loop around B multiplies).
+    template <int B>
+    __device__ __forceinline__ static void times_pow(double (&x)[B], const double (&y)[B], int e) {
+        for (int k = 0; k < e; ++k) {
 #pragma unroll
-            for (int i = 0; i < B; ++i) t[i] = c;
-        } else {
-            if constexpr (V + 1 < NV) {
-#pragma unroll
-                for (int i = 0; i < B; ++i) {
-                    double x = a[V + 1][i];
-                    for (int e = 0; e < tail; ++e) x *= y[V + 1][i];
-                    t[i] = x;
-                }
-            }
-        }
-        if (w & 16u) {
-#pragma unroll
-            for (int i = 0; i < B; ++i) a[V][i] = t[i];
-        } else {
-#pragma unroll
-            for (int i = 0; i < B; ++i) {
-                double yp = y[V][i];
-                for (int e = 1; e < gap; ++e) yp *= y[V][i];
-                a[V][i] = fma(a[V][i], yp, t[i]);
-            }
+            for (int i = 0; i < B; ++i) x[i] *= y[i];
         }
     }
 
-    template <int B>
-    __device__ __forceinline__ static void apply(const PolyRec& r, double (&a)[NV][B], const double (&y)[NV][B],
-                                                 double (&Sl)[B]) {
-        const uint32_t w = uint32_t(r.op);
-        switch (w & 7u) {
-            case 0: step<0, B>(w, r.c, a, y); break;
-            case 1: step<1, B>(w, r.c, a, y); break;
-            case 2: if constexpr (NV > 2) { step<2, B>(w, r.c, a, y); } break;
-            case 3: if constexpr (NV > 3) { step<3, B>(w, r.c, a, y); } break;
-            case 4: if constexpr (NV > 4) { step<4, B>(w, r.c, a, y); } break;
-            case 5: if constexpr (NV > 5) { step<5, B>(w, r.c, a, y); } break;
-            case 7: {
-                const int tail = int((w >> 11) & 63u);
+    template <int V, int B>
+    __device__ __forceinline__ static void node(const_ptr<int>& s, const_ptr<double>& c, const double (&y)[NV][B],
+                                                double (&out)[B]) {
+        double a[B];
 #pragma unroll
-                for (int i = 0; i < B; ++i) {
-                    double x = a[0][i];
-                    for (int e = 0; e < tail; ++e) x *= y[0][i];
-                    Sl[i] = x;
-                }
-                break;
+        for (int i = 0; i < B; ++i) a[i] = 0.0;
+        if constexpr (V == NV - 1) {
+            const int L = s[0];
+            s += 1;
+            int j = 0;
+            for (; j + 4 <= L; j += 4) {
+                const double c0 = c[j], c1 = c[j + 1], c2 = c[j + 2], c3 = c[j + 3];
+#pragma unroll
+                for (int i = 0; i < B; ++i) a[i] = fma(a[i], y[V][i], c0);
+#pragma unroll
+                for (int i = 0; i < B; ++i) a[i] = fma(a[i], y[V][i], c1);
+#pragma unroll
+                for (int i = 0; i < B; ++i) a[i] = fma(a[i], y[V][i], c2);
+#pragma unroll
+                for (int i = 0; i < B; ++i) a[i] = fma(a[i], y[V][i], c3);
             }
-            default: break;
+            for (; j < L; ++j) {
+                const double c0 = c[j];
+#pragma unroll
+                for (int i = 0; i < B; ++i) a[i] = fma(a[i], y[V][i], c0);
+            }
+            c += L;
+        } else {
+            const int n = s[0];
+            s += 1;
+            for (int k = 0; k < n; ++k) {
+                const int h = s[0];
+                s += 1;
+                times_pow<B>(a, y[V], (h & 255) - 1);
+                double t[B];
+                node<V + 1, B>(s, c, y, t);
+                times_pow<B>(t, y[V + 1], h >> 8);
+#pragma unroll
+                for (int i = 0; i < B; ++i) a[i] = fma(a[i], y[V][i], t[i]);
+            }
         }
+#pragma unroll
+        for (int i = 0; i < B; ++i) out[i] = a[i];
     }
 
     template <int B>
     __device__ __forceinline__ void eval(int level, const double (&qa)[B][DIM], const double (&qb)[B][DIM],
                                          double& S) const {
         const int lv = __builtin_amdgcn_readfirstlane(level);
-        const PolyRec* R = reinterpret_cast<const PolyRec*>(tab + lv * stride);
-        const int n = stride / 2;
-        double y[NV][B], a[NV][B], Sl[B];
+        const_ptr<double> c = as_const(tab) + lv * stride;
+        const_ptr<int> s = as_const(code);
+        double y[NV][B];
 #pragma unroll
         for (int i = 0; i < B; ++i) {
 #pragma unroll
-            for (int c = 0; c < DIM; ++c) {
-                y[c][i] = qb[i][c] - qa[i][c];
-                y[DIM + c][i] = qa[i][c] + qb[i][c];
+            for (int k = 0; k < DIM; ++k) {
+                y[k][i] = qb[i][k] - qa[i][k];
+                y[DIM + k][i] = qa[i][k] + qb[i][k];
             }
-#pragma unroll
-            for (int v = 0; v < NV; ++v) a[v][i] = 0.0;
-            Sl[i] = 0.0;
         }
-        for (int o = 0; o < n; o += kPolyRecordGroup) {
-            PolyRec r[kPolyRecordGroup];
+        const int tail = s[0];
+        s += 1;
+        double v[B];
+        node<0, B>(s, c, y, v);
+        times_pow<B>(v, y[0], tail);
 #pragma unroll
-            for (int q = 0; q < kPolyRecordGroup; ++q) r[q] = R[o + q];
-#pragma unroll
-            for (int q = 0; q < kPolyRecordGroup; ++q) apply<B>(r[q], a, y, Sl);
-        }
-#pragma unroll
-        for (int i = 0; i < B; ++i) S += Sl[i];
+        for (int i = 0; i < B; ++i) S += v[i];
     }
 };
 
@@ -572,7 +565,7 @@ inline int resident_rt(int U, size_t lds, int device) {
 
 template <int DIM>
 inline hipError_t launch_poly(const VecArgs& A, int U, int grid, hipStream_t st) {
-    const PolyEvalRT<DIM> ev{A.tab, A.stride};
+    const PolyEvalRT<DIM> ev{A.tab, A.shape, A.stride};
     switch (U) {
         case 1: return launch_one<DIM, 1>(A, ev, grid, st);
         case 2: return launch_one<DIM, 2>(A, ev, grid, st);
