@@ -276,12 +276,16 @@ def oracle_vector_reference():
 
 
 def _fit_continuum(levels, p):
-    """Weighted least squares of eq.(fit), A_N = A + B/N^p + C/N^(p+1), over the given levels
-    (N = 2^n >= 4); returns (A, its standard error)."""
+    """Weighted least squares of eq.(fit), A_N = A + B/N^p + C/N^(p+1), over the given levels with
+    N = 2^n >= 16 (at T = 5 the levels N = 4, 8 carry higher orders than the two terms of the model);
+    returns (A, its standard error). The levels of one run share their paths, so
+    their errors are correlated: A = sum_n h_n A_N is linear in the levels, and the error returned is
+    sum_n |h_n| err_N, the bound that holds for any correlation (the independent-error formula
+    understates it by a factor of about 2.5 here)."""
     rows, rhs, w = [], [], []
     for n, r in levels:
         N = float(1 << n)
-        if N < 4 or r.err <= 0:
+        if N < 16 or r.err <= 0:
             continue
         rows.append([1.0, N ** -p, N ** -(p + 1)])
         rhs.append(r.amp)
@@ -289,8 +293,8 @@ def _fit_continuum(levels, p):
     X = np.array(rows) * np.array(w)[:, None]
     y = np.array(rhs) * np.array(w)
     coef, *_ = np.linalg.lstsq(X, y, rcond=None)
-    cov = np.linalg.pinv(X.T @ X)
-    return float(coef[0]), float(math.sqrt(max(cov[0, 0], 0.0)))
+    h = np.linalg.pinv(X)[0]                  # A = sum_n h_n w_n A_N, and w_n err_N = 1
+    return float(coef[0]), float(np.sum(np.abs(h)))
 
 
 def mpt_section(P, ctx, dvr, base=None):
