@@ -186,6 +186,11 @@ struct RadialEvalRT {
 // Every count and exponent is wave-uniform (scalar loads through the constant address space), so the
 // depth-nested loops are scalar branches around B-wide vector FMAs; a_v and the running pointers have
 // one register home per depth (no interpreter dispatch, no copies between depths).
+#ifndef PIMC_POLY_UNROLL
+#define PIMC_POLY_UNROLL 4
+#endif
+constexpr int kPolyUnroll = PIMC_POLY_UNROLL;   // coefficients per scalar load group of a chain
+
 template <int DIM>
 struct PolyEvalRT {
     static constexpr int NV = 2 * DIM;
@@ -213,16 +218,15 @@ struct PolyEvalRT {
             const int L = s[0];
             s += 1;
             int j = 0;
-            for (; j + 4 <= L; j += 4) {
-                const double c0 = c[j], c1 = c[j + 1], c2 = c[j + 2], c3 = c[j + 3];
+            for (; j + kPolyUnroll <= L; j += kPolyUnroll) {
+                double cq[kPolyUnroll];
 #pragma unroll
-                for (int i = 0; i < B; ++i) a[i] = fma(a[i], y[V][i], c0);
+                for (int q = 0; q < kPolyUnroll; ++q) cq[q] = c[j + q];
 #pragma unroll
-                for (int i = 0; i < B; ++i) a[i] = fma(a[i], y[V][i], c1);
+                for (int q = 0; q < kPolyUnroll; ++q) {
 #pragma unroll
-                for (int i = 0; i < B; ++i) a[i] = fma(a[i], y[V][i], c2);
-#pragma unroll
-                for (int i = 0; i < B; ++i) a[i] = fma(a[i], y[V][i], c3);
+                    for (int i = 0; i < B; ++i) a[i] = fma(a[i], y[V][i], cq[q]);
+                }
             }
             for (; j < L; ++j) {
                 const double c0 = c[j];
