@@ -1082,6 +1082,8 @@ def summarize(line):
         out["general"]["p18"] = {"rate": _r(g18["slice_evals_per_s"]), "frac": _r(g18["roofline"]["frac"]),
                                  "diff_vs_p8_sigma": _r(g18["diff_vs_p8_in_sigma"], 3)}
     out["vector"] = {d: {"rate": _r(r["slice_evals_per_s"]), "frac": _r(r["fp64_frac"])} for d, r in line["vector"]["per_dim"].items()}
+    out["vector"]["component"] = [{"rate": _r(r["slice_evals_per_s"]), "frac": _r(r["fp64_frac"])}
+                                  for r in line["vector"].get("component", [])]
     out["spectrum"] = [{"matrix_ms": _r(r["matrix_ms"]), "lanczos_ms_per_step": _r(r["lanczos_ms_per_step"]),
                         "max_abs_diff_vs_dvr": _r(r.get("max_abs_diff_vs_dvr"), 3)} for r in line["spectrum"]]
     return out
