@@ -655,14 +655,13 @@ int emit_poly_node(const std::vector<MKey>& keys, size_t r0, size_t r1, int v, i
     return prev;
 }
 
+// keys must not be empty (a polynomial without monomials is given the constant monomial, whose
+// coefficient is then 0): every node has a child and every chain a coefficient.
 bool build_poly_code(const std::vector<MKey>& keys, int d, PolyCode& P) {
     P.code.assign(1, 0);
     P.slot.clear();
+    if (keys.empty()) return false;
     bool ok = true;
-    if (keys.empty()) {
-        P.code.push_back(0);                     // a root without children: eps W_p = 0
-        return true;
-    }
     P.code[0] = emit_poly_node(keys, 0, keys.size(), 0, 2 * d, d, P, ok);
     return ok;
 }
@@ -670,15 +669,18 @@ bool build_poly_code(const std::vector<MKey>& keys, int d, PolyCode& P) {
 // The same arithmetic as PolyEvalRT on one slice (y as defined above), for the reference actions.
 double eval_poly_node(const std::vector<int>& code, size_t& s, const double* coef, size_t& c, const double* y, int v,
                       int nv) {
-    double a = 0.0;
     if (v == nv - 1) {
         const int L = code[s++];
-        for (int j = 0; j < L; ++j) a = std::fma(a, y[v], coef[c + size_t(j)]);
+        double a = coef[c];
+        for (int j = 1; j < L; ++j) a = std::fma(a, y[v], coef[c + size_t(j)]);
         c += size_t(L);
         return a;
     }
     const int n = code[s++];
-    for (int k = 0; k < n; ++k) {
+    const int h0 = code[s++];
+    double a = eval_poly_node(code, s, coef, c, y, v + 1, nv);
+    for (int e = 0; e < (h0 >> 8); ++e) a *= y[v + 1];
+    for (int k = 1; k < n; ++k) {
         const int h = code[s++];
         for (int e = 1; e < (h & 255); ++e) a *= y[v];
         double t = eval_poly_node(code, s, coef, c, y, v + 1, nv);
@@ -822,8 +824,9 @@ int build_poly_problem(const pimc_poly_potential* V, double m, const double* a, 
         std::snprintf(why, whylen, "eps W_p has %zu monomials (limit %d)", C.keys.size(), PIMC_POLY_MAX_MONOMIALS);
         return PIMC_EUNSUPPORTED;
     }
+    const std::vector<MKey> keys = C.keys.empty() ? std::vector<MKey>(1, MKey{}) : C.keys;
     PolyCode R;
-    if (!build_poly_code(C.keys, P.dim, R) || R.slot.size() > size_t(kPolyMaxSlots)) {
+    if (!build_poly_code(keys, P.dim, R) || R.slot.size() > size_t(kPolyMaxSlots)) {
         std::snprintf(why, whylen, "internal: the monomials do not fit the component evaluator");
         return PIMC_EUNSUPPORTED;
     }
@@ -836,7 +839,7 @@ int build_poly_problem(const pimc_poly_potential* V, double m, const double* a, 
         const std::vector<double> f = fold_poly(C, std::ldexp(T, -n));
         double* coef = P.tab.data() + size_t(n) * nslot;
         for (size_t o = 0; o < nslot; ++o) {
-            if (R.slot[o] < 0) continue;
+            if (R.slot[o] < 0 || C.keys.empty()) continue;          // no monomials: the one slot is 0
             const MKey& k = C.keys[size_t(R.slot[o])];
             int deg = 0;
             for (int c = 0; c < 2 * kVecMaxDim; ++c) deg += k[size_t(c)];
@@ -1016,6 +1019,10 @@ int pimc_level_table_poly(const pimc_poly_potential* V, double m, double T, int 
     if (!n_out) { set_thread_error("n_out is NULL"); return PIMC_EINVAL; }
     const PolyCoefficients& C = cached_poly(V, m, p);
     PolyCode R;
+    if (C.keys.empty()) {
+        *n_out = 0;
+        return PIMC_OK;
+    }
     if (!build_poly_code(C.keys, V->dim, R)) {
         set_thread_error("internal: the monomials do not fit the component evaluator");
         return PIMC_EUNSUPPORTED;

@@ -178,9 +178,10 @@ struct RadialEvalRT {
 // y_c = qb_c - qa_c (c < DIM) and y_{DIM+c} = qa_c + qb_c, evaluated by a multivariate Horner scheme
 // over the prefix tree of its monomials (exponents of y_0, y_1, ... from high to low). The tree is a
 // level-independent structure stream of ints (pre-order); only the coefficients depend on the level.
-//   node at depth v < 2 DIM - 1:  [n children] then per child [gap | tail << 8] and the child's node;
-//       a_v = 0; per child: a_v = a_v y_v^gap + (child value) y_{v+1}^tail  (gap = 1 for the first);
-//   node at depth 2 DIM - 1:      [L]: the dense Horner chain in y_{2 DIM - 1} over the next L
+//   node at depth v < 2 DIM - 1:  [n >= 1 children] then per child [gap | tail << 8] and the child's
+//       node; a_v = first child's value y_{v+1}^tail, then per child a_v = a_v y_v^gap + (child value)
+//       y_{v+1}^tail;
+//   node at depth 2 DIM - 1:      [L >= 1]: the dense Horner chain in y_{2 DIM - 1} over the next L
 //       coefficients of the level's array (zeros fill the exponents that are absent);
 //   stream head: [tail of the root]; the slice value is a_0 y_0^tail.
 // Every count and exponent is wave-uniform (scalar loads through the constant address space), so the
@@ -199,6 +200,14 @@ struct PolyEvalRT {
     int stride;
     __device__ __forceinline__ void launder() { asm volatile("" : "+s"(tab), "+s"(code)); }
 
+    // a = a * y + t in a's registers. Written as fma(), the compiler picks the two-operand form that
+    // accumulates into t's registers and then copies the result back to a at every iteration of a
+    // node's child loop (B 64-bit moves per child); the three-operand instruction with a tied to its
+    // destination needs no copy. Same operation, same rounding.
+    __device__ __forceinline__ static void fma_into(double& a, double y, double t) {
+        asm("v_fma_f64 %0, %0, %1, %2" : "+v"(a) : "v"(y), "v"(t));
+    }
+
     // x[i] *= y[i]^e for a wave-uniform e >= 0 (a scalar loop around B multiplies).
     template <int B>
     __device__ __forceinline__ static void times_pow(double (&x)[B], const double (&y)[B], int e) {
@@ -208,16 +217,20 @@ struct PolyEvalRT {
         }
     }
 
+    // The node's value into out. A chain starts from its first coefficient and a node from its first
+    // child's value (the same bits as starting from 0: fma(0, y, t) = t), so no accumulator is
+    // zeroed and no first step is spent on it; every node has at least one child and every chain at
+    // least one coefficient.
     template <int V, int B>
     __device__ __forceinline__ static void node(const_ptr<int>& s, const_ptr<double>& c, const double (&y)[NV][B],
                                                 double (&out)[B]) {
-        double a[B];
-#pragma unroll
-        for (int i = 0; i < B; ++i) a[i] = 0.0;
         if constexpr (V == NV - 1) {
             const int L = s[0];
             s += 1;
-            int j = 0;
+            const double c0 = c[0];
+#pragma unroll
+            for (int i = 0; i < B; ++i) out[i] = c0;
+            int j = 1;
             for (; j + kPolyUnroll <= L; j += kPolyUnroll) {
                 double cq[kPolyUnroll];
 #pragma unroll
@@ -225,31 +238,32 @@ struct PolyEvalRT {
 #pragma unroll
                 for (int q = 0; q < kPolyUnroll; ++q) {
 #pragma unroll
-                    for (int i = 0; i < B; ++i) a[i] = fma(a[i], y[V][i], cq[q]);
+                    for (int i = 0; i < B; ++i) out[i] = fma(out[i], y[V][i], cq[q]);
                 }
             }
             for (; j < L; ++j) {
-                const double c0 = c[j];
+                const double c1 = c[j];
 #pragma unroll
-                for (int i = 0; i < B; ++i) a[i] = fma(a[i], y[V][i], c0);
+                for (int i = 0; i < B; ++i) out[i] = fma(out[i], y[V][i], c1);
             }
             c += L;
         } else {
             const int n = s[0];
-            s += 1;
-            for (int k = 0; k < n; ++k) {
+            const int h0 = s[1];
+            s += 2;
+            node<V + 1, B>(s, c, y, out);
+            times_pow<B>(out, y[V + 1], h0 >> 8);
+            for (int k = 1; k < n; ++k) {
                 const int h = s[0];
                 s += 1;
-                times_pow<B>(a, y[V], (h & 255) - 1);
+                times_pow<B>(out, y[V], (h & 255) - 1);
                 double t[B];
                 node<V + 1, B>(s, c, y, t);
                 times_pow<B>(t, y[V + 1], h >> 8);
 #pragma unroll
-                for (int i = 0; i < B; ++i) a[i] = fma(a[i], y[V][i], t[i]);
+                for (int i = 0; i < B; ++i) fma_into(out[i], y[V][i], t[i]);
             }
         }
-#pragma unroll
-        for (int i = 0; i < B; ++i) out[i] = a[i];
     }
 
     template <int B>
