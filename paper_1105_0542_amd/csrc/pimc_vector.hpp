@@ -113,9 +113,12 @@ inline size_t vec_lds_bytes(int dim, int D, int s) {
 // per-level coefficient arrays (A.tab, A.stride doubles per level); layout in pimc_vector_impl.hpp,
 // PolyEvalRT.
 #ifndef PIMC_POLY_U
-#define PIMC_POLY_U 3
+#define PIMC_POLY_U 5
 #endif
-constexpr int kPolyU = PIMC_POLY_U;     // register-subtree levels of the component evaluator
+// Subtree levels of the component evaluator (1..5): deeper than the radial kernels' 3, because its
+// cost is a pass over the structure per slice batch, and deeper subtrees give fewer, wider batches
+// (the points that do not fit the registers live in scratch).
+constexpr int kPolyU = PIMC_POLY_U;
 constexpr int kPolyMaxSlots = 1 << 20;  // coefficient slots per level
 
 // Launch the vector estimation kernel: dim 1..3; U = min(s, kVecU); `specialized` selects the
@@ -135,11 +138,10 @@ hipError_t launch_vector_d3(const VecArgs& A, int p, int U, bool specialized, in
 int vector_resident_d1(int p, int U, bool specialized, size_t lds, int device);
 int vector_resident_d2(int p, int U, bool specialized, size_t lds, int device);
 int vector_resident_d3(int p, int U, bool specialized, size_t lds, int device);
-hipError_t launch_vector_poly_d1(const VecArgs& A, int U, int grid, hipStream_t st);
-hipError_t launch_vector_poly_d2(const VecArgs& A, int U, int grid, hipStream_t st);
-hipError_t launch_vector_poly_d3(const VecArgs& A, int U, int grid, hipStream_t st);
-int vector_poly_resident_d1(int U, size_t lds, int device);
-int vector_poly_resident_d2(int U, size_t lds, int device);
-int vector_poly_resident_d3(int U, size_t lds, int device);
+// The component evaluator's kernels, one translation unit per dimension (pimc_vector_poly.hip).
+template <int DIM>
+hipError_t launch_vector_poly_dim(const VecArgs& A, int U, int grid, hipStream_t st);
+template <int DIM>
+int vector_poly_resident_dim(int U, size_t lds, int device);
 
 }  // namespace pimc

@@ -16,10 +16,4 @@ int vector_resident_d1(int p, int U, bool specialized, size_t lds, int device) {
     return vec::resident_rt<1>(U, lds, device);
 }
 
-hipError_t launch_vector_poly_d1(const VecArgs& A, int U, int grid, hipStream_t st) {
-    return vec::launch_poly<1>(A, U, grid, st);
-}
-
-int vector_poly_resident_d1(int U, size_t lds, int device) { return vec::resident_poly<1>(U, lds, device); }
-
 }  // namespace pimc

@@ -17,10 +17,4 @@ int vector_resident_d2(int p, int U, bool specialized, size_t lds, int device) {
     return vec::resident_rt<2>(U, lds, device);
 }
 
-hipError_t launch_vector_poly_d2(const VecArgs& A, int U, int grid, hipStream_t st) {
-    return vec::launch_poly<2>(A, U, grid, st);
-}
-
-int vector_poly_resident_d2(int U, size_t lds, int device) { return vec::resident_poly<2>(U, lds, device); }
-
 }  // namespace pimc

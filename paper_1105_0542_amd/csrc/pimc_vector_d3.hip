@@ -17,10 +17,4 @@ int vector_resident_d3(int p, int U, bool specialized, size_t lds, int device) {
     return vec::resident_rt<3>(U, lds, device);
 }
 
-hipError_t launch_vector_poly_d3(const VecArgs& A, int U, int grid, hipStream_t st) {
-    return vec::launch_poly<3>(A, U, grid, st);
-}
-
-int vector_poly_resident_d3(int U, size_t lds, int device) { return vec::resident_poly<3>(U, lds, device); }
-
 }  // namespace pimc

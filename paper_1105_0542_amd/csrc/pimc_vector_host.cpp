@@ -882,18 +882,18 @@ hipError_t launch_vector(const VecArgs& A, int dim, int p, int U, bool specializ
 
 hipError_t launch_vector_poly(const VecArgs& A, int dim, int U, int grid, hipStream_t st) {
     switch (dim) {
-        case 1: return launch_vector_poly_d1(A, U, grid, st);
-        case 2: return launch_vector_poly_d2(A, U, grid, st);
-        case 3: return launch_vector_poly_d3(A, U, grid, st);
+        case 1: return launch_vector_poly_dim<1>(A, U, grid, st);
+        case 2: return launch_vector_poly_dim<2>(A, U, grid, st);
+        case 3: return launch_vector_poly_dim<3>(A, U, grid, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 int vector_poly_resident(int dim, int U, size_t lds_bytes, int device) {
     switch (dim) {
-        case 1: return vector_poly_resident_d1(U, lds_bytes, device);
-        case 2: return vector_poly_resident_d2(U, lds_bytes, device);
-        case 3: return vector_poly_resident_d3(U, lds_bytes, device);
+        case 1: return vector_poly_resident_dim<1>(U, lds_bytes, device);
+        case 2: return vector_poly_resident_dim<2>(U, lds_bytes, device);
+        case 3: return vector_poly_resident_dim<3>(U, lds_bytes, device);
         default: return 256;
     }
 }

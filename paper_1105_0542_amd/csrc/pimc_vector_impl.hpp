@@ -217,10 +217,9 @@ struct PolyEvalRT {
         }
     }
 
-    // The node's value into out. A chain starts from its first coefficient and a node from its first
-    // child's value (the same bits as starting from 0: fma(0, y, t) = t), so no accumulator is
-    // zeroed and no first step is spent on it; every node has at least one child and every chain at
-    // least one coefficient.
+    // The node's value into out. A chain starts from its first coefficient and a node of the two
+    // deepest internal levels from its first child's value (the same bits as starting from 0:
+    // fma(0, y, t) = t); every node has at least one child and every chain at least one coefficient.
     template <int V, int B>
     __device__ __forceinline__ static void node(const_ptr<int>& s, const_ptr<double>& c, const double (&y)[NV][B],
                                                 double (&out)[B]) {
@@ -249,11 +248,22 @@ struct PolyEvalRT {
             c += L;
         } else {
             const int n = s[0];
-            const int h0 = s[1];
-            s += 2;
-            node<V + 1, B>(s, c, y, out);
-            times_pow<B>(out, y[V + 1], h0 >> 8);
-            for (int k = 1; k < n; ++k) {
+            int k = 0;
+            if constexpr (V >= NV - 3) {
+                // the two deepest internal levels (most of the nodes) let the first child write the
+                // accumulator; above them it is zeroed, which keeps one copy of a child's code per
+                // level instead of two (2^(2 DIM - 1) copies of the chain loop when peeled throughout)
+                const int h0 = s[1];
+                s += 2;
+                node<V + 1, B>(s, c, y, out);
+                times_pow<B>(out, y[V + 1], h0 >> 8);
+                k = 1;
+            } else {
+                s += 1;
+#pragma unroll
+                for (int i = 0; i < B; ++i) out[i] = 0.0;
+            }
+            for (; k < n; ++k) {
                 const int h = s[0];
                 s += 1;
                 times_pow<B>(out, y[V], (h & 255) - 1);
@@ -588,6 +598,12 @@ inline hipError_t launch_poly(const VecArgs& A, int U, int grid, hipStream_t st)
         case 1: return launch_one<DIM, 1>(A, ev, grid, st);
         case 2: return launch_one<DIM, 2>(A, ev, grid, st);
         case 3: return launch_one<DIM, 3>(A, ev, grid, st);
+#if PIMC_POLY_U > 3
+        case 4: return launch_one<DIM, 4>(A, ev, grid, st);
+#endif
+#if PIMC_POLY_U > 4
+        case 5: return launch_one<DIM, 5>(A, ev, grid, st);
+#endif
         default: return hipErrorInvalidValue;
     }
 }
@@ -597,6 +613,12 @@ inline int resident_poly(int U, size_t lds, int device) {
     switch (U) {
         case 1: return resident_one<DIM, 1, PolyEvalRT<DIM>>(lds, device);
         case 2: return resident_one<DIM, 2, PolyEvalRT<DIM>>(lds, device);
+#if PIMC_POLY_U > 3
+        case 4: return resident_one<DIM, 4, PolyEvalRT<DIM>>(lds, device);
+#endif
+#if PIMC_POLY_U > 4
+        case 5: return resident_one<DIM, 5, PolyEvalRT<DIM>>(lds, device);
+#endif
         default: return resident_one<DIM, 3, PolyEvalRT<DIM>>(lds, device);
     }
 }

@@ -48,6 +48,8 @@ CASES = [  # terms, dim, m, a, b, T, s, p, flags, k
     (COUPLED_3D, 3, 2.0, (0.1, -0.2, 0.3), (0.4, 0.1, -0.5), 2.0, 6, 4, 0, 1200),
     (COUPLED_2D, 2, 1.0, (0.2, 0.1), (-0.3, 0.6), 0.5, 2, 5, P.FLAG_HIERARCHY, 1200),    # U = 2
     (COUPLED_3D, 3, 1.0, (0.0, 0.2, 0.0), (0.5, 0.0, -0.1), 0.7, 1, 6, P.FLAG_HIERARCHY, 1200),  # U = 1
+    (COUPLED_3D, 3, 1.5, (0.3, 0.2, -0.1), (0.5, -0.4, 0.2), 1.0, 3, 5, P.FLAG_HIERARCHY, 1200),   # U = 3
+    (COUPLED_2D, 2, 1.0, (0.1, -0.1), (0.6, 0.2), 1.0, 4, 7, P.FLAG_HIERARCHY, 1200),           # U = 4
     (COUPLED_2D, 2, 1.0, (0.0, 0.0), (1.0, 0.0), 1.0, 10, 10, P.FLAG_HIERARCHY, 200),     # full size
     (COUPLED_3D, 3, 1.0, (0.0, 0.0, 0.0), (0.5, 0.5, 0.0), 1.0, 8, 8, P.FLAG_HIERARCHY, 200),
 ]
@@ -70,7 +72,7 @@ def test_path_actions_match_oracle(ctx, case):
     _check_levels(got, ref, scale, s, flags)
 
 
-@pytest.mark.parametrize("case", CASES[:4])
+@pytest.mark.parametrize("case", CASES[:6])
 def test_amplitude_matches_oracle_on_identical_samples(ctx, case):
     terms, dim, m, a, b, T, s, p, _, _ = case
     n = 20000
