@@ -115,10 +115,15 @@ inline size_t vec_lds_bytes(int dim, int D, int s) {
 #ifndef PIMC_POLY_U
 #define PIMC_POLY_U 5
 #endif
-// Subtree levels of the component evaluator (1..5): deeper than the radial kernels' 3, because its
-// cost is a pass over the structure per slice batch, and deeper subtrees give fewer, wider batches
-// (the points that do not fit the registers live in scratch).
+#ifndef PIMC_POLY_U3
+#define PIMC_POLY_U3 6
+#endif
+// Subtree levels of the component evaluator (1..6) in d = 1, 2 and in d = 3: deeper than the radial
+// kernels' 3, because its cost is a pass over the structure per slice batch, and deeper subtrees give
+// fewer, wider batches (the points that do not fit the registers live in scratch).
 constexpr int kPolyU = PIMC_POLY_U;
+constexpr int kPolyU3 = PIMC_POLY_U3;
+constexpr int poly_subtree_levels(int dim) { return dim == 3 ? kPolyU3 : kPolyU; }
 constexpr int kPolyMaxSlots = 1 << 20;  // coefficient slots per level
 
 // Launch the vector estimation kernel: dim 1..3; U = min(s, kVecU); `specialized` selects the

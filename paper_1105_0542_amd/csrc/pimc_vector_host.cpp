@@ -816,7 +816,7 @@ int build_poly_problem(const pimc_poly_potential* V, double m, const double* a, 
     }
     P.pref = std::pow(sm, double(P.dim));
     P.K0 = std::exp(-r2 / (2.0 * T)) / std::pow(2.0 * kPi * T, 0.5 * double(P.dim));
-    P.U = std::min(P.s, kPolyU);
+    P.U = std::min(P.s, poly_subtree_levels(P.dim));
     P.D = P.s - P.U;
     P.specialized = false;
     const PolyCoefficients& C = cached_poly(V, m, p);

@@ -598,14 +598,12 @@ inline hipError_t launch_poly(const VecArgs& A, int U, int grid, hipStream_t st)
         case 1: return launch_one<DIM, 1>(A, ev, grid, st);
         case 2: return launch_one<DIM, 2>(A, ev, grid, st);
         case 3: return launch_one<DIM, 3>(A, ev, grid, st);
-#if PIMC_POLY_U > 3
-        case 4: return launch_one<DIM, 4>(A, ev, grid, st);
-#endif
-#if PIMC_POLY_U > 4
-        case 5: return launch_one<DIM, 5>(A, ev, grid, st);
-#endif
-        default: return hipErrorInvalidValue;
+        case 4: if constexpr (poly_subtree_levels(DIM) >= 4) return launch_one<DIM, 4>(A, ev, grid, st); break;
+        case 5: if constexpr (poly_subtree_levels(DIM) >= 5) return launch_one<DIM, 5>(A, ev, grid, st); break;
+        case 6: if constexpr (poly_subtree_levels(DIM) >= 6) return launch_one<DIM, 6>(A, ev, grid, st); break;
+        default: break;
     }
+    return hipErrorInvalidValue;
 }
 
 template <int DIM>
@@ -613,14 +611,12 @@ inline int resident_poly(int U, size_t lds, int device) {
     switch (U) {
         case 1: return resident_one<DIM, 1, PolyEvalRT<DIM>>(lds, device);
         case 2: return resident_one<DIM, 2, PolyEvalRT<DIM>>(lds, device);
-#if PIMC_POLY_U > 3
-        case 4: return resident_one<DIM, 4, PolyEvalRT<DIM>>(lds, device);
-#endif
-#if PIMC_POLY_U > 4
-        case 5: return resident_one<DIM, 5, PolyEvalRT<DIM>>(lds, device);
-#endif
-        default: return resident_one<DIM, 3, PolyEvalRT<DIM>>(lds, device);
+        case 4: if constexpr (poly_subtree_levels(DIM) >= 4) return resident_one<DIM, 4, PolyEvalRT<DIM>>(lds, device); break;
+        case 5: if constexpr (poly_subtree_levels(DIM) >= 5) return resident_one<DIM, 5, PolyEvalRT<DIM>>(lds, device); break;
+        case 6: if constexpr (poly_subtree_levels(DIM) >= 6) return resident_one<DIM, 6, PolyEvalRT<DIM>>(lds, device); break;
+        default: break;
     }
+    return resident_one<DIM, 3, PolyEvalRT<DIM>>(lds, device);
 }
 
 template <int DIM, int P>
