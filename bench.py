@@ -1068,12 +1068,16 @@ def summarize(line):
             pair.setdefault(f"{g},{T}", {})[p.split("=")[1]] = _r(r.get("pair_slope"), 3)
         out["c2"] = {"slice_evals_per_s": _r(c["slice_evals_per_s"]), "slopes": slopes, "pair_slopes": pair,
                      "g0_max_abs_z": {p: _r(v["max_abs_z_vs_exact_discretized"], 3) for p, v in c["g0"].items()},
-                     "max_abs_z_N1024_vs_dvr": {}}
+                     "max_abs_z_N1024_vs_dvr": {}, "max_abs_z_fit_vs_dvr": {}}
         for key, r in c["points"].items():
+            p_key = key.split(",")[1].split("=")[1]
             if r.get("z_N1024") is not None:
-                p_key = key.split(",")[1].split("=")[1]
                 zmax = out["c2"]["max_abs_z_N1024_vs_dvr"]
                 zmax[p_key] = max(zmax.get(p_key, 0.0), _r(abs(r["z_N1024"]), 3))
+            if r.get("fit_err") and r.get("continuum_dvr") is not None:
+                zf = abs(r["fit_A"] - r["continuum_dvr"]) / r["fit_err"]
+                zmax = out["c2"]["max_abs_z_fit_vs_dvr"]
+                zmax[p_key] = max(zmax.get(p_key, 0.0), _r(zf, 3))
     out["mpt"] = {p: {"rate": _r(r["slice_evals_per_s"]), "frac": _r(r["fp64_frac"])} for p, r in line["mpt"]["per_p"].items()}
     gq = line["general"]["quartic_g10_general_mode"]
     out["general"] = {"rate": _r(gq["slice_evals_per_s"]), "frac": _r(gq["roofline"]["frac"])}
