@@ -134,6 +134,16 @@ def test_free_particle_and_split_runs(ctx):
     assert np.array_equal(whole, np.concatenate([a, b]))
 
 
+def test_path_indices_beyond_32_bits(ctx):
+    """Path indices above 2^32 (the high word enters the generator counter): the oracle's paths."""
+    first = (1 << 33) + 7
+    got = ctx.path_actions_poly(COUPLED_2D, 2, 1.0, (0.1, 0.0), (0.4, -0.2), 1.0, 16, 5, 3, 9, P.FLAG_HIERARCHY,
+                                first, 300)
+    ref, scale = ov.poly_path_actions(COUPLED_2D, 2, 1.0, (0.1, 0.0), (0.4, -0.2), 1.0, 4, 5, 3, 9,
+                                      np.arange(first, first + 300, dtype=np.uint64), with_scale=True)
+    _check_levels(got, ref, scale, 4, P.FLAG_HIERARCHY)
+
+
 def test_largest_size_nests(ctx):
     """Three coordinates at N = 2^20 (the deepest walk): levels 0..8 of the per-path actions equal an
     s = 8 run of the same paths bitwise, and the finest level is finite and converged."""
