@@ -34,12 +34,9 @@ hipError_t launch_symv_tiles(const double* M, const uint32_t* map, uint32_t ntil
                              const double* x, double* prow, double* pcol, double* y, hipStream_t st);
 // y = M x (ld even; M and x 16-byte aligned).
 hipError_t launch_gemv(const double* M, uint64_t ld, uint32_t n, const double* x, double* y, hipStream_t st);
-// out[c] = <Q_c, w>, c < ncols (Q_c = Q + c*ldq).
+// out[c] = <Q_c, w>, c < ncols (Q_c = Q + c*ldq); with diag non-null also *diag = out[diag_col].
 hipError_t launch_col_dots(const double* Q, uint64_t ldq, uint32_t n, uint32_t ncols, const double* w, double* out,
-                           hipStream_t st);
-// w -= alpha[j] Q_j + beta[j-1] Q_{j-1}.
-hipError_t launch_lanczos_recur(double* w, const double* Q, uint64_t ldq, uint32_t n, uint32_t j, const double* alpha,
-                                const double* beta, hipStream_t st);
+                           hipStream_t st, double* diag = nullptr, uint32_t diag_col = 0);
 // y = sum_c h[c] Q_c (subtract = 0) or y -= sum_c h[c] Q_c (subtract = 1).
 hipError_t launch_combine_cols(const double* Q, uint64_t ldq, uint32_t n, uint32_t ncols, const double* h, double* y,
                                int subtract, hipStream_t st);

@@ -299,10 +299,11 @@ int pimc_spectrum(pimc_ctx* c, const pimc_potential* V, double m, double t, int 
     for (uint32_t j = 0; j < max_iter; ++j) {
         double* qj = Q + uint64_t(j) * ld;
         HIP_TRY(c, launch_symv_tiles(M, dmap, ntiles, nb, n, qj, prow, pcol, w, c->stream));
-        HIP_TRY(c, launch_col_dots(qj, ld, n, 1, w, alpha + j, c->stream));
-        HIP_TRY(c, launch_lanczos_recur(w, Q, ld, n, j, alpha, beta, c->stream));
+        // w = (1 - Q Q^T) M q_j by classical Gram-Schmidt, twice: in exact arithmetic the first pass
+        // removes alpha_j q_j + beta_{j-1} q_{j-1} (the three-term recurrence) and nothing else, so
+        // alpha_j = <q_j, M q_j> is its coefficient of q_j, and beta_j = |w| afterwards
         for (int pass = 0; pass < 2; ++pass) {
-            HIP_TRY(c, launch_col_dots(Q, ld, n, j + 1, w, h, c->stream));
+            HIP_TRY(c, launch_col_dots(Q, ld, n, j + 1, w, h, c->stream, pass == 0 ? alpha + j : nullptr, j));
             HIP_TRY(c, launch_combine_cols(Q, ld, n, j + 1, h, w, 1, c->stream));
         }
         HIP_TRY(c, launch_normalize(w, n, beta, j, Q + uint64_t(j + 1) * ld, c->stream));
