@@ -44,7 +44,7 @@ C3_SAMPLES = 1_000_000           # samples per task of the batched grid (the con
 C3_TUNE_SAMPLES = 10_000         # the same grid with fewer samples, for the autotuner
 C3_REPLAY_SAMPLES = 100_000      # samples per task of one graph replay (about 12 s of device time)
 # Precision workload: FP32 slice polynomials against FP64, g = 10, p = 18, N = 512, T = 1.
-PREC = dict(g=10.0, p=18, s=9, T=1.0, samples=1_000_000_000, oracle_paths=20_000)
+PREC = dict(g=10.0, p=18, s=9, T=1.0, samples=1_000_000_000, oracle_paths=1_000_000)
 # Learned proposal: the anharmonic oscillator g = 10 at p = 12, N = 128, T = 2, a = 0, b = 1; 8 couplings,
 # batches of 4096 fresh base paths, 2442 Adam steps (1e7 training paths), loss 0.1 log E[w^2] + 0.9 KL.
 FLOW = dict(g=10.0, p=12, s=7, T=2.0, layers=8, batch=4096, lr=1e-3, beta=0.9, steps=2442,
