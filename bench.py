@@ -200,6 +200,17 @@ def _oracle_mpt_worker(args):
     return count
 
 
+def _oracle_component_worker(args):
+    k, first, count = args
+    import numpy as np
+    from oracle import vector as ov
+    case = COMPONENT["cases"][k]
+    idx = np.arange(first, first + count, dtype=np.uint64)
+    ov.poly_path_actions(case["terms"], case["dim"], 1.0, case["a"], case["b"], COMPONENT["T"], COMPONENT["s"],
+                         case["p"], 1, 0, idx)
+    return count
+
+
 def _oracle_general_worker(args):
     p, first, count = args
     import numpy as np
@@ -231,6 +242,14 @@ def oracle_section_baselines(which):
             out["vector"][str(dim)] = {"value": n * sl / dt, "unit": "slice-evals/s", "cores": cores, "kind": "oracle",
                                        "sample": f"first {n} paths of the d={dim} workload (p=18, s=10, every level), "
                                                  f"{dt:.1f} s wall"}
+        out["vector"]["component"] = []
+        slc = slices_per_sample(COMPONENT["s"], True)
+        for k, case in enumerate(COMPONENT["cases"]):
+            n, dt, cores = _timed_pool(_oracle_component_worker, [(k, 128 * i, 128) for i in range(16)])
+            out["vector"]["component"].append({
+                "value": n * slc / dt, "unit": "slice-evals/s", "cores": cores, "kind": "oracle",
+                "sample": f"first {n} paths of the {case['name']} workload (p={case['p']}, s={COMPONENT['s']}, "
+                          f"every level), {dt:.1f} s wall"})
     if "mpt" in which:
         n, dt, cores = _timed_pool(_oracle_mpt_worker, [(10, 1024 * i, 1024) for i in range(16)])
         out["mpt"] = {"value": n * sl / dt, "unit": "slice-evals/s", "cores": cores, "kind": "oracle",
@@ -407,11 +426,11 @@ def vector_section(P, ctx, dvr, base=None):
         if base is not None:
             row["cpu_baseline"] = base[str(dim)]
         out["per_dim"][str(dim)] = row
-    out["component"] = component_rows(P, ctx)
+    out["component"] = component_rows(P, ctx, base.get("component") if base is not None else None)
     return out
 
 
-def component_rows(P, ctx):
+def component_rows(P, ctx, base=None):
     """Any polynomial V through the component evaluator: the rate, and the FP64 fraction counting one
     FMA (2 flops) per monomial of eps W_p, the least any Horner scheme over the monomials does."""
     C = COMPONENT
@@ -429,6 +448,8 @@ def component_rows(P, ctx):
                      "A_N": [r.amp for r in res], "err_N": [r.err for r in res], "kernel_ms": ms,
                      "slice_evals_per_s": rate, "monomials": int(coef.size), "flop_per_slice": flop,
                      "fp64_frac": rate * flop / 1e12 / FP64_PEAK_TFLOPS})
+        if base is not None:
+            rows[-1]["cpu_baseline"] = base[len(rows) - 1]
         _progress(f"component {case['name']}: {rate:.3e} slice-evals/s")
     return rows
 
