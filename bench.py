@@ -61,8 +61,9 @@ VECTOR = dict(g=10.0, T=1.0, s=10, p=18, samples=100_000_000,
               ends={2: ((0.0, 0.0), (1.0, 0.4)), 3: ((0.0, 0.0, 0.0), (1.0, 0.4, -0.2))})
 RADIAL_E = {18: 102}                     # coefficients of the (u, z, w^2) table at p = 18
 # Any polynomial V (component route): two particles on a line with a quartic pair interaction
-# 0.1 (q1 - q2)^4 in an anisotropic trap with a field (d = 2, p = 10), and an anisotropic 3D trap with
-# cubic and quartic couplings (d = 3, p = 8); one s = 10 run each (every level).
+# 0.1 (q1 - q2)^4 in an anisotropic trap with a field (d = 2, p = 10), an anisotropic 3D trap with
+# cubic and quartic couplings (d = 3, p = 8) and two particles in two dimensions (d = 4, p = 8); one
+# s = 10 run each (every level).
 COMPONENT = dict(T=1.0, s=10, samples=4_000_000, cases=[
     dict(name="pair (q1-q2)^4 + trap, d=2", dim=2, p=10, a=(0.0, 0.0), b=(1.0, 0.4),
          terms=[(0.5, (2, 0)), (0.7, (0, 2)), (0.1, (4, 0)), (-0.4, (3, 1)), (0.6, (2, 2)), (-0.4, (1, 3)),
@@ -70,6 +71,14 @@ COMPONENT = dict(T=1.0, s=10, samples=4_000_000, cases=[
     dict(name="anisotropic 3D trap, cubic + quartic couplings", dim=3, p=8, a=(0.0, 0.0, 0.0), b=(1.0, 0.4, -0.2),
          terms=[(0.5, (2, 0, 0)), (0.4, (0, 2, 0)), (0.3, (0, 0, 2)), (0.2, (0, 2, 1)), (0.05, (1, 1, 2)),
                 (0.05, (0, 0, 4)), (0.1, (2, 2, 0)), (0.1, (0, 0, 1))]),
+    # two particles in two dimensions: |r_1|^2/2 + |r_2|^2/2 + 0.1 |r_1 - r_2|^4, r_1 = (q1, q2), r_2 = (q3, q4)
+    dict(name="two particles in 2D, quartic pair interaction, d=4", dim=4, p=8, samples=2_097_152,
+         a=(0.0, 0.0, 0.0, 0.0), b=(1.0, 0.4, -0.2, 0.3),
+         terms=[(0.1, (4, 0, 0, 0)), (-0.4, (3, 0, 1, 0)), (0.2, (2, 2, 0, 0)), (-0.4, (2, 1, 0, 1)), (0.6, (2, 0, 2, 0)),
+                (0.2, (2, 0, 0, 2)), (0.5, (2, 0, 0, 0)), (-0.4, (1, 2, 1, 0)), (0.8, (1, 1, 1, 1)), (-0.4, (1, 0, 3, 0)),
+                (-0.4, (1, 0, 1, 2)), (0.1, (0, 4, 0, 0)), (-0.4, (0, 3, 0, 1)), (0.2, (0, 2, 2, 0)), (0.6, (0, 2, 0, 2)),
+                (0.5, (0, 2, 0, 0)), (-0.4, (0, 1, 2, 1)), (-0.4, (0, 1, 0, 3)), (0.1, (0, 0, 4, 0)), (0.2, (0, 0, 2, 2)),
+                (0.5, (0, 0, 2, 0)), (0.1, (0, 0, 0, 4)), (0.5, (0, 0, 0, 2))]),
 ])
 HBM_PEAK_GBS = 8000.0
 # Modified Poeschl-Teller potential (the paper's Fig. 2): V = -lambda/cosh^2(alpha q), lambda = alpha = 1,
@@ -437,14 +446,15 @@ def component_rows(P, ctx, base=None):
     rows = []
     for case in C["cases"]:
         args = (case["terms"], case["dim"], 1.0, case["a"], case["b"], C["T"], 1 << C["s"], case["p"])
-        ctx.amplitude_poly(*args, 1 << 20, 1, 0, P.FLAG_HIERARCHY)
-        res, st = ctx.amplitude_poly(*args, C["samples"], 1, 0, P.FLAG_HIERARCHY)
+        ns = case.get("samples", C["samples"])
+        ctx.amplitude_poly(*args, 1 << 16, 1, 0, P.FLAG_HIERARCHY)                # load the kernels
+        res, st = ctx.amplitude_poly(*args, ns, 1, 0, P.FLAG_HIERARCHY)
         ms = ctx.last_kernel_ms()
-        rate = C["samples"] * slices_per_sample(C["s"], True) / (ms / 1e3)
+        rate = ns * slices_per_sample(C["s"], True) / (ms / 1e3)
         coef, _ = P.level_table_poly(case["terms"], case["dim"], 1.0, C["T"], case["p"], C["s"])
         flop = 2 * coef.size
         rows.append({"workload": f"{case['name']}, p={case['p']}, s={C['s']} (every level), T={C['T']:g}, "
-                                 f"{C['samples']:.0e} samples", "status": st,
+                                 f"{ns:.0e} samples", "status": st,
                      "A_N": [r.amp for r in res], "err_N": [r.err for r in res], "kernel_ms": ms,
                      "slice_evals_per_s": rate, "monomials": int(coef.size), "flop_per_slice": flop,
                      "fp64_frac": rate * flop / 1e12 / FP64_PEAK_TFLOPS})

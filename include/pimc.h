@@ -234,7 +234,7 @@ int pimc_path_actions_general(pimc_ctx *ctx, const pimc_general_potential *V, do
  * flags and errors as pimc_amplitude / pimc_path_actions. EINVAL: dim outside 1..PIMC_MAX_DIM,
  * degree outside 0..PIMC_MAX_RADIAL_DEGREE, non-finite coefficients or endpoints, and the conditions
  * of pimc_amplitude. */
-#define PIMC_MAX_DIM 3
+#define PIMC_MAX_DIM 4             /* d = D*M <= 4: e.g. two particles in two dimensions        */
 #define PIMC_MAX_RADIAL_DEGREE 2   /* up to (q.q)^2: the anharmonic-oscillator family               */
 
 typedef struct {
@@ -263,7 +263,7 @@ int pimc_level_table_radial(const pimc_radial_potential *V, double m, double T, 
  *
  * The same as the radial entry points for a potential without rotational symmetry (anisotropic
  * traps, pair interactions such as (q_1 - q_2)^4 of two particles on a line):
- *     V(q) = sum_t coef[t] q_1^exps[t][0] q_2^exps[t][1] q_3^exps[t][2],   q in R^dim
+ *     V(q) = sum_t coef[t] prod_c q_c^exps[t][c - 1],   q in R^dim
  * (exponents of coordinates beyond dim must be 0). eq.(MBrec) and eq.(DIA) run on polynomials in
  * the 2 dim components of x and xbar (FP64); each level's eps W_p is a polynomial in those
  * components, evaluated by a multivariate Horner scheme over the prefix tree of its monomials.
@@ -273,7 +273,7 @@ int pimc_level_table_radial(const pimc_radial_potential *V, double m, double T, 
  * coefficients or endpoints, and the conditions of pimc_amplitude. EUNSUPPORTED: a level polynomial
  * with more than PIMC_POLY_MAX_MONOMIALS monomials. The recursion for one (V, m, p) is computed once
  * per process and cached. */
-#define PIMC_POLY_MAX_TERMS 35      /* every monomial of total degree <= 4 in 3 coordinates         */
+#define PIMC_POLY_MAX_TERMS 70      /* every monomial of total degree <= 4 in 4 coordinates         */
 #define PIMC_POLY_MAX_DEGREE 4
 #define PIMC_POLY_MAX_MONOMIALS 65536
 

@@ -77,8 +77,8 @@ class Mpt(C.Structure):
     _fields_ = [("lambda_", C.c_double), ("alpha", C.c_double)]
 
 
-MAX_DIM = 3
-POLY_MAX_TERMS = 35
+MAX_DIM = 4
+POLY_MAX_TERMS = 70
 POLY_MAX_DEGREE = 4
 MAX_RADIAL_DEGREE = 2
 

@@ -18,8 +18,8 @@ CLI = os.path.join(PKG, "pimc")
 
 SOURCES = ["pimc_batch_p18.hip", "pimc_batch_p12.hip", "pimc_batch_p8.hip",
            "pimc_kernels_q64.hip", "pimc_kernels_q32.hip", "pimc_kernels_tanh.hip", "pimc_kernels_batch.hip",
-           "pimc_vector_d2.hip", "pimc_vector_d3.hip", "pimc_general_kernels.hip", "pimc_kernels.hip", "pimc_flow.hip",
-           "pimc_spectrum.hip", "pimc_vector_d1.hip", "pimc_host.cpp", "pimc_flow_host.cpp", "pimc_spectrum_host.cpp",
+           "pimc_vector_d2.hip", "pimc_vector_d3.hip", "pimc_vector_d4.hip", "pimc_general_kernels.hip",
+           "pimc_kernels.hip", "pimc_flow.hip", "pimc_spectrum.hip", "pimc_vector_d1.hip", "pimc_host.cpp", "pimc_flow_host.cpp", "pimc_spectrum_host.cpp",
            "pimc_general_host.cpp", "pimc_vector_host.cpp", "pimc_noalloc.cpp"]
 HEADERS = ["pimc_tables.hpp", "pimc_device.hpp", "pimc_internal.hpp", "pimc_math.hpp", "pimc_walker.hpp",
            "pimc_flow.hpp", "pimc_host_common.hpp", "pimc_spectrum.hpp", "pimc_general.hpp",
@@ -33,7 +33,7 @@ GENERATED = "pimc_general_gen.hpp"
 GEN_HI_LEVELS = range(11, 19)
 VARIANTS = [("pimc_general_hi.hip", [f"-DPIMC_GEN_P={p}"], f"pimc_general_hi_p{p}") for p in GEN_HI_LEVELS]
 # One translation unit per dimension for the component evaluator's kernels.
-VARIANTS += [("pimc_vector_poly.hip", [f"-DPIMC_POLY_DIM={d}"], f"pimc_vector_poly_d{d}") for d in (1, 2, 3)]
+VARIANTS += [("pimc_vector_poly.hip", [f"-DPIMC_POLY_DIM={d}"], f"pimc_vector_poly_d{d}") for d in (1, 2, 3, 4)]
 
 # -ffp-contract=off: every fused multiply-add in the kernels is written as fma(); no other
 # expression is contracted, so the arithmetic is exactly what the source states.

@@ -24,7 +24,7 @@
 
 namespace pimc {
 
-constexpr int kVecMaxDim = 3;
+constexpr int kVecMaxDim = 4;
 constexpr int kVecBlock = 256;          // lanes of a workgroup
 #ifndef PIMC_VEC_U
 #define PIMC_VEC_U 3
@@ -118,15 +118,15 @@ inline size_t vec_lds_bytes(int dim, int D, int s) {
 #ifndef PIMC_POLY_U3
 #define PIMC_POLY_U3 6
 #endif
-// Subtree levels of the component evaluator (1..6) in d = 1, 2 and in d = 3: deeper than the radial
+// Subtree levels of the component evaluator (1..6) in d = 1, 2 and in d = 3, 4: deeper than the radial
 // kernels' 3, because its cost is a pass over the structure per slice batch, and deeper subtrees give
 // fewer, wider batches (the points that do not fit the registers live in scratch).
 constexpr int kPolyU = PIMC_POLY_U;
 constexpr int kPolyU3 = PIMC_POLY_U3;
-constexpr int poly_subtree_levels(int dim) { return dim == 3 ? kPolyU3 : kPolyU; }
+constexpr int poly_subtree_levels(int dim) { return dim >= 3 ? kPolyU3 : kPolyU; }
 constexpr int kPolyMaxSlots = 1 << 20;  // coefficient slots per level
 
-// Launch the vector estimation kernel: dim 1..3; U = min(s, kVecU); `specialized` selects the
+// Launch the vector estimation kernel: dim 1..4; U = min(s, kVecU); `specialized` selects the
 // evaluator with the compile-time shape of level p (dim 2 or 3, U = kVecU), else the evaluator
 // that reads the shape array. hipErrorInvalidValue for an unsupported combination.
 hipError_t launch_vector(const VecArgs& A, int dim, int p, int U, bool specialized, int grid, hipStream_t st);
@@ -143,6 +143,8 @@ hipError_t launch_vector_d3(const VecArgs& A, int p, int U, bool specialized, in
 int vector_resident_d1(int p, int U, bool specialized, size_t lds, int device);
 int vector_resident_d2(int p, int U, bool specialized, size_t lds, int device);
 int vector_resident_d3(int p, int U, bool specialized, size_t lds, int device);
+hipError_t launch_vector_d4(const VecArgs& A, int p, int U, bool specialized, int grid, hipStream_t st);
+int vector_resident_d4(int p, int U, bool specialized, size_t lds, int device);
 // The component evaluator's kernels, one translation unit per dimension (pimc_vector_poly.hip).
 template <int DIM>
 hipError_t launch_vector_poly_dim(const VecArgs& A, int U, int grid, hipStream_t st);

@@ -496,11 +496,11 @@ int vector_path_actions_core(pimc_ctx* c, const VecProblem& P, uint64_t seed, ui
 }
 
 // ============================================================================ component route
-// eq.(MBrec)/(DIA) with W_{m,k} as polynomials in the components x_1..x_3 (slots 0..2) and
-// xbar_1..xbar_3 (slots 3..5); every derivative is taken component by component, so any polynomial V.
-using MKey = std::array<uint8_t, 6>;
+// eq.(MBrec)/(DIA) with W_{m,k} as polynomials in the components x_1..x_4 (slots 0..3) and
+// xbar_1..xbar_4 (slots 4..7); every derivative is taken component by component, so any polynomial V.
+using MKey = std::array<uint8_t, 2 * kVecMaxDim>;
 using MPoly = std::map<MKey, double>;
-constexpr int kXb = 3;                            // slot of xbar_1
+constexpr int kXb = kVecMaxDim;                   // slot of xbar_1
 
 void maxpy(MPoly& y, double a, const MPoly& x) {
     for (const auto& kv : x) y[kv.first] += a * kv.second;
@@ -876,6 +876,7 @@ hipError_t launch_vector(const VecArgs& A, int dim, int p, int U, bool specializ
         case 1: return launch_vector_d1(A, p, U, specialized, grid, st);
         case 2: return launch_vector_d2(A, p, U, specialized, grid, st);
         case 3: return launch_vector_d3(A, p, U, specialized, grid, st);
+        case 4: return launch_vector_d4(A, p, U, specialized, grid, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -885,6 +886,7 @@ hipError_t launch_vector_poly(const VecArgs& A, int dim, int U, int grid, hipStr
         case 1: return launch_vector_poly_dim<1>(A, U, grid, st);
         case 2: return launch_vector_poly_dim<2>(A, U, grid, st);
         case 3: return launch_vector_poly_dim<3>(A, U, grid, st);
+        case 4: return launch_vector_poly_dim<4>(A, U, grid, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -894,6 +896,7 @@ int vector_poly_resident(int dim, int U, size_t lds_bytes, int device) {
         case 1: return vector_poly_resident_dim<1>(U, lds_bytes, device);
         case 2: return vector_poly_resident_dim<2>(U, lds_bytes, device);
         case 3: return vector_poly_resident_dim<3>(U, lds_bytes, device);
+        case 4: return vector_poly_resident_dim<4>(U, lds_bytes, device);
         default: return 256;
     }
 }
@@ -903,6 +906,7 @@ int vector_resident_blocks(int dim, int p, int U, bool specialized, size_t lds_b
         case 1: return vector_resident_d1(p, U, specialized, lds_bytes, device);
         case 2: return vector_resident_d2(p, U, specialized, lds_bytes, device);
         case 3: return vector_resident_d3(p, U, specialized, lds_bytes, device);
+        case 4: return vector_resident_d4(p, U, specialized, lds_bytes, device);
         default: return 256;
     }
 }

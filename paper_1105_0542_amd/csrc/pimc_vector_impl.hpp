@@ -1,5 +1,5 @@
 // Vector estimation kernels (several coordinates, Sec. 2.2 with the bisection estimator of Sec. 4),
-// included once per dimension by pimc_vector_d{1,2,3}.hip.
+// included once per dimension by pimc_vector_d{1,2,3,4}.hip and pimc_vector_poly.hip.
 //
 // The walk is the one of the one-dimensional kernels, with a point of DIM coordinates per node: one
 // lane owns one path; the bottom U bisection levels of each subtree live in registers, the levels

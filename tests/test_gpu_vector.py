@@ -42,6 +42,8 @@ CASES = [  # coefs, dim, m, a, b, T, s, p, flags, k
     ((0.25, 1.0, 0.125), 1, 1.0, (0.3,), (-0.4,), 1.0, 7, 12, P.FLAG_HIERARCHY, 1500),  # one coordinate
     (AHO6, 3, 1.0, (0.0, 0.2, 0.0), (0.5, 0.0, -0.1), 0.7, 1, 18, P.FLAG_HIERARCHY, 1500),  # U = 1, p = 18
     ((0.0, 0.5, 48 / 24), 2, 1.0, (0.0, 0.0), (1.0, 0.0), 1.0, 10, 18, P.FLAG_HIERARCHY, 300),  # full size
+    ((0.0, 0.5, 0.4), 4, 1.5, (0.0, 0.1, 0.2, -0.1), (0.3, 0.0, -0.2, 0.1), 1.0, 6, 12, P.FLAG_HIERARCHY, 600),  # d = 4
+    ((0.1, 0.5, 0.4), 4, 1.0, (0.1, 0.0, 0.0, 0.2), (0.0, 0.3, 0.1, 0.0), 0.5, 2, 6, P.FLAG_HIERARCHY, 600),  # d = 4, U = 2
 ]
 
 
@@ -141,6 +143,16 @@ def test_isotropic_oscillator_is_the_mehler_product(ctx):
     """Three coordinates, V = r^2/2, mass 2: the exact kernel is the product of three Mehler kernels."""
     a, b, T, m = (0.1, -0.3, 0.2), (0.4, 0.2, -0.1), 1.2, 2.0
     res, _ = ctx.amplitude_radial((0.0, 0.5), 3, m, a, b, T, 256, 12, 1_000_000, 4, 2, P.FLAG_HIERARCHY)
+    ref = math.prod(cf.mehler(x, y, T, 1.0, m) for x, y in zip(a, b))
+    for lev in (3, 6, 8):
+        assert abs(res[lev].amp - ref) <= 5 * res[lev].err, (lev, res[lev].amp, ref, res[lev].err)
+
+
+def test_four_dimensional_oscillator_is_the_mehler_product(ctx):
+    """Four coordinates (two particles in two dimensions, no interaction), V = r^2/2, mass 1.5: the
+    exact kernel is the product of four Mehler kernels."""
+    a, b, T, m = (0.1, -0.3, 0.2, 0.0), (0.4, 0.2, -0.1, 0.3), 1.0, 1.5
+    res, _ = ctx.amplitude_radial((0.0, 0.5), 4, m, a, b, T, 256, 12, 1_000_000, 4, 2, P.FLAG_HIERARCHY)
     ref = math.prod(cf.mehler(x, y, T, 1.0, m) for x, y in zip(a, b))
     for lev in (3, 6, 8):
         assert abs(res[lev].amp - ref) <= 5 * res[lev].err, (lev, res[lev].amp, ref, res[lev].err)

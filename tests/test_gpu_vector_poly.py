@@ -29,6 +29,13 @@ COUPLED_2D = [(0.5, (2, 0)), (0.7, (0, 2)), (0.1, (4, 0)), (-0.4, (3, 1)), (0.6,
 # an anisotropic trap with cubic and quartic couplings in three coordinates
 COUPLED_3D = [(0.5, (2, 0, 0)), (0.4, (0, 2, 0)), (0.3, (0, 0, 2)), (0.2, (0, 2, 1)), (0.05, (1, 1, 2)),
               (0.05, (0, 0, 4)), (0.1, (2, 2, 0)), (0.1, (0, 0, 1))]
+# two particles in two dimensions, r_1 = (q_1, q_2), r_2 = (q_3, q_4): |r_1|^2/2 + |r_2|^2/2 + 0.1 |r_1 - r_2|^4
+TWO_PARTICLES_2D = [
+    (0.1, (4, 0, 0, 0)), (-0.4, (3, 0, 1, 0)), (0.2, (2, 2, 0, 0)), (-0.4, (2, 1, 0, 1)), (0.6, (2, 0, 2, 0)),
+    (0.2, (2, 0, 0, 2)), (0.5, (2, 0, 0, 0)), (-0.4, (1, 2, 1, 0)), (0.8, (1, 1, 1, 1)), (-0.4, (1, 0, 3, 0)),
+    (-0.4, (1, 0, 1, 2)), (0.1, (0, 4, 0, 0)), (-0.4, (0, 3, 0, 1)), (0.2, (0, 2, 2, 0)), (0.6, (0, 2, 0, 2)),
+    (0.5, (0, 2, 0, 0)), (-0.4, (0, 1, 2, 1)), (-0.4, (0, 1, 0, 3)), (0.1, (0, 0, 4, 0)), (0.2, (0, 0, 2, 2)),
+    (0.5, (0, 0, 2, 0)), (0.1, (0, 0, 0, 4)), (0.5, (0, 0, 0, 2))]
 
 
 def _log(msg):
@@ -52,6 +59,8 @@ CASES = [  # terms, dim, m, a, b, T, s, p, flags, k
     (COUPLED_2D, 2, 1.0, (0.1, -0.1), (0.6, 0.2), 1.0, 4, 7, P.FLAG_HIERARCHY, 1200),           # U = 4
     (COUPLED_2D, 2, 1.0, (0.0, 0.0), (1.0, 0.0), 1.0, 10, 10, P.FLAG_HIERARCHY, 200),     # full size
     (COUPLED_3D, 3, 1.0, (0.0, 0.0, 0.0), (0.5, 0.5, 0.0), 1.0, 8, 8, P.FLAG_HIERARCHY, 200),
+    (TWO_PARTICLES_2D, 4, 1.0, (0.0, 0.1, 0.2, 0.0), (0.3, 0.0, 0.1, -0.2), 1.0, 6, 6, P.FLAG_HIERARCHY, 400),  # d = 4
+    (TWO_PARTICLES_2D, 4, 2.0, (0.1, 0.0, 0.0, 0.2), (0.0, 0.3, 0.1, 0.0), 0.5, 3, 5, 0, 400),      # d = 4, U = 3
 ]
 
 
@@ -90,13 +99,13 @@ def _radial_terms(a, d):
     return [(float(c), k[:d]) for k, c in ov.radial_to_components(a, d).items()]
 
 
-@pytest.mark.parametrize("dim,p,s", [(2, 12, 6), (3, 8, 5)])
+@pytest.mark.parametrize("dim,p,s", [(2, 12, 6), (3, 8, 5), (4, 8, 6)])
 def test_rotation_invariant_V_equals_the_radial_route(ctx, dim, p, s):
     """V = r^2/2 + r^4/4 written out in components: per-path actions equal the oracle's invariant route
     (and the library's radial mode) on the same paths."""
     a = (0.0, 0.5, 0.25)
     terms = _radial_terms(a, dim)
-    qa, qb = (0.1, -0.2, 0.3)[:dim], (0.4, 0.1, -0.2)[:dim]
+    qa, qb = (0.1, -0.2, 0.3, 0.0)[:dim], (0.4, 0.1, -0.2, 0.1)[:dim]
     _log(f"poly isotropic dim={dim} p={p} s={s}")
     got = ctx.path_actions_poly(terms, dim, 1.5, qa, qb, 1.0, 1 << s, p, 11, 2, P.FLAG_HIERARCHY, 0, 400)
     ref = ov.path_actions(a, dim, 1.5, qa, qb, 1.0, s, p, 11, 2, np.arange(400))
@@ -142,6 +151,32 @@ def test_path_indices_beyond_32_bits(ctx):
     ref, scale = ov.poly_path_actions(COUPLED_2D, 2, 1.0, (0.1, 0.0), (0.4, -0.2), 1.0, 4, 5, 3, 9,
                                       np.arange(first, first + 300, dtype=np.uint64), with_scale=True)
     _check_levels(got, ref, scale, 4, P.FLAG_HIERARCHY)
+
+
+def test_two_particles_in_two_dimensions(ctx):
+    """Four coordinates: amplitudes on identical samples against the oracle, and the exact separation
+    R = (r_1 + r_2)/sqrt 2, rho = (r_1 - r_2)/sqrt 2 (|R|^2/2 + |rho|^2/2 + 0.4 |rho|^4, same free
+    measure): at the continuum the amplitude is the Mehler product in R times the two-dimensional
+    anharmonic oscillator in rho, which the radial mode gives (here both at p = 10, N = 64)."""
+    a, b, T = (0.0, 0.1, 0.2, 0.0), (0.3, 0.0, 0.1, -0.2), 1.0
+    n = 4000
+    res, st = ctx.amplitude_poly(TWO_PARTICLES_2D, 4, 1.0, a, b, T, 16, 5, n, 5, 1, P.FLAG_HIERARCHY)
+    ref = ov.poly_amplitude(TWO_PARTICLES_2D, 4, 1.0, a, b, T, 4, 5, n, 5, 1)
+    assert st == 0
+    for lev in range(5):
+        assert res[lev].amp == pytest.approx(ref[lev]["amp"], rel=1e-10), lev
+        if lev:
+            assert res[lev].err == pytest.approx(ref[lev]["err"], rel=1e-7), lev
+    r2 = math.sqrt(2.0)
+    Ra, Rb = [(a[i] + a[i + 2]) / r2 for i in (0, 1)], [(b[i] + b[i + 2]) / r2 for i in (0, 1)]
+    ra, rb = [(a[i] - a[i + 2]) / r2 for i in (0, 1)], [(b[i] - b[i + 2]) / r2 for i in (0, 1)]
+    full, _ = ctx.amplitude_poly(TWO_PARTICLES_2D, 4, 1.0, a, b, T, 64, 10, 2_000_000, 3, 0, P.FLAG_HIERARCHY)
+    rel, _ = ctx.amplitude_radial((0.0, 0.5, 0.4), 2, 1.0, ra, rb, T, 64, 10, 2_000_000, 4, 0, P.FLAG_HIERARCHY)
+    com = cf.mehler(Ra[0], Rb[0], T) * cf.mehler(Ra[1], Rb[1], T)
+    ref6 = com * rel[6].amp
+    err6 = math.hypot(full[6].err, com * rel[6].err)
+    _log(f"two particles in 2D: {full[6].amp:.8e} +- {full[6].err:.1e}; separated {ref6:.8e}")
+    assert abs(full[6].amp - ref6) <= 5 * err6, (full[6].amp, ref6, err6)
 
 
 def test_largest_size_nests(ctx):

@@ -189,6 +189,7 @@ def test_mpt_level_table_matches_exact_oracle(lam, alpha, m, T, p, level):
 @pytest.mark.parametrize("coefs,dim,m,T,p,level", [
     ((0.0, 0.5, 10 / 24), 2, 1.0, 1.0, 18, 3), ((0.0, 0.5, 10 / 24), 2, 1.0, 2.0, 10, 0),
     ((0.3, 0.5, 1 / 24), 3, 2.0, 1.0, 12, 5), ((0.25, 1.0, 0.125), 1, 1.0, 0.5, 8, 2), ((1.0,), 2, 1.0, 1.0, 4, 1),
+    ((0.0, 0.5, 0.4), 4, 1.5, 1.0, 10, 3),
 ])
 def test_radial_level_table_matches_exact_oracle(coefs, dim, m, T, p, level):
     """Several coordinates: the library's FP64 invariant recursion folded per level agrees with the
@@ -223,6 +224,8 @@ COUPLED_2D = [(0.5, (2, 0)), (0.7, (0, 2)), (0.1, (4, 0)), (-0.4, (3, 1)), (0.6,
     (COUPLED_2D, 2, 1.0, 1.0, 6, 2), (COUPLED_2D, 2, 4.0, 2.0, 5, 0),
     ([(0.5, (2, 0, 0)), (0.2, (0, 2, 1)), (0.05, (1, 1, 2)), (0.3, (0, 0, 2)), (0.1, (0, 0, 1))], 3, 2.0, 1.0, 4, 3),
     ([(0.2, (0,)), (-0.3, (1,)), (0.5, (2,)), (0.25, (4,))], 1, 1.0, 0.5, 7, 1),
+    ([(0.5, (2, 0, 0, 0)), (0.5, (0, 0, 0, 2)), (0.1, (2, 0, 2, 0)), (-0.2, (1, 1, 1, 1)), (0.05, (0, 4, 0, 0)),
+      (0.3, (0, 0, 1, 0))], 4, 2.0, 1.0, 5, 2),
 ])
 def test_poly_level_table_matches_exact_oracle(terms, dim, m, T, p, level):
     """Any polynomial V: the library's FP64 component recursion folded per level agrees monomial by
@@ -252,7 +255,7 @@ def test_poly_entry_points_validate_without_a_device():
         return lib.pimc_path_actions_poly(None, ctypes.byref(V), 1.0, a, b, 1.0, N, p, 1, 0, 0, 0, 1, out)
 
     assert st(P.poly_potential([(0.5, (2, 0))], 0)) == -1                  # dim
-    assert st(P.poly_potential([(0.5, (2, 0))], 4)) == -1
+    assert st(P.poly_potential([(0.5, (2, 0))], 5)) == -1
     assert st(P.poly_potential([(0.5, (2, 1, 1))], 2)) == -1               # exponent beyond dim
     assert st(P.poly_potential([(0.5, (3, 2))], 2)) == -1                  # total degree 5
     assert st(P.poly_potential([(0.5, (-1, 2))], 2)) == -1                 # negative exponent
@@ -260,10 +263,10 @@ def test_poly_entry_points_validate_without_a_device():
     assert st(P.poly_potential([(0.5, (2, 0))], 2), N=15) == -1
     assert st(P.poly_potential([(0.5, (2, 0))], 2), p=0) == -1
     V = P.poly_potential([(0.5, (2, 0))], 2)
-    V.n_terms = 36
+    V.n_terms = 71
     assert st(V) == -1
     with pytest.raises(ValueError):
-        P.poly_potential([(0.1, (1, 0))] * 36, 2)
+        P.poly_potential([(0.1, (1, 0))] * 71, 2)
     need = ctypes.c_size_t(0)
     V = P.poly_potential([(0.5, (2, 0))], 2)
     assert lib.pimc_level_table_poly(ctypes.byref(V), 1.0, 1.0, 4, 0, None, 0, None, 0, ctypes.byref(need)) == -1
@@ -276,7 +279,7 @@ def test_radial_entry_points_validate_without_a_device():
     a = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
     b = (ctypes.c_double * 3)(1.0, 0.0, 0.0)
     out = (ctypes.c_double * 16)()
-    for dim, coefs in ((0, (0, 0.5)), (4, (0, 0.5)), (2, (0, 0.5, 0.1))):
+    for dim, coefs in ((0, (0, 0.5)), (5, (0, 0.5)), (2, (0, 0.5, 0.1))):
         V = P.binding.RadialPotential()
         V.dim = dim
         V.degree = len(coefs) - 1

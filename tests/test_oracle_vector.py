@@ -189,7 +189,7 @@ def test_separable_potential_gives_the_sum_of_one_dimensional_actions():
         assert poly == ref, (m, k)
 
 
-@pytest.mark.parametrize("d,p", [(2, 3), (2, 5), (3, 3), (3, 4)])
+@pytest.mark.parametrize("d,p", [(2, 3), (2, 5), (3, 3), (3, 4), (4, 3)])
 @pytest.mark.parametrize("a", [ov.aho2d(1, 6), (F(1, 3), F(1, 2), F(-1, 4), F(1, 12))])
 def test_invariant_route_equals_the_component_route(d, p, a):
     Wc = ov.component_coefficients(ov.radial_to_components(a, d), d, p)
@@ -282,7 +282,7 @@ def _terms_of(C, d):
     return [(float(c), k[:d]) for k, c in C.items()]
 
 
-@pytest.mark.parametrize("d,p", [(2, 6), (3, 4)])
+@pytest.mark.parametrize("d,p", [(2, 6), (3, 4), (4, 4)])
 def test_component_slice_action_of_a_radial_V_is_the_invariant_one(d, p):
     """For V = sum a_n (q.q)^n written out in components, the component-route slice action (fold over
     m, k of the exact W_{m,k} and term-by-term evaluation) equals the invariant-route tables evaluated
@@ -357,3 +357,36 @@ def test_one_coordinate_component_route_is_the_one_dimensional_path_action():
     S, scale = ov.poly_path_actions(terms, 1, 2.0, (0.3,), (-0.4,), 1.0, 4, 5, 9, 1, np.arange(40), with_scale=True)
     ref = opimc.path_actions(ea.poly(coefs), 2.0, 0.3, -0.4, 1.0, 4, 5, 9, 1, np.arange(40))
     assert np.all(np.abs(S - ref) <= 1e-13 * scale)
+
+
+# two particles in two dimensions, r_1 = (q_1, q_2), r_2 = (q_3, q_4): V = |r_1|^2/2 + |r_2|^2/2
+# + 0.1 |r_1 - r_2|^4, expanded in the four coordinates
+TWO_PARTICLES_2D = [
+    (0.1, (4, 0, 0, 0)), (-0.4, (3, 0, 1, 0)), (0.2, (2, 2, 0, 0)), (-0.4, (2, 1, 0, 1)), (0.6, (2, 0, 2, 0)),
+    (0.2, (2, 0, 0, 2)), (0.5, (2, 0, 0, 0)), (-0.4, (1, 2, 1, 0)), (0.8, (1, 1, 1, 1)), (-0.4, (1, 0, 3, 0)),
+    (-0.4, (1, 0, 1, 2)), (0.1, (0, 4, 0, 0)), (-0.4, (0, 3, 0, 1)), (0.2, (0, 2, 2, 0)), (0.6, (0, 2, 0, 2)),
+    (0.5, (0, 2, 0, 0)), (-0.4, (0, 1, 2, 1)), (-0.4, (0, 1, 0, 3)), (0.1, (0, 0, 4, 0)), (0.2, (0, 0, 2, 2)),
+    (0.5, (0, 0, 2, 0)), (0.1, (0, 0, 0, 4)), (0.5, (0, 0, 0, 2))]
+
+
+def test_two_particles_in_two_dimensions_separate_into_centre_of_mass_and_relative_motion():
+    """With R = (r_1 + r_2)/sqrt 2 and rho = (r_1 - r_2)/sqrt 2 the potential is |R|^2/2 + |rho|^2/2 +
+    0.4 |rho|^4 and the free measure is unchanged, so the four-coordinate slice action (component
+    route, every cross term of the pair interaction) equals the two-dimensional isotropic oscillator's
+    at (R, Rbar) plus the two-dimensional anharmonic oscillator's at (rho, rhobar), both from the
+    invariant route."""
+    p, eps = 5, 0.3
+    tab = ov.component_tables(ov.terms_to_components(TWO_PARTICLES_2D, 4), 4, p, eps, 0)[0]
+    rng = np.random.default_rng(11)
+    x = rng.uniform(-1.2, 1.2, (30, 4))
+    xb = rng.uniform(-0.3, 0.3, (30, 4))
+    got = ov.component_eps_W(tab, x, xb)
+    r2 = math.sqrt(2.0)
+
+    def split(v):
+        return (v[:, :2] + v[:, 2:]) / r2, (v[:, :2] - v[:, 2:]) / r2
+    (R, rho), (Rb, rhob) = split(x), split(xb)
+    ref = (ov.eps_W(ov.level_tables((0.0, 0.5), 2, p, eps, 0)[0], R, Rb)
+           + ov.eps_W(ov.level_tables((0.0, 0.5, 0.4), 2, p, eps, 0)[0], rho, rhob))
+    scale = ov.component_eps_W_abs(tab, x, xb)
+    assert np.all(np.abs(got - ref) <= 1e-13 * scale + 1e-15), np.max(np.abs(got - ref))
