@@ -447,7 +447,9 @@ def component_rows(P, ctx, base=None):
     for case in C["cases"]:
         args = (case["terms"], case["dim"], 1.0, case["a"], case["b"], C["T"], 1 << C["s"], case["p"])
         ns = case.get("samples", C["samples"])
-        ctx.amplitude_poly(*args, 1 << 16, 1, 0, P.FLAG_HIERARCHY)                # load the kernels
+        # warm-up: the host recursion of (V, m, p) (cached) and the code object, at N = 2
+        ctx.amplitude_poly(case["terms"], case["dim"], 1.0, case["a"], case["b"], C["T"], 2, case["p"], 4096, 1, 0,
+                           P.FLAG_HIERARCHY)
         res, st = ctx.amplitude_poly(*args, ns, 1, 0, P.FLAG_HIERARCHY)
         ms = ctx.last_kernel_ms()
         rate = ns * slices_per_sample(C["s"], True) / (ms / 1e3)
