@@ -162,6 +162,9 @@ def test_invalid_arguments(ctx):
     with pytest.raises(P.PimcError) as e:
         ctx.amplitude_radial(AHO6, 2, 1.0, (0, 0), (1, 0), 1.0, 16, 4, 100, 1, 0, P.FLAG_FP32_POLY)
     assert e.value.status == -2
+    with pytest.raises(P.PimcError) as e:             # four coordinates: the walk's LDS at N = 2^18
+        ctx.amplitude_radial(AHO6, 4, 1.0, (0, 0, 0, 0), (1, 0, 0, 0), 1.0, 1 << 18, 4, 100, 1)
+    assert e.value.status == -2
     with pytest.raises(P.PimcError):
         ctx.amplitude_radial(AHO6, 2, 1.0, (0, 0), (1, 0), 1.0, 16, 19, 100, 1)           # p > 18
     with pytest.raises(P.PimcError):
