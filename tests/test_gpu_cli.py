@@ -32,3 +32,22 @@ def test_cli_help_and_errors():
     assert out.returncode == 0 and "usage" in out.stdout
     bad = subprocess.run([CLI, "1", "0", "1", "4", "1"], capture_output=True, text=True, timeout=60)
     assert bad.returncode == 2
+
+
+def test_cli_several_coordinates_like_the_library():
+    # 2D anharmonic oscillator of Sec. 3.3 (A = 1, g = 10): V = (q.q)/2 + 10 (q.q)^2 / 24
+    args = ["--dim", "2", "-p", "8", "1.0", "0", "0.5", "1", "-0.5", "4", "20000", "7", "0", "0.5", str(10 / 24)]
+    out = subprocess.run([CLI] + args, capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    rows = np.array([[float(v) for v in line.split()] for line in out.stdout.strip().splitlines()])
+    assert rows.shape == (5, 4) and list(rows[:, 1]) == [1, 2, 4, 8, 16]
+    with P.Context() as ctx:
+        res, _ = ctx.amplitude_radial([0, 0.5, 10 / 24], 2, 1.0, [0.0, 0.5], [1.0, -0.5], 1.0, 16, 8, 20000, 7, 0,
+                                      P.FLAG_HIERARCHY)
+    for n in range(5):
+        assert rows[n, 2] == res[n].amp and rows[n, 3] == res[n].err
+    bad = subprocess.run([CLI, "--dim", "5", "1", "0"], capture_output=True, text=True, timeout=60)
+    assert bad.returncode == 2
+    short = subprocess.run([CLI, "--dim", "2", "1.0", "0", "0", "1", "1", "4", "100", "1"], capture_output=True,
+                           text=True, timeout=60)
+    assert short.returncode == 2                     # no coefficient given
