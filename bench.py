@@ -56,9 +56,10 @@ SPECTRUM = [dict(name="anharmonic A=1 g=48", A=1.0, g=48.0, t=0.02, L=8.0),
             dict(name="double well A=-10 g=12", A=-10.0, g=12.0, t=0.1, L=10.0)]
 SPEC_N, SPEC_P, SPEC_K = 16384, 21, 10
 # Several coordinates (Sec. 2.2): the 2D anharmonic oscillator of Sec. 3.3, V = r^2/2 + g r^4/24, and its
-# 3D analogue, at p = 18, every level of s = 10, 1e8 samples; the 2D value against a tensor-product DVR.
+# 3D and 4D analogues, at p = 18, every level of s = 10, 1e8 samples; the 2D value against a tensor-product DVR.
 VECTOR = dict(g=10.0, T=1.0, s=10, p=18, samples=100_000_000,
-              ends={2: ((0.0, 0.0), (1.0, 0.4)), 3: ((0.0, 0.0, 0.0), (1.0, 0.4, -0.2))})
+              ends={2: ((0.0, 0.0), (1.0, 0.4)), 3: ((0.0, 0.0, 0.0), (1.0, 0.4, -0.2)),
+                    4: ((0.0, 0.0, 0.0, 0.0), (1.0, 0.4, -0.2, 0.3))})
 RADIAL_E = {18: 102}                     # coefficients of the (u, z, w^2) table at p = 18
 # Any polynomial V (component route): two particles on a line with a quartic pair interaction
 # 0.1 (q1 - q2)^4 in an anisotropic trap with a field (d = 2, p = 10), an anisotropic 3D trap with
@@ -246,7 +247,7 @@ def oracle_section_baselines(which):
     sl = slices_per_sample(10, True)
     if "vector" in which:
         out["vector"] = {}
-        for dim in (2, 3):
+        for dim in (2, 3, 4):
             n, dt, cores = _timed_pool(_oracle_vector_worker, [(dim, 256 * i, 256) for i in range(16)])
             out["vector"][str(dim)] = {"value": n * sl / dt, "unit": "slice-evals/s", "cores": cores, "kind": "oracle",
                                        "sample": f"first {n} paths of the d={dim} workload (p=18, s=10, every level), "
@@ -412,13 +413,13 @@ def general_section(P, ctx, base=None):
 
 
 def vector_section(P, ctx, dvr, base=None):
-    """Several coordinates: A_N^(18) of the 2D and 3D anharmonic oscillators from one s = 10 run each
+    """Several coordinates: A_N^(18) of the 2D, 3D and 4D anharmonic oscillators from one s = 10 run each
     (every level), the kernel rate against the FP64 vector peak, and the 2D value against the DVR."""
     V = VECTOR
     coefs = (0.0, 0.5, V["g"] / 24.0)
-    out = {"workload": f"V=r^2/2+{V['g']:g} r^4/24 in d=2 and d=3, p={V['p']}, s={V['s']} (every level), "
+    out = {"workload": f"V=r^2/2+{V['g']:g} r^4/24 in d=2, 3 and 4, p={V['p']}, s={V['s']} (every level), "
                        f"T={V['T']:g}, {V['samples']:.0e} samples", "per_dim": {}}
-    for dim in (2, 3):
+    for dim in (2, 3, 4):
         a, b = V["ends"][dim]
         ctx.amplitude_radial(coefs, dim, 1.0, a, b, V["T"], 1 << V["s"], V["p"], 1 << 20, 1, 0, P.FLAG_HIERARCHY)
         res, st = ctx.amplitude_radial(coefs, dim, 1.0, a, b, V["T"], 1 << V["s"], V["p"], V["samples"], 1, 0,
@@ -435,6 +436,7 @@ def vector_section(P, ctx, dvr, base=None):
         if base is not None:
             row["cpu_baseline"] = base[str(dim)]
         out["per_dim"][str(dim)] = row
+        _progress(f"vector d={dim}: {rate:.3e} slice-evals/s")
     out["component"] = component_rows(P, ctx, base.get("component") if base is not None else None)
     return out
 
