@@ -233,7 +233,7 @@ int pimc_path_actions_general(pimc_ctx *ctx, const pimc_general_potential *V, do
  * a and b: host arrays of dim doubles. FP64 only (PIMC_FP32_POLY returns EUNSUPPORTED); outputs,
  * flags and errors as pimc_amplitude / pimc_path_actions. EUNSUPPORTED also when the walk's
  * per-workgroup LDS (the pending right endpoints of its upper levels) exceeds the device's limit:
- * with 160 KB, N > 2^17 in four coordinates. EINVAL: dim outside 1..PIMC_MAX_DIM,
+ * with 160 KB, N = 2^20 in four coordinates. EINVAL: dim outside 1..PIMC_MAX_DIM,
  * degree outside 0..PIMC_MAX_RADIAL_DEGREE, non-finite coefficients or endpoints, and the conditions
  * of pimc_amplitude. */
 #define PIMC_MAX_DIM 4             /* d = D*M <= 4: e.g. two particles in two dimensions        */

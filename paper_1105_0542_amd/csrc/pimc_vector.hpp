@@ -102,11 +102,15 @@ struct VecArgs {
     double* dump;                      // device [path][s+1] or null
 };
 
-// Dynamic LDS bytes: the Box-Muller table; per lane D level sums and (D+1)*dim pending right
-// endpoints; per accumulator slot and level three sums.
+// LDS doubles per lane of the walk above the register subtrees (D levels): D level sums and the
+// pending right endpoints of levels 2..D (level 1's right endpoint is b itself), dim each.
+__host__ __device__ constexpr int vec_top_slots(int dim, int D) { return D + (D > 1 ? (D - 1) * dim : 0); }
+
+// Dynamic LDS bytes: the Box-Muller table; per lane the walk's slots; per accumulator slot and level
+// three sums.
 inline size_t vec_lds_bytes(int dim, int D, int s) {
-    return (size_t(kBoxMullerTable) + size_t(D + (D + 1) * dim) * kVecBlock + size_t(kChunkSlots * (s + 1) * 3)) *
-           sizeof(double);
+    return (size_t(kBoxMullerTable) + size_t(vec_top_slots(dim, D)) * kVecBlock +
+            size_t(kChunkSlots * (s + 1) * 3)) * sizeof(double);
 }
 
 // Component evaluator (any polynomial V): a level-independent structure stream (A.shape, ints) and

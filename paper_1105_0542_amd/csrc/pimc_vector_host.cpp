@@ -384,7 +384,7 @@ int stage_vector(pimc_ctx* c, const VecProblem& P, uint64_t seed, uint32_t strea
     return PIMC_OK;
 }
 
-// The walk keeps (D + (D+1)*dim) doubles per lane in LDS: refuse a launch the device cannot hold.
+// The walk keeps vec_top_slots(dim, D) doubles per lane in LDS: refuse a launch the device cannot hold.
 int check_lds(pimc_ctx* c, const VecProblem& P) {
     int max_lds = 0;
     HIP_TRY(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));

@@ -377,7 +377,7 @@ __device__ __forceinline__ void run_subtree(const Eval& ev_in, const VecArgs& A,
 
 // ---------------------------------------------------------------------------- one path
 // top: this lane's LDS slots (stride kVecBlock): S_top[n] at slot n (n < D); the pending right
-// endpoint of level L (L = 2..D), coordinate c, at slot D + L*DIM + c.
+// endpoint of level L (L = 2..D), coordinate c, at slot D + (L-2)*DIM + c.
 template <int DIM, int U, class Eval>
 __device__ __forceinline__ void walk_path(const Eval& ev, const VecArgs& A, const VecSource<DIM>& src, double* top,
                                           double (&Ssub)[U + 1]) {
@@ -423,7 +423,7 @@ __device__ __forceinline__ void walk_path(const Eval& ev, const VecArgs& A, cons
             L = D - t;
             node = (nTop + J) >> t;
 #pragma unroll
-            for (int c = 0; c < DIM; ++c) qR[c] = R[(L * DIM + c) * kVecBlock];
+            for (int c = 0; c < DIM; ++c) qR[c] = R[((L - 2) * DIM + c) * kVecBlock];
             src.node(node, z);
         }
         double qm[DIM], zl[DIM], zr[DIM];
@@ -446,7 +446,7 @@ __device__ __forceinline__ void walk_path(const Eval& ev, const VecArgs& A, cons
             if (L == D) break;
 #pragma unroll
             for (int c = 0; c < DIM; ++c) {
-                R[((L + 1) * DIM + c) * kVecBlock] = qR[c];   // right child of `node`: (qm, qR)
+                R[((L - 1) * DIM + c) * kVecBlock] = qR[c];   // right child of `node`: (qm, qR), level L+1
                 qR[c] = qm[c];
                 z[c] = zl[c];
             }
@@ -488,7 +488,7 @@ __device__ __forceinline__ void process_chunk(const Eval& ev, const VecArgs& A, 
     const int nlev = A.s + 1;
     const double* bm = smem;
     double* top = smem + kBoxMullerTable + tid;
-    double* acc = smem + kBoxMullerTable + size_t(D + (D + 1) * DIM) * kVecBlock;
+    double* acc = smem + kBoxMullerTable + size_t(vec_top_slots(DIM, D)) * kVecBlock;
     const uint64_t first = c * kChunkPaths;
     if (A.partials) {
         for (int i = tid; i < kChunkSlots * nlev * 3; i += kVecBlock) acc[i] = 0.0;

@@ -108,7 +108,7 @@ def test_single_slice_is_the_short_time_amplitude(ctx):
 
 
 def test_largest_size_nests(ctx):
-    """Three coordinates at N = 2^20 (the deepest walk, 67 LDS slots per lane): levels 0..8 of the
+    """Three coordinates at N = 2^20 (the deepest walk, 65 LDS slots per lane): levels 0..8 of the
     per-path actions equal an s = 8 run of the same paths bitwise, and the finest level is finite."""
     big = ctx.path_actions_radial(AHO6, 3, 1.0, (0.0, 0.1, 0.0), (0.3, 0.0, 0.2), 1.0, 1 << 20, 6, 3, 1,
                                   P.FLAG_HIERARCHY, 0, 256)
@@ -120,6 +120,17 @@ def test_largest_size_nests(ctx):
     d_fine = np.abs(big[:, 20] - big[:, 19]).mean()
     d_coarse = np.abs(big[:, 5] - big[:, 4]).mean()
     assert d_fine < 1e-3 * d_coarse
+
+
+def test_largest_four_coordinate_walk_nests(ctx):
+    """Four coordinates at N = 2^19, the deepest walk whose LDS (16 level sums and the pending right
+    endpoints of levels 2..16, 76 slots per lane, 159,616 bytes per workgroup) fits in 160 KB: levels
+    0..8 of the per-path actions equal an s = 8 run of the same paths bitwise."""
+    a, b = (0.0, 0.1, 0.0, -0.2), (0.3, 0.0, 0.2, 0.1)
+    big = ctx.path_actions_radial(AHO6, 4, 1.0, a, b, 1.0, 1 << 19, 6, 5, 2, P.FLAG_HIERARCHY, 0, 128)
+    small = ctx.path_actions_radial(AHO6, 4, 1.0, a, b, 1.0, 1 << 8, 6, 5, 2, P.FLAG_HIERARCHY, 0, 128)
+    assert np.array_equal(big[:, :9], small)
+    assert np.all(np.isfinite(big[:, 19]))
 
 
 def test_convergence_to_the_2d_continuum(ctx):
@@ -162,8 +173,8 @@ def test_invalid_arguments(ctx):
     with pytest.raises(P.PimcError) as e:
         ctx.amplitude_radial(AHO6, 2, 1.0, (0, 0), (1, 0), 1.0, 16, 4, 100, 1, 0, P.FLAG_FP32_POLY)
     assert e.value.status == -2
-    with pytest.raises(P.PimcError) as e:             # four coordinates: the walk's LDS at N = 2^18
-        ctx.amplitude_radial(AHO6, 4, 1.0, (0, 0, 0, 0), (1, 0, 0, 0), 1.0, 1 << 18, 4, 100, 1)
+    with pytest.raises(P.PimcError) as e:             # four coordinates: the walk's LDS at N = 2^20
+        ctx.amplitude_radial(AHO6, 4, 1.0, (0, 0, 0, 0), (1, 0, 0, 0), 1.0, 1 << 20, 4, 100, 1)
     assert e.value.status == -2
     with pytest.raises(P.PimcError):
         ctx.amplitude_radial(AHO6, 2, 1.0, (0, 0), (1, 0), 1.0, 16, 19, 100, 1)           # p > 18
