@@ -190,6 +190,17 @@ def test_largest_size_nests(ctx):
     assert np.abs(big[:, 20] - big[:, 19]).mean() < 1e-3 * np.abs(big[:, 5] - big[:, 4]).mean()
 
 
+def test_largest_four_coordinate_walk_nests(ctx):
+    """Two particles in two dimensions at N = 2^20 (6-level subtrees, 14 walk levels: 66 LDS slots
+    per lane, 139,232 bytes per workgroup): levels 0..8 of the per-path actions equal an s = 8 run of
+    the same paths bitwise, and the finest level is finite."""
+    args = (TWO_PARTICLES_2D, 4, 1.0, (0.0, 0.1, 0.0, -0.2), (0.3, 0.0, 0.2, 0.1), 1.0)
+    big = ctx.path_actions_poly(*args, 1 << 20, 4, 3, 1, P.FLAG_HIERARCHY, 0, 64)
+    small = ctx.path_actions_poly(*args, 1 << 8, 4, 3, 1, P.FLAG_HIERARCHY, 0, 64)
+    assert np.array_equal(big[:, :9], small)
+    assert np.all(np.isfinite(big[:, 20]))
+
+
 def test_coupled_oscillators_are_a_mehler_product(ctx):
     """V = q1^2/2 + q2^2/2 + g (q1 - q2)^2 separates in r = (q1 - q2)/sqrt 2 (omega^2 = 1 + 4g) and
     s = (q1 + q2)/sqrt 2 (omega = 1); the exact kernel is the product of the two Mehler kernels at the
