@@ -120,9 +120,9 @@ inline size_t vec_lds_bytes(int dim, int D, int s) {
 #define PIMC_POLY_U 5
 #endif
 #ifndef PIMC_POLY_U3
-#define PIMC_POLY_U3 6
+#define PIMC_POLY_U3 7
 #endif
-// Subtree levels of the component evaluator (1..6) in d = 1, 2 and in d = 3, 4: deeper than the radial
+// Subtree levels of the component evaluator (1..7) in d = 1, 2 and in d = 3, 4: deeper than the radial
 // kernels' 3, because its cost is a pass over the structure per slice batch, and deeper subtrees give
 // fewer, wider batches (the points that do not fit the registers live in scratch).
 constexpr int kPolyU = PIMC_POLY_U;

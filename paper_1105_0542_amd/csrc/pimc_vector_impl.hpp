@@ -601,6 +601,7 @@ inline hipError_t launch_poly(const VecArgs& A, int U, int grid, hipStream_t st)
         case 4: if constexpr (poly_subtree_levels(DIM) >= 4) return launch_one<DIM, 4>(A, ev, grid, st); break;
         case 5: if constexpr (poly_subtree_levels(DIM) >= 5) return launch_one<DIM, 5>(A, ev, grid, st); break;
         case 6: if constexpr (poly_subtree_levels(DIM) >= 6) return launch_one<DIM, 6>(A, ev, grid, st); break;
+        case 7: if constexpr (poly_subtree_levels(DIM) >= 7) return launch_one<DIM, 7>(A, ev, grid, st); break;
         default: break;
     }
     return hipErrorInvalidValue;
@@ -614,6 +615,7 @@ inline int resident_poly(int U, size_t lds, int device) {
         case 4: if constexpr (poly_subtree_levels(DIM) >= 4) return resident_one<DIM, 4, PolyEvalRT<DIM>>(lds, device); break;
         case 5: if constexpr (poly_subtree_levels(DIM) >= 5) return resident_one<DIM, 5, PolyEvalRT<DIM>>(lds, device); break;
         case 6: if constexpr (poly_subtree_levels(DIM) >= 6) return resident_one<DIM, 6, PolyEvalRT<DIM>>(lds, device); break;
+        case 7: if constexpr (poly_subtree_levels(DIM) >= 7) return resident_one<DIM, 7, PolyEvalRT<DIM>>(lds, device); break;
         default: break;
     }
     return resident_one<DIM, 3, PolyEvalRT<DIM>>(lds, device);

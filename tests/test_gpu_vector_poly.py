@@ -61,6 +61,9 @@ CASES = [  # terms, dim, m, a, b, T, s, p, flags, k
     (COUPLED_3D, 3, 1.0, (0.0, 0.0, 0.0), (0.5, 0.5, 0.0), 1.0, 8, 8, P.FLAG_HIERARCHY, 200),
     (TWO_PARTICLES_2D, 4, 1.0, (0.0, 0.1, 0.2, 0.0), (0.3, 0.0, 0.1, -0.2), 1.0, 6, 6, P.FLAG_HIERARCHY, 400),  # d = 4
     (TWO_PARTICLES_2D, 4, 2.0, (0.1, 0.0, 0.0, 0.2), (0.0, 0.3, 0.1, 0.0), 0.5, 3, 5, 0, 400),      # d = 4, U = 3
+    (TWO_PARTICLES_2D, 4, 1.0, (0.2, 0.0, -0.1, 0.1), (0.1, 0.2, 0.0, -0.3), 1.0, 7, 4, P.FLAG_HIERARCHY, 100),
+    # d = 4, U = 7 (one subtree, no walk levels)
+    (COUPLED_3D, 3, 1.0, (0.1, 0.0, 0.2), (0.0, -0.3, 0.4), 1.5, 9, 5, P.FLAG_HIERARCHY, 100),  # U = 7, 2 walk levels
 ]
 
 
@@ -191,8 +194,8 @@ def test_largest_size_nests(ctx):
 
 
 def test_largest_four_coordinate_walk_nests(ctx):
-    """Two particles in two dimensions at N = 2^20 (6-level subtrees, 14 walk levels: 66 LDS slots
-    per lane, 139,232 bytes per workgroup): levels 0..8 of the per-path actions equal an s = 8 run of
+    """Two particles in two dimensions at N = 2^20 (7-level subtrees, 13 walk levels: 61 LDS slots
+    per lane, 128,992 bytes per workgroup): levels 0..8 of the per-path actions equal an s = 8 run of
     the same paths bitwise, and the finest level is finite."""
     args = (TWO_PARTICLES_2D, 4, 1.0, (0.0, 0.1, 0.0, -0.2), (0.3, 0.0, 0.2, 0.1), 1.0)
     big = ctx.path_actions_poly(*args, 1 << 20, 4, 3, 1, P.FLAG_HIERARCHY, 0, 64)
