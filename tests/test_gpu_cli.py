@@ -46,6 +46,17 @@ def test_cli_several_coordinates_like_the_library():
                                       P.FLAG_HIERARCHY)
     for n in range(5):
         assert rows[n, 2] == res[n].amp and rows[n, 3] == res[n].err
+    # four coordinates (two particles in two dimensions, isotropic): 4 + 4 endpoint coordinates
+    a4, b4 = [0.1, 0.0, -0.2, 0.3], [0.4, 0.1, 0.0, -0.1]
+    args4 = ["--dim", "4", "-p", "6", "-m", "1.5", "0.8"] + [str(v) for v in a4 + b4] + ["3", "5000", "2", "0.1", "0.5"]
+    out4 = subprocess.run([CLI] + args4, capture_output=True, text=True, timeout=120)
+    assert out4.returncode == 0, out4.stderr
+    rows4 = np.array([[float(v) for v in line.split()] for line in out4.stdout.strip().splitlines()])
+    assert rows4.shape == (4, 4)
+    with P.Context() as ctx:
+        res4, _ = ctx.amplitude_radial([0.1, 0.5], 4, 1.5, a4, b4, 0.8, 8, 6, 5000, 2, 0, P.FLAG_HIERARCHY)
+    for n in range(4):
+        assert rows4[n, 2] == res4[n].amp and rows4[n, 3] == res4[n].err
     bad = subprocess.run([CLI, "--dim", "5", "1", "0"], capture_output=True, text=True, timeout=60)
     assert bad.returncode == 2
     short = subprocess.run([CLI, "--dim", "2", "1.0", "0", "0", "1", "1", "4", "100", "1"], capture_output=True,
