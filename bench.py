@@ -1028,8 +1028,8 @@ def main():
                                           "relvar": r[S_DEPTH].relvar, "nonfinite": r[S_DEPTH].n_nonfinite}
                     for (g, T, r) in last},
     }
-    # detailed sections first (long arrays), then a compact summary of every section last, so that the
-    # end of the line -- what a log tail keeps -- carries every figure
+    # detailed sections first (long arrays), then a compact summary of every section as the last key
+    # (after cpu_baseline), so that the end of the line -- what a log tail keeps -- carries the figures
     if c2_line is not None:
         line["c2"] = c2_line
     line["spectrum"] = spec_line
@@ -1044,9 +1044,9 @@ def main():
     line["level_s_only"] = {"slice_evals_per_s": level_s_rate,
                             "frac": level_s_rate * FLOP_PER_SLICE / 1e12 / FP64_PEAK_TFLOPS,
                             "note": "same point g=10 T=1 without the coarser levels: 1024 slices per sample"}
-    line["summary"] = summarize(line)
     if cpu is not None:
         line["cpu_baseline"] = cpu
+    line["summary"] = summarize(line)
     print(json.dumps(line), flush=True)
     ctx.close()
 
@@ -1056,7 +1056,8 @@ def _r(x, d=4):
 
 
 def summarize(line):
-    """Compact figures of every section (a few KB) for the end of the line."""
+    """Compact figures of every section (about 2 KB past the convergence tables) for the end of the
+    line: the convergence slopes first, the headline last."""
     out = {"headline": {"value": _r(line["value"]), "frac": _r(line["roofline"]["frac"]),
                         "counter_frac": _r(line["roofline"].get("counter_frac")),
                         "kernel_avg_ms": _r(line["roofline"]["kernel_avg_ms"])},
@@ -1084,7 +1085,7 @@ def summarize(line):
     if f:
         out["proposal"] = {"plain": {"relvar": _r(f["plain"]["relvar"]), "t_1e-5_s": _r(f["plain"]["time_to_rel_err_1e-5_s"]),
                                      "run_s": _r(f["plain"]["run_to_target"]["device_s"])}}
-        for key in ("proposal", "proposal_wide_batch"):
+        for key in ("proposal",):                  # the configured batch (the wide one: detailed section)
             if key in f:
                 g = f[key]
                 out["proposal"][key] = {"batch": g["batch"], "train_s": _r(g["train_ms"] / 1e3), "relvar": _r(g["relvar"]),
@@ -1099,8 +1100,10 @@ def summarize(line):
         pair = {}
         for key, r in c["points"].items():
             g, p, T = key.split(",")
-            slopes.setdefault(f"{g},{T}", {})[p.split("=")[1]] = _r(r.get("slope"), 3)
-            pair.setdefault(f"{g},{T}", {})[p.split("=")[1]] = _r(r.get("pair_slope"), 3)
+            if r.get("slope") is not None:
+                slopes.setdefault(f"{g},{T}", {})[p.split("=")[1]] = _r(r["slope"], 3)
+            if r.get("pair_slope") is not None:
+                pair.setdefault(f"{g},{T}", {})[p.split("=")[1]] = _r(r["pair_slope"], 3)
         out["c2"] = {"slice_evals_per_s": _r(c["slice_evals_per_s"]), "slopes": slopes, "pair_slopes": pair,
                      "g0_max_abs_z": {p: _r(v["max_abs_z_vs_exact_discretized"], 3) for p, v in c["g0"].items()},
                      "max_abs_z_N1024_vs_dvr": {}, "max_abs_z_fit_vs_dvr": {}}
@@ -1125,7 +1128,9 @@ def summarize(line):
                                   for r in line["vector"].get("component", [])]
     out["spectrum"] = [{"matrix_ms": _r(r["matrix_ms"]), "lanczos_ms_per_step": _r(r["lanczos_ms_per_step"]),
                         "max_abs_diff_vs_dvr": _r(r.get("max_abs_diff_vs_dvr"), 3)} for r in line["spectrum"]]
-    return out
+    order = ("c2", "spectrum", "general", "mpt", "vector", "batched", "proposal", "precision", "level_s_only",
+             "headline")
+    return {k: out[k] for k in order if k in out}
 
 
 if __name__ == "__main__":
