@@ -32,8 +32,11 @@ GENERATED = "pimc_general_gen.hpp"
 # One translation unit per out-of-line general-mode level: (source, defines, object name).
 GEN_HI_LEVELS = range(11, 19)
 VARIANTS = [("pimc_general_hi.hip", [f"-DPIMC_GEN_P={p}"], f"pimc_general_hi_p{p}") for p in GEN_HI_LEVELS]
-# One translation unit per dimension for the component evaluator's kernels.
+# One translation unit per dimension for the component evaluator's kernels, and one more for the
+# deepest subtree of d = 3 and 4 (empty where that depth is below the split).
 VARIANTS += [("pimc_vector_poly.hip", [f"-DPIMC_POLY_DIM={d}"], f"pimc_vector_poly_d{d}") for d in (1, 2, 3, 4)]
+VARIANTS += [("pimc_vector_poly.hip", [f"-DPIMC_POLY_DIM={d}", "-DPIMC_POLY_DEEP=1"], f"pimc_vector_poly_d{d}_deep")
+             for d in (3, 4)]
 
 # -ffp-contract=off: every fused multiply-add in the kernels is written as fma(); no other
 # expression is contracted, so the arithmetic is exactly what the source states.

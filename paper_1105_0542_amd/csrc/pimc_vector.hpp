@@ -154,5 +154,13 @@ template <int DIM>
 hipError_t launch_vector_poly_dim(const VecArgs& A, int U, int grid, hipStream_t st);
 template <int DIM>
 int vector_poly_resident_dim(int U, size_t lds, int device);
+// Subtrees of kPolySplitU levels or more (the deepest, poly_subtree_levels(DIM)) are compiled in a
+// translation unit of their own per dimension (pimc_vector_poly.hip with PIMC_POLY_DEEP), in
+// parallel with the shallower ones; launch_vector_poly_dim forwards to them.
+constexpr int kPolySplitU = 7;
+template <int DIM>
+hipError_t launch_vector_poly_deep(const VecArgs& A, int grid, hipStream_t st);
+template <int DIM>
+int vector_poly_resident_deep(size_t lds, int device);
 
 }  // namespace pimc

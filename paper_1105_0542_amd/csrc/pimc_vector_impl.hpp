@@ -591,31 +591,33 @@ inline int resident_rt(int U, size_t lds, int device) {
     }
 }
 
-template <int DIM>
+// UMAX: the deepest subtree instantiated by the caller's translation unit (the deepest of all may be
+// compiled in a unit of its own).
+template <int DIM, int UMAX = poly_subtree_levels(DIM)>
 inline hipError_t launch_poly(const VecArgs& A, int U, int grid, hipStream_t st) {
     const PolyEvalRT<DIM> ev{A.tab, A.shape, A.stride};
     switch (U) {
         case 1: return launch_one<DIM, 1>(A, ev, grid, st);
         case 2: return launch_one<DIM, 2>(A, ev, grid, st);
         case 3: return launch_one<DIM, 3>(A, ev, grid, st);
-        case 4: if constexpr (poly_subtree_levels(DIM) >= 4) return launch_one<DIM, 4>(A, ev, grid, st); break;
-        case 5: if constexpr (poly_subtree_levels(DIM) >= 5) return launch_one<DIM, 5>(A, ev, grid, st); break;
-        case 6: if constexpr (poly_subtree_levels(DIM) >= 6) return launch_one<DIM, 6>(A, ev, grid, st); break;
-        case 7: if constexpr (poly_subtree_levels(DIM) >= 7) return launch_one<DIM, 7>(A, ev, grid, st); break;
+        case 4: if constexpr (UMAX >= 4) return launch_one<DIM, 4>(A, ev, grid, st); break;
+        case 5: if constexpr (UMAX >= 5) return launch_one<DIM, 5>(A, ev, grid, st); break;
+        case 6: if constexpr (UMAX >= 6) return launch_one<DIM, 6>(A, ev, grid, st); break;
+        case 7: if constexpr (UMAX >= 7) return launch_one<DIM, 7>(A, ev, grid, st); break;
         default: break;
     }
     return hipErrorInvalidValue;
 }
 
-template <int DIM>
+template <int DIM, int UMAX = poly_subtree_levels(DIM)>
 inline int resident_poly(int U, size_t lds, int device) {
     switch (U) {
         case 1: return resident_one<DIM, 1, PolyEvalRT<DIM>>(lds, device);
         case 2: return resident_one<DIM, 2, PolyEvalRT<DIM>>(lds, device);
-        case 4: if constexpr (poly_subtree_levels(DIM) >= 4) return resident_one<DIM, 4, PolyEvalRT<DIM>>(lds, device); break;
-        case 5: if constexpr (poly_subtree_levels(DIM) >= 5) return resident_one<DIM, 5, PolyEvalRT<DIM>>(lds, device); break;
-        case 6: if constexpr (poly_subtree_levels(DIM) >= 6) return resident_one<DIM, 6, PolyEvalRT<DIM>>(lds, device); break;
-        case 7: if constexpr (poly_subtree_levels(DIM) >= 7) return resident_one<DIM, 7, PolyEvalRT<DIM>>(lds, device); break;
+        case 4: if constexpr (UMAX >= 4) return resident_one<DIM, 4, PolyEvalRT<DIM>>(lds, device); break;
+        case 5: if constexpr (UMAX >= 5) return resident_one<DIM, 5, PolyEvalRT<DIM>>(lds, device); break;
+        case 6: if constexpr (UMAX >= 6) return resident_one<DIM, 6, PolyEvalRT<DIM>>(lds, device); break;
+        case 7: if constexpr (UMAX >= 7) return resident_one<DIM, 7, PolyEvalRT<DIM>>(lds, device); break;
         default: break;
     }
     return resident_one<DIM, 3, PolyEvalRT<DIM>>(lds, device);
